@@ -1,0 +1,11 @@
+"""specdd: spectral path tracing over a cell-decomposed triangle scene on one MI355X.
+
+The compute path is libspecdd.so (hand-written HIP for gfx950 behind a C ABI, declared in
+include/specdd.h); this package is its thin ctypes binding. PyTorch supplies device memory and
+the stream only.
+"""
+from ._binding import (MODE_CACHED, MODE_PLAIN, Camera, Context, RenderParams, Scene, SddError, camera, lib,
+                       render_params)
+
+__all__ = ["Scene", "Context", "Camera", "RenderParams", "SddError", "camera", "render_params", "lib",
+           "MODE_PLAIN", "MODE_CACHED"]

@@ -1,0 +1,330 @@
+"""ctypes binding of libspecdd.so -- argument marshalling only.
+
+Every step of the rendering path runs in the library's HIP kernels; this module only turns
+arrays and tensors into pointers, PyTorch provides the device memory and the stream. If the
+library is missing the import fails loudly: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libspecdd.so")
+
+SDD_OK = 0
+ERRORS = {-1: "SDD_ERR_INVALID_ARG", -2: "SDD_ERR_HIP", -3: "SDD_ERR_WORKSPACE", -4: "SDD_ERR_QUEUE_OVERFLOW",
+          -5: "SDD_ERR_NOT_READY", -6: "SDD_ERR_INTERNAL", -7: "SDD_ERR_DEVICE"}
+
+MODE_PLAIN = 0
+MODE_CACHED = 1
+
+
+class SddError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Material(C.Structure):
+    _fields_ = [("type", C.c_int32), ("thickness_m", C.c_float)]
+
+
+class SceneDesc(C.Structure):
+    _fields_ = [("verts", C.c_void_p), ("mat", C.c_void_p), ("n_tri", C.c_int64), ("materials", C.c_void_p),
+                ("n_mat", C.c_int32), ("n_tab", C.c_void_p), ("k_tab", C.c_void_p), ("rho_tab", C.c_void_p),
+                ("n_bins", C.c_int32), ("lambda_min_nm", C.c_float), ("lambda_max_nm", C.c_float),
+                ("sun_dir", C.c_float * 3), ("sun_irradiance", C.c_void_p), ("env_radiance", C.c_void_p),
+                ("grid", C.c_int32 * 3)]
+
+
+class SceneInfo(C.Structure):
+    _fields_ = [("n_tri", C.c_int64), ("n_refs", C.c_int64), ("n_nodes", C.c_int64), ("n_cells", C.c_int64),
+                ("n_empty_cells", C.c_int64), ("max_depth", C.c_int32), ("max_leaf", C.c_int32),
+                ("device_bytes", C.c_size_t), ("grid_lo", C.c_float * 3), ("grid_hi", C.c_float * 3)]
+
+
+class Camera(C.Structure):
+    _fields_ = [("eye", C.c_float * 3), ("target", C.c_float * 3), ("up", C.c_float * 3), ("vfov_deg", C.c_float),
+                ("width", C.c_int32), ("height", C.c_int32)]
+
+
+class RenderParams(C.Structure):
+    _fields_ = [("spp", C.c_int32), ("max_depth", C.c_int32), ("seed", C.c_uint64), ("mode", C.c_int32),
+                ("wave_paths", C.c_int32), ("migrate_rounds", C.c_int32), ("view", C.c_uint32),
+                ("timing", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [(n, C.c_uint64) for n in (
+        "paths", "vertices", "ext_rays", "shadow_rays", "cell_visits", "migrations", "escapes", "glass_crossings",
+        "trace_launches", "shade_launches", "wavefronts", "err_cross_overflow", "err_nonfinite", "err_stack")] + [
+        ("trace_ms", C.c_double), ("shade_ms", C.c_double)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+# Every exported function: (name, restype, argtypes)
+_vp, _i32, _i64, _sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
+SIGNATURES = [
+    ("sdd_scene_create", _i32, [_vp, _vp]),
+    ("sdd_scene_destroy", None, [_vp]),
+    ("sdd_scene_get_info", _i32, [_vp, _vp]),
+    ("sdd_scene_device_bytes", _i32, [_vp, _vp]),
+    ("sdd_scene_host_image", _i32, [_vp, _vp, _vp]),
+    ("sdd_create", _i32, [_vp, C.c_int, _vp]),
+    ("sdd_destroy", None, [_vp]),
+    ("sdd_set_stream", _i32, [_vp, _vp]),
+    ("sdd_scene_upload", _i32, [_vp, _vp, _vp, _sz]),
+    ("sdd_workspace_bytes", _i32, [_vp, _vp, _vp]),
+    ("sdd_render", _i32, [_vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    ("sdd_render_batch", _i32, [_vp, _vp, _vp, _vp, _i32, _vp, _vp, _sz, _vp]),
+    ("sdd_query_workspace_bytes", _i32, [_vp, _i64, _vp]),
+    ("sdd_trace", _i32, [_vp, _vp, _vp, _vp, _vp, _i64, _vp, _sz, _vp, _vp, _vp, _vp]),
+    ("sdd_shadow", _i32, [_vp, _vp, _vp, _vp, _vp, _i64, _vp, _sz, _vp]),
+    ("sdd_philox", _i32, [_vp, _vp, _vp, _i64, _vp]),
+    ("sdd_finish", _i32, [_vp]),
+    ("sdd_get_stats", _i32, [_vp, _vp]),
+    ("sdd_reset_stats", _i32, [_vp]),
+    ("sdd_last_error", C.c_char_p, [_vp]),
+]
+
+_lib = None
+
+
+def lib():
+    """Load libspecdd.so (built in-tree by ``paper_1912_04000_amd.build``)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1912_04000_amd.build` "
+                              "(there is no fallback implementation)")
+        L = C.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc, ctx=None):
+    if rc != SDD_OK:
+        msg = lib().sdd_last_error(ctx)
+        raise SddError(rc, msg.decode() if msg else "")
+
+
+def _ptr(a):
+    """Pointer of a contiguous numpy array or torch tensor."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        assert a.flags["C_CONTIGUOUS"]
+        return a.ctypes.data
+    assert a.is_contiguous()
+    return a.data_ptr()
+
+
+class Scene:
+    """Host-built cell-decomposed scene (``sdd_scene``), optionally uploaded to a device buffer."""
+
+    def __init__(self, verts, mat, mat_type, thickness_m, n_tab, k_tab, rho_tab, lambda_min_nm, lambda_max_nm,
+                 sun_dir, sun_E, env=None, grid=(2, 2, 2)):
+        self._keep = dict(
+            verts=np.ascontiguousarray(verts, dtype=np.float32), mat=np.ascontiguousarray(mat, dtype=np.uint16),
+            n=np.ascontiguousarray(n_tab, dtype=np.float32), k=np.ascontiguousarray(k_tab, dtype=np.float32),
+            rho=np.ascontiguousarray(rho_tab, dtype=np.float32), E=np.ascontiguousarray(sun_E, dtype=np.float32),
+            env=None if env is None else np.ascontiguousarray(env, dtype=np.float32))
+        n_mat = len(mat_type)
+        mats = (Material * n_mat)()
+        for i in range(n_mat):
+            mats[i].type = int(mat_type[i])
+            mats[i].thickness_m = float(thickness_m[i])
+        self._keep["mats"] = mats
+        k = self._keep
+        self.n_bins = int(k["n"].shape[1])
+        d = SceneDesc()
+        d.verts = _ptr(k["verts"])
+        d.mat = _ptr(k["mat"])
+        d.n_tri = k["verts"].shape[0]
+        d.materials = C.cast(mats, C.c_void_p)
+        d.n_mat = n_mat
+        d.n_tab, d.k_tab, d.rho_tab = _ptr(k["n"]), _ptr(k["k"]), _ptr(k["rho"])
+        d.n_bins = self.n_bins
+        d.lambda_min_nm, d.lambda_max_nm = float(lambda_min_nm), float(lambda_max_nm)
+        d.sun_dir[:] = [float(x) for x in sun_dir]
+        d.sun_irradiance = _ptr(k["E"])
+        d.env_radiance = _ptr(k["env"]) if k["env"] is not None else None
+        d.grid[:] = [int(g) for g in grid]
+        h = C.c_void_p()
+        _check(lib().sdd_scene_create(C.byref(d), C.byref(h)))
+        self.handle = h
+        self.grid = tuple(int(g) for g in grid)
+        self.device_buffer = None
+
+    @classmethod
+    def from_description(cls, sc, grid=(2, 2, 2)):
+        """Build from any object carrying the scene arrays by name (verts, mat, mat_type, ...)."""
+        return cls(sc.verts, sc.mat, sc.mat_type, sc.thickness_m, sc.n_tab, sc.k_tab, sc.rho_tab, sc.lambda_min_nm,
+                   sc.lambda_max_nm, sc.sun_dir, sc.sun_E, sc.env, grid)
+
+    def info(self) -> dict:
+        i = SceneInfo()
+        _check(lib().sdd_scene_get_info(self.handle, C.byref(i)))
+        return dict(n_tri=i.n_tri, n_refs=i.n_refs, n_nodes=i.n_nodes, n_cells=i.n_cells,
+                    n_empty_cells=i.n_empty_cells, max_depth=i.max_depth, max_leaf=i.max_leaf,
+                    device_bytes=i.device_bytes, grid_lo=list(i.grid_lo), grid_hi=list(i.grid_hi))
+
+    def device_bytes(self) -> int:
+        b = C.c_size_t()
+        _check(lib().sdd_scene_device_bytes(self.handle, C.byref(b)))
+        return b.value
+
+    def host_image(self) -> np.ndarray:
+        p, b = C.c_void_p(), C.c_size_t()
+        _check(lib().sdd_scene_host_image(self.handle, C.byref(p), C.byref(b)))
+        return np.ctypeslib.as_array(C.cast(p, C.POINTER(C.c_uint8)), shape=(b.value,)).copy()
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.sdd_scene_destroy(self.handle)
+            self.handle = None
+
+
+def camera(eye, target, up=(0.0, 0.0, 1.0), vfov_deg=60.0, width=64, height=64) -> Camera:
+    c = Camera()
+    c.eye[:] = [float(x) for x in eye]
+    c.target[:] = [float(x) for x in target]
+    c.up[:] = [float(x) for x in up]
+    c.vfov_deg = float(vfov_deg)
+    c.width, c.height = int(width), int(height)
+    return c
+
+
+def render_params(spp=1, max_depth=4, seed=1, mode=MODE_PLAIN, wave_paths=0, migrate_rounds=0, view=0, timing=0):
+    p = RenderParams()
+    p.spp, p.max_depth, p.seed, p.mode = int(spp), int(max_depth), int(seed), int(mode)
+    p.wave_paths, p.migrate_rounds, p.view, p.timing = int(wave_paths), int(migrate_rounds), int(view), int(timing)
+    return p
+
+
+class Context:
+    """``sdd_ctx`` on a torch CUDA (HIP) device; device memory comes from torch allocations."""
+
+    def __init__(self, device=0, stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        _check(lib().sdd_create(C.byref(h), int(device), C.c_void_p(self.stream.cuda_stream)))
+        self.handle = h
+        self._ws = None
+
+    def _err(self, rc):
+        _check(rc, self.handle)
+
+    def upload(self, scene: Scene):
+        nbytes = scene.device_bytes()
+        buf = self.torch.empty(nbytes + 256, dtype=self.torch.uint8, device=self.device)
+        off = (-buf.data_ptr()) % 256
+        view = buf[off:off + nbytes]
+        self._err(lib().sdd_scene_upload(self.handle, scene.handle, C.c_void_p(view.data_ptr()), nbytes))
+        scene.device_buffer = buf
+        return scene
+
+    def workspace(self, nbytes):
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = None
+            self._ws = self.torch.empty(nbytes, dtype=self.torch.uint8, device=self.device)
+        return self._ws
+
+    def workspace_bytes(self, scene: Scene, params: RenderParams) -> int:
+        b = C.c_size_t()
+        _check(lib().sdd_workspace_bytes(scene.handle, C.byref(params), C.byref(b)))
+        return b.value
+
+    def render(self, scene: Scene, cam: Camera, params: RenderParams, out=None, finish=True):
+        ws = self.workspace(self.workspace_bytes(scene, params))
+        img = out if out is not None else self.torch.empty((scene.n_bins, cam.height, cam.width),
+                                                           dtype=self.torch.float32, device=self.device)
+        self._err(lib().sdd_render(self.handle, scene.handle, C.byref(cam), C.byref(params),
+                                   C.c_void_p(ws.data_ptr()), ws.numel(), C.c_void_p(img.data_ptr())))
+        if finish:
+            self.finish()
+        return img
+
+    def render_batch(self, scene: Scene, cams, spp, params: RenderParams, outs=None, finish=True):
+        n = len(cams)
+        arr = (Camera * n)(*cams)
+        spp_arr = (C.c_int32 * n)(*[int(s) for s in spp])
+        if outs is None:
+            outs = [self.torch.empty((scene.n_bins, c.height, c.width), dtype=self.torch.float32, device=self.device)
+                    for c in cams]
+        ptrs = (C.c_void_p * n)(*[o.data_ptr() for o in outs])
+        ws = self.workspace(self.workspace_bytes(scene, params))
+        self._err(lib().sdd_render_batch(self.handle, scene.handle, arr, spp_arr, n, C.byref(params),
+                                         C.c_void_p(ws.data_ptr()), ws.numel(), ptrs))
+        if finish:
+            self.finish()
+        return outs
+
+    def _query_ws(self, scene, n):
+        b = C.c_size_t()
+        _check(lib().sdd_query_workspace_bytes(scene.handle, int(n), C.byref(b)))
+        return self.workspace(b.value)
+
+    def trace(self, scene: Scene, orig, dirs, skip=None):
+        """Closest hits of device rays (float32 [n][3]); returns (t, id, u, v) tensors."""
+        torch = self.torch
+        n = orig.shape[0]
+        ws = self._query_ws(scene, n)
+        t = torch.empty(n, dtype=torch.float32, device=self.device)
+        ids = torch.empty(n, dtype=torch.int32, device=self.device)
+        u = torch.empty_like(t)
+        v = torch.empty_like(t)
+        self._err(lib().sdd_trace(self.handle, scene.handle, C.c_void_p(orig.data_ptr()), C.c_void_p(dirs.data_ptr()),
+                                  None if skip is None else C.c_void_p(skip.data_ptr()), n, C.c_void_p(ws.data_ptr()),
+                                  ws.numel(), C.c_void_p(t.data_ptr()), C.c_void_p(ids.data_ptr()),
+                                  C.c_void_p(u.data_ptr()), C.c_void_p(v.data_ptr())))
+        self.finish()
+        return t, ids, u, v
+
+    def shadow(self, scene: Scene, orig, dirs, skip=None):
+        torch = self.torch
+        n = orig.shape[0]
+        ws = self._query_ws(scene, n)
+        vis = torch.empty((n, scene.n_bins), dtype=torch.float32, device=self.device)
+        self._err(lib().sdd_shadow(self.handle, scene.handle, C.c_void_p(orig.data_ptr()),
+                                   C.c_void_p(dirs.data_ptr()), None if skip is None else C.c_void_p(skip.data_ptr()),
+                                   n, C.c_void_p(ws.data_ptr()), ws.numel(), C.c_void_p(vis.data_ptr())))
+        self.finish()
+        return vis
+
+    def philox(self, ctr, key, n):
+        torch = self.torch
+        out = torch.empty((n, 4), dtype=torch.int32, device=self.device)
+        c = (C.c_uint32 * 4)(*[int(x) & 0xFFFFFFFF for x in ctr])
+        k = (C.c_uint32 * 2)(*[int(x) & 0xFFFFFFFF for x in key])
+        self._err(lib().sdd_philox(self.handle, c, k, int(n), C.c_void_p(out.data_ptr())))
+        self.finish()
+        return out
+
+    def finish(self):
+        self._err(lib().sdd_finish(self.handle))
+
+    def stats(self) -> dict:
+        s = Stats()
+        self._err(lib().sdd_get_stats(self.handle, C.byref(s)))
+        return s.as_dict()
+
+    def reset_stats(self):
+        self._err(lib().sdd_reset_stats(self.handle))
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.sdd_destroy(self.handle)
+            self.handle = None

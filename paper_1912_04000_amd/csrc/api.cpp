@@ -1,0 +1,536 @@
+// C ABI of libspecdd: argument validation, workspace layout and the wavefront loop.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "host.h"
+
+using namespace sdd;
+
+struct sdd_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  Ctl* last_ctl = nullptr;     // control block of the last launched work (inside a workspace)
+  sdd_stats acc;               // accumulated statistics
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_trace, ev_shade;
+  size_t ev_used_trace = 0, ev_used_shade = 0;
+  int cu_count = 256;
+};
+
+namespace sdd {
+
+static thread_local std::string g_thread_err;
+void set_thread_error(const std::string& m) { g_thread_err = m; }
+const char* thread_error() { return g_thread_err.c_str(); }
+
+}  // namespace sdd
+
+namespace {
+
+int fail(sdd_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  set_thread_error(msg);
+  return code;
+}
+
+#define HIP_TRY(ctx, expr)                                                              \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess) return fail(ctx, SDD_ERR_HIP, std::string(#expr ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr int kDefaultWave = 1 << 20;
+constexpr int kDefaultMigrate = 3;
+constexpr int kMaxViewsPerStore = 16;
+
+struct ViewBlock {
+  ViewDesc v[kMaxViewsPerStore];
+};
+
+__global__ void k_store_views(ViewBlock vb, ViewDesc* dst, int first, int count) {
+  int i = threadIdx.x;
+  if (i < count) dst[first + i] = vb.v[i];
+}
+
+size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
+
+enum {
+  L_FLAGS, L_PIX, L_SMP, L_VIEW, L_BETA, L_NEE, L_HIT, L_RAYS, L_SHCNT, L_SHX, L_ACTIVE, L_LSRC, L_LDST, L_LRANK,
+  L_QUEUE, L_CCOUNT, L_COFF, L_TILES, L_SPILL, L_CTL, L_VIEWS, L_COUNT
+};
+
+struct Plan {
+  uint32_t W;
+  int B;
+  int n_cells;
+  int n_views;
+  int trace_blocks;
+  uint32_t max_tiles;
+  size_t off[L_COUNT];
+  size_t total;
+};
+
+Plan make_plan(uint32_t W, int B, int n_cells, int n_views) {
+  Plan p;
+  p.W = W;
+  p.B = B;
+  p.n_cells = n_cells;
+  p.n_views = n_views;
+  size_t want = ((size_t)2 * W + kWG - 1) / kWG;
+  int tb = (int)std::min<size_t>(2048, std::max<size_t>(kXcds, want));
+  tb = (tb + kXcds - 1) / kXcds * kXcds;
+  p.trace_blocks = tb;
+  p.max_tiles = (uint32_t)(((size_t)2 * W + kTile - 1) / kTile + n_cells + 8);
+  size_t sz[L_COUNT];
+  sz[L_FLAGS] = 4ull * W;
+  sz[L_PIX] = 4ull * W;
+  sz[L_SMP] = 4ull * W;
+  sz[L_VIEW] = 4ull * W;
+  sz[L_BETA] = 4ull * B * W;
+  sz[L_NEE] = 4ull * B * W;
+  sz[L_HIT] = 16ull * W;
+  sz[L_RAYS] = 64ull * W;
+  sz[L_SHCNT] = 4ull * W;
+  sz[L_SHX] = 8ull * kMaxCross * W;
+  sz[L_ACTIVE] = 12ull * W;
+  sz[L_LSRC] = 8ull * W;
+  sz[L_LDST] = 8ull * W;
+  sz[L_LRANK] = 8ull * W;
+  sz[L_QUEUE] = 8ull * W;
+  sz[L_CCOUNT] = 8ull * n_cells;
+  sz[L_COFF] = 4ull * n_cells;
+  sz[L_TILES] = 16ull * p.max_tiles;
+  sz[L_SPILL] = 4ull * (kMaxStack - kShortStack) * (size_t)tb * kWG;
+  sz[L_CTL] = sizeof(Ctl);
+  sz[L_VIEWS] = sizeof(ViewDesc) * (size_t)std::max(1, n_views);
+  size_t o = 0;
+  for (int i = 0; i < L_COUNT; ++i) {
+    p.off[i] = o;
+    o = a256(o + sz[i]);
+  }
+  p.total = o;
+  return p;
+}
+
+DevWS ws_view(const Plan& p, void* base) {
+  uint8_t* b = (uint8_t*)base;
+  DevWS w;
+  std::memset(&w, 0, sizeof(w));
+  w.flags = (uint32_t*)(b + p.off[L_FLAGS]);
+  w.pix = (uint32_t*)(b + p.off[L_PIX]);
+  w.smp = (uint32_t*)(b + p.off[L_SMP]);
+  w.view = (uint32_t*)(b + p.off[L_VIEW]);
+  w.beta = (float*)(b + p.off[L_BETA]);
+  w.nee = (float*)(b + p.off[L_NEE]);
+  w.hit = (float4*)(b + p.off[L_HIT]);
+  w.rays = (float4*)(b + p.off[L_RAYS]);
+  w.shcnt = (uint32_t*)(b + p.off[L_SHCNT]);
+  w.shx = (float2*)(b + p.off[L_SHX]);
+  w.active = (uint32_t*)(b + p.off[L_ACTIVE]);
+  w.lsrc = (uint32_t*)(b + p.off[L_LSRC]);
+  w.ldst = (uint32_t*)(b + p.off[L_LDST]);
+  w.lrank = (uint32_t*)(b + p.off[L_LRANK]);
+  w.queue = (uint32_t*)(b + p.off[L_QUEUE]);
+  w.ccount = (uint32_t*)(b + p.off[L_CCOUNT]);
+  w.coff = (uint32_t*)(b + p.off[L_COFF]);
+  w.tiles = (uint4*)(b + p.off[L_TILES]);
+  w.spill = (uint32_t*)(b + p.off[L_SPILL]);
+  w.ctl = (Ctl*)(b + p.off[L_CTL]);
+  w.views = (ViewDesc*)(b + p.off[L_VIEWS]);
+  w.W = p.W;
+  w.max_tiles = p.max_tiles;
+  w.trace_threads = (uint32_t)p.trace_blocks * kWG;
+  w.n_views = p.n_views;
+  return w;
+}
+
+bool finite3(const float* v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+
+// Camera basis in FP64, handed to the kernels as FP32 vectors.
+std::string make_view(const sdd_camera& c, ViewDesc* v) {
+  if (!finite3(c.eye) || !finite3(c.target) || !finite3(c.up)) return "camera vectors must be finite";
+  if (!(c.vfov_deg > 0 && c.vfov_deg < 180)) return "vfov must lie in (0, 180)";
+  if (c.width < 1 || c.height < 1 || (int64_t)c.width * c.height > (1ll << 31)) return "bad image size";
+  double f[3] = {(double)c.target[0] - c.eye[0], (double)c.target[1] - c.eye[1], (double)c.target[2] - c.eye[2]};
+  double fl = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+  if (!(fl > 0)) return "camera target equals eye";
+  for (double& x : f) x /= fl;
+  double up[3] = {c.up[0], c.up[1], c.up[2]};
+  double r[3] = {f[1] * up[2] - f[2] * up[1], f[2] * up[0] - f[0] * up[2], f[0] * up[1] - f[1] * up[0]};
+  double rl = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+  if (!(rl > 0)) return "camera up is parallel to the view direction";
+  for (double& x : r) x /= rl;
+  double u[3] = {r[1] * f[2] - r[2] * f[1], r[2] * f[0] - r[0] * f[2], r[0] * f[1] - r[1] * f[0]};
+  double t = std::tan(c.vfov_deg * M_PI / 360.0);
+  double aspect = (double)c.width / c.height;
+  std::memset(v, 0, sizeof(*v));
+  for (int i = 0; i < 3; ++i) {
+    v->eye[i] = c.eye[i];
+    v->fwd[i] = (float)f[i];
+    v->right[i] = (float)(r[i] * t * aspect);
+    v->upv[i] = (float)(u[i] * t);
+  }
+  v->width = c.width;
+  v->height = c.height;
+  return "";
+}
+
+std::string check_params(const sdd_render_params* p) {
+  if (!p) return "params is null";
+  if (p->spp < 1) return "spp must be >= 1";
+  if (p->max_depth < 1 || p->max_depth > 64) return "max_depth must lie in 1..64";
+  if (p->mode != SDD_MODE_PLAIN && p->mode != SDD_MODE_CACHED) return "unknown mode";
+  if (p->wave_paths != 0 && (p->wave_paths < 64 || p->wave_paths > (1 << 26))) return "wave_paths out of range";
+  if (p->migrate_rounds < 0 || p->migrate_rounds > 256) return "migrate_rounds out of range";
+  return "";
+}
+
+int scene_ready(sdd_ctx* ctx, const sdd_scene* s) {
+  if (!s) return fail(ctx, SDD_ERR_INVALID_ARG, "scene is null");
+  if (!s->dev) return fail(ctx, SDD_ERR_NOT_READY, "scene has not been uploaded");
+  return SDD_OK;
+}
+
+void record(sdd_ctx* ctx, std::vector<std::pair<hipEvent_t, hipEvent_t>>& pool, size_t& used, bool start) {
+  if (start) {
+    if (used == pool.size()) {
+      hipEvent_t a, b;
+      (void)hipEventCreate(&a);
+      (void)hipEventCreate(&b);
+      pool.push_back({a, b});
+    }
+    (void)hipEventRecord(pool[used].first, ctx->stream);
+  } else {
+    (void)hipEventRecord(pool[used].second, ctx->stream);
+    ++used;
+  }
+}
+
+// Trace every entry produced so far: rounds of (scan, scatter, trace). In the first
+// `migrate` rounds a ray visits one cell and migrates to the next cell's queue; the last
+// round walks the remaining rays through their remaining cells in place.
+int trace_phase(sdd_ctx* ctx, const Launch& L, const DevScene& S, const DevWS& w, int& gen, int migrate, bool timing) {
+  for (int r = 0; r <= migrate; ++r) {
+    const int hops = r == migrate ? (1 << 30) : 1;
+    HIP_TRY(ctx, launch_scan(L, S, w, gen));
+    HIP_TRY(ctx, launch_scatter(L, w, gen));
+    if (timing) record(ctx, ctx->ev_trace, ctx->ev_used_trace, true);
+    HIP_TRY(ctx, launch_trace(L, S, w, gen, hops));
+    if (timing) record(ctx, ctx->ev_trace, ctx->ev_used_trace, false);
+    ctx->acc.trace_launches++;
+    ++gen;
+  }
+  return SDD_OK;
+}
+
+int store_views(sdd_ctx* ctx, const std::vector<ViewDesc>& views, const DevWS& w) {
+  for (size_t first = 0; first < views.size(); first += kMaxViewsPerStore) {
+    ViewBlock vb;
+    std::memset(&vb, 0, sizeof(vb));
+    int cnt = (int)std::min<size_t>(kMaxViewsPerStore, views.size() - first);
+    for (int i = 0; i < cnt; ++i) vb.v[i] = views[first + i];
+    hipLaunchKernelGGL(k_store_views, dim3(1), dim3(kMaxViewsPerStore), 0, ctx->stream, vb, w.views, (int)first, cnt);
+    HIP_TRY(ctx, hipGetLastError());
+  }
+  return SDD_OK;
+}
+
+int render_views(sdd_ctx* ctx, const sdd_scene* scene, std::vector<ViewDesc>& views, const sdd_render_params* p,
+                 void* ws, size_t ws_bytes) {
+  const int B = scene->hdr.n_bins;
+  uint64_t total = 0;
+  for (auto& v : views) {
+    v.item_base = total;
+    total += (uint64_t)v.width * v.height * (uint64_t)v.spp;
+  }
+  uint32_t W = p->wave_paths ? (uint32_t)p->wave_paths : (uint32_t)std::min<uint64_t>(kDefaultWave, total);
+  W = std::max<uint32_t>(W, 64);
+  Plan plan = make_plan(W, B, scene->hdr.n_cells, (int)views.size());
+  if (!ws) return fail(ctx, SDD_ERR_INVALID_ARG, "workspace is null");
+  if (ws_bytes < plan.total)
+    return fail(ctx, SDD_ERR_WORKSPACE,
+                "workspace too small: need " + std::to_string(plan.total) + " bytes, got " + std::to_string(ws_bytes));
+  DevWS w = ws_view(plan, ws);
+  DevScene S = device_view(scene);
+  Launch L{ctx->stream, plan.trace_blocks};
+  const int migrate = p->migrate_rounds ? p->migrate_rounds : kDefaultMigrate;
+  const bool timing = p->timing != 0;
+  int rc = store_views(ctx, views, w);
+  if (rc) return rc;
+  for (auto& v : views) HIP_TRY(ctx, launch_fill_f32(ctx->stream, v.image, (size_t)B * v.width * v.height, 0.0f));
+  HIP_TRY(ctx, launch_fill_u32(ctx->stream, (uint32_t*)w.ctl, sizeof(Ctl) / 4, 0u));
+  HIP_TRY(ctx, launch_fill_u32(ctx->stream, w.ccount, 2ull * scene->hdr.n_cells, 0u));
+  ctx->last_ctl = w.ctl;
+  int gen = 0;
+  const int D = p->max_depth;
+  for (uint64_t k0 = 0; k0 < total; k0 += W) {
+    const uint32_t n = (uint32_t)std::min<uint64_t>(W, total - k0);
+    HIP_TRY(ctx, launch_raygen(L, S, w, k0, n, p->seed, gen));
+    rc = trace_phase(ctx, L, S, w, gen, migrate, timing);
+    if (rc) return rc;
+    for (int d = 1; d <= D + 1; ++d) {
+      if (timing) record(ctx, ctx->ev_shade, ctx->ev_used_shade, true);
+      HIP_TRY(ctx, launch_shade(L, S, w, d, D, p->seed, gen));
+      if (timing) record(ctx, ctx->ev_shade, ctx->ev_used_shade, false);
+      ctx->acc.shade_launches++;
+      if (d <= D) {
+        rc = trace_phase(ctx, L, S, w, gen, migrate, timing);
+        if (rc) return rc;
+      }
+    }
+    ctx->acc.wavefronts++;
+  }
+  return SDD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sdd_scene_create(const sdd_scene_desc* desc, sdd_scene** out) {
+  if (!desc || !out) return fail(nullptr, SDD_ERR_INVALID_ARG, "null argument");
+  *out = nullptr;
+  sdd_scene* s = new (std::nothrow) sdd_scene();
+  if (!s) return fail(nullptr, SDD_ERR_INTERNAL, "out of host memory");
+  std::string e;
+  try {
+    e = build_scene(*desc, s);
+  } catch (const std::exception& ex) {
+    e = std::string("internal: ") + ex.what();
+  }
+  if (!e.empty()) {
+    delete s;
+    return fail(nullptr, e.rfind("internal", 0) == 0 ? SDD_ERR_INTERNAL : SDD_ERR_INVALID_ARG, e);
+  }
+  *out = s;
+  return SDD_OK;
+}
+
+void sdd_scene_destroy(sdd_scene* s) { delete s; }
+
+int sdd_scene_get_info(const sdd_scene* s, sdd_scene_info* out) {
+  if (!s || !out) return fail(nullptr, SDD_ERR_INVALID_ARG, "null argument");
+  *out = s->info;
+  return SDD_OK;
+}
+
+int sdd_scene_device_bytes(const sdd_scene* s, size_t* bytes) {
+  if (!s || !bytes) return fail(nullptr, SDD_ERR_INVALID_ARG, "null argument");
+  *bytes = s->image.size();
+  return SDD_OK;
+}
+
+int sdd_scene_host_image(const sdd_scene* s, const void** data, size_t* bytes) {
+  if (!s || !data || !bytes) return fail(nullptr, SDD_ERR_INVALID_ARG, "null argument");
+  *data = s->image.data();
+  *bytes = s->image.size();
+  return SDD_OK;
+}
+
+int sdd_create(sdd_ctx** out, int hip_device, void* hip_stream) {
+  if (!out) return fail(nullptr, SDD_ERR_INVALID_ARG, "null argument");
+  *out = nullptr;
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || n == 0) return fail(nullptr, SDD_ERR_HIP, "no HIP device available");
+  if (hip_device < 0 || hip_device >= n) return fail(nullptr, SDD_ERR_INVALID_ARG, "device index out of range");
+  e = hipSetDevice(hip_device);
+  if (e != hipSuccess) return fail(nullptr, SDD_ERR_HIP, hipGetErrorString(e));
+  sdd_ctx* c = new sdd_ctx();
+  c->device = hip_device;
+  c->stream = (hipStream_t)hip_stream;
+  std::memset(&c->acc, 0, sizeof(c->acc));
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess) c->cu_count = prop.multiProcessorCount;
+  *out = c;
+  return SDD_OK;
+}
+
+void sdd_destroy(sdd_ctx* c) {
+  if (!c) return;
+  for (auto& p : c->ev_trace) { (void)hipEventDestroy(p.first); (void)hipEventDestroy(p.second); }
+  for (auto& p : c->ev_shade) { (void)hipEventDestroy(p.first); (void)hipEventDestroy(p.second); }
+  delete c;
+}
+
+int sdd_set_stream(sdd_ctx* c, void* s) {
+  if (!c) return fail(nullptr, SDD_ERR_INVALID_ARG, "ctx is null");
+  c->stream = (hipStream_t)s;
+  return SDD_OK;
+}
+
+int sdd_scene_upload(sdd_ctx* c, sdd_scene* s, void* dev_buf, size_t bytes) {
+  if (!c || !s || !dev_buf) return fail(c, SDD_ERR_INVALID_ARG, "null argument");
+  if (bytes < s->image.size()) return fail(c, SDD_ERR_WORKSPACE, "scene buffer smaller than sdd_scene_device_bytes");
+  if (((uintptr_t)dev_buf & 255) != 0) return fail(c, SDD_ERR_INVALID_ARG, "scene buffer must be 256-byte aligned");
+  HIP_TRY(c, hipSetDevice(c->device));
+  HIP_TRY(c, hipMemcpyAsync(dev_buf, s->image.data(), s->image.size(), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  s->dev = dev_buf;
+  s->dev_bytes = bytes;
+  s->dev_device = c->device;
+  return SDD_OK;
+}
+
+int sdd_workspace_bytes(const sdd_scene* s, const sdd_render_params* p, size_t* bytes) {
+  if (!s || !bytes) return fail(nullptr, SDD_ERR_INVALID_ARG, "null argument");
+  std::string e = check_params(p);
+  if (!e.empty()) return fail(nullptr, SDD_ERR_INVALID_ARG, e);
+  uint32_t W = p->wave_paths ? (uint32_t)p->wave_paths : (uint32_t)kDefaultWave;
+  *bytes = make_plan(W, s->hdr.n_bins, s->hdr.n_cells, 64).total;
+  return SDD_OK;
+}
+
+int sdd_render(sdd_ctx* c, const sdd_scene* s, const sdd_camera* cam, const sdd_render_params* p, void* ws,
+               size_t ws_bytes, float* image) {
+  if (!c) return fail(nullptr, SDD_ERR_INVALID_ARG, "ctx is null");
+  int rc = scene_ready(c, s);
+  if (rc) return rc;
+  if (!cam || !image) return fail(c, SDD_ERR_INVALID_ARG, "null camera or image");
+  std::string e = check_params(p);
+  if (!e.empty()) return fail(c, SDD_ERR_INVALID_ARG, e);
+  if (p->mode != SDD_MODE_PLAIN) return fail(c, SDD_ERR_INVALID_ARG, "cached mode requires a configured cache");
+  std::vector<ViewDesc> views(1);
+  e = make_view(*cam, &views[0]);
+  if (!e.empty()) return fail(c, SDD_ERR_INVALID_ARG, e);
+  views[0].spp = p->spp;
+  views[0].inv_spp = 1.0f / (float)p->spp;
+  views[0].image = image;
+  views[0].view_id = p->view;
+  HIP_TRY(c, hipSetDevice(c->device));
+  return render_views(c, s, views, p, ws, ws_bytes);
+}
+
+int sdd_render_batch(sdd_ctx* c, const sdd_scene* s, const sdd_camera* cams, const int32_t* spp, int32_t n_views,
+                     const sdd_render_params* p, void* ws, size_t ws_bytes, float* const* images) {
+  if (!c) return fail(nullptr, SDD_ERR_INVALID_ARG, "ctx is null");
+  int rc = scene_ready(c, s);
+  if (rc) return rc;
+  if (!cams || !spp || !images || n_views < 1 || n_views > 64)
+    return fail(c, SDD_ERR_INVALID_ARG, "bad view list (1..64 views)");
+  std::string e = check_params(p);
+  if (!e.empty()) return fail(c, SDD_ERR_INVALID_ARG, e);
+  if (p->mode != SDD_MODE_PLAIN) return fail(c, SDD_ERR_INVALID_ARG, "cached mode requires a configured cache");
+  std::vector<ViewDesc> views(n_views);
+  for (int v = 0; v < n_views; ++v) {
+    e = make_view(cams[v], &views[v]);
+    if (!e.empty()) return fail(c, SDD_ERR_INVALID_ARG, "view " + std::to_string(v) + ": " + e);
+    if (spp[v] < 1) return fail(c, SDD_ERR_INVALID_ARG, "spp per view must be >= 1");
+    if (!images[v]) return fail(c, SDD_ERR_INVALID_ARG, "null image pointer");
+    views[v].spp = spp[v];
+    views[v].inv_spp = 1.0f / (float)spp[v];
+    views[v].image = images[v];
+    views[v].view_id = (uint32_t)v;
+  }
+  HIP_TRY(c, hipSetDevice(c->device));
+  return render_views(c, s, views, p, ws, ws_bytes);
+}
+
+int sdd_query_workspace_bytes(const sdd_scene* s, int64_t n, size_t* bytes) {
+  if (!s || !bytes || n < 1) return fail(nullptr, SDD_ERR_INVALID_ARG, "bad argument");
+  uint32_t W = (uint32_t)std::min<int64_t>(n, kDefaultWave);
+  *bytes = make_plan(std::max<uint32_t>(W, 64), s->hdr.n_bins, s->hdr.n_cells, 1).total;
+  return SDD_OK;
+}
+
+static int query(sdd_ctx* c, const sdd_scene* s, const float* orig, const float* dir, const int32_t* skip, int64_t n,
+                 void* ws, size_t ws_bytes, bool shadow, float* t, int32_t* id, float* u, float* v, float* vis) {
+  if (!c) return fail(nullptr, SDD_ERR_INVALID_ARG, "ctx is null");
+  int rc = scene_ready(c, s);
+  if (rc) return rc;
+  if (!orig || !dir || n < 1 || !ws) return fail(c, SDD_ERR_INVALID_ARG, "bad ray arrays");
+  uint32_t W = std::max<uint32_t>(64, (uint32_t)std::min<int64_t>(n, kDefaultWave));
+  Plan plan = make_plan(W, s->hdr.n_bins, s->hdr.n_cells, 1);
+  if (ws_bytes < plan.total) return fail(c, SDD_ERR_WORKSPACE, "workspace too small for the ray query");
+  HIP_TRY(c, hipSetDevice(c->device));
+  DevWS w = ws_view(plan, ws);
+  DevScene S = device_view(s);
+  Launch L{c->stream, plan.trace_blocks};
+  HIP_TRY(c, launch_fill_u32(c->stream, (uint32_t*)w.ctl, sizeof(Ctl) / 4, 0u));
+  HIP_TRY(c, launch_fill_u32(c->stream, w.ccount, 2ull * s->hdr.n_cells, 0u));
+  c->last_ctl = w.ctl;
+  int gen = 0;
+  for (int64_t a = 0; a < n; a += W) {
+    uint32_t m = (uint32_t)std::min<int64_t>(W, n - a);
+    HIP_TRY(c, launch_pack_rays(L, S, w, orig + 3 * a, dir + 3 * a, skip ? skip + a : nullptr, m, shadow ? 1 : 0, gen));
+    rc = trace_phase(c, L, S, w, gen, kDefaultMigrate, false);
+    if (rc) return rc;
+    if (shadow)
+      HIP_TRY(c, launch_resolve_vis(L, S, w, m, vis + (size_t)a * s->hdr.n_bins));
+    else
+      HIP_TRY(c, launch_unpack_hits(L, w, m, t + a, id + a, u + a, v + a));
+  }
+  return SDD_OK;
+}
+
+int sdd_trace(sdd_ctx* c, const sdd_scene* s, const float* orig, const float* dir, const int32_t* skip, int64_t n,
+              void* ws, size_t ws_bytes, float* t, int32_t* id, float* u, float* v) {
+  if (!t || !id || !u || !v) return fail(c, SDD_ERR_INVALID_ARG, "null output array");
+  return query(c, s, orig, dir, skip, n, ws, ws_bytes, false, t, id, u, v, nullptr);
+}
+
+int sdd_shadow(sdd_ctx* c, const sdd_scene* s, const float* orig, const float* dir, const int32_t* skip, int64_t n,
+               void* ws, size_t ws_bytes, float* vis) {
+  if (!vis) return fail(c, SDD_ERR_INVALID_ARG, "null output array");
+  return query(c, s, orig, dir, skip, n, ws, ws_bytes, true, nullptr, nullptr, nullptr, nullptr, vis);
+}
+
+int sdd_philox(sdd_ctx* c, const uint32_t ctr[4], const uint32_t key[2], int64_t n, uint32_t* out) {
+  if (!c || !ctr || !key || !out || n < 0) return fail(c, SDD_ERR_INVALID_ARG, "bad argument");
+  HIP_TRY(c, hipSetDevice(c->device));
+  HIP_TRY(c, launch_philox(c->stream, ctr, key, (uint64_t)n, out));
+  return SDD_OK;
+}
+
+int sdd_finish(sdd_ctx* c) {
+  if (!c) return fail(nullptr, SDD_ERR_INVALID_ARG, "ctx is null");
+  HIP_TRY(c, hipSetDevice(c->device));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  int status = SDD_OK;
+  if (c->last_ctl) {
+    Ctl h;
+    HIP_TRY(c, hipMemcpy(&h, c->last_ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+    c->acc.paths += h.st_paths;
+    c->acc.vertices += h.st_vertices;
+    c->acc.ext_rays += h.st_ext;
+    c->acc.shadow_rays += h.st_shadow;
+    c->acc.cell_visits += h.st_visits;
+    c->acc.migrations += h.st_migr;
+    c->acc.escapes += h.st_escape;
+    c->acc.glass_crossings += h.st_glass;
+    c->acc.err_cross_overflow += h.err_cross;
+    c->acc.err_nonfinite += h.err_nonfinite;
+    c->acc.err_stack += h.err_stack;
+    if (h.err_cross) status = fail(c, SDD_ERR_QUEUE_OVERFLOW, "a shadow ray crossed more glass slabs than recorded");
+    c->last_ctl = nullptr;
+  }
+  for (size_t i = 0; i < c->ev_used_trace; ++i) {
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, c->ev_trace[i].first, c->ev_trace[i].second) == hipSuccess) c->acc.trace_ms += ms;
+  }
+  for (size_t i = 0; i < c->ev_used_shade; ++i) {
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, c->ev_shade[i].first, c->ev_shade[i].second) == hipSuccess) c->acc.shade_ms += ms;
+  }
+  c->ev_used_trace = c->ev_used_shade = 0;
+  return status;
+}
+
+int sdd_get_stats(sdd_ctx* c, sdd_stats* out) {
+  if (!c || !out) return fail(c, SDD_ERR_INVALID_ARG, "null argument");
+  *out = c->acc;
+  return SDD_OK;
+}
+
+int sdd_reset_stats(sdd_ctx* c) {
+  if (!c) return fail(nullptr, SDD_ERR_INVALID_ARG, "ctx is null");
+  std::memset(&c->acc, 0, sizeof(c->acc));
+  return SDD_OK;
+}
+
+const char* sdd_last_error(const sdd_ctx* c) { return c ? c->err.c_str() : thread_error(); }
+
+}  // extern "C"

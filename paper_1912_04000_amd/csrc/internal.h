@@ -1,0 +1,166 @@
+// Internal layout shared by the host runtime and the gfx950 kernels of libspecdd.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace sdd {
+
+// ------------------------------------------------------------------------------------------
+// Tunables fixed at compile time
+// ------------------------------------------------------------------------------------------
+constexpr int kWG = 256;            // threads per workgroup of the traversal/shading kernels
+constexpr int kTile = 256;          // rays of one cell handled by one workgroup tile
+constexpr int kTopNodes = 32;       // top BVH nodes of a cell staged in LDS per tile
+constexpr int kShortStack = 12;     // traversal stack entries kept in LDS per thread
+constexpr int kMaxStack = 48;       // builder caps BVH depth so the stack never exceeds this
+constexpr int kMaxCross = 8;        // glass crossings recorded per shadow ray
+constexpr int kMaxBins = 128;
+constexpr int kMaxGrid = 64;
+constexpr int kXcds = 8;            // MI355X: 8 XCDs, workgroups dispatched round-robin
+constexpr uint32_t kBlocked = 0xFFFFFFFFu;
+constexpr uint32_t kFirstVisit = 0x80000000u;
+constexpr uint32_t kShadowBit = 0x80000000u;  // in the ray's slot word
+constexpr uint32_t kInvalidCell = 0xFFFFFFFFu;
+constexpr uint32_t kEmptyChild = 0xFFFFFFFFu;
+
+// path flags
+constexpr uint32_t kFlagExt = 1u;     // an extension ray is in flight
+constexpr uint32_t kFlagShadow = 2u;  // a shadow ray (pending NEE) is in flight
+
+// ------------------------------------------------------------------------------------------
+// Serialised scene image (one device buffer, offsets in bytes from its start)
+// ------------------------------------------------------------------------------------------
+struct SceneHeader {
+  uint32_t magic, version;
+  int32_t n_tri, n_mat, n_bins, n_cells;
+  int32_t grid[3];
+  int32_t max_depth;
+  float lo[3], hi[3];
+  float sun[3];
+  int32_t env_nonzero;
+  uint64_t off_planes, off_cells, off_nodes, off_ctris, off_gtris, off_mtype, off_thick, off_n, off_k, off_rho,
+      off_lambda, off_sunE, off_env;
+  uint64_t n_nodes, n_refs;
+  float lambda_min_nm, lambda_max_nm;
+  int32_t max_leaf;
+  int32_t pad[5];
+};
+static_assert(sizeof(SceneHeader) <= 256, "header fits in 256 bytes");
+
+// Node of a cell BVH: the two child boxes are stored in the parent (64 bytes):
+//   a = (c0.lo.x, c0.hi.x, c0.lo.y, c0.hi.y)   b = (c1.lo.x, c1.hi.x, c1.lo.y, c1.hi.y)
+//   c = (c0.lo.z, c0.hi.z, c1.lo.z, c1.hi.z)   d = (idx0, idx1, cnt0, cnt1) as int bits
+// cnt > 0: leaf with cnt cell triangles starting at idx (cell-relative); cnt == 0: inner node
+// idx (cell-relative); idx == kEmptyChild: no child.
+// Cell triangle (48 bytes): (v0, global id) (v1, material id) (v2, 0).
+// Global triangle: the same 48-byte record indexed by the triangle id.
+
+// Device view of a scene (built from the device base pointer and the header).
+struct DevScene {
+  const float4* nodes;
+  const float4* ctris;
+  const float4* gtris;
+  const int4* cells;    // (node base, node count, tri base, tri count)
+  const float* planes;  // gx+1 | gy+1 | gz+1
+  const int32_t* mtype;
+  const float* thick;
+  const float* ntab;
+  const float* ktab;
+  const float* rho;
+  const float* lambda;
+  const float* sunE;
+  const float* env;
+  int32_t gx, gy, gz, n_cells;
+  float lo[3], hi[3];
+  float inv_cs[3];
+  float sun[3];
+  int32_t n_bins, n_mat, env_nonzero, pad;
+};
+
+// Per-view description for raygen and accumulation.
+struct ViewDesc {
+  float eye[3];
+  float fwd[3];     // unit forward
+  float right[3];   // right * tan(vfov/2) * W/H
+  float upv[3];     // up * tan(vfov/2)
+  int32_t width, height;
+  int32_t spp;
+  float inv_spp;
+  uint64_t item_base;  // first global item of this view
+  uint64_t image_off;  // float offset of this view's image inside the image arena (batch)
+  float* image;        // [B][H][W]
+  uint32_t view_id;
+  int32_t pad;
+};
+
+// Control block (device) -- counters of the wavefront machinery and statistics.
+struct Ctl {
+  uint32_t list_count[2];   // produced (ray, cell, rank) entries per generation parity
+  uint32_t n_queue;         // entries in the cell-sorted queue of the current round
+  uint32_t n_tiles;         // tiles of the current round
+  uint32_t act_count[3];    // active-slot lists (rotating)
+  uint32_t pad0[9];
+  unsigned long long st_paths, st_vertices, st_ext, st_shadow, st_visits, st_migr, st_escape, st_glass;
+  unsigned long long err_cross, err_nonfinite, err_stack;
+  unsigned long long pad1[5];
+};
+
+// Device view of a workspace.
+struct DevWS {
+  uint32_t* flags;
+  uint32_t* pix;
+  uint32_t* smp;
+  uint32_t* view;
+  float* beta;       // [B][W]
+  float* nee;        // [B][W]
+  float4* hit;       // [W] (t, id bits, u, v)
+  float4* rays;      // [2W][2]  (o.xyz, skip bits) (d.xyz, slot | shadow bit)
+  uint32_t* shcnt;   // [W] glass crossings of the pending shadow ray, kBlocked if blocked
+  float2* shx;       // [kMaxCross][W] (material id bits, cos theta)
+  uint32_t* active;  // [3][W]
+  uint32_t* lsrc;    // [2W] produced entries: ray index | first-visit bit
+  uint32_t* ldst;    // [2W] destination cell
+  uint32_t* lrank;   // [2W] rank inside the destination cell
+  uint32_t* queue;   // [2W] cell-sorted entries of the current round
+  uint32_t* ccount;  // [2][n_cells]
+  uint32_t* coff;    // [n_cells]
+  uint4* tiles;      // [max_tiles] (cell, start, count, 0)
+  uint32_t* spill;   // [kMaxStack - kShortStack][trace_threads]
+  Ctl* ctl;
+  ViewDesc* views;   // [n_views]
+  uint32_t W;        // path slots
+  uint32_t max_tiles;
+  uint32_t trace_threads;
+  int32_t n_views;
+};
+
+// Layout of a workspace for W slots, B bins, C cells, V views and a traversal grid.
+struct WSLayout {
+  size_t off[24];
+  size_t total;
+};
+
+// Host helpers implemented in the kernels' translation unit.
+struct Launch {
+  hipStream_t stream;
+  int trace_blocks;   // workgroups of the persistent traversal grid (multiple of kXcds)
+};
+
+hipError_t launch_fill_f32(hipStream_t s, float* p, size_t n, float v);
+hipError_t launch_fill_u32(hipStream_t s, uint32_t* p, size_t n, uint32_t v);
+hipError_t launch_raygen(const Launch& L, const DevScene& S, const DevWS& w, uint64_t k0, uint32_t n, uint64_t seed,
+                         int gen);
+hipError_t launch_scan(const Launch& L, const DevScene& S, const DevWS& w, int gen);
+hipError_t launch_scatter(const Launch& L, const DevWS& w, int gen);
+hipError_t launch_trace(const Launch& L, const DevScene& S, const DevWS& w, int gen, int hops);
+hipError_t launch_shade(const Launch& L, const DevScene& S, const DevWS& w, int depth, int max_depth, uint64_t seed,
+                        int gen);
+hipError_t launch_pack_rays(const Launch& L, const DevScene& S, const DevWS& w, const float* orig, const float* dir,
+                            const int32_t* skip, uint32_t n, int shadow, int gen);
+hipError_t launch_unpack_hits(const Launch& L, const DevWS& w, uint32_t n, float* t, int32_t* id, float* u, float* v);
+hipError_t launch_resolve_vis(const Launch& L, const DevScene& S, const DevWS& w, uint32_t n, float* vis);
+hipError_t launch_philox(hipStream_t s, const uint32_t ctr[4], const uint32_t key[2], uint64_t n, uint32_t* out);
+
+}  // namespace sdd

@@ -1,0 +1,985 @@
+// gfx950 kernels of the spectral path tracer.
+//
+// Wavefront structure (one "phase" traces every ray produced by the previous step):
+//   producer (raygen / shade / pack)  -> (ray, start cell, rank in cell) entries
+//   k_scan     one workgroup: per-cell offsets, cell-sorted tile list
+//   k_scatter  entries -> cell-sorted queue
+//   k_trace    a tile = up to 256 rays of ONE cell: the cell's top BVH nodes are staged in LDS,
+//              each lane traverses its ray inside the cell's slab interval; rays that leave the
+//              cell are re-queued for the next cell (the interface conditions between the
+//              paper's sub-domains, section 5) or, in the final round, walk on in place.
+//   shade      per-bin SoA spectral shading: complex Fresnel (eq. 1), thin-slab Beer-Lambert
+//              glass, next-event estimation toward the directional sun (eq. 3).
+#include "internal.h"
+
+namespace sdd {
+
+// ==========================================================================================
+// small helpers
+// ==========================================================================================
+struct F3 { float x, y, z; };
+__device__ __forceinline__ F3 f3(float x, float y, float z) { return {x, y, z}; }
+__device__ __forceinline__ F3 operator+(F3 a, F3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ __forceinline__ F3 operator-(F3 a, F3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ F3 operator*(F3 a, float s) { return {a.x * s, a.y * s, a.z * s}; }
+__device__ __forceinline__ float dot3(F3 a, F3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ F3 cross3(F3 a, F3 b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+__device__ __forceinline__ F3 norm3(F3 a) { return a * (1.0f / sqrtf(dot3(a, a))); }
+__device__ __forceinline__ float maxabs3(F3 a) { return fmaxf(fabsf(a.x), fmaxf(fabsf(a.y), fabsf(a.z))); }
+__device__ __forceinline__ float comp(F3 a, int k) { return k == 0 ? a.x : (k == 1 ? a.y : a.z); }
+
+// Philox4x32-10 (Salmon et al., SC'11).
+__device__ __forceinline__ uint4 philox(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c.x), lo0 = 0xD2511F53u * c.x;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z), lo1 = 0xCD9E8D57u * c.z;
+    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+  }
+  return c;
+}
+__device__ __forceinline__ float unif24(uint32_t x) { return (float)(x >> 8) * 0x1p-24f; }
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+__device__ __forceinline__ uint32_t count_below(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Wave-level append of (src, cell) entries: one atomic per wave on the list counter and one
+// per distinct destination cell of the wave (ballot + mbcnt prefix); every lane of the wave
+// must call it.
+__device__ void wave_append(bool valid, uint32_t src, uint32_t cell, uint32_t* list_count, uint32_t* cell_count,
+                            uint32_t* lsrc, uint32_t* ldst, uint32_t* lrank) {
+  const uint64_t m = __ballot(valid);
+  if (m == 0) return;
+  const uint32_t leader = (uint32_t)__ffsll((unsigned long long)m) - 1u;
+  uint32_t base = 0;
+  if (lane_id() == leader) base = atomicAdd(list_count, (uint32_t)__popcll(m));
+  base = __shfl(base, (int)leader);
+  const uint32_t pos = base + count_below(m);
+  uint32_t rank = 0;
+  uint64_t pending = m;
+  while (pending) {
+    const uint32_t l = (uint32_t)__ffsll((unsigned long long)pending) - 1u;
+    const uint32_t c = __shfl(cell, (int)l);
+    const bool mine = valid && cell == c;
+    const uint64_t same = __ballot(mine);
+    uint32_t cb = 0;
+    if (lane_id() == l) cb = atomicAdd(&cell_count[c], (uint32_t)__popcll(same));
+    cb = __shfl(cb, (int)l);
+    if (mine) rank = cb + count_below(same);
+    pending &= ~same;
+  }
+  if (valid) {
+    lsrc[pos] = src;
+    ldst[pos] = cell;
+    lrank[pos] = rank;
+  }
+}
+
+// Wave-level sum, then one 64-bit atomic per wave.
+__device__ __forceinline__ void wave_add(unsigned long long* ctr, uint32_t x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+  if (lane_id() == 0 && x) atomicAdd(ctr, (unsigned long long)x);
+}
+
+// ==========================================================================================
+// cell grid
+// ==========================================================================================
+__device__ __forceinline__ const float* planes_of(const DevScene& S, int axis) {
+  return axis == 0 ? S.planes : (axis == 1 ? S.planes + S.gx + 1 : S.planes + S.gx + 1 + S.gy + 1);
+}
+
+__device__ __forceinline__ int locate_axis(const float* pl, int g, float lo, float inv_cs, float p) {
+  int i = (int)floorf((p - lo) * inv_cs);
+  i = min(max(i, 0), g - 1);
+  while (i > 0 && p < pl[i]) --i;
+  while (i < g - 1 && p >= pl[i + 1]) ++i;
+  return i;
+}
+
+// Start cell of a ray: the cell holding its origin, or the cell where it enters the grid box.
+// Returns kInvalidCell if the ray misses the grid box entirely.
+__device__ uint32_t start_cell(const DevScene& S, F3 o, F3 d) {
+  const float* px = planes_of(S, 0);
+  const float* py = planes_of(S, 1);
+  const float* pz = planes_of(S, 2);
+  const float lo[3] = {px[0], py[0], pz[0]};
+  const float hi[3] = {px[S.gx], py[S.gy], pz[S.gz]};
+  const float oo[3] = {o.x, o.y, o.z}, dd[3] = {d.x, d.y, d.z};
+  float tn = -INFINITY, tf = INFINITY;
+  bool inside = true;
+  for (int a = 0; a < 3; ++a) {
+    if (oo[a] < lo[a] || oo[a] >= hi[a]) inside = false;
+    if (dd[a] == 0.0f) {
+      if (oo[a] < lo[a] || oo[a] > hi[a]) return kInvalidCell;
+      continue;
+    }
+    const float inv = 1.0f / dd[a];
+    float t0 = (lo[a] - oo[a]) * inv, t1 = (hi[a] - oo[a]) * inv;
+    tn = fmaxf(tn, fminf(t0, t1));
+    tf = fminf(tf, fmaxf(t0, t1));
+  }
+  F3 p = o;
+  if (!inside) {
+    if (!(tn <= tf) || tf < 0.0f) return kInvalidCell;
+    if (tn > 0.0f) p = o + d * tn;
+  }
+  const int ix = locate_axis(px, S.gx, lo[0], S.inv_cs[0], p.x);
+  const int iy = locate_axis(py, S.gy, lo[1], S.inv_cs[1], p.y);
+  const int iz = locate_axis(pz, S.gz, lo[2], S.inv_cs[2], p.z);
+  return (uint32_t)((iz * S.gy + iy) * S.gx + ix);
+}
+
+// Slab interval of a ray inside cell (ix, iy, iz) and the axis through which it leaves.
+// The shared plane of two neighbouring cells is read from one table and evaluated with one
+// expression, so the exit distance of a cell equals the entry distance of the next exactly.
+__device__ __forceinline__ void cell_interval(const DevScene& S, int ix, int iy, int iz, F3 o, F3 d, F3 inv, float& tn,
+                                              float& tf, int& axis) {
+  const float* px = planes_of(S, 0);
+  const float* py = planes_of(S, 1);
+  const float* pz = planes_of(S, 2);
+  float n0 = -INFINITY, f0 = INFINITY, n1 = -INFINITY, f1 = INFINITY, n2 = -INFINITY, f2 = INFINITY;
+  if (d.x != 0.0f) {
+    const float a = (px[ix] - o.x) * inv.x, b = (px[ix + 1] - o.x) * inv.x;
+    n0 = fminf(a, b);
+    f0 = fmaxf(a, b);
+  }
+  if (d.y != 0.0f) {
+    const float a = (py[iy] - o.y) * inv.y, b = (py[iy + 1] - o.y) * inv.y;
+    n1 = fminf(a, b);
+    f1 = fmaxf(a, b);
+  }
+  if (d.z != 0.0f) {
+    const float a = (pz[iz] - o.z) * inv.z, b = (pz[iz + 1] - o.z) * inv.z;
+    n2 = fminf(a, b);
+    f2 = fmaxf(a, b);
+  }
+  tn = fmaxf(n0, fmaxf(n1, n2));
+  axis = 0;
+  tf = f0;
+  if (f1 < tf) { tf = f1; axis = 1; }
+  if (f2 < tf) { tf = f2; axis = 2; }
+}
+
+// ==========================================================================================
+// spectral optics
+// ==========================================================================================
+// Unpolarised Fresnel reflectance of air -> n + ik at incidence cosine c (principal branch of
+// w = sqrt(eta^2 - sin^2)).
+__device__ __forceinline__ float fresnel(float n, float k, float c) {
+  c = fminf(1.0f, fmaxf(0.0f, c));
+  const float s2 = 1.0f - c * c;
+  const float er = n * n - k * k, ei = 2.0f * n * k;
+  const float zr = er - s2, zi = ei;
+  const float r = sqrtf(zr * zr + zi * zi);
+  float wr, wi;
+  if (r == 0.0f) {
+    wr = 0.0f;
+    wi = 0.0f;
+  } else if (zr >= 0.0f) {
+    wr = sqrtf(0.5f * (r + zr));
+    wi = zi / (2.0f * wr);
+  } else {
+    wi = copysignf(sqrtf(0.5f * (r - zr)), zi);
+    wr = zi / (2.0f * wi);
+  }
+  const float an = c - wr, ad = c + wr;
+  const float Rs = (an * an + wi * wi) / (ad * ad + wi * wi);
+  const float pr = er * c, pi = ei * c;
+  const float bnr = pr - wr, bni = pi - wi, bdr = pr + wr, bdi = pi + wi;
+  const float Rp = (bnr * bnr + bni * bni) / (bdr * bdr + bdi * bdi);
+  return 0.5f * (Rs + Rp);
+}
+
+// Thin slab: incoherent multiple reflection, Beer-Lambert alpha = 4 pi k / lambda over the
+// internal path d / cos(theta_t), refraction angle from the real index.
+__device__ __forceinline__ void slab(float n, float k, float lambda_nm, float d_m, float c, float& R, float& T) {
+  c = fminf(1.0f, fmaxf(0.0f, c));
+  const float st = sqrtf(fmaxf(0.0f, 1.0f - c * c));
+  const float si = st / n;
+  const float ci = sqrtf(fmaxf(0.0f, 1.0f - si * si));
+  const float alpha = 4.0f * 3.14159265358979f * k / (lambda_nm * 1e-9f);
+  const float tau = expf(-alpha * d_m / ci);
+  const float R1 = fresnel(n, k, c);
+  const float den = 1.0f - R1 * R1 * tau * tau;
+  const float q = (1.0f - R1) * (1.0f - R1);
+  R = R1 + q * tau * tau * R1 / den;
+  T = q * tau / den;
+}
+
+// ==========================================================================================
+// fills / philox test kernel
+// ==========================================================================================
+__global__ void k_fill_f32(float* p, size_t n, float v) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+__global__ void k_fill_u32(uint32_t* p, size_t n, uint32_t v) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+__global__ void k_philox(uint4 base, uint32_t k0, uint32_t k1, uint64_t n, uint4* out) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    out[i] = philox(make_uint4(base.x + (uint32_t)i, base.y, base.z, base.w), k0, k1);
+}
+
+// ==========================================================================================
+// ray generation
+// ==========================================================================================
+__global__ __launch_bounds__(kWG) void k_raygen(DevScene S, DevWS w, uint64_t k0, uint32_t n, uint32_t key0,
+                                                uint32_t key1, int gen) {
+  const uint32_t i = blockIdx.x * kWG + threadIdx.x;
+  const bool valid = i < n;
+  uint32_t cell = kInvalidCell;
+  if (valid) {
+    const uint64_t k = k0 + i;
+    int v = 0;
+    while (v + 1 < w.n_views && w.views[v + 1].item_base <= k) ++v;
+    const ViewDesc& V = w.views[v];
+    const uint64_t local = k - V.item_base;
+    const uint64_t P = (uint64_t)V.width * V.height;
+    const uint32_t s = (uint32_t)(local / P);
+    const uint32_t pix = (uint32_t)(local % P);
+    const uint32_t px = pix % (uint32_t)V.width, py = pix / (uint32_t)V.width;
+    const uint4 rn = philox(make_uint4(pix, s, 0u, V.view_id), key0, key1);
+    const float sx = 2.0f * ((float)px + unif24(rn.x)) / (float)V.width - 1.0f;
+    const float sy = 1.0f - 2.0f * ((float)py + unif24(rn.y)) / (float)V.height;
+    const F3 fw = f3(V.fwd[0], V.fwd[1], V.fwd[2]);
+    const F3 rt = f3(V.right[0], V.right[1], V.right[2]);
+    const F3 up = f3(V.upv[0], V.upv[1], V.upv[2]);
+    const F3 d = norm3(fw + rt * sx + up * sy);
+    const F3 o = f3(V.eye[0], V.eye[1], V.eye[2]);
+    w.rays[2 * i] = make_float4(o.x, o.y, o.z, __int_as_float(-1));
+    w.rays[2 * i + 1] = make_float4(d.x, d.y, d.z, __uint_as_float(i));
+    w.flags[i] = kFlagExt;
+    w.pix[i] = pix;
+    w.smp[i] = s;
+    w.view[i] = (uint32_t)v;
+    for (int j = 0; j < S.n_bins; ++j) w.beta[(size_t)j * w.W + i] = 1.0f;
+    w.active[1 * w.W + i] = i;
+    cell = start_cell(S, o, d);
+    if (cell == kInvalidCell) w.hit[i] = make_float4(INFINITY, __uint_as_float(0xFFFFFFFFu), 0.0f, 0.0f);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    w.ctl->act_count[1] = n;
+    w.ctl->act_count[2] = 0;
+  }
+  const int p = gen & 1;
+  wave_append(valid && cell != kInvalidCell, i | kFirstVisit, cell, &w.ctl->list_count[p],
+              w.ccount + (size_t)p * S.n_cells, w.lsrc, w.ldst, w.lrank);
+  wave_add(&w.ctl->st_paths, valid ? 1u : 0u);
+  wave_add(&w.ctl->st_ext, valid ? 1u : 0u);
+}
+
+// User rays (closest-hit or shadow queries).
+__global__ __launch_bounds__(kWG) void k_pack_rays(DevScene S, DevWS w, const float* orig, const float* dir,
+                                                   const int32_t* skip, uint32_t n, int shadow, int gen) {
+  const uint32_t i = blockIdx.x * kWG + threadIdx.x;
+  const bool valid = i < n;
+  uint32_t cell = kInvalidCell;
+  uint32_t r = 0;
+  if (valid) {
+    const F3 o = f3(orig[3 * i], orig[3 * i + 1], orig[3 * i + 2]);
+    const F3 d = f3(dir[3 * i], dir[3 * i + 1], dir[3 * i + 2]);
+    const int sk = skip ? skip[i] : -1;
+    r = shadow ? w.W + i : i;
+    w.rays[2 * r] = make_float4(o.x, o.y, o.z, __int_as_float(sk));
+    w.rays[2 * r + 1] = make_float4(d.x, d.y, d.z, __uint_as_float(shadow ? (i | kShadowBit) : i));
+    const bool finite = isfinite(o.x) && isfinite(o.y) && isfinite(o.z) && isfinite(d.x) && isfinite(d.y) &&
+                        isfinite(d.z) && (d.x != 0.0f || d.y != 0.0f || d.z != 0.0f);
+    if (finite) cell = start_cell(S, o, d);
+    if (shadow)
+      w.shcnt[i] = 0;
+    else
+      w.hit[i] = make_float4(INFINITY, __uint_as_float(0xFFFFFFFFu), 0.0f, 0.0f);
+  }
+  const int p = gen & 1;
+  wave_append(valid && cell != kInvalidCell, r | kFirstVisit, cell, &w.ctl->list_count[p],
+              w.ccount + (size_t)p * S.n_cells, w.lsrc, w.ldst, w.lrank);
+}
+
+__global__ void k_unpack_hits(DevWS w, uint32_t n, float* t, int32_t* id, float* u, float* v) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const float4 h = w.hit[i];
+    t[i] = h.x;
+    id[i] = __float_as_int(h.y);
+    u[i] = h.z;
+    v[i] = h.w;
+  }
+}
+
+__global__ void k_resolve_vis(DevScene S, DevWS w, uint32_t n, float* vis) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const uint32_t c = w.shcnt[i];
+    for (int j = 0; j < S.n_bins; ++j) {
+      float V = 0.0f;
+      if (c != kBlocked) {
+        V = 1.0f;
+        for (uint32_t q = 0; q < c && q < (uint32_t)kMaxCross; ++q) {
+          const float2 x = w.shx[(size_t)q * w.W + i];
+          const int m = __float_as_int(x.x);
+          float R, T;
+          slab(S.ntab[m * S.n_bins + j], S.ktab[m * S.n_bins + j], S.lambda[j], S.thick[m], x.y, R, T);
+          V *= T;
+        }
+      }
+      vis[(size_t)i * S.n_bins + j] = V;
+    }
+  }
+}
+
+// ==========================================================================================
+// queue: scan + scatter
+// ==========================================================================================
+constexpr int kScanThreads = 1024;
+
+__global__ __launch_bounds__(kScanThreads) void k_scan(DevScene S, DevWS w, int gen) {
+  __shared__ uint32_t s_cnt[kScanThreads], s_til[kScanThreads];
+  const int p = gen & 1;
+  const uint32_t* cnt = w.ccount + (size_t)p * S.n_cells;
+  const int nc = S.n_cells;
+  const int chunk = (nc + kScanThreads - 1) / kScanThreads;
+  const int c0 = min(nc, (int)threadIdx.x * chunk), c1 = min(nc, c0 + chunk);
+  uint32_t sc = 0, st = 0;
+  for (int c = c0; c < c1; ++c) {
+    const uint32_t x = cnt[c];
+    sc += x;
+    st += (x + kTile - 1) / kTile;
+  }
+  s_cnt[threadIdx.x] = sc;
+  s_til[threadIdx.x] = st;
+  __syncthreads();
+  // Hillis-Steele inclusive scan over the per-thread sums
+  for (int off = 1; off < kScanThreads; off <<= 1) {
+    uint32_t a = 0, b = 0;
+    if ((int)threadIdx.x >= off) {
+      a = s_cnt[threadIdx.x - off];
+      b = s_til[threadIdx.x - off];
+    }
+    __syncthreads();
+    s_cnt[threadIdx.x] += a;
+    s_til[threadIdx.x] += b;
+    __syncthreads();
+  }
+  uint32_t run = s_cnt[threadIdx.x] - sc, trun = s_til[threadIdx.x] - st;
+  for (int c = c0; c < c1; ++c) {
+    const uint32_t x = cnt[c];
+    w.coff[c] = run;
+    const uint32_t nt = (x + kTile - 1) / kTile;
+    for (uint32_t q = 0; q < nt; ++q)
+      w.tiles[trun + q] = make_uint4((uint32_t)c, run + q * kTile, min((uint32_t)kTile, x - q * kTile), 0u);
+    run += x;
+    trun += nt;
+  }
+  if (threadIdx.x == kScanThreads - 1) {
+    w.ctl->n_queue = s_cnt[kScanThreads - 1];
+    w.ctl->n_tiles = s_til[kScanThreads - 1];
+    w.ctl->list_count[p ^ 1] = 0;
+  }
+  uint32_t* other = w.ccount + (size_t)(p ^ 1) * S.n_cells;
+  for (int c = threadIdx.x; c < nc; c += kScanThreads) other[c] = 0;
+}
+
+__global__ void k_scatter(DevWS w, int gen) {
+  const uint32_t n = w.ctl->list_count[gen & 1];
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    w.queue[w.coff[w.ldst[i]] + w.lrank[i]] = w.lsrc[i];
+}
+
+// ==========================================================================================
+// traversal
+// ==========================================================================================
+struct RayPre {
+  F3 o, d, inv;
+  int kx, ky, kz;
+  float Sx, Sy, Sz;
+};
+
+__device__ __forceinline__ RayPre make_pre(F3 o, F3 d) {
+  RayPre R;
+  R.o = o;
+  R.d = d;
+  R.inv = f3(1.0f / d.x, 1.0f / d.y, 1.0f / d.z);
+  const float ax = fabsf(d.x), ay = fabsf(d.y), az = fabsf(d.z);
+  R.kz = (ax >= ay && ax >= az) ? 0 : (ay >= az ? 1 : 2);
+  R.kx = R.kz == 2 ? 0 : R.kz + 1;
+  R.ky = R.kx == 2 ? 0 : R.kx + 1;
+  if (comp(d, R.kz) < 0.0f) {
+    const int t = R.kx;
+    R.kx = R.ky;
+    R.ky = t;
+  }
+  const float dz = comp(d, R.kz);
+  R.Sx = comp(d, R.kx) / dz;
+  R.Sy = comp(d, R.ky) / dz;
+  R.Sz = 1.0f / dz;
+  return R;
+}
+
+// Watertight ray/triangle test (Woop, Benthin, Wald, JCGT 2013): shear the triangle into the
+// ray's frame, evaluate the three 2D edge functions (re-evaluated in FP64 when one is exactly
+// zero), inclusive of edges, no back-face culling. Returns false or t with barycentrics.
+__device__ __forceinline__ bool wt_test(const RayPre& R, F3 v0, F3 v1, F3 v2, float& t, float& bu, float& bv) {
+#pragma clang fp contract(off)
+  const F3 A = v0 - R.o, B = v1 - R.o, C = v2 - R.o;
+  const float Akz = comp(A, R.kz), Bkz = comp(B, R.kz), Ckz = comp(C, R.kz);
+  const float Ax = comp(A, R.kx) - R.Sx * Akz, Ay = comp(A, R.ky) - R.Sy * Akz;
+  const float Bx = comp(B, R.kx) - R.Sx * Bkz, By = comp(B, R.ky) - R.Sy * Bkz;
+  const float Cx = comp(C, R.kx) - R.Sx * Ckz, Cy = comp(C, R.ky) - R.Sy * Ckz;
+  float U = Cx * By - Cy * Bx;
+  float V = Ax * Cy - Ay * Cx;
+  float W = Bx * Ay - By * Ax;
+  if (U == 0.0f || V == 0.0f || W == 0.0f) {
+    const double Ud = (double)Cx * (double)By - (double)Cy * (double)Bx;
+    const double Vd = (double)Ax * (double)Cy - (double)Ay * (double)Cx;
+    const double Wd = (double)Bx * (double)Ay - (double)By * (double)Ax;
+    if ((Ud < 0.0 || Vd < 0.0 || Wd < 0.0) && (Ud > 0.0 || Vd > 0.0 || Wd > 0.0)) return false;
+    U = (float)Ud;
+    V = (float)Vd;
+    W = (float)Wd;
+  } else if ((U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f)) {
+    return false;
+  }
+  const float det = U + V + W;
+  if (det == 0.0f) return false;
+  const float T = U * (R.Sz * Akz) + V * (R.Sz * Bkz) + W * (R.Sz * Ckz);
+  const float inv = 1.0f / det;
+  t = T * inv;
+  bu = V * inv;
+  bv = W * inv;
+  return true;
+}
+
+// Distance and barycentrics of the winning triangle re-evaluated in FP64 with the same
+// sheared formulation: the FP32 test decides which triangle is hit, this pass removes the
+// cancellation that makes FP32 distances inaccurate for grazing rays.
+__device__ __forceinline__ void refine_hit(F3 of, F3 df, F3 v0, F3 v1, F3 v2, float& t, float& bu, float& bv) {
+  const double o[3] = {of.x, of.y, of.z}, d[3] = {df.x, df.y, df.z};
+  const double ad[3] = {fabs(d[0]), fabs(d[1]), fabs(d[2])};
+  const int kz = (ad[0] >= ad[1] && ad[0] >= ad[2]) ? 0 : (ad[1] >= ad[2] ? 1 : 2);
+  const int kx = kz == 2 ? 0 : kz + 1, ky = kx == 2 ? 0 : kx + 1;
+  const double Sx = d[kx] / d[kz], Sy = d[ky] / d[kz], Sz = 1.0 / d[kz];
+  const double A[3] = {v0.x - o[0], v0.y - o[1], v0.z - o[2]};
+  const double B[3] = {v1.x - o[0], v1.y - o[1], v1.z - o[2]};
+  const double C[3] = {v2.x - o[0], v2.y - o[1], v2.z - o[2]};
+  const double Ax = A[kx] - Sx * A[kz], Ay = A[ky] - Sy * A[kz];
+  const double Bx = B[kx] - Sx * B[kz], By = B[ky] - Sy * B[kz];
+  const double Cx = C[kx] - Sx * C[kz], Cy = C[ky] - Sy * C[kz];
+  const double U = Cx * By - Cy * Bx, V = Ax * Cy - Ay * Cx, W = Bx * Ay - By * Ax;
+  const double det = U + V + W;
+  if (det == 0.0) return;
+  const double T = Sz * (U * A[kz] + V * B[kz] + W * C[kz]);
+  t = (float)(T / det);
+  bu = (float)(V / det);
+  bv = (float)(W / det);
+}
+
+// Both child boxes of a node against [tmin, tmax] (robust slab test, Ize 2013: the far
+// distance is scaled by 1 + 2 gamma_3 so that rounding never culls a box the ray touches).
+__device__ __forceinline__ void box2(const RayPre& R, float4 a, float4 b, float4 c, float tmin, float tmax, bool& h0,
+                                     float& t0, bool& h1, float& t1) {
+  constexpr float kSlop = 1.0f + 2.0f * 3.0f * 5.9604645e-8f / (1.0f - 3.0f * 5.9604645e-8f);
+  const float x0 = (a.x - R.o.x) * R.inv.x, x1 = (a.y - R.o.x) * R.inv.x;
+  const float y0 = (a.z - R.o.y) * R.inv.y, y1 = (a.w - R.o.y) * R.inv.y;
+  const float z0 = (c.x - R.o.z) * R.inv.z, z1 = (c.y - R.o.z) * R.inv.z;
+  const float n0 = fmaxf(fmaxf(fminf(x0, x1), fminf(y0, y1)), fmaxf(fminf(z0, z1), tmin));
+  const float f0 = fminf(fminf(fmaxf(x0, x1), fmaxf(y0, y1)), fmaxf(z0, z1)) * kSlop;
+  h0 = n0 <= fminf(f0, tmax);
+  t0 = n0;
+  const float X0 = (b.x - R.o.x) * R.inv.x, X1 = (b.y - R.o.x) * R.inv.x;
+  const float Y0 = (b.z - R.o.y) * R.inv.y, Y1 = (b.w - R.o.y) * R.inv.y;
+  const float Z0 = (c.z - R.o.z) * R.inv.z, Z1 = (c.w - R.o.z) * R.inv.z;
+  const float n1 = fmaxf(fmaxf(fminf(X0, X1), fminf(Y0, Y1)), fmaxf(fminf(Z0, Z1), tmin));
+  const float f1 = fminf(fminf(fmaxf(X0, X1), fmaxf(Y0, Y1)), fmaxf(Z0, Z1)) * kSlop;
+  h1 = n1 <= fminf(f1, tmax);
+  t1 = n1;
+}
+
+struct TraceState {
+  // closest hit
+  float tbest;
+  uint32_t best_id;
+  float bu, bv;
+  // shadow
+  bool blocked;
+  uint32_t ncross;
+};
+
+// Traverse the BVH of one cell for hits with t > 0, t >= t_lo, t < t_hi. Closest hit mode
+// shrinks t_hi; shadow mode stops at the first opaque hit and records glass crossings.
+template <bool kShadow>
+__device__ void traverse_cell(const DevScene& S, const DevWS& w, const RayPre& R, int4 cinfo, const float4* lds_nodes,
+                              int n_lds, uint32_t* stack_lds, uint32_t* spill, uint32_t spill_stride, uint32_t skip,
+                              float t_lo, float t_hi, uint32_t slot, TraceState& st) {
+  const float4* gnodes = S.nodes + (size_t)cinfo.x * 4;
+  const float4* ctris = S.ctris + (size_t)cinfo.z * 3;
+  const float box_lo = fmaxf(t_lo, 0.0f);
+  uint32_t node = 0;
+  int sp = 0;
+  for (;;) {
+    float4 na, nb, nc, nd;
+    if ((int)node < n_lds) {
+      na = lds_nodes[node * 4 + 0];
+      nb = lds_nodes[node * 4 + 1];
+      nc = lds_nodes[node * 4 + 2];
+      nd = lds_nodes[node * 4 + 3];
+    } else {
+      na = gnodes[node * 4 + 0];
+      nb = gnodes[node * 4 + 1];
+      nc = gnodes[node * 4 + 2];
+      nd = gnodes[node * 4 + 3];
+    }
+    const uint32_t i0 = __float_as_uint(nd.x), i1 = __float_as_uint(nd.y);
+    const uint32_t c0 = __float_as_uint(nd.z), c1 = __float_as_uint(nd.w);
+    bool h0, h1;
+    float t0, t1;
+    box2(R, na, nb, nc, box_lo, kShadow ? t_hi : st.tbest, h0, t0, h1, t1);
+    h0 = h0 && i0 != kEmptyChild;
+    h1 = h1 && i1 != kEmptyChild;
+#pragma unroll
+    for (int ch = 0; ch < 2; ++ch) {
+      const bool hit_leaf = ch == 0 ? (h0 && c0) : (h1 && c1);
+      if (!hit_leaf) continue;
+      const uint32_t first = ch == 0 ? i0 : i1, cnt = ch == 0 ? c0 : c1;
+      if (ch == 0) h0 = false; else h1 = false;
+      for (uint32_t q = first; q < first + cnt; ++q) {
+        const float4 A = ctris[q * 3 + 0], B = ctris[q * 3 + 1], C = ctris[q * 3 + 2];
+        const uint32_t id = __float_as_uint(A.w);
+        if (id == skip) continue;
+        float t, u, v;
+        if (!wt_test(R, f3(A.x, A.y, A.z), f3(B.x, B.y, B.z), f3(C.x, C.y, C.z), t, u, v)) continue;
+        if (!(t > 0.0f && t >= t_lo && t < t_hi)) continue;
+        if (kShadow) {
+          const int m = (int)__float_as_uint(B.w);
+          if (S.mtype[m] == 0) {
+            st.blocked = true;
+            return;
+          }
+          const F3 e1 = f3(B.x - A.x, B.y - A.y, B.z - A.z), e2 = f3(C.x - A.x, C.y - A.y, C.z - A.z);
+          const F3 ng = norm3(cross3(e1, e2));
+          if (st.ncross < (uint32_t)kMaxCross)
+            w.shx[(size_t)st.ncross * w.W + slot] = make_float2(__int_as_float(m), fabsf(dot3(R.d, ng)));
+          st.ncross++;
+        } else if (t < st.tbest || (t == st.tbest && id < st.best_id)) {
+          st.tbest = t;
+          st.best_id = id;
+          st.bu = u;
+          st.bv = v;
+        }
+      }
+    }
+    if (!kShadow) {
+      h0 = h0 && t0 <= st.tbest;
+      h1 = h1 && t1 <= st.tbest;
+    }
+    if (h0 && h1) {
+      const bool first0 = t0 <= t1;
+      const uint32_t near = first0 ? i0 : i1, far = first0 ? i1 : i0;
+      if (sp < kShortStack)
+        stack_lds[sp * kWG] = far;
+      else
+        spill[(size_t)(sp - kShortStack) * spill_stride] = far;
+      ++sp;
+      node = near;
+    } else if (h0) {
+      node = i0;
+    } else if (h1) {
+      node = i1;
+    } else {
+      if (sp == 0) break;
+      --sp;
+      node = sp < kShortStack ? stack_lds[sp * kWG] : spill[(size_t)(sp - kShortStack) * spill_stride];
+    }
+  }
+}
+
+__global__ __launch_bounds__(kWG) void k_trace(DevScene S, DevWS w, int gen, int hops) {
+  __shared__ float4 s_nodes[kTopNodes * 4];
+  __shared__ uint32_t s_stack[kShortStack * kWG];
+  const uint32_t n_tiles = w.ctl->n_tiles;
+  const uint32_t xcd = blockIdx.x % kXcds;
+  const uint32_t per_xcd = gridDim.x / kXcds;
+  const uint32_t t_begin = (uint32_t)(((uint64_t)n_tiles * xcd) / kXcds);
+  const uint32_t t_end = (uint32_t)(((uint64_t)n_tiles * (xcd + 1)) / kXcds);
+  const uint32_t gtid = blockIdx.x * kWG + threadIdx.x;
+  uint32_t* spill = w.spill + gtid;
+  uint32_t* stack = s_stack + threadIdx.x;
+  const int np = (gen + 1) & 1;
+  uint32_t n_visit = 0, n_migr = 0, n_esc = 0, n_glass = 0;
+  int prev_cell = -1;
+  for (uint32_t t = t_begin + blockIdx.x / kXcds; t < t_end; t += per_xcd) {
+    const uint4 tile = w.tiles[t];
+    const int tcell = (int)tile.x;
+    const int4 tinfo = S.cells[tcell];
+    const int n_top = min(tinfo.y, kTopNodes);
+    if (tcell != prev_cell) {
+      __syncthreads();
+      for (int q = threadIdx.x; q < n_top * 4; q += kWG) s_nodes[q] = S.nodes[(size_t)tinfo.x * 4 + q];
+      __syncthreads();
+      prev_cell = tcell;
+    }
+    const bool active = threadIdx.x < tile.z;
+    bool requeue = false;
+    uint32_t out_src = 0, out_cell = 0;
+    if (active) {
+      const uint32_t entry = w.queue[tile.y + threadIdx.x];
+      const uint32_t r = entry & ~kFirstVisit;
+      bool first = (entry & kFirstVisit) != 0;
+      const float4 ro = w.rays[2 * r], rd = w.rays[2 * r + 1];
+      const uint32_t skip = __float_as_uint(ro.w);
+      const uint32_t sw = __float_as_uint(rd.w);
+      const bool shadow = (sw & kShadowBit) != 0;
+      const uint32_t slot = sw & ~kShadowBit;
+      const RayPre R = make_pre(f3(ro.x, ro.y, ro.z), f3(rd.x, rd.y, rd.z));
+      int cell = tcell;
+      int ix = cell % S.gx, iy = (cell / S.gx) % S.gy, iz = cell / (S.gx * S.gy);
+      TraceState st;
+      st.tbest = INFINITY;
+      st.best_id = 0xFFFFFFFFu;
+      st.bu = st.bv = 0.0f;
+      st.blocked = false;
+      st.ncross = shadow ? w.shcnt[slot] : 0u;
+      const uint32_t ncross0 = st.ncross;
+      bool done = false;
+      for (int h = 0; h < hops; ++h) {
+        float tn, tf;
+        int axis;
+        cell_interval(S, ix, iy, iz, R.o, R.d, R.inv, tn, tf, axis);
+        const float t_lo = first ? -INFINITY : tn;
+        const int4 cinfo = h == 0 ? tinfo : S.cells[cell];
+        ++n_visit;
+        if (cinfo.y > 0 && t_lo < tf) {
+          const int nl = h == 0 ? n_top : 0;
+          if (shadow) {
+            traverse_cell<true>(S, w, R, cinfo, s_nodes, nl, stack, spill, w.trace_threads, skip, t_lo, tf, slot, st);
+            if (st.blocked) {
+              w.shcnt[slot] = kBlocked;
+              done = true;
+              break;
+            }
+          } else {
+            st.tbest = tf;
+            traverse_cell<false>(S, w, R, cinfo, s_nodes, nl, stack, spill, w.trace_threads, skip, t_lo, tf, slot, st);
+            if (st.best_id != 0xFFFFFFFFu) {
+              const float4* g = S.gtris + (size_t)st.best_id * 3;
+              const float4 A = g[0], Bq = g[1], Cq = g[2];
+              refine_hit(R.o, R.d, f3(A.x, A.y, A.z), f3(Bq.x, Bq.y, Bq.z), f3(Cq.x, Cq.y, Cq.z), st.tbest, st.bu,
+                         st.bv);
+              w.hit[slot] = make_float4(st.tbest, __uint_as_float(st.best_id), st.bu, st.bv);
+              done = true;
+              break;
+            }
+          }
+        }
+        // leave through the exit face (Amanatides-Woo step)
+        const float dc = comp(R.d, axis);
+        int* idx = axis == 0 ? &ix : (axis == 1 ? &iy : &iz);
+        const int g = axis == 0 ? S.gx : (axis == 1 ? S.gy : S.gz);
+        *idx += dc > 0.0f ? 1 : -1;
+        if (*idx < 0 || *idx >= g || !(tf < INFINITY)) {
+          // escaped the grid
+          if (!shadow) w.hit[slot] = make_float4(INFINITY, __uint_as_float(0xFFFFFFFFu), 0.0f, 0.0f);
+          ++n_esc;
+          done = true;
+          break;
+        }
+        cell = (iz * S.gy + iy) * S.gx + ix;
+        first = false;
+      }
+      if (shadow && st.ncross != ncross0 && !st.blocked) {
+        n_glass += st.ncross - ncross0;
+        w.shcnt[slot] = st.ncross;
+      }
+      if (!done) {
+        requeue = true;
+        out_src = r;
+        out_cell = (uint32_t)cell;
+        ++n_migr;
+      }
+    }
+    wave_append(requeue, out_src, out_cell, &w.ctl->list_count[np], w.ccount + (size_t)np * S.n_cells, w.lsrc, w.ldst,
+                w.lrank);
+  }
+  wave_add(&w.ctl->st_visits, n_visit);
+  wave_add(&w.ctl->st_migr, n_migr);
+  wave_add(&w.ctl->st_escape, n_esc);
+  wave_add(&w.ctl->st_glass, n_glass);
+}
+
+// ==========================================================================================
+// shading
+// ==========================================================================================
+__device__ __forceinline__ float* image_of(const ViewDesc& V) { return V.image; }
+
+__global__ __launch_bounds__(kWG) void k_shade(DevScene S, DevWS w, int depth, int max_depth, uint32_t key0,
+                                               uint32_t key1, int gen) {
+  const int rd = depth % 3, wr = (depth + 1) % 3, zr = (depth + 2) % 3;
+  const uint32_t n_act = w.ctl->act_count[rd];
+  if (blockIdx.x == 0 && threadIdx.x == 0) w.ctl->act_count[zr] = 0;
+  const int B = S.n_bins;
+  const size_t W = w.W;
+  const int p = gen & 1;
+  const uint32_t n_iter = (n_act + kWG - 1) / kWG * kWG;
+  for (uint32_t a = blockIdx.x * kWG + threadIdx.x; a < n_iter; a += gridDim.x * kWG) {
+    const bool valid = a < n_act;
+    uint32_t s = 0;
+    uint32_t nflags = 0;
+    uint32_t ext_cell = kInvalidCell, sh_cell = kInvalidCell;
+    uint32_t n_vert = 0, n_sh = 0;
+    if (valid) {
+      s = w.active[(size_t)rd * W + a];
+      const uint32_t f = w.flags[s];
+      const ViewDesc& V = w.views[w.view[s]];
+      const uint32_t pix = w.pix[s];
+      const size_t plane = (size_t)V.width * V.height;
+      float* img = V.image + pix;
+      const float inv_spp = V.inv_spp;
+      // ---- resolve the pending shadow ray of the previous vertex (eq. 3 direct term) ----
+      if (f & kFlagShadow) {
+        const uint32_t c = w.shcnt[s];
+        if (c != kBlocked) {
+          const uint32_t nc = min(c, (uint32_t)kMaxCross);
+          for (int j = 0; j < B; ++j) {
+            float Vj = 1.0f;
+            for (uint32_t q = 0; q < nc; ++q) {
+              const float2 x = w.shx[(size_t)q * W + s];
+              const int m = __float_as_int(x.x);
+              float Rq, Tq;
+              slab(S.ntab[m * B + j], S.ktab[m * B + j], S.lambda[j], S.thick[m], x.y, Rq, Tq);
+              Vj *= Tq;
+            }
+            const float c_j = w.nee[(size_t)j * W + s] * Vj * inv_spp;
+            if (c_j != 0.0f) unsafeAtomicAdd(img + (size_t)j * plane, c_j);
+          }
+        }
+      }
+      if ((f & kFlagExt) && depth <= max_depth) {
+        const float4 h = w.hit[s];
+        const uint32_t id = __float_as_uint(h.y);
+        const float4 rdir = w.rays[2 * s + 1];
+        const F3 d = f3(rdir.x, rdir.y, rdir.z);
+        if (id == 0xFFFFFFFFu) {
+          // escaped: environment radiance
+          if (S.env_nonzero)
+            for (int j = 0; j < B; ++j) {
+              const float c_j = w.beta[(size_t)j * W + s] * S.env[j] * inv_spp;
+              if (c_j != 0.0f) unsafeAtomicAdd(img + (size_t)j * plane, c_j);
+            }
+        } else {
+          n_vert = 1;
+          const float4 A = S.gtris[(size_t)id * 3 + 0], Bv = S.gtris[(size_t)id * 3 + 1], C = S.gtris[(size_t)id * 3 + 2];
+          const F3 v0 = f3(A.x, A.y, A.z), v1 = f3(Bv.x, Bv.y, Bv.z), v2 = f3(C.x, C.y, C.z);
+          const int m = (int)__float_as_uint(Bv.w);
+          const F3 ng = norm3(cross3(v1 - v0, v2 - v0));
+          const float dn = dot3(d, ng);
+          const F3 n = dn > 0.0f ? ng * -1.0f : ng;
+          const float cos_o = fabsf(dn);
+          const float bu = h.z, bv = h.w;
+          const F3 pt = v0 * (1.0f - bu - bv) + v1 * bu + v2 * bv;
+          const float eps = 1e-5f * (1.0f + maxabs3(pt));
+          const uint4 rn = philox(make_uint4(pix, w.smp[s], (uint32_t)depth, V.view_id), key0, key1);
+          const float u0 = unif24(rn.x), u1 = unif24(rn.y), u2 = unif24(rn.z);
+          const float* nt = S.ntab + m * B;
+          const float* kt = S.ktab + m * B;
+          const float* rt = S.rho + m * B;
+          F3 no, nd;
+          bool cont = false;
+          if (S.mtype[m] == 0) {
+            const F3 ws = f3(S.sun[0], S.sun[1], S.sun[2]);
+            const float cs = dot3(n, ws);
+            const bool nee = cs > 0.0f;
+            const float kn = cs * (1.0f / 3.14159265358979f);
+            float a_sum = 0.0f, b_sum = 0.0f;
+            for (int j = 0; j < B; ++j) {
+              const float F = fresnel(nt[j], kt[j], cos_o);
+              const float dif = (1.0f - F) * rt[j];
+              a_sum += F;
+              b_sum += dif;
+              if (nee) w.nee[(size_t)j * W + s] = w.beta[(size_t)j * W + s] * dif * kn * S.sunE[j];
+            }
+            if (nee) {
+              nflags |= kFlagShadow;
+              n_sh = 1;
+              const F3 so = pt + n * eps;
+              w.rays[2 * (W + s)] = make_float4(so.x, so.y, so.z, __uint_as_float(id));
+              w.rays[2 * (W + s) + 1] = make_float4(ws.x, ws.y, ws.z, __uint_as_float(s | kShadowBit));
+              w.shcnt[s] = 0;
+              sh_cell = start_cell(S, so, ws);
+              if (sh_cell == kInvalidCell) w.shcnt[s] = 0;
+            }
+            if (depth < max_depth) {
+              const float am = a_sum / (float)B, bm = b_sum / (float)B;
+              if (am + bm > 0.0f) {
+                const float Ps = am / (am + bm);
+                cont = true;
+                if (u0 < Ps) {
+                  const float inv_p = 1.0f / Ps;
+                  for (int j = 0; j < B; ++j) {
+                    const float F = fresnel(nt[j], kt[j], cos_o);
+                    w.beta[(size_t)j * W + s] *= F * inv_p;
+                  }
+                  nd = d - ng * (2.0f * dn);
+                } else {
+                  const float inv_p = 1.0f / (1.0f - Ps);
+                  for (int j = 0; j < B; ++j) {
+                    const float F = fresnel(nt[j], kt[j], cos_o);
+                    w.beta[(size_t)j * W + s] *= (1.0f - F) * rt[j] * inv_p;
+                  }
+                  float sn, cn;
+                  sincosf(2.0f * 3.14159265358979f * u1, &sn, &cn);
+                  const float rr = sqrtf(u2);
+                  const float lx = rr * cn, ly = rr * sn, lz = sqrtf(fmaxf(0.0f, 1.0f - u2));
+                  // orthonormal basis around n (Duff et al., JCGT 2017)
+                  const float sg = copysignf(1.0f, n.z);
+                  const float aa = -1.0f / (sg + n.z);
+                  const float bb = n.x * n.y * aa;
+                  const F3 t1 = f3(1.0f + sg * n.x * n.x * aa, sg * bb, -sg * n.x);
+                  const F3 t2 = f3(bb, sg + n.y * n.y * aa, -n.y);
+                  nd = t1 * lx + t2 * ly + n * lz;
+                }
+                no = pt + n * eps;
+              }
+            }
+          } else if (depth < max_depth) {
+            float mr = 0.0f, mt = 0.0f;
+            const float th = S.thick[m];
+            for (int j = 0; j < B; ++j) {
+              float Rj, Tj;
+              slab(nt[j], kt[j], S.lambda[j], th, cos_o, Rj, Tj);
+              mr += Rj;
+              mt += Tj;
+            }
+            const float Pr = mr / (mr + mt);
+            cont = true;
+            if (u0 < Pr) {
+              const float inv_p = 1.0f / Pr;
+              for (int j = 0; j < B; ++j) {
+                float Rj, Tj;
+                slab(nt[j], kt[j], S.lambda[j], th, cos_o, Rj, Tj);
+                w.beta[(size_t)j * W + s] *= Rj * inv_p;
+              }
+              nd = d - ng * (2.0f * dn);
+              no = pt + n * eps;
+            } else {
+              const float inv_p = 1.0f / (1.0f - Pr);
+              for (int j = 0; j < B; ++j) {
+                float Rj, Tj;
+                slab(nt[j], kt[j], S.lambda[j], th, cos_o, Rj, Tj);
+                w.beta[(size_t)j * W + s] *= Tj * inv_p;
+              }
+              nd = d;
+              no = pt - n * eps;
+            }
+          }
+          if (cont) {
+            nflags |= kFlagExt;
+            w.rays[2 * s] = make_float4(no.x, no.y, no.z, __uint_as_float(id));
+            w.rays[2 * s + 1] = make_float4(nd.x, nd.y, nd.z, __uint_as_float(s));
+            ext_cell = start_cell(S, no, nd);
+            if (ext_cell == kInvalidCell) w.hit[s] = make_float4(INFINITY, __uint_as_float(0xFFFFFFFFu), 0.0f, 0.0f);
+          }
+        }
+      }
+      w.flags[s] = nflags;
+    }
+    // next active list: every slot with a ray in flight
+    const bool keep = valid && nflags != 0;
+    const uint64_t m = __ballot(keep);
+    if (m) {
+      const uint32_t leader = (uint32_t)__ffsll((unsigned long long)m) - 1u;
+      uint32_t base = 0;
+      if (lane_id() == leader) base = atomicAdd(&w.ctl->act_count[wr], (uint32_t)__popcll(m));
+      base = __shfl(base, (int)leader);
+      if (keep) w.active[(size_t)wr * W + base + count_below(m)] = s;
+    }
+    wave_append(valid && ext_cell != kInvalidCell, s | kFirstVisit, ext_cell, &w.ctl->list_count[p],
+                w.ccount + (size_t)p * S.n_cells, w.lsrc, w.ldst, w.lrank);
+    wave_append(valid && sh_cell != kInvalidCell, ((uint32_t)W + s) | kFirstVisit, sh_cell, &w.ctl->list_count[p],
+                w.ccount + (size_t)p * S.n_cells, w.lsrc, w.ldst, w.lrank);
+    wave_add(&w.ctl->st_vertices, n_vert);
+    wave_add(&w.ctl->st_shadow, n_sh);
+    wave_add(&w.ctl->st_ext, (valid && (nflags & kFlagExt)) ? 1u : 0u);
+  }
+}
+
+// ==========================================================================================
+// host-side launchers
+// ==========================================================================================
+static inline unsigned grid_for(size_t n, unsigned cap = 8192) {
+  size_t g = (n + kWG - 1) / kWG;
+  if (g < 1) g = 1;
+  return (unsigned)(g < cap ? g : cap);
+}
+
+hipError_t launch_fill_f32(hipStream_t s, float* p, size_t n, float v) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_f32, dim3(grid_for(n)), dim3(kWG), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(hipStream_t s, uint32_t* p, size_t n, uint32_t v) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n)), dim3(kWG), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_philox(hipStream_t s, const uint32_t ctr[4], const uint32_t key[2], uint64_t n, uint32_t* out) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_philox, dim3(grid_for(n)), dim3(kWG), 0, s, make_uint4(ctr[0], ctr[1], ctr[2], ctr[3]), key[0],
+                     key[1], n, (uint4*)out);
+  return hipGetLastError();
+}
+
+hipError_t launch_raygen(const Launch& L, const DevScene& S, const DevWS& w, uint64_t k0, uint32_t n, uint64_t seed,
+                         int gen) {
+  hipLaunchKernelGGL(k_raygen, dim3((n + kWG - 1) / kWG), dim3(kWG), 0, L.stream, S, w, k0, n, (uint32_t)seed,
+                     (uint32_t)(seed >> 32), gen);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan(const Launch& L, const DevScene& S, const DevWS& w, int gen) {
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, L.stream, S, w, gen);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter(const Launch& L, const DevWS& w, int gen) {
+  hipLaunchKernelGGL(k_scatter, dim3(grid_for(2 * (size_t)w.W, 4096)), dim3(kWG), 0, L.stream, w, gen);
+  return hipGetLastError();
+}
+
+hipError_t launch_trace(const Launch& L, const DevScene& S, const DevWS& w, int gen, int hops) {
+  hipLaunchKernelGGL(k_trace, dim3(L.trace_blocks), dim3(kWG), 0, L.stream, S, w, gen, hops);
+  return hipGetLastError();
+}
+
+hipError_t launch_shade(const Launch& L, const DevScene& S, const DevWS& w, int depth, int max_depth, uint64_t seed,
+                        int gen) {
+  hipLaunchKernelGGL(k_shade, dim3(grid_for(w.W, 4096)), dim3(kWG), 0, L.stream, S, w, depth, max_depth,
+                     (uint32_t)seed, (uint32_t)(seed >> 32), gen);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_rays(const Launch& L, const DevScene& S, const DevWS& w, const float* orig, const float* dir,
+                            const int32_t* skip, uint32_t n, int shadow, int gen) {
+  hipLaunchKernelGGL(k_pack_rays, dim3((n + kWG - 1) / kWG), dim3(kWG), 0, L.stream, S, w, orig, dir, skip, n, shadow,
+                     gen);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack_hits(const Launch& L, const DevWS& w, uint32_t n, float* t, int32_t* id, float* u, float* v) {
+  hipLaunchKernelGGL(k_unpack_hits, dim3(grid_for(n)), dim3(kWG), 0, L.stream, w, n, t, id, u, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_resolve_vis(const Launch& L, const DevScene& S, const DevWS& w, uint32_t n, float* vis) {
+  hipLaunchKernelGGL(k_resolve_vis, dim3(grid_for(n)), dim3(kWG), 0, L.stream, S, w, n, vis);
+  return hipGetLastError();
+}
+
+}  // namespace sdd

@@ -299,3 +299,209 @@ def random_rays(n: int, seed: int = 5, lo=-2.0, hi=12.0, aim_lo=0.0, aim_hi=10.0
     d = a - o
     d /= np.linalg.norm(d, axis=1, keepdims=True)
     return o.astype(np.float32), d.astype(np.float32)
+
+
+# ----------------------------------------------------------------------------------------------
+# C2 / C5: procedural church
+# ----------------------------------------------------------------------------------------------
+
+def _grid_tris(P, skip=None):
+    """Two triangles per cell of a point lattice P [nu+1][nv+1][3]; skip [nu][nv] drops cells."""
+    a, b = P[:-1, :-1], P[1:, :-1]
+    c, d = P[1:, 1:], P[:-1, 1:]
+    t1 = np.stack([a, b, c], axis=-2)
+    t2 = np.stack([a, c, d], axis=-2)
+    t = np.stack([t1, t2], axis=2)          # [nu][nv][2][3][3]
+    if skip is not None:
+        t = t[~skip]
+    return t.reshape(-1, 3, 3)
+
+
+def _lattice(origin, ex, ey, nu, nv):
+    u = np.linspace(0.0, 1.0, nu + 1)[:, None, None]
+    v = np.linspace(0.0, 1.0, nv + 1)[None, :, None]
+    return np.asarray(origin, float) + u * np.asarray(ex, float) + v * np.asarray(ey, float)
+
+
+def _pointed_arch(width, rise, n):
+    """Two-arc pointed arch over y in [0, width], springing at z = 0, apex at (width/2, rise).
+    Returns n+1 points (y, z) along the curve, uniform in angle on each arc."""
+    half = width / 2.0
+    R = (rise**2 + half**2) / (2 * half)       # arc radius: R^2 = rise^2 + (R - half)^2
+    phi_max = math.acos((R - half) / R)
+    m = n // 2
+    phi = np.linspace(0.0, phi_max, m + 1)
+    left = np.column_stack([R - R * np.cos(phi), R * np.sin(phi)])
+    right = np.column_stack([width - left[::-1, 0], left[::-1, 1]])
+    return np.vstack([left, right[1:]])
+
+
+def _sweep_square(path, half, n_seg):
+    """Square tube of half-width `half` swept along a polyline path [k][3] (4 faces)."""
+    path = np.asarray(path, float)
+    tng = np.gradient(path, axis=0)
+    tng /= np.linalg.norm(tng, axis=1, keepdims=True)
+    ref = np.where(np.abs(tng[:, 2:3]) < 0.9, np.array([[0, 0, 1.0]]), np.array([[1.0, 0, 0]]))
+    n1 = np.cross(tng, ref)
+    n1 /= np.linalg.norm(n1, axis=1, keepdims=True)
+    n2 = np.cross(tng, n1)
+    corners = [n1 + n2, -n1 + n2, -n1 - n2, n1 - n2, n1 + n2]
+    ring = np.stack([path + half * c for c in corners], axis=1)   # [k][5][3]
+    return _grid_tris(ring)
+
+
+def _cylinder(cx, cy, r, h, n_around, n_up):
+    th = np.linspace(0.0, 2 * math.pi, n_around + 1)
+    z = np.linspace(0.0, h, n_up + 1)
+    P = np.stack(np.broadcast_arrays(cx + r * np.cos(th)[:, None], cy + r * np.sin(th)[:, None], z[None, :]), -1)
+    return _grid_tris(P)
+
+
+def _window_spectrum(rng, lam):
+    k = np.full_like(lam, 1e-7)
+    for _ in range(rng.integers(1, 4)):
+        a, mu, sg = rng.uniform(2e-6, 2e-5), rng.uniform(400, 760), rng.uniform(15, 60)
+        k += a * np.exp(-((lam - mu) ** 2) / (2 * sg**2))
+    return k
+
+
+def church_scene(n_bins=40, target_tris=1_000_000, seed=SCENE_SEED, length=60.0, width=14.0, wall_h=14.0,
+                 rise=10.0, n_bays=10, tiers=2, lambda_min_nm=380.0, lambda_max_nm=780.0) -> Scene:
+    """Procedural church: a nave `length` x `width` m whose side walls (height wall_h) carry a
+    pointed two-arc barrel vault of the given rise, transverse and diagonal vault ribs at each
+    bay, two rows of cylindrical columns, and tiers x n_bays window openings per side closed by
+    glass quads with per-window Gaussian-bump absorption spectra. The tessellation density is
+    scaled so that the triangle count lands near `target_tris` (the exact count is recorded in
+    `info`). Materials: 0 floor, 1 walls, 2 columns, 3 vault and ribs (stone), 4.. glass."""
+    rng = np.random.default_rng(seed)
+    bay = length / n_bays
+    win_w = min(1.6, 0.4 * bay)
+    tier_z = [(3.0, 8.0), (9.5, 13.0)][:tiers] if tiers <= 2 else [
+        (1.0 + i * (wall_h - 2) / tiers, 1.0 + (i + 0.8) * (wall_h - 2) / tiers) for i in range(tiers)]
+
+    def counts(s):
+        fx = max(1, int(round(length * s)))                    # along the nave
+        fy = max(1, int(round(width * s)))
+        wz = max(1, int(round(wall_h * s)))
+        ez = max(1, int(round((wall_h + rise) * s)))
+        va = max(2, 2 * int(round(0.6 * (rise + width) * s)))  # around the vault arch (even)
+        ca = max(6, int(round(2 * math.pi * 0.6 * s * 0.9)))   # around a column
+        cu = max(1, int(round(wall_h * s * 0.9)))
+        rs = max(4, int(round((rise + width) * s * 0.5)))      # rib segments
+        return fx, fy, wz, ez, va, ca, cu, rs
+
+    def n_tris(s):
+        fx, fy, wz, ez, va, ca, cu, rs = counts(s)
+        return (2 * fx * fy + 2 * 2 * fx * wz + 2 * 2 * fy * ez + 2 * fx * va + 2 * n_bays * 2 * ca * cu
+                + (n_bays + 1 + 2 * n_bays) * 8 * rs)
+
+    lo_s, hi_s = 0.5, 200.0
+    for _ in range(60):
+        mid = math.sqrt(lo_s * hi_s)
+        lo_s, hi_s = (mid, hi_s) if n_tris(mid) < target_tris else (lo_s, mid)
+    fx, fy, wz, ez, va, ca, cu, rs = counts(lo_s)
+
+    parts, mats = [], []
+
+    def add(t, m):
+        parts.append(np.asarray(t, float).reshape(-1, 3, 3))
+        mats.append(np.full(len(parts[-1]), m, dtype=np.int64))
+
+    add(_grid_tris(_lattice((0, 0, 0), (length, 0, 0), (0, width, 0), fx, fy)), 0)
+    # side walls with window openings (cells whose centre falls in an opening are dropped)
+    uc = (np.arange(fx) + 0.5) * length / fx
+    vc = (np.arange(wz) + 0.5) * wall_h / wz
+    skip = np.zeros((fx, wz), dtype=bool)
+    windows = []
+    for side_y in (0.0, width):
+        for b in range(n_bays):
+            xc = (b + 0.5) * bay
+            for (z0, z1) in tier_z:
+                # snap the opening to the wall lattice so the glass exactly fills it
+                i0 = int(np.floor((xc - win_w / 2) * fx / length + 0.5))
+                i1 = max(i0 + 1, int(np.floor((xc + win_w / 2) * fx / length + 0.5)))
+                j0 = int(np.floor(z0 * wz / wall_h + 0.5))
+                j1 = max(j0 + 1, int(np.floor(z1 * wz / wall_h + 0.5)))
+                windows.append((side_y, i0 * length / fx, i1 * length / fx, j0 * wall_h / wz, j1 * wall_h / wz,
+                                (i0, i1, j0, j1)))
+    for side_y in (0.0, width):
+        sk = np.zeros((fx, wz), dtype=bool)
+        for (sy, x0, x1, z0, z1, (i0, i1, j0, j1)) in windows:
+            if sy == side_y:
+                sk[i0:i1, j0:j1] = True
+        add(_grid_tris(_lattice((0, side_y, 0), (length, 0, 0), (0, 0, wall_h), fx, wz), skip=sk), 1)
+    # end walls up to the vault apex
+    for side_x in (0.0, length):
+        add(_grid_tris(_lattice((side_x, 0, 0), (0, width, 0), (0, 0, wall_h + rise), fy, ez)), 1)
+    # columns: two rows, one per bay
+    for b in range(n_bays):
+        xc = (b + 0.5) * bay
+        for yc in (0.18 * width, 0.82 * width):
+            add(_cylinder(xc, yc, 0.6, wall_h, ca, cu), 2)
+    # pointed barrel vault
+    arch = _pointed_arch(width, rise, va)
+    P = np.stack(np.broadcast_arrays(np.linspace(0, length, fx + 1)[:, None], arch[None, :, 0],
+                                     wall_h + arch[None, :, 1]), -1)
+    add(_grid_tris(P), 3)
+    # transverse ribs at the bay boundaries, diagonal ribs across each bay (hanging under the vault)
+    rib = _pointed_arch(width, rise, 2 * rs)
+    for b in range(n_bays + 1):
+        x = b * bay
+        path = np.column_stack([np.full(len(rib), x), rib[:, 0], wall_h + rib[:, 1] - 0.2])
+        add(_sweep_square(path, 0.15, len(path) - 1), 3)
+    for b in range(n_bays):
+        for flip in (False, True):
+            s = np.linspace(0.0, 1.0, 2 * rs + 1)
+            y = s * width
+            x = b * bay + (1 - s if flip else s) * bay
+            z = wall_h + np.interp(y, rib[:, 0], rib[:, 1]) - 0.25
+            add(_sweep_square(np.column_stack([x, y, z]), 0.12, len(s) - 1), 3)
+    # glass quads
+    for wi, (sy, x0, x1, z0, z1, _) in enumerate(windows):
+        add(_grid_tris(_lattice((x0, sy, z0), (x1 - x0, 0, 0), (0, 0, z1 - z0), 1, 1)), 4 + wi)
+
+    verts = np.concatenate(parts).astype(np.float32)
+    mat = np.concatenate(mats).astype(np.uint16)
+    lam = bin_centres(n_bins, lambda_min_nm, lambda_max_nm)
+    n_glass = len(windows)
+    n_s, k_s, rho_s = _stone_tables(rng, n_bins, 4)
+    k_g = np.stack([_window_spectrum(rng, lam) for _ in range(n_glass)])
+    n_tab = np.vstack([n_s, np.full((n_glass, n_bins), 1.52)])
+    k_tab = np.vstack([k_s, k_g])
+    rho_tab = np.vstack([rho_s, np.zeros((n_glass, n_bins))])
+    n_mat = 4 + n_glass
+    return Scene(
+        verts=verts, mat=mat,
+        mat_type=np.array([MAT_OPAQUE] * 4 + [MAT_GLASS] * n_glass, dtype=np.int32),
+        thickness_m=np.array([0.0] * 4 + [0.005] * n_glass, dtype=np.float32),
+        n_tab=n_tab.astype(np.float32), k_tab=k_tab.astype(np.float32), rho_tab=rho_tab.astype(np.float32),
+        lambda_min_nm=lambda_min_nm, lambda_max_nm=lambda_max_nm,
+        sun_dir=sun_direction(35.0, -75.0), sun_E=sun_irradiance(n_bins, lambda_min_nm, lambda_max_nm),
+        env=np.zeros(n_bins, dtype=np.float32), name="church",
+        info=dict(n_tri=int(len(verts)), n_windows=n_glass, n_mat=n_mat, density=lo_s, length=length, width=width,
+                  wall_h=wall_h, rise=rise, n_bays=n_bays),
+    ).check()
+
+
+def church_camera(width=1920, height=1080, length=60.0, nave_w=14.0) -> Camera:
+    return Camera(eye=(2.0, 0.5 * nave_w, 1.7), target=(0.66 * length, 0.36 * nave_w, 9.0), up=(0.0, 0.0, 1.0),
+                  vfov_deg=60.0, width=width, height=height)
+
+
+RESOLUTIONS = [(256, 256), (512, 512), (640, 480), (800, 600), (1024, 768)]
+
+
+def batch_views(n_views=32, seed=VIEW_SEED, length=60.0, width=14.0):
+    """Seeded cameras inside the nave: eye height 1.2-2.5 m, yaw U[0, 360), pitch U[-10, 40] deg,
+    vfov 60, resolution from RESOLUTIONS, spp uniform in 4..64."""
+    rng = np.random.default_rng(seed)
+    cams, spps = [], []
+    for _ in range(n_views):
+        eye = np.array([rng.uniform(1.0, length - 1.0), rng.uniform(1.5, width - 1.5), rng.uniform(1.2, 2.5)])
+        yaw, pitch = math.radians(rng.uniform(0, 360)), math.radians(rng.uniform(-10, 40))
+        d = np.array([math.cos(pitch) * math.cos(yaw), math.cos(pitch) * math.sin(yaw), math.sin(pitch)])
+        w, h = RESOLUTIONS[rng.integers(len(RESOLUTIONS))]
+        cams.append(Camera(eye=tuple(eye), target=tuple(eye + d), up=(0.0, 0.0, 1.0), vfov_deg=60.0, width=w,
+                           height=h))
+        spps.append(int(rng.integers(4, 65)))
+    return cams, spps

@@ -1,0 +1,145 @@
+"""C-ABI checks that need no GPU: the library loads, exports what include/specdd.h declares,
+validates its inputs, and builds a cell-decomposed scene with the intended structure."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1912_04000_amd as sd
+import scenegen
+from paper_1912_04000_amd import _binding
+from sceneimg import EMPTY, SceneImage
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "specdd.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sdd_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = sd.lib()
+    names = _declared_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n
+    bound = {s[0] for s in _binding.SIGNATURES}
+    assert set(names) == bound, set(names) ^ bound
+
+
+def _desc_kwargs(sc):
+    return dict(verts=sc.verts, mat=sc.mat, mat_type=sc.mat_type, thickness_m=sc.thickness_m, n_tab=sc.n_tab,
+                k_tab=sc.k_tab, rho_tab=sc.rho_tab, lambda_min_nm=sc.lambda_min_nm, lambda_max_nm=sc.lambda_max_nm,
+                sun_dir=sc.sun_dir, sun_E=sc.sun_E, env=sc.env)
+
+
+@pytest.mark.parametrize("mutate,needle", [
+    (lambda k: k["verts"].__setitem__((3, 1, 2), np.nan), "non-finite vertex"),
+    (lambda k: k["mat"].__setitem__(5, 9), "material id"),
+    (lambda k: k["n_tab"].__setitem__((0, 0), 0.0), "n must be"),
+    (lambda k: k["k_tab"].__setitem__((0, 1), -1e-3), "k must be"),
+    (lambda k: k["rho_tab"].__setitem__((1, 2), 1.5), "rho"),
+    (lambda k: k["sun_dir"].__setitem__(slice(None), 0.0), "sun direction"),
+    (lambda k: k["sun_E"].__setitem__(0, np.inf), "sun irradiance"),
+    (lambda k: k.__setitem__("grid", (0, 2, 2)), "grid"),
+    (lambda k: k.__setitem__("grid", (65, 1, 1)), "grid"),
+    (lambda k: k.__setitem__("lambda_max_nm", 100.0), "wavelength"),
+])
+def test_scene_validation(mutate, needle):
+    sc = scenegen.nave_scene(8)
+    kw = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in _desc_kwargs(sc).items()}
+    kw["grid"] = (2, 2, 2)
+    mutate(kw)
+    with pytest.raises(sd.SddError) as e:
+        sd.Scene(**kw)
+    assert e.value.code == -1
+    assert needle in str(e.value)
+
+
+def test_too_many_bins_rejected():
+    sc = scenegen.plane_scene(n_bins=129)
+    with pytest.raises(sd.SddError):
+        sd.Scene.from_description(sc)
+
+
+@pytest.mark.parametrize("grid", [(1, 1, 1), (2, 2, 2), (4, 2, 2), (8, 8, 8), (3, 5, 2)])
+def test_scene_structure(grid):
+    sc = scenegen.nave_scene(8)
+    S = sd.Scene.from_description(sc, grid=grid)
+    info = S.info()
+    im = SceneImage(S.host_image())
+    assert im.h["magic"] == 0x53444431
+    assert int(im.h["n_cells"]) == grid[0] * grid[1] * grid[2] == info["n_cells"]
+    assert info["max_depth"] < 48
+    # planes strictly increasing and covering every vertex
+    v = sc.verts.reshape(-1, 3)
+    for a in range(3):
+        assert np.all(np.diff(im.planes[a]) > 0)
+        assert im.planes[a][0] < v[:, a].min() and im.planes[a][-1] > v[:, a].max()
+    # global triangles reproduce the input
+    np.testing.assert_array_equal(im.gtri_v, sc.verts)
+    # bin centres
+    np.testing.assert_allclose(im.lam, scenegen.bin_centres(8), rtol=1e-7)
+    refs = {}
+    for c, (nb, nn, tb, nt) in enumerate(im.cells):
+        ids = set(int(x) for x in im.ctri_id[tb:tb + nt])
+        assert len(ids) == nt  # no duplicate reference inside a cell
+        refs[c] = ids
+        if nt == 0:
+            assert nn == 0
+            continue
+        # walk the tree: leaf ranges partition the cell's triangle list, child boxes nest
+        covered = np.zeros(nt, dtype=int)
+        stack = [(0, None, None)]
+        while stack:
+            node, plo, phi = stack.pop()
+            for ch in range(2):
+                lo, hi, idx, cnt = im.child(nb + node, ch)
+                if idx == EMPTY:
+                    continue
+                if plo is not None:
+                    assert np.all(lo >= plo) and np.all(hi <= phi)
+                if cnt > 0:
+                    covered[idx:idx + cnt] += 1
+                    tv = im.ctri_v[tb + idx:tb + idx + cnt]
+                    tmin, tmax = tv.min(axis=1), tv.max(axis=1)
+                    # every triangle box meets the leaf box (boxes are clipped to the cell) ...
+                    assert np.all(tmax >= lo - 1e-6) and np.all(tmin <= hi + 1e-6)
+                    # ... and the leaf box is no larger than its triangles' box
+                    assert np.all(lo >= tmin.min(0) - 1e-6) and np.all(hi <= tmax.max(0) + 1e-6)
+                else:
+                    assert idx > node  # breadth-first order: children after parents
+                    stack.append((idx, lo, hi))
+        assert np.all(covered == 1)
+    # completeness: every point sampled on a triangle lies in a cell that references it
+    rng = np.random.default_rng(0)
+    for t in rng.choice(sc.n_tri, 300, replace=False):
+        tri = sc.verts[t].astype(np.float64)
+        for a, b in [(0, 0), (1, 0), (0, 1), (0.5, 0.5), (0.3, 0.3), (0.9, 0.05), (0.05, 0.9), (0.2, 0.7)]:
+            p = (1 - a - b) * tri[0] + a * tri[1] + b * tri[2]
+            assert int(t) in refs[im.cell_of_point(p)], (t, p)
+
+
+def test_degenerate_triangles_are_not_referenced():
+    sc = scenegen.random_soup(50, seed=3)
+    sc.verts[7] = sc.verts[7][0]  # zero area
+    S = sd.Scene.from_description(sc, grid=(2, 2, 2))
+    im = SceneImage(S.host_image())
+    assert 7 not in set(int(x) for x in im.ctri_id)
+
+
+def test_render_params_validation_without_gpu():
+    sc = scenegen.nave_scene(8)
+    S = sd.Scene.from_description(sc)
+    import ctypes as C
+    b = C.c_size_t()
+    for bad in [dict(spp=0), dict(max_depth=0), dict(max_depth=65), dict(mode=7), dict(wave_paths=10)]:
+        p = sd.render_params(**bad)
+        rc = sd.lib().sdd_workspace_bytes(S.handle, C.byref(p), C.byref(b))
+        assert rc == -1
+    p = sd.render_params(spp=4, max_depth=8, wave_paths=1 << 16)
+    assert sd.lib().sdd_workspace_bytes(S.handle, C.byref(p), C.byref(b)) == 0
+    assert b.value > (1 << 16) * 8 * 8

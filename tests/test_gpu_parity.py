@@ -1,0 +1,237 @@
+"""Parity of the HIP path (through the C ABI) against the CPU oracle, on one MI355X.
+
+Bars: triangle ids bit-exact on rays the oracle does not flag as tied, hit distance within
+1e-5 relative; Philox bit-exact; per-pixel spectral radiance within 1e-4 relative
+(|a - b| <= 1e-4 max(|b|, 1e-3 mean_bin)) on tie-free pixels with identical RNG streams.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import scenegen
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1912_04000_amd as sd
+    return sd.Context(0)
+
+
+def _dev(a, torch_dtype=None):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _scene(ctx, sc, grid):
+    import paper_1912_04000_amd as sd
+    S = sd.Scene.from_description(sc, grid=grid)
+    ctx.upload(S)
+    return S
+
+
+def _interior_rays(n, seed, lo, hi):
+    rng = np.random.default_rng(seed)
+    o = rng.uniform(lo, hi, size=(n, 3))
+    d = rng.normal(size=(n, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    return o.astype(np.float32), d.astype(np.float32)
+
+
+def _compare_hits(ctx, sc, S, o, d, skip=None, label=""):
+    t, ids, u, v = ctx.trace(S, _dev(o), _dev(d), None if skip is None else _dev(skip))
+    t, ids = t.cpu().numpy(), ids.cpu().numpy()
+    ot, oid, ou, ov, tie = oracle.intersect(sc, o, d, skip=skip)
+    ok = ~tie
+    mism = np.nonzero(ok & (ids != oid))[0]
+    say(f"[{label}] rays={len(o)} tied={tie.sum()} hits={(oid >= 0).sum()} id-mismatch={len(mism)}")
+    assert len(mism) == 0, (mism[:10], ids[mism[:10]], oid[mism[:10]], t[mism[:10]], ot[mism[:10]])
+    h = ok & (oid >= 0)
+    rel = np.abs(t[h] - ot[h]) / np.maximum(ot[h], 1e-30)
+    say(f"[{label}] max rel t error {rel.max() if rel.size else 0:.3e}")
+    assert rel.size == 0 or rel.max() <= 1e-5
+    assert np.all(np.isinf(t[ok & (oid < 0)]))
+    return ids, t, tie
+
+
+def test_philox_bit_exact(ctx):
+    say("philox: 2^18 counters vs oracle")
+    base, key = (7, 3, (1 << 24) | 2, 5), (0x12345678, 0x9ABCDEF0)
+    g = ctx.philox(base, key, 1 << 18).cpu().numpy().view(np.uint32)
+    o = oracle.philox_stream(base, key, 1 << 18)
+    assert np.array_equal(g, o)
+    kat = ctx.philox((0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344), (0xA4093822, 0x299F31D0), 1)
+    assert [int(x) for x in kat.cpu().numpy().view(np.uint32)[0]] == [0xD16CFE09, 0x94FDCCEB, 0x5001E420, 0x24126EA1]
+
+
+@pytest.mark.parametrize("grid", [(1, 1, 1), (2, 2, 2), (4, 2, 2), (8, 8, 8)])
+def test_trace_parity_nave(ctx, grid):
+    sc = scenegen.nave_scene(8)
+    S = _scene(ctx, sc, grid)
+    o, d = _interior_rays(40000, 1, [0.2, 0.2, 0.2], [19.8, 9.8, 7.8])
+    _compare_hits(ctx, sc, S, o, d, label=f"nave grid={grid}")
+
+
+def test_trace_grid_invariance_exact(ctx):
+    sc = scenegen.nave_scene(8)
+    o, d = _interior_rays(30000, 2, [-3, -3, -3], [23, 13, 11])  # also origins outside the grid
+    out = []
+    for grid in [(1, 1, 1), (2, 2, 2), (4, 2, 2), (8, 8, 8), (3, 5, 7)]:
+        S = _scene(ctx, sc, grid)
+        t, ids, u, v = ctx.trace(S, _dev(o), _dev(d))
+        out.append((ids.cpu().numpy(), t.cpu().numpy()))
+        say(f"grid {grid}: hits={(out[-1][0] >= 0).sum()}")
+    for ids, t in out[1:]:
+        assert np.array_equal(ids, out[0][0])
+        assert np.array_equal(t, out[0][1])
+
+
+@pytest.mark.parametrize("grid", [(1, 1, 1), (4, 4, 4)])
+def test_trace_parity_soup(ctx, grid):
+    sc = scenegen.random_soup(3000, seed=4, extent=10.0, size=0.6)
+    S = _scene(ctx, sc, grid)
+    o, d = scenegen.random_rays(30000, seed=9)
+    _compare_hits(ctx, sc, S, o, d, label=f"soup grid={grid}")
+
+
+def test_trace_skip_and_ragged(ctx):
+    sc = scenegen.nave_scene(8)
+    S = _scene(ctx, sc, (2, 2, 2))
+    # rays spawned from triangle centroids, skipping their own triangle; odd count (ragged tail)
+    rng = np.random.default_rng(3)
+    tri = rng.choice(sc.n_tri, 3001)
+    c = sc.verts[tri].astype(np.float64).mean(axis=1)
+    d = rng.normal(size=(3001, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    _compare_hits(ctx, sc, S, c.astype(np.float32), d.astype(np.float32), skip=tri.astype(np.int32), label="skip")
+    # a single ray
+    _compare_hits(ctx, sc, S, c[:1].astype(np.float32), d[:1].astype(np.float32), label="one ray")
+
+
+def test_shadow_parity(ctx):
+    sc = scenegen.nave_scene(8)
+    S = _scene(ctx, sc, (2, 2, 2))
+    rng = np.random.default_rng(4)
+    # points on the floor and walls toward the sun
+    n = 20000
+    o = np.column_stack([rng.uniform(0.5, 19.5, n), rng.uniform(0.5, 9.5, n), rng.uniform(0.01, 7.5, n)])
+    d = np.tile(sc.sun_dir, (n, 1))
+    o32, d32 = o.astype(np.float32), d.astype(np.float32)
+    vis = ctx.shadow(S, _dev(o32), _dev(d32)).cpu().numpy()
+    ovis, tie = oracle.shadow(sc, o32, d32)
+    ok = ~tie
+    lit = ok & (ovis[:, 0] > 0)
+    say(f"shadow: tied={tie.sum()} lit={lit.sum()} through-glass={(ok & (ovis[:, 0] > 0) & (ovis[:, 0] < 1)).sum()}")
+    assert np.array_equal(vis[ok] == 0, ovis[ok] == 0)
+    np.testing.assert_allclose(vis[ok], ovis[ok], rtol=2e-6, atol=1e-7)
+    assert (ok & (ovis[:, 0] > 0) & (ovis[:, 0] < 1)).sum() > 50  # glass really crossed
+
+
+def _pixel_parity(img, ref, tied, label):
+    B = ref.shape[0]
+    mean_bin = ref.reshape(B, -1).mean(axis=1)
+    tol = 1e-4 * np.maximum(np.abs(ref), 1e-3 * mean_bin[:, None, None])
+    ok = tied == 0
+    bad = (np.abs(img - ref) > tol) & ok[None]
+    say(f"[{label}] pixels={ok.size} tie-free={ok.sum()} bad={bad.any(axis=0).sum()} "
+        f"max rel={np.max(np.abs(img - ref)[:, ok] / np.maximum(np.abs(ref)[:, ok], 1e-12)):.3e}")
+    assert not bad.any(), np.argwhere(bad)[:10]
+    return ok
+
+
+def test_render_c1_parity(ctx):
+    import paper_1912_04000_amd as sd
+    sc = scenegen.nave_scene(8)
+    cam = scenegen.nave_camera()
+    S = _scene(ctx, sc, (2, 2, 2))
+    img = ctx.render(S, sd.camera(cam.eye, cam.target, cam.up, cam.vfov_deg, cam.width, cam.height),
+                     sd.render_params(spp=1, max_depth=4, seed=1)).cpu().numpy()
+    ref = oracle.render(sc, cam, spp=1, max_depth=4, seed=1)
+    st = ctx.stats()
+    say(f"C1 stats: {st}")
+    say(f"C1 oracle stats: {ref.stats}")
+    ok = _pixel_parity(img, ref.image, ref.tied, "C1")
+    assert ok.mean() > 0.97
+    assert ref.image.max() > 0.05  # the sun really lights the nave
+
+
+@pytest.mark.parametrize("spp,depth,grid,wave,migrate", [
+    (3, 6, (4, 2, 2), 0, 0), (2, 4, (1, 1, 1), 1000, 1), (1, 8, (8, 8, 8), 64, 20)])
+def test_render_parity_variants(ctx, spp, depth, grid, wave, migrate):
+    import paper_1912_04000_amd as sd
+    sc = scenegen.nave_scene(8)
+    cam = scenegen.nave_camera(48, 40)
+    S = _scene(ctx, sc, grid)
+    img = ctx.render(S, sd.camera(cam.eye, cam.target, cam.up, cam.vfov_deg, cam.width, cam.height),
+                     sd.render_params(spp=spp, max_depth=depth, seed=11, wave_paths=wave,
+                                      migrate_rounds=migrate)).cpu().numpy()
+    ref = oracle.render(sc, cam, spp=spp, max_depth=depth, seed=11)
+    ok = _pixel_parity(img, ref.image, ref.tied, f"spp={spp} D={depth} grid={grid} W={wave}")
+    assert ok.mean() > 0.9
+
+
+def test_white_furnace_gpu(ctx):
+    import paper_1912_04000_amd as sd
+    sc = scenegen.furnace_scene(n_bins=4)
+    S = _scene(ctx, sc, (4, 4, 2))
+    img = ctx.render(S, sd.camera((0.0, -14.0, 6.0), (0.0, 0.0, 0.5), (0, 0, 1), 70, 32, 32),
+                     sd.render_params(spp=4, max_depth=64, seed=5)).cpu().numpy()
+    say(f"furnace: min={img.min()} max={img.max()}")
+    np.testing.assert_allclose(img, 1.0, atol=1e-5)
+
+
+def test_nee_closed_form_gpu(ctx):
+    import paper_1912_04000_amd as sd
+    B = 8
+    sc = scenegen.plane_scene(n_bins=B, n=1.6, k=0.02, rho=0.8, sun_dir=(0, 0, 1), window=(6.0, 4.0), glass_k=3e-6)
+    S = _scene(ctx, sc, (2, 2, 2))
+    img = ctx.render(S, sd.camera((0.0, 0.3, 3.0), (0.0, 0.3, 0.0), (0, 1, 0), 1e-4, 2, 2),
+                     sd.render_params(spp=1, max_depth=1)).cpu().numpy()
+    lam = scenegen.bin_centres(B)
+    f = lambda x: float(np.float32(x))
+    F0 = ((f(1.6) - 1) ** 2 + f(0.02) ** 2) / ((f(1.6) + 1) ** 2 + f(0.02) ** 2)
+    G1 = ((f(1.52) - 1) ** 2 + f(3e-6) ** 2) / ((f(1.52) + 1) ** 2 + f(3e-6) ** 2)
+    tau = np.exp(-4 * np.pi * f(3e-6) / (lam * 1e-9) * f(0.005))
+    T = (1 - G1) ** 2 * tau / (1 - G1**2 * tau**2)
+    exp = (1 - F0) * f(0.8) / np.pi * sc.sun_E.astype(np.float64) * T
+    np.testing.assert_allclose(img[:, 0, 0], exp, rtol=2e-6)
+
+
+def test_batch_matches_single_views(ctx):
+    import paper_1912_04000_amd as sd
+    sc = scenegen.nave_scene(8)
+    S = _scene(ctx, sc, (2, 2, 2))
+    cams = [sd.camera((3.0, 8.0, 1.7), (12.0, 1.0, 1.5), (0, 0, 1), 60, 40, 30),
+            sd.camera((15.0, 2.0, 3.0), (5.0, 8.0, 1.0), (0, 0, 1), 75, 17, 23),
+            sd.camera((10.0, 5.0, 6.0), (10.0, 5.0, 0.0), (0, 1, 0), 90, 32, 32)]
+    spp = [2, 5, 1]
+    p = sd.render_params(max_depth=5, seed=3, wave_paths=2000)
+    outs = [o.cpu().numpy() for o in ctx.render_batch(S, cams, spp, p)]
+    for v, (c, s) in enumerate(zip(cams, spp)):
+        single = ctx.render(S, c, sd.render_params(spp=s, max_depth=5, seed=3, view=v)).cpu().numpy()
+        err = np.abs(outs[v] - single).max() / max(single.max(), 1e-12)
+        say(f"view {v}: max rel diff {err:.3e}")
+        assert err < 1e-5
+
+
+def test_workspace_too_small_is_reported(ctx):
+    import ctypes as C
+    import torch
+    import paper_1912_04000_amd as sd
+    sc = scenegen.nave_scene(8)
+    S = _scene(ctx, sc, (2, 2, 2))
+    ws = torch.empty(1024, dtype=torch.uint8, device="cuda")
+    img = torch.empty((8, 4, 4), dtype=torch.float32, device="cuda")
+    cam = sd.camera((3.0, 8.0, 1.7), (12.0, 1.0, 1.5), (0, 0, 1), 60, 4, 4)
+    p = sd.render_params()
+    rc = sd.lib().sdd_render(ctx.handle, S.handle, C.byref(cam), C.byref(p), C.c_void_p(ws.data_ptr()), 1024,
+                             C.c_void_p(img.data_ptr()))
+    assert rc == -3
