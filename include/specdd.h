@@ -124,11 +124,15 @@ typedef struct {
   uint64_t seed;               /* Philox key                                                   */
   int32_t mode;                /* SDD_MODE_PLAIN or SDD_MODE_CACHED                            */
   int32_t wave_paths;          /* paths in flight per wavefront, >= 64 (0 = library default)   */
-  int32_t migrate_rounds;      /* cell-queue rounds in which rays migrate one cell at a time
-                                  before a final round walks the remaining cells in place
-                                  (0 = library default; >= grid sum = pure migration)          */
+  int32_t queue_rounds;        /* traversal rounds per wavefront phase (0 = library default 2):
+                                  in each round but the last a ray is traversed in one cell and
+                                  then migrates to the queue of the next cell along it; in the
+                                  last round rays walk their remaining cells in place         */
   uint32_t view;               /* view index used in the RNG counter (sdd_render only)         */
   int32_t timing;              /* 1: time the traversal launches with HIP events (stats)       */
+  int32_t first_sample;        /* samples [first_sample, first_sample + spp) of each pixel are
+                                  drawn; renders of consecutive sample ranges average exactly
+                                  to one longer render (progressive / resumable rendering)    */
 } sdd_render_params;
 
 /* Workspace bytes for rendering with these parameters (paths in flight, bins, cells). */
@@ -179,6 +183,7 @@ typedef struct {
   uint64_t paths, vertices, ext_rays, shadow_rays, cell_visits, migrations, escapes, glass_crossings;
   uint64_t trace_launches, shade_launches, wavefronts;
   uint64_t err_cross_overflow, err_nonfinite, err_stack;
+  uint64_t node_visits, tri_tests; /* BVH nodes visited and triangle tests of the traversal     */
   double trace_ms;             /* HIP-event time of the traversal launches (timing = 1)      */
   double shade_ms;             /* HIP-event time of the shading launches (timing = 1)        */
 } sdd_stats;

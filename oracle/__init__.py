@@ -54,7 +54,7 @@ class _Params(C.Structure):
     _fields_ = [("spp", C.c_int32), ("max_depth", C.c_int32), ("seed", C.c_uint64), ("view", C.c_uint32),
                 ("threads", C.c_int32), ("force_bvh", C.c_int32), ("tie_t_rel", C.c_double),
                 ("tie_edge_abs", C.c_double), ("tie_edge_rel_t", C.c_double), ("tie_lobe", C.c_double),
-                ("tie_cos_sun", C.c_double), ("cached", C.c_int32)]
+                ("tie_cos_sun", C.c_double), ("cached", C.c_int32), ("first_sample", C.c_int32)]
 
 
 class _Queries(C.Structure):
@@ -91,10 +91,10 @@ def _p(a):
 class TieParams:
     """Margins that decide when FP32 rounding could change a path's outcome."""
     t_rel: float = 1e-5
-    edge_abs: float = 4e-6
-    edge_rel_t: float = 4e-6
+    edge_abs: float = 2e-6
+    edge_rel_t: float = 2e-6
     lobe: float = 2e-5
-    cos_sun: float = 1e-6
+    cos_sun: float = 1e-6      # also: grazing hits and normals with 0 < |n_z| below it
 
 
 def _scene_struct(sc):
@@ -181,7 +181,7 @@ class RenderResult:
 
 
 def render(scene, camera, spp=1, max_depth=4, seed=1, view=0, pixels=None, threads=None,
-           tie: TieParams = TieParams(), force_bvh=-1, cached=False) -> RenderResult:
+           tie: TieParams = TieParams(), force_bvh=-1, cached=False, first_sample=0) -> RenderResult:
     """Reference spectral image (mean of spp path samples per pixel), FP64 accumulation.
     With cached=True the paths stop at the vertex after bounce 2 and the query there
     (position, direction toward the previous vertex, material, throughput) is returned."""
@@ -190,7 +190,7 @@ def render(scene, camera, spp=1, max_depth=4, seed=1, view=0, pixels=None, threa
                   float(camera.vfov_deg), int(camera.width), int(camera.height))
     th = threads or min(8, os.cpu_count() or 1)
     prm = _Params(int(spp), int(max_depth), int(seed), int(view), int(th), int(force_bvh), tie.t_rel, tie.edge_abs,
-                  tie.edge_rel_t, tie.lobe, tie.cos_sun, 1 if cached else 0)
+                  tie.edge_rel_t, tie.lobe, tie.cos_sun, 1 if cached else 0, int(first_sample))
     B = scene.n_bins
     if pixels is None:
         npx = camera.width * camera.height

@@ -364,6 +364,7 @@ typedef struct {
   int32_t force_bvh;         // -1 auto (BVH above 1e4 triangles), 0 brute force, 1 BVH
   double tie_t_rel, tie_edge_abs, tie_edge_rel_t, tie_lobe, tie_cos_sun;
   int32_t cached;            // 1: stop at vertex 3 and record the cache query instead
+  int32_t first_sample;      // sample indices first_sample .. first_sample + spp - 1
 } orc_params;
 
 void orc_philox4x32_10(const uint32_t* ctr, const uint32_t* key, uint32_t* out) {
@@ -513,7 +514,8 @@ int orc_render(const orc_scene* sc, const orc_camera* cam, const orc_params* prm
     int64_t pix = pixels ? pixels[i] : i;
     int px = (int)(pix % W), py = (int)(pix / W);
     std::fill(acc.begin(), acc.end(), 0.0);
-    for (int s = 0; s < spp; ++s) {
+    for (int si = 0; si < spp; ++si) {
+      const int s = prm->first_sample + si;
       bool tied = false;
       std::fill(L.begin(), L.end(), 0.0);
       std::fill(beta.begin(), beta.end(), 1.0);
@@ -534,11 +536,13 @@ int orc_render(const orc_scene* sc, const orc_camera* cam, const orc_params* prm
         double dn = dot(d, ng);
         V3 n = dn > 0 ? ng * -1.0 : ng;  // face forward: -sign(d . n_g) n_g
         double cos_o = std::fabs(dn);
+        // grazing hit: the side the surface is seen from (and so the spawn side) is uncertain
+        if (cos_o <= tie.cos_sun) tied = true;
         V3 p = T.v0 * (1.0 - h.u - h.v) + T.v1 * h.u + T.v2 * h.v;
         double eps = 1e-5 * (1.0 + maxabs(p));
         int m = T.mat;
         if (prm->cached && dep == 3) {
-          int64_t q = i * spp + s;
+          int64_t q = i * spp + si;
           cq->x[3 * q] = p.x; cq->x[3 * q + 1] = p.y; cq->x[3 * q + 2] = p.z;
           cq->wo[3 * q] = -d.x; cq->wo[3 * q + 1] = -d.y; cq->wo[3 * q + 2] = -d.z;
           cq->mat[q] = m;
@@ -587,7 +591,9 @@ int orc_render(const orc_scene* sc, const orc_camera* cam, const orc_params* prm
             for (int j = 0; j < B; ++j) beta[j] *= (1.0 - F[j]) * rt[j] / (1.0 - Ps);
             double phi = 2.0 * M_PI * u1, rr = std::sqrt(u2);
             double lx = rr * std::cos(phi), ly = rr * std::sin(phi), lz = std::sqrt(std::max(0.0, 1.0 - u2));
-            // orthonormal basis around n (Duff et al. 2017)
+            // orthonormal basis around n (Duff et al. 2017); the frame switches with the sign
+            // of n_z, so a normal with a tiny non-zero z could land on either side in FP32
+            if (n.z != 0.0 && std::fabs(n.z) <= tie.cos_sun) tied = true;
             double sgn = std::copysign(1.0, n.z);
             double aa = -1.0 / (sgn + n.z);
             double bb = n.x * n.y * aa;

@@ -53,14 +53,15 @@ class Camera(C.Structure):
 
 class RenderParams(C.Structure):
     _fields_ = [("spp", C.c_int32), ("max_depth", C.c_int32), ("seed", C.c_uint64), ("mode", C.c_int32),
-                ("wave_paths", C.c_int32), ("migrate_rounds", C.c_int32), ("view", C.c_uint32),
-                ("timing", C.c_int32)]
+                ("wave_paths", C.c_int32), ("queue_rounds", C.c_int32), ("view", C.c_uint32),
+                ("timing", C.c_int32), ("first_sample", C.c_int32)]
 
 
 class Stats(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in (
         "paths", "vertices", "ext_rays", "shadow_rays", "cell_visits", "migrations", "escapes", "glass_crossings",
-        "trace_launches", "shade_launches", "wavefronts", "err_cross_overflow", "err_nonfinite", "err_stack")] + [
+        "trace_launches", "shade_launches", "wavefronts", "err_cross_overflow", "err_nonfinite", "err_stack",
+        "node_visits", "tri_tests")] + [
         ("trace_ms", C.c_double), ("shade_ms", C.c_double)]
 
     def as_dict(self):
@@ -204,10 +205,12 @@ def camera(eye, target, up=(0.0, 0.0, 1.0), vfov_deg=60.0, width=64, height=64) 
     return c
 
 
-def render_params(spp=1, max_depth=4, seed=1, mode=MODE_PLAIN, wave_paths=0, migrate_rounds=0, view=0, timing=0):
+def render_params(spp=1, max_depth=4, seed=1, mode=MODE_PLAIN, wave_paths=0, queue_rounds=0, view=0, timing=0,
+                  first_sample=0):
     p = RenderParams()
+    p.first_sample = int(first_sample)
     p.spp, p.max_depth, p.seed, p.mode = int(spp), int(max_depth), int(seed), int(mode)
-    p.wave_paths, p.migrate_rounds, p.view, p.timing = int(wave_paths), int(migrate_rounds), int(view), int(timing)
+    p.wave_paths, p.queue_rounds, p.view, p.timing = int(wave_paths), int(queue_rounds), int(view), int(timing)
     return p
 
 

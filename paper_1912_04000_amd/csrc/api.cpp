@@ -43,7 +43,7 @@ int fail(sdd_ctx* c, int code, const std::string& msg) {
   } while (0)
 
 constexpr int kDefaultWave = 1 << 20;
-constexpr int kDefaultMigrate = 3;
+constexpr int kDefaultRounds = 2;
 constexpr int kMaxViewsPerStore = 16;
 
 struct ViewBlock {
@@ -184,7 +184,8 @@ std::string check_params(const sdd_render_params* p) {
   if (p->max_depth < 1 || p->max_depth > 64) return "max_depth must lie in 1..64";
   if (p->mode != SDD_MODE_PLAIN && p->mode != SDD_MODE_CACHED) return "unknown mode";
   if (p->wave_paths != 0 && (p->wave_paths < 64 || p->wave_paths > (1 << 26))) return "wave_paths out of range";
-  if (p->migrate_rounds < 0 || p->migrate_rounds > 256) return "migrate_rounds out of range";
+  if (p->queue_rounds < 0 || p->queue_rounds > 256) return "queue_rounds out of range";
+  if (p->first_sample < 0) return "first_sample must be >= 0";
   return "";
 }
 
@@ -209,12 +210,12 @@ void record(sdd_ctx* ctx, std::vector<std::pair<hipEvent_t, hipEvent_t>>& pool, 
   }
 }
 
-// Trace every entry produced so far: rounds of (scan, scatter, trace). In the first
-// `migrate` rounds a ray visits one cell and migrates to the next cell's queue; the last
-// round walks the remaining rays through their remaining cells in place.
-int trace_phase(sdd_ctx* ctx, const Launch& L, const DevScene& S, const DevWS& w, int& gen, int migrate, bool timing) {
-  for (int r = 0; r <= migrate; ++r) {
-    const int hops = r == migrate ? (1 << 30) : 1;
+// Trace every entry produced so far: rounds of (scan, scatter, trace). In every round but the
+// last a ray visits one cell and migrates to the next cell's queue; the last round walks the
+// remaining rays through their remaining cells in place.
+int trace_phase(sdd_ctx* ctx, const Launch& L, const DevScene& S, const DevWS& w, int& gen, int rounds, bool timing) {
+  for (int r = 0; r < rounds; ++r) {
+    const int hops = r == rounds - 1 ? (1 << 30) : 1;
     HIP_TRY(ctx, launch_scan(L, S, w, gen));
     HIP_TRY(ctx, launch_scatter(L, w, gen));
     if (timing) record(ctx, ctx->ev_trace, ctx->ev_used_trace, true);
@@ -256,7 +257,7 @@ int render_views(sdd_ctx* ctx, const sdd_scene* scene, std::vector<ViewDesc>& vi
   DevWS w = ws_view(plan, ws);
   DevScene S = device_view(scene);
   Launch L{ctx->stream, plan.trace_blocks};
-  const int migrate = p->migrate_rounds ? p->migrate_rounds : kDefaultMigrate;
+  const int rounds = p->queue_rounds ? p->queue_rounds : kDefaultRounds;
   const bool timing = p->timing != 0;
   int rc = store_views(ctx, views, w);
   if (rc) return rc;
@@ -269,7 +270,7 @@ int render_views(sdd_ctx* ctx, const sdd_scene* scene, std::vector<ViewDesc>& vi
   for (uint64_t k0 = 0; k0 < total; k0 += W) {
     const uint32_t n = (uint32_t)std::min<uint64_t>(W, total - k0);
     HIP_TRY(ctx, launch_raygen(L, S, w, k0, n, p->seed, gen));
-    rc = trace_phase(ctx, L, S, w, gen, migrate, timing);
+    rc = trace_phase(ctx, L, S, w, gen, rounds, timing);
     if (rc) return rc;
     for (int d = 1; d <= D + 1; ++d) {
       if (timing) record(ctx, ctx->ev_shade, ctx->ev_used_shade, true);
@@ -277,7 +278,7 @@ int render_views(sdd_ctx* ctx, const sdd_scene* scene, std::vector<ViewDesc>& vi
       if (timing) record(ctx, ctx->ev_shade, ctx->ev_used_shade, false);
       ctx->acc.shade_launches++;
       if (d <= D) {
-        rc = trace_phase(ctx, L, S, w, gen, migrate, timing);
+        rc = trace_phase(ctx, L, S, w, gen, rounds, timing);
         if (rc) return rc;
       }
     }
@@ -400,6 +401,7 @@ int sdd_render(sdd_ctx* c, const sdd_scene* s, const sdd_camera* cam, const sdd_
   views[0].inv_spp = 1.0f / (float)p->spp;
   views[0].image = image;
   views[0].view_id = p->view;
+  views[0].first_sample = (uint32_t)p->first_sample;
   HIP_TRY(c, hipSetDevice(c->device));
   return render_views(c, s, views, p, ws, ws_bytes);
 }
@@ -424,6 +426,7 @@ int sdd_render_batch(sdd_ctx* c, const sdd_scene* s, const sdd_camera* cams, con
     views[v].inv_spp = 1.0f / (float)spp[v];
     views[v].image = images[v];
     views[v].view_id = (uint32_t)v;
+    views[v].first_sample = (uint32_t)p->first_sample;
   }
   HIP_TRY(c, hipSetDevice(c->device));
   return render_views(c, s, views, p, ws, ws_bytes);
@@ -456,7 +459,7 @@ static int query(sdd_ctx* c, const sdd_scene* s, const float* orig, const float*
   for (int64_t a = 0; a < n; a += W) {
     uint32_t m = (uint32_t)std::min<int64_t>(W, n - a);
     HIP_TRY(c, launch_pack_rays(L, S, w, orig + 3 * a, dir + 3 * a, skip ? skip + a : nullptr, m, shadow ? 1 : 0, gen));
-    rc = trace_phase(c, L, S, w, gen, kDefaultMigrate, false);
+    rc = trace_phase(c, L, S, w, gen, kDefaultRounds, false);
     if (rc) return rc;
     if (shadow)
       HIP_TRY(c, launch_resolve_vis(L, S, w, m, vis + (size_t)a * s->hdr.n_bins));
@@ -504,6 +507,8 @@ int sdd_finish(sdd_ctx* c) {
     c->acc.err_cross_overflow += h.err_cross;
     c->acc.err_nonfinite += h.err_nonfinite;
     c->acc.err_stack += h.err_stack;
+    c->acc.node_visits += h.st_nodes;
+    c->acc.tri_tests += h.st_tris;
     if (h.err_cross) status = fail(c, SDD_ERR_QUEUE_OVERFLOW, "a shadow ray crossed more glass slabs than recorded");
     c->last_ctl = nullptr;
   }

@@ -92,7 +92,7 @@ struct ViewDesc {
   uint64_t image_off;  // float offset of this view's image inside the image arena (batch)
   float* image;        // [B][H][W]
   uint32_t view_id;
-  int32_t pad;
+  uint32_t first_sample;
 };
 
 // Control block (device) -- counters of the wavefront machinery and statistics.
@@ -104,7 +104,8 @@ struct Ctl {
   uint32_t pad0[9];
   unsigned long long st_paths, st_vertices, st_ext, st_shadow, st_visits, st_migr, st_escape, st_glass;
   unsigned long long err_cross, err_nonfinite, err_stack;
-  unsigned long long pad1[5];
+  unsigned long long st_nodes, st_tris;  // BVH nodes visited, triangle tests (traversal work)
+  unsigned long long pad1[3];
 };
 
 // Device view of a workspace.

@@ -30,6 +30,22 @@ __device__ __forceinline__ F3 norm3(F3 a) { return a * (1.0f / sqrtf(dot3(a, a))
 __device__ __forceinline__ float maxabs3(F3 a) { return fmaxf(fabsf(a.x), fmaxf(fabsf(a.y), fabsf(a.z))); }
 __device__ __forceinline__ float comp(F3 a, int k) { return k == 0 ? a.x : (k == 1 ? a.y : a.z); }
 
+// Geometric normal and the dot products whose sign selects a branch (face side, sun side),
+// evaluated without FMA contraction: an exactly cancelling sum (a vertical facet's z, for
+// example) then stays exactly zero, as in exact arithmetic, instead of keeping the rounding
+// error of one product, which would flip the sign-dependent choices downstream.
+__device__ __forceinline__ F3 geo_normal(F3 v0, F3 v1, F3 v2) {
+#pragma clang fp contract(off)
+  const F3 e1 = v1 - v0, e2 = v2 - v0;
+  const F3 c = {e1.y * e2.z - e1.z * e2.y, e1.z * e2.x - e1.x * e2.z, e1.x * e2.y - e1.y * e2.x};
+  const float l2 = c.x * c.x + c.y * c.y + c.z * c.z;
+  return c * (1.0f / sqrtf(l2));
+}
+__device__ __forceinline__ float dot_exact_sign(F3 a, F3 b) {
+#pragma clang fp contract(off)
+  return a.x * b.x + a.y * b.y + a.z * b.z;
+}
+
 // Philox4x32-10 (Salmon et al., SC'11).
 __device__ __forceinline__ uint4 philox(uint4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
@@ -244,7 +260,7 @@ __global__ __launch_bounds__(kWG) void k_raygen(DevScene S, DevWS w, uint64_t k0
     const ViewDesc& V = w.views[v];
     const uint64_t local = k - V.item_base;
     const uint64_t P = (uint64_t)V.width * V.height;
-    const uint32_t s = (uint32_t)(local / P);
+    const uint32_t s = (uint32_t)(local / P) + V.first_sample;
     const uint32_t pix = (uint32_t)(local % P);
     const uint32_t px = pix % (uint32_t)V.width, py = pix / (uint32_t)V.width;
     const uint4 rn = philox(make_uint4(pix, s, 0u, V.view_id), key0, key1);
@@ -509,6 +525,8 @@ struct TraceState {
   // shadow
   bool blocked;
   uint32_t ncross;
+  // work counters
+  uint32_t nodes, tris;
 };
 
 // Traverse the BVH of one cell for hits with t > 0, t >= t_lo, t < t_hi. Closest hit mode
@@ -537,6 +555,7 @@ __device__ void traverse_cell(const DevScene& S, const DevWS& w, const RayPre& R
     }
     const uint32_t i0 = __float_as_uint(nd.x), i1 = __float_as_uint(nd.y);
     const uint32_t c0 = __float_as_uint(nd.z), c1 = __float_as_uint(nd.w);
+    ++st.nodes;
     bool h0, h1;
     float t0, t1;
     box2(R, na, nb, nc, box_lo, kShadow ? t_hi : st.tbest, h0, t0, h1, t1);
@@ -552,6 +571,7 @@ __device__ void traverse_cell(const DevScene& S, const DevWS& w, const RayPre& R
         const float4 A = ctris[q * 3 + 0], B = ctris[q * 3 + 1], C = ctris[q * 3 + 2];
         const uint32_t id = __float_as_uint(A.w);
         if (id == skip) continue;
+        ++st.tris;
         float t, u, v;
         if (!wt_test(R, f3(A.x, A.y, A.z), f3(B.x, B.y, B.z), f3(C.x, C.y, C.z), t, u, v)) continue;
         if (!(t > 0.0f && t >= t_lo && t < t_hi)) continue;
@@ -561,8 +581,7 @@ __device__ void traverse_cell(const DevScene& S, const DevWS& w, const RayPre& R
             st.blocked = true;
             return;
           }
-          const F3 e1 = f3(B.x - A.x, B.y - A.y, B.z - A.z), e2 = f3(C.x - A.x, C.y - A.y, C.z - A.z);
-          const F3 ng = norm3(cross3(e1, e2));
+          const F3 ng = geo_normal(f3(A.x, A.y, A.z), f3(B.x, B.y, B.z), f3(C.x, C.y, C.z));
           if (st.ncross < (uint32_t)kMaxCross)
             w.shx[(size_t)st.ncross * w.W + slot] = make_float2(__int_as_float(m), fabsf(dot3(R.d, ng)));
           st.ncross++;
@@ -599,7 +618,7 @@ __device__ void traverse_cell(const DevScene& S, const DevWS& w, const RayPre& R
   }
 }
 
-__global__ __launch_bounds__(kWG) void k_trace(DevScene S, DevWS w, int gen, int hops) {
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k_trace(DevScene S, DevWS w, int gen, int hops) {
   __shared__ float4 s_nodes[kTopNodes * 4];
   __shared__ uint32_t s_stack[kShortStack * kWG];
   const uint32_t n_tiles = w.ctl->n_tiles;
@@ -611,7 +630,7 @@ __global__ __launch_bounds__(kWG) void k_trace(DevScene S, DevWS w, int gen, int
   uint32_t* spill = w.spill + gtid;
   uint32_t* stack = s_stack + threadIdx.x;
   const int np = (gen + 1) & 1;
-  uint32_t n_visit = 0, n_migr = 0, n_esc = 0, n_glass = 0;
+  uint32_t n_visit = 0, n_migr = 0, n_esc = 0, n_glass = 0, n_xover = 0, n_nodes = 0, n_tris = 0;
   int prev_cell = -1;
   for (uint32_t t = t_begin + blockIdx.x / kXcds; t < t_end; t += per_xcd) {
     const uint4 tile = w.tiles[t];
@@ -645,6 +664,8 @@ __global__ __launch_bounds__(kWG) void k_trace(DevScene S, DevWS w, int gen, int
       st.bu = st.bv = 0.0f;
       st.blocked = false;
       st.ncross = shadow ? w.shcnt[slot] : 0u;
+      st.nodes = 0;
+      st.tris = 0;
       const uint32_t ncross0 = st.ncross;
       bool done = false;
       for (int h = 0; h < hops; ++h) {
@@ -694,8 +715,11 @@ __global__ __launch_bounds__(kWG) void k_trace(DevScene S, DevWS w, int gen, int
       }
       if (shadow && st.ncross != ncross0 && !st.blocked) {
         n_glass += st.ncross - ncross0;
+        if (st.ncross > (uint32_t)kMaxCross && ncross0 <= (uint32_t)kMaxCross) ++n_xover;
         w.shcnt[slot] = st.ncross;
       }
+      n_nodes += st.nodes;
+      n_tris += st.tris;
       if (!done) {
         requeue = true;
         out_src = r;
@@ -710,6 +734,9 @@ __global__ __launch_bounds__(kWG) void k_trace(DevScene S, DevWS w, int gen, int
   wave_add(&w.ctl->st_migr, n_migr);
   wave_add(&w.ctl->st_escape, n_esc);
   wave_add(&w.ctl->st_glass, n_glass);
+  wave_add(&w.ctl->err_cross, n_xover);
+  wave_add(&w.ctl->st_nodes, n_nodes);
+  wave_add(&w.ctl->st_tris, n_tris);
 }
 
 // ==========================================================================================
@@ -776,8 +803,8 @@ __global__ __launch_bounds__(kWG) void k_shade(DevScene S, DevWS w, int depth, i
           const float4 A = S.gtris[(size_t)id * 3 + 0], Bv = S.gtris[(size_t)id * 3 + 1], C = S.gtris[(size_t)id * 3 + 2];
           const F3 v0 = f3(A.x, A.y, A.z), v1 = f3(Bv.x, Bv.y, Bv.z), v2 = f3(C.x, C.y, C.z);
           const int m = (int)__float_as_uint(Bv.w);
-          const F3 ng = norm3(cross3(v1 - v0, v2 - v0));
-          const float dn = dot3(d, ng);
+          const F3 ng = geo_normal(v0, v1, v2);
+          const float dn = dot_exact_sign(d, ng);
           const F3 n = dn > 0.0f ? ng * -1.0f : ng;
           const float cos_o = fabsf(dn);
           const float bu = h.z, bv = h.w;
@@ -792,7 +819,7 @@ __global__ __launch_bounds__(kWG) void k_shade(DevScene S, DevWS w, int depth, i
           bool cont = false;
           if (S.mtype[m] == 0) {
             const F3 ws = f3(S.sun[0], S.sun[1], S.sun[2]);
-            const float cs = dot3(n, ws);
+            const float cs = dot_exact_sign(n, ws);
             const bool nee = cs > 0.0f;
             const float kn = cs * (1.0f / 3.14159265358979f);
             float a_sum = 0.0f, b_sum = 0.0f;
