@@ -83,13 +83,14 @@ def algorithmic_bytes(st, B):
 
 
 def cpu_baseline(sc, cam, cfg, threads):
-    """The oracle as it stands, on the host cores, on the pixel subset x%4==0, y%4==0 at 4 spp
-    (a bounded sample of the same frame); its fixed per-call cost (BVH build) is subtracted."""
+    """The oracle as it stands, on the host cores, on the pixel subset x%4==0, y%4==0 at 32 spp
+    (a bounded sample of the same frame, ~10-30 s of CPU work); its fixed per-call cost (BVH
+    build) is subtracted."""
     import numpy as np
     import oracle
     ys, xs = np.meshgrid(np.arange(0, cam.height, 4), np.arange(0, cam.width, 4), indexing="ij")
     px = (ys * cam.width + xs).ravel()
-    spp = 4 if cfg["spp"] >= 4 else cfg["spp"]
+    spp = min(32, cfg["spp"])
     t0 = time.perf_counter()
     oracle.render(sc, cam, spp=1, max_depth=cfg["max_depth"], seed=1, pixels=px[:1], threads=threads)
     fixed = time.perf_counter() - t0

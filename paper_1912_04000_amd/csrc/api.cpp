@@ -1,6 +1,7 @@
 // C ABI of libspecdd: argument validation, workspace layout and the wavefront loop.
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -58,13 +59,13 @@ __global__ void k_store_views(ViewBlock vb, ViewDesc* dst, int first, int count)
 size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
 
 enum {
-  L_FLAGS, L_PIX, L_SMP, L_VIEW, L_BETA, L_NEE, L_HIT, L_RAYS, L_SHCNT, L_SHX, L_ACTIVE, L_LSRC, L_LDST, L_LRANK,
+  L_PIX, L_SMP, L_VIEW, L_BETA, L_NEE, L_LACC, L_HIT, L_RAYS, L_SHCNT, L_SHX, L_CAT, L_LSRC, L_LDST, L_LRANK,
   L_QUEUE, L_CCOUNT, L_COFF, L_TILES, L_SPILL, L_CTL, L_VIEWS, L_COUNT
 };
 
 struct Plan {
   uint32_t W;
-  int B;
+  int B, Bp;
   int n_cells;
   int n_views;
   int trace_blocks;
@@ -77,6 +78,7 @@ Plan make_plan(uint32_t W, int B, int n_cells, int n_views) {
   Plan p;
   p.W = W;
   p.B = B;
+  p.Bp = (B + 3) & ~3;
   p.n_cells = n_cells;
   p.n_views = n_views;
   size_t want = ((size_t)2 * W + kWG - 1) / kWG;
@@ -85,17 +87,17 @@ Plan make_plan(uint32_t W, int B, int n_cells, int n_views) {
   p.trace_blocks = tb;
   p.max_tiles = (uint32_t)(((size_t)2 * W + kTile - 1) / kTile + n_cells + 8);
   size_t sz[L_COUNT];
-  sz[L_FLAGS] = 4ull * W;
   sz[L_PIX] = 4ull * W;
   sz[L_SMP] = 4ull * W;
   sz[L_VIEW] = 4ull * W;
-  sz[L_BETA] = 4ull * B * W;
-  sz[L_NEE] = 4ull * B * W;
+  sz[L_BETA] = 4ull * p.Bp * W;
+  sz[L_NEE] = 4ull * p.Bp * W;
+  sz[L_LACC] = 4ull * p.Bp * W;
   sz[L_HIT] = 16ull * W;
   sz[L_RAYS] = 64ull * W;
   sz[L_SHCNT] = 4ull * W;
   sz[L_SHX] = 8ull * kMaxCross * W;
-  sz[L_ACTIVE] = 12ull * W;
+  sz[L_CAT] = 4ull * 2 * kCats * W;
   sz[L_LSRC] = 8ull * W;
   sz[L_LDST] = 8ull * W;
   sz[L_LRANK] = 8ull * W;
@@ -119,17 +121,17 @@ DevWS ws_view(const Plan& p, void* base) {
   uint8_t* b = (uint8_t*)base;
   DevWS w;
   std::memset(&w, 0, sizeof(w));
-  w.flags = (uint32_t*)(b + p.off[L_FLAGS]);
   w.pix = (uint32_t*)(b + p.off[L_PIX]);
   w.smp = (uint32_t*)(b + p.off[L_SMP]);
   w.view = (uint32_t*)(b + p.off[L_VIEW]);
   w.beta = (float*)(b + p.off[L_BETA]);
   w.nee = (float*)(b + p.off[L_NEE]);
+  w.lacc = (float*)(b + p.off[L_LACC]);
   w.hit = (float4*)(b + p.off[L_HIT]);
   w.rays = (float4*)(b + p.off[L_RAYS]);
   w.shcnt = (uint32_t*)(b + p.off[L_SHCNT]);
   w.shx = (float2*)(b + p.off[L_SHX]);
-  w.active = (uint32_t*)(b + p.off[L_ACTIVE]);
+  w.cat = (uint32_t*)(b + p.off[L_CAT]);
   w.lsrc = (uint32_t*)(b + p.off[L_LSRC]);
   w.ldst = (uint32_t*)(b + p.off[L_LDST]);
   w.lrank = (uint32_t*)(b + p.off[L_LRANK]);
@@ -144,6 +146,7 @@ DevWS ws_view(const Plan& p, void* base) {
   w.max_tiles = p.max_tiles;
   w.trace_threads = (uint32_t)p.trace_blocks * kWG;
   w.n_views = p.n_views;
+  w.Bp = p.Bp;
   return w;
 }
 
@@ -213,13 +216,14 @@ void record(sdd_ctx* ctx, std::vector<std::pair<hipEvent_t, hipEvent_t>>& pool, 
 // Trace every entry produced so far: rounds of (scan, scatter, trace). In every round but the
 // last a ray visits one cell and migrates to the next cell's queue; the last round walks the
 // remaining rays through their remaining cells in place.
-int trace_phase(sdd_ctx* ctx, const Launch& L, const DevScene& S, const DevWS& w, int& gen, int rounds, bool timing) {
+int trace_phase(sdd_ctx* ctx, const Launch& L, const DevScene& S, const DevWS& w, int& gen, int rounds, int cat_par,
+                bool timing) {
   for (int r = 0; r < rounds; ++r) {
     const int hops = r == rounds - 1 ? (1 << 30) : 1;
     HIP_TRY(ctx, launch_scan(L, S, w, gen));
     HIP_TRY(ctx, launch_scatter(L, w, gen));
     if (timing) record(ctx, ctx->ev_trace, ctx->ev_used_trace, true);
-    HIP_TRY(ctx, launch_trace(L, S, w, gen, hops));
+    HIP_TRY(ctx, launch_trace(L, S, w, gen, hops, cat_par));
     if (timing) record(ctx, ctx->ev_trace, ctx->ev_used_trace, false);
     ctx->acc.trace_launches++;
     ++gen;
@@ -262,23 +266,35 @@ int render_views(sdd_ctx* ctx, const sdd_scene* scene, std::vector<ViewDesc>& vi
   int rc = store_views(ctx, views, w);
   if (rc) return rc;
   for (auto& v : views) HIP_TRY(ctx, launch_fill_f32(ctx->stream, v.image, (size_t)B * v.width * v.height, 0.0f));
-  HIP_TRY(ctx, launch_fill_u32(ctx->stream, (uint32_t*)w.ctl, sizeof(Ctl) / 4, 0u));
+  // The wavefront counters restart with every render; the statistics keep accumulating on the
+  // device until sdd_finish collects them (consecutive renders into one workspace add up).
+  const size_t zero_words = (ctx->last_ctl == w.ctl) ? offsetof(Ctl, st_paths) / 4 : sizeof(Ctl) / 4;
+  HIP_TRY(ctx, launch_fill_u32(ctx->stream, (uint32_t*)w.ctl, zero_words, 0u));
   HIP_TRY(ctx, launch_fill_u32(ctx->stream, w.ccount, 2ull * scene->hdr.n_cells, 0u));
   ctx->last_ctl = w.ctl;
   int gen = 0;
   const int D = p->max_depth;
+  uint32_t* cat_counts = &w.ctl->cat_count[0][0];
   for (uint64_t k0 = 0; k0 < total; k0 += W) {
     const uint32_t n = (uint32_t)std::min<uint64_t>(W, total - k0);
+    HIP_TRY(ctx, launch_fill_u32(ctx->stream, cat_counts, 2 * 8, 0u));
     HIP_TRY(ctx, launch_raygen(L, S, w, k0, n, p->seed, gen));
-    rc = trace_phase(ctx, L, S, w, gen, rounds, timing);
+    rc = trace_phase(ctx, L, S, w, gen, rounds, 1, timing);
     if (rc) return rc;
     for (int d = 1; d <= D + 1; ++d) {
       if (timing) record(ctx, ctx->ev_shade, ctx->ev_used_shade, true);
-      HIP_TRY(ctx, launch_shade(L, S, w, d, D, p->seed, gen));
+      HIP_TRY(ctx, launch_resolve(L, S, w, d));
+      if (scene->hdr.env_nonzero) HIP_TRY(ctx, launch_escape(L, S, w, d));
+      if (d <= D) {
+        HIP_TRY(ctx, launch_shade_opaque(L, S, w, d, D, p->seed, gen));
+        if (d < D) HIP_TRY(ctx, launch_shade_glass(L, S, w, d, p->seed, gen));
+      } else {
+        HIP_TRY(ctx, launch_accumulate(L, S, w, n));
+      }
       if (timing) record(ctx, ctx->ev_shade, ctx->ev_used_shade, false);
       ctx->acc.shade_launches++;
       if (d <= D) {
-        rc = trace_phase(ctx, L, S, w, gen, rounds, timing);
+        rc = trace_phase(ctx, L, S, w, gen, rounds, (d + 1) & 1, timing);
         if (rc) return rc;
       }
     }
@@ -458,8 +474,9 @@ static int query(sdd_ctx* c, const sdd_scene* s, const float* orig, const float*
   int gen = 0;
   for (int64_t a = 0; a < n; a += W) {
     uint32_t m = (uint32_t)std::min<int64_t>(W, n - a);
+    HIP_TRY(c, launch_fill_u32(c->stream, &w.ctl->cat_count[0][0], 2 * 8, 0u));
     HIP_TRY(c, launch_pack_rays(L, S, w, orig + 3 * a, dir + 3 * a, skip ? skip + a : nullptr, m, shadow ? 1 : 0, gen));
-    rc = trace_phase(c, L, S, w, gen, kDefaultRounds, false);
+    rc = trace_phase(c, L, S, w, gen, kDefaultRounds, 0, false);
     if (rc) return rc;
     if (shadow)
       HIP_TRY(c, launch_resolve_vis(L, S, w, m, vis + (size_t)a * s->hdr.n_bins));

@@ -25,9 +25,14 @@ constexpr uint32_t kShadowBit = 0x80000000u;  // in the ray's slot word
 constexpr uint32_t kInvalidCell = 0xFFFFFFFFu;
 constexpr uint32_t kEmptyChild = 0xFFFFFFFFu;
 
-// path flags
-constexpr uint32_t kFlagExt = 1u;     // an extension ray is in flight
-constexpr uint32_t kFlagShadow = 2u;  // a shadow ray (pending NEE) is in flight
+// Categories of finished rays: the traversal sorts every ray it finishes into one list per
+// category so that each shading kernel runs one branch only (no divergence between kinds).
+constexpr int kCatOpaque = 0;      // extension ray hit an opaque triangle
+constexpr int kCatGlass = 1;       // extension ray hit a glass triangle
+constexpr int kCatEscape = 2;      // extension ray left the scene (environment radiance)
+constexpr int kCatShadowClear = 3; // shadow ray reached the sun without crossing glass
+constexpr int kCatShadowGlass = 4; // shadow ray reached the sun through glass
+constexpr int kCats = 5;
 
 // ------------------------------------------------------------------------------------------
 // Serialised scene image (one device buffer, offsets in bytes from its start)
@@ -45,7 +50,8 @@ struct SceneHeader {
   uint64_t n_nodes, n_refs;
   float lambda_min_nm, lambda_max_nm;
   int32_t max_leaf;
-  int32_t pad[5];
+  int32_t bins_pad;    // row stride of the spectral tables: n_bins rounded up to a multiple of 4
+  int32_t pad[4];
 };
 static_assert(sizeof(SceneHeader) <= 256, "header fits in 256 bytes");
 
@@ -76,7 +82,7 @@ struct DevScene {
   float lo[3], hi[3];
   float inv_cs[3];
   float sun[3];
-  int32_t n_bins, n_mat, env_nonzero, pad;
+  int32_t n_bins, n_mat, env_nonzero, bins_pad;
 };
 
 // Per-view description for raygen and accumulation.
@@ -100,8 +106,8 @@ struct Ctl {
   uint32_t list_count[2];   // produced (ray, cell, rank) entries per generation parity
   uint32_t n_queue;         // entries in the cell-sorted queue of the current round
   uint32_t n_tiles;         // tiles of the current round
-  uint32_t act_count[3];    // active-slot lists (rotating)
-  uint32_t pad0[9];
+  uint32_t cat_count[2][8]; // finished-ray lists per bounce parity and category (kCats used)
+  // statistics (accumulated until collected)
   unsigned long long st_paths, st_vertices, st_ext, st_shadow, st_visits, st_migr, st_escape, st_glass;
   unsigned long long err_cross, err_nonfinite, err_stack;
   unsigned long long st_nodes, st_tris;  // BVH nodes visited, triangle tests (traversal work)
@@ -110,17 +116,17 @@ struct Ctl {
 
 // Device view of a workspace.
 struct DevWS {
-  uint32_t* flags;
   uint32_t* pix;
   uint32_t* smp;
   uint32_t* view;
-  float* beta;       // [B][W]
-  float* nee;        // [B][W]
+  float* beta;       // [W][Bp] path throughput per bin
+  float* nee;        // [W][Bp] direct-term weight of the pending shadow ray
+  float* lacc;       // [W][Bp] radiance gathered by the path so far
   float4* hit;       // [W] (t, id bits, u, v)
   float4* rays;      // [2W][2]  (o.xyz, skip bits) (d.xyz, slot | shadow bit)
   uint32_t* shcnt;   // [W] glass crossings of the pending shadow ray, kBlocked if blocked
   float2* shx;       // [kMaxCross][W] (material id bits, cos theta)
-  uint32_t* active;  // [3][W]
+  uint32_t* cat;     // [2][kCats][W] finished-ray lists
   uint32_t* lsrc;    // [2W] produced entries: ray index | first-visit bit
   uint32_t* ldst;    // [2W] destination cell
   uint32_t* lrank;   // [2W] rank inside the destination cell
@@ -135,12 +141,8 @@ struct DevWS {
   uint32_t max_tiles;
   uint32_t trace_threads;
   int32_t n_views;
-};
-
-// Layout of a workspace for W slots, B bins, C cells, V views and a traversal grid.
-struct WSLayout {
-  size_t off[24];
-  size_t total;
+  int32_t Bp;        // row stride of the per-slot spectral rows
+  int32_t pad;
 };
 
 // Host helpers implemented in the kernels' translation unit.
@@ -155,9 +157,13 @@ hipError_t launch_raygen(const Launch& L, const DevScene& S, const DevWS& w, uin
                          int gen);
 hipError_t launch_scan(const Launch& L, const DevScene& S, const DevWS& w, int gen);
 hipError_t launch_scatter(const Launch& L, const DevWS& w, int gen);
-hipError_t launch_trace(const Launch& L, const DevScene& S, const DevWS& w, int gen, int hops);
-hipError_t launch_shade(const Launch& L, const DevScene& S, const DevWS& w, int depth, int max_depth, uint64_t seed,
-                        int gen);
+hipError_t launch_trace(const Launch& L, const DevScene& S, const DevWS& w, int gen, int hops, int cat_par);
+hipError_t launch_resolve(const Launch& L, const DevScene& S, const DevWS& w, int depth);
+hipError_t launch_escape(const Launch& L, const DevScene& S, const DevWS& w, int depth);
+hipError_t launch_shade_opaque(const Launch& L, const DevScene& S, const DevWS& w, int depth, int max_depth,
+                               uint64_t seed, int gen);
+hipError_t launch_shade_glass(const Launch& L, const DevScene& S, const DevWS& w, int depth, uint64_t seed, int gen);
+hipError_t launch_accumulate(const Launch& L, const DevScene& S, const DevWS& w, uint32_t n);
 hipError_t launch_pack_rays(const Launch& L, const DevScene& S, const DevWS& w, const float* orig, const float* dir,
                             const int32_t* skip, uint32_t n, int shadow, int gen);
 hipError_t launch_unpack_hits(const Launch& L, const DevWS& w, uint32_t n, float* t, int32_t* id, float* u, float* v);

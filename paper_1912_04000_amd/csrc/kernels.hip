@@ -186,32 +186,37 @@ __device__ __forceinline__ void cell_interval(const DevScene& S, int ix, int iy,
 }
 
 // ==========================================================================================
-// spectral optics
+// spectral optics (hardware reciprocal / square root / exp2: about 1 ulp each, far inside the
+// 1e-4 parity bar, against the multi-instruction IEEE expansions)
 // ==========================================================================================
-// Unpolarised Fresnel reflectance of air -> n + ik at incidence cosine c (principal branch of
-// w = sqrt(eta^2 - sin^2)).
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float fexp(float x) { return __builtin_amdgcn_exp2f(x * 1.4426950408889634f); }
+
+// Unpolarised Fresnel reflectance of air -> n + ik at incidence cosine c:
+//   eta^2 = (n + ik)^2, w = sqrt(eta^2 - sin^2) (principal branch),
+//   r_s = (c - w)/(c + w), r_p = (eta^2 c - w)/(eta^2 c + w), F = (|r_s|^2 + |r_p|^2)/2.
 __device__ __forceinline__ float fresnel(float n, float k, float c) {
   c = fminf(1.0f, fmaxf(0.0f, c));
   const float s2 = 1.0f - c * c;
   const float er = n * n - k * k, ei = 2.0f * n * k;
   const float zr = er - s2, zi = ei;
-  const float r = sqrtf(zr * zr + zi * zi);
-  float wr, wi;
-  if (r == 0.0f) {
-    wr = 0.0f;
-    wi = 0.0f;
-  } else if (zr >= 0.0f) {
-    wr = sqrtf(0.5f * (r + zr));
-    wi = zi / (2.0f * wr);
-  } else {
-    wi = copysignf(sqrtf(0.5f * (r - zr)), zi);
-    wr = zi / (2.0f * wi);
+  const float r = fsqrt(zr * zr + zi * zi);
+  float wr = 0.0f, wi = 0.0f;
+  if (r > 0.0f) {
+    if (zr >= 0.0f) {
+      wr = fsqrt(0.5f * (r + zr));
+      wi = 0.5f * zi * frcp(wr);
+    } else {
+      wi = copysignf(fsqrt(0.5f * (r - zr)), zi);
+      wr = 0.5f * zi * frcp(wi);
+    }
   }
   const float an = c - wr, ad = c + wr;
-  const float Rs = (an * an + wi * wi) / (ad * ad + wi * wi);
+  const float Rs = (an * an + wi * wi) * frcp(ad * ad + wi * wi);
   const float pr = er * c, pi = ei * c;
   const float bnr = pr - wr, bni = pi - wi, bdr = pr + wr, bdi = pi + wi;
-  const float Rp = (bnr * bnr + bni * bni) / (bdr * bdr + bdi * bdi);
+  const float Rp = (bnr * bnr + bni * bni) * frcp(bdr * bdr + bdi * bdi);
   return 0.5f * (Rs + Rp);
 }
 
@@ -219,16 +224,16 @@ __device__ __forceinline__ float fresnel(float n, float k, float c) {
 // internal path d / cos(theta_t), refraction angle from the real index.
 __device__ __forceinline__ void slab(float n, float k, float lambda_nm, float d_m, float c, float& R, float& T) {
   c = fminf(1.0f, fmaxf(0.0f, c));
-  const float st = sqrtf(fmaxf(0.0f, 1.0f - c * c));
-  const float si = st / n;
-  const float ci = sqrtf(fmaxf(0.0f, 1.0f - si * si));
-  const float alpha = 4.0f * 3.14159265358979f * k / (lambda_nm * 1e-9f);
-  const float tau = expf(-alpha * d_m / ci);
+  const float st = fsqrt(fmaxf(0.0f, 1.0f - c * c));
+  const float si = st * frcp(n);
+  const float ci = fsqrt(fmaxf(0.0f, 1.0f - si * si));
+  const float alpha = 1.2566370614359172e10f * k * frcp(lambda_nm);  // 4 pi k / (lambda_nm 1e-9 m)
+  const float tau = fexp(-alpha * d_m * frcp(ci));
   const float R1 = fresnel(n, k, c);
-  const float den = 1.0f - R1 * R1 * tau * tau;
+  const float inv_den = frcp(1.0f - R1 * R1 * tau * tau);
   const float q = (1.0f - R1) * (1.0f - R1);
-  R = R1 + q * tau * tau * R1 / den;
-  T = q * tau / den;
+  R = R1 + q * tau * tau * R1 * inv_den;
+  T = q * tau * inv_den;
 }
 
 // ==========================================================================================
@@ -248,6 +253,21 @@ __global__ void k_philox(uint4 base, uint32_t k0, uint32_t k1, uint64_t n, uint4
 // ==========================================================================================
 // ray generation
 // ==========================================================================================
+// Wave-level push of one value to a list (one atomic per wave); every lane must call it.
+__device__ __forceinline__ void wave_push(bool pred, uint32_t val, uint32_t* count, uint32_t* list) {
+  const uint64_t m = __ballot(pred);
+  if (m == 0) return;
+  const uint32_t leader = (uint32_t)__ffsll((unsigned long long)m) - 1u;
+  uint32_t base = 0;
+  if (lane_id() == leader) base = atomicAdd(count, (uint32_t)__popcll(m));
+  base = __shfl(base, (int)leader);
+  if (pred) list[base + count_below(m)] = val;
+}
+
+__device__ __forceinline__ uint32_t* cat_list(const DevWS& w, int par, int cat) {
+  return w.cat + ((size_t)par * kCats + cat) * w.W;
+}
+
 __global__ __launch_bounds__(kWG) void k_raygen(DevScene S, DevWS w, uint64_t k0, uint32_t n, uint32_t key0,
                                                 uint32_t key1, int gen) {
   const uint32_t i = blockIdx.x * kWG + threadIdx.x;
@@ -273,22 +293,23 @@ __global__ __launch_bounds__(kWG) void k_raygen(DevScene S, DevWS w, uint64_t k0
     const F3 o = f3(V.eye[0], V.eye[1], V.eye[2]);
     w.rays[2 * i] = make_float4(o.x, o.y, o.z, __int_as_float(-1));
     w.rays[2 * i + 1] = make_float4(d.x, d.y, d.z, __uint_as_float(i));
-    w.flags[i] = kFlagExt;
     w.pix[i] = pix;
     w.smp[i] = s;
     w.view[i] = (uint32_t)v;
-    for (int j = 0; j < S.n_bins; ++j) w.beta[(size_t)j * w.W + i] = 1.0f;
-    w.active[1 * w.W + i] = i;
+    float4* b4 = (float4*)(w.beta + (size_t)i * w.Bp);
+    float4* l4 = (float4*)(w.lacc + (size_t)i * w.Bp);
+    for (int q = 0; q < w.Bp / 4; ++q) {
+      b4[q] = make_float4(1.0f, 1.0f, 1.0f, 1.0f);
+      l4[q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
     cell = start_cell(S, o, d);
-    if (cell == kInvalidCell) w.hit[i] = make_float4(INFINITY, __uint_as_float(0xFFFFFFFFu), 0.0f, 0.0f);
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    w.ctl->act_count[1] = n;
-    w.ctl->act_count[2] = 0;
   }
   const int p = gen & 1;
   wave_append(valid && cell != kInvalidCell, i | kFirstVisit, cell, &w.ctl->list_count[p],
               w.ccount + (size_t)p * S.n_cells, w.lsrc, w.ldst, w.lrank);
+  // camera rays that miss the grid box escape at once (bounce 1 lists, parity 1)
+  wave_push(valid && cell == kInvalidCell && S.env_nonzero, i, &w.ctl->cat_count[1][kCatEscape],
+            cat_list(w, 1, kCatEscape));
   wave_add(&w.ctl->st_paths, valid ? 1u : 0u);
   wave_add(&w.ctl->st_ext, valid ? 1u : 0u);
 }
@@ -341,7 +362,7 @@ __global__ void k_resolve_vis(DevScene S, DevWS w, uint32_t n, float* vis) {
           const float2 x = w.shx[(size_t)q * w.W + i];
           const int m = __float_as_int(x.x);
           float R, T;
-          slab(S.ntab[m * S.n_bins + j], S.ktab[m * S.n_bins + j], S.lambda[j], S.thick[m], x.y, R, T);
+          slab(S.ntab[m * S.bins_pad + j], S.ktab[m * S.bins_pad + j], S.lambda[j], S.thick[m], x.y, R, T);
           V *= T;
         }
       }
@@ -465,7 +486,7 @@ __device__ __forceinline__ bool wt_test(const RayPre& R, F3 v0, F3 v1, F3 v2, fl
   const float det = U + V + W;
   if (det == 0.0f) return false;
   const float T = U * (R.Sz * Akz) + V * (R.Sz * Bkz) + W * (R.Sz * Ckz);
-  const float inv = 1.0f / det;
+  const float inv = __builtin_amdgcn_rcpf(det);
   t = T * inv;
   bu = V * inv;
   bv = W * inv;
@@ -520,7 +541,7 @@ __device__ __forceinline__ void box2(const RayPre& R, float4 a, float4 b, float4
 struct TraceState {
   // closest hit
   float tbest;
-  uint32_t best_id;
+  uint32_t best_id, best_mat;
   float bu, bv;
   // shadow
   bool blocked;
@@ -529,12 +550,14 @@ struct TraceState {
   uint32_t nodes, tris;
 };
 
-// Traverse the BVH of one cell for hits with t > 0, t >= t_lo, t < t_hi. Closest hit mode
-// shrinks t_hi; shadow mode stops at the first opaque hit and records glass crossings.
-template <bool kShadow>
-__device__ void traverse_cell(const DevScene& S, const DevWS& w, const RayPre& R, int4 cinfo, const float4* lds_nodes,
-                              int n_lds, uint32_t* stack_lds, uint32_t* spill, uint32_t spill_stride, uint32_t skip,
-                              float t_lo, float t_hi, uint32_t slot, TraceState& st) {
+// Traverse the BVH of one cell for hits with t > 0, t >= t_lo, t < t_hi. One loop serves both
+// ray kinds (lanes of a wave may hold either): a closest-hit ray shrinks its far bound with every
+// accepted hit; a shadow ray keeps it, stops at the first opaque hit and records every glass
+// crossing. Both hit children that are leaves are tested in one triangle loop.
+__device__ void traverse_cell(const DevScene& S, const DevWS& w, const RayPre& R, bool shadow, int4 cinfo,
+                              const float4* lds_nodes, int n_lds, uint32_t* stack_lds, uint32_t* spill,
+                              uint32_t spill_stride, uint32_t skip, float t_lo, float t_hi, uint32_t slot,
+                              TraceState& st) {
   const float4* gnodes = S.nodes + (size_t)cinfo.x * 4;
   const float4* ctris = S.ctris + (size_t)cinfo.z * 3;
   const float box_lo = fmaxf(t_lo, 0.0f);
@@ -558,42 +581,40 @@ __device__ void traverse_cell(const DevScene& S, const DevWS& w, const RayPre& R
     ++st.nodes;
     bool h0, h1;
     float t0, t1;
-    box2(R, na, nb, nc, box_lo, kShadow ? t_hi : st.tbest, h0, t0, h1, t1);
+    box2(R, na, nb, nc, box_lo, shadow ? t_hi : st.tbest, h0, t0, h1, t1);
     h0 = h0 && i0 != kEmptyChild;
     h1 = h1 && i1 != kEmptyChild;
-#pragma unroll
-    for (int ch = 0; ch < 2; ++ch) {
-      const bool hit_leaf = ch == 0 ? (h0 && c0) : (h1 && c1);
-      if (!hit_leaf) continue;
-      const uint32_t first = ch == 0 ? i0 : i1, cnt = ch == 0 ? c0 : c1;
-      if (ch == 0) h0 = false; else h1 = false;
-      for (uint32_t q = first; q < first + cnt; ++q) {
-        const float4 A = ctris[q * 3 + 0], B = ctris[q * 3 + 1], C = ctris[q * 3 + 2];
-        const uint32_t id = __float_as_uint(A.w);
-        if (id == skip) continue;
-        ++st.tris;
-        float t, u, v;
-        if (!wt_test(R, f3(A.x, A.y, A.z), f3(B.x, B.y, B.z), f3(C.x, C.y, C.z), t, u, v)) continue;
-        if (!(t > 0.0f && t >= t_lo && t < t_hi)) continue;
-        if (kShadow) {
-          const int m = (int)__float_as_uint(B.w);
-          if (S.mtype[m] == 0) {
-            st.blocked = true;
-            return;
-          }
-          const F3 ng = geo_normal(f3(A.x, A.y, A.z), f3(B.x, B.y, B.z), f3(C.x, C.y, C.z));
-          if (st.ncross < (uint32_t)kMaxCross)
-            w.shx[(size_t)st.ncross * w.W + slot] = make_float2(__int_as_float(m), fabsf(dot3(R.d, ng)));
-          st.ncross++;
-        } else if (t < st.tbest || (t == st.tbest && id < st.best_id)) {
-          st.tbest = t;
-          st.best_id = id;
-          st.bu = u;
-          st.bv = v;
+    const uint32_t la = (h0 && c0) ? c0 : 0u, lb = (h1 && c1) ? c1 : 0u;
+    if (la) h0 = false;
+    if (lb) h1 = false;
+    for (uint32_t q = 0; q < la + lb; ++q) {
+      const uint32_t tri = q < la ? i0 + q : i1 + (q - la);
+      const float4 A = ctris[tri * 3 + 0], B = ctris[tri * 3 + 1], C = ctris[tri * 3 + 2];
+      const uint32_t id = __float_as_uint(A.w);
+      if (id == skip) continue;
+      ++st.tris;
+      float t, u, v;
+      if (!wt_test(R, f3(A.x, A.y, A.z), f3(B.x, B.y, B.z), f3(C.x, C.y, C.z), t, u, v)) continue;
+      if (!(t > 0.0f && t >= t_lo && t < t_hi)) continue;
+      if (shadow) {
+        const int m = (int)__float_as_uint(B.w);
+        if (S.mtype[m] == 0) {
+          st.blocked = true;
+          return;
         }
+        const F3 ng = geo_normal(f3(A.x, A.y, A.z), f3(B.x, B.y, B.z), f3(C.x, C.y, C.z));
+        if (st.ncross < (uint32_t)kMaxCross)
+          w.shx[(size_t)st.ncross * w.W + slot] = make_float2(__int_as_float(m), fabsf(dot3(R.d, ng)));
+        st.ncross++;
+      } else if (t < st.tbest || (t == st.tbest && id < st.best_id)) {
+        st.tbest = t;
+        st.best_id = id;
+        st.best_mat = __float_as_uint(B.w);
+        st.bu = u;
+        st.bv = v;
       }
     }
-    if (!kShadow) {
+    if (!shadow) {
       h0 = h0 && t0 <= st.tbest;
       h1 = h1 && t1 <= st.tbest;
     }
@@ -618,7 +639,8 @@ __device__ void traverse_cell(const DevScene& S, const DevWS& w, const RayPre& R
   }
 }
 
-__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k_trace(DevScene S, DevWS w, int gen, int hops) {
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k_trace(DevScene S, DevWS w, int gen, int hops,
+                                                                                               int cat_par) {
   __shared__ float4 s_nodes[kTopNodes * 4];
   __shared__ uint32_t s_stack[kShortStack * kWG];
   const uint32_t n_tiles = w.ctl->n_tiles;
@@ -646,6 +668,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
     const bool active = threadIdx.x < tile.z;
     bool requeue = false;
     uint32_t out_src = 0, out_cell = 0;
+    int cat = -1;
+    uint32_t cat_slot = 0;
     if (active) {
       const uint32_t entry = w.queue[tile.y + threadIdx.x];
       const uint32_t r = entry & ~kFirstVisit;
@@ -661,6 +685,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
       TraceState st;
       st.tbest = INFINITY;
       st.best_id = 0xFFFFFFFFu;
+      st.best_mat = 0;
       st.bu = st.bv = 0.0f;
       st.blocked = false;
       st.ncross = shadow ? w.shcnt[slot] : 0u;
@@ -677,25 +702,22 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
         ++n_visit;
         if (cinfo.y > 0 && t_lo < tf) {
           const int nl = h == 0 ? n_top : 0;
-          if (shadow) {
-            traverse_cell<true>(S, w, R, cinfo, s_nodes, nl, stack, spill, w.trace_threads, skip, t_lo, tf, slot, st);
-            if (st.blocked) {
-              w.shcnt[slot] = kBlocked;
-              done = true;
-              break;
-            }
-          } else {
-            st.tbest = tf;
-            traverse_cell<false>(S, w, R, cinfo, s_nodes, nl, stack, spill, w.trace_threads, skip, t_lo, tf, slot, st);
-            if (st.best_id != 0xFFFFFFFFu) {
-              const float4* g = S.gtris + (size_t)st.best_id * 3;
-              const float4 A = g[0], Bq = g[1], Cq = g[2];
-              refine_hit(R.o, R.d, f3(A.x, A.y, A.z), f3(Bq.x, Bq.y, Bq.z), f3(Cq.x, Cq.y, Cq.z), st.tbest, st.bu,
-                         st.bv);
-              w.hit[slot] = make_float4(st.tbest, __uint_as_float(st.best_id), st.bu, st.bv);
-              done = true;
-              break;
-            }
+          if (!shadow) st.tbest = tf;
+          traverse_cell(S, w, R, shadow, cinfo, s_nodes, nl, stack, spill, w.trace_threads, skip, t_lo, tf, slot, st);
+          if (shadow && st.blocked) {
+            w.shcnt[slot] = kBlocked;
+            done = true;
+            break;
+          }
+          if (!shadow && st.best_id != 0xFFFFFFFFu) {
+            const float4* g = S.gtris + (size_t)st.best_id * 3;
+            const float4 A = g[0], Bq = g[1], Cq = g[2];
+            refine_hit(R.o, R.d, f3(A.x, A.y, A.z), f3(Bq.x, Bq.y, Bq.z), f3(Cq.x, Cq.y, Cq.z), st.tbest, st.bu,
+                       st.bv);
+            w.hit[slot] = make_float4(st.tbest, __uint_as_float(st.best_id), st.bu, st.bv);
+            cat = S.mtype[st.best_mat] == 0 ? kCatOpaque : kCatGlass;
+            done = true;
+            break;
           }
         }
         // leave through the exit face (Amanatides-Woo step)
@@ -705,7 +727,12 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
         *idx += dc > 0.0f ? 1 : -1;
         if (*idx < 0 || *idx >= g || !(tf < INFINITY)) {
           // escaped the grid
-          if (!shadow) w.hit[slot] = make_float4(INFINITY, __uint_as_float(0xFFFFFFFFu), 0.0f, 0.0f);
+          if (!shadow) {
+            w.hit[slot] = make_float4(INFINITY, __uint_as_float(0xFFFFFFFFu), 0.0f, 0.0f);
+            if (S.env_nonzero) cat = kCatEscape;
+          } else {
+            cat = st.ncross > 0 ? kCatShadowGlass : kCatShadowClear;
+          }
           ++n_esc;
           done = true;
           break;
@@ -726,7 +753,11 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
         out_cell = (uint32_t)cell;
         ++n_migr;
       }
+      cat_slot = slot;
     }
+#pragma unroll
+    for (int c = 0; c < kCats; ++c)
+      wave_push(cat == c, cat_slot, &w.ctl->cat_count[cat_par][c], cat_list(w, cat_par, c));
     wave_append(requeue, out_src, out_cell, &w.ctl->list_count[np], w.ccount + (size_t)np * S.n_cells, w.lsrc, w.ldst,
                 w.lrank);
   }
@@ -740,198 +771,280 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
 }
 
 // ==========================================================================================
-// shading
+// shading: per-category kernels over the lists the traversal produced. Every path slot keeps
+// its spectral rows contiguous ([slot][bin], rows of Bp floats read as float4), because list
+// order follows the traversal (cell by cell), not the slot order.
 // ==========================================================================================
-__device__ __forceinline__ float* image_of(const ViewDesc& V) { return V.image; }
+// Shadow rays that reached the sun (eq. 3 direct term, weight stored when the ray was spawned,
+// attenuated by every glass slab crossed). A slot holds one shadow ray at a time, so no two
+// threads of this kernel touch the same radiance row.
+__global__ __launch_bounds__(kWG) void k_resolve(DevScene S, DevWS w, int depth) {
+  const int p = depth & 1;
+  const uint32_t n_clear = w.ctl->cat_count[p][kCatShadowClear];
+  const uint32_t n_glass = w.ctl->cat_count[p][kCatShadowGlass];
+  if (blockIdx.x == 0 && threadIdx.x < kCats) w.ctl->cat_count[p ^ 1][threadIdx.x] = 0;  // lists of the next bounce
+  const uint32_t n = n_clear + n_glass;
+  const int Bp = w.Bp, nq = Bp / 4;
+  for (uint32_t i = blockIdx.x * kWG + threadIdx.x; i < n; i += gridDim.x * kWG) {
+    if (i < n_clear) {
+      const uint32_t s = cat_list(w, p, kCatShadowClear)[i];
+      const float4* e = (const float4*)(w.nee + (size_t)s * Bp);
+      float4* l = (float4*)(w.lacc + (size_t)s * Bp);
+      for (int q = 0; q < nq; ++q) {
+        const float4 a = e[q];
+        float4 b = l[q];
+        b.x += a.x; b.y += a.y; b.z += a.z; b.w += a.w;
+        l[q] = b;
+      }
+    } else {
+      const uint32_t s = cat_list(w, p, kCatShadowGlass)[i - n_clear];
+      const uint32_t nc = min(w.shcnt[s], (uint32_t)kMaxCross);
+      const float* e = w.nee + (size_t)s * Bp;
+      float* l = w.lacc + (size_t)s * Bp;
+      for (int j = 0; j < S.n_bins; ++j) {
+        float V = 1.0f;
+        for (uint32_t q = 0; q < nc; ++q) {
+          const float2 x = w.shx[(size_t)q * w.W + s];
+          const int m = __float_as_int(x.x);
+          float Rq, Tq;
+          slab(S.ntab[m * Bp + j], S.ktab[m * Bp + j], S.lambda[j], S.thick[m], x.y, Rq, Tq);
+          V *= Tq;
+        }
+        l[j] += e[j] * V;
+      }
+    }
+  }
+}
 
-__global__ __launch_bounds__(kWG) void k_shade(DevScene S, DevWS w, int depth, int max_depth, uint32_t key0,
-                                               uint32_t key1, int gen) {
-  const int rd = depth % 3, wr = (depth + 1) % 3, zr = (depth + 2) % 3;
-  const uint32_t n_act = w.ctl->act_count[rd];
-  if (blockIdx.x == 0 && threadIdx.x == 0) w.ctl->act_count[zr] = 0;
-  const int B = S.n_bins;
+// Extension rays that left the scene pick up the environment radiance. Launched after
+// k_resolve: the same slot may also have had a shadow ray resolved there.
+__global__ __launch_bounds__(kWG) void k_escape(DevScene S, DevWS w, int depth) {
+  const int p = depth & 1;
+  const uint32_t n = w.ctl->cat_count[p][kCatEscape];
+  const int Bp = w.Bp, nq = Bp / 4;
+  const float4* env = (const float4*)S.env;
+  for (uint32_t i = blockIdx.x * kWG + threadIdx.x; i < n; i += gridDim.x * kWG) {
+    const uint32_t s = cat_list(w, p, kCatEscape)[i];
+    const float4* b4 = (const float4*)(w.beta + (size_t)s * Bp);
+    float4* l = (float4*)(w.lacc + (size_t)s * Bp);
+    for (int q = 0; q < nq; ++q) {
+      const float4 a = b4[q], e = env[q];
+      float4 b = l[q];
+      b.x += a.x * e.x; b.y += a.y * e.y; b.z += a.z * e.z; b.w += a.w * e.w;
+      l[q] = b;
+    }
+  }
+}
+
+// Geometry of the hit of slot s: vertex position, face-forward normal, geometric normal.
+struct Vertex {
+  F3 p, n, ng, d;
+  float dn, cos_o, eps;
+  uint32_t id;
+  int m;
+};
+
+__device__ __forceinline__ Vertex load_vertex(const DevScene& S, const DevWS& w, uint32_t s) {
+  Vertex V;
+  const float4 h = w.hit[s];
+  V.id = __float_as_uint(h.y);
+  const float4 rdir = w.rays[2 * s + 1];
+  V.d = f3(rdir.x, rdir.y, rdir.z);
+  const float4 A = S.gtris[(size_t)V.id * 3 + 0], Bv = S.gtris[(size_t)V.id * 3 + 1], C = S.gtris[(size_t)V.id * 3 + 2];
+  const F3 v0 = f3(A.x, A.y, A.z), v1 = f3(Bv.x, Bv.y, Bv.z), v2 = f3(C.x, C.y, C.z);
+  V.m = (int)__float_as_uint(Bv.w);
+  V.ng = geo_normal(v0, v1, v2);
+  V.dn = dot_exact_sign(V.d, V.ng);
+  V.n = V.dn > 0.0f ? V.ng * -1.0f : V.ng;
+  V.cos_o = fabsf(V.dn);
+  const float bu = h.z, bv = h.w;
+  V.p = v0 * (1.0f - bu - bv) + v1 * bu + v2 * bv;
+  V.eps = 1e-5f * (1.0f + maxabs3(V.p));
+  return V;
+}
+
+// Opaque vertex: direct term toward the sun through a shadow ray (eq. 3), then the
+// Fresnel-split lobe choice (mirror with probability mean F, else cosine-weighted diffuse).
+__global__ __launch_bounds__(kWG) void k_shade_opaque(DevScene S, DevWS w, int depth, int max_depth, uint32_t key0,
+                                                      uint32_t key1, int gen) {
+  const int p = depth & 1;
+  const uint32_t n = w.ctl->cat_count[p][kCatOpaque];
+  const uint32_t* list = cat_list(w, p, kCatOpaque);
+  const int B = S.n_bins, Bp = w.Bp, nq = Bp / 4;
   const size_t W = w.W;
-  const int p = gen & 1;
-  const uint32_t n_iter = (n_act + kWG - 1) / kWG * kWG;
+  const int gp = gen & 1;
+  const uint32_t n_iter = (n + kWG - 1) / kWG * kWG;
   for (uint32_t a = blockIdx.x * kWG + threadIdx.x; a < n_iter; a += gridDim.x * kWG) {
-    const bool valid = a < n_act;
-    uint32_t s = 0;
-    uint32_t nflags = 0;
-    uint32_t ext_cell = kInvalidCell, sh_cell = kInvalidCell;
-    uint32_t n_vert = 0, n_sh = 0;
+    const bool valid = a < n;
+    uint32_t s = 0, ext_cell = kInvalidCell, sh_cell = kInvalidCell;
+    bool has_sh = false, has_ext = false;
     if (valid) {
-      s = w.active[(size_t)rd * W + a];
-      const uint32_t f = w.flags[s];
-      const ViewDesc& V = w.views[w.view[s]];
-      const uint32_t pix = w.pix[s];
-      const size_t plane = (size_t)V.width * V.height;
-      float* img = V.image + pix;
-      const float inv_spp = V.inv_spp;
-      // ---- resolve the pending shadow ray of the previous vertex (eq. 3 direct term) ----
-      if (f & kFlagShadow) {
-        const uint32_t c = w.shcnt[s];
-        if (c != kBlocked) {
-          const uint32_t nc = min(c, (uint32_t)kMaxCross);
-          for (int j = 0; j < B; ++j) {
-            float Vj = 1.0f;
-            for (uint32_t q = 0; q < nc; ++q) {
-              const float2 x = w.shx[(size_t)q * W + s];
-              const int m = __float_as_int(x.x);
-              float Rq, Tq;
-              slab(S.ntab[m * B + j], S.ktab[m * B + j], S.lambda[j], S.thick[m], x.y, Rq, Tq);
-              Vj *= Tq;
-            }
-            const float c_j = w.nee[(size_t)j * W + s] * Vj * inv_spp;
-            if (c_j != 0.0f) unsafeAtomicAdd(img + (size_t)j * plane, c_j);
+      s = list[a];
+      const Vertex V = load_vertex(S, w, s);
+      const uint4 rn = philox(make_uint4(w.pix[s], w.smp[s], (uint32_t)depth, w.views[w.view[s]].view_id), key0, key1);
+      const float u0 = unif24(rn.x), u1 = unif24(rn.y), u2 = unif24(rn.z);
+      const float4* nt = (const float4*)(S.ntab + V.m * Bp);
+      const float4* kt = (const float4*)(S.ktab + V.m * Bp);
+      const float4* rt = (const float4*)(S.rho + V.m * Bp);
+      const float4* E4 = (const float4*)S.sunE;
+      float4* b4 = (float4*)(w.beta + (size_t)s * Bp);
+      float4* e4 = (float4*)(w.nee + (size_t)s * Bp);
+      const F3 ws = f3(S.sun[0], S.sun[1], S.sun[2]);
+      const float cs = dot_exact_sign(V.n, ws);
+      const bool nee = cs > 0.0f;
+      const float kn = cs * (1.0f / 3.14159265358979f);
+      float a_sum = 0.0f, b_sum = 0.0f;
+      for (int q = 0; q < nq; ++q) {
+        const float4 nn = nt[q], kk = kt[q], rr = rt[q];
+        float F[4] = {fresnel(nn.x, kk.x, V.cos_o), fresnel(nn.y, kk.y, V.cos_o), fresnel(nn.z, kk.z, V.cos_o),
+                      fresnel(nn.w, kk.w, V.cos_o)};
+        const float rho[4] = {rr.x, rr.y, rr.z, rr.w};
+        float dif[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          dif[c] = (1.0f - F[c]) * rho[c];
+          if (4 * q + c < B) {
+            a_sum += F[c];
+            b_sum += dif[c];
           }
         }
+        if (nee) {
+          const float4 bb = b4[q], EE = E4[q];
+          e4[q] = make_float4(bb.x * dif[0] * kn * EE.x, bb.y * dif[1] * kn * EE.y, bb.z * dif[2] * kn * EE.z,
+                              bb.w * dif[3] * kn * EE.w);
+        }
       }
-      if ((f & kFlagExt) && depth <= max_depth) {
-        const float4 h = w.hit[s];
-        const uint32_t id = __float_as_uint(h.y);
-        const float4 rdir = w.rays[2 * s + 1];
-        const F3 d = f3(rdir.x, rdir.y, rdir.z);
-        if (id == 0xFFFFFFFFu) {
-          // escaped: environment radiance
-          if (S.env_nonzero)
-            for (int j = 0; j < B; ++j) {
-              const float c_j = w.beta[(size_t)j * W + s] * S.env[j] * inv_spp;
-              if (c_j != 0.0f) unsafeAtomicAdd(img + (size_t)j * plane, c_j);
-            }
+      if (nee) {
+        has_sh = true;
+        const F3 so = V.p + V.n * V.eps;
+        w.rays[2 * (W + s)] = make_float4(so.x, so.y, so.z, __uint_as_float(V.id));
+        w.rays[2 * (W + s) + 1] = make_float4(ws.x, ws.y, ws.z, __uint_as_float(s | kShadowBit));
+        w.shcnt[s] = 0;
+        sh_cell = start_cell(S, so, ws);
+      }
+      const float am = a_sum / (float)B, bm = b_sum / (float)B;
+      if (depth < max_depth && am + bm > 0.0f) {
+        const float Ps = am / (am + bm);
+        const bool mirror = u0 < Ps;
+        const float inv_p = mirror ? 1.0f / Ps : 1.0f / (1.0f - Ps);
+        for (int q = 0; q < nq; ++q) {
+          const float4 nn = nt[q], kk = kt[q], rr = rt[q];
+          const float F0 = fresnel(nn.x, kk.x, V.cos_o), F1 = fresnel(nn.y, kk.y, V.cos_o);
+          const float F2 = fresnel(nn.z, kk.z, V.cos_o), F3v = fresnel(nn.w, kk.w, V.cos_o);
+          float4 bb = b4[q];
+          bb.x *= (mirror ? F0 : (1.0f - F0) * rr.x) * inv_p;
+          bb.y *= (mirror ? F1 : (1.0f - F1) * rr.y) * inv_p;
+          bb.z *= (mirror ? F2 : (1.0f - F2) * rr.z) * inv_p;
+          bb.w *= (mirror ? F3v : (1.0f - F3v) * rr.w) * inv_p;
+          b4[q] = bb;
+        }
+        F3 nd;
+        if (mirror) {
+          nd = V.d - V.ng * (2.0f * V.dn);
         } else {
-          n_vert = 1;
-          const float4 A = S.gtris[(size_t)id * 3 + 0], Bv = S.gtris[(size_t)id * 3 + 1], C = S.gtris[(size_t)id * 3 + 2];
-          const F3 v0 = f3(A.x, A.y, A.z), v1 = f3(Bv.x, Bv.y, Bv.z), v2 = f3(C.x, C.y, C.z);
-          const int m = (int)__float_as_uint(Bv.w);
-          const F3 ng = geo_normal(v0, v1, v2);
-          const float dn = dot_exact_sign(d, ng);
-          const F3 n = dn > 0.0f ? ng * -1.0f : ng;
-          const float cos_o = fabsf(dn);
-          const float bu = h.z, bv = h.w;
-          const F3 pt = v0 * (1.0f - bu - bv) + v1 * bu + v2 * bv;
-          const float eps = 1e-5f * (1.0f + maxabs3(pt));
-          const uint4 rn = philox(make_uint4(pix, w.smp[s], (uint32_t)depth, V.view_id), key0, key1);
-          const float u0 = unif24(rn.x), u1 = unif24(rn.y), u2 = unif24(rn.z);
-          const float* nt = S.ntab + m * B;
-          const float* kt = S.ktab + m * B;
-          const float* rt = S.rho + m * B;
-          F3 no, nd;
-          bool cont = false;
-          if (S.mtype[m] == 0) {
-            const F3 ws = f3(S.sun[0], S.sun[1], S.sun[2]);
-            const float cs = dot_exact_sign(n, ws);
-            const bool nee = cs > 0.0f;
-            const float kn = cs * (1.0f / 3.14159265358979f);
-            float a_sum = 0.0f, b_sum = 0.0f;
-            for (int j = 0; j < B; ++j) {
-              const float F = fresnel(nt[j], kt[j], cos_o);
-              const float dif = (1.0f - F) * rt[j];
-              a_sum += F;
-              b_sum += dif;
-              if (nee) w.nee[(size_t)j * W + s] = w.beta[(size_t)j * W + s] * dif * kn * S.sunE[j];
-            }
-            if (nee) {
-              nflags |= kFlagShadow;
-              n_sh = 1;
-              const F3 so = pt + n * eps;
-              w.rays[2 * (W + s)] = make_float4(so.x, so.y, so.z, __uint_as_float(id));
-              w.rays[2 * (W + s) + 1] = make_float4(ws.x, ws.y, ws.z, __uint_as_float(s | kShadowBit));
-              w.shcnt[s] = 0;
-              sh_cell = start_cell(S, so, ws);
-              if (sh_cell == kInvalidCell) w.shcnt[s] = 0;
-            }
-            if (depth < max_depth) {
-              const float am = a_sum / (float)B, bm = b_sum / (float)B;
-              if (am + bm > 0.0f) {
-                const float Ps = am / (am + bm);
-                cont = true;
-                if (u0 < Ps) {
-                  const float inv_p = 1.0f / Ps;
-                  for (int j = 0; j < B; ++j) {
-                    const float F = fresnel(nt[j], kt[j], cos_o);
-                    w.beta[(size_t)j * W + s] *= F * inv_p;
-                  }
-                  nd = d - ng * (2.0f * dn);
-                } else {
-                  const float inv_p = 1.0f / (1.0f - Ps);
-                  for (int j = 0; j < B; ++j) {
-                    const float F = fresnel(nt[j], kt[j], cos_o);
-                    w.beta[(size_t)j * W + s] *= (1.0f - F) * rt[j] * inv_p;
-                  }
-                  float sn, cn;
-                  sincosf(2.0f * 3.14159265358979f * u1, &sn, &cn);
-                  const float rr = sqrtf(u2);
-                  const float lx = rr * cn, ly = rr * sn, lz = sqrtf(fmaxf(0.0f, 1.0f - u2));
-                  // orthonormal basis around n (Duff et al., JCGT 2017)
-                  const float sg = copysignf(1.0f, n.z);
-                  const float aa = -1.0f / (sg + n.z);
-                  const float bb = n.x * n.y * aa;
-                  const F3 t1 = f3(1.0f + sg * n.x * n.x * aa, sg * bb, -sg * n.x);
-                  const F3 t2 = f3(bb, sg + n.y * n.y * aa, -n.y);
-                  nd = t1 * lx + t2 * ly + n * lz;
-                }
-                no = pt + n * eps;
-              }
-            }
-          } else if (depth < max_depth) {
-            float mr = 0.0f, mt = 0.0f;
-            const float th = S.thick[m];
-            for (int j = 0; j < B; ++j) {
-              float Rj, Tj;
-              slab(nt[j], kt[j], S.lambda[j], th, cos_o, Rj, Tj);
-              mr += Rj;
-              mt += Tj;
-            }
-            const float Pr = mr / (mr + mt);
-            cont = true;
-            if (u0 < Pr) {
-              const float inv_p = 1.0f / Pr;
-              for (int j = 0; j < B; ++j) {
-                float Rj, Tj;
-                slab(nt[j], kt[j], S.lambda[j], th, cos_o, Rj, Tj);
-                w.beta[(size_t)j * W + s] *= Rj * inv_p;
-              }
-              nd = d - ng * (2.0f * dn);
-              no = pt + n * eps;
-            } else {
-              const float inv_p = 1.0f / (1.0f - Pr);
-              for (int j = 0; j < B; ++j) {
-                float Rj, Tj;
-                slab(nt[j], kt[j], S.lambda[j], th, cos_o, Rj, Tj);
-                w.beta[(size_t)j * W + s] *= Tj * inv_p;
-              }
-              nd = d;
-              no = pt - n * eps;
-            }
-          }
-          if (cont) {
-            nflags |= kFlagExt;
-            w.rays[2 * s] = make_float4(no.x, no.y, no.z, __uint_as_float(id));
-            w.rays[2 * s + 1] = make_float4(nd.x, nd.y, nd.z, __uint_as_float(s));
-            ext_cell = start_cell(S, no, nd);
-            if (ext_cell == kInvalidCell) w.hit[s] = make_float4(INFINITY, __uint_as_float(0xFFFFFFFFu), 0.0f, 0.0f);
-          }
+          float sn, cn;
+          sincosf(2.0f * 3.14159265358979f * u1, &sn, &cn);
+          const float rr = sqrtf(u2);
+          const float lx = rr * cn, ly = rr * sn, lz = sqrtf(fmaxf(0.0f, 1.0f - u2));
+          // orthonormal basis around n (Duff et al., JCGT 2017)
+          const F3 nrm = V.n;
+          const float sg = copysignf(1.0f, nrm.z);
+          const float aa = -1.0f / (sg + nrm.z);
+          const float bb = nrm.x * nrm.y * aa;
+          const F3 t1 = f3(1.0f + sg * nrm.x * nrm.x * aa, sg * bb, -sg * nrm.x);
+          const F3 t2 = f3(bb, sg + nrm.y * nrm.y * aa, -nrm.y);
+          nd = t1 * lx + t2 * ly + nrm * lz;
         }
+        const F3 no = V.p + V.n * V.eps;
+        has_ext = true;
+        w.rays[2 * s] = make_float4(no.x, no.y, no.z, __uint_as_float(V.id));
+        w.rays[2 * s + 1] = make_float4(nd.x, nd.y, nd.z, __uint_as_float(s));
+        ext_cell = start_cell(S, no, nd);
+        if (ext_cell == kInvalidCell) w.hit[s] = make_float4(INFINITY, __uint_as_float(0xFFFFFFFFu), 0.0f, 0.0f);
       }
-      w.flags[s] = nflags;
     }
-    // next active list: every slot with a ray in flight
-    const bool keep = valid && nflags != 0;
-    const uint64_t m = __ballot(keep);
-    if (m) {
-      const uint32_t leader = (uint32_t)__ffsll((unsigned long long)m) - 1u;
-      uint32_t base = 0;
-      if (lane_id() == leader) base = atomicAdd(&w.ctl->act_count[wr], (uint32_t)__popcll(m));
-      base = __shfl(base, (int)leader);
-      if (keep) w.active[(size_t)wr * W + base + count_below(m)] = s;
+    wave_append(has_ext && ext_cell != kInvalidCell, s | kFirstVisit, ext_cell, &w.ctl->list_count[gp],
+                w.ccount + (size_t)gp * S.n_cells, w.lsrc, w.ldst, w.lrank);
+    wave_append(has_sh && sh_cell != kInvalidCell, ((uint32_t)W + s) | kFirstVisit, sh_cell, &w.ctl->list_count[gp],
+                w.ccount + (size_t)gp * S.n_cells, w.lsrc, w.ldst, w.lrank);
+    // rays that miss the grid box finish at once: straight into the next bounce's lists
+    wave_push(has_sh && sh_cell == kInvalidCell, s, &w.ctl->cat_count[p ^ 1][kCatShadowClear],
+              cat_list(w, p ^ 1, kCatShadowClear));
+    wave_push(has_ext && ext_cell == kInvalidCell && S.env_nonzero, s, &w.ctl->cat_count[p ^ 1][kCatEscape],
+              cat_list(w, p ^ 1, kCatEscape));
+    wave_add(&w.ctl->st_vertices, valid ? 1u : 0u);
+    wave_add(&w.ctl->st_shadow, has_sh ? 1u : 0u);
+    wave_add(&w.ctl->st_ext, has_ext ? 1u : 0u);
+  }
+}
+
+// Glass vertex: thin slab, reflect with probability mean R / (mean R + mean T), else transmit
+// straight through (no lateral shift); no direct term at glass.
+__global__ __launch_bounds__(kWG) void k_shade_glass(DevScene S, DevWS w, int depth, uint32_t key0, uint32_t key1,
+                                                     int gen) {
+  const int p = depth & 1;
+  const uint32_t n = w.ctl->cat_count[p][kCatGlass];
+  const uint32_t* list = cat_list(w, p, kCatGlass);
+  const int B = S.n_bins, Bp = w.Bp;
+  const int gp = gen & 1;
+  const uint32_t n_iter = (n + kWG - 1) / kWG * kWG;
+  for (uint32_t a = blockIdx.x * kWG + threadIdx.x; a < n_iter; a += gridDim.x * kWG) {
+    const bool valid = a < n;
+    uint32_t s = 0, ext_cell = kInvalidCell;
+    if (valid) {
+      s = list[a];
+      const Vertex V = load_vertex(S, w, s);
+      const uint4 rn = philox(make_uint4(w.pix[s], w.smp[s], (uint32_t)depth, w.views[w.view[s]].view_id), key0, key1);
+      const float u0 = unif24(rn.x);
+      const float* nt = S.ntab + V.m * Bp;
+      const float* kt = S.ktab + V.m * Bp;
+      const float th = S.thick[V.m];
+      float mr = 0.0f, mt = 0.0f;
+      for (int j = 0; j < B; ++j) {
+        float Rj, Tj;
+        slab(nt[j], kt[j], S.lambda[j], th, V.cos_o, Rj, Tj);
+        mr += Rj;
+        mt += Tj;
+      }
+      const float Pr = mr / (mr + mt);
+      const bool refl = u0 < Pr;
+      const float inv_p = refl ? 1.0f / Pr : 1.0f / (1.0f - Pr);
+      float* b = w.beta + (size_t)s * Bp;
+      for (int j = 0; j < B; ++j) {
+        float Rj, Tj;
+        slab(nt[j], kt[j], S.lambda[j], th, V.cos_o, Rj, Tj);
+        b[j] *= (refl ? Rj : Tj) * inv_p;
+      }
+      const F3 nd = refl ? V.d - V.ng * (2.0f * V.dn) : V.d;
+      const F3 no = refl ? V.p + V.n * V.eps : V.p - V.n * V.eps;
+      w.rays[2 * s] = make_float4(no.x, no.y, no.z, __uint_as_float(V.id));
+      w.rays[2 * s + 1] = make_float4(nd.x, nd.y, nd.z, __uint_as_float(s));
+      ext_cell = start_cell(S, no, nd);
+      if (ext_cell == kInvalidCell) w.hit[s] = make_float4(INFINITY, __uint_as_float(0xFFFFFFFFu), 0.0f, 0.0f);
     }
-    wave_append(valid && ext_cell != kInvalidCell, s | kFirstVisit, ext_cell, &w.ctl->list_count[p],
-                w.ccount + (size_t)p * S.n_cells, w.lsrc, w.ldst, w.lrank);
-    wave_append(valid && sh_cell != kInvalidCell, ((uint32_t)W + s) | kFirstVisit, sh_cell, &w.ctl->list_count[p],
-                w.ccount + (size_t)p * S.n_cells, w.lsrc, w.ldst, w.lrank);
-    wave_add(&w.ctl->st_vertices, n_vert);
-    wave_add(&w.ctl->st_shadow, n_sh);
-    wave_add(&w.ctl->st_ext, (valid && (nflags & kFlagExt)) ? 1u : 0u);
+    wave_append(valid && ext_cell != kInvalidCell, s | kFirstVisit, ext_cell, &w.ctl->list_count[gp],
+                w.ccount + (size_t)gp * S.n_cells, w.lsrc, w.ldst, w.lrank);
+    wave_push(valid && ext_cell == kInvalidCell && S.env_nonzero, s, &w.ctl->cat_count[p ^ 1][kCatEscape],
+              cat_list(w, p ^ 1, kCatEscape));
+    wave_add(&w.ctl->st_vertices, valid ? 1u : 0u);
+    wave_add(&w.ctl->st_ext, valid ? 1u : 0u);
+  }
+}
+
+// End of a wavefront: every path's gathered radiance, divided by the view's spp, into its
+// pixel of the spectral image [B][H][W]. Slots are visited in order, so a wave adds to
+// consecutive pixels of one bin plane at a time.
+__global__ __launch_bounds__(kWG) void k_accumulate(DevScene S, DevWS w, uint32_t n) {
+  const int B = S.n_bins, Bp = w.Bp;
+  for (uint32_t s = blockIdx.x * kWG + threadIdx.x; s < n; s += gridDim.x * kWG) {
+    const ViewDesc& V = w.views[w.view[s]];
+    const size_t plane = (size_t)V.width * V.height;
+    float* img = V.image + w.pix[s];
+    const float* l = w.lacc + (size_t)s * Bp;
+    for (int j = 0; j < B; ++j) {
+      const float c = l[j] * V.inv_spp;
+      if (c != 0.0f) unsafeAtomicAdd(img + (size_t)j * plane, c);
+    }
   }
 }
 
@@ -980,15 +1093,36 @@ hipError_t launch_scatter(const Launch& L, const DevWS& w, int gen) {
   return hipGetLastError();
 }
 
-hipError_t launch_trace(const Launch& L, const DevScene& S, const DevWS& w, int gen, int hops) {
-  hipLaunchKernelGGL(k_trace, dim3(L.trace_blocks), dim3(kWG), 0, L.stream, S, w, gen, hops);
+hipError_t launch_trace(const Launch& L, const DevScene& S, const DevWS& w, int gen, int hops, int cat_par) {
+  hipLaunchKernelGGL(k_trace, dim3(L.trace_blocks), dim3(kWG), 0, L.stream, S, w, gen, hops, cat_par);
   return hipGetLastError();
 }
 
-hipError_t launch_shade(const Launch& L, const DevScene& S, const DevWS& w, int depth, int max_depth, uint64_t seed,
-                        int gen) {
-  hipLaunchKernelGGL(k_shade, dim3(grid_for(w.W, 4096)), dim3(kWG), 0, L.stream, S, w, depth, max_depth,
+hipError_t launch_resolve(const Launch& L, const DevScene& S, const DevWS& w, int depth) {
+  hipLaunchKernelGGL(k_resolve, dim3(grid_for(2 * (size_t)w.W, 4096)), dim3(kWG), 0, L.stream, S, w, depth);
+  return hipGetLastError();
+}
+
+hipError_t launch_escape(const Launch& L, const DevScene& S, const DevWS& w, int depth) {
+  hipLaunchKernelGGL(k_escape, dim3(grid_for(w.W, 2048)), dim3(kWG), 0, L.stream, S, w, depth);
+  return hipGetLastError();
+}
+
+hipError_t launch_shade_opaque(const Launch& L, const DevScene& S, const DevWS& w, int depth, int max_depth,
+                               uint64_t seed, int gen) {
+  hipLaunchKernelGGL(k_shade_opaque, dim3(grid_for(w.W, 4096)), dim3(kWG), 0, L.stream, S, w, depth, max_depth,
                      (uint32_t)seed, (uint32_t)(seed >> 32), gen);
+  return hipGetLastError();
+}
+
+hipError_t launch_shade_glass(const Launch& L, const DevScene& S, const DevWS& w, int depth, uint64_t seed, int gen) {
+  hipLaunchKernelGGL(k_shade_glass, dim3(grid_for(w.W, 1024)), dim3(kWG), 0, L.stream, S, w, depth, (uint32_t)seed,
+                     (uint32_t)(seed >> 32), gen);
+  return hipGetLastError();
+}
+
+hipError_t launch_accumulate(const Launch& L, const DevScene& S, const DevWS& w, uint32_t n) {
+  hipLaunchKernelGGL(k_accumulate, dim3(grid_for(n, 8192)), dim3(kWG), 0, L.stream, S, w, n);
   return hipGetLastError();
 }
 

@@ -418,12 +418,16 @@ std::string build_scene(const sdd_scene_desc& d, sdd_scene* out) {
   H.off_gtris = off;  off = align256(off + (size_t)N * 48);
   H.off_mtype = off;  off = align256(off + (size_t)M * 4);
   H.off_thick = off;  off = align256(off + (size_t)M * 4);
-  H.off_n = off;      off = align256(off + (size_t)M * B * 4);
-  H.off_k = off;      off = align256(off + (size_t)M * B * 4);
-  H.off_rho = off;    off = align256(off + (size_t)M * B * 4);
-  H.off_lambda = off; off = align256(off + (size_t)B * 4);
-  H.off_sunE = off;   off = align256(off + (size_t)B * 4);
-  H.off_env = off;    off = align256(off + (size_t)B * 4);
+  // spectral tables use a row stride of Bp = B rounded up to 4 so kernels read them as float4;
+  // the padding bins hold harmless values (n = 1.5, k = 0, rho = 0, E = 0, lambda = 500 nm)
+  const int Bp = (B + 3) & ~3;
+  H.off_n = off;      off = align256(off + (size_t)M * Bp * 4);
+  H.off_k = off;      off = align256(off + (size_t)M * Bp * 4);
+  H.off_rho = off;    off = align256(off + (size_t)M * Bp * 4);
+  H.off_lambda = off; off = align256(off + (size_t)Bp * 4);
+  H.off_sunE = off;   off = align256(off + (size_t)Bp * 4);
+  H.off_env = off;    off = align256(off + (size_t)Bp * 4);
+  H.bins_pad = Bp;
   H.n_nodes = n_nodes;
   H.n_refs = n_refs;
   out->image.assign(off, 0);
@@ -475,14 +479,24 @@ std::string build_scene(const sdd_scene_desc& d, sdd_scene* out) {
     mt[m] = d.materials[m].type;
     th[m] = d.materials[m].thickness_m;
   }
-  std::memcpy(img + H.off_n, d.n_tab, (size_t)M * B * 4);
-  std::memcpy(img + H.off_k, d.k_tab, (size_t)M * B * 4);
-  std::memcpy(img + H.off_rho, d.rho_tab, (size_t)M * B * 4);
+  float* tn = (float*)(img + H.off_n);
+  float* tk = (float*)(img + H.off_k);
+  float* tr = (float*)(img + H.off_rho);
+  for (int m = 0; m < M; ++m)
+    for (int j = 0; j < Bp; ++j) {
+      tn[m * Bp + j] = j < B ? d.n_tab[m * B + j] : 1.5f;
+      tk[m * Bp + j] = j < B ? d.k_tab[m * B + j] : 0.0f;
+      tr[m * Bp + j] = j < B ? d.rho_tab[m * B + j] : 0.0f;
+    }
   float* lam = (float*)(img + H.off_lambda);
-  for (int j = 0; j < B; ++j)
-    lam[j] = (float)((double)d.lambda_min_nm + (j + 0.5) * ((double)d.lambda_max_nm - d.lambda_min_nm) / B);
-  std::memcpy(img + H.off_sunE, d.sun_irradiance, (size_t)B * 4);
-  if (d.env_radiance) std::memcpy(img + H.off_env, d.env_radiance, (size_t)B * 4);
+  float* sE = (float*)(img + H.off_sunE);
+  float* sL = (float*)(img + H.off_env);
+  for (int j = 0; j < Bp; ++j) {
+    lam[j] = j < B ? (float)((double)d.lambda_min_nm + (j + 0.5) * ((double)d.lambda_max_nm - d.lambda_min_nm) / B)
+                   : 500.0f;
+    sE[j] = j < B ? d.sun_irradiance[j] : 0.0f;
+    sL[j] = (j < B && d.env_radiance) ? d.env_radiance[j] : 0.0f;
+  }
 
   out->hdr = H;
   sdd_scene_info& I = out->info;
@@ -531,6 +545,7 @@ DevScene device_view(const sdd_scene* s) {
     S.sun[a] = H.sun[a];
   }
   S.n_bins = H.n_bins;
+  S.bins_pad = H.bins_pad;
   S.n_mat = H.n_mat;
   S.env_nonzero = H.env_nonzero;
   return S;

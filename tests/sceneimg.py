@@ -7,7 +7,7 @@ HEADER = np.dtype([
     ("env_nonzero", "<i4"), ("off_planes", "<u8"), ("off_cells", "<u8"), ("off_nodes", "<u8"), ("off_ctris", "<u8"),
     ("off_gtris", "<u8"), ("off_mtype", "<u8"), ("off_thick", "<u8"), ("off_n", "<u8"), ("off_k", "<u8"),
     ("off_rho", "<u8"), ("off_lambda", "<u8"), ("off_sunE", "<u8"), ("off_env", "<u8"), ("n_nodes", "<u8"),
-    ("n_refs", "<u8"), ("lambda_min_nm", "<f4"), ("lambda_max_nm", "<f4"), ("max_leaf", "<i4")])
+    ("n_refs", "<u8"), ("lambda_min_nm", "<f4"), ("lambda_max_nm", "<f4"), ("max_leaf", "<i4"), ("bins_pad", "<i4")])
 
 EMPTY = 0xFFFFFFFF
 

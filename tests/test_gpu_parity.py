@@ -300,3 +300,18 @@ def test_progressive_split_is_exact(ctx, church):
     err = ((comb - full).abs().max() / full.abs().max()).item()
     say(f"split 3+5 vs 8: max rel {err:.2e}")
     assert err < 1e-5
+
+
+@pytest.mark.parametrize("depth", [1, 3])
+def test_environment_radiance_parity(ctx, depth):
+    """Escaping rays pick up the environment radiance: nave with a non-zero sky, sun on."""
+    import paper_1912_04000_amd as sd
+    sc = scenegen.nave_scene(8)
+    sc.env = np.linspace(0.2, 0.6, 8).astype(np.float32)
+    cam = scenegen.nave_camera(40, 40)
+    S = _scene(ctx, sc, (2, 2, 2))
+    img = ctx.render(S, sd.camera(cam.eye, cam.target, cam.up, cam.vfov_deg, cam.width, cam.height),
+                     sd.render_params(spp=2, max_depth=depth, seed=4)).cpu().numpy()
+    ref = oracle.render(sc, cam, spp=2, max_depth=depth, seed=4)
+    ok = _pixel_parity(img, ref.image, ref.tied, f"env D={depth}")
+    assert ok.mean() > 0.9
