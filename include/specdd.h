@@ -133,6 +133,10 @@ typedef struct {
   int32_t first_sample;        /* samples [first_sample, first_sample + spp) of each pixel are
                                   drawn; renders of consecutive sample ranges average exactly
                                   to one longer render (progressive / resumable rendering)    */
+  int32_t use_graph;           /* 1: the call's whole launch sequence is captured into a HIP
+                                  graph the first time and replayed (one graph launch) while
+                                  the same call (scene, views, images, workspace, parameters)
+                                  repeats; timing then covers the whole graph               */
 } sdd_render_params;
 
 /* Workspace bytes for rendering with these parameters (paths in flight, bins, cells). */
@@ -175,6 +179,46 @@ int sdd_shadow(sdd_ctx* ctx, const sdd_scene* scene, const float* orig, const fl
  * uint32 (device). The generator that drives every random decision of the renderer. */
 int sdd_philox(sdd_ctx* ctx, const uint32_t ctr[4], const uint32_t key[2], int64_t n, uint32_t* out_dev);
 
+/* Search space of the autotuner. */
+typedef struct {
+  int32_t n_waves;             /* wavefront sizes (paths in flight) to try, 1..8            */
+  int32_t wave_paths[8];
+  int32_t n_grids;             /* cell grids to try, 1..8                                   */
+  int32_t grids[8][3];
+  int32_t n_rounds;            /* queue_rounds values to try, 1..4                          */
+  int32_t queue_rounds[4];
+  int32_t calib_spp;           /* samples per pixel of every view in calibration renders    */
+  int32_t reps;                /* timed repetitions per candidate (the fastest is kept)     */
+} sdd_tune_space;
+
+typedef struct {
+  int32_t grid[3];
+  int32_t wave_paths;
+  int32_t queue_rounds;
+  int32_t pad;
+  double samples_per_s;
+} sdd_tune_point;
+
+typedef struct {
+  sdd_tune_point best;         /* fastest candidate                                          */
+  int32_t from_cache;          /* 1: taken from the cache file, nothing was measured          */
+  int32_t n_tried;             /* candidates measured (skipped ones do not count)            */
+  sdd_tune_point tried[128];
+} sdd_tune_result;
+
+/* Autotuner: picks the cell grid, wavefront size and queue rounds with the highest throughput
+ * on short calibration renders of the given views (calib_spp samples each), timed with HIP
+ * events. The scene is rebuilt on the host for every grid and uploaded to scene_buf; grids whose
+ * scene does not fit scene_bytes, and wavefront sizes whose workspace does not fit ws_bytes, are
+ * skipped. images are the views' output images (overwritten). The result is appended to the
+ * JSON-lines file cache_path (may be NULL) under a key made of the scene arrays, bins, depth,
+ * views and device name; a later call with the same key returns the cached choice without
+ * rendering. */
+int sdd_autotune(sdd_ctx* ctx, const sdd_scene_desc* desc, const sdd_camera* views, int32_t n_views,
+                 const sdd_render_params* base, const sdd_tune_space* space, void* scene_buf, size_t scene_bytes,
+                 void* workspace, size_t ws_bytes, float* const* images, const char* cache_path,
+                 sdd_tune_result* out);
+
 /* Wait for the context stream, then report device-side errors (capacity overflow, non-finite
  * values) of the work enqueued since the previous sdd_finish. */
 int sdd_finish(sdd_ctx* ctx);
@@ -186,6 +230,8 @@ typedef struct {
   uint64_t node_visits, tri_tests; /* BVH nodes visited and triangle tests of the traversal     */
   double trace_ms;             /* HIP-event time of the traversal launches (timing = 1)      */
   double shade_ms;             /* HIP-event time of the shading launches (timing = 1)        */
+  uint64_t graph_launches;     /* graph-mode renders replayed                                 */
+  double graph_ms;             /* HIP-event time of the graph launches (timing = 1)          */
 } sdd_stats;
 
 /* Counters accumulated since the previous sdd_reset_stats (valid after sdd_finish). */

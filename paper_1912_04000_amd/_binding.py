@@ -54,7 +54,7 @@ class Camera(C.Structure):
 class RenderParams(C.Structure):
     _fields_ = [("spp", C.c_int32), ("max_depth", C.c_int32), ("seed", C.c_uint64), ("mode", C.c_int32),
                 ("wave_paths", C.c_int32), ("queue_rounds", C.c_int32), ("view", C.c_uint32),
-                ("timing", C.c_int32), ("first_sample", C.c_int32)]
+                ("timing", C.c_int32), ("first_sample", C.c_int32), ("use_graph", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -62,10 +62,29 @@ class Stats(C.Structure):
         "paths", "vertices", "ext_rays", "shadow_rays", "cell_visits", "migrations", "escapes", "glass_crossings",
         "trace_launches", "shade_launches", "wavefronts", "err_cross_overflow", "err_nonfinite", "err_stack",
         "node_visits", "tri_tests")] + [
-        ("trace_ms", C.c_double), ("shade_ms", C.c_double)]
+        ("trace_ms", C.c_double), ("shade_ms", C.c_double), ("graph_launches", C.c_uint64), ("graph_ms", C.c_double)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class TuneSpace(C.Structure):
+    _fields_ = [("n_waves", C.c_int32), ("wave_paths", C.c_int32 * 8), ("n_grids", C.c_int32),
+                ("grids", (C.c_int32 * 3) * 8), ("n_rounds", C.c_int32), ("queue_rounds", C.c_int32 * 4),
+                ("calib_spp", C.c_int32), ("reps", C.c_int32)]
+
+
+class TunePoint(C.Structure):
+    _fields_ = [("grid", C.c_int32 * 3), ("wave_paths", C.c_int32), ("queue_rounds", C.c_int32), ("pad", C.c_int32),
+                ("samples_per_s", C.c_double)]
+
+    def as_dict(self):
+        return dict(grid=list(self.grid), wave_paths=self.wave_paths, queue_rounds=self.queue_rounds,
+                    samples_per_s=self.samples_per_s)
+
+
+class TuneResult(C.Structure):
+    _fields_ = [("best", TunePoint), ("from_cache", C.c_int32), ("n_tried", C.c_int32), ("tried", TunePoint * 128)]
 
 
 # Every exported function: (name, restype, argtypes)
@@ -91,6 +110,7 @@ SIGNATURES = [
     ("sdd_get_stats", _i32, [_vp, _vp]),
     ("sdd_reset_stats", _i32, [_vp]),
     ("sdd_last_error", C.c_char_p, [_vp]),
+    ("sdd_autotune", _i32, [_vp, _vp, _vp, _i32, _vp, _vp, _vp, _sz, _vp, _sz, _vp, C.c_char_p, _vp]),
 ]
 
 _lib = None
@@ -129,39 +149,52 @@ def _ptr(a):
     return a.data_ptr()
 
 
+def make_desc(verts, mat, mat_type, thickness_m, n_tab, k_tab, rho_tab, lambda_min_nm, lambda_max_nm, sun_dir, sun_E,
+              env=None, grid=(2, 2, 2)):
+    """sdd_scene_desc over host arrays; returns the struct and the arrays it points into."""
+    keep = dict(
+        verts=np.ascontiguousarray(verts, dtype=np.float32), mat=np.ascontiguousarray(mat, dtype=np.uint16),
+        n=np.ascontiguousarray(n_tab, dtype=np.float32), k=np.ascontiguousarray(k_tab, dtype=np.float32),
+        rho=np.ascontiguousarray(rho_tab, dtype=np.float32), E=np.ascontiguousarray(sun_E, dtype=np.float32),
+        env=None if env is None else np.ascontiguousarray(env, dtype=np.float32))
+    n_mat = len(mat_type)
+    mats = (Material * n_mat)()
+    for i in range(n_mat):
+        mats[i].type = int(mat_type[i])
+        mats[i].thickness_m = float(thickness_m[i])
+    keep["mats"] = mats
+    d = SceneDesc()
+    d.verts = _ptr(keep["verts"])
+    d.mat = _ptr(keep["mat"])
+    d.n_tri = keep["verts"].shape[0]
+    d.materials = C.cast(mats, C.c_void_p)
+    d.n_mat = n_mat
+    d.n_tab, d.k_tab, d.rho_tab = _ptr(keep["n"]), _ptr(keep["k"]), _ptr(keep["rho"])
+    d.n_bins = int(keep["n"].shape[1])
+    d.lambda_min_nm, d.lambda_max_nm = float(lambda_min_nm), float(lambda_max_nm)
+    d.sun_dir[:] = [float(x) for x in sun_dir]
+    d.sun_irradiance = _ptr(keep["E"])
+    d.env_radiance = _ptr(keep["env"]) if keep["env"] is not None else None
+    d.grid[:] = [int(g) for g in grid]
+    return d, keep
+
+
+def desc_from(sc, grid=(2, 2, 2)):
+    return make_desc(sc.verts, sc.mat, sc.mat_type, sc.thickness_m, sc.n_tab, sc.k_tab, sc.rho_tab, sc.lambda_min_nm,
+                     sc.lambda_max_nm, sc.sun_dir, sc.sun_E, sc.env, grid)
+
+
 class Scene:
     """Host-built cell-decomposed scene (``sdd_scene``), optionally uploaded to a device buffer."""
 
     def __init__(self, verts, mat, mat_type, thickness_m, n_tab, k_tab, rho_tab, lambda_min_nm, lambda_max_nm,
                  sun_dir, sun_E, env=None, grid=(2, 2, 2)):
-        self._keep = dict(
-            verts=np.ascontiguousarray(verts, dtype=np.float32), mat=np.ascontiguousarray(mat, dtype=np.uint16),
-            n=np.ascontiguousarray(n_tab, dtype=np.float32), k=np.ascontiguousarray(k_tab, dtype=np.float32),
-            rho=np.ascontiguousarray(rho_tab, dtype=np.float32), E=np.ascontiguousarray(sun_E, dtype=np.float32),
-            env=None if env is None else np.ascontiguousarray(env, dtype=np.float32))
-        n_mat = len(mat_type)
-        mats = (Material * n_mat)()
-        for i in range(n_mat):
-            mats[i].type = int(mat_type[i])
-            mats[i].thickness_m = float(thickness_m[i])
-        self._keep["mats"] = mats
-        k = self._keep
-        self.n_bins = int(k["n"].shape[1])
-        d = SceneDesc()
-        d.verts = _ptr(k["verts"])
-        d.mat = _ptr(k["mat"])
-        d.n_tri = k["verts"].shape[0]
-        d.materials = C.cast(mats, C.c_void_p)
-        d.n_mat = n_mat
-        d.n_tab, d.k_tab, d.rho_tab = _ptr(k["n"]), _ptr(k["k"]), _ptr(k["rho"])
-        d.n_bins = self.n_bins
-        d.lambda_min_nm, d.lambda_max_nm = float(lambda_min_nm), float(lambda_max_nm)
-        d.sun_dir[:] = [float(x) for x in sun_dir]
-        d.sun_irradiance = _ptr(k["E"])
-        d.env_radiance = _ptr(k["env"]) if k["env"] is not None else None
-        d.grid[:] = [int(g) for g in grid]
+        d, self._keep = make_desc(verts, mat, mat_type, thickness_m, n_tab, k_tab, rho_tab, lambda_min_nm,
+                                  lambda_max_nm, sun_dir, sun_E, env, grid)
+        self.n_bins = d.n_bins
         h = C.c_void_p()
         _check(lib().sdd_scene_create(C.byref(d), C.byref(h)))
+        self._desc = d
         self.handle = h
         self.grid = tuple(int(g) for g in grid)
         self.device_buffer = None
@@ -206,9 +239,10 @@ def camera(eye, target, up=(0.0, 0.0, 1.0), vfov_deg=60.0, width=64, height=64) 
 
 
 def render_params(spp=1, max_depth=4, seed=1, mode=MODE_PLAIN, wave_paths=0, queue_rounds=0, view=0, timing=0,
-                  first_sample=0):
+                  first_sample=0, use_graph=0):
     p = RenderParams()
     p.first_sample = int(first_sample)
+    p.use_graph = int(use_graph)
     p.spp, p.max_depth, p.seed, p.mode = int(spp), int(max_depth), int(seed), int(mode)
     p.wave_paths, p.queue_rounds, p.view, p.timing = int(wave_paths), int(queue_rounds), int(view), int(timing)
     return p
@@ -274,6 +308,51 @@ class Context:
         if finish:
             self.finish()
         return outs
+
+    def autotune(self, scene_description, cams, base: RenderParams, waves, grids, rounds=(1, 2), calib_spp=1,
+                 reps=2, cache_path=None, scene_bytes=None, ws_bytes=None):
+        """Measure (grid, wavefront size, queue rounds) candidates on calibration renders of the
+        views and return the fastest (the library's autotuner; cached in cache_path)."""
+        torch = self.torch
+        d, keep = desc_from(scene_description)
+        sp = TuneSpace()
+        sp.n_waves = len(waves)
+        for i, wv in enumerate(waves):
+            sp.wave_paths[i] = int(wv)
+        sp.n_grids = len(grids)
+        for i, g in enumerate(grids):
+            sp.grids[i][:] = [int(x) for x in g]
+        sp.n_rounds = len(rounds)
+        for i, r in enumerate(rounds):
+            sp.queue_rounds[i] = int(r)
+        sp.calib_spp, sp.reps = int(calib_spp), int(reps)
+        if scene_bytes is None:
+            # finest grid bounds the scene size (more duplicated references): measure it once
+            finest = max(grids, key=lambda g: g[0] * g[1] * g[2])
+            probe = Scene.from_description(scene_description, grid=finest)
+            scene_bytes = int(probe.device_bytes() * 1.25) + (1 << 20)
+        if ws_bytes is None:
+            p = RenderParams()
+            C.memmove(C.byref(p), C.byref(base), C.sizeof(RenderParams))
+            p.wave_paths = int(max(waves))
+            b = C.c_size_t()
+            probe = probe if "probe" in locals() else Scene.from_description(scene_description)
+            _check(lib().sdd_workspace_bytes(probe.handle, C.byref(p), C.byref(b)))
+            ws_bytes = b.value
+        sbuf = torch.empty(scene_bytes + 256, dtype=torch.uint8, device=self.device)
+        soff = (-sbuf.data_ptr()) % 256
+        ws = self.workspace(ws_bytes)
+        n = len(cams)
+        arr = (Camera * n)(*cams)
+        outs = [torch.empty((d.n_bins, c.height, c.width), dtype=torch.float32, device=self.device) for c in cams]
+        ptrs = (C.c_void_p * n)(*[o.data_ptr() for o in outs])
+        res = TuneResult()
+        self._err(lib().sdd_autotune(self.handle, C.byref(d), arr, n, C.byref(base), C.byref(sp),
+                                     C.c_void_p(sbuf.data_ptr() + soff), scene_bytes, C.c_void_p(ws.data_ptr()),
+                                     ws.numel(), ptrs, None if cache_path is None else cache_path.encode(),
+                                     C.byref(res)))
+        return dict(best=res.best.as_dict(), from_cache=bool(res.from_cache),
+                    tried=[res.tried[i].as_dict() for i in range(res.n_tried)])
 
     def _query_ws(self, scene, n):
         b = C.c_size_t()

@@ -16,15 +16,22 @@ struct sdd_ctx {
   std::string err;
   Ctl* last_ctl = nullptr;     // control block of the last launched work (inside a workspace)
   sdd_stats acc;               // accumulated statistics
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_trace, ev_shade;
-  size_t ev_used_trace = 0, ev_used_shade = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_trace, ev_shade, ev_graph;
+  size_t ev_used_trace = 0, ev_used_shade = 0, ev_used_graph = 0;
   int cu_count = 256;
+  // captured launch sequence of the last graph-mode render and the key it was captured for
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  hipStream_t capture_stream = nullptr;   // own stream (default priority) used only to record graphs
+  uint64_t graph_key = 0;
+  uint64_t graph_trace_launches = 0, graph_shade_launches = 0, graph_wavefronts = 0;
 };
 
 namespace sdd {
 
 static thread_local std::string g_thread_err;
 void set_thread_error(const std::string& m) { g_thread_err = m; }
+hipStream_t ctx_stream(const sdd_ctx* ctx) { return ctx->stream; }
 const char* thread_error() { return g_thread_err.c_str(); }
 
 }  // namespace sdd
@@ -243,35 +250,30 @@ int store_views(sdd_ctx* ctx, const std::vector<ViewDesc>& views, const DevWS& w
   return SDD_OK;
 }
 
-int render_views(sdd_ctx* ctx, const sdd_scene* scene, std::vector<ViewDesc>& views, const sdd_render_params* p,
-                 void* ws, size_t ws_bytes) {
-  const int B = scene->hdr.n_bins;
-  uint64_t total = 0;
-  for (auto& v : views) {
-    v.item_base = total;
-    total += (uint64_t)v.width * v.height * (uint64_t)v.spp;
+// FNV-1a over a byte range (graph keys).
+uint64_t fnv(uint64_t h, const void* data, size_t n) {
+  const uint8_t* b = (const uint8_t*)data;
+  for (size_t i = 0; i < n; ++i) {
+    h ^= b[i];
+    h *= 1099511628211ull;
   }
-  uint32_t W = p->wave_paths ? (uint32_t)p->wave_paths : (uint32_t)std::min<uint64_t>(kDefaultWave, total);
-  W = std::max<uint32_t>(W, 64);
-  Plan plan = make_plan(W, B, scene->hdr.n_cells, (int)views.size());
-  if (!ws) return fail(ctx, SDD_ERR_INVALID_ARG, "workspace is null");
-  if (ws_bytes < plan.total)
-    return fail(ctx, SDD_ERR_WORKSPACE,
-                "workspace too small: need " + std::to_string(plan.total) + " bytes, got " + std::to_string(ws_bytes));
-  DevWS w = ws_view(plan, ws);
+  return h;
+}
+
+// Every launch of one render call, in stream order. Statistics are never zeroed here, so the
+// sequence can be captured once and replayed.
+int enqueue_frame(sdd_ctx* ctx, const sdd_scene* scene, const std::vector<ViewDesc>& views,
+                  const sdd_render_params* p, const Plan& plan, const DevWS& w, uint64_t total, bool timing) {
+  const int B = scene->hdr.n_bins;
+  const uint32_t W = plan.W;
   DevScene S = device_view(scene);
   Launch L{ctx->stream, plan.trace_blocks};
   const int rounds = p->queue_rounds ? p->queue_rounds : kDefaultRounds;
-  const bool timing = p->timing != 0;
   int rc = store_views(ctx, views, w);
   if (rc) return rc;
   for (auto& v : views) HIP_TRY(ctx, launch_fill_f32(ctx->stream, v.image, (size_t)B * v.width * v.height, 0.0f));
-  // The wavefront counters restart with every render; the statistics keep accumulating on the
-  // device until sdd_finish collects them (consecutive renders into one workspace add up).
-  const size_t zero_words = (ctx->last_ctl == w.ctl) ? offsetof(Ctl, st_paths) / 4 : sizeof(Ctl) / 4;
-  HIP_TRY(ctx, launch_fill_u32(ctx->stream, (uint32_t*)w.ctl, zero_words, 0u));
+  HIP_TRY(ctx, launch_fill_u32(ctx->stream, (uint32_t*)w.ctl, offsetof(Ctl, st_paths) / 4, 0u));
   HIP_TRY(ctx, launch_fill_u32(ctx->stream, w.ccount, 2ull * scene->hdr.n_cells, 0u));
-  ctx->last_ctl = w.ctl;
   int gen = 0;
   const int D = p->max_depth;
   uint32_t* cat_counts = &w.ctl->cat_count[0][0];
@@ -300,6 +302,90 @@ int render_views(sdd_ctx* ctx, const sdd_scene* scene, std::vector<ViewDesc>& vi
     }
     ctx->acc.wavefronts++;
   }
+  return SDD_OK;
+}
+
+int render_views(sdd_ctx* ctx, const sdd_scene* scene, std::vector<ViewDesc>& views, const sdd_render_params* p,
+                 void* ws, size_t ws_bytes) {
+  const int B = scene->hdr.n_bins;
+  uint64_t total = 0;
+  for (auto& v : views) {
+    v.item_base = total;
+    total += (uint64_t)v.width * v.height * (uint64_t)v.spp;
+  }
+  uint32_t W = p->wave_paths ? (uint32_t)p->wave_paths : (uint32_t)std::min<uint64_t>(kDefaultWave, total);
+  W = std::max<uint32_t>(W, 64);
+  Plan plan = make_plan(W, B, scene->hdr.n_cells, (int)views.size());
+  if (!ws) return fail(ctx, SDD_ERR_INVALID_ARG, "workspace is null");
+  if (ws_bytes < plan.total)
+    return fail(ctx, SDD_ERR_WORKSPACE,
+                "workspace too small: need " + std::to_string(plan.total) + " bytes, got " + std::to_string(ws_bytes));
+  DevWS w = ws_view(plan, ws);
+  // Statistics keep accumulating on the device until sdd_finish collects them; a render into a
+  // workspace other than the previous one starts them afresh (outside any captured graph).
+  if (ctx->last_ctl != w.ctl)
+    HIP_TRY(ctx, launch_fill_u32(ctx->stream, (uint32_t*)&w.ctl->st_paths,
+                                 (sizeof(Ctl) - offsetof(Ctl, st_paths)) / 4, 0u));
+  ctx->last_ctl = w.ctl;
+  if (!p->use_graph) return enqueue_frame(ctx, scene, views, p, plan, w, total, p->timing != 0);
+
+  // Graph mode: capture the whole launch sequence once, replay it while the call repeats.
+  uint64_t key = 1469598103934665603ull;
+  key = fnv(key, views.data(), views.size() * sizeof(ViewDesc));
+  sdd_render_params kp = *p;
+  kp.timing = 0;
+  key = fnv(key, &kp, sizeof(kp));
+  key = fnv(key, &scene->dev, sizeof(void*));
+  key = fnv(key, &scene->hdr, sizeof(scene->hdr));
+  key = fnv(key, &ws, sizeof(void*));
+  key = fnv(key, &plan.total, sizeof(plan.total));
+  if (!(ctx->graph_exec && ctx->graph_key == key)) {
+    if (ctx->graph_exec) {
+      (void)hipGraphExecDestroy(ctx->graph_exec);
+      ctx->graph_exec = nullptr;
+    }
+    if (ctx->graph) {
+      (void)hipGraphDestroy(ctx->graph);
+      ctx->graph = nullptr;
+    }
+    const uint64_t t0 = ctx->acc.trace_launches, s0 = ctx->acc.shade_launches, f0 = ctx->acc.wavefronts;
+    // The caller's stream may be the null stream, which cannot be captured: record the sequence
+    // on the context's own stream (nothing runs there), then launch the graph on the caller's.
+    if (!ctx->capture_stream) HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
+    hipStream_t user = ctx->stream;
+    ctx->stream = ctx->capture_stream;
+    hipError_t eb = hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal);
+    if (eb != hipSuccess) {
+      ctx->stream = user;
+      return fail(ctx, SDD_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(eb));
+    }
+    int rc = enqueue_frame(ctx, scene, views, p, plan, w, total, false);
+    hipGraph_t g = nullptr;
+    hipError_t ec = hipStreamEndCapture(ctx->stream, &g);
+    ctx->stream = user;
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (ec != hipSuccess) return fail(ctx, SDD_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(ec));
+    ctx->graph = g;
+    HIP_TRY(ctx, hipGraphInstantiate(&ctx->graph_exec, g, nullptr, nullptr, 0));
+    ctx->graph_key = key;
+    ctx->graph_trace_launches = ctx->acc.trace_launches - t0;
+    ctx->graph_shade_launches = ctx->acc.shade_launches - s0;
+    ctx->graph_wavefronts = ctx->acc.wavefronts - f0;
+    // the capture only recorded the launches; count them when the graph actually runs
+    ctx->acc.trace_launches = t0;
+    ctx->acc.shade_launches = s0;
+    ctx->acc.wavefronts = f0;
+  }
+  if (p->timing) record(ctx, ctx->ev_graph, ctx->ev_used_graph, true);
+  HIP_TRY(ctx, hipGraphLaunch(ctx->graph_exec, ctx->stream));
+  if (p->timing) record(ctx, ctx->ev_graph, ctx->ev_used_graph, false);
+  ctx->acc.trace_launches += ctx->graph_trace_launches;
+  ctx->acc.shade_launches += ctx->graph_shade_launches;
+  ctx->acc.wavefronts += ctx->graph_wavefronts;
+  ctx->acc.graph_launches++;
   return SDD_OK;
 }
 
@@ -370,6 +456,10 @@ void sdd_destroy(sdd_ctx* c) {
   if (!c) return;
   for (auto& p : c->ev_trace) { (void)hipEventDestroy(p.first); (void)hipEventDestroy(p.second); }
   for (auto& p : c->ev_shade) { (void)hipEventDestroy(p.first); (void)hipEventDestroy(p.second); }
+  for (auto& p : c->ev_graph) { (void)hipEventDestroy(p.first); (void)hipEventDestroy(p.second); }
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
   delete c;
 }
 
@@ -537,7 +627,11 @@ int sdd_finish(sdd_ctx* c) {
     float ms = 0;
     if (hipEventElapsedTime(&ms, c->ev_shade[i].first, c->ev_shade[i].second) == hipSuccess) c->acc.shade_ms += ms;
   }
-  c->ev_used_trace = c->ev_used_shade = 0;
+  for (size_t i = 0; i < c->ev_used_graph; ++i) {
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, c->ev_graph[i].first, c->ev_graph[i].second) == hipSuccess) c->acc.graph_ms += ms;
+  }
+  c->ev_used_trace = c->ev_used_shade = c->ev_used_graph = 0;
   return status;
 }
 

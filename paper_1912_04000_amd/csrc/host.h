@@ -25,6 +25,7 @@ std::string build_scene(const sdd_scene_desc& d, sdd_scene* out);
 DevScene device_view(const sdd_scene* s);
 
 void set_thread_error(const std::string& msg);
+hipStream_t ctx_stream(const sdd_ctx* ctx);
 const char* thread_error();
 
 }  // namespace sdd

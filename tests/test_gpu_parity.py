@@ -315,3 +315,50 @@ def test_environment_radiance_parity(ctx, depth):
     ref = oracle.render(sc, cam, spp=2, max_depth=depth, seed=4)
     ok = _pixel_parity(img, ref.image, ref.tied, f"env D={depth}")
     assert ok.mean() > 0.9
+
+
+def _batch_views(sd):
+    return [sd.camera((3.0, 8.0, 1.7), (12.0, 1.0, 1.5), (0, 0, 1), 60, 40, 30),
+            sd.camera((15.0, 2.0, 3.0), (5.0, 8.0, 1.0), (0, 0, 1), 75, 17, 23),
+            sd.camera((10.0, 5.0, 6.0), (10.0, 5.0, 0.0), (0, 1, 0), 90, 32, 32)]
+
+
+def test_graph_replays_match_eager(ctx):
+    """The captured launch sequence, replayed several times with eager renders and syncs in
+    between, reproduces the eager batch every time (no memset nodes in the graph)."""
+    import paper_1912_04000_amd as sd
+    sc = scenegen.nave_scene(8)
+    S = _scene(ctx, sc, (2, 2, 2))
+    cams = _batch_views(sd)
+    spp = [3, 2, 4]
+    eager = [o.cpu().numpy() for o in ctx.render_batch(S, cams, spp, sd.render_params(max_depth=5, seed=9,
+                                                                                      wave_paths=1500))]
+    outs = None
+    for rep in range(3):
+        outs = ctx.render_batch(S, cams, spp, sd.render_params(max_depth=5, seed=9, wave_paths=1500, use_graph=1),
+                                outs=outs)
+        got = [o.cpu().numpy() for o in outs]
+        for v in range(3):
+            err = np.abs(got[v] - eager[v]).max() / max(eager[v].max(), 1e-12)
+            say(f"replay {rep} view {v}: max rel diff {err:.2e}")
+            assert err < 1e-5
+        # eager work between replays
+        ctx.render(S, cams[0], sd.render_params(spp=1, max_depth=3, seed=rep))
+    assert ctx.stats()["graph_launches"] >= 3
+
+
+def test_autotune_picks_a_measured_candidate_and_caches(ctx, tmp_path):
+    import paper_1912_04000_amd as sd
+    sc = scenegen.nave_scene(8)
+    cams = _batch_views(sd)
+    cache = str(tmp_path / "tune_cache.json")
+    base = sd.render_params(max_depth=4, seed=1)
+    r1 = ctx.autotune(sc, cams, base, waves=[1024, 4096], grids=[(1, 1, 1), (2, 2, 2), (4, 2, 2)], rounds=(1, 2),
+                      calib_spp=1, reps=1, cache_path=cache)
+    say(f"autotune: {r1['best']} from {len(r1['tried'])} candidates")
+    assert not r1["from_cache"] and len(r1["tried"]) == 12
+    assert r1["best"]["samples_per_s"] == max(t["samples_per_s"] for t in r1["tried"])
+    r2 = ctx.autotune(sc, cams, base, waves=[1024, 4096], grids=[(1, 1, 1), (2, 2, 2), (4, 2, 2)], rounds=(1, 2),
+                      calib_spp=1, reps=1, cache_path=cache)
+    assert r2["from_cache"] and r2["best"]["grid"] == r1["best"]["grid"]
+    assert r2["best"]["wave_paths"] == r1["best"]["wave_paths"]
