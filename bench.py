@@ -8,6 +8,9 @@ samples, each carrying all 40 bins). Prints one JSON line.
 
   python bench.py [--steps K] [--warmup W] [--workload church|nave] [--no-cpu-baseline]
   python bench.py --copy-calibration 1.0   # a plain 1 GiB device copy (for PMC byte scaling)
+  python bench.py --pmc-summary F.csv W.csv CF.csv CW.csv   # HBM bytes of k_trace from rocprofv3 --pmc
+      (FETCH_SIZE and WRITE_SIZE runs of this bench, then of --copy-calibration; writes
+       profiles/k_trace_church1M_pmc.json, which later bench lines report as roofline.traffic)
 """
 from __future__ import annotations
 
@@ -46,6 +49,9 @@ def parse():
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="GiB: only run a plain device-to-device copy of that size (PMC calibration)")
+    ap.add_argument("--pmc-summary", nargs=4, default=None, metavar="CSV",
+                    help="counter_collection.csv of FETCH_SIZE, WRITE_SIZE (bench), FETCH_SIZE, WRITE_SIZE (copy)")
+    ap.add_argument("--pmc-command", default="", help="the rocprofv3 command lines, recorded in the summary")
     return ap.parse_args()
 
 
@@ -130,6 +136,53 @@ def copy_calibration(gib):
     print(json.dumps({"copy_calibration_bytes_read": n * 4, "copy_calibration_bytes_written": n * 4, "launches": 3}))
 
 
+def _pmc_per_kernel(path, counter):
+    """Mean counter value (KiB per dispatch) and dispatch count per kernel name."""
+    import csv
+    acc = {}
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] != counter:
+            continue
+        k = r["Kernel_Name"].split("(")[0].strip()
+        v = acc.setdefault(k, [0.0, 0])
+        v[0] += float(r["Counter_Value"])
+        v[1] += 1
+    return {k: (v[0] / v[1], v[1]) for k, v in acc.items()}
+
+
+def pmc_summary(args):
+    """HBM bytes per k_trace launch: FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each scaled by
+    what the same counter reads for a plain device copy of known size."""
+    f_csv, w_csv, cf_csv, cw_csv = args.pmc_summary
+    copy_bytes = 3 * (1 << 30)  # three 1 GiB copies (bench.py --copy-calibration 1)
+    cf = _pmc_per_kernel(cf_csv, "FETCH_SIZE")["__amd_rocclr_copyBuffer"]
+    cw = _pmc_per_kernel(cw_csv, "WRITE_SIZE")["__amd_rocclr_copyBuffer"]
+    f_scale = copy_bytes / (cf[0] * cf[1] * 1024)
+    w_scale = copy_bytes / (cw[0] * cw[1] * 1024)
+    fk = _pmc_per_kernel(f_csv, "FETCH_SIZE")
+    wk = _pmc_per_kernel(w_csv, "WRITE_SIZE")
+    kernels = {}
+    for k in sorted(set(fk) & set(wk)):
+        if not k.startswith("sdd::"):
+            continue
+        rd = fk[k][0] * 1024 * f_scale
+        wr = wk[k][0] * 1024 * w_scale
+        kernels[k] = {"dispatches": fk[k][1], "fetch_kib_raw": fk[k][0], "write_kib_raw": wk[k][0],
+                      "read_bytes": rd, "write_bytes": wr, "hbm_bytes_per_launch": rd + wr}
+    src = open(os.path.join(ROOT, "paper_1912_04000_amd", "csrc", "kernels.hip"), "rb").read()
+    out = {"kernel": "sdd::k_trace", "kernel_source_sha256": hashlib.sha256(src).hexdigest(),
+           "hbm_bytes_per_launch": kernels["sdd::k_trace"]["hbm_bytes_per_launch"],
+           "fetch_scale": f_scale, "write_scale": w_scale,
+           "calibration": "FETCH_SIZE / WRITE_SIZE of three 1 GiB torch device copies "
+                          "(__amd_rocclr_copyBuffer) against their known 3 GiB read and written",
+           "command": args.pmc_command, "kernels": kernels}
+    p = os.path.join(ROOT, "profiles", "k_trace_church1M_pmc.json")
+    os.makedirs(os.path.dirname(p), exist_ok=True)
+    with open(p, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps({k: round(v["hbm_bytes_per_launch"] / 1e6, 3) for k, v in kernels.items()}))
+
+
 def bench_batch(args):
     """32 seeded views of the church with uneven resolutions (256x256 .. 1024x768) and spp (4..64),
     rendered together in one graph launch per step, with the grid, wavefront size and queue rounds
@@ -191,6 +244,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration > 0:
         copy_calibration(args.copy_calibration)
+        return
+    if args.pmc_summary:
+        pmc_summary(args)
         return
     if args.workload == "batch":
         bench_batch(args)

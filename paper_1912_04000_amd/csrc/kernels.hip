@@ -10,62 +10,9 @@
 //              paper's sub-domains, section 5) or, in the final round, walk on in place.
 //   shade      per-bin SoA spectral shading: complex Fresnel (eq. 1), thin-slab Beer-Lambert
 //              glass, next-event estimation toward the directional sun (eq. 3).
-#include "internal.h"
+#include "device_common.h"
 
 namespace sdd {
-
-// ==========================================================================================
-// small helpers
-// ==========================================================================================
-struct F3 { float x, y, z; };
-__device__ __forceinline__ F3 f3(float x, float y, float z) { return {x, y, z}; }
-__device__ __forceinline__ F3 operator+(F3 a, F3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
-__device__ __forceinline__ F3 operator-(F3 a, F3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
-__device__ __forceinline__ F3 operator*(F3 a, float s) { return {a.x * s, a.y * s, a.z * s}; }
-__device__ __forceinline__ float dot3(F3 a, F3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
-__device__ __forceinline__ F3 cross3(F3 a, F3 b) {
-  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
-}
-__device__ __forceinline__ F3 norm3(F3 a) { return a * (1.0f / sqrtf(dot3(a, a))); }
-__device__ __forceinline__ float maxabs3(F3 a) { return fmaxf(fabsf(a.x), fmaxf(fabsf(a.y), fabsf(a.z))); }
-__device__ __forceinline__ float comp(F3 a, int k) { return k == 0 ? a.x : (k == 1 ? a.y : a.z); }
-
-// Geometric normal and the dot products whose sign selects a branch (face side, sun side),
-// evaluated without FMA contraction: an exactly cancelling sum (a vertical facet's z, for
-// example) then stays exactly zero, as in exact arithmetic, instead of keeping the rounding
-// error of one product, which would flip the sign-dependent choices downstream.
-__device__ __forceinline__ F3 geo_normal(F3 v0, F3 v1, F3 v2) {
-#pragma clang fp contract(off)
-  const F3 e1 = v1 - v0, e2 = v2 - v0;
-  const F3 c = {e1.y * e2.z - e1.z * e2.y, e1.z * e2.x - e1.x * e2.z, e1.x * e2.y - e1.y * e2.x};
-  const float l2 = c.x * c.x + c.y * c.y + c.z * c.z;
-  return c * (1.0f / sqrtf(l2));
-}
-__device__ __forceinline__ float dot_exact_sign(F3 a, F3 b) {
-#pragma clang fp contract(off)
-  return a.x * b.x + a.y * b.y + a.z * b.z;
-}
-
-// Philox4x32-10 (Salmon et al., SC'11).
-__device__ __forceinline__ uint4 philox(uint4 c, uint32_t k0, uint32_t k1) {
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    if (r) {
-      k0 += 0x9E3779B9u;
-      k1 += 0xBB67AE85u;
-    }
-    const uint32_t hi0 = __umulhi(0xD2511F53u, c.x), lo0 = 0xD2511F53u * c.x;
-    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z), lo1 = 0xCD9E8D57u * c.z;
-    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
-  }
-  return c;
-}
-__device__ __forceinline__ float unif24(uint32_t x) { return (float)(x >> 8) * 0x1p-24f; }
-
-__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
-__device__ __forceinline__ uint32_t count_below(uint64_t m) {
-  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-}
 
 // Wave-level append of (src, cell) entries: one atomic per wave on the list counter and one
 // per distinct destination cell of the wave (ballot + mbcnt prefix); every lane of the wave
@@ -97,13 +44,6 @@ __device__ void wave_append(bool valid, uint32_t src, uint32_t cell, uint32_t* l
     ldst[pos] = cell;
     lrank[pos] = rank;
   }
-}
-
-// Wave-level sum, then one 64-bit atomic per wave.
-__device__ __forceinline__ void wave_add(unsigned long long* ctr, uint32_t x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-  if (lane_id() == 0 && x) atomicAdd(ctr, (unsigned long long)x);
 }
 
 // ==========================================================================================
@@ -834,33 +774,6 @@ __global__ __launch_bounds__(kWG) void k_escape(DevScene S, DevWS w, int depth) 
       l[q] = b;
     }
   }
-}
-
-// Geometry of the hit of slot s: vertex position, face-forward normal, geometric normal.
-struct Vertex {
-  F3 p, n, ng, d;
-  float dn, cos_o, eps;
-  uint32_t id;
-  int m;
-};
-
-__device__ __forceinline__ Vertex load_vertex(const DevScene& S, const DevWS& w, uint32_t s) {
-  Vertex V;
-  const float4 h = w.hit[s];
-  V.id = __float_as_uint(h.y);
-  const float4 rdir = w.rays[2 * s + 1];
-  V.d = f3(rdir.x, rdir.y, rdir.z);
-  const float4 A = S.gtris[(size_t)V.id * 3 + 0], Bv = S.gtris[(size_t)V.id * 3 + 1], C = S.gtris[(size_t)V.id * 3 + 2];
-  const F3 v0 = f3(A.x, A.y, A.z), v1 = f3(Bv.x, Bv.y, Bv.z), v2 = f3(C.x, C.y, C.z);
-  V.m = (int)__float_as_uint(Bv.w);
-  V.ng = geo_normal(v0, v1, v2);
-  V.dn = dot_exact_sign(V.d, V.ng);
-  V.n = V.dn > 0.0f ? V.ng * -1.0f : V.ng;
-  V.cos_o = fabsf(V.dn);
-  const float bu = h.z, bv = h.w;
-  V.p = v0 * (1.0f - bu - bv) + v1 * bu + v2 * bv;
-  V.eps = 1e-5f * (1.0f + maxabs3(V.p));
-  return V;
 }
 
 // Opaque vertex: direct term toward the sun through a shadow ray (eq. 3), then the
