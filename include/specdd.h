@@ -219,6 +219,129 @@ int sdd_autotune(sdd_ctx* ctx, const sdd_scene_desc* desc, const sdd_camera* vie
                  void* workspace, size_t ws_bytes, float* const* images, const char* cache_path,
                  sdd_tune_result* out);
 
+/* ------------------------------------------------------------------------------------------
+ * Learned spectral radiance cache
+ *
+ * The paper computes the indirect part of global illumination from photon maps (section 4). In
+ * the cached mode of this library that role is taken by a small network trained online on the
+ * renderer's own paths: a camera path stops at its third surface vertex x (after two bounces)
+ * and adds beta_j L(x, w, lambda_j, material) for every bin j, where L is the network's
+ * estimate of the radiance leaving x toward the previous vertex. The plain full-depth path is
+ * the fallback and the reference.
+ *
+ * Network: input 64 = [multiresolution hash grid of the position (L_p levels x 2 features, 3D,
+ * Mueller et al. 2022) | hash grid of the octahedral map of w (L_d levels x 2, 2D) | material
+ * embedding (8) | one-blob encoding of t = (lambda - lambda_min) / (lambda_max - lambda_min)
+ * (8 Gaussians of width 1/8) | zero padding], four 64-wide ReLU layers without biases, one
+ * output. Level l has resolution N_l = floor(N_min b^l), b = exp((ln N_max - ln N_min)/(L - 1));
+ * its vertices are indexed densely when (N_l + 1)^dim <= T, else by
+ * (x * 1 xor y * 2654435761 xor z * 805459861) mod T (32-bit unsigned). Matrix products run in
+ * bf16 with FP32 accumulation (grids, layer inputs and weights rounded to bf16 to nearest even);
+ * FP32 masters are trained with Adam (Kingma & Ba 2015, bias-corrected) on the relative L2 loss
+ * mean((y - t)^2 / (y^2 + 0.01)) with the denominator held constant.
+ *
+ * Flat parameter layout (FP32, the unit of sdd_cache_get/set_params and of the gradients):
+ *   pos grid [L_p][T_p][2] | dir grid [L_d][T_d][2] | material [n_mat][8] |
+ *   W0 [64][n_in] | W1 [64][64] | W2 [64][64] | W3 [64][64] | w4 [64],
+ *   n_in = 2 (L_p + L_d) + 16; W[out][in] acts as h_out = relu(W h_in).
+ * ------------------------------------------------------------------------------------------ */
+typedef struct sdd_cache sdd_cache;
+
+typedef struct {
+  int32_t levels_pos;          /* L_p, 1..16                                                  */
+  int32_t log2_table_pos;      /* T_p = 2^t entries per position level, 4..24                 */
+  float nmin_pos, nmax_pos;    /* coarsest / finest position resolution, 1 <= nmin <= nmax <= 2^20 */
+  int32_t levels_dir;          /* L_d, 1..16, with 2 (L_p + L_d) + 16 <= 64                    */
+  int32_t log2_table_dir;      /* T_d, 2..24                                                  */
+  float nmin_dir, nmax_dir;
+  int32_t n_mat;               /* materials with an embedding row, 1..65535 (>= scene n_mat)  */
+  int32_t max_bins;            /* most wavelength bins of a query or a training record, 1..128 */
+  int32_t max_records;         /* training records held at once (training paths per batch)   */
+  int32_t max_step;            /* records per Adam step, 32 .. max_records                    */
+  float lr, beta1, beta2, eps; /* Adam: lr > 0, 0 <= beta < 1, eps > 0                         */
+  float box_lo[3], box_hi[3];  /* the position grid spans this box (hi > lo on every axis)    */
+} sdd_cache_config;
+
+typedef struct {
+  int64_t n_param;             /* FP32 parameters in the flat layout                          */
+  size_t device_bytes;         /* bytes of the cache's device buffer                          */
+  int32_t n_in;                /* network inputs before padding to 64                         */
+  int32_t npos[16], ndir[16];  /* level resolutions N_l                                       */
+  uint32_t dense_pos, dense_dir; /* bit l set: level l is indexed densely                     */
+  int64_t adam_steps;          /* Adam steps taken since init / set_params                   */
+  int64_t train_paths_done;    /* training paths traced by sdd_render_cached so far           */
+} sdd_cache_info;
+
+/* Size of the flat parameter vector and of the device buffer of a configuration. */
+int sdd_cache_param_count(const sdd_cache_config* cfg, int64_t* n);
+int sdd_cache_bytes(const sdd_cache_config* cfg, size_t* bytes);
+
+/* Bind a cache to caller device memory dev_buf (>= sdd_cache_bytes, 256-byte aligned); it
+ * must stay valid while the cache is used. The parameters are undefined until sdd_cache_init
+ * or sdd_cache_set_params. Errors: SDD_ERR_INVALID_ARG for a configuration out of range,
+ * SDD_ERR_WORKSPACE for a small buffer. */
+int sdd_cache_create(sdd_ctx* ctx, const sdd_cache_config* cfg, void* dev_buf, size_t bytes, sdd_cache** out);
+void sdd_cache_destroy(sdd_cache* cache);
+int sdd_cache_get_info(sdd_ctx* ctx, sdd_cache* cache, sdd_cache_info* out);   /* waits */
+
+/* Random initialisation from Philox (grids U(-1e-4, 1e-4), material embedding U(-1, 1),
+ * weights Glorot-uniform); clears the Adam state. */
+int sdd_cache_init(sdd_ctx* ctx, sdd_cache* cache, uint64_t seed);
+/* Copy FP32 parameters (flat layout, n = sdd_cache_param_count) from HOST memory; clears the
+ * Adam state. get_params / get_grads copy to HOST memory and wait for the stream. */
+int sdd_cache_set_params(sdd_ctx* ctx, sdd_cache* cache, const float* host, int64_t n);
+int sdd_cache_get_params(sdd_ctx* ctx, sdd_cache* cache, float* host, int64_t n);
+int sdd_cache_get_grads(sdd_ctx* ctx, sdd_cache* cache, float* host, int64_t n);
+
+/* Network output y (before the clamp at zero that the render applies) for n explicit vertices:
+ * device arrays x [n][3] (position), wo [n][3] (unit direction toward the previous vertex),
+ * mat [n] int32 (< n_mat); out [n][n_bins] FP32, bin j at wavelength parameter
+ * t_j = (j + 1/2) / n_bins. n_bins <= max_bins. */
+int sdd_cache_eval(sdd_ctx* ctx, sdd_cache* cache, const float* x, const float* wo, const int32_t* mat, int64_t n,
+                   int32_t n_bins, float* out);
+
+/* Gradients of the mean relative L2 loss over the n x n_bins rows of explicit records
+ * (device arrays as in sdd_cache_eval, target [n][n_bins]), n <= max_step: the gradient buffer
+ * is cleared first; read it with sdd_cache_get_grads. sdd_cache_step then applies one Adam step
+ * with it (and clears it). */
+int sdd_cache_backward(sdd_ctx* ctx, sdd_cache* cache, const float* x, const float* wo, const int32_t* mat,
+                       const float* target, int64_t n, int32_t n_bins);
+int sdd_cache_step(sdd_ctx* ctx, sdd_cache* cache);
+/* Train on n <= max_records explicit records: ceil(n / max_step) Adam steps, step s on records
+ * [s max_step, (s + 1) max_step). */
+int sdd_cache_train(sdd_ctx* ctx, sdd_cache* cache, const float* x, const float* wo, const int32_t* mat,
+                    const float* target, int64_t n, int32_t n_bins);
+/* Mean loss over the rows of the backward passes since the previous call (waits; NaN if none). */
+int sdd_cache_loss(sdd_ctx* ctx, sdd_cache* cache, double* mean_loss);
+
+/* Online training inside sdd_render_cached. After every `every`-th wavefront, train_paths
+ * training paths are traced at full depth: path g (counted across calls by the cache) starts
+ * at a pixel of the view drawn from Philox counter (g, g >> 32, 2 << 24, view), draws its
+ * decisions with purpose 1 (bit 24 of the counter's depth word), restarts its throughput at one
+ * at its third vertex and records that vertex; the radiance it then gathers is the record's
+ * target for every bin. The records (in path order, at most steps x step_records) feed `steps`
+ * Adam steps of step_records records each. train_paths = 0 leaves the cache unchanged. */
+typedef struct {
+  int32_t train_paths;         /* 0 .. min(max_records, wave_paths)                            */
+  int32_t step_records;        /* 32 .. max_step                                               */
+  int32_t steps;               /* >= 1                                                         */
+  int32_t every;               /* >= 1                                                         */
+} sdd_train_params;
+
+/* Render in cached mode (params->mode = SDD_MODE_CACHED, max_depth >= 3, use_graph = 0):
+ * vertices 1 and 2 of every path are shaded as in sdd_render (the direct sun term included);
+ * the continuation from vertex 2 that hits vertex 3 adds beta_j max(y_j, 0) from the cache for
+ * every bin and stops; escapes add the environment as before. The scene's bins must not exceed
+ * max_bins and its materials n_mat; the position box is the cache's. train may be NULL. */
+int sdd_render_cached(sdd_ctx* ctx, const sdd_scene* scene, sdd_cache* cache, const sdd_camera* camera,
+                      const sdd_render_params* params, const sdd_train_params* train, void* workspace,
+                      size_t workspace_bytes, float* image_dev);
+
+/* Training records of the last batch, slot by slot (HOST outputs, waits): rec_x [n][4] =
+ * (position, material id as uint32 bits), rec_w [n][4] = (direction toward the previous vertex,
+ * 1 if the slot's path reached its third vertex else 0), target [n][max_bins]. */
+int sdd_cache_get_records(sdd_ctx* ctx, sdd_cache* cache, int64_t n, float* rec_x, float* rec_w, float* target);
+
 /* Wait for the context stream, then report device-side errors (capacity overflow, non-finite
  * values) of the work enqueued since the previous sdd_finish. */
 int sdd_finish(sdd_ctx* ctx);
@@ -232,6 +355,9 @@ typedef struct {
   double shade_ms;             /* HIP-event time of the shading launches (timing = 1)        */
   uint64_t graph_launches;     /* graph-mode renders replayed                                 */
   double graph_ms;             /* HIP-event time of the graph launches (timing = 1)          */
+  uint64_t cache_queries;      /* path vertices that took their radiance from the cache       */
+  uint64_t train_batches;      /* training batches (training paths + Adam steps) run          */
+  double cache_ms;             /* HIP-event time of cache queries and training (timing = 1)  */
 } sdd_stats;
 
 /* Counters accumulated since the previous sdd_reset_stats (valid after sdd_finish). */

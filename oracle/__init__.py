@@ -54,7 +54,8 @@ class _Params(C.Structure):
     _fields_ = [("spp", C.c_int32), ("max_depth", C.c_int32), ("seed", C.c_uint64), ("view", C.c_uint32),
                 ("threads", C.c_int32), ("force_bvh", C.c_int32), ("tie_t_rel", C.c_double),
                 ("tie_edge_abs", C.c_double), ("tie_edge_rel_t", C.c_double), ("tie_lobe", C.c_double),
-                ("tie_cos_sun", C.c_double), ("cached", C.c_int32), ("first_sample", C.c_int32)]
+                ("tie_cos_sun", C.c_double), ("cached", C.c_int32), ("first_sample", C.c_int32),
+                ("purpose", C.c_uint32), ("record_depth", C.c_int32), ("sample_per_entry", C.c_int32)]
 
 
 class _Queries(C.Structure):
@@ -181,16 +182,20 @@ class RenderResult:
 
 
 def render(scene, camera, spp=1, max_depth=4, seed=1, view=0, pixels=None, threads=None,
-           tie: TieParams = TieParams(), force_bvh=-1, cached=False, first_sample=0) -> RenderResult:
+           tie: TieParams = TieParams(), force_bvh=-1, cached=False, first_sample=0, purpose=0,
+           sample_per_entry=False) -> RenderResult:
     """Reference spectral image (mean of spp path samples per pixel), FP64 accumulation.
     With cached=True the paths stop at the vertex after bounce 2 and the query there
-    (position, direction toward the previous vertex, material, throughput) is returned."""
+    (position, direction toward the previous vertex, material, throughput) is returned.
+    purpose is added to the depth word of every random-number counter; with sample_per_entry
+    entry i of ``pixels`` is one path (spp = 1) with sample index first_sample + i."""
     s, keep = _scene_struct(scene)
     cam = _Camera((C.c_double * 3)(*camera.eye), (C.c_double * 3)(*camera.target), (C.c_double * 3)(*camera.up),
                   float(camera.vfov_deg), int(camera.width), int(camera.height))
     th = threads or min(8, os.cpu_count() or 1)
     prm = _Params(int(spp), int(max_depth), int(seed), int(view), int(th), int(force_bvh), tie.t_rel, tie.edge_abs,
-                  tie.edge_rel_t, tie.lobe, tie.cos_sun, 1 if cached else 0, int(first_sample))
+                  tie.edge_rel_t, tie.lobe, tie.cos_sun, 1 if cached else 0, int(first_sample), int(purpose), 0,
+                  1 if sample_per_entry else 0)
     B = scene.n_bins
     if pixels is None:
         npx = camera.width * camera.height
@@ -216,3 +221,30 @@ def render(scene, camera, spp=1, max_depth=4, seed=1, view=0, pixels=None, threa
         tied = tied.reshape(camera.height, camera.width)
     stats = dict(paths=int(st[0]), vertices=int(st[1]), shadow_rays=int(st[2]), tied_paths=int(st[3]))
     return RenderResult(img, tied, stats, q)
+
+
+def training_records(scene, camera, pixels, first_path, max_depth=8, seed=1, view=0, record_depth=3, threads=None,
+                     tie: TieParams = TieParams()):
+    """Training paths of the radiance cache: entry i of ``pixels`` is path g = first_path + i,
+    traced with random-number purpose 1 (bit 24 of the depth word of the counter
+    (pixel, g, depth | purpose, view)) to full depth. At vertex ``record_depth`` the path records
+    (position, direction toward the previous vertex, material) and restarts its throughput at
+    one and its gathered radiance at zero; the radiance gathered from there on is the target.
+    Returns x [n][3], wo [n][3], mat [n], valid [n] (vertex reached), target [n][B], tied [n]."""
+    s, keep = _scene_struct(scene)
+    cam = _Camera((C.c_double * 3)(*camera.eye), (C.c_double * 3)(*camera.target), (C.c_double * 3)(*camera.up),
+                  float(camera.vfov_deg), int(camera.width), int(camera.height))
+    th = threads or min(8, os.cpu_count() or 1)
+    prm = _Params(1, int(max_depth), int(seed), int(view), int(th), -1, tie.t_rel, tie.edge_abs, tie.edge_rel_t,
+                  tie.lobe, tie.cos_sun, 0, int(first_path), 1 << 24, int(record_depth), 1)
+    B = scene.n_bins
+    px = np.ascontiguousarray(pixels, dtype=np.int64)
+    n = px.shape[0]
+    img = np.zeros((B, n))
+    tied = np.zeros(n, dtype=np.int32)
+    st = np.zeros(4, dtype=np.int64)
+    q = dict(x=np.zeros((n, 3)), wo=np.zeros((n, 3)), mat=np.full(n, -1, dtype=np.int32), beta=np.zeros((n, B)),
+             valid=np.zeros(n, dtype=np.uint8))
+    qs = _Queries(_p(q["x"]).value, _p(q["wo"]).value, _p(q["mat"]).value, _p(q["beta"]).value, _p(q["valid"]).value)
+    lib().orc_render(C.byref(s), C.byref(cam), C.byref(prm), _p(px), n, _p(img), _p(tied), _p(st), C.byref(qs))
+    return dict(x=q["x"], wo=q["wo"], mat=q["mat"], valid=q["valid"].astype(bool), target=img.T.copy(), tied=tied)

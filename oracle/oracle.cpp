@@ -365,6 +365,9 @@ typedef struct {
   double tie_t_rel, tie_edge_abs, tie_edge_rel_t, tie_lobe, tie_cos_sun;
   int32_t cached;            // 1: stop at vertex 3 and record the cache query instead
   int32_t first_sample;      // sample indices first_sample .. first_sample + spp - 1
+  uint32_t purpose;          // random-number purpose: added to the depth word (0 or 1 << 24)
+  int32_t record_depth;      // > 0: training paths; record that vertex and restart beta and L there
+  int32_t sample_per_entry;  // 1: entry i of the pixel list is one path with sample first_sample + i
 } orc_params;
 
 void orc_philox4x32_10(const uint32_t* ctr, const uint32_t* key, uint32_t* out) {
@@ -515,11 +518,11 @@ int orc_render(const orc_scene* sc, const orc_camera* cam, const orc_params* prm
     int px = (int)(pix % W), py = (int)(pix / W);
     std::fill(acc.begin(), acc.end(), 0.0);
     for (int si = 0; si < spp; ++si) {
-      const int s = prm->first_sample + si;
+      const int s = prm->sample_per_entry ? prm->first_sample + (int)i : prm->first_sample + si;
       bool tied = false;
       std::fill(L.begin(), L.end(), 0.0);
       std::fill(beta.begin(), beta.end(), 1.0);
-      U4 rn = philox4x32_10({{(uint32_t)pix, (uint32_t)s, 0u, prm->view}}, k0, k1);
+      U4 rn = philox4x32_10({{(uint32_t)pix, (uint32_t)s, prm->purpose, prm->view}}, k0, k1);
       double sx = (2.0 * (px + unif(rn.x[0])) / W - 1.0) * tf * W / H;
       double sy = (1.0 - 2.0 * (py + unif(rn.x[1])) / H) * tf;
       V3 o = eye, d = normalize(f + r * sx + up * sy);
@@ -541,6 +544,17 @@ int orc_render(const orc_scene* sc, const orc_camera* cam, const orc_params* prm
         V3 p = T.v0 * (1.0 - h.u - h.v) + T.v1 * h.u + T.v2 * h.v;
         double eps = 1e-5 * (1.0 + maxabs(p));
         int m = T.mat;
+        if (prm->record_depth == dep) {
+          // training path: this vertex is the record; what the path gathers from here on is the
+          // radiance leaving it toward the previous vertex
+          int64_t q = i * spp + si;
+          cq->x[3 * q] = p.x; cq->x[3 * q + 1] = p.y; cq->x[3 * q + 2] = p.z;
+          cq->wo[3 * q] = -d.x; cq->wo[3 * q + 1] = -d.y; cq->wo[3 * q + 2] = -d.z;
+          cq->mat[q] = m;
+          cq->valid[q] = 1;
+          std::fill(L.begin(), L.end(), 0.0);
+          std::fill(beta.begin(), beta.end(), 1.0);
+        }
         if (prm->cached && dep == 3) {
           int64_t q = i * spp + si;
           cq->x[3 * q] = p.x; cq->x[3 * q + 1] = p.y; cq->x[3 * q + 2] = p.z;
@@ -550,7 +564,7 @@ int orc_render(const orc_scene* sc, const orc_camera* cam, const orc_params* prm
           cq->valid[q] = 1;
           break;
         }
-        U4 rv = philox4x32_10({{(uint32_t)pix, (uint32_t)s, (uint32_t)dep, prm->view}}, k0, k1);
+        U4 rv = philox4x32_10({{(uint32_t)pix, (uint32_t)s, (uint32_t)dep | prm->purpose, prm->view}}, k0, k1);
         double u0 = unif(rv.x[0]), u1 = unif(rv.x[1]), u2 = unif(rv.x[2]);
         const float* nt = sc->n_tab + m * B;
         const float* kt = sc->k_tab + m * B;

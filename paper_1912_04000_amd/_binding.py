@@ -62,7 +62,8 @@ class Stats(C.Structure):
         "paths", "vertices", "ext_rays", "shadow_rays", "cell_visits", "migrations", "escapes", "glass_crossings",
         "trace_launches", "shade_launches", "wavefronts", "err_cross_overflow", "err_nonfinite", "err_stack",
         "node_visits", "tri_tests")] + [
-        ("trace_ms", C.c_double), ("shade_ms", C.c_double), ("graph_launches", C.c_uint64), ("graph_ms", C.c_double)]
+        ("trace_ms", C.c_double), ("shade_ms", C.c_double), ("graph_launches", C.c_uint64), ("graph_ms", C.c_double),
+        ("cache_queries", C.c_uint64), ("train_batches", C.c_uint64), ("cache_ms", C.c_double)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -85,6 +86,24 @@ class TunePoint(C.Structure):
 
 class TuneResult(C.Structure):
     _fields_ = [("best", TunePoint), ("from_cache", C.c_int32), ("n_tried", C.c_int32), ("tried", TunePoint * 128)]
+
+
+class CacheConfig(C.Structure):
+    _fields_ = [("levels_pos", C.c_int32), ("log2_table_pos", C.c_int32), ("nmin_pos", C.c_float),
+                ("nmax_pos", C.c_float), ("levels_dir", C.c_int32), ("log2_table_dir", C.c_int32),
+                ("nmin_dir", C.c_float), ("nmax_dir", C.c_float), ("n_mat", C.c_int32), ("max_bins", C.c_int32),
+                ("max_records", C.c_int32), ("max_step", C.c_int32), ("lr", C.c_float), ("beta1", C.c_float),
+                ("beta2", C.c_float), ("eps", C.c_float), ("box_lo", C.c_float * 3), ("box_hi", C.c_float * 3)]
+
+
+class CacheInfo(C.Structure):
+    _fields_ = [("n_param", C.c_int64), ("device_bytes", C.c_size_t), ("n_in", C.c_int32),
+                ("npos", C.c_int32 * 16), ("ndir", C.c_int32 * 16), ("dense_pos", C.c_uint32),
+                ("dense_dir", C.c_uint32), ("adam_steps", C.c_int64), ("train_paths_done", C.c_int64)]
+
+
+class TrainParams(C.Structure):
+    _fields_ = [("train_paths", C.c_int32), ("step_records", C.c_int32), ("steps", C.c_int32), ("every", C.c_int32)]
 
 
 # Every exported function: (name, restype, argtypes)
@@ -111,6 +130,22 @@ SIGNATURES = [
     ("sdd_reset_stats", _i32, [_vp]),
     ("sdd_last_error", C.c_char_p, [_vp]),
     ("sdd_autotune", _i32, [_vp, _vp, _vp, _i32, _vp, _vp, _vp, _sz, _vp, _sz, _vp, C.c_char_p, _vp]),
+    ("sdd_cache_param_count", _i32, [_vp, _vp]),
+    ("sdd_cache_bytes", _i32, [_vp, _vp]),
+    ("sdd_cache_create", _i32, [_vp, _vp, _vp, _sz, _vp]),
+    ("sdd_cache_destroy", None, [_vp]),
+    ("sdd_cache_get_info", _i32, [_vp, _vp, _vp]),
+    ("sdd_cache_init", _i32, [_vp, _vp, C.c_uint64]),
+    ("sdd_cache_set_params", _i32, [_vp, _vp, _vp, _i64]),
+    ("sdd_cache_get_params", _i32, [_vp, _vp, _vp, _i64]),
+    ("sdd_cache_get_grads", _i32, [_vp, _vp, _vp, _i64]),
+    ("sdd_cache_eval", _i32, [_vp, _vp, _vp, _vp, _vp, _i64, _i32, _vp]),
+    ("sdd_cache_backward", _i32, [_vp, _vp, _vp, _vp, _vp, _vp, _i64, _i32]),
+    ("sdd_cache_step", _i32, [_vp, _vp]),
+    ("sdd_cache_train", _i32, [_vp, _vp, _vp, _vp, _vp, _vp, _i64, _i32]),
+    ("sdd_cache_loss", _i32, [_vp, _vp, _vp]),
+    ("sdd_render_cached", _i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    ("sdd_cache_get_records", _i32, [_vp, _vp, _i64, _vp, _vp, _vp]),
 ]
 
 _lib = None
@@ -236,6 +271,25 @@ def camera(eye, target, up=(0.0, 0.0, 1.0), vfov_deg=60.0, width=64, height=64) 
     c.vfov_deg = float(vfov_deg)
     c.width, c.height = int(width), int(height)
     return c
+
+
+def cache_config(n_mat, box_lo, box_hi, levels_pos=12, log2_table_pos=19, nmin_pos=16.0, nmax_pos=2048.0,
+                 levels_dir=12, log2_table_dir=14, nmin_dir=4.0, nmax_dir=256.0, max_bins=40, max_records=1 << 17,
+                 max_step=1 << 14, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8) -> CacheConfig:
+    c = CacheConfig()
+    c.levels_pos, c.log2_table_pos, c.nmin_pos, c.nmax_pos = int(levels_pos), int(log2_table_pos), nmin_pos, nmax_pos
+    c.levels_dir, c.log2_table_dir, c.nmin_dir, c.nmax_dir = int(levels_dir), int(log2_table_dir), nmin_dir, nmax_dir
+    c.n_mat, c.max_bins, c.max_records, c.max_step = int(n_mat), int(max_bins), int(max_records), int(max_step)
+    c.lr, c.beta1, c.beta2, c.eps = lr, beta1, beta2, eps
+    c.box_lo[:] = [float(x) for x in box_lo]
+    c.box_hi[:] = [float(x) for x in box_hi]
+    return c
+
+
+def train_params(train_paths=0, step_records=1 << 14, steps=4, every=1) -> TrainParams:
+    t = TrainParams()
+    t.train_paths, t.step_records, t.steps, t.every = int(train_paths), int(step_records), int(steps), int(every)
+    return t
 
 
 def render_params(spp=1, max_depth=4, seed=1, mode=MODE_PLAIN, wave_paths=0, queue_rounds=0, view=0, timing=0,
@@ -398,6 +452,24 @@ class Context:
     def finish(self):
         self._err(lib().sdd_finish(self.handle))
 
+    # -- learned radiance cache ------------------------------------------------------------
+    def cache(self, cfg: CacheConfig, seed=None):
+        """Create a radiance cache in a torch device buffer; random init when seed is given."""
+        return Cache(self, cfg, seed)
+
+    def render_cached(self, scene: Scene, cache, cam: Camera, params: RenderParams, train: TrainParams = None,
+                      out=None, finish=True):
+        ws = self.workspace(self.workspace_bytes(scene, params))
+        img = out if out is not None else self.torch.empty((scene.n_bins, cam.height, cam.width),
+                                                           dtype=self.torch.float32, device=self.device)
+        self._err(lib().sdd_render_cached(self.handle, scene.handle, cache.handle, C.byref(cam), C.byref(params),
+                                          None if train is None else C.byref(train), C.c_void_p(ws.data_ptr()),
+                                          ws.numel(), C.c_void_p(img.data_ptr())))
+        if finish:
+            self.finish()
+        return img
+
+
     def stats(self) -> dict:
         s = Stats()
         self._err(lib().sdd_get_stats(self.handle, C.byref(s)))
@@ -409,4 +481,94 @@ class Context:
     def __del__(self):
         if getattr(self, "handle", None) and _lib is not None:
             _lib.sdd_destroy(self.handle)
+            self.handle = None
+
+
+def param_count(cfg: CacheConfig) -> int:
+    n = C.c_int64()
+    _check(lib().sdd_cache_param_count(C.byref(cfg), C.byref(n)))
+    return n.value
+
+
+class Cache:
+    """``sdd_cache`` bound to a torch device buffer."""
+
+    def __init__(self, ctx: Context, cfg: CacheConfig, seed=None):
+        torch = ctx.torch
+        self.ctx, self.cfg = ctx, cfg
+        b = C.c_size_t()
+        _check(lib().sdd_cache_bytes(C.byref(cfg), C.byref(b)))
+        self.buffer = torch.empty(b.value + 256, dtype=torch.uint8, device=ctx.device)
+        off = (-self.buffer.data_ptr()) % 256
+        h = C.c_void_p()
+        ctx._err(lib().sdd_cache_create(ctx.handle, C.byref(cfg), C.c_void_p(self.buffer.data_ptr() + off), b.value,
+                                        C.byref(h)))
+        self.handle = h
+        self.n_param = param_count(cfg)
+        if seed is not None:
+            self.init(seed)
+
+    def init(self, seed):
+        self.ctx._err(lib().sdd_cache_init(self.ctx.handle, self.handle, int(seed)))
+
+    def info(self) -> dict:
+        i = CacheInfo()
+        self.ctx._err(lib().sdd_cache_get_info(self.ctx.handle, self.handle, C.byref(i)))
+        return dict(n_param=i.n_param, device_bytes=i.device_bytes, n_in=i.n_in,
+                    npos=list(i.npos)[:self.cfg.levels_pos], ndir=list(i.ndir)[:self.cfg.levels_dir],
+                    dense_pos=i.dense_pos, dense_dir=i.dense_dir, adam_steps=i.adam_steps,
+                    train_paths_done=i.train_paths_done)
+
+    def set_params(self, flat):
+        a = np.ascontiguousarray(flat, dtype=np.float32)
+        self.ctx._err(lib().sdd_cache_set_params(self.ctx.handle, self.handle, _ptr(a), a.size))
+
+    def params(self) -> np.ndarray:
+        a = np.empty(self.n_param, dtype=np.float32)
+        self.ctx._err(lib().sdd_cache_get_params(self.ctx.handle, self.handle, _ptr(a), a.size))
+        return a
+
+    def grads(self) -> np.ndarray:
+        a = np.empty(self.n_param, dtype=np.float32)
+        self.ctx._err(lib().sdd_cache_get_grads(self.ctx.handle, self.handle, _ptr(a), a.size))
+        return a
+
+    def eval(self, x, wo, mat, n_bins):
+        """Network outputs [n][n_bins] for device tensors x, wo (float32 [n][3]) and mat (int32 [n])."""
+        out = self.ctx.torch.empty((x.shape[0], n_bins), dtype=self.ctx.torch.float32, device=self.ctx.device)
+        self.ctx._err(lib().sdd_cache_eval(self.ctx.handle, self.handle, C.c_void_p(x.data_ptr()),
+                                           C.c_void_p(wo.data_ptr()), C.c_void_p(mat.data_ptr()), x.shape[0],
+                                           int(n_bins), C.c_void_p(out.data_ptr())))
+        self.ctx.finish()
+        return out
+
+    def backward(self, x, wo, mat, target):
+        self.ctx._err(lib().sdd_cache_backward(self.ctx.handle, self.handle, C.c_void_p(x.data_ptr()),
+                                               C.c_void_p(wo.data_ptr()), C.c_void_p(mat.data_ptr()),
+                                               C.c_void_p(target.data_ptr()), x.shape[0], target.shape[1]))
+
+    def step(self):
+        self.ctx._err(lib().sdd_cache_step(self.ctx.handle, self.handle))
+
+    def train(self, x, wo, mat, target):
+        self.ctx._err(lib().sdd_cache_train(self.ctx.handle, self.handle, C.c_void_p(x.data_ptr()),
+                                            C.c_void_p(wo.data_ptr()), C.c_void_p(mat.data_ptr()),
+                                            C.c_void_p(target.data_ptr()), x.shape[0], target.shape[1]))
+
+    def loss(self) -> float:
+        d = C.c_double()
+        self.ctx._err(lib().sdd_cache_loss(self.ctx.handle, self.handle, C.byref(d)))
+        return d.value
+
+    def records(self, n):
+        """Training records of the last batch (slot order): rec_x [n][4], rec_w [n][4], target [n][max_bins]."""
+        rx = np.empty((n, 4), dtype=np.float32)
+        rw = np.empty((n, 4), dtype=np.float32)
+        t = np.empty((n, self.cfg.max_bins), dtype=np.float32)
+        self.ctx._err(lib().sdd_cache_get_records(self.ctx.handle, self.handle, int(n), _ptr(rx), _ptr(rw), _ptr(t)))
+        return rx, rw, t
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.sdd_cache_destroy(self.handle)
             self.handle = None

@@ -10,22 +10,7 @@
 
 using namespace sdd;
 
-struct sdd_ctx {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  std::string err;
-  Ctl* last_ctl = nullptr;     // control block of the last launched work (inside a workspace)
-  sdd_stats acc;               // accumulated statistics
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_trace, ev_shade, ev_graph;
-  size_t ev_used_trace = 0, ev_used_shade = 0, ev_used_graph = 0;
-  int cu_count = 256;
-  // captured launch sequence of the last graph-mode render and the key it was captured for
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t graph_exec = nullptr;
-  hipStream_t capture_stream = nullptr;   // own stream (default priority) used only to record graphs
-  uint64_t graph_key = 0;
-  uint64_t graph_trace_launches = 0, graph_shade_launches = 0, graph_wavefronts = 0;
-};
+
 
 namespace sdd {
 
@@ -262,45 +247,93 @@ uint64_t fnv(uint64_t h, const void* data, size_t n) {
 
 // Every launch of one render call, in stream order. Statistics are never zeroed here, so the
 // sequence can be captured once and replayed.
+// One population of paths (render items k0 .. k0 + n, or training paths) through the bounce
+// loop. A cached render stops its paths at vertex kCacheDepth and queries the cache there;
+// `finish` runs after the last bounce (accumulation into the images, or the gathering of
+// training targets).
+constexpr int kCacheDepth = 3;
+
+template <typename Finish>
+int run_paths(sdd_ctx* ctx, const sdd_scene* scene, const sdd_render_params* p, const Launch& L, const DevScene& S,
+              const DevWS& w, uint64_t k0, uint32_t n, int& gen, bool timing, const PathMode& pm,
+              const sdd_cache* cache, Finish finish) {
+  const int rounds = p->queue_rounds ? p->queue_rounds : kDefaultRounds;
+  const int D = p->max_depth;
+  const bool query = cache && pm.purpose == 0 && D >= kCacheDepth;
+  HIP_TRY(ctx, launch_fill_u32(ctx->stream, &w.ctl->cat_count[0][0], 2 * 8, 0u));
+  HIP_TRY(ctx, launch_raygen(L, S, w, k0, n, p->seed, gen, pm));
+  int rc = trace_phase(ctx, L, S, w, gen, rounds, 1, timing);
+  if (rc) return rc;
+  for (int d = 1; d <= D + 1; ++d) {
+    const bool last = d == D + 1 || (query && d == kCacheDepth);
+    if (timing) record(ctx, ctx->ev_shade, ctx->ev_used_shade, true);
+    HIP_TRY(ctx, launch_resolve(L, S, w, d));
+    if (scene->hdr.env_nonzero) HIP_TRY(ctx, launch_escape(L, S, w, d));
+    if (!last) {
+      HIP_TRY(ctx, launch_shade_opaque(L, S, w, d, D, p->seed, gen, pm));
+      if (d < D) HIP_TRY(ctx, launch_shade_glass(L, S, w, d, p->seed, gen, pm));
+    }
+    if (timing) record(ctx, ctx->ev_shade, ctx->ev_used_shade, false);
+    ctx->acc.shade_launches++;
+    if (last) {
+      if (query) {
+        if (timing) record(ctx, ctx->ev_cache, ctx->ev_used_cache, true);
+        HIP_TRY(ctx, launch_cache_query(ctx->stream, cache->dev, S, w, d & 1));
+        if (timing) record(ctx, ctx->ev_cache, ctx->ev_used_cache, false);
+      }
+      rc = finish();
+      if (rc) return rc;
+      break;
+    }
+    rc = trace_phase(ctx, L, S, w, gen, rounds, (d + 1) & 1, timing);
+    if (rc) return rc;
+  }
+  return SDD_OK;
+}
+
 int enqueue_frame(sdd_ctx* ctx, const sdd_scene* scene, const std::vector<ViewDesc>& views,
-                  const sdd_render_params* p, const Plan& plan, const DevWS& w, uint64_t total, bool timing) {
+                  const sdd_render_params* p, const Plan& plan, const DevWS& w, uint64_t total, bool timing,
+                  sdd_cache* cache = nullptr, const sdd_train_params* tp = nullptr) {
   const int B = scene->hdr.n_bins;
   const uint32_t W = plan.W;
   DevScene S = device_view(scene);
   Launch L{ctx->stream, plan.trace_blocks};
-  const int rounds = p->queue_rounds ? p->queue_rounds : kDefaultRounds;
   int rc = store_views(ctx, views, w);
   if (rc) return rc;
   for (auto& v : views) HIP_TRY(ctx, launch_fill_f32(ctx->stream, v.image, (size_t)B * v.width * v.height, 0.0f));
   HIP_TRY(ctx, launch_fill_u32(ctx->stream, (uint32_t*)w.ctl, offsetof(Ctl, st_paths) / 4, 0u));
   HIP_TRY(ctx, launch_fill_u32(ctx->stream, w.ccount, 2ull * scene->hdr.n_cells, 0u));
   int gen = 0;
-  const int D = p->max_depth;
-  uint32_t* cat_counts = &w.ctl->cat_count[0][0];
-  for (uint64_t k0 = 0; k0 < total; k0 += W) {
+  const PathMode render_mode{0u, 0, nullptr, nullptr};
+  uint64_t wavefront = 0;
+  for (uint64_t k0 = 0; k0 < total; k0 += W, ++wavefront) {
     const uint32_t n = (uint32_t)std::min<uint64_t>(W, total - k0);
-    HIP_TRY(ctx, launch_fill_u32(ctx->stream, cat_counts, 2 * 8, 0u));
-    HIP_TRY(ctx, launch_raygen(L, S, w, k0, n, p->seed, gen));
-    rc = trace_phase(ctx, L, S, w, gen, rounds, 1, timing);
-    if (rc) return rc;
-    for (int d = 1; d <= D + 1; ++d) {
+    rc = run_paths(ctx, scene, p, L, S, w, k0, n, gen, timing, render_mode, cache, [&]() -> int {
       if (timing) record(ctx, ctx->ev_shade, ctx->ev_used_shade, true);
-      HIP_TRY(ctx, launch_resolve(L, S, w, d));
-      if (scene->hdr.env_nonzero) HIP_TRY(ctx, launch_escape(L, S, w, d));
-      if (d <= D) {
-        HIP_TRY(ctx, launch_shade_opaque(L, S, w, d, D, p->seed, gen));
-        if (d < D) HIP_TRY(ctx, launch_shade_glass(L, S, w, d, p->seed, gen));
-      } else {
-        HIP_TRY(ctx, launch_accumulate(L, S, w, n));
-      }
+      HIP_TRY(ctx, launch_accumulate(L, S, w, n));
       if (timing) record(ctx, ctx->ev_shade, ctx->ev_used_shade, false);
-      ctx->acc.shade_launches++;
-      if (d <= D) {
-        rc = trace_phase(ctx, L, S, w, gen, rounds, (d + 1) & 1, timing);
-        if (rc) return rc;
-      }
-    }
+      return SDD_OK;
+    });
+    if (rc) return rc;
     ctx->acc.wavefronts++;
+    if (cache && tp && tp->train_paths > 0 && wavefront % (uint64_t)tp->every == 0) {
+      // training batch: full-depth paths recording their third vertex, then Adam steps
+      const uint32_t nt = (uint32_t)tp->train_paths;
+      const PathMode train_mode{1u << 24, kCacheDepth, cache->dev.rx, cache->dev.rw};
+      rc = run_paths(ctx, scene, p, L, S, w, cache->train_paths_done, nt, gen, timing, train_mode, cache,
+                     [&]() -> int {
+                       if (timing) record(ctx, ctx->ev_cache, ctx->ev_used_cache, true);
+                       HIP_TRY(ctx, launch_cache_gather(ctx->stream, cache->dev, w, nt, B));
+                       HIP_TRY(ctx, launch_cache_compact(ctx->stream, cache->dev, nt,
+                                                         (uint32_t)tp->steps * (uint32_t)tp->step_records));
+                       int r = cache_train_records(ctx, cache, B, tp->steps, tp->step_records);
+                       if (timing) record(ctx, ctx->ev_cache, ctx->ev_used_cache, false);
+                       return r;
+                     });
+      if (rc) return rc;
+      cache->train_paths_done += nt;
+      ctx->acc.train_batches++;
+    }
   }
   return SDD_OK;
 }
@@ -457,6 +490,7 @@ void sdd_destroy(sdd_ctx* c) {
   for (auto& p : c->ev_trace) { (void)hipEventDestroy(p.first); (void)hipEventDestroy(p.second); }
   for (auto& p : c->ev_shade) { (void)hipEventDestroy(p.first); (void)hipEventDestroy(p.second); }
   for (auto& p : c->ev_graph) { (void)hipEventDestroy(p.first); (void)hipEventDestroy(p.second); }
+  for (auto& p : c->ev_cache) { (void)hipEventDestroy(p.first); (void)hipEventDestroy(p.second); }
   if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
   if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
@@ -538,6 +572,57 @@ int sdd_render_batch(sdd_ctx* c, const sdd_scene* s, const sdd_camera* cams, con
   return render_views(c, s, views, p, ws, ws_bytes);
 }
 
+int sdd_render_cached(sdd_ctx* c, const sdd_scene* s, sdd_cache* k, const sdd_camera* cam,
+                      const sdd_render_params* p, const sdd_train_params* tp, void* ws, size_t ws_bytes,
+                      float* image) {
+  if (!c) return fail(nullptr, SDD_ERR_INVALID_ARG, "ctx is null");
+  int rc = scene_ready(c, s);
+  if (rc) return rc;
+  if (!cam || !image) return fail(c, SDD_ERR_INVALID_ARG, "null camera or image");
+  std::string e = check_params(p);
+  if (!e.empty()) return fail(c, SDD_ERR_INVALID_ARG, e);
+  if (p->mode != SDD_MODE_CACHED) return fail(c, SDD_ERR_INVALID_ARG, "sdd_render_cached needs mode SDD_MODE_CACHED");
+  if (p->use_graph) return fail(c, SDD_ERR_INVALID_ARG, "cached renders are not captured into graphs");
+  if (p->max_depth < kCacheDepth) return fail(c, SDD_ERR_INVALID_ARG, "cached mode needs max_depth >= 3");
+  if (!k) return fail(c, SDD_ERR_INVALID_ARG, "cache is null");
+  if (!k->ready) return fail(c, SDD_ERR_NOT_READY, "cache parameters are not set (sdd_cache_init / set_params)");
+  if (k->device != c->device) return fail(c, SDD_ERR_INVALID_ARG, "cache was created on another device");
+  if (s->hdr.n_bins > k->cfg.max_bins) return fail(c, SDD_ERR_INVALID_ARG, "scene has more bins than the cache");
+  if (s->hdr.n_mat > k->cfg.n_mat) return fail(c, SDD_ERR_INVALID_ARG, "scene has more materials than the cache");
+  std::vector<ViewDesc> views(1);
+  e = make_view(*cam, &views[0]);
+  if (!e.empty()) return fail(c, SDD_ERR_INVALID_ARG, e);
+  views[0].spp = p->spp;
+  views[0].inv_spp = 1.0f / (float)p->spp;
+  views[0].image = image;
+  views[0].view_id = p->view;
+  views[0].first_sample = (uint32_t)p->first_sample;
+  const uint64_t total = (uint64_t)cam->width * cam->height * (uint64_t)p->spp;
+  uint32_t W = p->wave_paths ? (uint32_t)p->wave_paths : (uint32_t)std::min<uint64_t>(kDefaultWave, total);
+  W = std::max<uint32_t>(W, 64);
+  if (tp && tp->train_paths != 0) {
+    if (tp->train_paths < 0 || (uint32_t)tp->train_paths > W || tp->train_paths > k->cfg.max_records)
+      return fail(c, SDD_ERR_INVALID_ARG, "train_paths must lie in 0..min(wave paths, max_records)");
+    if (tp->step_records < kCacheVerts || tp->step_records > k->cfg.max_step)
+      return fail(c, SDD_ERR_INVALID_ARG, "step_records must lie in 32..max_step");
+    if (tp->steps < 1 || tp->every < 1) return fail(c, SDD_ERR_INVALID_ARG, "steps and every must be >= 1");
+    if (p->max_depth <= kCacheDepth)
+      return fail(c, SDD_ERR_INVALID_ARG, "training paths need max_depth >= 4 (they continue past the cached vertex)");
+  }
+  Plan plan = make_plan(W, s->hdr.n_bins, s->hdr.n_cells, 1);
+  if (!ws) return fail(c, SDD_ERR_INVALID_ARG, "workspace is null");
+  if (ws_bytes < plan.total)
+    return fail(c, SDD_ERR_WORKSPACE,
+                "workspace too small: need " + std::to_string(plan.total) + " bytes, got " + std::to_string(ws_bytes));
+  HIP_TRY(c, hipSetDevice(c->device));
+  DevWS w = ws_view(plan, ws);
+  if (c->last_ctl != w.ctl)
+    HIP_TRY(c, launch_fill_u32(c->stream, (uint32_t*)&w.ctl->st_paths, (sizeof(Ctl) - offsetof(Ctl, st_paths)) / 4, 0u));
+  c->last_ctl = w.ctl;
+  views[0].item_base = 0;
+  return enqueue_frame(c, s, views, p, plan, w, total, p->timing != 0, k, tp);
+}
+
 int sdd_query_workspace_bytes(const sdd_scene* s, int64_t n, size_t* bytes) {
   if (!s || !bytes || n < 1) return fail(nullptr, SDD_ERR_INVALID_ARG, "bad argument");
   uint32_t W = (uint32_t)std::min<int64_t>(n, kDefaultWave);
@@ -616,6 +701,7 @@ int sdd_finish(sdd_ctx* c) {
     c->acc.err_stack += h.err_stack;
     c->acc.node_visits += h.st_nodes;
     c->acc.tri_tests += h.st_tris;
+    c->acc.cache_queries += h.st_queries;
     if (h.err_cross) status = fail(c, SDD_ERR_QUEUE_OVERFLOW, "a shadow ray crossed more glass slabs than recorded");
     c->last_ctl = nullptr;
   }
@@ -631,7 +717,11 @@ int sdd_finish(sdd_ctx* c) {
     float ms = 0;
     if (hipEventElapsedTime(&ms, c->ev_graph[i].first, c->ev_graph[i].second) == hipSuccess) c->acc.graph_ms += ms;
   }
-  c->ev_used_trace = c->ev_used_shade = c->ev_used_graph = 0;
+  for (size_t i = 0; i < c->ev_used_cache; ++i) {
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, c->ev_cache[i].first, c->ev_cache[i].second) == hipSuccess) c->acc.cache_ms += ms;
+  }
+  c->ev_used_trace = c->ev_used_shade = c->ev_used_graph = c->ev_used_cache = 0;
   return status;
 }
 

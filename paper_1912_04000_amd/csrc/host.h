@@ -2,6 +2,7 @@
 #pragma once
 
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/specdd.h"
@@ -16,6 +17,36 @@ struct sdd_scene {
   int dev_device = -1;
 };
 
+struct sdd_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  sdd::Ctl* last_ctl = nullptr;     // control block of the last launched work (inside a workspace)
+  sdd_stats acc;               // accumulated statistics
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_trace, ev_shade, ev_graph;
+  size_t ev_used_trace = 0, ev_used_shade = 0, ev_used_graph = 0;
+  int cu_count = 256;
+  // captured launch sequence of the last graph-mode render and the key it was captured for
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  hipStream_t capture_stream = nullptr;   // own stream (default priority) used only to record graphs
+  uint64_t graph_key = 0;
+  uint64_t graph_trace_launches = 0, graph_shade_launches = 0, graph_wavefronts = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_cache;
+  size_t ev_used_cache = 0;
+};
+
+struct sdd_cache {
+  sdd_cache_config cfg;
+  sdd::CacheDev dev;          // device view (pointers into the caller's buffer)
+  float* opt = nullptr;       // device [4]: Adam step count (uint bits), 1/(1-b1^t), 1/(1-b2^t), step active
+  void* buf = nullptr;
+  size_t bytes = 0;
+  int device = -1;
+  bool ready = false;         // parameters defined (init / set_params)
+  uint64_t train_paths_done = 0;
+};
+
 namespace sdd {
 
 // Builds the cell-decomposed scene image. Returns an empty string on success, else the reason.
@@ -26,6 +57,8 @@ DevScene device_view(const sdd_scene* s);
 
 void set_thread_error(const std::string& msg);
 hipStream_t ctx_stream(const sdd_ctx* ctx);
+// One training batch over the records held by the cache (cache_api.cpp).
+int cache_train_records(sdd_ctx* c, sdd_cache* k, int B, int steps, int step_records);
 const char* thread_error();
 
 }  // namespace sdd

@@ -111,7 +111,8 @@ struct Ctl {
   unsigned long long st_paths, st_vertices, st_ext, st_shadow, st_visits, st_migr, st_escape, st_glass;
   unsigned long long err_cross, err_nonfinite, err_stack;
   unsigned long long st_nodes, st_tris;  // BVH nodes visited, triangle tests (traversal work)
-  unsigned long long pad1[3];
+  unsigned long long st_queries;         // vertices answered by the radiance cache
+  unsigned long long pad1[2];
 };
 
 // Device view of a workspace.
@@ -145,6 +146,60 @@ struct DevWS {
   int32_t pad;
 };
 
+// ------------------------------------------------------------------------------------------
+// Learned spectral radiance cache
+// ------------------------------------------------------------------------------------------
+// Network: input 64 = [position grid 2 Lp | direction grid 2 Ld | material embedding 8 |
+// wavelength one-blob 8 | zero padding], four 64-wide ReLU layers without biases, one output.
+constexpr int kCacheWidth = 64;
+constexpr int kCacheFeat = 2;       // features per grid level
+constexpr int kCacheMatDim = 8;
+constexpr int kCacheBlob = 8;
+constexpr int kCacheMaxLevels = 16;
+constexpr int kCacheVerts = 32;     // query vertices per wave (the MFMA N dimension)
+constexpr int kCacheWaves = 4;      // waves per workgroup of the cache kernels
+constexpr int kCacheERow = 72;      // bf16 row stride of the per-wave encoding tile in LDS
+
+// Device view of a cache (masters, optimizer state, packed weights, training buffers).
+struct CacheDev {
+  float* P;            // FP32 master parameters, flat layout (see sdd_cache_param_count)
+  float* M;            // Adam first moments [n_param]
+  float* V;            // Adam second moments [n_param]
+  float* G;            // gradients [n_param]
+  uint32_t* gpos;      // bf16x2 copy of the position grid [Lp][Tp]
+  uint32_t* gdir;      // bf16x2 copy of the direction grid [Ld][Td]
+  uint4* wf;           // forward MFMA A operands [4 layers][2 mt][4 kb][64 lanes] (8 bf16 each)
+  uint4* wb;           // backward (transposed) A operands, same shape
+  uint4* w4b;          // output weights as B-operand words [4 kb][2 halves] (8 bf16 each)
+  // training buffers
+  float4* rx;          // [max_train] record position, material id bits in w
+  float4* rw;          // [max_train] record direction toward the previous vertex, valid flag in w
+  float* tgt;          // [max_train][max_bins] suffix radiance targets
+  uint32_t* ridx;      // [max_train] compacted record slots; ridx[max_train] = count
+  uint16_t* hst;       // [4][max_rows/32][64][32] bf16 layer inputs h0..h3 (tile, unit, row)
+  uint16_t* dst;       // [4][max_rows/32][64][32] bf16 deltas of layers 1..4
+  float* dE;           // [max_step][64] gradient of the encoding (pos | dir | mat)
+  float* loss;         // [2] loss sum, rows
+  int64_t n_param;
+  int64_t o_pos, o_dir, o_mat, o_w[4], o_w4;
+  int32_t Lp, Ld, Tp_log2, Td_log2, n_mat, n_in;
+  int32_t Npos[kCacheMaxLevels], Ndir[kCacheMaxLevels];
+  uint32_t dense_pos, dense_dir;   // bit l: level l is indexed densely
+  float lo[3], ext[3];             // position normalisation box (lo, hi - lo)
+  int32_t max_bins, max_train, max_step;
+  int32_t pad;
+};
+
+// Random-number purpose and training record of a path population: rendered paths use purpose 0
+// and record nothing; training paths use purpose 1 (bit 24 of the counter's depth word) and
+// record their vertex at depth rec_depth.
+struct PathMode {
+  uint32_t purpose;    // 0 or 1u << 24
+  int32_t rec_depth;   // vertex recorded for training, 0 = none
+  float4* rec_x;       // [W] (position, material bits)
+  float4* rec_w;       // [W] (direction toward the previous vertex, valid)
+};
+
 // Host helpers implemented in the kernels' translation unit.
 struct Launch {
   hipStream_t stream;
@@ -154,20 +209,35 @@ struct Launch {
 hipError_t launch_fill_f32(hipStream_t s, float* p, size_t n, float v);
 hipError_t launch_fill_u32(hipStream_t s, uint32_t* p, size_t n, uint32_t v);
 hipError_t launch_raygen(const Launch& L, const DevScene& S, const DevWS& w, uint64_t k0, uint32_t n, uint64_t seed,
-                         int gen);
+                         int gen, const PathMode& pm);
 hipError_t launch_scan(const Launch& L, const DevScene& S, const DevWS& w, int gen);
 hipError_t launch_scatter(const Launch& L, const DevWS& w, int gen);
 hipError_t launch_trace(const Launch& L, const DevScene& S, const DevWS& w, int gen, int hops, int cat_par);
 hipError_t launch_resolve(const Launch& L, const DevScene& S, const DevWS& w, int depth);
 hipError_t launch_escape(const Launch& L, const DevScene& S, const DevWS& w, int depth);
 hipError_t launch_shade_opaque(const Launch& L, const DevScene& S, const DevWS& w, int depth, int max_depth,
-                               uint64_t seed, int gen);
-hipError_t launch_shade_glass(const Launch& L, const DevScene& S, const DevWS& w, int depth, uint64_t seed, int gen);
+                               uint64_t seed, int gen, const PathMode& pm);
+hipError_t launch_shade_glass(const Launch& L, const DevScene& S, const DevWS& w, int depth, uint64_t seed, int gen,
+                              const PathMode& pm);
 hipError_t launch_accumulate(const Launch& L, const DevScene& S, const DevWS& w, uint32_t n);
 hipError_t launch_pack_rays(const Launch& L, const DevScene& S, const DevWS& w, const float* orig, const float* dir,
                             const int32_t* skip, uint32_t n, int shadow, int gen);
 hipError_t launch_unpack_hits(const Launch& L, const DevWS& w, uint32_t n, float* t, int32_t* id, float* u, float* v);
 hipError_t launch_resolve_vis(const Launch& L, const DevScene& S, const DevWS& w, uint32_t n, float* vis);
 hipError_t launch_philox(hipStream_t s, const uint32_t ctr[4], const uint32_t key[2], uint64_t n, uint32_t* out);
+
+// radiance cache (cache.hip)
+hipError_t launch_cache_init(hipStream_t s, const CacheDev& C, uint64_t seed);
+hipError_t launch_cache_sync(hipStream_t s, const CacheDev& C);
+hipError_t launch_cache_eval(hipStream_t s, const CacheDev& C, const float* x, const float* wo, const int32_t* mat,
+                             uint32_t n, int B, float* out);
+hipError_t launch_cache_query(hipStream_t s, const CacheDev& C, const DevScene& S, const DevWS& w, int p);
+hipError_t launch_cache_load_records(hipStream_t s, const CacheDev& C, const float* x, const float* wo,
+                                     const int32_t* mat, const float* t, uint32_t n, int B);
+hipError_t launch_cache_gather(hipStream_t s, const CacheDev& C, const DevWS& w, uint32_t n, int B);
+hipError_t launch_cache_compact(hipStream_t s, const CacheDev& C, uint32_t n, uint32_t cap);
+hipError_t launch_cache_backward(hipStream_t s, const CacheDev& C, int B, uint32_t v0, uint32_t step_max);
+hipError_t launch_cache_adam(hipStream_t s, const CacheDev& C, uint32_t v0, uint32_t step_max, float* opt, float lr,
+                             float b1, float b2, float eps);
 
 }  // namespace sdd

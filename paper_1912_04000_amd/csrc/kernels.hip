@@ -208,22 +208,38 @@ __device__ __forceinline__ uint32_t* cat_list(const DevWS& w, int par, int cat) 
   return w.cat + ((size_t)par * kCats + cat) * w.W;
 }
 
+// Camera paths. Render items k0 + i map to (view, sample, pixel) in sample-major order. Training
+// paths (kTrain) are items of view 0: path g = k0 + i starts at a pixel drawn from the counter
+// (g, g >> 32, purpose 2, view) and uses g as its sample index under purpose 1, so that its
+// random numbers never coincide with those of a rendered sample.
+template <bool kTrain>
 __global__ __launch_bounds__(kWG) void k_raygen(DevScene S, DevWS w, uint64_t k0, uint32_t n, uint32_t key0,
-                                                uint32_t key1, int gen) {
+                                                uint32_t key1, int gen, PathMode pm) {
   const uint32_t i = blockIdx.x * kWG + threadIdx.x;
   const bool valid = i < n;
   uint32_t cell = kInvalidCell;
   if (valid) {
     const uint64_t k = k0 + i;
     int v = 0;
-    while (v + 1 < w.n_views && w.views[v + 1].item_base <= k) ++v;
+    uint32_t s, pix;
+    if (kTrain) {
+      const ViewDesc& V0 = w.views[0];
+      const uint64_t P = (uint64_t)V0.width * V0.height;
+      const uint4 r0 = philox(make_uint4((uint32_t)k, (uint32_t)(k >> 32), 2u << 24, V0.view_id), key0, key1);
+      pix = (uint32_t)(r0.x % P);
+      s = (uint32_t)k;
+      pm.rec_w[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    } else {
+      while (v + 1 < w.n_views && w.views[v + 1].item_base <= k) ++v;
+      const ViewDesc& V1 = w.views[v];
+      const uint64_t local = k - V1.item_base;
+      const uint64_t P = (uint64_t)V1.width * V1.height;
+      s = (uint32_t)(local / P) + V1.first_sample;
+      pix = (uint32_t)(local % P);
+    }
     const ViewDesc& V = w.views[v];
-    const uint64_t local = k - V.item_base;
-    const uint64_t P = (uint64_t)V.width * V.height;
-    const uint32_t s = (uint32_t)(local / P) + V.first_sample;
-    const uint32_t pix = (uint32_t)(local % P);
     const uint32_t px = pix % (uint32_t)V.width, py = pix / (uint32_t)V.width;
-    const uint4 rn = philox(make_uint4(pix, s, 0u, V.view_id), key0, key1);
+    const uint4 rn = philox(make_uint4(pix, s, pm.purpose, V.view_id), key0, key1);
     const float sx = 2.0f * ((float)px + unif24(rn.x)) / (float)V.width - 1.0f;
     const float sy = 1.0f - 2.0f * ((float)py + unif24(rn.y)) / (float)V.height;
     const F3 fw = f3(V.fwd[0], V.fwd[1], V.fwd[2]);
@@ -778,8 +794,22 @@ __global__ __launch_bounds__(kWG) void k_escape(DevScene S, DevWS w, int depth) 
 
 // Opaque vertex: direct term toward the sun through a shadow ray (eq. 3), then the
 // Fresnel-split lobe choice (mirror with probability mean F, else cosine-weighted diffuse).
+// Records a training vertex: position, direction toward the previous vertex, material; the
+// path's throughput restarts at one and its gathered radiance at zero, so that what the path
+// gathers from here on is the radiance leaving this vertex toward the previous one.
+__device__ __forceinline__ void record_vertex(const PathMode& pm, const DevWS& w, uint32_t s, const Vertex& V) {
+  pm.rec_x[s] = make_float4(V.p.x, V.p.y, V.p.z, __uint_as_float((uint32_t)V.m));
+  pm.rec_w[s] = make_float4(-V.d.x, -V.d.y, -V.d.z, 1.0f);
+  float4* b4 = (float4*)(w.beta + (size_t)s * w.Bp);
+  float4* l4 = (float4*)(w.lacc + (size_t)s * w.Bp);
+  for (int q = 0; q < w.Bp / 4; ++q) {
+    b4[q] = make_float4(1.0f, 1.0f, 1.0f, 1.0f);
+    l4[q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  }
+}
+
 __global__ __launch_bounds__(kWG) void k_shade_opaque(DevScene S, DevWS w, int depth, int max_depth, uint32_t key0,
-                                                      uint32_t key1, int gen) {
+                                                      uint32_t key1, int gen, PathMode pm) {
   const int p = depth & 1;
   const uint32_t n = w.ctl->cat_count[p][kCatOpaque];
   const uint32_t* list = cat_list(w, p, kCatOpaque);
@@ -794,7 +824,9 @@ __global__ __launch_bounds__(kWG) void k_shade_opaque(DevScene S, DevWS w, int d
     if (valid) {
       s = list[a];
       const Vertex V = load_vertex(S, w, s);
-      const uint4 rn = philox(make_uint4(w.pix[s], w.smp[s], (uint32_t)depth, w.views[w.view[s]].view_id), key0, key1);
+      if (depth == pm.rec_depth) record_vertex(pm, w, s, V);
+      const uint4 rn = philox(make_uint4(w.pix[s], w.smp[s], (uint32_t)depth | pm.purpose, w.views[w.view[s]].view_id),
+                              key0, key1);
       const float u0 = unif24(rn.x), u1 = unif24(rn.y), u2 = unif24(rn.z);
       const float4* nt = (const float4*)(S.ntab + V.m * Bp);
       const float4* kt = (const float4*)(S.ktab + V.m * Bp);
@@ -894,7 +926,7 @@ __global__ __launch_bounds__(kWG) void k_shade_opaque(DevScene S, DevWS w, int d
 // Glass vertex: thin slab, reflect with probability mean R / (mean R + mean T), else transmit
 // straight through (no lateral shift); no direct term at glass.
 __global__ __launch_bounds__(kWG) void k_shade_glass(DevScene S, DevWS w, int depth, uint32_t key0, uint32_t key1,
-                                                     int gen) {
+                                                     int gen, PathMode pm) {
   const int p = depth & 1;
   const uint32_t n = w.ctl->cat_count[p][kCatGlass];
   const uint32_t* list = cat_list(w, p, kCatGlass);
@@ -907,7 +939,9 @@ __global__ __launch_bounds__(kWG) void k_shade_glass(DevScene S, DevWS w, int de
     if (valid) {
       s = list[a];
       const Vertex V = load_vertex(S, w, s);
-      const uint4 rn = philox(make_uint4(w.pix[s], w.smp[s], (uint32_t)depth, w.views[w.view[s]].view_id), key0, key1);
+      if (depth == pm.rec_depth) record_vertex(pm, w, s, V);
+      const uint4 rn = philox(make_uint4(w.pix[s], w.smp[s], (uint32_t)depth | pm.purpose, w.views[w.view[s]].view_id),
+                              key0, key1);
       const float u0 = unif24(rn.x);
       const float* nt = S.ntab + V.m * Bp;
       const float* kt = S.ktab + V.m * Bp;
@@ -990,9 +1024,13 @@ hipError_t launch_philox(hipStream_t s, const uint32_t ctr[4], const uint32_t ke
 }
 
 hipError_t launch_raygen(const Launch& L, const DevScene& S, const DevWS& w, uint64_t k0, uint32_t n, uint64_t seed,
-                         int gen) {
-  hipLaunchKernelGGL(k_raygen, dim3((n + kWG - 1) / kWG), dim3(kWG), 0, L.stream, S, w, k0, n, (uint32_t)seed,
-                     (uint32_t)(seed >> 32), gen);
+                         int gen, const PathMode& pm) {
+  if (pm.purpose)
+    hipLaunchKernelGGL(k_raygen<true>, dim3((n + kWG - 1) / kWG), dim3(kWG), 0, L.stream, S, w, k0, n, (uint32_t)seed,
+                       (uint32_t)(seed >> 32), gen, pm);
+  else
+    hipLaunchKernelGGL(k_raygen<false>, dim3((n + kWG - 1) / kWG), dim3(kWG), 0, L.stream, S, w, k0, n,
+                       (uint32_t)seed, (uint32_t)(seed >> 32), gen, pm);
   return hipGetLastError();
 }
 
@@ -1022,15 +1060,16 @@ hipError_t launch_escape(const Launch& L, const DevScene& S, const DevWS& w, int
 }
 
 hipError_t launch_shade_opaque(const Launch& L, const DevScene& S, const DevWS& w, int depth, int max_depth,
-                               uint64_t seed, int gen) {
+                               uint64_t seed, int gen, const PathMode& pm) {
   hipLaunchKernelGGL(k_shade_opaque, dim3(grid_for(w.W, 4096)), dim3(kWG), 0, L.stream, S, w, depth, max_depth,
-                     (uint32_t)seed, (uint32_t)(seed >> 32), gen);
+                     (uint32_t)seed, (uint32_t)(seed >> 32), gen, pm);
   return hipGetLastError();
 }
 
-hipError_t launch_shade_glass(const Launch& L, const DevScene& S, const DevWS& w, int depth, uint64_t seed, int gen) {
+hipError_t launch_shade_glass(const Launch& L, const DevScene& S, const DevWS& w, int depth, uint64_t seed, int gen,
+                              const PathMode& pm) {
   hipLaunchKernelGGL(k_shade_glass, dim3(grid_for(w.W, 1024)), dim3(kWG), 0, L.stream, S, w, depth, (uint32_t)seed,
-                     (uint32_t)(seed >> 32), gen);
+                     (uint32_t)(seed >> 32), gen, pm);
   return hipGetLastError();
 }
 

@@ -143,3 +143,18 @@ def test_render_params_validation_without_gpu():
     p = sd.render_params(spp=4, max_depth=8, wave_paths=1 << 16)
     assert sd.lib().sdd_workspace_bytes(S.handle, C.byref(p), C.byref(b)) == 0
     assert b.value > (1 << 16) * 8 * 8
+
+
+def test_binding_classes_keep_their_methods():
+    """Context and Cache each own their destructor (a destructor of the wrong class would free a
+    handle of the other type)."""
+    import inspect
+    from paper_1912_04000_amd import _binding as b
+    ctx_src = inspect.getsource(b.Context.__del__)
+    cache_src = inspect.getsource(b.Cache.__del__)
+    assert "sdd_destroy" in ctx_src and "sdd_cache_destroy" not in ctx_src
+    assert "sdd_cache_destroy" in cache_src
+    for m in ("stats", "reset_stats", "render_cached", "finish"):
+        assert hasattr(b.Context, m)
+    for m in ("eval", "backward", "step", "train", "params", "grads", "records"):
+        assert hasattr(b.Cache, m)
