@@ -21,6 +21,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -39,7 +41,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="church", choices=["church", "nave", "batch"])
+    ap.add_argument("--workload", default="church", choices=["church", "nave", "batch", "cached"])
+    ap.add_argument("--cached-spp", type=int, default=64, help="cached workload: samples per pixel of the scored frame")
+    ap.add_argument("--warm-frames", type=int, default=8, help="cached workload: 1-spp training frames before it")
+    ap.add_argument("--train-paths", type=int, default=1 << 17, help="cached workload: training paths per batch")
+    ap.add_argument("--train-every", type=int, default=1, help="cached workload: wavefronts between batches")
     ap.add_argument("--tune-cache", default=os.path.join(os.path.expanduser("~"), ".cache", "specdd",
                                                           "tune_cache.json"))
     ap.add_argument("--spp", type=int, default=None, help="override samples per pixel (profiling runs)")
@@ -183,6 +189,108 @@ def pmc_summary(args):
     print(json.dumps({k: round(v["hbm_bytes_per_launch"] / 1e6, 3) for k, v in kernels.items()}))
 
 
+def _rmse(img, ref, px):
+    """RMSE over (subset pixel, bin) of an image [B][H][W] against the reference [B][n]."""
+    B = ref.shape[0]
+    sub = img.reshape(B, -1)[:, px]
+    return float(np.sqrt(np.mean((sub.astype(np.float64) - ref) ** 2)))
+
+
+def bench_cached(args):
+    """Equal-RMSE comparison of the plain full-depth path and the cache-terminated path on the
+    church-1M view (the C2 frame, 40 bins, depth 8). Both are scored by RMSE against the
+    oracle's FP64 1024-spp reference on the pixel subset x % 16 == 0, y % 16 == 0
+    (tests/golden/c4_reference.npz). Plain: RMSE at spp = 1 .. 64 gives the fit
+    RMSE = a / sqrt(spp) and the frame rate. Cached: the cache starts untrained, is trained
+    online during warm_frames 1-spp frames and the scored frame (2^16 records per training
+    batch, 4 Adam steps of 2^14, lr 1e-3); the time of every warm-up and scored frame counts.
+    value = W H spp_eq / time_cached, with spp_eq = (a / RMSE_cached)^2 the plain samples per
+    pixel that reach the cached frame's RMSE: plain-equivalent samples per second."""
+    import torch
+    import paper_1912_04000_amd as sd
+    import scenegen
+    ref_f = np.load(os.path.join(ROOT, "tests", "golden", "c4_reference.npz"))
+    px, ref = ref_f["pixels"], ref_f["image"].astype(np.float64)
+    sc = scenegen.church_scene(40)
+    cam = scenegen.church_camera()
+    B, W, H = sc.n_bins, cam.width, cam.height
+    ctx = sd.Context(0)
+    S = sd.Scene.from_description(sc, grid=(8, 4, 4))
+    ctx.upload(S)
+    c = sd.camera(cam.eye, cam.target, cam.up, cam.vfov_deg, W, H)
+    img = torch.empty((B, H, W), dtype=torch.float32, device="cuda")
+    wave = 1 << 21
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    # plain: RMSE vs spp (seed 1, the bench frame's), frame time at 64 spp
+    ctx.render(S, c, sd.render_params(spp=1, max_depth=8, seed=1, wave_paths=wave), out=img)  # warm-up
+    plain = []
+    for spp in (1, 2, 4, 8, 16, 32, 64):
+        dt = timed(lambda: ctx.render(S, c, sd.render_params(spp=spp, max_depth=8, seed=1, wave_paths=wave), out=img))
+        plain.append(dict(spp=spp, seconds=dt, rmse=_rmse(img.cpu().numpy(), ref, px)))
+    sp = np.array([p["spp"] for p in plain], dtype=np.float64)
+    rm = np.array([p["rmse"] for p in plain])
+    a = float(np.sum(rm * sp ** -0.5) / np.sum(1.0 / sp))   # least squares of rmse = a spp^-1/2
+    plain_rate = W * H * 64 / plain[-1]["seconds"]
+    # cached
+    lo = sc.verts.reshape(-1, 3).min(0) - 0.05
+    hi = sc.verts.reshape(-1, 3).max(0) + 0.05
+    cache = sd.Cache(ctx, sd.cache_config(len(sc.mat_type), lo, hi, max_bins=B, max_records=max(args.train_paths, 1 << 14),
+                                          max_step=1 << 14), seed=12345)
+    tp = sd.train_params(train_paths=args.train_paths, step_records=1 << 14, steps=4, every=args.train_every)
+    ctx.reset_stats()
+    frames = []
+    t_total = 0.0
+    for f in range(args.warm_frames):
+        dt = timed(lambda: ctx.render_cached(S, cache, c, sd.render_params(spp=1, max_depth=8, seed=1000 + f,
+                                                                          mode=sd.MODE_CACHED, wave_paths=wave),
+                                             tp, out=img))
+        t_total += dt
+        frames.append(dict(frame=f, spp=1, seconds=dt, rmse=_rmse(img.cpu().numpy(), ref, px)))
+    n_spp = args.cached_spp
+    p = sd.render_params(spp=n_spp, max_depth=8, seed=1, mode=sd.MODE_CACHED, wave_paths=wave, timing=1)
+    dt = timed(lambda: ctx.render_cached(S, cache, c, p, tp, out=img))
+    t_total += dt
+    r_c = _rmse(img.cpu().numpy(), ref, px)
+    frames.append(dict(frame=args.warm_frames, spp=n_spp, seconds=dt, rmse=r_c))
+    st = ctx.stats()
+    info = cache.info()
+    # the same scored frame with training switched off (inference-only throughput)
+    dt_inf = timed(lambda: ctx.render_cached(S, cache, c, sd.render_params(spp=n_spp, max_depth=8, seed=1,
+                                                                            mode=sd.MODE_CACHED, wave_paths=wave),
+                                             None, out=img))
+    r_inf = _rmse(img.cpu().numpy(), ref, px)
+    spp_eq = (a / r_c) ** 2
+    t_plain_eq = W * H * spp_eq / plain_rate
+    value = W * H * spp_eq / t_total
+    out = {
+        "metric": METRIC, "value": value, "unit": "plain-equivalent spectral path samples/s", "n_gpus": 1,
+        "steps": 1, "warmup": args.warm_frames, "ms_per_step": t_total * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16 (cache MLP) / f32 (tracer)",
+        "data": f"synthetic (seeded procedural scene, {sc.n_tri} triangles)",
+        "config": {"workload": "church-1M cached vs plain at equal RMSE: 1920x1080, 40 bins, depth 8, cache at vertex 3, "
+                               f"{args.warm_frames} 1-spp warm-up frames + one {n_spp}-spp frame, online training",
+                   "reference": "oracle FP64 1024 spp, pixels x%16==0 and y%16==0",
+                   "train_paths_per_batch": args.train_paths, "train_every": args.train_every,
+                   "records_per_batch": 4 << 14, "adam_steps": info["adam_steps"]},
+        "equal_rmse": {"rmse_cached": r_c, "plain_fit_a": a, "spp_plain_equivalent": spp_eq,
+                       "time_cached_s": t_total, "time_plain_equivalent_s": t_plain_eq,
+                       "speedup": t_plain_eq / t_total,
+                       "cached_samples_per_s": W * H * (n_spp + args.warm_frames) / t_total,
+                       "plain_samples_per_s": plain_rate,
+                       "rmse_cached_frame_inference_only": r_inf, "inference_only_frame_s": dt_inf},
+        "plain_curve": plain, "cached_frames": frames,
+        "cache_ms": st["cache_ms"], "train_batches": st["train_batches"], "cache_queries": st["cache_queries"],
+    }
+    print(json.dumps(out), flush=True)
+
+
 def bench_batch(args):
     """32 seeded views of the church with uneven resolutions (256x256 .. 1024x768) and spp (4..64),
     rendered together in one graph launch per step, with the grid, wavefront size and queue rounds
@@ -250,6 +358,9 @@ def main():
         return
     if args.workload == "batch":
         bench_batch(args)
+        return
+    if args.workload == "cached":
+        bench_cached(args)
         return
     import torch
     import paper_1912_04000_amd as sd
