@@ -1,12 +1,16 @@
 #!/usr/bin/env python
-"""Benchmark of the plain spectral path tracer on one MI355X.
+"""Benchmark of the spectral path tracer on one MI355X.
 
 Workload (default): the seeded procedural church of 979,664 triangles (40 coloured glass windows),
 1920x1080 pixels, 40 wavelength bins over 380-780 nm, 64 samples per pixel, 8 surface vertices
-per path, 8x4x4 cells, 2^21 paths in flight. One step = one full frame (132.7 M spectral path
-samples, each carrying all 40 bins). Prints one JSON line.
+per path, 8x4x4 cells, 2^21 paths in flight. One step = one full plain frame (132.7 M spectral
+path samples, each carrying all 40 bins); `value` is the plain path's samples/s. The same line
+carries `equal_rmse`: the cache-terminated path on the same view (untrained cache, eight 1-spp
+online-training frames, then a 64-spp frame, all timed) scored against the oracle's 1024-spp
+reference, with the plain time to reach the same RMSE. Prints one JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--workload church|nave] [--no-cpu-baseline]
+  python bench.py [--steps K] [--warmup W] [--workload church|nave|batch|cached] [--no-cpu-baseline]
+                  [--no-cached]
   python bench.py --copy-calibration 1.0   # a plain 1 GiB device copy (for PMC byte scaling)
   python bench.py --pmc-summary F.csv W.csv CF.csv CW.csv   # HBM bytes of k_trace from rocprofv3 --pmc
       (FETCH_SIZE and WRITE_SIZE runs of this bench, then of --copy-calibration; writes
@@ -31,6 +35,7 @@ HBM_PEAK_GBPS = 8000.0
 # Non-packed FP32 VALU issue rate of MI355X: 256 CUs x 64 lanes x 2.4 GHz (ops/s, 1 op = 1 flop).
 # The 157.3 TFLOP/s vector figure counts an FMA as 2 flops on packed (2-wide) lanes.
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+BF16_PEAK_TFLOPS = 2500.0   # dense bf16 matrix-core peak of MI355X
 # Algorithmic VALU operations per unit of traversal work (counted from the kernel source):
 OPS_PER_NODE = 52       # two robust slab tests (6 sub, 6 mul, 12 min/max, 1 slop mul, 1 cmp each)
 OPS_PER_TRI = 56        # watertight test: translate, shear, 3 edge functions, signs, det, t, u, v
@@ -52,6 +57,7 @@ def parse():
     ap.add_argument("--wave-paths", type=int, default=1 << 21)
     ap.add_argument("--queue-rounds", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cached", action="store_true", help="skip the cached-path comparison of the default run")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="GiB: only run a plain device-to-device copy of that size (PMC calibration)")
@@ -196,11 +202,90 @@ def _rmse(img, ref, px):
     return float(np.sqrt(np.mean((sub.astype(np.float64) - ref) ** 2)))
 
 
+def load_reference():
+    ref_f = np.load(os.path.join(ROOT, "tests", "golden", "c4_reference.npz"))
+    return ref_f["pixels"], ref_f["image"].astype(np.float64)
+
+
+def _timed(fn):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def run_cached(ctx, S, sc, cam, img, args, px, ref, wave=1 << 21):
+    """The cache-terminated path on the church view: an untrained cache, warm_frames 1-spp frames
+    with online training, then one scored frame of cached_spp samples (training on), all timed;
+    then the same frame again with training off (inference-only throughput)."""
+    import paper_1912_04000_amd as sd
+    B, W, H = sc.n_bins, cam.width, cam.height
+    c = sd.camera(cam.eye, cam.target, cam.up, cam.vfov_deg, W, H)
+    lo = sc.verts.reshape(-1, 3).min(0) - 0.05
+    hi = sc.verts.reshape(-1, 3).max(0) + 0.05
+    cache = sd.Cache(ctx, sd.cache_config(len(sc.mat_type), lo, hi, max_bins=B,
+                                          max_records=max(args.train_paths, 1 << 14), max_step=1 << 14), seed=12345)
+    tp = sd.train_params(train_paths=args.train_paths, step_records=1 << 14, steps=4, every=args.train_every)
+    ctx.reset_stats()
+    frames, t_total = [], 0.0
+    for f in range(args.warm_frames):
+        dt = _timed(lambda: ctx.render_cached(S, cache, c, sd.render_params(spp=1, max_depth=8, seed=1000 + f,
+                                                                           mode=sd.MODE_CACHED, wave_paths=wave),
+                                              tp, out=img))
+        t_total += dt
+        frames.append(dict(frame=f, spp=1, seconds=dt, rmse=_rmse(img.cpu().numpy(), ref, px)))
+    n_spp = args.cached_spp
+    ctx.finish()
+    ctx.reset_stats()   # the statistics below cover the scored frame only
+    p = sd.render_params(spp=n_spp, max_depth=8, seed=1, mode=sd.MODE_CACHED, wave_paths=wave, timing=1)
+    dt = _timed(lambda: ctx.render_cached(S, cache, c, p, tp, out=img))
+    t_total += dt
+    r_c = _rmse(img.cpu().numpy(), ref, px)
+    frames.append(dict(frame=args.warm_frames, spp=n_spp, seconds=dt, rmse=r_c))
+    st = ctx.stats()
+    dt_inf = _timed(lambda: ctx.render_cached(S, cache, c, sd.render_params(spp=n_spp, max_depth=8, seed=1,
+                                                                             mode=sd.MODE_CACHED, wave_paths=wave),
+                                              None, out=img))
+    r_inf = _rmse(img.cpu().numpy(), ref, px)
+    # matrix-core roofline of the query kernel in the scored frame: MFMA flops per queried vertex
+    # = 2*64*64 (z = W0 e) + B * 3 * 2*64*64 (three 64x64 layers per bin)
+    flops = st["cache_queries"] * (2 * 64 * 64 + B * 3 * 2 * 64 * 64)
+    q_s = st["query_ms"] / 1e3
+    achieved = flops / q_s / 1e12 if q_s > 0 else 0.0
+    roof = {"kernel": "k_cache_query", "bound": "mfma", "achieved": achieved, "peak": BF16_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": achieved / BF16_PEAK_TFLOPS, "launches": st["query_launches"],
+            "avg_launch_ms": st["query_ms"] / max(1, st["query_launches"]),
+            "queries_per_launch": st["cache_queries"] / max(1, st["query_launches"]),
+            "note": "algorithmic MFMA flops (2*64*64 per vertex + 3*2*64*64 per vertex and bin) of the scored "
+                    "frame's queries over the HIP-event time of its query launches; peak = bf16 dense"}
+    return dict(rmse=r_c, seconds=t_total, frames=frames, inference_rmse=r_inf, inference_seconds=dt_inf,
+                spp=n_spp, adam_steps=cache.info()["adam_steps"], train_ms=st["train_ms"],
+                train_batches=st["train_batches"], cache_queries=st["cache_queries"], roofline=roof)
+
+
+def equal_rmse(cached, a, plain_rate, W, H, warm_frames):
+    """Plain spp that reaches the cached frame's RMSE under RMSE = a / sqrt(spp), and the times."""
+    spp_eq = (a / cached["rmse"]) ** 2
+    t_plain = W * H * spp_eq / plain_rate
+    return {"rmse_cached": cached["rmse"], "plain_fit_a": a, "spp_plain_equivalent": spp_eq,
+            "time_cached_s": cached["seconds"], "time_plain_equivalent_s": t_plain,
+            "speedup": t_plain / cached["seconds"],
+            "plain_equivalent_samples_per_s": W * H * spp_eq / cached["seconds"],
+            "cached_samples_per_s": W * H * (cached["spp"] + warm_frames) / cached["seconds"],
+            "plain_samples_per_s": plain_rate,
+            "rmse_cached_inference_only": cached["inference_rmse"],
+            "inference_only_frame_s": cached["inference_seconds"],
+            "adam_steps": cached["adam_steps"], "train_ms": cached["train_ms"],
+            "train_batches": cached["train_batches"], "cache_roofline": cached["roofline"]}
+
+
 def bench_cached(args):
     """Equal-RMSE comparison of the plain full-depth path and the cache-terminated path on the
     church-1M view (the C2 frame, 40 bins, depth 8). Both are scored by RMSE against the
     oracle's FP64 1024-spp reference on the pixel subset x % 16 == 0, y % 16 == 0
-    (tests/golden/c4_reference.npz). Plain: RMSE at spp = 1 .. 64 gives the fit
+    (tests/golden/c4_reference.npz). Plain: RMSE at spp = 1 .. 64 gives the least-squares fit
     RMSE = a / sqrt(spp) and the frame rate. Cached: the cache starts untrained, is trained
     online during warm_frames 1-spp frames and the scored frame (2^16 records per training
     batch, 4 Adam steps of 2^14, lr 1e-3); the time of every warm-up and scored frame counts.
@@ -209,8 +294,7 @@ def bench_cached(args):
     import torch
     import paper_1912_04000_amd as sd
     import scenegen
-    ref_f = np.load(os.path.join(ROOT, "tests", "golden", "c4_reference.npz"))
-    px, ref = ref_f["pixels"], ref_f["image"].astype(np.float64)
+    px, ref = load_reference()
     sc = scenegen.church_scene(40)
     cam = scenegen.church_camera()
     B, W, H = sc.n_bins, cam.width, cam.height
@@ -220,73 +304,30 @@ def bench_cached(args):
     c = sd.camera(cam.eye, cam.target, cam.up, cam.vfov_deg, W, H)
     img = torch.empty((B, H, W), dtype=torch.float32, device="cuda")
     wave = 1 << 21
-
-    def timed(fn):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        fn()
-        torch.cuda.synchronize()
-        return time.perf_counter() - t0
-
-    # plain: RMSE vs spp (seed 1, the bench frame's), frame time at 64 spp
     ctx.render(S, c, sd.render_params(spp=1, max_depth=8, seed=1, wave_paths=wave), out=img)  # warm-up
     plain = []
     for spp in (1, 2, 4, 8, 16, 32, 64):
-        dt = timed(lambda: ctx.render(S, c, sd.render_params(spp=spp, max_depth=8, seed=1, wave_paths=wave), out=img))
+        dt = _timed(lambda: ctx.render(S, c, sd.render_params(spp=spp, max_depth=8, seed=1, wave_paths=wave), out=img))
         plain.append(dict(spp=spp, seconds=dt, rmse=_rmse(img.cpu().numpy(), ref, px)))
     sp = np.array([p["spp"] for p in plain], dtype=np.float64)
     rm = np.array([p["rmse"] for p in plain])
     a = float(np.sum(rm * sp ** -0.5) / np.sum(1.0 / sp))   # least squares of rmse = a spp^-1/2
     plain_rate = W * H * 64 / plain[-1]["seconds"]
-    # cached
-    lo = sc.verts.reshape(-1, 3).min(0) - 0.05
-    hi = sc.verts.reshape(-1, 3).max(0) + 0.05
-    cache = sd.Cache(ctx, sd.cache_config(len(sc.mat_type), lo, hi, max_bins=B, max_records=max(args.train_paths, 1 << 14),
-                                          max_step=1 << 14), seed=12345)
-    tp = sd.train_params(train_paths=args.train_paths, step_records=1 << 14, steps=4, every=args.train_every)
-    ctx.reset_stats()
-    frames = []
-    t_total = 0.0
-    for f in range(args.warm_frames):
-        dt = timed(lambda: ctx.render_cached(S, cache, c, sd.render_params(spp=1, max_depth=8, seed=1000 + f,
-                                                                          mode=sd.MODE_CACHED, wave_paths=wave),
-                                             tp, out=img))
-        t_total += dt
-        frames.append(dict(frame=f, spp=1, seconds=dt, rmse=_rmse(img.cpu().numpy(), ref, px)))
-    n_spp = args.cached_spp
-    p = sd.render_params(spp=n_spp, max_depth=8, seed=1, mode=sd.MODE_CACHED, wave_paths=wave, timing=1)
-    dt = timed(lambda: ctx.render_cached(S, cache, c, p, tp, out=img))
-    t_total += dt
-    r_c = _rmse(img.cpu().numpy(), ref, px)
-    frames.append(dict(frame=args.warm_frames, spp=n_spp, seconds=dt, rmse=r_c))
-    st = ctx.stats()
-    info = cache.info()
-    # the same scored frame with training switched off (inference-only throughput)
-    dt_inf = timed(lambda: ctx.render_cached(S, cache, c, sd.render_params(spp=n_spp, max_depth=8, seed=1,
-                                                                            mode=sd.MODE_CACHED, wave_paths=wave),
-                                             None, out=img))
-    r_inf = _rmse(img.cpu().numpy(), ref, px)
-    spp_eq = (a / r_c) ** 2
-    t_plain_eq = W * H * spp_eq / plain_rate
-    value = W * H * spp_eq / t_total
+    cached = run_cached(ctx, S, sc, cam, img, args, px, ref, wave)
+    eq = equal_rmse(cached, a, plain_rate, W, H, args.warm_frames)
     out = {
-        "metric": METRIC, "value": value, "unit": "plain-equivalent spectral path samples/s", "n_gpus": 1,
-        "steps": 1, "warmup": args.warm_frames, "ms_per_step": t_total * 1e3, "higher_is_better": True,
+        "metric": METRIC, "value": eq["plain_equivalent_samples_per_s"],
+        "unit": "plain-equivalent spectral path samples/s", "n_gpus": 1,
+        "steps": 1, "warmup": args.warm_frames, "ms_per_step": cached["seconds"] * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "bf16 (cache MLP) / f32 (tracer)",
         "data": f"synthetic (seeded procedural scene, {sc.n_tri} triangles)",
         "config": {"workload": "church-1M cached vs plain at equal RMSE: 1920x1080, 40 bins, depth 8, cache at vertex 3, "
-                               f"{args.warm_frames} 1-spp warm-up frames + one {n_spp}-spp frame, online training",
+                               f"{args.warm_frames} 1-spp warm-up frames + one {args.cached_spp}-spp frame, "
+                               "online training",
                    "reference": "oracle FP64 1024 spp, pixels x%16==0 and y%16==0",
                    "train_paths_per_batch": args.train_paths, "train_every": args.train_every,
-                   "records_per_batch": 4 << 14, "adam_steps": info["adam_steps"]},
-        "equal_rmse": {"rmse_cached": r_c, "plain_fit_a": a, "spp_plain_equivalent": spp_eq,
-                       "time_cached_s": t_total, "time_plain_equivalent_s": t_plain_eq,
-                       "speedup": t_plain_eq / t_total,
-                       "cached_samples_per_s": W * H * (n_spp + args.warm_frames) / t_total,
-                       "plain_samples_per_s": plain_rate,
-                       "rmse_cached_frame_inference_only": r_inf, "inference_only_frame_s": dt_inf},
-        "plain_curve": plain, "cached_frames": frames,
-        "cache_ms": st["cache_ms"], "train_batches": st["train_batches"], "cache_queries": st["cache_queries"],
+                   "records_per_batch": 4 << 14},
+        "equal_rmse": eq, "plain_curve": plain, "cached_frames": cached["frames"],
     }
     print(json.dumps(out), flush=True)
 
@@ -422,6 +463,15 @@ def main():
                      "nodes_per_ray": st["node_visits"] / max(1, st["ext_rays"] + st["shadow_rays"])},
         "scene_build_s": build_s,
     }
+    if args.workload == "church" and not args.no_cached:
+        # the cached half of the metric on the same view: the plain frame just timed (64 spp,
+        # seed 1) fixes a = RMSE_64 sqrt(64) of the plain estimator's RMSE = a / sqrt(spp)
+        px, ref = load_reference()
+        r64 = _rmse(img.cpu().numpy(), ref, px)
+        a = r64 * np.sqrt(cfg["spp"])
+        cached = run_cached(ctx, S, sc, cam, img, args, px, ref)
+        out["equal_rmse"] = equal_rmse(cached, a, value, cam.width, cam.height, args.warm_frames)
+        out["equal_rmse"]["rmse_plain_frame"] = r64
     if not args.no_cpu_baseline:
         threads = args.cpu_threads or min(16, os.cpu_count() or 1)
         out["cpu_baseline"] = cpu_baseline(sc, cam, cfg, threads)

@@ -356,8 +356,11 @@ typedef struct {
   uint64_t graph_launches;     /* graph-mode renders replayed                                 */
   double graph_ms;             /* HIP-event time of the graph launches (timing = 1)          */
   uint64_t cache_queries;      /* path vertices that took their radiance from the cache       */
+  uint64_t query_launches;     /* cache-query launches (one per wavefront of a cached render)  */
   uint64_t train_batches;      /* training batches (training paths + Adam steps) run          */
-  double cache_ms;             /* HIP-event time of cache queries and training (timing = 1)  */
+  double query_ms;             /* HIP-event time of the cache-query launches (timing = 1)     */
+  double train_ms;             /* HIP-event time of the training-batch finishing steps:
+                                  target gathering, compaction and Adam steps (timing = 1)  */
 } sdd_stats;
 
 /* Counters accumulated since the previous sdd_reset_stats (valid after sdd_finish). */

@@ -63,7 +63,8 @@ class Stats(C.Structure):
         "trace_launches", "shade_launches", "wavefronts", "err_cross_overflow", "err_nonfinite", "err_stack",
         "node_visits", "tri_tests")] + [
         ("trace_ms", C.c_double), ("shade_ms", C.c_double), ("graph_launches", C.c_uint64), ("graph_ms", C.c_double),
-        ("cache_queries", C.c_uint64), ("train_batches", C.c_uint64), ("cache_ms", C.c_double)]
+        ("cache_queries", C.c_uint64), ("query_launches", C.c_uint64), ("train_batches", C.c_uint64),
+        ("query_ms", C.c_double), ("train_ms", C.c_double)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

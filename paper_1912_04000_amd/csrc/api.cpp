@@ -277,9 +277,10 @@ int run_paths(sdd_ctx* ctx, const sdd_scene* scene, const sdd_render_params* p, 
     ctx->acc.shade_launches++;
     if (last) {
       if (query) {
-        if (timing) record(ctx, ctx->ev_cache, ctx->ev_used_cache, true);
+        if (timing) record(ctx, ctx->ev_query, ctx->ev_used_query, true);
         HIP_TRY(ctx, launch_cache_query(ctx->stream, cache->dev, S, w, d & 1));
-        if (timing) record(ctx, ctx->ev_cache, ctx->ev_used_cache, false);
+        if (timing) record(ctx, ctx->ev_query, ctx->ev_used_query, false);
+        ctx->acc.query_launches++;
       }
       rc = finish();
       if (rc) return rc;
@@ -322,12 +323,12 @@ int enqueue_frame(sdd_ctx* ctx, const sdd_scene* scene, const std::vector<ViewDe
       const PathMode train_mode{1u << 24, kCacheDepth, cache->dev.rx, cache->dev.rw};
       rc = run_paths(ctx, scene, p, L, S, w, cache->train_paths_done, nt, gen, timing, train_mode, cache,
                      [&]() -> int {
-                       if (timing) record(ctx, ctx->ev_cache, ctx->ev_used_cache, true);
+                       if (timing) record(ctx, ctx->ev_train, ctx->ev_used_train, true);
                        HIP_TRY(ctx, launch_cache_gather(ctx->stream, cache->dev, w, nt, B));
                        HIP_TRY(ctx, launch_cache_compact(ctx->stream, cache->dev, nt,
                                                          (uint32_t)tp->steps * (uint32_t)tp->step_records));
                        int r = cache_train_records(ctx, cache, B, tp->steps, tp->step_records);
-                       if (timing) record(ctx, ctx->ev_cache, ctx->ev_used_cache, false);
+                       if (timing) record(ctx, ctx->ev_train, ctx->ev_used_train, false);
                        return r;
                      });
       if (rc) return rc;
@@ -490,7 +491,8 @@ void sdd_destroy(sdd_ctx* c) {
   for (auto& p : c->ev_trace) { (void)hipEventDestroy(p.first); (void)hipEventDestroy(p.second); }
   for (auto& p : c->ev_shade) { (void)hipEventDestroy(p.first); (void)hipEventDestroy(p.second); }
   for (auto& p : c->ev_graph) { (void)hipEventDestroy(p.first); (void)hipEventDestroy(p.second); }
-  for (auto& p : c->ev_cache) { (void)hipEventDestroy(p.first); (void)hipEventDestroy(p.second); }
+  for (auto& p : c->ev_query) { (void)hipEventDestroy(p.first); (void)hipEventDestroy(p.second); }
+  for (auto& p : c->ev_train) { (void)hipEventDestroy(p.first); (void)hipEventDestroy(p.second); }
   if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
   if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
@@ -717,11 +719,15 @@ int sdd_finish(sdd_ctx* c) {
     float ms = 0;
     if (hipEventElapsedTime(&ms, c->ev_graph[i].first, c->ev_graph[i].second) == hipSuccess) c->acc.graph_ms += ms;
   }
-  for (size_t i = 0; i < c->ev_used_cache; ++i) {
+  for (size_t i = 0; i < c->ev_used_query; ++i) {
     float ms = 0;
-    if (hipEventElapsedTime(&ms, c->ev_cache[i].first, c->ev_cache[i].second) == hipSuccess) c->acc.cache_ms += ms;
+    if (hipEventElapsedTime(&ms, c->ev_query[i].first, c->ev_query[i].second) == hipSuccess) c->acc.query_ms += ms;
   }
-  c->ev_used_trace = c->ev_used_shade = c->ev_used_graph = c->ev_used_cache = 0;
+  for (size_t i = 0; i < c->ev_used_train; ++i) {
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, c->ev_train[i].first, c->ev_train[i].second) == hipSuccess) c->acc.train_ms += ms;
+  }
+  c->ev_used_trace = c->ev_used_shade = c->ev_used_graph = c->ev_used_query = c->ev_used_train = 0;
   return status;
 }
 

@@ -32,8 +32,8 @@ struct sdd_ctx {
   hipStream_t capture_stream = nullptr;   // own stream (default priority) used only to record graphs
   uint64_t graph_key = 0;
   uint64_t graph_trace_launches = 0, graph_shade_launches = 0, graph_wavefronts = 0;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_cache;
-  size_t ev_used_cache = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_query, ev_train;
+  size_t ev_used_query = 0, ev_used_train = 0;
 };
 
 struct sdd_cache {
