@@ -77,7 +77,7 @@ Plan make_plan(uint32_t W, int B, int n_cells, int n_views) {
   int tb = (int)std::min<size_t>(2048, std::max<size_t>(kXcds, want));
   tb = (tb + kXcds - 1) / kXcds * kXcds;
   p.trace_blocks = tb;
-  p.max_tiles = (uint32_t)(((size_t)2 * W + kTile - 1) / kTile + n_cells + 8);
+  p.max_tiles = (uint32_t)(((size_t)2 * W + kTile - 1) / kTile + (size_t)n_cells * kDirBins + 8);
   size_t sz[L_COUNT];
   sz[L_PIX] = 4ull * W;
   sz[L_SMP] = 4ull * W;
@@ -94,8 +94,8 @@ Plan make_plan(uint32_t W, int B, int n_cells, int n_views) {
   sz[L_LDST] = 8ull * W;
   sz[L_LRANK] = 8ull * W;
   sz[L_QUEUE] = 8ull * W;
-  sz[L_CCOUNT] = 8ull * n_cells;
-  sz[L_COFF] = 4ull * n_cells;
+  sz[L_CCOUNT] = 8ull * n_cells * kDirBins;
+  sz[L_COFF] = 4ull * n_cells * kDirBins;
   sz[L_TILES] = 16ull * p.max_tiles;
   sz[L_SPILL] = 4ull * (kMaxStack - kShortStack) * (size_t)tb * kWG;
   sz[L_CTL] = sizeof(Ctl);
@@ -303,7 +303,7 @@ int enqueue_frame(sdd_ctx* ctx, const sdd_scene* scene, const std::vector<ViewDe
   if (rc) return rc;
   for (auto& v : views) HIP_TRY(ctx, launch_fill_f32(ctx->stream, v.image, (size_t)B * v.width * v.height, 0.0f));
   HIP_TRY(ctx, launch_fill_u32(ctx->stream, (uint32_t*)w.ctl, offsetof(Ctl, st_paths) / 4, 0u));
-  HIP_TRY(ctx, launch_fill_u32(ctx->stream, w.ccount, 2ull * scene->hdr.n_cells, 0u));
+  HIP_TRY(ctx, launch_fill_u32(ctx->stream, w.ccount, 2ull * scene->hdr.n_cells * kDirBins, 0u));
   int gen = 0;
   const PathMode render_mode{0u, 0, nullptr, nullptr};
   uint64_t wavefront = 0;
@@ -646,7 +646,7 @@ static int query(sdd_ctx* c, const sdd_scene* s, const float* orig, const float*
   DevScene S = device_view(s);
   Launch L{c->stream, plan.trace_blocks};
   HIP_TRY(c, launch_fill_u32(c->stream, (uint32_t*)w.ctl, sizeof(Ctl) / 4, 0u));
-  HIP_TRY(c, launch_fill_u32(c->stream, w.ccount, 2ull * s->hdr.n_cells, 0u));
+  HIP_TRY(c, launch_fill_u32(c->stream, w.ccount, 2ull * s->hdr.n_cells * kDirBins, 0u));
   c->last_ctl = w.ctl;
   int gen = 0;
   for (int64_t a = 0; a < n; a += W) {

@@ -50,6 +50,20 @@ __device__ __forceinline__ uint4 philox(uint4 c, uint32_t k0, uint32_t k1) {
 }
 __device__ __forceinline__ float unif24(uint32_t x) { return (float)(x >> 8) * 0x1p-24f; }
 
+// Ray queues are keyed by (cell, direction bin): rays of one tile then share a cell, the signs of
+// their direction components and their dominant axis, which keeps the lanes of a wave on similar
+// BVH paths.
+__device__ __forceinline__ uint32_t dir_bin(F3 d) {
+  const uint32_t oct = (d.x < 0.0f ? 1u : 0u) | (d.y < 0.0f ? 2u : 0u) | (d.z < 0.0f ? 4u : 0u);
+  const float ax = fabsf(d.x), ay = fabsf(d.y), az = fabsf(d.z);
+  const uint32_t dom = (ax >= ay && ax >= az) ? 0u : (ay >= az ? 1u : 2u);
+  return oct * 3u + dom;
+}
+__device__ __forceinline__ uint32_t qkey(uint32_t cell, uint32_t dbin) { return cell * (uint32_t)kDirBins + dbin; }
+__device__ __forceinline__ uint32_t* ccount_of(const DevScene& S, const DevWS& w, int parity) {
+  return w.ccount + (size_t)parity * S.n_cells * kDirBins;
+}
+
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 __device__ __forceinline__ uint32_t count_below(uint64_t m) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));

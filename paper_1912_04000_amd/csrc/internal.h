@@ -19,6 +19,7 @@ constexpr int kMaxCross = 8;        // glass crossings recorded per shadow ray
 constexpr int kMaxBins = 128;
 constexpr int kMaxGrid = 64;
 constexpr int kXcds = 8;            // MI355X: 8 XCDs, workgroups dispatched round-robin
+constexpr int kDirBins = 24;        // ray queues per cell: direction octant x dominant axis
 constexpr uint32_t kBlocked = 0xFFFFFFFFu;
 constexpr uint32_t kFirstVisit = 0x80000000u;
 constexpr uint32_t kShadowBit = 0x80000000u;  // in the ray's slot word
@@ -106,6 +107,7 @@ struct Ctl {
   uint32_t list_count[2];   // produced (ray, cell, rank) entries per generation parity
   uint32_t n_queue;         // entries in the cell-sorted queue of the current round
   uint32_t n_tiles;         // tiles of the current round
+  uint32_t tile_next[8];    // per-XCD tile counters of the current round (reset by k_scan)
   uint32_t cat_count[2][8]; // finished-ray lists per bounce parity and category (kCats used)
   // statistics (accumulated until collected)
   unsigned long long st_paths, st_vertices, st_ext, st_shadow, st_visits, st_migr, st_escape, st_glass;

@@ -217,7 +217,7 @@ __global__ __launch_bounds__(kWG) void k_raygen(DevScene S, DevWS w, uint64_t k0
                                                 uint32_t key1, int gen, PathMode pm) {
   const uint32_t i = blockIdx.x * kWG + threadIdx.x;
   const bool valid = i < n;
-  uint32_t cell = kInvalidCell;
+  uint32_t cell = kInvalidCell, qdir = 0;
   if (valid) {
     const uint64_t k = k0 + i;
     int v = 0;
@@ -259,10 +259,11 @@ __global__ __launch_bounds__(kWG) void k_raygen(DevScene S, DevWS w, uint64_t k0
       l4[q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     }
     cell = start_cell(S, o, d);
+    qdir = dir_bin(d);
   }
   const int p = gen & 1;
-  wave_append(valid && cell != kInvalidCell, i | kFirstVisit, cell, &w.ctl->list_count[p],
-              w.ccount + (size_t)p * S.n_cells, w.lsrc, w.ldst, w.lrank);
+  wave_append(valid && cell != kInvalidCell, i | kFirstVisit, qkey(cell, qdir), &w.ctl->list_count[p],
+              ccount_of(S, w, p), w.lsrc, w.ldst, w.lrank);
   // camera rays that miss the grid box escape at once (bounce 1 lists, parity 1)
   wave_push(valid && cell == kInvalidCell && S.env_nonzero, i, &w.ctl->cat_count[1][kCatEscape],
             cat_list(w, 1, kCatEscape));
@@ -275,7 +276,7 @@ __global__ __launch_bounds__(kWG) void k_pack_rays(DevScene S, DevWS w, const fl
                                                    const int32_t* skip, uint32_t n, int shadow, int gen) {
   const uint32_t i = blockIdx.x * kWG + threadIdx.x;
   const bool valid = i < n;
-  uint32_t cell = kInvalidCell;
+  uint32_t cell = kInvalidCell, qdir = 0;
   uint32_t r = 0;
   if (valid) {
     const F3 o = f3(orig[3 * i], orig[3 * i + 1], orig[3 * i + 2]);
@@ -287,14 +288,15 @@ __global__ __launch_bounds__(kWG) void k_pack_rays(DevScene S, DevWS w, const fl
     const bool finite = isfinite(o.x) && isfinite(o.y) && isfinite(o.z) && isfinite(d.x) && isfinite(d.y) &&
                         isfinite(d.z) && (d.x != 0.0f || d.y != 0.0f || d.z != 0.0f);
     if (finite) cell = start_cell(S, o, d);
+    qdir = dir_bin(d);
     if (shadow)
       w.shcnt[i] = 0;
     else
       w.hit[i] = make_float4(INFINITY, __uint_as_float(0xFFFFFFFFu), 0.0f, 0.0f);
   }
   const int p = gen & 1;
-  wave_append(valid && cell != kInvalidCell, r | kFirstVisit, cell, &w.ctl->list_count[p],
-              w.ccount + (size_t)p * S.n_cells, w.lsrc, w.ldst, w.lrank);
+  wave_append(valid && cell != kInvalidCell, r | kFirstVisit, qkey(cell, qdir), &w.ctl->list_count[p],
+              ccount_of(S, w, p), w.lsrc, w.ldst, w.lrank);
 }
 
 __global__ void k_unpack_hits(DevWS w, uint32_t n, float* t, int32_t* id, float* u, float* v) {
@@ -335,8 +337,8 @@ constexpr int kScanThreads = 1024;
 __global__ __launch_bounds__(kScanThreads) void k_scan(DevScene S, DevWS w, int gen) {
   __shared__ uint32_t s_cnt[kScanThreads], s_til[kScanThreads];
   const int p = gen & 1;
-  const uint32_t* cnt = w.ccount + (size_t)p * S.n_cells;
-  const int nc = S.n_cells;
+  const uint32_t* cnt = ccount_of(S, w, p);
+  const int nc = S.n_cells * kDirBins;   // queue keys: (cell, direction octant)
   const int chunk = (nc + kScanThreads - 1) / kScanThreads;
   const int c0 = min(nc, (int)threadIdx.x * chunk), c1 = min(nc, c0 + chunk);
   uint32_t sc = 0, st = 0;
@@ -375,7 +377,8 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(DevScene S, DevWS w, int 
     w.ctl->n_tiles = s_til[kScanThreads - 1];
     w.ctl->list_count[p ^ 1] = 0;
   }
-  uint32_t* other = w.ccount + (size_t)(p ^ 1) * S.n_cells;
+  if (threadIdx.x < kXcds) w.ctl->tile_next[threadIdx.x] = 0;
+  uint32_t* other = ccount_of(S, w, p ^ 1);
   for (int c = threadIdx.x; c < nc; c += kScanThreads) other[c] = 0;
 }
 
@@ -599,20 +602,39 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
                                                                                                int cat_par) {
   __shared__ float4 s_nodes[kTopNodes * 4];
   __shared__ uint32_t s_stack[kShortStack * kWG];
+  __shared__ uint32_t s_next[2];
   const uint32_t n_tiles = w.ctl->n_tiles;
   const uint32_t xcd = blockIdx.x % kXcds;
-  const uint32_t per_xcd = gridDim.x / kXcds;
-  const uint32_t t_begin = (uint32_t)(((uint64_t)n_tiles * xcd) / kXcds);
-  const uint32_t t_end = (uint32_t)(((uint64_t)n_tiles * (xcd + 1)) / kXcds);
   const uint32_t gtid = blockIdx.x * kWG + threadIdx.x;
   uint32_t* spill = w.spill + gtid;
   uint32_t* stack = s_stack + threadIdx.x;
   const int np = (gen + 1) & 1;
   uint32_t n_visit = 0, n_migr = 0, n_esc = 0, n_glass = 0, n_xover = 0, n_nodes = 0, n_tris = 0;
   int prev_cell = -1;
-  for (uint32_t t = t_begin + blockIdx.x / kXcds; t < t_end; t += per_xcd) {
+  // Tiles are handed out dynamically: each XCD owns a contiguous range of the cell-sorted tiles
+  // (its L2 then holds few cells at a time) and its workgroups take the next tile of that range
+  // from a counter; a workgroup whose range is exhausted takes tiles from the other XCDs' ranges.
+  uint32_t donor = 0;   // thread 0 only: how many ranges it has exhausted
+  for (int it = 0;; ++it) {
+    if (threadIdx.x == 0) {
+      uint32_t t = 0xFFFFFFFFu;
+      for (; donor < (uint32_t)kXcds; ++donor) {
+        const uint32_t X = (xcd + donor) % kXcds;
+        const uint32_t b = (uint32_t)(((uint64_t)n_tiles * X) / kXcds);
+        const uint32_t e = (uint32_t)(((uint64_t)n_tiles * (X + 1)) / kXcds);
+        const uint32_t q = b + atomicAdd(&w.ctl->tile_next[X], 1u);
+        if (q < e) {
+          t = q;
+          break;
+        }
+      }
+      s_next[it & 1] = t;
+    }
+    __syncthreads();
+    const uint32_t t = s_next[it & 1];
+    if (t == 0xFFFFFFFFu) break;
     const uint4 tile = w.tiles[t];
-    const int tcell = (int)tile.x;
+    const int tcell = (int)(tile.x / kDirBins);
     const int4 tinfo = S.cells[tcell];
     const int n_top = min(tinfo.y, kTopNodes);
     if (tcell != prev_cell) {
@@ -706,7 +728,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
       if (!done) {
         requeue = true;
         out_src = r;
-        out_cell = (uint32_t)cell;
+        out_cell = qkey((uint32_t)cell, dir_bin(f3(rd.x, rd.y, rd.z)));
         ++n_migr;
       }
       cat_slot = slot;
@@ -714,8 +736,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
 #pragma unroll
     for (int c = 0; c < kCats; ++c)
       wave_push(cat == c, cat_slot, &w.ctl->cat_count[cat_par][c], cat_list(w, cat_par, c));
-    wave_append(requeue, out_src, out_cell, &w.ctl->list_count[np], w.ccount + (size_t)np * S.n_cells, w.lsrc, w.ldst,
-                w.lrank);
+    wave_append(requeue, out_src, out_cell, &w.ctl->list_count[np], ccount_of(S, w, np), w.lsrc, w.ldst, w.lrank);
   }
   wave_add(&w.ctl->st_visits, n_visit);
   wave_add(&w.ctl->st_migr, n_migr);
@@ -819,7 +840,7 @@ __global__ __launch_bounds__(kWG) void k_shade_opaque(DevScene S, DevWS w, int d
   const uint32_t n_iter = (n + kWG - 1) / kWG * kWG;
   for (uint32_t a = blockIdx.x * kWG + threadIdx.x; a < n_iter; a += gridDim.x * kWG) {
     const bool valid = a < n;
-    uint32_t s = 0, ext_cell = kInvalidCell, sh_cell = kInvalidCell;
+    uint32_t s = 0, ext_cell = kInvalidCell, sh_cell = kInvalidCell, ext_dir = 0, sh_dir = 0;
     bool has_sh = false, has_ext = false;
     if (valid) {
       s = list[a];
@@ -866,6 +887,7 @@ __global__ __launch_bounds__(kWG) void k_shade_opaque(DevScene S, DevWS w, int d
         w.rays[2 * (W + s) + 1] = make_float4(ws.x, ws.y, ws.z, __uint_as_float(s | kShadowBit));
         w.shcnt[s] = 0;
         sh_cell = start_cell(S, so, ws);
+        sh_dir = dir_bin(ws);
       }
       const float am = a_sum / (float)B, bm = b_sum / (float)B;
       if (depth < max_depth && am + bm > 0.0f) {
@@ -905,13 +927,14 @@ __global__ __launch_bounds__(kWG) void k_shade_opaque(DevScene S, DevWS w, int d
         w.rays[2 * s] = make_float4(no.x, no.y, no.z, __uint_as_float(V.id));
         w.rays[2 * s + 1] = make_float4(nd.x, nd.y, nd.z, __uint_as_float(s));
         ext_cell = start_cell(S, no, nd);
+        ext_dir = dir_bin(nd);
         if (ext_cell == kInvalidCell) w.hit[s] = make_float4(INFINITY, __uint_as_float(0xFFFFFFFFu), 0.0f, 0.0f);
       }
     }
-    wave_append(has_ext && ext_cell != kInvalidCell, s | kFirstVisit, ext_cell, &w.ctl->list_count[gp],
-                w.ccount + (size_t)gp * S.n_cells, w.lsrc, w.ldst, w.lrank);
-    wave_append(has_sh && sh_cell != kInvalidCell, ((uint32_t)W + s) | kFirstVisit, sh_cell, &w.ctl->list_count[gp],
-                w.ccount + (size_t)gp * S.n_cells, w.lsrc, w.ldst, w.lrank);
+    wave_append(has_ext && ext_cell != kInvalidCell, s | kFirstVisit, qkey(ext_cell, ext_dir), &w.ctl->list_count[gp],
+                ccount_of(S, w, gp), w.lsrc, w.ldst, w.lrank);
+    wave_append(has_sh && sh_cell != kInvalidCell, ((uint32_t)W + s) | kFirstVisit, qkey(sh_cell, sh_dir),
+                &w.ctl->list_count[gp], ccount_of(S, w, gp), w.lsrc, w.ldst, w.lrank);
     // rays that miss the grid box finish at once: straight into the next bounce's lists
     wave_push(has_sh && sh_cell == kInvalidCell, s, &w.ctl->cat_count[p ^ 1][kCatShadowClear],
               cat_list(w, p ^ 1, kCatShadowClear));
@@ -935,7 +958,7 @@ __global__ __launch_bounds__(kWG) void k_shade_glass(DevScene S, DevWS w, int de
   const uint32_t n_iter = (n + kWG - 1) / kWG * kWG;
   for (uint32_t a = blockIdx.x * kWG + threadIdx.x; a < n_iter; a += gridDim.x * kWG) {
     const bool valid = a < n;
-    uint32_t s = 0, ext_cell = kInvalidCell;
+    uint32_t s = 0, ext_cell = kInvalidCell, ext_dir = 0;
     if (valid) {
       s = list[a];
       const Vertex V = load_vertex(S, w, s);
@@ -967,10 +990,11 @@ __global__ __launch_bounds__(kWG) void k_shade_glass(DevScene S, DevWS w, int de
       w.rays[2 * s] = make_float4(no.x, no.y, no.z, __uint_as_float(V.id));
       w.rays[2 * s + 1] = make_float4(nd.x, nd.y, nd.z, __uint_as_float(s));
       ext_cell = start_cell(S, no, nd);
+      ext_dir = dir_bin(nd);
       if (ext_cell == kInvalidCell) w.hit[s] = make_float4(INFINITY, __uint_as_float(0xFFFFFFFFu), 0.0f, 0.0f);
     }
-    wave_append(valid && ext_cell != kInvalidCell, s | kFirstVisit, ext_cell, &w.ctl->list_count[gp],
-                w.ccount + (size_t)gp * S.n_cells, w.lsrc, w.ldst, w.lrank);
+    wave_append(valid && ext_cell != kInvalidCell, s | kFirstVisit, qkey(ext_cell, ext_dir), &w.ctl->list_count[gp],
+                ccount_of(S, w, gp), w.lsrc, w.ldst, w.lrank);
     wave_push(valid && ext_cell == kInvalidCell && S.env_nonzero, s, &w.ctl->cat_count[p ^ 1][kCatEscape],
               cat_list(w, p ^ 1, kCatEscape));
     wave_add(&w.ctl->st_vertices, valid ? 1u : 0u);
