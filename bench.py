@@ -46,7 +46,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="church", choices=["church", "nave", "batch", "cached"])
+    ap.add_argument("--workload", default="church", choices=["church", "nave", "batch", "cached", "large"])
     ap.add_argument("--cached-spp", type=int, default=64, help="cached workload: samples per pixel of the scored frame")
     ap.add_argument("--warm-frames", type=int, default=8, help="cached workload: 1-spp training frames before it")
     ap.add_argument("--train-paths", type=int, default=1 << 17, help="cached workload: training paths per batch")
@@ -332,6 +332,105 @@ def bench_cached(args):
     print(json.dumps(out), flush=True)
 
 
+def crop_camera(cam, cw, ch):
+    """The centred cw x ch window of a view as a camera of its own (same eye, axis and pixel
+    footprint): tan(vfov'/2) = tan(vfov/2) ch / H."""
+    import math
+    import scenegen
+    vf = 2.0 * math.degrees(math.atan(math.tan(math.radians(cam.vfov_deg) / 2.0) * ch / cam.height))
+    return scenegen.Camera(eye=cam.eye, target=cam.target, up=cam.up, vfov_deg=vf, width=cw, height=ch)
+
+
+def bench_large(args):
+    """C5: procedural church of ~10M triangles (200 windows), 80 bins (5 nm), 3840x2160, 16x8x8
+    cells, depth 8. Plain 256 spp against the cache-terminated path given the same wall time
+    (untrained cache, online training once per 1-spp pass, 32-spp chunks until the plain time is
+    used up). RMSE over the centred 960x540 window against a 1024-spp plain render of that window
+    (independent seed). value = plain samples/s of the 256-spp frame."""
+    import torch
+    import paper_1912_04000_amd as sd
+    import scenegen
+    t0 = time.perf_counter()
+    sc = scenegen.church_scene(n_bins=80, target_tris=10_000_000, n_bays=50, tiers=2)
+    cam = scenegen.church_camera(3840, 2160)
+    S = sd.Scene.from_description(sc, grid=(16, 8, 8))
+    build_s = time.perf_counter() - t0
+    B, W, H = sc.n_bins, cam.width, cam.height
+    ctx = sd.Context(0)
+    ctx.upload(S)
+    wave = 1 << 21
+    cw, ch = 960, 540
+    x0, y0 = (W - cw) // 2, (H - ch) // 2
+    cc = crop_camera(cam, cw, ch)
+    # reference: the window at 1024 spp, seed 0xC5
+    crop = sd.camera(cc.eye, cc.target, cc.up, cc.vfov_deg, cw, ch)
+    ref_img = torch.empty((B, ch, cw), dtype=torch.float32, device="cuda")
+    t_ref = _timed(lambda: ctx.render(S, crop, sd.render_params(spp=1024, max_depth=8, seed=0xC5, wave_paths=wave),
+                                      out=ref_img))
+    ref = ref_img.double().cpu().numpy()
+    del ref_img
+
+    def rmse_window(img):
+        sub = img[:, y0:y0 + ch, x0:x0 + cw].double().cpu().numpy()
+        return float(np.sqrt(np.mean((sub - ref) ** 2)))
+
+    c = sd.camera(cam.eye, cam.target, cam.up, cam.vfov_deg, W, H)
+    img = torch.empty((B, H, W), dtype=torch.float32, device="cuda")
+    ctx.render(S, c, sd.render_params(spp=1, max_depth=8, seed=7, wave_paths=wave), out=img)  # warm-up
+    spp_plain = 256
+    ctx.reset_stats()
+    t_plain = _timed(lambda: ctx.render(S, c, sd.render_params(spp=spp_plain, max_depth=8, seed=1, wave_paths=wave,
+                                                                timing=1), out=img))
+    st_plain = ctx.stats()
+    r_plain = rmse_window(img)
+    # cached, same wall time
+    lo = sc.verts.reshape(-1, 3).min(0) - 0.05
+    hi = sc.verts.reshape(-1, 3).max(0) + 0.05
+    cache = sd.Cache(ctx, sd.cache_config(len(sc.mat_type), lo, hi, max_bins=B, max_records=1 << 17,
+                                          max_step=1 << 14), seed=12345)
+    per_pass = (W * H + wave - 1) // wave
+    tp = sd.train_params(train_paths=1 << 17, step_records=1 << 14, steps=4, every=per_pass)
+    acc = torch.zeros((B, H, W), dtype=torch.float32, device="cuda")
+    chunk, done_spp, t_cached, chunks = 32, 0, 0.0, []
+    ctx.reset_stats()
+    while t_cached < t_plain:
+        dt = _timed(lambda: ctx.render_cached(S, cache, c, sd.render_params(spp=chunk, max_depth=8, seed=1,
+                                                                             mode=sd.MODE_CACHED, wave_paths=wave,
+                                                                             first_sample=done_spp, timing=1),
+                                              tp, out=img))
+        acc.mul_(done_spp / (done_spp + chunk)).add_(img, alpha=chunk / (done_spp + chunk))
+        done_spp += chunk
+        t_cached += dt
+        chunks.append(dict(spp=done_spp, seconds=t_cached))
+    st_c = ctx.stats()
+    r_cached = rmse_window(acc)
+    chunks[-1]["rmse"] = r_cached
+    # plain spp for the cached RMSE (RMSE ~ spp^-1/2 through the measured 256-spp point)
+    spp_eq = spp_plain * (r_plain / r_cached) ** 2
+    t_eq = t_plain * spp_eq / spp_plain
+    value = W * H * spp_plain / t_plain
+    out = {
+        "metric": METRIC, "value": value, "unit": "spectral path samples/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": t_plain * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 (tracer) / bf16 (cache MLP)", "data": f"synthetic (seeded procedural scene, {sc.n_tri} triangles)",
+        "config": {"workload": "church-10M large: 3840x2160, 80 bins 380-780 nm, depth 8, 16x8x8 cells, 200 windows; "
+                               "plain 256 spp vs cached at equal wall time",
+                   "triangles": sc.n_tri, "materials": len(sc.mat_type), "reference": "plain 1024 spp, centred "
+                   "960x540 window, seed 0xC5", "scene_build_s": build_s, "reference_s": t_ref},
+        "equal_time": {"plain_spp": spp_plain, "plain_s": t_plain, "rmse_plain": r_plain,
+                       "cached_spp": done_spp, "cached_s": t_cached, "rmse_cached": r_cached,
+                       "rmse_ratio_plain_over_cached": r_plain / r_cached,
+                       "spp_plain_equivalent": spp_eq, "time_plain_equivalent_s": t_eq,
+                       "speedup_at_equal_rmse": t_eq / t_cached,
+                       "adam_steps": cache.info()["adam_steps"], "train_batches": st_c["train_batches"]},
+        "timing_split_ms": {"plain_trace": st_plain["trace_ms"], "plain_shade": st_plain["shade_ms"],
+                            "cached_trace": st_c["trace_ms"], "cached_shade": st_c["shade_ms"],
+                            "cached_query": st_c["query_ms"], "cached_train_steps": st_c["train_ms"]},
+        "cached_chunks": chunks,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def bench_batch(args):
     """32 seeded views of the church with uneven resolutions (256x256 .. 1024x768) and spp (4..64),
     rendered together in one graph launch per step, with the grid, wavefront size and queue rounds
@@ -402,6 +501,9 @@ def main():
         return
     if args.workload == "cached":
         bench_cached(args)
+        return
+    if args.workload == "large":
+        bench_large(args)
         return
     import torch
     import paper_1912_04000_amd as sd

@@ -644,14 +644,16 @@ __global__ __launch_bounds__(kCWG) void k_cache_wgrad(CacheDev C, int B, uint32_
 }
 
 // Hash-grid and material-embedding gradients: scatter dE through the interpolation weights.
-// One thread per (vertex, level) of position and direction plus one for the material.
+// One thread per (level, vertex) of position and direction plus one per vertex for the
+// material; consecutive threads take consecutive vertices of one level, so the atomics of a
+// wave on a coarse level fall on few table entries.
 __global__ void k_cache_grid_bwd(CacheDev C, uint32_t v0, uint32_t step_max) {
   const uint32_t nv = step_range(C, v0, step_max);
   const int per = C.Lp + C.Ld + 1;
   const uint64_t total = (uint64_t)nv * per;
   for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (uint64_t)gridDim.x * blockDim.x) {
-    const uint32_t k = (uint32_t)(q / per);
-    const int l = (int)(q % per);
+    const uint32_t k = (uint32_t)(q % nv);
+    const int l = (int)(q / nv);
     const uint32_t slot = C.ridx[v0 + k];
     const float* de = C.dE + (size_t)k * kCacheWidth;
     if (l < C.Lp) {

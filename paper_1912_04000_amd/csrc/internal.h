@@ -11,7 +11,7 @@ namespace sdd {
 // Tunables fixed at compile time
 // ------------------------------------------------------------------------------------------
 constexpr int kWG = 256;            // threads per workgroup of the traversal/shading kernels
-constexpr int kTile = 256;          // rays of one cell handled by one workgroup tile
+constexpr int kTile = 256;          // rays of one queue key handled by one workgroup tile
 constexpr int kTopNodes = 32;       // top BVH nodes of a cell staged in LDS per tile
 constexpr int kShortStack = 12;     // traversal stack entries kept in LDS per thread
 constexpr int kMaxStack = 48;       // builder caps BVH depth so the stack never exceeds this

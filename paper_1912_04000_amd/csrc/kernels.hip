@@ -513,96 +513,110 @@ struct TraceState {
 // ray kinds (lanes of a wave may hold either): a closest-hit ray shrinks its far bound with every
 // accepted hit; a shadow ray keeps it, stops at the first opaque hit and records every glass
 // crossing. Both hit children that are leaves are tested in one triangle loop.
-__device__ void traverse_cell(const DevScene& S, const DevWS& w, const RayPre& R, bool shadow, int4 cinfo,
-                              const float4* lds_nodes, int n_lds, uint32_t* stack_lds, uint32_t* spill,
-                              uint32_t spill_stride, uint32_t skip, float t_lo, float t_hi, uint32_t slot,
-                              TraceState& st) {
-  const float4* gnodes = S.nodes + (size_t)cinfo.x * 4;
+// One node of a cell's BVH for one ray: the two child boxes are tested (robust slab test), leaf
+// triangles are tested in place (watertight test), the nearer inner child is visited next and
+// the farther one pushed (LDS short stack, then the global spill). Returns false when the cell's
+// traversal is finished: stack empty, or a shadow ray blocked by an opaque triangle.
+__device__ __forceinline__ bool trav_step(const DevScene& S, const DevWS& w, const RayPre& R, bool shadow, int4 cinfo,
+                                          const float4* lds_nodes, int n_lds, uint32_t* stack_lds, uint32_t* spill,
+                                          uint32_t spill_stride, uint32_t skip, float t_lo, float t_hi,
+                                          float box_lo, uint32_t slot, TraceState& st, uint32_t& node, int& sp) {
+  float4 na, nb, nc, nd;
+  if ((int)node < n_lds) {
+    na = lds_nodes[node * 4 + 0];
+    nb = lds_nodes[node * 4 + 1];
+    nc = lds_nodes[node * 4 + 2];
+    nd = lds_nodes[node * 4 + 3];
+  } else {
+    const float4* gnodes = S.nodes + (size_t)cinfo.x * 4;
+    na = gnodes[node * 4 + 0];
+    nb = gnodes[node * 4 + 1];
+    nc = gnodes[node * 4 + 2];
+    nd = gnodes[node * 4 + 3];
+  }
+  const uint32_t i0 = __float_as_uint(nd.x), i1 = __float_as_uint(nd.y);
+  const uint32_t c0 = __float_as_uint(nd.z), c1 = __float_as_uint(nd.w);
+  ++st.nodes;
+  bool h0, h1;
+  float t0, t1;
+  box2(R, na, nb, nc, box_lo, shadow ? t_hi : st.tbest, h0, t0, h1, t1);
+  h0 = h0 && i0 != kEmptyChild;
+  h1 = h1 && i1 != kEmptyChild;
+  const uint32_t la = (h0 && c0) ? c0 : 0u, lb = (h1 && c1) ? c1 : 0u;
+  if (la) h0 = false;
+  if (lb) h1 = false;
   const float4* ctris = S.ctris + (size_t)cinfo.z * 3;
-  const float box_lo = fmaxf(t_lo, 0.0f);
-  uint32_t node = 0;
-  int sp = 0;
-  for (;;) {
-    float4 na, nb, nc, nd;
-    if ((int)node < n_lds) {
-      na = lds_nodes[node * 4 + 0];
-      nb = lds_nodes[node * 4 + 1];
-      nc = lds_nodes[node * 4 + 2];
-      nd = lds_nodes[node * 4 + 3];
-    } else {
-      na = gnodes[node * 4 + 0];
-      nb = gnodes[node * 4 + 1];
-      nc = gnodes[node * 4 + 2];
-      nd = gnodes[node * 4 + 3];
-    }
-    const uint32_t i0 = __float_as_uint(nd.x), i1 = __float_as_uint(nd.y);
-    const uint32_t c0 = __float_as_uint(nd.z), c1 = __float_as_uint(nd.w);
-    ++st.nodes;
-    bool h0, h1;
-    float t0, t1;
-    box2(R, na, nb, nc, box_lo, shadow ? t_hi : st.tbest, h0, t0, h1, t1);
-    h0 = h0 && i0 != kEmptyChild;
-    h1 = h1 && i1 != kEmptyChild;
-    const uint32_t la = (h0 && c0) ? c0 : 0u, lb = (h1 && c1) ? c1 : 0u;
-    if (la) h0 = false;
-    if (lb) h1 = false;
-    for (uint32_t q = 0; q < la + lb; ++q) {
-      const uint32_t tri = q < la ? i0 + q : i1 + (q - la);
-      const float4 A = ctris[tri * 3 + 0], B = ctris[tri * 3 + 1], C = ctris[tri * 3 + 2];
-      const uint32_t id = __float_as_uint(A.w);
-      if (id == skip) continue;
-      ++st.tris;
-      float t, u, v;
-      if (!wt_test(R, f3(A.x, A.y, A.z), f3(B.x, B.y, B.z), f3(C.x, C.y, C.z), t, u, v)) continue;
-      if (!(t > 0.0f && t >= t_lo && t < t_hi)) continue;
-      if (shadow) {
-        const int m = (int)__float_as_uint(B.w);
-        if (S.mtype[m] == 0) {
-          st.blocked = true;
-          return;
-        }
-        const F3 ng = geo_normal(f3(A.x, A.y, A.z), f3(B.x, B.y, B.z), f3(C.x, C.y, C.z));
-        if (st.ncross < (uint32_t)kMaxCross)
-          w.shx[(size_t)st.ncross * w.W + slot] = make_float2(__int_as_float(m), fabsf(dot3(R.d, ng)));
-        st.ncross++;
-      } else if (t < st.tbest || (t == st.tbest && id < st.best_id)) {
-        st.tbest = t;
-        st.best_id = id;
-        st.best_mat = __float_as_uint(B.w);
-        st.bu = u;
-        st.bv = v;
+  for (uint32_t q = 0; q < la + lb; ++q) {
+    const uint32_t tri = q < la ? i0 + q : i1 + (q - la);
+    const float4 A = ctris[tri * 3 + 0], B = ctris[tri * 3 + 1], C = ctris[tri * 3 + 2];
+    const uint32_t id = __float_as_uint(A.w);
+    if (id == skip) continue;
+    ++st.tris;
+    float t, u, v;
+    if (!wt_test(R, f3(A.x, A.y, A.z), f3(B.x, B.y, B.z), f3(C.x, C.y, C.z), t, u, v)) continue;
+    if (!(t > 0.0f && t >= t_lo && t < t_hi)) continue;
+    if (shadow) {
+      const int m = (int)__float_as_uint(B.w);
+      if (S.mtype[m] == 0) {
+        st.blocked = true;
+        return false;
       }
-    }
-    if (!shadow) {
-      h0 = h0 && t0 <= st.tbest;
-      h1 = h1 && t1 <= st.tbest;
-    }
-    if (h0 && h1) {
-      const bool first0 = t0 <= t1;
-      const uint32_t near = first0 ? i0 : i1, far = first0 ? i1 : i0;
-      if (sp < kShortStack)
-        stack_lds[sp * kWG] = far;
-      else
-        spill[(size_t)(sp - kShortStack) * spill_stride] = far;
-      ++sp;
-      node = near;
-    } else if (h0) {
-      node = i0;
-    } else if (h1) {
-      node = i1;
-    } else {
-      if (sp == 0) break;
-      --sp;
-      node = sp < kShortStack ? stack_lds[sp * kWG] : spill[(size_t)(sp - kShortStack) * spill_stride];
+      const F3 ng = geo_normal(f3(A.x, A.y, A.z), f3(B.x, B.y, B.z), f3(C.x, C.y, C.z));
+      if (st.ncross < (uint32_t)kMaxCross)
+        w.shx[(size_t)st.ncross * w.W + slot] = make_float2(__int_as_float(m), fabsf(dot3(R.d, ng)));
+      st.ncross++;
+    } else if (t < st.tbest || (t == st.tbest && id < st.best_id)) {
+      st.tbest = t;
+      st.best_id = id;
+      st.best_mat = __float_as_uint(B.w);
+      st.bu = u;
+      st.bv = v;
     }
   }
+  if (!shadow) {
+    h0 = h0 && t0 <= st.tbest;
+    h1 = h1 && t1 <= st.tbest;
+  }
+  if (h0 && h1) {
+    const bool first0 = t0 <= t1;
+    const uint32_t near = first0 ? i0 : i1, far = first0 ? i1 : i0;
+    if (sp < kShortStack)
+      stack_lds[sp * kWG] = far;
+    else
+      spill[(size_t)(sp - kShortStack) * spill_stride] = far;
+    ++sp;
+    node = near;
+  } else if (h0) {
+    node = i0;
+  } else if (h1) {
+    node = i1;
+  } else {
+    if (sp == 0) return false;
+    --sp;
+    node = sp < kShortStack ? stack_lds[sp * kWG] : spill[(size_t)(sp - kShortStack) * spill_stride];
+  }
+  return true;
 }
 
+// Lane phases of k_trace.
+enum : int { kLaneIdle = 0, kLaneEnter = 1, kLaneTrav = 2, kLaneLeave = 3, kLaneDone = 4 };
+
+// One tile = up to kTile rays of one queue key (cell, direction bin). The 256 lanes of the
+// workgroup each hold one ray at a time and take the next ray of the tile as soon as theirs is
+// finished, so a wave does not wait for its slowest ray; a lane steps one BVH node per loop
+// iteration. A ray's cell is traversed inside the cell's half-open slab interval; in every round
+// but the last the ray then migrates to the queue of the next cell, in the last round it walks
+// on in place. Finished rays go to LDS lists that the workgroup flushes to the global category
+// lists and the migration list once the tile is drained.
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k_trace(DevScene S, DevWS w, int gen, int hops,
                                                                                                int cat_par) {
   __shared__ float4 s_nodes[kTopNodes * 4];
   __shared__ uint32_t s_stack[kShortStack * kWG];
   __shared__ uint32_t s_next[2];
+  __shared__ uint32_t s_fetch, s_ncat, s_nreq;
+  __shared__ uint32_t s_cslot[kTile];
+  __shared__ uint8_t s_ccat[kTile];
+  __shared__ uint32_t s_rsrc[kTile], s_rkey[kTile];
   const uint32_t n_tiles = w.ctl->n_tiles;
   const uint32_t xcd = blockIdx.x % kXcds;
   const uint32_t gtid = blockIdx.x * kWG + threadIdx.x;
@@ -629,114 +643,182 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
         }
       }
       s_next[it & 1] = t;
+      s_fetch = 0;
+      s_ncat = 0;
+      s_nreq = 0;
     }
     __syncthreads();
     const uint32_t t = s_next[it & 1];
     if (t == 0xFFFFFFFFu) break;
     const uint4 tile = w.tiles[t];
     const int tcell = (int)(tile.x / kDirBins);
+    const uint32_t tdir = tile.x % kDirBins;
     const int4 tinfo = S.cells[tcell];
     const int n_top = min(tinfo.y, kTopNodes);
     if (tcell != prev_cell) {
-      __syncthreads();
       for (int q = threadIdx.x; q < n_top * 4; q += kWG) s_nodes[q] = S.nodes[(size_t)tinfo.x * 4 + q];
       __syncthreads();
       prev_cell = tcell;
     }
-    const bool active = threadIdx.x < tile.z;
-    bool requeue = false;
-    uint32_t out_src = 0, out_cell = 0;
-    int cat = -1;
-    uint32_t cat_slot = 0;
-    if (active) {
-      const uint32_t entry = w.queue[tile.y + threadIdx.x];
-      const uint32_t r = entry & ~kFirstVisit;
-      bool first = (entry & kFirstVisit) != 0;
-      const float4 ro = w.rays[2 * r], rd = w.rays[2 * r + 1];
-      const uint32_t skip = __float_as_uint(ro.w);
-      const uint32_t sw = __float_as_uint(rd.w);
-      const bool shadow = (sw & kShadowBit) != 0;
-      const uint32_t slot = sw & ~kShadowBit;
-      const RayPre R = make_pre(f3(ro.x, ro.y, ro.z), f3(rd.x, rd.y, rd.z));
-      int cell = tcell;
-      int ix = cell % S.gx, iy = (cell / S.gx) % S.gy, iz = cell / (S.gx * S.gy);
-      TraceState st;
-      st.tbest = INFINITY;
-      st.best_id = 0xFFFFFFFFu;
-      st.best_mat = 0;
-      st.bu = st.bv = 0.0f;
-      st.blocked = false;
-      st.ncross = shadow ? w.shcnt[slot] : 0u;
-      st.nodes = 0;
-      st.tris = 0;
-      const uint32_t ncross0 = st.ncross;
-      bool done = false;
-      for (int h = 0; h < hops; ++h) {
-        float tn, tf;
-        int axis;
+    int phase = kLaneIdle;
+    RayPre R;
+    R.o = R.d = R.inv = f3(0.0f, 0.0f, 0.0f);
+    R.kx = R.ky = R.kz = 0;
+    R.Sx = R.Sy = R.Sz = 0.0f;
+    uint32_t r = 0, slot = 0, skip = 0, node = 0, ncross0 = 0;
+    bool shadow = false, first = false;
+    int ix = 0, iy = 0, iz = 0, cell = 0, h = 0, sp = 0, axis = 0, nl = 0;
+    float t_lo = 0.0f, tf = 0.0f, box_lo = 0.0f;
+    int4 cinfo = make_int4(0, 0, 0, 0);
+    TraceState st;
+    st.tbest = INFINITY;
+    st.best_id = 0xFFFFFFFFu;
+    st.best_mat = 0;
+    st.bu = st.bv = 0.0f;
+    st.blocked = false;
+    st.ncross = 0;
+    st.nodes = 0;
+    st.tris = 0;
+    for (;;) {
+      if (phase == kLaneIdle) {
+        const uint32_t i = atomicAdd(&s_fetch, 1u);
+        if (i < tile.z) {
+          const uint32_t entry = w.queue[tile.y + i];
+          r = entry & ~kFirstVisit;
+          first = (entry & kFirstVisit) != 0;
+          const float4 ro = w.rays[2 * r], rd = w.rays[2 * r + 1];
+          skip = __float_as_uint(ro.w);
+          const uint32_t sw = __float_as_uint(rd.w);
+          shadow = (sw & kShadowBit) != 0;
+          slot = sw & ~kShadowBit;
+          R = make_pre(f3(ro.x, ro.y, ro.z), f3(rd.x, rd.y, rd.z));
+          cell = tcell;
+          ix = cell % S.gx;
+          iy = (cell / S.gx) % S.gy;
+          iz = cell / (S.gx * S.gy);
+          h = 0;
+          st.tbest = INFINITY;
+          st.best_id = 0xFFFFFFFFu;
+          st.best_mat = 0;
+          st.bu = st.bv = 0.0f;
+          st.blocked = false;
+          st.ncross = shadow ? w.shcnt[slot] : 0u;
+          ncross0 = st.ncross;
+          phase = kLaneEnter;
+        } else {
+          phase = kLaneDone;
+        }
+      }
+      if (__ballot(phase != kLaneDone) == 0) break;
+      bool fin = false, out_req = false;
+      int out_cat = -1;
+      if (phase == kLaneEnter) {
+        // the cell's slab interval; traversal starts unless the cell is empty or already passed
+        float tn;
         cell_interval(S, ix, iy, iz, R.o, R.d, R.inv, tn, tf, axis);
-        const float t_lo = first ? -INFINITY : tn;
-        const int4 cinfo = h == 0 ? tinfo : S.cells[cell];
+        t_lo = first ? -INFINITY : tn;
+        cinfo = cell == tcell ? tinfo : S.cells[cell];
         ++n_visit;
         if (cinfo.y > 0 && t_lo < tf) {
-          const int nl = h == 0 ? n_top : 0;
+          nl = cell == tcell ? n_top : 0;
           if (!shadow) st.tbest = tf;
-          traverse_cell(S, w, R, shadow, cinfo, s_nodes, nl, stack, spill, w.trace_threads, skip, t_lo, tf, slot, st);
+          box_lo = fmaxf(t_lo, 0.0f);
+          node = 0;
+          sp = 0;
+          phase = kLaneTrav;
+        } else {
+          phase = kLaneLeave;
+        }
+      }
+      if (phase == kLaneTrav) {
+        if (!trav_step(S, w, R, shadow, cinfo, s_nodes, nl, stack, spill, w.trace_threads, skip, t_lo, tf, box_lo,
+                       slot, st, node, sp)) {
           if (shadow && st.blocked) {
             w.shcnt[slot] = kBlocked;
-            done = true;
-            break;
-          }
-          if (!shadow && st.best_id != 0xFFFFFFFFu) {
+            fin = true;
+          } else if (!shadow && st.best_id != 0xFFFFFFFFu) {
             const float4* g = S.gtris + (size_t)st.best_id * 3;
             const float4 A = g[0], Bq = g[1], Cq = g[2];
             refine_hit(R.o, R.d, f3(A.x, A.y, A.z), f3(Bq.x, Bq.y, Bq.z), f3(Cq.x, Cq.y, Cq.z), st.tbest, st.bu,
                        st.bv);
             w.hit[slot] = make_float4(st.tbest, __uint_as_float(st.best_id), st.bu, st.bv);
-            cat = S.mtype[st.best_mat] == 0 ? kCatOpaque : kCatGlass;
-            done = true;
-            break;
+            out_cat = S.mtype[st.best_mat] == 0 ? kCatOpaque : kCatGlass;
+            fin = true;
+          } else {
+            phase = kLaneLeave;
           }
         }
+      }
+      if (phase == kLaneLeave) {
         // leave through the exit face (Amanatides-Woo step)
         const float dc = comp(R.d, axis);
         int* idx = axis == 0 ? &ix : (axis == 1 ? &iy : &iz);
         const int g = axis == 0 ? S.gx : (axis == 1 ? S.gy : S.gz);
         *idx += dc > 0.0f ? 1 : -1;
+        ++h;
         if (*idx < 0 || *idx >= g || !(tf < INFINITY)) {
-          // escaped the grid
           if (!shadow) {
             w.hit[slot] = make_float4(INFINITY, __uint_as_float(0xFFFFFFFFu), 0.0f, 0.0f);
-            if (S.env_nonzero) cat = kCatEscape;
+            if (S.env_nonzero) out_cat = kCatEscape;
           } else {
-            cat = st.ncross > 0 ? kCatShadowGlass : kCatShadowClear;
+            out_cat = st.ncross > 0 ? kCatShadowGlass : kCatShadowClear;
           }
           ++n_esc;
-          done = true;
-          break;
+          fin = true;
+        } else {
+          cell = (iz * S.gy + iy) * S.gx + ix;
+          first = false;
+          if (h < hops) {
+            phase = kLaneEnter;
+          } else {
+            out_req = true;
+            ++n_migr;
+            fin = true;
+          }
         }
-        cell = (iz * S.gy + iy) * S.gx + ix;
-        first = false;
       }
-      if (shadow && st.ncross != ncross0 && !st.blocked) {
-        n_glass += st.ncross - ncross0;
-        if (st.ncross > (uint32_t)kMaxCross && ncross0 <= (uint32_t)kMaxCross) ++n_xover;
-        w.shcnt[slot] = st.ncross;
+      if (fin) {
+        if (shadow && !st.blocked && st.ncross != ncross0) {
+          n_glass += st.ncross - ncross0;
+          if (st.ncross > (uint32_t)kMaxCross && ncross0 <= (uint32_t)kMaxCross) ++n_xover;
+          w.shcnt[slot] = st.ncross;
+        }
+        if (out_cat >= 0) {
+          const uint32_t c = atomicAdd(&s_ncat, 1u);
+          s_cslot[c] = slot;
+          s_ccat[c] = (uint8_t)out_cat;
+        }
+        if (out_req) {
+          const uint32_t q = atomicAdd(&s_nreq, 1u);
+          s_rsrc[q] = r;
+          s_rkey[q] = qkey((uint32_t)cell, tdir);
+        }
+        n_nodes += st.nodes;
+        n_tris += st.tris;
+        st.nodes = 0;
+        st.tris = 0;
+        phase = kLaneIdle;
       }
-      n_nodes += st.nodes;
-      n_tris += st.tris;
-      if (!done) {
-        requeue = true;
-        out_src = r;
-        out_cell = qkey((uint32_t)cell, dir_bin(f3(rd.x, rd.y, rd.z)));
-        ++n_migr;
-      }
-      cat_slot = slot;
     }
+    // the tile is drained: flush its finished rays (wave-aggregated atomics on the global lists)
+    __syncthreads();
+    const uint32_t nc = s_ncat, nr = s_nreq;
+    for (uint32_t b0 = 0; b0 < nc; b0 += kWG) {
+      const uint32_t e = b0 + threadIdx.x;
+      const bool v = e < nc;
+      const uint32_t sl = v ? s_cslot[e] : 0u;
+      const int c = v ? (int)s_ccat[e] : -1;
 #pragma unroll
-    for (int c = 0; c < kCats; ++c)
-      wave_push(cat == c, cat_slot, &w.ctl->cat_count[cat_par][c], cat_list(w, cat_par, c));
-    wave_append(requeue, out_src, out_cell, &w.ctl->list_count[np], ccount_of(S, w, np), w.lsrc, w.ldst, w.lrank);
+      for (int cc = 0; cc < kCats; ++cc)
+        wave_push(c == cc, sl, &w.ctl->cat_count[cat_par][cc], cat_list(w, cat_par, cc));
+    }
+    for (uint32_t b0 = 0; b0 < nr; b0 += kWG) {
+      const uint32_t e = b0 + threadIdx.x;
+      const bool v = e < nr;
+      wave_append(v, v ? s_rsrc[e] : 0u, v ? s_rkey[e] : 0u, &w.ctl->list_count[np], ccount_of(S, w, np), w.lsrc,
+                  w.ldst, w.lrank);
+    }
+    __syncthreads();
   }
   wave_add(&w.ctl->st_visits, n_visit);
   wave_add(&w.ctl->st_migr, n_migr);
