@@ -50,7 +50,8 @@ def parse():
     ap.add_argument("--cached-spp", type=int, default=64, help="cached workload: samples per pixel of the scored frame")
     ap.add_argument("--warm-frames", type=int, default=8, help="cached workload: 1-spp training frames before it")
     ap.add_argument("--train-paths", type=int, default=1 << 17, help="cached workload: training paths per batch")
-    ap.add_argument("--train-every", type=int, default=1, help="cached workload: wavefronts between batches")
+    ap.add_argument("--train-every", type=int, default=0,
+                    help="cached path: wavefronts between training batches (0: one batch per frame)")
     ap.add_argument("--tune-cache", default=os.path.join(os.path.expanduser("~"), ".cache", "specdd",
                                                           "tune_cache.json"))
     ap.add_argument("--spp", type=int, default=None, help="override samples per pixel (profiling runs)")
@@ -217,9 +218,10 @@ def _timed(fn):
 
 
 def run_cached(ctx, S, sc, cam, img, args, px, ref, wave=1 << 21):
-    """The cache-terminated path on the church view: an untrained cache, warm_frames 1-spp frames
-    with online training, then one scored frame of cached_spp samples (training on), all timed;
-    then the same frame again with training off (inference-only throughput)."""
+    """The cache-terminated path on the church view: an untrained cache, warm_frames 1-spp frames,
+    then one scored frame of cached_spp samples, all timed; every frame (render call) trains the
+    cache once on 2^16 records (--train-every 0). Then the scored frame again with training off
+    (inference-only throughput, the steady state of a converged cache)."""
     import paper_1912_04000_amd as sd
     B, W, H = sc.n_bins, cam.width, cam.height
     c = sd.camera(cam.eye, cam.target, cam.up, cam.vfov_deg, W, H)
@@ -286,9 +288,9 @@ def bench_cached(args):
     church-1M view (the C2 frame, 40 bins, depth 8). Both are scored by RMSE against the
     oracle's FP64 1024-spp reference on the pixel subset x % 16 == 0, y % 16 == 0
     (tests/golden/c4_reference.npz). Plain: RMSE at spp = 1 .. 64 gives the least-squares fit
-    RMSE = a / sqrt(spp) and the frame rate. Cached: the cache starts untrained, is trained
-    online during warm_frames 1-spp frames and the scored frame (2^16 records per training
-    batch, 4 Adam steps of 2^14, lr 1e-3); the time of every warm-up and scored frame counts.
+    RMSE = a / sqrt(spp) and the frame rate. Cached: the cache starts untrained and is trained
+    online once per frame (2^16 records, 4 Adam steps of 2^14, lr 1e-3) during warm_frames 1-spp
+    frames and the scored frame; the time of every warm-up and scored frame counts.
     value = W H spp_eq / time_cached, with spp_eq = (a / RMSE_cached)^2 the plain samples per
     pixel that reach the cached frame's RMSE: plain-equivalent samples per second."""
     import torch
@@ -323,7 +325,7 @@ def bench_cached(args):
         "data": f"synthetic (seeded procedural scene, {sc.n_tri} triangles)",
         "config": {"workload": "church-1M cached vs plain at equal RMSE: 1920x1080, 40 bins, depth 8, cache at vertex 3, "
                                f"{args.warm_frames} 1-spp warm-up frames + one {args.cached_spp}-spp frame, "
-                               "online training",
+                               "online training once per frame",
                    "reference": "oracle FP64 1024 spp, pixels x%16==0 and y%16==0",
                    "train_paths_per_batch": args.train_paths, "train_every": args.train_every,
                    "records_per_batch": 4 << 14},
@@ -344,9 +346,10 @@ def crop_camera(cam, cw, ch):
 def bench_large(args):
     """C5: procedural church of ~10M triangles (200 windows), 80 bins (5 nm), 3840x2160, 16x8x8
     cells, depth 8. Plain 256 spp against the cache-terminated path given the same wall time
-    (untrained cache, online training once per 1-spp pass, 32-spp chunks until the plain time is
-    used up). RMSE over the centred 960x540 window against a 1024-spp plain render of that window
-    (independent seed). value = plain samples/s of the 256-spp frame."""
+    (untrained cache; eight 1-spp frames, then 32-spp frames until the plain time is used up;
+    every frame trains the cache once on 2^16 records). RMSE over the centred 960x540 window
+    against a 1024-spp plain render of that window (independent seed). value = plain samples/s
+    of the 256-spp frame."""
     import torch
     import paper_1912_04000_amd as sd
     import scenegen
@@ -388,12 +391,12 @@ def bench_large(args):
     hi = sc.verts.reshape(-1, 3).max(0) + 0.05
     cache = sd.Cache(ctx, sd.cache_config(len(sc.mat_type), lo, hi, max_bins=B, max_records=1 << 17,
                                           max_step=1 << 14), seed=12345)
-    per_pass = (W * H + wave - 1) // wave
-    tp = sd.train_params(train_paths=1 << 17, step_records=1 << 14, steps=4, every=per_pass)
+    tp = sd.train_params(train_paths=1 << 17, step_records=1 << 14, steps=4, every=0)
     acc = torch.zeros((B, H, W), dtype=torch.float32, device="cuda")
-    chunk, done_spp, t_cached, chunks = 32, 0, 0.0, []
+    chunk, done_spp, t_cached, chunks = 1, 0, 0.0, []
     ctx.reset_stats()
     while t_cached < t_plain:
+        chunk = 1 if len(chunks) < 8 else 32
         dt = _timed(lambda: ctx.render_cached(S, cache, c, sd.render_params(spp=chunk, max_depth=8, seed=1,
                                                                              mode=sd.MODE_CACHED, wave_paths=wave,
                                                                              first_sample=done_spp, timing=1),

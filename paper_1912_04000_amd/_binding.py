@@ -287,7 +287,7 @@ def cache_config(n_mat, box_lo, box_hi, levels_pos=12, log2_table_pos=19, nmin_p
     return c
 
 
-def train_params(train_paths=0, step_records=1 << 14, steps=4, every=1) -> TrainParams:
+def train_params(train_paths=0, step_records=1 << 14, steps=4, every=0) -> TrainParams:
     t = TrainParams()
     t.train_paths, t.step_records, t.steps, t.every = int(train_paths), int(step_records), int(steps), int(every)
     return t

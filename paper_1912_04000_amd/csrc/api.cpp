@@ -317,7 +317,8 @@ int enqueue_frame(sdd_ctx* ctx, const sdd_scene* scene, const std::vector<ViewDe
     });
     if (rc) return rc;
     ctx->acc.wavefronts++;
-    if (cache && tp && tp->train_paths > 0 && wavefront % (uint64_t)tp->every == 0) {
+    if (cache && tp && tp->train_paths > 0 &&
+        (tp->every > 0 ? wavefront % (uint64_t)tp->every == 0 : wavefront == 0)) {
       // training batch: full-depth paths recording their third vertex, then Adam steps
       const uint32_t nt = (uint32_t)tp->train_paths;
       const PathMode train_mode{1u << 24, kCacheDepth, cache->dev.rx, cache->dev.rw};
@@ -607,7 +608,7 @@ int sdd_render_cached(sdd_ctx* c, const sdd_scene* s, sdd_cache* k, const sdd_ca
       return fail(c, SDD_ERR_INVALID_ARG, "train_paths must lie in 0..min(wave paths, max_records)");
     if (tp->step_records < kCacheVerts || tp->step_records > k->cfg.max_step)
       return fail(c, SDD_ERR_INVALID_ARG, "step_records must lie in 32..max_step");
-    if (tp->steps < 1 || tp->every < 1) return fail(c, SDD_ERR_INVALID_ARG, "steps and every must be >= 1");
+    if (tp->steps < 1 || tp->every < 0) return fail(c, SDD_ERR_INVALID_ARG, "steps must be >= 1 and every >= 0");
     if (p->max_depth <= kCacheDepth)
       return fail(c, SDD_ERR_INVALID_ARG, "training paths need max_depth >= 4 (they continue past the cached vertex)");
   }
