@@ -25,6 +25,11 @@ constexpr uint32_t kFirstVisit = 0x80000000u;
 constexpr uint32_t kShadowBit = 0x80000000u;  // in the ray's slot word
 constexpr uint32_t kInvalidCell = 0xFFFFFFFFu;
 constexpr uint32_t kEmptyChild = 0xFFFFFFFFu;
+// Traversal stack entries: an inner node index, or a leaf as flag | count << 27 | first triangle.
+constexpr uint32_t kStackLeaf = 0x80000000u;
+constexpr uint32_t kStackLeafMaxCount = 15u;
+constexpr uint32_t kStackLeafMaxIndex = (1u << 27) - 1u;
+constexpr uint32_t kNoNode = 0xFFFFFFFFu;
 
 // Categories of finished rays: the traversal sorts every ray it finishes into one list per
 // category so that each shading kernel runs one branch only (no divergence between kinds).

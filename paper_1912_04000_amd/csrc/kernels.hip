@@ -513,14 +513,58 @@ struct TraceState {
 // ray kinds (lanes of a wave may hold either): a closest-hit ray shrinks its far bound with every
 // accepted hit; a shadow ray keeps it, stops at the first opaque hit and records every glass
 // crossing. Both hit children that are leaves are tested in one triangle loop.
-// One node of a cell's BVH for one ray: the two child boxes are tested (robust slab test), leaf
-// triangles are tested in place (watertight test), the nearer inner child is visited next and
-// the farther one pushed (LDS short stack, then the global spill). Returns false when the cell's
-// traversal is finished: stack empty, or a shadow ray blocked by an opaque triangle.
+// One unit of traversal work for one ray in a cell's BVH: either one triangle of a pending leaf
+// (watertight test) or one node (both child boxes, robust slab test). A node visit makes the
+// nearer hit inner child the next node and pushes the farther one; a hit leaf child becomes the
+// pending leaf (a second one is pushed as a leaf entry). Doing one unit per step keeps the
+// lanes of a wave on the same kind of work. Returns false when the cell's traversal is
+// finished: nothing pending and the stack empty, or a shadow ray blocked by an opaque triangle.
 __device__ __forceinline__ bool trav_step(const DevScene& S, const DevWS& w, const RayPre& R, bool shadow, int4 cinfo,
                                           const float4* lds_nodes, int n_lds, uint32_t* stack_lds, uint32_t* spill,
                                           uint32_t spill_stride, uint32_t skip, float t_lo, float t_hi,
-                                          float box_lo, uint32_t slot, TraceState& st, uint32_t& node, int& sp) {
+                                          float box_lo, uint32_t slot, TraceState& st, uint32_t& node, int& sp,
+                                          uint32_t& pend_idx, uint32_t& pend_cnt) {
+  if (pend_cnt == 0 && node == kNoNode) {
+    if (sp == 0) return false;
+    --sp;
+    const uint32_t e = sp < kShortStack ? stack_lds[sp * kWG] : spill[(size_t)(sp - kShortStack) * spill_stride];
+    if (e & kStackLeaf) {
+      pend_idx = e & kStackLeafMaxIndex;
+      pend_cnt = (e >> 27) & kStackLeafMaxCount;
+    } else {
+      node = e;
+    }
+  }
+  if (pend_cnt > 0) {
+    const float4* ctris = S.ctris + (size_t)cinfo.z * 3;
+    const uint32_t tri = pend_idx++;
+    --pend_cnt;
+    const float4 A = ctris[tri * 3 + 0], B = ctris[tri * 3 + 1], C = ctris[tri * 3 + 2];
+    const uint32_t id = __float_as_uint(A.w);
+    if (id == skip) return true;
+    ++st.tris;
+    float t, u, v;
+    if (!wt_test(R, f3(A.x, A.y, A.z), f3(B.x, B.y, B.z), f3(C.x, C.y, C.z), t, u, v)) return true;
+    if (!(t > 0.0f && t >= t_lo && t < t_hi)) return true;
+    if (shadow) {
+      const int m = (int)__float_as_uint(B.w);
+      if (S.mtype[m] == 0) {
+        st.blocked = true;
+        return false;
+      }
+      const F3 ng = geo_normal(f3(A.x, A.y, A.z), f3(B.x, B.y, B.z), f3(C.x, C.y, C.z));
+      if (st.ncross < (uint32_t)kMaxCross)
+        w.shx[(size_t)st.ncross * w.W + slot] = make_float2(__int_as_float(m), fabsf(dot3(R.d, ng)));
+      st.ncross++;
+    } else if (t < st.tbest || (t == st.tbest && id < st.best_id)) {
+      st.tbest = t;
+      st.best_id = id;
+      st.best_mat = __float_as_uint(B.w);
+      st.bu = u;
+      st.bv = v;
+    }
+    return true;
+  }
   float4 na, nb, nc, nd;
   if ((int)node < n_lds) {
     na = lds_nodes[node * 4 + 0];
@@ -542,42 +586,27 @@ __device__ __forceinline__ bool trav_step(const DevScene& S, const DevWS& w, con
   box2(R, na, nb, nc, box_lo, shadow ? t_hi : st.tbest, h0, t0, h1, t1);
   h0 = h0 && i0 != kEmptyChild;
   h1 = h1 && i1 != kEmptyChild;
-  const uint32_t la = (h0 && c0) ? c0 : 0u, lb = (h1 && c1) ? c1 : 0u;
-  if (la) h0 = false;
-  if (lb) h1 = false;
-  const float4* ctris = S.ctris + (size_t)cinfo.z * 3;
-  for (uint32_t q = 0; q < la + lb; ++q) {
-    const uint32_t tri = q < la ? i0 + q : i1 + (q - la);
-    const float4 A = ctris[tri * 3 + 0], B = ctris[tri * 3 + 1], C = ctris[tri * 3 + 2];
-    const uint32_t id = __float_as_uint(A.w);
-    if (id == skip) continue;
-    ++st.tris;
-    float t, u, v;
-    if (!wt_test(R, f3(A.x, A.y, A.z), f3(B.x, B.y, B.z), f3(C.x, C.y, C.z), t, u, v)) continue;
-    if (!(t > 0.0f && t >= t_lo && t < t_hi)) continue;
-    if (shadow) {
-      const int m = (int)__float_as_uint(B.w);
-      if (S.mtype[m] == 0) {
-        st.blocked = true;
-        return false;
-      }
-      const F3 ng = geo_normal(f3(A.x, A.y, A.z), f3(B.x, B.y, B.z), f3(C.x, C.y, C.z));
-      if (st.ncross < (uint32_t)kMaxCross)
-        w.shx[(size_t)st.ncross * w.W + slot] = make_float2(__int_as_float(m), fabsf(dot3(R.d, ng)));
-      st.ncross++;
-    } else if (t < st.tbest || (t == st.tbest && id < st.best_id)) {
-      st.tbest = t;
-      st.best_id = id;
-      st.best_mat = __float_as_uint(B.w);
-      st.bu = u;
-      st.bv = v;
+  // leaf children: the first becomes pending, a second is pushed as a leaf entry
+  const bool l0 = h0 && c0, l1 = h1 && c1;
+  if (l0) {
+    pend_idx = i0;
+    pend_cnt = c0;
+  }
+  if (l1) {
+    if (!l0) {
+      pend_idx = i1;
+      pend_cnt = c1;
+    } else {
+      const uint32_t e = kStackLeaf | (c1 << 27) | i1;
+      if (sp < kShortStack)
+        stack_lds[sp * kWG] = e;
+      else
+        spill[(size_t)(sp - kShortStack) * spill_stride] = e;
+      ++sp;
     }
   }
-  if (!shadow) {
-    h0 = h0 && t0 <= st.tbest;
-    h1 = h1 && t1 <= st.tbest;
-  }
-  if (h0 && h1) {
+  const bool n0 = h0 && !c0, n1 = h1 && !c1;
+  if (n0 && n1) {
     const bool first0 = t0 <= t1;
     const uint32_t near = first0 ? i0 : i1, far = first0 ? i1 : i0;
     if (sp < kShortStack)
@@ -586,14 +615,12 @@ __device__ __forceinline__ bool trav_step(const DevScene& S, const DevWS& w, con
       spill[(size_t)(sp - kShortStack) * spill_stride] = far;
     ++sp;
     node = near;
-  } else if (h0) {
+  } else if (n0) {
     node = i0;
-  } else if (h1) {
+  } else if (n1) {
     node = i1;
   } else {
-    if (sp == 0) return false;
-    --sp;
-    node = sp < kShortStack ? stack_lds[sp * kWG] : spill[(size_t)(sp - kShortStack) * spill_stride];
+    node = kNoNode;
   }
   return true;
 }
@@ -665,7 +692,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
     R.o = R.d = R.inv = f3(0.0f, 0.0f, 0.0f);
     R.kx = R.ky = R.kz = 0;
     R.Sx = R.Sy = R.Sz = 0.0f;
-    uint32_t r = 0, slot = 0, skip = 0, node = 0, ncross0 = 0;
+    uint32_t r = 0, slot = 0, skip = 0, node = 0, ncross0 = 0, pend_idx = 0, pend_cnt = 0;
     bool shadow = false, first = false;
     int ix = 0, iy = 0, iz = 0, cell = 0, h = 0, sp = 0, axis = 0, nl = 0;
     float t_lo = 0.0f, tf = 0.0f, box_lo = 0.0f;
@@ -725,6 +752,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
           box_lo = fmaxf(t_lo, 0.0f);
           node = 0;
           sp = 0;
+          pend_cnt = 0;
           phase = kLaneTrav;
         } else {
           phase = kLaneLeave;
@@ -732,7 +760,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
       }
       if (phase == kLaneTrav) {
         if (!trav_step(S, w, R, shadow, cinfo, s_nodes, nl, stack, spill, w.trace_threads, skip, t_lo, tf, box_lo,
-                       slot, st, node, sp)) {
+                       slot, st, node, sp, pend_idx, pend_cnt)) {
           if (shadow && st.blocked) {
             w.shcnt[slot] = kBlocked;
             fin = true;

@@ -386,6 +386,10 @@ std::string build_scene(const sdd_scene_desc& d, sdd_scene* out) {
     if (c.tris.empty()) ++empty;
   }
   if (max_depth >= kMaxStack) return "internal: BVH depth exceeds the traversal stack";
+  // the traversal stack encodes a leaf as (first triangle, count) in one word
+  if (max_leaf > (int)kStackLeafMaxCount) return "scene too degenerate: a BVH leaf holds more than 15 triangles";
+  for (auto& c : cells)
+    if (c.tris.size() > (size_t)kStackLeafMaxIndex) return "scene too large: a cell holds more than 2^27 triangles";
   if (n_refs > (uint64_t)INT32_MAX || n_nodes > (uint64_t)INT32_MAX) return "scene too large for 32-bit indices";
 
   SceneHeader H;
