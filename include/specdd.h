@@ -124,8 +124,9 @@ typedef struct {
   uint64_t seed;               /* Philox key                                                   */
   int32_t mode;                /* SDD_MODE_PLAIN or SDD_MODE_CACHED                            */
   int32_t wave_paths;          /* paths in flight per wavefront, >= 64 (0 = library default)   */
-  int32_t queue_rounds;        /* traversal rounds per wavefront phase (0 = library default 2):
-                                  in each round but the last a ray is traversed in one cell and
+  int32_t queue_rounds;        /* traversal rounds per wavefront phase (0 = library default 1):
+                                  every new ray is queued at the cell holding its origin; in
+                                  each round but the last a ray is traversed in one cell and
                                   then migrates to the queue of the next cell along it; in the
                                   last round rays walk their remaining cells in place         */
   uint32_t view;               /* view index used in the RNG counter (sdd_render only)         */

@@ -36,7 +36,10 @@ int fail(sdd_ctx* c, int code, const std::string& msg) {
   } while (0)
 
 constexpr int kDefaultWave = 1 << 20;
-constexpr int kDefaultRounds = 2;
+constexpr int kDefaultRounds = 1;
+// Ray queries (sdd_trace / sdd_shadow) run one migration round before walking in place, so that
+// every query also exercises the migration between cell queues.
+constexpr int kQueryRounds = 2;
 constexpr int kMaxViewsPerStore = 16;
 
 struct ViewBlock {
@@ -654,7 +657,7 @@ static int query(sdd_ctx* c, const sdd_scene* s, const float* orig, const float*
     uint32_t m = (uint32_t)std::min<int64_t>(W, n - a);
     HIP_TRY(c, launch_fill_u32(c->stream, &w.ctl->cat_count[0][0], 2 * 8, 0u));
     HIP_TRY(c, launch_pack_rays(L, S, w, orig + 3 * a, dir + 3 * a, skip ? skip + a : nullptr, m, shadow ? 1 : 0, gen));
-    rc = trace_phase(c, L, S, w, gen, kDefaultRounds, 0, false);
+    rc = trace_phase(c, L, S, w, gen, kQueryRounds, 0, false);
     if (rc) return rc;
     if (shadow)
       HIP_TRY(c, launch_resolve_vis(L, S, w, m, vis + (size_t)a * s->hdr.n_bins));
