@@ -157,6 +157,8 @@ def _pmc_per_kernel(path, counter):
         if r["Counter_Name"] != counter:
             continue
         k = r["Kernel_Name"].split("(")[0].strip()
+        if k.startswith("void "):
+            k = k[5:]
         v = acc.setdefault(k, [0.0, 0])
         v[0] += float(r["Counter_Value"])
         v[1] += 1
