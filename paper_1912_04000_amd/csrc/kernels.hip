@@ -14,9 +14,11 @@
 
 namespace sdd {
 
-// Wave-level append of (src, cell) entries: one atomic per wave on the list counter and one
-// per distinct destination cell of the wave (ballot + mbcnt prefix); every lane of the wave
-// must call it.
+// Wave-level append of (src, key) entries: one atomic per wave on the list counter and one per
+// distinct destination queue key of the wave. The lanes are first grouped by key (ballot +
+// mbcnt, no memory traffic), then the group leaders add their group sizes to the per-key
+// counters in one atomic instruction, so a wave waits for one atomic round trip however many
+// keys it holds. Every lane of the wave must call it.
 __device__ void wave_append(bool valid, uint32_t src, uint32_t cell, uint32_t* list_count, uint32_t* cell_count,
                             uint32_t* lsrc, uint32_t* ldst, uint32_t* lrank) {
   const uint64_t m = __ballot(valid);
@@ -24,21 +26,35 @@ __device__ void wave_append(bool valid, uint32_t src, uint32_t cell, uint32_t* l
   const uint32_t leader = (uint32_t)__ffsll((unsigned long long)m) - 1u;
   uint32_t base = 0;
   if (lane_id() == leader) base = atomicAdd(list_count, (uint32_t)__popcll(m));
-  base = __shfl(base, (int)leader);
-  const uint32_t pos = base + count_below(m);
-  uint32_t rank = 0;
+  uint32_t my_leader = 0, my_off = 0, gcount = 0;
+  bool is_leader = false;
   uint64_t pending = m;
   while (pending) {
     const uint32_t l = (uint32_t)__ffsll((unsigned long long)pending) - 1u;
     const uint32_t c = __shfl(cell, (int)l);
     const bool mine = valid && cell == c;
     const uint64_t same = __ballot(mine);
-    uint32_t cb = 0;
-    if (lane_id() == l) cb = atomicAdd(&cell_count[c], (uint32_t)__popcll(same));
-    cb = __shfl(cb, (int)l);
-    if (mine) rank = cb + count_below(same);
+    if (mine) {
+      my_leader = l;
+      my_off = count_below(same);
+    }
+    if (lane_id() == l) {
+      is_leader = true;
+      gcount = (uint32_t)__popcll(same);
+    }
     pending &= ~same;
   }
+  uint32_t cb = 0;
+  if (is_leader) cb = atomicAdd(&cell_count[cell], gcount);
+  cb = __shfl(cb, (int)my_leader);
+  base = __shfl(base, (int)leader);
+  if (valid) {
+    const uint32_t pos = base + count_below(m);
+    lsrc[pos] = src;
+    ldst[pos] = cell;
+    lrank[pos] = cb + my_off;
+  }
+}
   if (valid) {
     lsrc[pos] = src;
     ldst[pos] = cell;
@@ -401,7 +417,9 @@ __device__ __forceinline__ RayPre make_pre(F3 o, F3 d) {
   RayPre R;
   R.o = o;
   R.d = d;
-  R.inv = f3(1.0f / d.x, 1.0f / d.y, 1.0f / d.z);
+  // hardware reciprocals (1 ulp): the box test's slack covers the extra rounding, the shear
+  // constants of the watertight test only need to be the same for every triangle of the ray
+  R.inv = f3(frcp(d.x), frcp(d.y), frcp(d.z));
   const float ax = fabsf(d.x), ay = fabsf(d.y), az = fabsf(d.z);
   R.kz = (ax >= ay && ax >= az) ? 0 : (ay >= az ? 1 : 2);
   R.kx = R.kz == 2 ? 0 : R.kz + 1;
@@ -412,9 +430,9 @@ __device__ __forceinline__ RayPre make_pre(F3 o, F3 d) {
     R.ky = t;
   }
   const float dz = comp(d, R.kz);
-  R.Sx = comp(d, R.kx) / dz;
-  R.Sy = comp(d, R.ky) / dz;
-  R.Sz = 1.0f / dz;
+  R.Sz = frcp(dz);
+  R.Sx = comp(d, R.kx) * R.Sz;
+  R.Sy = comp(d, R.ky) * R.Sz;
   return R;
 }
 
@@ -471,16 +489,19 @@ __device__ __forceinline__ void refine_hit(F3 of, F3 df, F3 v0, F3 v1, F3 v2, fl
   const double det = U + V + W;
   if (det == 0.0) return;
   const double T = Sz * (U * A[kz] + V * B[kz] + W * C[kz]);
-  t = (float)(T / det);
-  bu = (float)(V / det);
-  bv = (float)(W / det);
+  const double inv_det = 1.0 / det;
+  t = (float)(T * inv_det);
+  bu = (float)(V * inv_det);
+  bv = (float)(W * inv_det);
 }
 
 // Both child boxes of a node against [tmin, tmax] (robust slab test, Ize 2013: the far
-// distance is scaled by 1 + 2 gamma_3 so that rounding never culls a box the ray touches).
+// distance is scaled by 1 + 2 gamma_5 so that rounding never culls a box the ray touches; a slab
+// distance carries the subtraction, the product and the 1-ulp reciprocal, four roundings, and
+// gamma_5 keeps one in reserve).
 __device__ __forceinline__ void box2(const RayPre& R, float4 a, float4 b, float4 c, float tmin, float tmax, bool& h0,
                                      float& t0, bool& h1, float& t1) {
-  constexpr float kSlop = 1.0f + 2.0f * 3.0f * 5.9604645e-8f / (1.0f - 3.0f * 5.9604645e-8f);
+  constexpr float kSlop = 1.0f + 2.0f * 5.0f * 5.9604645e-8f / (1.0f - 5.0f * 5.9604645e-8f);
   const float x0 = (a.x - R.o.x) * R.inv.x, x1 = (a.y - R.o.x) * R.inv.x;
   const float y0 = (a.z - R.o.y) * R.inv.y, y1 = (a.w - R.o.y) * R.inv.y;
   const float z0 = (c.x - R.o.z) * R.inv.z, z1 = (c.y - R.o.z) * R.inv.z;
