@@ -55,12 +55,6 @@ __device__ void wave_append(bool valid, uint32_t src, uint32_t cell, uint32_t* l
     lrank[pos] = cb + my_off;
   }
 }
-  if (valid) {
-    lsrc[pos] = src;
-    ldst[pos] = cell;
-    lrank[pos] = rank;
-  }
-}
 
 // ==========================================================================================
 // cell grid
