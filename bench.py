@@ -567,7 +567,8 @@ def main():
         "per_path": {"vertices": st["vertices"] / max(1, st["paths"]),
                      "shadow_rays": st["shadow_rays"] / max(1, st["paths"]),
                      "cell_visits_per_ray": st["cell_visits"] / max(1, st["ext_rays"] + st["shadow_rays"]),
-                     "nodes_per_ray": st["node_visits"] / max(1, st["ext_rays"] + st["shadow_rays"])},
+                     "nodes_per_ray": st["node_visits"] / max(1, st["ext_rays"] + st["shadow_rays"]),
+                     "tri_tests_per_ray": st["tri_tests"] / max(1, st["ext_rays"] + st["shadow_rays"])},
         "scene_build_s": build_s,
     }
     if args.workload == "church" and not args.no_cached:

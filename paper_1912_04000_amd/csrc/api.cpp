@@ -662,7 +662,7 @@ static int query(sdd_ctx* c, const sdd_scene* s, const float* orig, const float*
     if (shadow)
       HIP_TRY(c, launch_resolve_vis(L, S, w, m, vis + (size_t)a * s->hdr.n_bins));
     else
-      HIP_TRY(c, launch_unpack_hits(L, w, m, t + a, id + a, u + a, v + a));
+      HIP_TRY(c, launch_unpack_hits(L, S, w, m, t + a, id + a, u + a, v + a));
   }
   return SDD_OK;
 }

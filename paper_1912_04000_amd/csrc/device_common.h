@@ -79,6 +79,33 @@ __device__ __forceinline__ void wave_add(unsigned long long* ctr, uint32_t x) {
 
 
 // Geometry of the hit of slot s: vertex position, face-forward normal, geometric normal.
+// Distance and barycentrics of the winning triangle re-evaluated in FP64 with the sheared
+// formulation of the watertight test: the FP32 test of the traversal decides which triangle is
+// hit, this pass (run by whoever reads the hit) removes the cancellation that makes FP32
+// distances and barycentrics inaccurate for grazing rays. t, bu, bv are left as passed in when
+// the FP64 determinant is zero.
+__device__ __forceinline__ void refine_hit(F3 of, F3 df, F3 v0, F3 v1, F3 v2, float& t, float& bu, float& bv) {
+  const double o[3] = {of.x, of.y, of.z}, d[3] = {df.x, df.y, df.z};
+  const double ad[3] = {fabs(d[0]), fabs(d[1]), fabs(d[2])};
+  const int kz = (ad[0] >= ad[1] && ad[0] >= ad[2]) ? 0 : (ad[1] >= ad[2] ? 1 : 2);
+  const int kx = kz == 2 ? 0 : kz + 1, ky = kx == 2 ? 0 : kx + 1;
+  const double Sx = d[kx] / d[kz], Sy = d[ky] / d[kz], Sz = 1.0 / d[kz];
+  const double A[3] = {v0.x - o[0], v0.y - o[1], v0.z - o[2]};
+  const double B[3] = {v1.x - o[0], v1.y - o[1], v1.z - o[2]};
+  const double C[3] = {v2.x - o[0], v2.y - o[1], v2.z - o[2]};
+  const double Ax = A[kx] - Sx * A[kz], Ay = A[ky] - Sy * A[kz];
+  const double Bx = B[kx] - Sx * B[kz], By = B[ky] - Sy * B[kz];
+  const double Cx = C[kx] - Sx * C[kz], Cy = C[ky] - Sy * C[kz];
+  const double U = Cx * By - Cy * Bx, V = Ax * Cy - Ay * Cx, W = Bx * Ay - By * Ax;
+  const double det = U + V + W;
+  if (det == 0.0) return;
+  const double T = Sz * (U * A[kz] + V * B[kz] + W * C[kz]);
+  const double inv_det = 1.0 / det;
+  t = (float)(T * inv_det);
+  bu = (float)(V * inv_det);
+  bv = (float)(W * inv_det);
+}
+
 struct Vertex {
   F3 p, n, ng, d;
   float dn, cos_o, eps;
@@ -99,7 +126,9 @@ __device__ __forceinline__ Vertex load_vertex(const DevScene& S, const DevWS& w,
   V.dn = dot_exact_sign(V.d, V.ng);
   V.n = V.dn > 0.0f ? V.ng * -1.0f : V.ng;
   V.cos_o = fabsf(V.dn);
-  const float bu = h.z, bv = h.w;
+  const float4 rorg = w.rays[2 * s];
+  float t = h.x, bu = 1.0f / 3.0f, bv = 1.0f / 3.0f;
+  refine_hit(f3(rorg.x, rorg.y, rorg.z), V.d, v0, v1, v2, t, bu, bv);
   V.p = v0 * (1.0f - bu - bv) + v1 * bu + v2 * bv;
   V.eps = 1e-5f * (1.0f + maxabs3(V.p));
   return V;

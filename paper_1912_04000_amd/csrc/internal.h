@@ -229,7 +229,8 @@ hipError_t launch_shade_glass(const Launch& L, const DevScene& S, const DevWS& w
 hipError_t launch_accumulate(const Launch& L, const DevScene& S, const DevWS& w, uint32_t n);
 hipError_t launch_pack_rays(const Launch& L, const DevScene& S, const DevWS& w, const float* orig, const float* dir,
                             const int32_t* skip, uint32_t n, int shadow, int gen);
-hipError_t launch_unpack_hits(const Launch& L, const DevWS& w, uint32_t n, float* t, int32_t* id, float* u, float* v);
+hipError_t launch_unpack_hits(const Launch& L, const DevScene& S, const DevWS& w, uint32_t n, float* t, int32_t* id,
+                              float* u, float* v);
 hipError_t launch_resolve_vis(const Launch& L, const DevScene& S, const DevWS& w, uint32_t n, float* vis);
 hipError_t launch_philox(hipStream_t s, const uint32_t ctr[4], const uint32_t key[2], uint64_t n, uint32_t* out);
 

@@ -309,13 +309,24 @@ __global__ __launch_bounds__(kWG) void k_pack_rays(DevScene S, DevWS w, const fl
               ccount_of(S, w, p), w.lsrc, w.ldst, w.lrank);
 }
 
-__global__ void k_unpack_hits(DevWS w, uint32_t n, float* t, int32_t* id, float* u, float* v) {
+// Hit records hold the FP32 distance and the triangle id; the distance and barycentrics handed
+// out are re-evaluated in FP64 here.
+__global__ void k_unpack_hits(DevScene S, DevWS w, uint32_t n, float* t, int32_t* id, float* u, float* v) {
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const float4 h = w.hit[i];
-    t[i] = h.x;
-    id[i] = __float_as_int(h.y);
-    u[i] = h.z;
-    v[i] = h.w;
+    const uint32_t tid = __float_as_uint(h.y);
+    float th = h.x, bu = 0.0f, bv = 0.0f;
+    if (tid != 0xFFFFFFFFu) {
+      const float4* g = S.gtris + (size_t)tid * 3;
+      const float4 A = g[0], B = g[1], C = g[2], ro = w.rays[2 * i], rd = w.rays[2 * i + 1];
+      bu = bv = 1.0f / 3.0f;
+      refine_hit(f3(ro.x, ro.y, ro.z), f3(rd.x, rd.y, rd.z), f3(A.x, A.y, A.z), f3(B.x, B.y, B.z), f3(C.x, C.y, C.z),
+                 th, bu, bv);
+    }
+    t[i] = th;
+    id[i] = (int32_t)tid;
+    u[i] = bu;
+    v[i] = bv;
   }
 }
 
@@ -464,31 +475,6 @@ __device__ __forceinline__ bool wt_test(const RayPre& R, F3 v0, F3 v1, F3 v2, fl
   return true;
 }
 
-// Distance and barycentrics of the winning triangle re-evaluated in FP64 with the same
-// sheared formulation: the FP32 test decides which triangle is hit, this pass removes the
-// cancellation that makes FP32 distances inaccurate for grazing rays.
-__device__ __forceinline__ void refine_hit(F3 of, F3 df, F3 v0, F3 v1, F3 v2, float& t, float& bu, float& bv) {
-  const double o[3] = {of.x, of.y, of.z}, d[3] = {df.x, df.y, df.z};
-  const double ad[3] = {fabs(d[0]), fabs(d[1]), fabs(d[2])};
-  const int kz = (ad[0] >= ad[1] && ad[0] >= ad[2]) ? 0 : (ad[1] >= ad[2] ? 1 : 2);
-  const int kx = kz == 2 ? 0 : kz + 1, ky = kx == 2 ? 0 : kx + 1;
-  const double Sx = d[kx] / d[kz], Sy = d[ky] / d[kz], Sz = 1.0 / d[kz];
-  const double A[3] = {v0.x - o[0], v0.y - o[1], v0.z - o[2]};
-  const double B[3] = {v1.x - o[0], v1.y - o[1], v1.z - o[2]};
-  const double C[3] = {v2.x - o[0], v2.y - o[1], v2.z - o[2]};
-  const double Ax = A[kx] - Sx * A[kz], Ay = A[ky] - Sy * A[kz];
-  const double Bx = B[kx] - Sx * B[kz], By = B[ky] - Sy * B[kz];
-  const double Cx = C[kx] - Sx * C[kz], Cy = C[ky] - Sy * C[kz];
-  const double U = Cx * By - Cy * Bx, V = Ax * Cy - Ay * Cx, W = Bx * Ay - By * Ax;
-  const double det = U + V + W;
-  if (det == 0.0) return;
-  const double T = Sz * (U * A[kz] + V * B[kz] + W * C[kz]);
-  const double inv_det = 1.0 / det;
-  t = (float)(T * inv_det);
-  bu = (float)(V * inv_det);
-  bv = (float)(W * inv_det);
-}
-
 // Both child boxes of a node against [tmin, tmax] (robust slab test, Ize 2013: the far
 // distance is scaled by 1 + 2 gamma_5 so that rounding never culls a box the ray touches; a slab
 // distance carries the subtraction, the product and the 1-ulp reciprocal, four roundings, and
@@ -513,16 +499,16 @@ __device__ __forceinline__ void box2(const RayPre& R, float4 a, float4 b, float4
 }
 
 struct TraceState {
-  // closest hit
+  // closest hit (distance and triangle id; the hit's reader refines both in FP64)
   float tbest;
-  uint32_t best_id, best_mat;
-  float bu, bv;
+  uint32_t best_id;
   // shadow
   bool blocked;
   uint32_t ncross;
-  // work counters
-  uint32_t nodes, tris;
 };
+
+// What one traversal step did, for the work counters.
+enum : int { kStepNone = 0, kStepNode = 1, kStepTri = 2 };
 
 // Traverse the BVH of one cell for hits with t > 0, t >= t_lo, t < t_hi. One loop serves both
 // ray kinds (lanes of a wave may hold either): a closest-hit ray shrinks its far bound with every
@@ -538,7 +524,7 @@ __device__ __forceinline__ bool trav_step(const DevScene& S, const DevWS& w, con
                                           const float4* lds_nodes, int n_lds, uint32_t* stack_lds, uint32_t* spill,
                                           uint32_t spill_stride, uint32_t skip, float t_lo, float t_hi,
                                           float box_lo, uint32_t slot, TraceState& st, uint32_t& node, int& sp,
-                                          uint32_t& pend_idx, uint32_t& pend_cnt) {
+                                          uint32_t& pend_idx, uint32_t& pend_cnt, int& work) {
   if (pend_cnt == 0 && node == kNoNode) {
     if (sp == 0) return false;
     --sp;
@@ -557,7 +543,7 @@ __device__ __forceinline__ bool trav_step(const DevScene& S, const DevWS& w, con
     const float4 A = ctris[tri * 3 + 0], B = ctris[tri * 3 + 1], C = ctris[tri * 3 + 2];
     const uint32_t id = __float_as_uint(A.w);
     if (id == skip) return true;
-    ++st.tris;
+    work = kStepTri;
     float t, u, v;
     if (!wt_test(R, f3(A.x, A.y, A.z), f3(B.x, B.y, B.z), f3(C.x, C.y, C.z), t, u, v)) return true;
     if (!(t > 0.0f && t >= t_lo && t < t_hi)) return true;
@@ -574,9 +560,6 @@ __device__ __forceinline__ bool trav_step(const DevScene& S, const DevWS& w, con
     } else if (t < st.tbest || (t == st.tbest && id < st.best_id)) {
       st.tbest = t;
       st.best_id = id;
-      st.best_mat = __float_as_uint(B.w);
-      st.bu = u;
-      st.bv = v;
     }
     return true;
   }
@@ -595,7 +578,7 @@ __device__ __forceinline__ bool trav_step(const DevScene& S, const DevWS& w, con
   }
   const uint32_t i0 = __float_as_uint(nd.x), i1 = __float_as_uint(nd.y);
   const uint32_t c0 = __float_as_uint(nd.z), c1 = __float_as_uint(nd.w);
-  ++st.nodes;
+  work = kStepNode;
   bool h0, h1;
   float t0, t1;
   box2(R, na, nb, nc, box_lo, shadow ? t_hi : st.tbest, h0, t0, h1, t1);
@@ -650,7 +633,7 @@ enum : int { kLaneIdle = 0, kLaneEnter = 1, kLaneTrav = 2, kLaneLeave = 3, kLane
 // but the last the ray then migrates to the queue of the next cell, in the last round it walks
 // on in place. Finished rays go to LDS lists that the workgroup flushes to the global category
 // lists and the migration list once the tile is drained.
-__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k_trace(DevScene S, DevWS w, int gen, int hops,
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(5))) void k_trace(DevScene S, DevWS w, int gen, int hops,
                                                                                                int cat_par) {
   __shared__ float4 s_nodes[kTopNodes * 4];
   __shared__ uint32_t s_stack[kShortStack * kWG];
@@ -665,6 +648,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
   uint32_t* spill = w.spill + gtid;
   uint32_t* stack = s_stack + threadIdx.x;
   const int np = (gen + 1) & 1;
+  // work counters: wave-uniform sums of ballots (scalar registers)
   uint32_t n_visit = 0, n_migr = 0, n_esc = 0, n_glass = 0, n_xover = 0, n_nodes = 0, n_tris = 0;
   int prev_cell = -1;
   // Tiles are handed out dynamically: each XCD owns a contiguous range of the cell-sorted tiles
@@ -690,7 +674,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
       s_nreq = 0;
     }
     __syncthreads();
-    const uint32_t t = s_next[it & 1];
+    const uint32_t t = __builtin_amdgcn_readfirstlane(s_next[it & 1]);
     if (t == 0xFFFFFFFFu) break;
     const uint4 tile = w.tiles[t];
     const int tcell = (int)(tile.x / kDirBins);
@@ -715,12 +699,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
     TraceState st;
     st.tbest = INFINITY;
     st.best_id = 0xFFFFFFFFu;
-    st.best_mat = 0;
-    st.bu = st.bv = 0.0f;
     st.blocked = false;
     st.ncross = 0;
-    st.nodes = 0;
-    st.tris = 0;
     for (;;) {
       if (phase == kLaneIdle) {
         const uint32_t i = atomicAdd(&s_fetch, 1u);
@@ -741,8 +721,6 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
           h = 0;
           st.tbest = INFINITY;
           st.best_id = 0xFFFFFFFFu;
-          st.best_mat = 0;
-          st.bu = st.bv = 0.0f;
           st.blocked = false;
           st.ncross = shadow ? w.shcnt[slot] : 0u;
           ncross0 = st.ncross;
@@ -752,15 +730,15 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
         }
       }
       if (__ballot(phase != kLaneDone) == 0) break;
-      bool fin = false, out_req = false;
-      int out_cat = -1;
+      bool fin = false, out_req = false, esc = false;
+      int out_cat = -1, work = kStepNone;
+      n_visit += (uint32_t)__popcll(__ballot(phase == kLaneEnter));
       if (phase == kLaneEnter) {
         // the cell's slab interval; traversal starts unless the cell is empty or already passed
         float tn;
         cell_interval(S, ix, iy, iz, R.o, R.d, R.inv, tn, tf, axis);
         t_lo = first ? -INFINITY : tn;
         cinfo = cell == tcell ? tinfo : S.cells[cell];
-        ++n_visit;
         if (cinfo.y > 0 && t_lo < tf) {
           nl = cell == tcell ? n_top : 0;
           if (!shadow) st.tbest = tf;
@@ -775,17 +753,14 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
       }
       if (phase == kLaneTrav) {
         if (!trav_step(S, w, R, shadow, cinfo, s_nodes, nl, stack, spill, w.trace_threads, skip, t_lo, tf, box_lo,
-                       slot, st, node, sp, pend_idx, pend_cnt)) {
+                       slot, st, node, sp, pend_idx, pend_cnt, work)) {
           if (shadow && st.blocked) {
             w.shcnt[slot] = kBlocked;
             fin = true;
           } else if (!shadow && st.best_id != 0xFFFFFFFFu) {
-            const float4* g = S.gtris + (size_t)st.best_id * 3;
-            const float4 A = g[0], Bq = g[1], Cq = g[2];
-            refine_hit(R.o, R.d, f3(A.x, A.y, A.z), f3(Bq.x, Bq.y, Bq.z), f3(Cq.x, Cq.y, Cq.z), st.tbest, st.bu,
-                       st.bv);
-            w.hit[slot] = make_float4(st.tbest, __uint_as_float(st.best_id), st.bu, st.bv);
-            out_cat = S.mtype[st.best_mat] == 0 ? kCatOpaque : kCatGlass;
+            const uint32_t mat = __float_as_uint(S.gtris[(size_t)st.best_id * 3 + 1].w);
+            w.hit[slot] = make_float4(st.tbest, __uint_as_float(st.best_id), 0.0f, 0.0f);
+            out_cat = S.mtype[mat] == 0 ? kCatOpaque : kCatGlass;
             fin = true;
           } else {
             phase = kLaneLeave;
@@ -806,7 +781,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
           } else {
             out_cat = st.ncross > 0 ? kCatShadowGlass : kCatShadowClear;
           }
-          ++n_esc;
+          esc = true;
           fin = true;
         } else {
           cell = (iz * S.gy + iy) * S.gx + ix;
@@ -815,17 +790,25 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
             phase = kLaneEnter;
           } else {
             out_req = true;
-            ++n_migr;
             fin = true;
           }
         }
       }
+      n_nodes += (uint32_t)__popcll(__ballot(work == kStepNode));
+      n_tris += (uint32_t)__popcll(__ballot(work == kStepTri));
+      n_esc += (uint32_t)__popcll(__ballot(esc));
+      n_migr += (uint32_t)__popcll(__ballot(out_req));
+      const bool crossed = fin && shadow && !st.blocked && st.ncross != ncross0;
+      if (__ballot(crossed) != 0) {
+        uint32_t dg = crossed ? st.ncross - ncross0 : 0u;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) dg += __shfl_xor(dg, o);
+        n_glass += __builtin_amdgcn_readfirstlane(dg);
+        n_xover += (uint32_t)__popcll(
+            __ballot(crossed && st.ncross > (uint32_t)kMaxCross && ncross0 <= (uint32_t)kMaxCross));
+      }
       if (fin) {
-        if (shadow && !st.blocked && st.ncross != ncross0) {
-          n_glass += st.ncross - ncross0;
-          if (st.ncross > (uint32_t)kMaxCross && ncross0 <= (uint32_t)kMaxCross) ++n_xover;
-          w.shcnt[slot] = st.ncross;
-        }
+        if (crossed) w.shcnt[slot] = st.ncross;
         if (out_cat >= 0) {
           const uint32_t c = atomicAdd(&s_ncat, 1u);
           s_cslot[c] = slot;
@@ -836,10 +819,6 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
           s_rsrc[q] = r;
           s_rkey[q] = qkey((uint32_t)cell, tdir);
         }
-        n_nodes += st.nodes;
-        n_tris += st.tris;
-        st.nodes = 0;
-        st.tris = 0;
         phase = kLaneIdle;
       }
     }
@@ -863,13 +842,15 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
     }
     __syncthreads();
   }
-  wave_add(&w.ctl->st_visits, n_visit);
-  wave_add(&w.ctl->st_migr, n_migr);
-  wave_add(&w.ctl->st_escape, n_esc);
-  wave_add(&w.ctl->st_glass, n_glass);
-  wave_add(&w.ctl->err_cross, n_xover);
-  wave_add(&w.ctl->st_nodes, n_nodes);
-  wave_add(&w.ctl->st_tris, n_tris);
+  if (lane_id() == 0) {
+    if (n_visit) atomicAdd(&w.ctl->st_visits, (unsigned long long)n_visit);
+    if (n_migr) atomicAdd(&w.ctl->st_migr, (unsigned long long)n_migr);
+    if (n_esc) atomicAdd(&w.ctl->st_escape, (unsigned long long)n_esc);
+    if (n_glass) atomicAdd(&w.ctl->st_glass, (unsigned long long)n_glass);
+    if (n_xover) atomicAdd(&w.ctl->err_cross, (unsigned long long)n_xover);
+    if (n_nodes) atomicAdd(&w.ctl->st_nodes, (unsigned long long)n_nodes);
+    if (n_tris) atomicAdd(&w.ctl->st_tris, (unsigned long long)n_tris);
+  }
 }
 
 // ==========================================================================================
@@ -954,12 +935,17 @@ __device__ __forceinline__ void record_vertex(const PathMode& pm, const DevWS& w
   }
 }
 
+// NQ > 0: the spectral rows have exactly NQ float4 quads (compile time), so the bin loops unroll,
+// their loads issue together and the Fresnel factors of the first pass stay in registers for
+// the throughput update; NQ = 0 handles any bin count.
+template <int NQ>
 __global__ __launch_bounds__(kWG) void k_shade_opaque(DevScene S, DevWS w, int depth, int max_depth, uint32_t key0,
                                                       uint32_t key1, int gen, PathMode pm) {
   const int p = depth & 1;
   const uint32_t n = w.ctl->cat_count[p][kCatOpaque];
   const uint32_t* list = cat_list(w, p, kCatOpaque);
-  const int B = S.n_bins, Bp = w.Bp, nq = Bp / 4;
+  const int B = S.n_bins, Bp = w.Bp, nq = NQ > 0 ? NQ : Bp / 4;
+  constexpr int kUnroll = NQ > 0 ? NQ : 1;
   const size_t W = w.W;
   const int gp = gen & 1;
   const uint32_t n_iter = (n + kWG - 1) / kWG * kWG;
@@ -985,10 +971,16 @@ __global__ __launch_bounds__(kWG) void k_shade_opaque(DevScene S, DevWS w, int d
       const bool nee = cs > 0.0f;
       const float kn = cs * (1.0f / 3.14159265358979f);
       float a_sum = 0.0f, b_sum = 0.0f;
+      float Fk[NQ > 0 ? 4 * NQ : 1];
+#pragma unroll kUnroll
       for (int q = 0; q < nq; ++q) {
         const float4 nn = nt[q], kk = kt[q], rr = rt[q];
         float F[4] = {fresnel(nn.x, kk.x, V.cos_o), fresnel(nn.y, kk.y, V.cos_o), fresnel(nn.z, kk.z, V.cos_o),
                       fresnel(nn.w, kk.w, V.cos_o)};
+        if (NQ > 0) {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) Fk[(4 * q + c) % (4 * (NQ > 0 ? NQ : 1))] = F[c];
+        }
         const float rho[4] = {rr.x, rr.y, rr.z, rr.w};
         float dif[4];
 #pragma unroll
@@ -1019,10 +1011,22 @@ __global__ __launch_bounds__(kWG) void k_shade_opaque(DevScene S, DevWS w, int d
         const float Ps = am / (am + bm);
         const bool mirror = u0 < Ps;
         const float inv_p = mirror ? 1.0f / Ps : 1.0f / (1.0f - Ps);
+#pragma unroll kUnroll
         for (int q = 0; q < nq; ++q) {
           const float4 nn = nt[q], kk = kt[q], rr = rt[q];
-          const float F0 = fresnel(nn.x, kk.x, V.cos_o), F1 = fresnel(nn.y, kk.y, V.cos_o);
-          const float F2 = fresnel(nn.z, kk.z, V.cos_o), F3v = fresnel(nn.w, kk.w, V.cos_o);
+          float F0, F1, F2, F3v;
+          if (NQ > 0) {
+            const int b0 = (4 * q) % (4 * (NQ > 0 ? NQ : 1));
+            F0 = Fk[b0];
+            F1 = Fk[b0 + 1];
+            F2 = Fk[b0 + 2];
+            F3v = Fk[b0 + 3];
+          } else {
+            F0 = fresnel(nn.x, kk.x, V.cos_o);
+            F1 = fresnel(nn.y, kk.y, V.cos_o);
+            F2 = fresnel(nn.z, kk.z, V.cos_o);
+            F3v = fresnel(nn.w, kk.w, V.cos_o);
+          }
           float4 bb = b4[q];
           bb.x *= (mirror ? F0 : (1.0f - F0) * rr.x) * inv_p;
           bb.y *= (mirror ? F1 : (1.0f - F1) * rr.y) * inv_p;
@@ -1210,8 +1214,13 @@ hipError_t launch_escape(const Launch& L, const DevScene& S, const DevWS& w, int
 
 hipError_t launch_shade_opaque(const Launch& L, const DevScene& S, const DevWS& w, int depth, int max_depth,
                                uint64_t seed, int gen, const PathMode& pm) {
-  hipLaunchKernelGGL(k_shade_opaque, dim3(grid_for(w.W, 4096)), dim3(kWG), 0, L.stream, S, w, depth, max_depth,
-                     (uint32_t)seed, (uint32_t)(seed >> 32), gen, pm);
+  const dim3 g(grid_for(w.W, 4096)), b(kWG);
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+  switch (w.Bp / 4) {
+    case 2: hipLaunchKernelGGL(k_shade_opaque<2>, g, b, 0, L.stream, S, w, depth, max_depth, k0, k1, gen, pm); break;
+    case 10: hipLaunchKernelGGL(k_shade_opaque<10>, g, b, 0, L.stream, S, w, depth, max_depth, k0, k1, gen, pm); break;
+    default: hipLaunchKernelGGL(k_shade_opaque<0>, g, b, 0, L.stream, S, w, depth, max_depth, k0, k1, gen, pm);
+  }
   return hipGetLastError();
 }
 
@@ -1234,8 +1243,9 @@ hipError_t launch_pack_rays(const Launch& L, const DevScene& S, const DevWS& w, 
   return hipGetLastError();
 }
 
-hipError_t launch_unpack_hits(const Launch& L, const DevWS& w, uint32_t n, float* t, int32_t* id, float* u, float* v) {
-  hipLaunchKernelGGL(k_unpack_hits, dim3(grid_for(n)), dim3(kWG), 0, L.stream, w, n, t, id, u, v);
+hipError_t launch_unpack_hits(const Launch& L, const DevScene& S, const DevWS& w, uint32_t n, float* t, int32_t* id,
+                              float* u, float* v) {
+  hipLaunchKernelGGL(k_unpack_hits, dim3(grid_for(n)), dim3(kWG), 0, L.stream, S, w, n, t, id, u, v);
   return hipGetLastError();
 }
 
