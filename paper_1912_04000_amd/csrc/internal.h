@@ -12,7 +12,6 @@ namespace sdd {
 // ------------------------------------------------------------------------------------------
 constexpr int kWG = 256;            // threads per workgroup of the traversal/shading kernels
 constexpr int kTile = 256;          // rays of one queue key handled by one workgroup tile
-constexpr int kTopNodes = 32;       // top BVH nodes of a cell staged in LDS per tile
 constexpr int kShortStack = 12;     // traversal stack entries kept in LDS per thread
 constexpr int kMaxStack = 48;       // builder caps BVH depth so the stack never exceeds this
 constexpr int kMaxCross = 8;        // glass crossings recorded per shadow ray
@@ -133,7 +132,7 @@ struct DevWS {
   float4* hit;       // [W] (t, id bits, u, v)
   float4* rays;      // [2W][2]  (o.xyz, skip bits) (d.xyz, slot | shadow bit)
   uint32_t* shcnt;   // [W] glass crossings of the pending shadow ray, kBlocked if blocked
-  float2* shx;       // [kMaxCross][W] (material id bits, cos theta)
+  float2* shx;       // [kMaxCross][W] glass crossings of shadow rays: (material id bits, triangle id bits)
   uint32_t* cat;     // [2][kCats][W] finished-ray lists
   uint32_t* lsrc;    // [2W] produced entries: ray index | first-visit bit
   uint32_t* ldst;    // [2W] destination cell

@@ -107,27 +107,18 @@ __device__ uint32_t start_cell(const DevScene& S, F3 o, F3 d) {
 // Slab interval of a ray inside cell (ix, iy, iz) and the axis through which it leaves.
 // The shared plane of two neighbouring cells is read from one table and evaluated with one
 // expression, so the exit distance of a cell equals the entry distance of the next exactly.
-__device__ __forceinline__ void cell_interval(const DevScene& S, int ix, int iy, int iz, F3 o, F3 d, F3 inv, float& tn,
+__device__ __forceinline__ void cell_interval(const DevScene& S, int ix, int iy, int iz, F3 o, F3 inv, float& tn,
                                               float& tf, int& axis) {
   const float* px = planes_of(S, 0);
   const float* py = planes_of(S, 1);
   const float* pz = planes_of(S, 2);
-  float n0 = -INFINITY, f0 = INFINITY, n1 = -INFINITY, f1 = INFINITY, n2 = -INFINITY, f2 = INFINITY;
-  if (d.x != 0.0f) {
-    const float a = (px[ix] - o.x) * inv.x, b = (px[ix + 1] - o.x) * inv.x;
-    n0 = fminf(a, b);
-    f0 = fmaxf(a, b);
-  }
-  if (d.y != 0.0f) {
-    const float a = (py[iy] - o.y) * inv.y, b = (py[iy + 1] - o.y) * inv.y;
-    n1 = fminf(a, b);
-    f1 = fmaxf(a, b);
-  }
-  if (d.z != 0.0f) {
-    const float a = (pz[iz] - o.z) * inv.z, b = (pz[iz + 1] - o.z) * inv.z;
-    n2 = fminf(a, b);
-    f2 = fmaxf(a, b);
-  }
+  // inv is finite (see make_pre), so no slab distance is NaN
+  const float ax = (px[ix] - o.x) * inv.x, bx = (px[ix + 1] - o.x) * inv.x;
+  const float ay = (py[iy] - o.y) * inv.y, by = (py[iy + 1] - o.y) * inv.y;
+  const float az = (pz[iz] - o.z) * inv.z, bz = (pz[iz + 1] - o.z) * inv.z;
+  const float n0 = fminf(ax, bx), f0 = fmaxf(ax, bx);
+  const float n1 = fminf(ay, by), f1 = fmaxf(ay, by);
+  const float n2 = fminf(az, bz), f2 = fmaxf(az, bz);
   tn = fmaxf(n0, fmaxf(n1, n2));
   axis = 0;
   tf = f0;
@@ -330,19 +321,45 @@ __global__ void k_unpack_hits(DevScene S, DevWS w, uint32_t n, float* t, int32_t
   }
 }
 
+// Glass crossings of the shadow ray of slot s (at most kMaxCross recorded, material and
+// triangle id each): the material and |cos| between the ray and the slab's normal of each.
+__device__ __forceinline__ void crossings(const DevScene& S, const DevWS& w, uint32_t s, uint32_t nc, int* mq,
+                                          float* cq) {
+  const float4 rd = w.rays[2 * ((size_t)w.W + s) + 1];
+  const F3 d = f3(rd.x, rd.y, rd.z);
+#pragma unroll
+  for (int q = 0; q < kMaxCross; ++q) {
+    mq[q] = 0;
+    cq[q] = 1.0f;
+    if ((uint32_t)q < nc) {
+      const float2 x = w.shx[(size_t)q * w.W + s];
+      const float4* g = S.gtris + (size_t)__float_as_uint(x.y) * 3;
+      const float4 A = g[0], B = g[1], C = g[2];
+      mq[q] = __float_as_int(x.x);
+      cq[q] = fabsf(dot3(d, geo_normal(f3(A.x, A.y, A.z), f3(B.x, B.y, B.z), f3(C.x, C.y, C.z))));
+    }
+  }
+}
+
 __global__ void k_resolve_vis(DevScene S, DevWS w, uint32_t n, float* vis) {
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const uint32_t c = w.shcnt[i];
+    const uint32_t nc = c == kBlocked ? 0u : min(c, (uint32_t)kMaxCross);
+    int mq[kMaxCross];
+    float cq[kMaxCross];
+    crossings(S, w, i, nc, mq, cq);
     for (int j = 0; j < S.n_bins; ++j) {
       float V = 0.0f;
       if (c != kBlocked) {
         V = 1.0f;
-        for (uint32_t q = 0; q < c && q < (uint32_t)kMaxCross; ++q) {
-          const float2 x = w.shx[(size_t)q * w.W + i];
-          const int m = __float_as_int(x.x);
-          float R, T;
-          slab(S.ntab[m * S.bins_pad + j], S.ktab[m * S.bins_pad + j], S.lambda[j], S.thick[m], x.y, R, T);
-          V *= T;
+#pragma unroll
+        for (int q = 0; q < kMaxCross; ++q) {
+          if ((uint32_t)q < nc) {
+            const int m = mq[q];
+            float R, T;
+            slab(S.ntab[m * S.bins_pad + j], S.ktab[m * S.bins_pad + j], S.lambda[j], S.thick[m], cq[q], R, T);
+            V *= T;
+          }
         }
       }
       vis[(size_t)i * S.n_bins + j] = V;
@@ -412,56 +429,73 @@ __global__ void k_scatter(DevWS w, int gen) {
 // ==========================================================================================
 // traversal
 // ==========================================================================================
+// Per-ray constants of the traversal: origin, reciprocal direction (box and cell slabs) and the
+// shear of the watertight test.
 struct RayPre {
-  F3 o, d, inv;
-  int kx, ky, kz;
+  F3 o, inv;
+  uint32_t k;  // axes of the watertight test's frame: kx | ky << 2 | kz << 4
   float Sx, Sy, Sz;
 };
+
+__device__ __forceinline__ float safe_dir(float c) { return fabsf(c) < 1e-18f ? copysignf(1e-18f, c) : c; }
 
 __device__ __forceinline__ RayPre make_pre(F3 o, F3 d) {
   RayPre R;
   R.o = o;
-  R.d = d;
   // hardware reciprocals (1 ulp): the box test's slack covers the extra rounding, the shear
-  // constants of the watertight test only need to be the same for every triangle of the ray
-  R.inv = f3(frcp(d.x), frcp(d.y), frcp(d.z));
+  // constants of the watertight test only need to be the same for every triangle of the ray.
+  // A direction component below 1e-18 in magnitude (zero included) is taken as +-1e-18: with an
+  // infinite reciprocal a ray lying in a box or cell face would give 0 * inf = NaN in the slab
+  // test and miss boxes it touches; the finite reciprocal makes box slabs, cell intervals and
+  // cell steps treat it consistently as tilted by 1e-18 (the triangle test keeps the exact d).
+  R.inv = f3(frcp(safe_dir(d.x)), frcp(safe_dir(d.y)), frcp(safe_dir(d.z)));
   const float ax = fabsf(d.x), ay = fabsf(d.y), az = fabsf(d.z);
-  R.kz = (ax >= ay && ax >= az) ? 0 : (ay >= az ? 1 : 2);
-  R.kx = R.kz == 2 ? 0 : R.kz + 1;
-  R.ky = R.kx == 2 ? 0 : R.kx + 1;
-  if (comp(d, R.kz) < 0.0f) {
-    const int t = R.kx;
-    R.kx = R.ky;
-    R.ky = t;
+  const int kz = (ax >= ay && ax >= az) ? 0 : (ay >= az ? 1 : 2);
+  int kx = kz == 2 ? 0 : kz + 1;
+  int ky = kx == 2 ? 0 : kx + 1;
+  if (comp(d, kz) < 0.0f) {
+    const int t = kx;
+    kx = ky;
+    ky = t;
   }
-  const float dz = comp(d, R.kz);
+  R.k = (uint32_t)kx | (uint32_t)ky << 2 | (uint32_t)kz << 4;
+  const float dz = comp(d, kz);
   R.Sz = frcp(dz);
-  R.Sx = comp(d, R.kx) * R.Sz;
-  R.Sy = comp(d, R.ky) * R.Sz;
+  R.Sx = comp(d, kx) * R.Sz;
+  R.Sy = comp(d, ky) * R.Sz;
   return R;
 }
 
+// a*b - c*d with Kahan's FMA scheme: relative error at most 2 ulp (Jeannerod, Louvet, Muller,
+// Math. Comp. 2013), so the sign is exact and the result is zero exactly when a*b == c*d.
+__device__ __forceinline__ float det2_exact_sign(float a, float b, float c, float d) {
+#pragma clang fp contract(off)
+  const float w = c * d;
+  const float e = __builtin_fmaf(-c, d, w);  // w - c*d, exactly
+  const float f = __builtin_fmaf(a, b, -w);
+  return f + e;
+}
+
 // Watertight ray/triangle test (Woop, Benthin, Wald, JCGT 2013): shear the triangle into the
-// ray's frame, evaluate the three 2D edge functions (re-evaluated in FP64 when one is exactly
-// zero), inclusive of edges, no back-face culling. Returns false or t with barycentrics.
+// ray's frame, evaluate the three 2D edge functions (re-evaluated with an exact-sign scheme
+// when one is exactly zero, where the original falls back to FP64), inclusive of edges, no
+// back-face culling. Returns false or t with barycentrics.
 __device__ __forceinline__ bool wt_test(const RayPre& R, F3 v0, F3 v1, F3 v2, float& t, float& bu, float& bv) {
 #pragma clang fp contract(off)
   const F3 A = v0 - R.o, B = v1 - R.o, C = v2 - R.o;
-  const float Akz = comp(A, R.kz), Bkz = comp(B, R.kz), Ckz = comp(C, R.kz);
-  const float Ax = comp(A, R.kx) - R.Sx * Akz, Ay = comp(A, R.ky) - R.Sy * Akz;
-  const float Bx = comp(B, R.kx) - R.Sx * Bkz, By = comp(B, R.ky) - R.Sy * Bkz;
-  const float Cx = comp(C, R.kx) - R.Sx * Ckz, Cy = comp(C, R.ky) - R.Sy * Ckz;
+  const int kx = (int)(R.k & 3u), ky = (int)((R.k >> 2) & 3u), kz = (int)(R.k >> 4);
+  const float Akz = comp(A, kz), Bkz = comp(B, kz), Ckz = comp(C, kz);
+  const float Ax = comp(A, kx) - R.Sx * Akz, Ay = comp(A, ky) - R.Sy * Akz;
+  const float Bx = comp(B, kx) - R.Sx * Bkz, By = comp(B, ky) - R.Sy * Bkz;
+  const float Cx = comp(C, kx) - R.Sx * Ckz, Cy = comp(C, ky) - R.Sy * Ckz;
   float U = Cx * By - Cy * Bx;
   float V = Ax * Cy - Ay * Cx;
   float W = Bx * Ay - By * Ax;
   if (U == 0.0f || V == 0.0f || W == 0.0f) {
-    const double Ud = (double)Cx * (double)By - (double)Cy * (double)Bx;
-    const double Vd = (double)Ax * (double)Cy - (double)Ay * (double)Cx;
-    const double Wd = (double)Bx * (double)Ay - (double)By * (double)Ax;
-    if ((Ud < 0.0 || Vd < 0.0 || Wd < 0.0) && (Ud > 0.0 || Vd > 0.0 || Wd > 0.0)) return false;
-    U = (float)Ud;
-    V = (float)Vd;
-    W = (float)Wd;
+    U = det2_exact_sign(Cx, By, Cy, Bx);
+    V = det2_exact_sign(Ax, Cy, Ay, Cx);
+    W = det2_exact_sign(Bx, Ay, By, Ax);
+    if ((U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f)) return false;
   } else if ((U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f)) {
     return false;
   }
@@ -508,7 +542,7 @@ struct TraceState {
 };
 
 // What one traversal step did, for the work counters.
-enum : int { kStepNone = 0, kStepNode = 1, kStepTri = 2 };
+enum : int { kStepNone = 0, kStepNode = 1, kStepTri = 2, kStepCross = 3 /* a triangle test that crossed glass */ };
 
 // Traverse the BVH of one cell for hits with t > 0, t >= t_lo, t < t_hi. One loop serves both
 // ray kinds (lanes of a wave may hold either): a closest-hit ray shrinks its far bound with every
@@ -520,80 +554,76 @@ enum : int { kStepNone = 0, kStepNode = 1, kStepTri = 2 };
 // pending leaf (a second one is pushed as a leaf entry). Doing one unit per step keeps the
 // lanes of a wave on the same kind of work. Returns false when the cell's traversal is
 // finished: nothing pending and the stack empty, or a shadow ray blocked by an opaque triangle.
+// pend: the pending leaf as count << 27 | next triangle; none pending while the count is 0.
 __device__ __forceinline__ bool trav_step(const DevScene& S, const DevWS& w, const RayPre& R, bool shadow, int4 cinfo,
-                                          const float4* lds_nodes, int n_lds, uint32_t* stack_lds, uint32_t* spill,
-                                          uint32_t spill_stride, uint32_t skip, float t_lo, float t_hi,
-                                          float box_lo, uint32_t slot, TraceState& st, uint32_t& node, int& sp,
-                                          uint32_t& pend_idx, uint32_t& pend_cnt, int& work) {
-  if (pend_cnt == 0 && node == kNoNode) {
+                                          uint32_t* stack_lds,
+                                          uint32_t* spill, uint32_t spill_stride, uint32_t skip, float t_lo,
+                                          float t_hi, uint32_t slot, TraceState& st, uint32_t& node, int& sp,
+                                          uint32_t& pend, int& work) {
+  if ((pend >> 27) == 0 && node == kNoNode) {
     if (sp == 0) return false;
     --sp;
-    const uint32_t e = sp < kShortStack ? stack_lds[sp * kWG] : spill[(size_t)(sp - kShortStack) * spill_stride];
+    // LDS and global memory are read through pointers of their own address spaces, so the two
+    // loads are not merged into one slower generic load
+    uint32_t e = ((const __attribute__((address_space(3))) uint32_t*)stack_lds)[min(sp, kShortStack - 1) * kWG];
+    if (sp >= kShortStack)
+      e = ((const __attribute__((address_space(1))) uint32_t*)spill)[(size_t)(sp - kShortStack) * spill_stride];
     if (e & kStackLeaf) {
-      pend_idx = e & kStackLeafMaxIndex;
-      pend_cnt = (e >> 27) & kStackLeafMaxCount;
+      pend = e & ~kStackLeaf;
     } else {
       node = e;
     }
   }
-  if (pend_cnt > 0) {
-    const float4* ctris = S.ctris + (size_t)cinfo.z * 3;
-    const uint32_t tri = pend_idx++;
-    --pend_cnt;
-    const float4 A = ctris[tri * 3 + 0], B = ctris[tri * 3 + 1], C = ctris[tri * 3 + 2];
-    const uint32_t id = __float_as_uint(A.w);
+  // One load of four float4 serves both kinds of step: a triangle (three of them; the fourth
+  // re-reads the first) or a node, so a wave whose lanes do different kinds of work waits for
+  // one memory round trip per step.
+  const bool is_tri = (pend >> 27) != 0;
+  const uint32_t tri = pend & kStackLeafMaxIndex;
+  if (is_tri) pend = pend + 1u - (1u << 27);  // next triangle, one fewer left (indices stay below 2^27)
+  const float4* src = is_tri ? S.ctris + ((size_t)cinfo.z + tri) * 3 : S.nodes + ((size_t)cinfo.x + node) * 4;
+  const float4 q0 = src[0], q1 = src[1], q2 = src[2], q3 = src[is_tri ? 0 : 3];
+  // an empty statement that reads all four: the loads are issued together here instead of the
+  // node-only ones being moved into the node branch (a second round trip)
+  asm volatile("" ::"v"(q0.x), "v"(q0.y), "v"(q0.z), "v"(q0.w), "v"(q1.x), "v"(q1.y), "v"(q1.z), "v"(q1.w),
+               "v"(q2.x), "v"(q2.y), "v"(q2.z), "v"(q2.w), "v"(q3.x), "v"(q3.y), "v"(q3.z), "v"(q3.w));
+  if (is_tri) {
+    const uint32_t id = __float_as_uint(q0.w);
     if (id == skip) return true;
     work = kStepTri;
     float t, u, v;
-    if (!wt_test(R, f3(A.x, A.y, A.z), f3(B.x, B.y, B.z), f3(C.x, C.y, C.z), t, u, v)) return true;
+    if (!wt_test(R, f3(q0.x, q0.y, q0.z), f3(q1.x, q1.y, q1.z), f3(q2.x, q2.y, q2.z), t, u, v)) return true;
     if (!(t > 0.0f && t >= t_lo && t < t_hi)) return true;
     if (shadow) {
-      const int m = (int)__float_as_uint(B.w);
+      const int m = (int)__float_as_uint(q1.w);
       if (S.mtype[m] == 0) {
         st.blocked = true;
         return false;
       }
-      const F3 ng = geo_normal(f3(A.x, A.y, A.z), f3(B.x, B.y, B.z), f3(C.x, C.y, C.z));
       if (st.ncross < (uint32_t)kMaxCross)
-        w.shx[(size_t)st.ncross * w.W + slot] = make_float2(__int_as_float(m), fabsf(dot3(R.d, ng)));
+        w.shx[(size_t)st.ncross * w.W + slot] = make_float2(__int_as_float(m), __uint_as_float(id));
       st.ncross++;
+      work = kStepCross;
     } else if (t < st.tbest || (t == st.tbest && id < st.best_id)) {
       st.tbest = t;
       st.best_id = id;
     }
     return true;
   }
-  float4 na, nb, nc, nd;
-  if ((int)node < n_lds) {
-    na = lds_nodes[node * 4 + 0];
-    nb = lds_nodes[node * 4 + 1];
-    nc = lds_nodes[node * 4 + 2];
-    nd = lds_nodes[node * 4 + 3];
-  } else {
-    const float4* gnodes = S.nodes + (size_t)cinfo.x * 4;
-    na = gnodes[node * 4 + 0];
-    nb = gnodes[node * 4 + 1];
-    nc = gnodes[node * 4 + 2];
-    nd = gnodes[node * 4 + 3];
-  }
+  const float4 na = q0, nb = q1, nc = q2, nd = q3;
   const uint32_t i0 = __float_as_uint(nd.x), i1 = __float_as_uint(nd.y);
   const uint32_t c0 = __float_as_uint(nd.z), c1 = __float_as_uint(nd.w);
   work = kStepNode;
   bool h0, h1;
   float t0, t1;
-  box2(R, na, nb, nc, box_lo, shadow ? t_hi : st.tbest, h0, t0, h1, t1);
+  box2(R, na, nb, nc, fmaxf(t_lo, 0.0f), shadow ? t_hi : st.tbest, h0, t0, h1, t1);
   h0 = h0 && i0 != kEmptyChild;
   h1 = h1 && i1 != kEmptyChild;
   // leaf children: the first becomes pending, a second is pushed as a leaf entry
   const bool l0 = h0 && c0, l1 = h1 && c1;
-  if (l0) {
-    pend_idx = i0;
-    pend_cnt = c0;
-  }
+  if (l0) pend = (c0 << 27) | i0;
   if (l1) {
     if (!l0) {
-      pend_idx = i1;
-      pend_cnt = c1;
+      pend = (c1 << 27) | i1;
     } else {
       const uint32_t e = kStackLeaf | (c1 << 27) | i1;
       if (sp < kShortStack)
@@ -623,6 +653,11 @@ __device__ __forceinline__ bool trav_step(const DevScene& S, const DevWS& w, con
   return true;
 }
 
+// Cell index of a packed cell position ix | iy << 6 | iz << 12 (higher bits ignored).
+__device__ __forceinline__ uint32_t cpos_cell(const DevScene& S, uint32_t cpos) {
+  return (((cpos >> 12) & 63u) * (uint32_t)S.gy + ((cpos >> 6) & 63u)) * (uint32_t)S.gx + (cpos & 63u);
+}
+
 // Lane phases of k_trace.
 enum : int { kLaneIdle = 0, kLaneEnter = 1, kLaneTrav = 2, kLaneLeave = 3, kLaneDone = 4 };
 
@@ -633,9 +668,8 @@ enum : int { kLaneIdle = 0, kLaneEnter = 1, kLaneTrav = 2, kLaneLeave = 3, kLane
 // but the last the ray then migrates to the queue of the next cell, in the last round it walks
 // on in place. Finished rays go to LDS lists that the workgroup flushes to the global category
 // lists and the migration list once the tile is drained.
-__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(5))) void k_trace(DevScene S, DevWS w, int gen, int hops,
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(7))) void k_trace(DevScene S, DevWS w, int gen, int hops,
                                                                                                int cat_par) {
-  __shared__ float4 s_nodes[kTopNodes * 4];
   __shared__ uint32_t s_stack[kShortStack * kWG];
   __shared__ uint32_t s_next[2];
   __shared__ uint32_t s_fetch, s_ncat, s_nreq;
@@ -650,7 +684,6 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(5))) void k
   const int np = (gen + 1) & 1;
   // work counters: wave-uniform sums of ballots (scalar registers)
   uint32_t n_visit = 0, n_migr = 0, n_esc = 0, n_glass = 0, n_xover = 0, n_nodes = 0, n_tris = 0;
-  int prev_cell = -1;
   // Tiles are handed out dynamically: each XCD owns a contiguous range of the cell-sorted tiles
   // (its L2 then holds few cells at a time) and its workgroups take the next tile of that range
   // from a counter; a workgroup whose range is exhausted takes tiles from the other XCDs' ranges.
@@ -680,21 +713,19 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(5))) void k
     const int tcell = (int)(tile.x / kDirBins);
     const uint32_t tdir = tile.x % kDirBins;
     const int4 tinfo = S.cells[tcell];
-    const int n_top = min(tinfo.y, kTopNodes);
-    if (tcell != prev_cell) {
-      for (int q = threadIdx.x; q < n_top * 4; q += kWG) s_nodes[q] = S.nodes[(size_t)tinfo.x * 4 + q];
-      __syncthreads();
-      prev_cell = tcell;
-    }
     int phase = kLaneIdle;
     RayPre R;
-    R.o = R.d = R.inv = f3(0.0f, 0.0f, 0.0f);
-    R.kx = R.ky = R.kz = 0;
+    R.o = R.inv = f3(0.0f, 0.0f, 0.0f);
+    R.k = 0;
     R.Sx = R.Sy = R.Sz = 0.0f;
-    uint32_t r = 0, slot = 0, skip = 0, node = 0, ncross0 = 0, pend_idx = 0, pend_cnt = 0;
+    uint32_t slot = 0, skip = 0, node = 0, pend = 0;
+    // cell coordinates, cells entered so far and the exit axis of the current cell:
+    // ix | iy << 6 | iz << 12 | hops << 18 | axis << 26 (grids are at most 64 per axis, so a
+    // ray enters fewer than 256 cells)
+    uint32_t cpos = 0;
     bool shadow = false, first = false;
-    int ix = 0, iy = 0, iz = 0, cell = 0, h = 0, sp = 0, axis = 0, nl = 0;
-    float t_lo = 0.0f, tf = 0.0f, box_lo = 0.0f;
+    int sp = 0;
+    float t_lo = 0.0f, tf = 0.0f;
     int4 cinfo = make_int4(0, 0, 0, 0);
     TraceState st;
     st.tbest = INFINITY;
@@ -706,7 +737,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(5))) void k
         const uint32_t i = atomicAdd(&s_fetch, 1u);
         if (i < tile.z) {
           const uint32_t entry = w.queue[tile.y + i];
-          r = entry & ~kFirstVisit;
+          const uint32_t r = entry & ~kFirstVisit;
           first = (entry & kFirstVisit) != 0;
           const float4 ro = w.rays[2 * r], rd = w.rays[2 * r + 1];
           skip = __float_as_uint(ro.w);
@@ -714,16 +745,12 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(5))) void k
           shadow = (sw & kShadowBit) != 0;
           slot = sw & ~kShadowBit;
           R = make_pre(f3(ro.x, ro.y, ro.z), f3(rd.x, rd.y, rd.z));
-          cell = tcell;
-          ix = cell % S.gx;
-          iy = (cell / S.gx) % S.gy;
-          iz = cell / (S.gx * S.gy);
-          h = 0;
+          cpos = (uint32_t)(tcell % S.gx) | (uint32_t)((tcell / S.gx) % S.gy) << 6 |
+                 (uint32_t)(tcell / (S.gx * S.gy)) << 12;
           st.tbest = INFINITY;
           st.best_id = 0xFFFFFFFFu;
           st.blocked = false;
           st.ncross = shadow ? w.shcnt[slot] : 0u;
-          ncross0 = st.ncross;
           phase = kLaneEnter;
         } else {
           phase = kLaneDone;
@@ -736,24 +763,26 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(5))) void k
       if (phase == kLaneEnter) {
         // the cell's slab interval; traversal starts unless the cell is empty or already passed
         float tn;
-        cell_interval(S, ix, iy, iz, R.o, R.d, R.inv, tn, tf, axis);
+        const int ix = (int)(cpos & 63u), iy = (int)((cpos >> 6) & 63u), iz = (int)((cpos >> 12) & 63u);
+        const int cell = (int)cpos_cell(S, cpos);
+        int axis;
+        cell_interval(S, ix, iy, iz, R.o, R.inv, tn, tf, axis);
+        cpos = (cpos & ~(3u << 26)) | (uint32_t)axis << 26;
         t_lo = first ? -INFINITY : tn;
         cinfo = cell == tcell ? tinfo : S.cells[cell];
         if (cinfo.y > 0 && t_lo < tf) {
-          nl = cell == tcell ? n_top : 0;
           if (!shadow) st.tbest = tf;
-          box_lo = fmaxf(t_lo, 0.0f);
           node = 0;
           sp = 0;
-          pend_cnt = 0;
+          pend = 0;
           phase = kLaneTrav;
         } else {
           phase = kLaneLeave;
         }
       }
       if (phase == kLaneTrav) {
-        if (!trav_step(S, w, R, shadow, cinfo, s_nodes, nl, stack, spill, w.trace_threads, skip, t_lo, tf, box_lo,
-                       slot, st, node, sp, pend_idx, pend_cnt, work)) {
+        if (!trav_step(S, w, R, shadow, cinfo, stack, spill, w.trace_threads, skip, t_lo, tf, slot, st, node, sp, pend,
+                       work)) {
           if (shadow && st.blocked) {
             w.shcnt[slot] = kBlocked;
             fin = true;
@@ -769,12 +798,11 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(5))) void k
       }
       if (phase == kLaneLeave) {
         // leave through the exit face (Amanatides-Woo step)
-        const float dc = comp(R.d, axis);
-        int* idx = axis == 0 ? &ix : (axis == 1 ? &iy : &iz);
+        const int axis = (int)((cpos >> 26) & 3u);
+        const float dc = comp(R.inv, axis);  // same sign as the direction component
         const int g = axis == 0 ? S.gx : (axis == 1 ? S.gy : S.gz);
-        *idx += dc > 0.0f ? 1 : -1;
-        ++h;
-        if (*idx < 0 || *idx >= g || !(tf < INFINITY)) {
+        const int ni = (int)((cpos >> (6 * axis)) & 63u) + (dc > 0.0f ? 1 : -1);
+        if (ni < 0 || ni >= g || !(tf < INFINITY)) {
           if (!shadow) {
             w.hit[slot] = make_float4(INFINITY, __uint_as_float(0xFFFFFFFFu), 0.0f, 0.0f);
             if (S.env_nonzero) out_cat = kCatEscape;
@@ -784,9 +812,10 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(5))) void k
           esc = true;
           fin = true;
         } else {
-          cell = (iz * S.gy + iy) * S.gx + ix;
+          cpos = (cpos & ~(63u << (6 * axis))) | ((uint32_t)ni << (6 * axis));
+          cpos += 1u << 18;
           first = false;
-          if (h < hops) {
+          if ((int)((cpos >> 18) & 0xFFu) < hops) {
             phase = kLaneEnter;
           } else {
             out_req = true;
@@ -795,20 +824,15 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(5))) void k
         }
       }
       n_nodes += (uint32_t)__popcll(__ballot(work == kStepNode));
-      n_tris += (uint32_t)__popcll(__ballot(work == kStepTri));
+      n_tris += (uint32_t)__popcll(__ballot(work >= kStepTri));
+      n_glass += (uint32_t)__popcll(__ballot(work == kStepCross));
       n_esc += (uint32_t)__popcll(__ballot(esc));
       n_migr += (uint32_t)__popcll(__ballot(out_req));
-      const bool crossed = fin && shadow && !st.blocked && st.ncross != ncross0;
-      if (__ballot(crossed) != 0) {
-        uint32_t dg = crossed ? st.ncross - ncross0 : 0u;
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) dg += __shfl_xor(dg, o);
-        n_glass += __builtin_amdgcn_readfirstlane(dg);
-        n_xover += (uint32_t)__popcll(
-            __ballot(crossed && st.ncross > (uint32_t)kMaxCross && ncross0 <= (uint32_t)kMaxCross));
-      }
+      // shadow rays that reach the sun through more slabs than were recorded
+      n_xover += (uint32_t)__popcll(
+          __ballot(fin && shadow && !st.blocked && !out_req && st.ncross > (uint32_t)kMaxCross));
       if (fin) {
-        if (crossed) w.shcnt[slot] = st.ncross;
+        if (shadow && !st.blocked) w.shcnt[slot] = st.ncross;
         if (out_cat >= 0) {
           const uint32_t c = atomicAdd(&s_ncat, 1u);
           s_cslot[c] = slot;
@@ -816,8 +840,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(5))) void k
         }
         if (out_req) {
           const uint32_t q = atomicAdd(&s_nreq, 1u);
-          s_rsrc[q] = r;
-          s_rkey[q] = qkey((uint32_t)cell, tdir);
+          s_rsrc[q] = shadow ? w.W + slot : slot;
+          s_rkey[q] = qkey(cpos_cell(S, cpos), tdir);
         }
         phase = kLaneIdle;
       }
@@ -884,14 +908,19 @@ __global__ __launch_bounds__(kWG) void k_resolve(DevScene S, DevWS w, int depth)
       const uint32_t nc = min(w.shcnt[s], (uint32_t)kMaxCross);
       const float* e = w.nee + (size_t)s * Bp;
       float* l = w.lacc + (size_t)s * Bp;
+      int mq[kMaxCross];
+      float cq[kMaxCross];
+      crossings(S, w, s, nc, mq, cq);
       for (int j = 0; j < S.n_bins; ++j) {
         float V = 1.0f;
-        for (uint32_t q = 0; q < nc; ++q) {
-          const float2 x = w.shx[(size_t)q * w.W + s];
-          const int m = __float_as_int(x.x);
-          float Rq, Tq;
-          slab(S.ntab[m * Bp + j], S.ktab[m * Bp + j], S.lambda[j], S.thick[m], x.y, Rq, Tq);
-          V *= Tq;
+#pragma unroll
+        for (int q = 0; q < kMaxCross; ++q) {
+          if ((uint32_t)q < nc) {
+            const int m = mq[q];
+            float Rq, Tq;
+            slab(S.ntab[m * Bp + j], S.ktab[m * Bp + j], S.lambda[j], S.thick[m], cq[q], Rq, Tq);
+            V *= Tq;
+          }
         }
         l[j] += e[j] * V;
       }

@@ -116,6 +116,68 @@ def test_trace_skip_and_ragged(ctx):
     _compare_hits(ctx, sc, S, c[:1].astype(np.float32), d[:1].astype(np.float32), label="one ray")
 
 
+def _grid_mesh(n, origin, ex, ey):
+    """n x n quads over origin + i ex + j ey, two triangles each with alternating diagonals; the
+    triangles share their float32 vertices exactly."""
+    o, ex, ey = (np.asarray(a, dtype=np.float64) for a in (origin, ex, ey))
+    P = np.array([[o + i * ex + j * ey for i in range(n + 1)] for j in range(n + 1)], dtype=np.float32)
+    tris = []
+    for j in range(n):
+        for i in range(n):
+            a, b, c, d = P[j, i], P[j, i + 1], P[j + 1, i + 1], P[j + 1, i]
+            tris += [(a, b, c), (a, c, d)] if (i + j) % 2 else [(a, b, d), (b, c, d)]
+    return P, np.asarray(tris, dtype=np.float32)
+
+
+def _inside(tri, p, tol):
+    """Barycentrics of p (projected on the triangle's plane) are all >= -tol."""
+    a, b, c = (tri[:, k].astype(np.float64) for k in range(3))
+    v0, v1, v2 = b - a, c - a, p - a
+    d00, d01, d11 = (v0 * v0).sum(1), (v0 * v1).sum(1), (v1 * v1).sum(1)
+    d20, d21 = (v2 * v0).sum(1), (v2 * v1).sum(1)
+    den = d00 * d11 - d01 * d01
+    bv = (d11 * d20 - d01 * d21) / den
+    bw = (d00 * d21 - d01 * d20) / den
+    return (bv >= -tol) & (bw >= -tol) & (1 - bv - bw >= -tol)
+
+
+@pytest.mark.parametrize("frame", ["axis", "tilted"])
+def test_watertight_shared_edges_and_vertices(ctx, frame):
+    """Rays through the shared vertices, edge midpoints and quad centres of a closed triangle grid
+    all hit it, each a triangle that contains the hit point (the watertight test, including the
+    exactly-zero edge functions of the axis-aligned case, leaks nowhere; the grid's cell
+    boundaries cross the mesh)."""
+    import dataclasses
+    n = 24
+    if frame == "axis":
+        origin, ex, ey, d = (0.0, 0.0, 0.0), (1.0, 0.0, 0.0), (0.0, 1.0, 0.0), np.array([0.0, 0.0, -1.0])
+    else:
+        e1 = np.array([0.83, 0.31, 0.12])
+        e2 = np.cross([0.1, -0.2, 1.0], e1)
+        e2 *= np.linalg.norm(e1) / np.linalg.norm(e2)
+        origin, ex, ey = (1.5, -2.25, 0.75), e1, e2
+        nrm = np.cross(e1, e2)
+        d = -(nrm / np.linalg.norm(nrm) + np.array([0.21, -0.17, 0.05]))
+    d = (d / np.linalg.norm(d)).astype(np.float32)
+    P, tris = _grid_mesh(n, origin, ex, ey)
+    sc = dataclasses.replace(scenegen.plane_scene(8), verts=tris, mat=np.zeros(len(tris), np.uint16)).check()
+    S = _scene(ctx, sc, (3, 3, 2))
+    inner = P[1:n, 1:n].reshape(-1, 3).astype(np.float64)
+    mid_x = 0.5 * (P[1:n, :-1].astype(np.float64) + P[1:n, 1:].astype(np.float64))
+    mid_y = 0.5 * (P[:-1, 1:n].astype(np.float64) + P[1:, 1:n].astype(np.float64))
+    cen = 0.25 * (P[:-1, :-1].astype(np.float64) + P[1:, 1:] + P[:-1, 1:] + P[1:, :-1])
+    targets = np.concatenate([inner, mid_x.reshape(-1, 3), mid_y.reshape(-1, 3), cen.reshape(-1, 3)]).astype(np.float32)
+    o = (targets.astype(np.float64) - 2.0 * d.astype(np.float64)).astype(np.float32)
+    dd = np.broadcast_to(d, o.shape).copy()
+    t, ids, u, v = ctx.trace(S, _dev(o), _dev(dd))
+    t, ids = t.cpu().numpy(), ids.cpu().numpy()
+    say(f"[watertight {frame}] rays={len(o)} misses={(ids < 0).sum()}")
+    assert (ids >= 0).all(), np.nonzero(ids < 0)[0][:10]
+    hp = o.astype(np.float64) + t[:, None].astype(np.float64) * dd.astype(np.float64)
+    assert np.abs(hp - targets).max() <= 1e-5 * (1.0 + np.abs(targets).max())
+    assert _inside(tris[ids], hp, 1e-5).all()
+
+
 def test_shadow_parity(ctx):
     sc = scenegen.nave_scene(8)
     S = _scene(ctx, sc, (2, 2, 2))
