@@ -54,7 +54,7 @@ __global__ void k_store_views(ViewBlock vb, ViewDesc* dst, int first, int count)
 size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
 
 enum {
-  L_PIX, L_SMP, L_VIEW, L_BETA, L_NEE, L_LACC, L_HIT, L_RAYS, L_SHCNT, L_SHX, L_CAT, L_LSRC, L_LDST, L_LRANK,
+  L_PIX, L_SMP, L_VIEW, L_BETA, L_NEE, L_LACC, L_HIT, L_RAYS, L_SHCNT, L_SHX, L_CAT, L_CATB, L_LSRC, L_LDST, L_LRANK,
   L_QUEUE, L_CCOUNT, L_COFF, L_TILES, L_SPILL, L_CTL, L_VIEWS, L_COUNT
 };
 
@@ -93,6 +93,7 @@ Plan make_plan(uint32_t W, int B, int n_cells, int n_views) {
   sz[L_SHCNT] = 4ull * W;
   sz[L_SHX] = 8ull * kMaxCross * W;
   sz[L_CAT] = 4ull * 2 * kCats * W;
+  sz[L_CATB] = 4ull * ((2ull * W + 3) / 4);
   sz[L_LSRC] = 8ull * W;
   sz[L_LDST] = 8ull * W;
   sz[L_LRANK] = 8ull * W;
@@ -127,6 +128,7 @@ DevWS ws_view(const Plan& p, void* base) {
   w.shcnt = (uint32_t*)(b + p.off[L_SHCNT]);
   w.shx = (float2*)(b + p.off[L_SHX]);
   w.cat = (uint32_t*)(b + p.off[L_CAT]);
+  w.catb = (uint8_t*)(b + p.off[L_CATB]);
   w.lsrc = (uint32_t*)(b + p.off[L_LSRC]);
   w.ldst = (uint32_t*)(b + p.off[L_LDST]);
   w.lrank = (uint32_t*)(b + p.off[L_LRANK]);
@@ -218,11 +220,13 @@ int trace_phase(sdd_ctx* ctx, const Launch& L, const DevScene& S, const DevWS& w
     HIP_TRY(ctx, launch_scan(L, S, w, gen));
     HIP_TRY(ctx, launch_scatter(L, w, gen));
     if (timing) record(ctx, ctx->ev_trace, ctx->ev_used_trace, true);
-    HIP_TRY(ctx, launch_trace(L, S, w, gen, hops, cat_par));
+    HIP_TRY(ctx, launch_trace(L, S, w, gen, hops));
     if (timing) record(ctx, ctx->ev_trace, ctx->ev_used_trace, false);
     ctx->acc.trace_launches++;
     ++gen;
   }
+  // the finished rays' category bytes become the lists the shading kernels read
+  HIP_TRY(ctx, launch_gather_cats(L, w, cat_par));
   return SDD_OK;
 }
 
@@ -264,6 +268,7 @@ int run_paths(sdd_ctx* ctx, const sdd_scene* scene, const sdd_render_params* p, 
   const int D = p->max_depth;
   const bool query = cache && pm.purpose == 0 && D >= kCacheDepth;
   HIP_TRY(ctx, launch_fill_u32(ctx->stream, &w.ctl->cat_count[0][0], 2 * 8, 0u));
+  HIP_TRY(ctx, launch_fill_u32(ctx->stream, (uint32_t*)w.catb, ((size_t)2 * w.W + 3) / 4, 0u));
   HIP_TRY(ctx, launch_raygen(L, S, w, k0, n, p->seed, gen, pm));
   int rc = trace_phase(ctx, L, S, w, gen, rounds, 1, timing);
   if (rc) return rc;
@@ -656,6 +661,7 @@ static int query(sdd_ctx* c, const sdd_scene* s, const float* orig, const float*
   for (int64_t a = 0; a < n; a += W) {
     uint32_t m = (uint32_t)std::min<int64_t>(W, n - a);
     HIP_TRY(c, launch_fill_u32(c->stream, &w.ctl->cat_count[0][0], 2 * 8, 0u));
+    HIP_TRY(c, launch_fill_u32(c->stream, (uint32_t*)w.catb, ((size_t)2 * w.W + 3) / 4, 0u));
     HIP_TRY(c, launch_pack_rays(L, S, w, orig + 3 * a, dir + 3 * a, skip ? skip + a : nullptr, m, shadow ? 1 : 0, gen));
     rc = trace_phase(c, L, S, w, gen, kQueryRounds, 0, false);
     if (rc) return rc;

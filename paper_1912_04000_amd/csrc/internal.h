@@ -134,6 +134,7 @@ struct DevWS {
   uint32_t* shcnt;   // [W] glass crossings of the pending shadow ray, kBlocked if blocked
   float2* shx;       // [kMaxCross][W] glass crossings of shadow rays: (material id bits, triangle id bits)
   uint32_t* cat;     // [2][kCats][W] finished-ray lists
+  uint8_t* catb;     // [2W] category + 1 of the finished extension (first W) / shadow ray of a slot
   uint32_t* lsrc;    // [2W] produced entries: ray index | first-visit bit
   uint32_t* ldst;    // [2W] destination cell
   uint32_t* lrank;   // [2W] rank inside the destination cell
@@ -218,7 +219,8 @@ hipError_t launch_raygen(const Launch& L, const DevScene& S, const DevWS& w, uin
                          int gen, const PathMode& pm);
 hipError_t launch_scan(const Launch& L, const DevScene& S, const DevWS& w, int gen);
 hipError_t launch_scatter(const Launch& L, const DevWS& w, int gen);
-hipError_t launch_trace(const Launch& L, const DevScene& S, const DevWS& w, int gen, int hops, int cat_par);
+hipError_t launch_trace(const Launch& L, const DevScene& S, const DevWS& w, int gen, int hops);
+hipError_t launch_gather_cats(const Launch& L, const DevWS& w, int par);
 hipError_t launch_resolve(const Launch& L, const DevScene& S, const DevWS& w, int depth);
 hipError_t launch_escape(const Launch& L, const DevScene& S, const DevWS& w, int depth);
 hipError_t launch_shade_opaque(const Launch& L, const DevScene& S, const DevWS& w, int depth, int max_depth,

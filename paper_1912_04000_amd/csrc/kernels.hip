@@ -265,9 +265,8 @@ __global__ __launch_bounds__(kWG) void k_raygen(DevScene S, DevWS w, uint64_t k0
   const int p = gen & 1;
   wave_append(valid && cell != kInvalidCell, i | kFirstVisit, qkey(cell, qdir), &w.ctl->list_count[p],
               ccount_of(S, w, p), w.lsrc, w.ldst, w.lrank);
-  // camera rays that miss the grid box escape at once (bounce 1 lists, parity 1)
-  wave_push(valid && cell == kInvalidCell && S.env_nonzero, i, &w.ctl->cat_count[1][kCatEscape],
-            cat_list(w, 1, kCatEscape));
+  // camera rays that miss the grid box escape at once
+  if (valid && cell == kInvalidCell && S.env_nonzero) w.catb[i] = (uint8_t)(kCatEscape + 1);
   wave_add(&w.ctl->st_paths, valid ? 1u : 0u);
   wave_add(&w.ctl->st_ext, valid ? 1u : 0u);
 }
@@ -668,13 +667,10 @@ enum : int { kLaneIdle = 0, kLaneEnter = 1, kLaneTrav = 2, kLaneLeave = 3, kLane
 // but the last the ray then migrates to the queue of the next cell, in the last round it walks
 // on in place. Finished rays go to LDS lists that the workgroup flushes to the global category
 // lists and the migration list once the tile is drained.
-__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(7))) void k_trace(DevScene S, DevWS w, int gen, int hops,
-                                                                                               int cat_par) {
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(7))) void k_trace(DevScene S, DevWS w, int gen, int hops) {
   __shared__ uint32_t s_stack[kShortStack * kWG];
   __shared__ uint32_t s_next[2];
-  __shared__ uint32_t s_fetch, s_ncat, s_nreq;
-  __shared__ uint32_t s_cslot[kTile];
-  __shared__ uint8_t s_ccat[kTile];
+  __shared__ uint32_t s_fetch, s_nreq;
   __shared__ uint32_t s_rsrc[kTile], s_rkey[kTile];
   const uint32_t n_tiles = w.ctl->n_tiles;
   const uint32_t xcd = blockIdx.x % kXcds;
@@ -703,7 +699,6 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(7))) void k
       }
       s_next[it & 1] = t;
       s_fetch = 0;
-      s_ncat = 0;
       s_nreq = 0;
     }
     __syncthreads();
@@ -833,11 +828,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(7))) void k
           __ballot(fin && shadow && !st.blocked && !out_req && st.ncross > (uint32_t)kMaxCross));
       if (fin) {
         if (shadow && !st.blocked) w.shcnt[slot] = st.ncross;
-        if (out_cat >= 0) {
-          const uint32_t c = atomicAdd(&s_ncat, 1u);
-          s_cslot[c] = slot;
-          s_ccat[c] = (uint8_t)out_cat;
-        }
+        // the finished ray's category, by slot: gathered into slot-ordered lists after the trace
+        if (out_cat >= 0) w.catb[(shadow ? (size_t)w.W : 0) + slot] = (uint8_t)(out_cat + 1);
         if (out_req) {
           const uint32_t q = atomicAdd(&s_nreq, 1u);
           s_rsrc[q] = shadow ? w.W + slot : slot;
@@ -846,18 +838,9 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(7))) void k
         phase = kLaneIdle;
       }
     }
-    // the tile is drained: flush its finished rays (wave-aggregated atomics on the global lists)
+    // the tile is drained: flush its migrating rays (wave-aggregated atomics)
     __syncthreads();
-    const uint32_t nc = s_ncat, nr = s_nreq;
-    for (uint32_t b0 = 0; b0 < nc; b0 += kWG) {
-      const uint32_t e = b0 + threadIdx.x;
-      const bool v = e < nc;
-      const uint32_t sl = v ? s_cslot[e] : 0u;
-      const int c = v ? (int)s_ccat[e] : -1;
-#pragma unroll
-      for (int cc = 0; cc < kCats; ++cc)
-        wave_push(c == cc, sl, &w.ctl->cat_count[cat_par][cc], cat_list(w, cat_par, cc));
-    }
+    const uint32_t nr = s_nreq;
     for (uint32_t b0 = 0; b0 < nr; b0 += kWG) {
       const uint32_t e = b0 + threadIdx.x;
       const bool v = e < nr;
@@ -874,6 +857,88 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(7))) void k
     if (n_xover) atomicAdd(&w.ctl->err_cross, (unsigned long long)n_xover);
     if (n_nodes) atomicAdd(&w.ctl->st_nodes, (unsigned long long)n_nodes);
     if (n_tris) atomicAdd(&w.ctl->st_tris, (unsigned long long)n_tris);
+  }
+}
+
+// Finished rays carry their category in a byte per ray slot (extension rays in the first W,
+// shadow rays in the second W; 0 = none). This pass turns the bytes into the per-category
+// lists of one bounce and clears them. A workgroup compacts a chunk of kWG * kGatherPer
+// consecutive slots with a prefix sum, so each chunk lands in the lists in ascending slot
+// order (the shading kernels then read neighbouring path slots together) at the cost of one
+// atomic per category and chunk.
+constexpr int kGatherPer = 16;
+
+__global__ __launch_bounds__(kWG) void k_gather_cats(DevWS w, int par) {
+  constexpr int kWaves = kWG / 64;
+  __shared__ uint32_t s_wsum[kCats][kWaves];
+  __shared__ uint32_t s_base[kCats];
+  const size_t n = 2 * (size_t)w.W;
+  const size_t chunk = (size_t)kWG * kGatherPer;
+  const uint32_t lane = lane_id(), wv = threadIdx.x / 64;
+  for (size_t c0 = (size_t)blockIdx.x * chunk; c0 < n; c0 += (size_t)gridDim.x * chunk) {
+    const size_t i0 = c0 + (size_t)threadIdx.x * kGatherPer;
+    uint8_t b[kGatherPer];
+    const bool whole = i0 + kGatherPer <= n;
+    if (whole) {
+      const uint4 v = *(const uint4*)(w.catb + i0);  // the byte lists start 256-byte aligned
+      const uint32_t x[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int j = 0; j < kGatherPer; ++j) b[j] = (uint8_t)(x[j >> 2] >> (8 * (j & 3)));
+    } else {
+#pragma unroll
+      for (int j = 0; j < kGatherPer; ++j) b[j] = i0 + j < n ? w.catb[i0 + j] : (uint8_t)0;
+    }
+    uint32_t cnt[kCats];
+#pragma unroll
+    for (int c = 0; c < kCats; ++c) cnt[c] = 0;
+#pragma unroll
+    for (int j = 0; j < kGatherPer; ++j)
+#pragma unroll
+      for (int c = 0; c < kCats; ++c) cnt[c] += b[j] == (uint8_t)(c + 1) ? 1u : 0u;
+    // exclusive prefix of the counts over the workgroup: within the wave, then over waves
+    uint32_t pre[kCats];
+#pragma unroll
+    for (int c = 0; c < kCats; ++c) {
+      uint32_t incl = cnt[c];
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o);
+        if (lane >= (uint32_t)o) incl += y;
+      }
+      pre[c] = incl - cnt[c];
+      if (lane == 63) s_wsum[c][wv] = incl;
+    }
+    __syncthreads();
+    if (threadIdx.x < kCats) {
+      const int c = threadIdx.x;
+      uint32_t tot = 0;
+      for (int q = 0; q < kWaves; ++q) {
+        const uint32_t x = s_wsum[c][q];
+        s_wsum[c][q] = tot;
+        tot += x;
+      }
+      s_base[c] = tot ? atomicAdd(&w.ctl->cat_count[par][c], tot) : 0u;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < kCats; ++c) pre[c] += s_base[c] + s_wsum[c][wv];
+#pragma unroll
+    for (int j = 0; j < kGatherPer; ++j) {
+      if (b[j]) {
+        const size_t i = i0 + j;
+        const uint32_t slot = (uint32_t)(i < w.W ? i : i - w.W);
+#pragma unroll
+        for (int c = 0; c < kCats; ++c)
+          if (b[j] == (uint8_t)(c + 1)) cat_list(w, par, c)[pre[c]++] = slot;
+      }
+    }
+    if (whole) {
+      *(uint4*)(w.catb + i0) = make_uint4(0u, 0u, 0u, 0u);
+    } else {
+      for (int j = 0; j < kGatherPer; ++j)
+        if (i0 + j < n) w.catb[i0 + j] = 0;
+    }
+    __syncthreads();  // s_wsum / s_base are rewritten by the next chunk
   }
 }
 
@@ -1093,11 +1158,9 @@ __global__ __launch_bounds__(kWG) void k_shade_opaque(DevScene S, DevWS w, int d
                 ccount_of(S, w, gp), w.lsrc, w.ldst, w.lrank);
     wave_append(has_sh && sh_cell != kInvalidCell, ((uint32_t)W + s) | kFirstVisit, qkey(sh_cell, sh_dir),
                 &w.ctl->list_count[gp], ccount_of(S, w, gp), w.lsrc, w.ldst, w.lrank);
-    // rays that miss the grid box finish at once: straight into the next bounce's lists
-    wave_push(has_sh && sh_cell == kInvalidCell, s, &w.ctl->cat_count[p ^ 1][kCatShadowClear],
-              cat_list(w, p ^ 1, kCatShadowClear));
-    wave_push(has_ext && ext_cell == kInvalidCell && S.env_nonzero, s, &w.ctl->cat_count[p ^ 1][kCatEscape],
-              cat_list(w, p ^ 1, kCatEscape));
+    // rays that miss the grid box finish at once
+    if (has_sh && sh_cell == kInvalidCell) w.catb[(size_t)W + s] = (uint8_t)(kCatShadowClear + 1);
+    if (has_ext && ext_cell == kInvalidCell && S.env_nonzero) w.catb[s] = (uint8_t)(kCatEscape + 1);
     wave_add(&w.ctl->st_vertices, valid ? 1u : 0u);
     wave_add(&w.ctl->st_shadow, has_sh ? 1u : 0u);
     wave_add(&w.ctl->st_ext, has_ext ? 1u : 0u);
@@ -1153,8 +1216,7 @@ __global__ __launch_bounds__(kWG) void k_shade_glass(DevScene S, DevWS w, int de
     }
     wave_append(valid && ext_cell != kInvalidCell, s | kFirstVisit, qkey(ext_cell, ext_dir), &w.ctl->list_count[gp],
                 ccount_of(S, w, gp), w.lsrc, w.ldst, w.lrank);
-    wave_push(valid && ext_cell == kInvalidCell && S.env_nonzero, s, &w.ctl->cat_count[p ^ 1][kCatEscape],
-              cat_list(w, p ^ 1, kCatEscape));
+    if (valid && ext_cell == kInvalidCell && S.env_nonzero) w.catb[s] = (uint8_t)(kCatEscape + 1);
     wave_add(&w.ctl->st_vertices, valid ? 1u : 0u);
     wave_add(&w.ctl->st_ext, valid ? 1u : 0u);
   }
@@ -1226,8 +1288,14 @@ hipError_t launch_scatter(const Launch& L, const DevWS& w, int gen) {
   return hipGetLastError();
 }
 
-hipError_t launch_trace(const Launch& L, const DevScene& S, const DevWS& w, int gen, int hops, int cat_par) {
-  hipLaunchKernelGGL(k_trace, dim3(L.trace_blocks), dim3(kWG), 0, L.stream, S, w, gen, hops, cat_par);
+hipError_t launch_trace(const Launch& L, const DevScene& S, const DevWS& w, int gen, int hops) {
+  hipLaunchKernelGGL(k_trace, dim3(L.trace_blocks), dim3(kWG), 0, L.stream, S, w, gen, hops);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_cats(const Launch& L, const DevWS& w, int par) {
+  const size_t chunks = (2 * (size_t)w.W + (size_t)kWG * kGatherPer - 1) / ((size_t)kWG * kGatherPer);
+  hipLaunchKernelGGL(k_gather_cats, dim3((unsigned)std::min<size_t>(chunks, 4096)), dim3(kWG), 0, L.stream, w, par);
   return hipGetLastError();
 }
 
