@@ -348,7 +348,9 @@ __global__ __launch_bounds__(kCWG) __attribute__((amdgpu_waves_per_eu(2))) void 
   __shared__ __attribute__((aligned(16))) float u[kMaxBins * kCacheWidth];
   __shared__ __attribute__((aligned(16))) uint16_t Es[kCacheWaves * kCacheVerts * kCacheERow];
   __shared__ float Ys[kCacheWaves * kCacheVerts * 8];
+  __shared__ uint32_t s_st[1];
   const int B = S.n_bins;
+  stats_init(s_st, 1);
   build_u_table(C, B, u);
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, v = lane & 31;
@@ -375,8 +377,10 @@ __global__ __launch_bounds__(kCWG) __attribute__((amdgpu_waves_per_eu(2))) void 
     }
     query_wave<true>(C, B, u, Es + wave * kCacheVerts * kCacheERow, Ys + wave * kCacheVerts * 8, lane, valid, s, x,
                      wo, mat, W, w4, o);
-    wave_add(&w.ctl->st_queries, (valid && lane < 32) ? 1u : 0u);
+    stats_add_ballot(s_st, 0, valid && lane < 32);
   }
+  __syncthreads();
+  stats_flush(s_st, 0, &w.ctl->st_queries);
 }
 
 // Network output y (before the clamp at zero) for explicit vertices: out [n][B].

@@ -70,6 +70,24 @@ __device__ __forceinline__ uint32_t count_below(uint64_t m) {
 }
 
 
+// Statistics counters of a workgroup in LDS: every wave adds its count with one LDS atomic, and
+// at the end of the kernel one thread per counter adds the workgroup's totals to the global
+// counters, a handful of global atomics per workgroup instead of one per wave and loop
+// iteration on the same few addresses. stats_init is followed by a barrier before the first
+// stats_add; stats_add is called by every lane of the wave; stats_flush by every thread.
+__device__ __forceinline__ void stats_init(uint32_t* s, int n) {
+  if ((int)threadIdx.x < n) s[threadIdx.x] = 0;
+}
+__device__ __forceinline__ void stats_add(uint32_t* s, int i, uint32_t wave_count) {
+  if (lane_id() == 0 && wave_count) atomicAdd(&s[i], wave_count);
+}
+__device__ __forceinline__ void stats_add_ballot(uint32_t* s, int i, bool pred) {
+  stats_add(s, i, (uint32_t)__popcll(__ballot(pred)));
+}
+__device__ __forceinline__ void stats_flush(const uint32_t* s, int i, unsigned long long* ctr) {
+  if ((int)threadIdx.x == i && s[i]) atomicAdd(ctr, (unsigned long long)s[i]);
+}
+
 // Wave-level sum, then one 64-bit atomic per wave.
 __device__ __forceinline__ void wave_add(unsigned long long* ctr, uint32_t x) {
 #pragma unroll

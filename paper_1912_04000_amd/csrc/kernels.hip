@@ -56,6 +56,78 @@ __device__ void wave_append(bool valid, uint32_t src, uint32_t cell, uint32_t* l
   }
 }
 
+// Rank of each valid lane's entry inside its destination queue key: lanes grouped by key, one
+// atomic per distinct key of the wave (as in wave_append). Every lane of the wave must call it.
+__device__ uint32_t wave_key_rank(bool valid, uint32_t key, uint32_t* cell_count) {
+  const uint64_t m = __ballot(valid);
+  if (m == 0) return 0;
+  uint32_t my_leader = 0, my_off = 0, gcount = 0;
+  bool is_leader = false;
+  uint64_t pending = m;
+  while (pending) {
+    const uint32_t l = (uint32_t)__ffsll((unsigned long long)pending) - 1u;
+    const uint32_t c = __shfl(key, (int)l);
+    const bool mine = valid && key == c;
+    const uint64_t same = __ballot(mine);
+    if (mine) {
+      my_leader = l;
+      my_off = count_below(same);
+    }
+    if (lane_id() == l) {
+      is_leader = true;
+      gcount = (uint32_t)__popcll(same);
+    }
+    pending &= ~same;
+  }
+  uint32_t cb = 0;
+  if (is_leader) cb = atomicAdd(&cell_count[key], gcount);
+  cb = __shfl(cb, (int)my_leader);
+  return cb + my_off;
+}
+
+// Workgroup-level append of up to two (src, key) entries per lane (all threads of the
+// workgroup call it; s_scr holds kWG / 64 words of LDS): the positions in the produced-entry
+// list come from one list-counter atomic per workgroup and a prefix over its waves, the ranks
+// inside the destination queues from wave_key_rank. Meant for one-shot kernels: inside a loop
+// its two barriers cost more than the per-wave list atomics of wave_append they save.
+__device__ void block_append2(uint32_t* s_scr, bool v0, uint32_t src0, uint32_t key0, bool v1, uint32_t src1,
+                              uint32_t key1, uint32_t* list_count, uint32_t* cell_count, uint32_t* lsrc,
+                              uint32_t* ldst, uint32_t* lrank) {
+  constexpr int kWaves = kWG / 64;
+  const uint32_t wv = threadIdx.x >> 6;
+  const uint64_t m0 = __ballot(v0), m1 = __ballot(v1);
+  const uint32_t c0 = (uint32_t)__popcll(m0);
+  if (lane_id() == 0) s_scr[wv] = c0 + (uint32_t)__popcll(m1);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t tot = 0;
+    for (int q = 0; q < kWaves; ++q) tot += s_scr[q];
+    uint32_t base = tot ? atomicAdd(list_count, tot) : 0u;
+    for (int q = 0; q < kWaves; ++q) {
+      const uint32_t x = s_scr[q];
+      s_scr[q] = base;
+      base += x;
+    }
+  }
+  __syncthreads();
+  // each wave reads only its own word, which no thread rewrites before the next call's barrier
+  const uint32_t wbase = s_scr[wv];
+  const uint32_t r0 = wave_key_rank(v0, key0, cell_count);
+  const uint32_t r1 = wave_key_rank(v1, key1, cell_count);
+  if (v0) {
+    const uint32_t pos = wbase + count_below(m0);
+    lsrc[pos] = src0;
+    ldst[pos] = key0;
+    lrank[pos] = r0;
+  }
+  if (v1) {
+    const uint32_t pos = wbase + c0 + count_below(m1);
+    lsrc[pos] = src1;
+    ldst[pos] = key1;
+    lrank[pos] = r1;
+  }
+}
+
 // ==========================================================================================
 // cell grid
 // ==========================================================================================
@@ -216,6 +288,8 @@ __device__ __forceinline__ uint32_t* cat_list(const DevWS& w, int par, int cat) 
 template <bool kTrain>
 __global__ __launch_bounds__(kWG) void k_raygen(DevScene S, DevWS w, uint64_t k0, uint32_t n, uint32_t key0,
                                                 uint32_t key1, int gen, PathMode pm) {
+  __shared__ uint32_t s_st[1];
+  stats_init(s_st, 1);
   const uint32_t i = blockIdx.x * kWG + threadIdx.x;
   const bool valid = i < n;
   uint32_t cell = kInvalidCell, qdir = 0;
@@ -263,12 +337,16 @@ __global__ __launch_bounds__(kWG) void k_raygen(DevScene S, DevWS w, uint64_t k0
     qdir = dir_bin(d);
   }
   const int p = gen & 1;
-  wave_append(valid && cell != kInvalidCell, i | kFirstVisit, qkey(cell, qdir), &w.ctl->list_count[p],
-              ccount_of(S, w, p), w.lsrc, w.ldst, w.lrank);
+  __shared__ uint32_t s_app[kWG / 64];
+  block_append2(s_app, valid && cell != kInvalidCell, i | kFirstVisit, qkey(cell, qdir), false, 0u, 0u,
+                &w.ctl->list_count[p], ccount_of(S, w, p), w.lsrc, w.ldst, w.lrank);
   // camera rays that miss the grid box escape at once
   if (valid && cell == kInvalidCell && S.env_nonzero) w.catb[i] = (uint8_t)(kCatEscape + 1);
-  wave_add(&w.ctl->st_paths, valid ? 1u : 0u);
-  wave_add(&w.ctl->st_ext, valid ? 1u : 0u);
+  __syncthreads();
+  stats_add_ballot(s_st, 0, valid);
+  __syncthreads();
+  stats_flush(s_st, 0, &w.ctl->st_paths);
+  if (threadIdx.x == 0 && s_st[0]) atomicAdd(&w.ctl->st_ext, (unsigned long long)s_st[0]);
 }
 
 // User rays (closest-hit or shadow queries).
@@ -295,8 +373,9 @@ __global__ __launch_bounds__(kWG) void k_pack_rays(DevScene S, DevWS w, const fl
       w.hit[i] = make_float4(INFINITY, __uint_as_float(0xFFFFFFFFu), 0.0f, 0.0f);
   }
   const int p = gen & 1;
-  wave_append(valid && cell != kInvalidCell, r | kFirstVisit, qkey(cell, qdir), &w.ctl->list_count[p],
-              ccount_of(S, w, p), w.lsrc, w.ldst, w.lrank);
+  __shared__ uint32_t s_app[kWG / 64];
+  block_append2(s_app, valid && cell != kInvalidCell, r | kFirstVisit, qkey(cell, qdir), false, 0u, 0u,
+                &w.ctl->list_count[p], ccount_of(S, w, p), w.lsrc, w.ldst, w.lrank);
 }
 
 // Hit records hold the FP32 distance and the triangle id; the distance and barycentrics handed
@@ -849,15 +928,25 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(7))) void k
     }
     __syncthreads();
   }
-  if (lane_id() == 0) {
-    if (n_visit) atomicAdd(&w.ctl->st_visits, (unsigned long long)n_visit);
-    if (n_migr) atomicAdd(&w.ctl->st_migr, (unsigned long long)n_migr);
-    if (n_esc) atomicAdd(&w.ctl->st_escape, (unsigned long long)n_esc);
-    if (n_glass) atomicAdd(&w.ctl->st_glass, (unsigned long long)n_glass);
-    if (n_xover) atomicAdd(&w.ctl->err_cross, (unsigned long long)n_xover);
-    if (n_nodes) atomicAdd(&w.ctl->st_nodes, (unsigned long long)n_nodes);
-    if (n_tris) atomicAdd(&w.ctl->st_tris, (unsigned long long)n_tris);
-  }
+  // the workgroup's counts, then one global atomic per counter
+  __shared__ uint32_t s_st[7];
+  stats_init(s_st, 7);
+  __syncthreads();
+  stats_add(s_st, 0, n_visit);
+  stats_add(s_st, 1, n_migr);
+  stats_add(s_st, 2, n_esc);
+  stats_add(s_st, 3, n_glass);
+  stats_add(s_st, 4, n_xover);
+  stats_add(s_st, 5, n_nodes);
+  stats_add(s_st, 6, n_tris);
+  __syncthreads();
+  stats_flush(s_st, 0, &w.ctl->st_visits);
+  stats_flush(s_st, 1, &w.ctl->st_migr);
+  stats_flush(s_st, 2, &w.ctl->st_escape);
+  stats_flush(s_st, 3, &w.ctl->st_glass);
+  stats_flush(s_st, 4, &w.ctl->err_cross);
+  stats_flush(s_st, 5, &w.ctl->st_nodes);
+  stats_flush(s_st, 6, &w.ctl->st_tris);
 }
 
 // Finished rays carry their category in a byte per ray slot (extension rays in the first W,
@@ -1035,6 +1124,9 @@ __device__ __forceinline__ void record_vertex(const PathMode& pm, const DevWS& w
 template <int NQ>
 __global__ __launch_bounds__(kWG) void k_shade_opaque(DevScene S, DevWS w, int depth, int max_depth, uint32_t key0,
                                                       uint32_t key1, int gen, PathMode pm) {
+  __shared__ uint32_t s_st[3];
+  stats_init(s_st, 3);
+  __syncthreads();
   const int p = depth & 1;
   const uint32_t n = w.ctl->cat_count[p][kCatOpaque];
   const uint32_t* list = cat_list(w, p, kCatOpaque);
@@ -1161,16 +1253,23 @@ __global__ __launch_bounds__(kWG) void k_shade_opaque(DevScene S, DevWS w, int d
     // rays that miss the grid box finish at once
     if (has_sh && sh_cell == kInvalidCell) w.catb[(size_t)W + s] = (uint8_t)(kCatShadowClear + 1);
     if (has_ext && ext_cell == kInvalidCell && S.env_nonzero) w.catb[s] = (uint8_t)(kCatEscape + 1);
-    wave_add(&w.ctl->st_vertices, valid ? 1u : 0u);
-    wave_add(&w.ctl->st_shadow, has_sh ? 1u : 0u);
-    wave_add(&w.ctl->st_ext, has_ext ? 1u : 0u);
+    stats_add_ballot(s_st, 0, valid);
+    stats_add_ballot(s_st, 1, has_sh);
+    stats_add_ballot(s_st, 2, has_ext);
   }
+  __syncthreads();
+  stats_flush(s_st, 0, &w.ctl->st_vertices);
+  stats_flush(s_st, 1, &w.ctl->st_shadow);
+  stats_flush(s_st, 2, &w.ctl->st_ext);
 }
 
 // Glass vertex: thin slab, reflect with probability mean R / (mean R + mean T), else transmit
 // straight through (no lateral shift); no direct term at glass.
 __global__ __launch_bounds__(kWG) void k_shade_glass(DevScene S, DevWS w, int depth, uint32_t key0, uint32_t key1,
                                                      int gen, PathMode pm) {
+  __shared__ uint32_t s_st[1];
+  stats_init(s_st, 1);
+  __syncthreads();
   const int p = depth & 1;
   const uint32_t n = w.ctl->cat_count[p][kCatGlass];
   const uint32_t* list = cat_list(w, p, kCatGlass);
@@ -1217,9 +1316,11 @@ __global__ __launch_bounds__(kWG) void k_shade_glass(DevScene S, DevWS w, int de
     wave_append(valid && ext_cell != kInvalidCell, s | kFirstVisit, qkey(ext_cell, ext_dir), &w.ctl->list_count[gp],
                 ccount_of(S, w, gp), w.lsrc, w.ldst, w.lrank);
     if (valid && ext_cell == kInvalidCell && S.env_nonzero) w.catb[s] = (uint8_t)(kCatEscape + 1);
-    wave_add(&w.ctl->st_vertices, valid ? 1u : 0u);
-    wave_add(&w.ctl->st_ext, valid ? 1u : 0u);
+    stats_add_ballot(s_st, 0, valid);
   }
+  __syncthreads();
+  stats_flush(s_st, 0, &w.ctl->st_vertices);
+  if (threadIdx.x == 0 && s_st[0]) atomicAdd(&w.ctl->st_ext, (unsigned long long)s_st[0]);
 }
 
 // End of a wavefront: every path's gathered radiance, divided by the view's spp, into its
