@@ -345,6 +345,11 @@ def crop_camera(cam, cw, ch):
     return scenegen.Camera(eye=cam.eye, target=cam.target, up=cam.up, vfov_deg=vf, width=cw, height=ch)
 
 
+def _progress(msg):
+    # long workloads report their steps on stderr (the JSON line stays the only stdout line)
+    print(msg, file=sys.stderr, flush=True)
+
+
 def bench_large(args):
     """C5: procedural church of ~10M triangles (200 windows), 80 bins (5 nm), 3840x2160, 16x8x8
     cells, depth 8. Plain 256 spp against the cache-terminated path given the same wall time
@@ -374,6 +379,7 @@ def bench_large(args):
                                       out=ref_img))
     ref = ref_img.double().cpu().numpy()
     del ref_img
+    _progress(f"large: scene {sc.n_tri} triangles built in {build_s:.1f} s, reference window in {t_ref:.1f} s")
 
     def rmse_window(img):
         sub = img[:, y0:y0 + ch, x0:x0 + cw].double().cpu().numpy()
@@ -388,6 +394,7 @@ def bench_large(args):
                                                                 timing=1), out=img))
     st_plain = ctx.stats()
     r_plain = rmse_window(img)
+    _progress(f"large: plain {spp_plain} spp in {t_plain:.1f} s, RMSE {r_plain:.3e}")
     # cached, same wall time
     lo = sc.verts.reshape(-1, 3).min(0) - 0.05
     hi = sc.verts.reshape(-1, 3).max(0) + 0.05
@@ -407,6 +414,7 @@ def bench_large(args):
         t_cached += dt
         if done_spp & (done_spp - 1) == 0:
             chunks.append(dict(spp=done_spp, seconds=t_cached, rmse=rmse_window(acc)))
+            _progress(f"large: cached {done_spp} spp after {t_cached:.1f} s")
     st_c = ctx.stats()
     r_cached = rmse_window(acc)
     chunks.append(dict(spp=done_spp, seconds=t_cached, rmse=r_cached))
