@@ -349,6 +349,9 @@ int sdd_cache_get_records(sdd_ctx* ctx, sdd_cache* cache, int64_t n, float* rec_
 int sdd_finish(sdd_ctx* ctx);
 
 typedef struct {
+  /* glass_crossings: glass slabs crossed by shadow rays (also by rays an opaque triangle blocks
+   * later); err_cross_overflow: shadow rays that reached the sun through more slabs than the
+   * kMaxCross = 8 recorded ones (sdd_finish reports SDD_ERR_QUEUE_OVERFLOW then) */
   uint64_t paths, vertices, ext_rays, shadow_rays, cell_visits, migrations, escapes, glass_crossings;
   uint64_t trace_launches, shade_launches, wavefronts;
   uint64_t err_cross_overflow, err_nonfinite, err_stack;
