@@ -76,8 +76,9 @@ struct CellBVH {
   int max_leaf = 0;
 };
 
-constexpr int kBins = 16;
-constexpr int kLeaf = 4;
+constexpr int kBins = 64;
+constexpr int kLeafMax = 4;        // largest leaf the cost rule may keep
+constexpr double kCostNode = 1.0;      // a node visit against one triangle test
 constexpr int kDepthCap = kMaxStack - 2;
 
 // Recursive binned-SAH build. Returns the child descriptor for refs[first, first+count).
@@ -98,7 +99,7 @@ Child build_rec(std::vector<Ref>& refs, int first, int count, int depth, std::ve
     out.max_leaf = std::max(out.max_leaf, count);
     return ch;
   };
-  if (count <= kLeaf || depth >= kDepthCap) return make_leaf();
+  if (count <= 1 || depth >= kDepthCap) return make_leaf();
 
   int best_axis = -1, best_split = -1;
   double best_cost = INFINITY;
@@ -139,6 +140,10 @@ Child build_rec(std::vector<Ref>& refs, int first, int count, int depth, std::ve
       if (cost < best_cost) { best_cost = cost; best_axis = ax; best_split = s; }
     }
   }
+  // a leaf costs one test per triangle; a split one node visit plus the children's triangles
+  // weighted by the chance that a ray through this box enters each child (area ratio)
+  if (count <= kLeafMax && best_axis >= 0 && count <= kCostNode + best_cost / bb.area()) return make_leaf();
+  if (count <= kLeafMax && best_axis < 0) return make_leaf();
   int mid;
   if (best_axis < 0) {
     // all centroids coincide: split the list in halves (boxes overlap, still correct)
