@@ -13,7 +13,8 @@ namespace sdd {
 constexpr int kWG = 256;            // threads per workgroup of the traversal/shading kernels
 constexpr int kTile = 256;          // rays of one queue key handled by one workgroup tile
 constexpr int kShortStack = 12;     // traversal stack entries kept in LDS per thread
-constexpr int kMaxStack = 48;       // builder caps BVH depth so the stack never exceeds this
+constexpr int kMaxStack = 72;       // builder caps BVH depth so the stack never exceeds this
+constexpr int kWide = 4;            // children per BVH node
 constexpr int kMaxCross = 8;        // glass crossings recorded per shadow ray
 constexpr int kMaxBins = 128;
 constexpr int kMaxGrid = 64;
@@ -60,11 +61,11 @@ struct SceneHeader {
 };
 static_assert(sizeof(SceneHeader) <= 256, "header fits in 256 bytes");
 
-// Node of a cell BVH: the two child boxes are stored in the parent (64 bytes):
-//   a = (c0.lo.x, c0.hi.x, c0.lo.y, c0.hi.y)   b = (c1.lo.x, c1.hi.x, c1.lo.y, c1.hi.y)
-//   c = (c0.lo.z, c0.hi.z, c1.lo.z, c1.hi.z)   d = (idx0, idx1, cnt0, cnt1) as int bits
-// cnt > 0: leaf with cnt cell triangles starting at idx (cell-relative); cnt == 0: inner node
-// idx (cell-relative); idx == kEmptyChild: no child.
+// Node of a cell BVH: four children, their boxes stored in the parent (128 bytes, one cache
+// line), one float4 per box coordinate over the four children:
+//   lo.x[4] | hi.x[4] | lo.y[4] | hi.y[4] | lo.z[4] | hi.z[4] | word[4] | 0
+// word: an inner child's node index (cell-relative, < 2^27), a leaf as count << 27 | first
+// cell triangle (count 1..15), or kEmptyChild for no child.
 // Cell triangle (48 bytes): (v0, global id) (v1, material id) (v2, 0).
 // Global triangle: the same 48-byte record indexed by the triangle id.
 

@@ -587,27 +587,48 @@ __device__ __forceinline__ bool wt_test(const RayPre& R, F3 v0, F3 v1, F3 v2, fl
   return true;
 }
 
-// Both child boxes of a node against [tmin, tmax] (robust slab test, Ize 2013: the far
+// The four child boxes of a 4-wide node against [tmin, tmax] (robust slab test, Ize 2013: the far
 // distance is scaled by 1 + 2 gamma_5 so that rounding never culls a box the ray touches; a slab
 // distance carries the subtraction, the product and the 1-ulp reciprocal, four roundings, and
-// gamma_5 keeps one in reserve).
-__device__ __forceinline__ void box2(const RayPre& R, float4 a, float4 b, float4 c, float tmin, float tmax, bool& h0,
-                                     float& t0, bool& h1, float& t1) {
+// gamma_5 keeps one in reserve): the entry distance of each hit child and its word, +inf and
+// kEmptyChild for a missed or empty one.
+__device__ __forceinline__ void box4(const RayPre& R, float4 lx, float4 hx, float4 ly, float4 hy, float4 lz, float4 hz,
+                                     float4 words, float tmin, float tmax, float (&t)[kWide], uint32_t (&w)[kWide]) {
   constexpr float kSlop = 1.0f + 2.0f * 5.0f * 5.9604645e-8f / (1.0f - 5.0f * 5.9604645e-8f);
-  const float x0 = (a.x - R.o.x) * R.inv.x, x1 = (a.y - R.o.x) * R.inv.x;
-  const float y0 = (a.z - R.o.y) * R.inv.y, y1 = (a.w - R.o.y) * R.inv.y;
-  const float z0 = (c.x - R.o.z) * R.inv.z, z1 = (c.y - R.o.z) * R.inv.z;
-  const float n0 = fmaxf(fmaxf(fminf(x0, x1), fminf(y0, y1)), fmaxf(fminf(z0, z1), tmin));
-  const float f0 = fminf(fminf(fmaxf(x0, x1), fmaxf(y0, y1)), fmaxf(z0, z1)) * kSlop;
-  h0 = n0 <= fminf(f0, tmax);
-  t0 = n0;
-  const float X0 = (b.x - R.o.x) * R.inv.x, X1 = (b.y - R.o.x) * R.inv.x;
-  const float Y0 = (b.z - R.o.y) * R.inv.y, Y1 = (b.w - R.o.y) * R.inv.y;
-  const float Z0 = (c.z - R.o.z) * R.inv.z, Z1 = (c.w - R.o.z) * R.inv.z;
-  const float n1 = fmaxf(fmaxf(fminf(X0, X1), fminf(Y0, Y1)), fmaxf(fminf(Z0, Z1), tmin));
-  const float f1 = fminf(fminf(fmaxf(X0, X1), fmaxf(Y0, Y1)), fmaxf(Z0, Z1)) * kSlop;
-  h1 = n1 <= fminf(f1, tmax);
-  t1 = n1;
+  const float LX[4] = {lx.x, lx.y, lx.z, lx.w}, HX[4] = {hx.x, hx.y, hx.z, hx.w};
+  const float LY[4] = {ly.x, ly.y, ly.z, ly.w}, HY[4] = {hy.x, hy.y, hy.z, hy.w};
+  const float LZ[4] = {lz.x, lz.y, lz.z, lz.w}, HZ[4] = {hz.x, hz.y, hz.z, hz.w};
+  const uint32_t W[4] = {__float_as_uint(words.x), __float_as_uint(words.y), __float_as_uint(words.z),
+                         __float_as_uint(words.w)};
+#pragma unroll
+  for (int c = 0; c < kWide; ++c) {
+    const float x0 = (LX[c] - R.o.x) * R.inv.x, x1 = (HX[c] - R.o.x) * R.inv.x;
+    const float y0 = (LY[c] - R.o.y) * R.inv.y, y1 = (HY[c] - R.o.y) * R.inv.y;
+    const float z0 = (LZ[c] - R.o.z) * R.inv.z, z1 = (HZ[c] - R.o.z) * R.inv.z;
+    const float n = fmaxf(fmaxf(fminf(x0, x1), fminf(y0, y1)), fmaxf(fminf(z0, z1), tmin));
+    const float f = fminf(fminf(fmaxf(x0, x1), fmaxf(y0, y1)), fmaxf(z0, z1)) * kSlop;
+    const bool hit = n <= fminf(f, tmax) && W[c] != kEmptyChild;
+    t[c] = hit ? n : INFINITY;
+    w[c] = hit ? W[c] : kEmptyChild;
+  }
+}
+
+// Sorting network on four (distance, word) pairs, ascending distance.
+__device__ __forceinline__ void cswap(float (&t)[kWide], uint32_t (&w)[kWide], int a, int b) {
+  const bool s = t[b] < t[a];
+  const float ta = t[a], tb = t[b];
+  const uint32_t wa = w[a], wb = w[b];
+  t[a] = s ? tb : ta;
+  t[b] = s ? ta : tb;
+  w[a] = s ? wb : wa;
+  w[b] = s ? wa : wb;
+}
+__device__ __forceinline__ void sort4(float (&t)[kWide], uint32_t (&w)[kWide]) {
+  cswap(t, w, 0, 1);
+  cswap(t, w, 2, 3);
+  cswap(t, w, 0, 2);
+  cswap(t, w, 1, 3);
+  cswap(t, w, 1, 2);
 }
 
 struct TraceState {
@@ -652,18 +673,23 @@ __device__ __forceinline__ bool trav_step(const DevScene& S, const DevWS& w, con
       node = e;
     }
   }
-  // One load of four float4 serves both kinds of step: a triangle (three of them; the fourth
-  // re-reads the first) or a node, so a wave whose lanes do different kinds of work waits for
-  // one memory round trip per step.
+  // One load serves both kinds of step: a triangle (three float4) or a 4-wide node (seven), so
+  // a wave whose lanes do different kinds of work waits for one memory round trip per step.
   const bool is_tri = (pend >> 27) != 0;
   const uint32_t tri = pend & kStackLeafMaxIndex;
   if (is_tri) pend = pend + 1u - (1u << 27);  // next triangle, one fewer left (indices stay below 2^27)
-  const float4* src = is_tri ? S.ctris + ((size_t)cinfo.z + tri) * 3 : S.nodes + ((size_t)cinfo.x + node) * 4;
-  const float4 q0 = src[0], q1 = src[1], q2 = src[2], q3 = src[is_tri ? 0 : 3];
-  // an empty statement that reads all four: the loads are issued together here instead of the
+  const float4* src = is_tri ? S.ctris + ((size_t)cinfo.z + tri) * 3 : S.nodes + ((size_t)cinfo.x + node) * 8;
+  const float4 q0 = src[0], q1 = src[1], q2 = src[2];
+  float4 q3 = q0, q4 = q0, q5 = q0, q6 = q0;
+  if (!is_tri) {
+    q3 = src[3];
+    q4 = src[4];
+    q5 = src[5];
+    q6 = src[6];
+  }
+  // an empty statement that reads every load: they are issued together here instead of the
   // node-only ones being moved into the node branch (a second round trip)
-  asm volatile("" ::"v"(q0.x), "v"(q0.y), "v"(q0.z), "v"(q0.w), "v"(q1.x), "v"(q1.y), "v"(q1.z), "v"(q1.w),
-               "v"(q2.x), "v"(q2.y), "v"(q2.z), "v"(q2.w), "v"(q3.x), "v"(q3.y), "v"(q3.z), "v"(q3.w));
+  asm volatile("" ::"v"(q0.x), "v"(q1.x), "v"(q2.x), "v"(q3.x), "v"(q4.x), "v"(q5.x), "v"(q6.x));
   if (is_tri) {
     const uint32_t id = __float_as_uint(q0.w);
     if (id == skip) return true;
@@ -687,46 +713,30 @@ __device__ __forceinline__ bool trav_step(const DevScene& S, const DevWS& w, con
     }
     return true;
   }
-  const float4 na = q0, nb = q1, nc = q2, nd = q3;
-  const uint32_t i0 = __float_as_uint(nd.x), i1 = __float_as_uint(nd.y);
-  const uint32_t c0 = __float_as_uint(nd.z), c1 = __float_as_uint(nd.w);
+  // node: the four child boxes (robust slab test), hit children sorted by entry distance; the
+  // nearest becomes the next node or the pending leaf, the others are pushed farthest first
   work = kStepNode;
-  bool h0, h1;
-  float t0, t1;
-  box2(R, na, nb, nc, fmaxf(t_lo, 0.0f), shadow ? t_hi : st.tbest, h0, t0, h1, t1);
-  h0 = h0 && i0 != kEmptyChild;
-  h1 = h1 && i1 != kEmptyChild;
-  // leaf children: the first becomes pending, a second is pushed as a leaf entry
-  const bool l0 = h0 && c0, l1 = h1 && c1;
-  if (l0) pend = (c0 << 27) | i0;
-  if (l1) {
-    if (!l0) {
-      pend = (c1 << 27) | i1;
-    } else {
-      const uint32_t e = kStackLeaf | (c1 << 27) | i1;
+  float kt[kWide];
+  uint32_t kw[kWide];
+  box4(R, q0, q1, q2, q3, q4, q5, q6, fmaxf(t_lo, 0.0f), shadow ? t_hi : st.tbest, kt, kw);
+  sort4(kt, kw);
+  node = kNoNode;
+  if (kw[0] != kEmptyChild) {
+    if (kw[0] >> 27)
+      pend = kw[0];
+    else
+      node = kw[0];
+  }
+#pragma unroll
+  for (int c = kWide - 1; c >= 1; --c) {
+    if (kw[c] != kEmptyChild) {
+      const uint32_t e = (kw[c] >> 27) ? (kStackLeaf | kw[c]) : kw[c];
       if (sp < kShortStack)
         stack_lds[sp * kWG] = e;
       else
         spill[(size_t)(sp - kShortStack) * spill_stride] = e;
       ++sp;
     }
-  }
-  const bool n0 = h0 && !c0, n1 = h1 && !c1;
-  if (n0 && n1) {
-    const bool first0 = t0 <= t1;
-    const uint32_t near = first0 ? i0 : i1, far = first0 ? i1 : i0;
-    if (sp < kShortStack)
-      stack_lds[sp * kWG] = far;
-    else
-      spill[(size_t)(sp - kShortStack) * spill_stride] = far;
-    ++sp;
-    node = near;
-  } else if (n0) {
-    node = i0;
-  } else if (n1) {
-    node = i1;
-  } else {
-    node = kNoNode;
   }
   return true;
 }

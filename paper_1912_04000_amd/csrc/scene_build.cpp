@@ -68,18 +68,20 @@ struct Ref { int32_t tri; Box3 box; float cen[3]; };
 struct Child { Box3 box; uint32_t idx; uint32_t cnt; };  // cnt > 0 leaf, 0 inner, idx==kEmptyChild none
 
 struct BNode { Child c[2]; };
+struct WNode { Child c[kWide]; };  // node of the 4-wide tree the traversal reads
 
 struct CellBVH {
-  std::vector<BNode> nodes;      // BFS order after finishing
+  std::vector<WNode> nodes;      // 4-wide, breadth-first order
   std::vector<int32_t> tris;     // reference order (leaves are contiguous ranges)
-  int depth = 0;
+  int depth = 0;                 // binary build depth
+  int wdepth = 0;                // 4-wide depth
   int max_leaf = 0;
 };
 
 constexpr int kBins = 64;
 constexpr int kLeafMax = 4;        // largest leaf the cost rule may keep
 constexpr double kCostNode = 1.0;      // a node visit against one triangle test
-constexpr int kDepthCap = kMaxStack - 2;
+constexpr int kDepthCap = 46;  // binary depth cap: 4-wide depth <= 23, stack <= 3 * 23 + 1 < kMaxStack
 
 // Recursive binned-SAH build. Returns the child descriptor for refs[first, first+count).
 Child build_rec(std::vector<Ref>& refs, int first, int count, int depth, std::vector<BNode>& nodes, CellBVH& out) {
@@ -171,6 +173,45 @@ Child build_rec(std::vector<Ref>& refs, int first, int count, int depth, std::ve
   return ch;
 }
 
+// Wide node for binary node i2 (children gathered as described in build_cell); returns its
+// index in `wide`.
+uint32_t collapse(const std::vector<BNode>& bin, uint32_t i2, int depth, std::vector<WNode>& wide, CellBVH& out) {
+  out.wdepth = std::max(out.wdepth, depth);
+  Child ch[kWide];
+  int n = 0;
+  for (int c = 0; c < 2; ++c)
+    if (bin[i2].c[c].idx != kEmptyChild) ch[n++] = bin[i2].c[c];
+  while (n < kWide) {
+    int best = -1;
+    double ba = -1.0;
+    for (int k = 0; k < n; ++k)
+      if (ch[k].cnt == 0 && ch[k].box.area() > ba) {
+        ba = ch[k].box.area();
+        best = k;
+      }
+    if (best < 0) break;
+    const BNode& o = bin[ch[best].idx];
+    ch[best] = ch[--n];
+    for (int c = 0; c < 2; ++c)
+      if (o.c[c].idx != kEmptyChild) ch[n++] = o.c[c];
+  }
+  const uint32_t me = (uint32_t)wide.size();
+  wide.push_back(WNode{});
+  WNode w;
+  for (int k = 0; k < kWide; ++k) {
+    if (k < n) {
+      w.c[k] = ch[k];
+      if (ch[k].cnt == 0) w.c[k].idx = collapse(bin, ch[k].idx, depth + 1, wide, out);
+    } else {
+      w.c[k].box.empty();
+      w.c[k].idx = kEmptyChild;
+      w.c[k].cnt = 0;
+    }
+  }
+  wide[me] = w;
+  return me;
+}
+
 void build_cell(std::vector<Ref>& refs, CellBVH& out) {
   out.nodes.clear();
   out.tris.clear();
@@ -189,12 +230,17 @@ void build_cell(std::vector<Ref>& refs, CellBVH& out) {
     nodes[0] = nodes[top.idx];
     nodes[top.idx].c[0].idx = kEmptyChild;  // orphan, dropped by the BFS pass
   }
-  // breadth-first renumbering of the nodes reachable from the root
-  std::vector<uint32_t> order{0}, remap(nodes.size(), kEmptyChild);
+  // 4-wide tree: every wide node takes a binary node's children and opens its largest inner
+  // child (by box area) until it holds four, so a traversal step tests four boxes
+  std::vector<WNode> wide;
+  wide.reserve(nodes.size() / 2 + 1);
+  collapse(nodes, 0, 1, wide, out);
+  // breadth-first renumbering (the top levels of a cell form a contiguous prefix)
+  std::vector<uint32_t> order{0}, remap(wide.size(), kEmptyChild);
   remap[0] = 0;
   for (size_t q = 0; q < order.size(); ++q) {
-    const BNode& n = nodes[order[q]];
-    for (int c = 0; c < 2; ++c)
+    const WNode& n = wide[order[q]];
+    for (int c = 0; c < kWide; ++c)
       if (n.c[c].cnt == 0 && n.c[c].idx != kEmptyChild) {
         remap[n.c[c].idx] = (uint32_t)order.size();
         order.push_back(n.c[c].idx);
@@ -202,8 +248,8 @@ void build_cell(std::vector<Ref>& refs, CellBVH& out) {
   }
   out.nodes.resize(order.size());
   for (size_t q = 0; q < order.size(); ++q) {
-    BNode n = nodes[order[q]];
-    for (int c = 0; c < 2; ++c)
+    WNode n = wide[order[q]];
+    for (int c = 0; c < kWide; ++c)
       if (n.c[c].cnt == 0 && n.c[c].idx != kEmptyChild) n.c[c].idx = remap[n.c[c].idx];
     out.nodes[q] = n;
   }
@@ -386,11 +432,12 @@ std::string build_scene(const sdd_scene_desc& d, sdd_scene* out) {
   for (auto& c : cells) {
     n_nodes += c.nodes.size();
     n_refs += c.tris.size();
-    max_depth = std::max(max_depth, c.depth);
+    max_depth = std::max(max_depth, c.wdepth);
     max_leaf = std::max(max_leaf, c.max_leaf);
     if (c.tris.empty()) ++empty;
   }
-  if (max_depth >= kMaxStack) return "internal: BVH depth exceeds the traversal stack";
+  // a wide node visit pushes at most three entries
+  if (3 * max_depth + 1 > kMaxStack) return "internal: BVH depth exceeds the traversal stack";
   // the traversal stack encodes a leaf as (first triangle, count) in one word
   if (max_leaf > (int)kStackLeafMaxCount) return "scene too degenerate: a BVH leaf holds more than 15 triangles";
   for (auto& c : cells)
@@ -422,7 +469,7 @@ std::string build_scene(const sdd_scene_desc& d, sdd_scene* out) {
   size_t off = 256;
   H.off_planes = off; off = align256(off + planes.size() * 4);
   H.off_cells = off;  off = align256(off + (size_t)n_cells * 16);
-  H.off_nodes = off;  off = align256(off + n_nodes * 64);
+  H.off_nodes = off;  off = align256(off + n_nodes * 128);
   H.off_ctris = off;  off = align256(off + n_refs * 48);
   H.off_gtris = off;  off = align256(off + (size_t)N * 48);
   H.off_mtype = off;  off = align256(off + (size_t)M * 4);
@@ -451,15 +498,23 @@ std::string build_scene(const sdd_scene_desc& d, sdd_scene* out) {
     CellBVH& cb = cells[c];
     ctab[c] = make_int4((int)nb, (int)cb.nodes.size(), (int)tb, (int)cb.tris.size());
     for (size_t i = 0; i < cb.nodes.size(); ++i) {
-      const BNode& n = cb.nodes[i];
-      float* o = nodes + (nb + i) * 16;
-      const Child& a = n.c[0];
-      const Child& b = n.c[1];
-      o[0] = a.box.lo[0]; o[1] = a.box.hi[0]; o[2] = a.box.lo[1]; o[3] = a.box.hi[1];
-      o[4] = b.box.lo[0]; o[5] = b.box.hi[0]; o[6] = b.box.lo[1]; o[7] = b.box.hi[1];
-      o[8] = a.box.lo[2]; o[9] = a.box.hi[2]; o[10] = b.box.lo[2]; o[11] = b.box.hi[2];
-      uint32_t ids[4] = {a.idx, b.idx, a.cnt, b.cnt};
-      std::memcpy(o + 12, ids, 16);
+      const WNode& n = cb.nodes[i];
+      float* o = nodes + (nb + i) * 32;
+      uint32_t words[kWide];
+      for (int k = 0; k < kWide; ++k) {
+        const Child& c = n.c[k];
+        const bool none = c.idx == kEmptyChild;
+        // an empty slot: a zero box and the all-ones word (the traversal skips it by the word)
+        o[0 + k] = none ? 0.0f : c.box.lo[0];
+        o[4 + k] = none ? 0.0f : c.box.hi[0];
+        o[8 + k] = none ? 0.0f : c.box.lo[1];
+        o[12 + k] = none ? 0.0f : c.box.hi[1];
+        o[16 + k] = none ? 0.0f : c.box.lo[2];
+        o[20 + k] = none ? 0.0f : c.box.hi[2];
+        words[k] = none ? kEmptyChild : (c.cnt > 0 ? (c.cnt << 27) | c.idx : c.idx);
+      }
+      std::memcpy(o + 24, words, 16);
+      std::memset(o + 28, 0, 16);
     }
     for (size_t i = 0; i < cb.tris.size(); ++i) {
       int32_t t = cb.tris[i];

@@ -23,7 +23,7 @@ class SceneImage:
         self.planes = [pl[:g[0] + 1], pl[g[0] + 1:g[0] + g[1] + 2], pl[g[0] + g[1] + 2:]]
         self.cells = np.frombuffer(buf, dtype="<i4", count=4 * int(h["n_cells"]), offset=int(h["off_cells"])).reshape(-1, 4)
         nn = int(h["n_nodes"])
-        raw = np.frombuffer(buf, dtype="<f4", count=16 * nn, offset=int(h["off_nodes"])).reshape(nn, 16)
+        raw = np.frombuffer(buf, dtype="<f4", count=32 * nn, offset=int(h["off_nodes"])).reshape(nn, 32)
         self.node_f = raw
         self.node_u = raw.view("<u4")
         nr = int(h["n_refs"])
@@ -38,16 +38,16 @@ class SceneImage:
         self.lam = np.frombuffer(buf, dtype="<f4", count=B, offset=int(h["off_lambda"]))
 
     def child(self, node, c):
-        """(box lo[3], box hi[3], idx, cnt) of child c of a (global) node."""
+        """(box lo[3], box hi[3], idx, cnt) of child c (0..3) of a (global) 4-wide node: one float4
+        per box coordinate over the children, then the child words (inner: node index; leaf:
+        count << 27 | first triangle; EMPTY: no child)."""
         f = self.node_f[node]
-        u = self.node_u[node]
-        if c == 0:
-            lo = np.array([f[0], f[2], f[8]])
-            hi = np.array([f[1], f[3], f[9]])
-        else:
-            lo = np.array([f[4], f[6], f[10]])
-            hi = np.array([f[5], f[7], f[11]])
-        return lo, hi, int(u[12 + c]), int(u[14 + c])
+        word = int(self.node_u[node][24 + c])
+        lo = np.array([f[c], f[8 + c], f[16 + c]])
+        hi = np.array([f[4 + c], f[12 + c], f[20 + c]])
+        if word == EMPTY:
+            return lo, hi, EMPTY, 0
+        return lo, hi, word & ((1 << 27) - 1), word >> 27
 
     def cell_of_point(self, p):
         idx = []

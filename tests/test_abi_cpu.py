@@ -96,7 +96,7 @@ def test_scene_structure(grid):
         stack = [(0, None, None)]
         while stack:
             node, plo, phi = stack.pop()
-            for ch in range(2):
+            for ch in range(4):
                 lo, hi, idx, cnt = im.child(nb + node, ch)
                 if idx == EMPTY:
                     continue
