@@ -37,7 +37,7 @@ HBM_PEAK_GBPS = 8000.0
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 BF16_PEAK_TFLOPS = 2500.0   # dense bf16 matrix-core peak of MI355X
 # Algorithmic VALU operations per unit of traversal work (counted from the kernel source):
-OPS_PER_NODE = 52       # two robust slab tests (6 sub, 6 mul, 12 min/max, 1 slop mul, 1 cmp each)
+OPS_PER_NODE = 104      # four robust slab tests (6 sub, 6 mul, 12 min/max, 1 slop mul, 1 cmp each)
 OPS_PER_TRI = 56        # watertight test: translate, shear, 3 edge functions, signs, det, t, u, v
 
 
@@ -566,7 +566,7 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / ALU_PEAK_TOPS, "traffic": traffic,
                      "launches": st["trace_launches"], "avg_launch_ms": st["trace_ms"] / max(1, st["trace_launches"]),
                      "ops_per_launch": ops / max(1, st["trace_launches"]),
-                     "note": "algorithmic FP32 VALU ops (52 per BVH node, 56 per triangle test) over the "
+                     "note": "algorithmic FP32 VALU ops (104 per 4-wide BVH node, 56 per triangle test) over the "
                              "HIP-event time of the k_trace launches; peak = non-packed VALU issue rate"},
         "path_hbm": {"algorithmic_bytes_per_sample": ab / max(1, st["paths"]),
                      "achieved_GBps": ab / dt / 1e9, "peak_GBps": HBM_PEAK_GBPS,
