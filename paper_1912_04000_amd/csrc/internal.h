@@ -18,6 +18,7 @@ constexpr int kWide = 4;            // children per BVH node
 constexpr int kMaxCross = 8;        // glass crossings recorded per shadow ray
 constexpr int kMaxBins = 128;
 constexpr int kMaxGrid = 64;
+constexpr int kLdsCells = 256;      // cell tables up to this size are staged in LDS by the traversal
 constexpr int kXcds = 8;            // MI355X: 8 XCDs, workgroups dispatched round-robin
 constexpr int kDirBins = 24;        // ray queues per cell: direction octant x dominant axis
 constexpr uint32_t kBlocked = 0xFFFFFFFFu;

@@ -198,6 +198,25 @@ __device__ __forceinline__ void cell_interval(const DevScene& S, int ix, int iy,
   if (f2 < tf) { tf = f2; axis = 2; }
 }
 
+// cell_interval over a plane table (gx+1 | gy+1 | gz+1 entries) held elsewhere (LDS).
+__device__ __forceinline__ void cell_interval_pl(const float* pl, int gx, int gy, int ix, int iy, int iz, F3 o, F3 inv,
+                                                 float& tn, float& tf, int& axis) {
+  const float* px = pl;
+  const float* py = pl + gx + 1;
+  const float* pz = pl + gx + 1 + gy + 1;
+  const float ax = (px[ix] - o.x) * inv.x, bx = (px[ix + 1] - o.x) * inv.x;
+  const float ay = (py[iy] - o.y) * inv.y, by = (py[iy + 1] - o.y) * inv.y;
+  const float az = (pz[iz] - o.z) * inv.z, bz = (pz[iz + 1] - o.z) * inv.z;
+  const float n0 = fminf(ax, bx), f0 = fmaxf(ax, bx);
+  const float n1 = fminf(ay, by), f1 = fmaxf(ay, by);
+  const float n2 = fminf(az, bz), f2 = fmaxf(az, bz);
+  tn = fmaxf(n0, fmaxf(n1, n2));
+  axis = 0;
+  tf = f0;
+  if (f1 < tf) { tf = f1; axis = 1; }
+  if (f2 < tf) { tf = f2; axis = 2; }
+}
+
 // ==========================================================================================
 // spectral optics (hardware reciprocal / square root / exp2: about 1 ulp each, far inside the
 // 1e-4 parity bar, against the multi-instruction IEEE expansions)
@@ -761,6 +780,16 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(7))) void k
   __shared__ uint32_t s_next[2];
   __shared__ uint32_t s_fetch, s_nreq;
   __shared__ uint32_t s_rsrc[kTile], s_rkey[kTile];
+  // the grid's slab planes, and its cell table when small enough, staged in LDS: a ray entering
+  // a cell then waits for LDS instead of a memory round trip
+  __shared__ float s_planes[3 * (kMaxGrid + 1)];
+  __shared__ int4 s_cells[kLdsCells];
+  const int n_planes = S.gx + S.gy + S.gz + 3;
+  const bool cells_lds = S.n_cells <= kLdsCells;
+  for (int q = threadIdx.x; q < n_planes; q += kWG) s_planes[q] = S.planes[q];
+  if (cells_lds)
+    for (int q = threadIdx.x; q < S.n_cells; q += kWG) s_cells[q] = S.cells[q];
+  __syncthreads();
   const uint32_t n_tiles = w.ctl->n_tiles;
   const uint32_t xcd = blockIdx.x % kXcds;
   const uint32_t gtid = blockIdx.x * kWG + threadIdx.x;
@@ -850,10 +879,19 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(7))) void k
         const int ix = (int)(cpos & 63u), iy = (int)((cpos >> 6) & 63u), iz = (int)((cpos >> 12) & 63u);
         const int cell = (int)cpos_cell(S, cpos);
         int axis;
-        cell_interval(S, ix, iy, iz, R.o, R.inv, tn, tf, axis);
+        cell_interval_pl(s_planes, S.gx, S.gy, ix, iy, iz, R.o, R.inv, tn, tf, axis);
         cpos = (cpos & ~(3u << 26)) | (uint32_t)axis << 26;
         t_lo = first ? -INFINITY : tn;
-        cinfo = cell == tcell ? tinfo : S.cells[cell];
+        if (cell == tcell) {
+          cinfo = tinfo;
+        } else if (cells_lds) {
+          // LDS and global memory through pointers of their own address spaces (no generic load)
+          const __attribute__((address_space(3))) int* c = (const __attribute__((address_space(3))) int*)s_cells + 4 * cell;
+          cinfo = make_int4(c[0], c[1], c[2], c[3]);
+        } else {
+          const __attribute__((address_space(1))) int* c = (const __attribute__((address_space(1))) int*)S.cells + 4 * cell;
+          cinfo = make_int4(c[0], c[1], c[2], c[3]);
+        }
         if (cinfo.y > 0 && t_lo < tf) {
           if (!shadow) st.tbest = tf;
           node = 0;
