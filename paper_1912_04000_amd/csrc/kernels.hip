@@ -131,9 +131,6 @@ __device__ void block_append2(uint32_t* s_scr, bool v0, uint32_t src0, uint32_t 
 // ==========================================================================================
 // cell grid
 // ==========================================================================================
-__device__ __forceinline__ const float* planes_of(const DevScene& S, int axis) {
-  return axis == 0 ? S.planes : (axis == 1 ? S.planes + S.gx + 1 : S.planes + S.gx + 1 + S.gy + 1);
-}
 
 __device__ __forceinline__ int locate_axis(const float* pl, int g, float lo, float inv_cs, float p) {
   int i = (int)floorf((p - lo) * inv_cs);
@@ -144,29 +141,33 @@ __device__ __forceinline__ int locate_axis(const float* pl, int g, float lo, flo
 }
 
 // Start cell of a ray: the cell holding its origin, or the cell where it enters the grid box.
-// Returns kInvalidCell if the ray misses the grid box entirely.
-__device__ uint32_t start_cell(const DevScene& S, F3 o, F3 d) {
-  const float* px = planes_of(S, 0);
-  const float* py = planes_of(S, 1);
-  const float* pz = planes_of(S, 2);
+// Returns kInvalidCell if the ray misses the grid box entirely. `pl` is the plane table
+// (gx+1 | gy+1 | gz+1 entries, in global memory or a copy in LDS).
+__device__ uint32_t start_cell_pl(const DevScene& S, const float* pl, F3 o, F3 d) {
+  const float* px = pl;
+  const float* py = pl + S.gx + 1;
+  const float* pz = pl + S.gx + 1 + S.gy + 1;
   const float lo[3] = {px[0], py[0], pz[0]};
   const float hi[3] = {px[S.gx], py[S.gy], pz[S.gz]};
   const float oo[3] = {o.x, o.y, o.z}, dd[3] = {d.x, d.y, d.z};
-  float tn = -INFINITY, tf = INFINITY;
   bool inside = true;
-  for (int a = 0; a < 3; ++a) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
     if (oo[a] < lo[a] || oo[a] >= hi[a]) inside = false;
-    if (dd[a] == 0.0f) {
-      if (oo[a] < lo[a] || oo[a] > hi[a]) return kInvalidCell;
-      continue;
-    }
-    const float inv = 1.0f / dd[a];
-    float t0 = (lo[a] - oo[a]) * inv, t1 = (hi[a] - oo[a]) * inv;
-    tn = fmaxf(tn, fminf(t0, t1));
-    tf = fminf(tf, fmaxf(t0, t1));
-  }
   F3 p = o;
   if (!inside) {
+    // entry point into the grid box (slab test with IEEE reciprocals)
+    float tn = -INFINITY, tf = INFINITY;
+    for (int a = 0; a < 3; ++a) {
+      if (dd[a] == 0.0f) {
+        if (oo[a] < lo[a] || oo[a] > hi[a]) return kInvalidCell;
+        continue;
+      }
+      const float inv = 1.0f / dd[a];
+      float t0 = (lo[a] - oo[a]) * inv, t1 = (hi[a] - oo[a]) * inv;
+      tn = fmaxf(tn, fminf(t0, t1));
+      tf = fminf(tf, fmaxf(t0, t1));
+    }
     if (!(tn <= tf) || tf < 0.0f) return kInvalidCell;
     if (tn > 0.0f) p = o + d * tn;
   }
@@ -176,29 +177,13 @@ __device__ uint32_t start_cell(const DevScene& S, F3 o, F3 d) {
   return (uint32_t)((iz * S.gy + iy) * S.gx + ix);
 }
 
-// Slab interval of a ray inside cell (ix, iy, iz) and the axis through which it leaves.
-// The shared plane of two neighbouring cells is read from one table and evaluated with one
-// expression, so the exit distance of a cell equals the entry distance of the next exactly.
-__device__ __forceinline__ void cell_interval(const DevScene& S, int ix, int iy, int iz, F3 o, F3 inv, float& tn,
-                                              float& tf, int& axis) {
-  const float* px = planes_of(S, 0);
-  const float* py = planes_of(S, 1);
-  const float* pz = planes_of(S, 2);
-  // inv is finite (see make_pre), so no slab distance is NaN
-  const float ax = (px[ix] - o.x) * inv.x, bx = (px[ix + 1] - o.x) * inv.x;
-  const float ay = (py[iy] - o.y) * inv.y, by = (py[iy + 1] - o.y) * inv.y;
-  const float az = (pz[iz] - o.z) * inv.z, bz = (pz[iz + 1] - o.z) * inv.z;
-  const float n0 = fminf(ax, bx), f0 = fmaxf(ax, bx);
-  const float n1 = fminf(ay, by), f1 = fmaxf(ay, by);
-  const float n2 = fminf(az, bz), f2 = fmaxf(az, bz);
-  tn = fmaxf(n0, fmaxf(n1, n2));
-  axis = 0;
-  tf = f0;
-  if (f1 < tf) { tf = f1; axis = 1; }
-  if (f2 < tf) { tf = f2; axis = 2; }
-}
+__device__ uint32_t start_cell(const DevScene& S, F3 o, F3 d) { return start_cell_pl(S, S.planes, o, d); }
 
-// cell_interval over a plane table (gx+1 | gy+1 | gz+1 entries) held elsewhere (LDS).
+// Slab interval of a ray inside cell (ix, iy, iz) and the axis through which it leaves, over a
+// plane table (gx+1 | gy+1 | gz+1 entries; the traversal keeps a copy in LDS). The shared
+// plane of two neighbouring cells is one table entry evaluated with one expression, so the
+// exit distance of a cell equals the entry distance of the next exactly. The reciprocal
+// direction is finite (see make_pre), so no slab distance is NaN.
 __device__ __forceinline__ void cell_interval_pl(const float* pl, int gx, int gy, int ix, int iy, int iz, F3 o, F3 inv,
                                                  float& tn, float& tf, int& axis) {
   const float* px = pl;
@@ -1173,7 +1158,9 @@ template <int NQ>
 __global__ __launch_bounds__(kWG) void k_shade_opaque(DevScene S, DevWS w, int depth, int max_depth, uint32_t key0,
                                                       uint32_t key1, int gen, PathMode pm) {
   __shared__ uint32_t s_st[3];
+  __shared__ float s_planes[3 * (kMaxGrid + 1)];  // the grid's slab planes, for locating new rays
   stats_init(s_st, 3);
+  for (int q = threadIdx.x; q < S.gx + S.gy + S.gz + 3; q += kWG) s_planes[q] = S.planes[q];
   __syncthreads();
   const int p = depth & 1;
   const uint32_t n = w.ctl->cat_count[p][kCatOpaque];
@@ -1237,7 +1224,7 @@ __global__ __launch_bounds__(kWG) void k_shade_opaque(DevScene S, DevWS w, int d
         w.rays[2 * (W + s)] = make_float4(so.x, so.y, so.z, __uint_as_float(V.id));
         w.rays[2 * (W + s) + 1] = make_float4(ws.x, ws.y, ws.z, __uint_as_float(s | kShadowBit));
         w.shcnt[s] = 0;
-        sh_cell = start_cell(S, so, ws);
+        sh_cell = start_cell_pl(S, s_planes, so, ws);
         sh_dir = dir_bin(ws);
       }
       const float am = a_sum / (float)B, bm = b_sum / (float)B;
@@ -1289,7 +1276,7 @@ __global__ __launch_bounds__(kWG) void k_shade_opaque(DevScene S, DevWS w, int d
         has_ext = true;
         w.rays[2 * s] = make_float4(no.x, no.y, no.z, __uint_as_float(V.id));
         w.rays[2 * s + 1] = make_float4(nd.x, nd.y, nd.z, __uint_as_float(s));
-        ext_cell = start_cell(S, no, nd);
+        ext_cell = start_cell_pl(S, s_planes, no, nd);
         ext_dir = dir_bin(nd);
         if (ext_cell == kInvalidCell) w.hit[s] = make_float4(INFINITY, __uint_as_float(0xFFFFFFFFu), 0.0f, 0.0f);
       }
@@ -1316,7 +1303,9 @@ __global__ __launch_bounds__(kWG) void k_shade_opaque(DevScene S, DevWS w, int d
 __global__ __launch_bounds__(kWG) void k_shade_glass(DevScene S, DevWS w, int depth, uint32_t key0, uint32_t key1,
                                                      int gen, PathMode pm) {
   __shared__ uint32_t s_st[1];
+  __shared__ float s_planes[3 * (kMaxGrid + 1)];  // the grid's slab planes, for locating new rays
   stats_init(s_st, 1);
+  for (int q = threadIdx.x; q < S.gx + S.gy + S.gz + 3; q += kWG) s_planes[q] = S.planes[q];
   __syncthreads();
   const int p = depth & 1;
   const uint32_t n = w.ctl->cat_count[p][kCatGlass];
@@ -1357,7 +1346,7 @@ __global__ __launch_bounds__(kWG) void k_shade_glass(DevScene S, DevWS w, int de
       const F3 no = refl ? V.p + V.n * V.eps : V.p - V.n * V.eps;
       w.rays[2 * s] = make_float4(no.x, no.y, no.z, __uint_as_float(V.id));
       w.rays[2 * s + 1] = make_float4(nd.x, nd.y, nd.z, __uint_as_float(s));
-      ext_cell = start_cell(S, no, nd);
+      ext_cell = start_cell_pl(S, s_planes, no, nd);
       ext_dir = dir_bin(nd);
       if (ext_cell == kInvalidCell) w.hit[s] = make_float4(INFINITY, __uint_as_float(0xFFFFFFFFu), 0.0f, 0.0f);
     }
