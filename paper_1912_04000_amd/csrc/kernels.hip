@@ -453,44 +453,101 @@ __global__ void k_resolve_vis(DevScene S, DevWS w, uint32_t n, float* vis) {
 // queue: scan + scatter
 // ==========================================================================================
 constexpr int kScanThreads = 1024;
+constexpr int kScanLdsKeys = 8192;  // queue keys whose counts are staged in LDS (beyond: read from memory)
+
+// Inclusive sums over the workgroup of one value per thread: shuffles within each wave, then the
+// wave totals, scanned by the first wave through LDS.
+__device__ __forceinline__ void block_scan2(uint32_t& a, uint32_t& b, uint32_t* s_wa, uint32_t* s_wb) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t xa = __shfl_up(a, off), xb = __shfl_up(b, off);
+    if (lane >= off) {
+      a += xa;
+      b += xb;
+    }
+  }
+  if (lane == 63) {
+    s_wa[wid] = a;
+    s_wb[wid] = b;
+  }
+  __syncthreads();
+  if (wid == 0) {
+    constexpr int nw = kScanThreads / 64;
+    uint32_t ta = lane < nw ? s_wa[lane] : 0u, tb = lane < nw ? s_wb[lane] : 0u;
+#pragma unroll
+    for (int off = 1; off < nw; off <<= 1) {
+      const uint32_t xa = __shfl_up(ta, off), xb = __shfl_up(tb, off);
+      if (lane >= off) {
+        ta += xa;
+        tb += xb;
+      }
+    }
+    if (lane < nw) {
+      s_wa[lane] = ta;
+      s_wb[lane] = tb;
+    }
+  }
+  __syncthreads();
+  if (wid > 0) {
+    a += s_wa[wid - 1];
+    b += s_wb[wid - 1];
+  }
+}
 
 __global__ __launch_bounds__(kScanThreads) void k_scan(DevScene S, DevWS w, int gen) {
-  __shared__ uint32_t s_cnt[kScanThreads], s_til[kScanThreads];
+  __shared__ uint32_t s_cnt[kScanThreads], s_til[kScanThreads], s_key[kScanLdsKeys];
+  __shared__ uint32_t s_wa[kScanThreads / 64], s_wb[kScanThreads / 64];
   const int p = gen & 1;
   const uint32_t* cnt = ccount_of(S, w, p);
   const int nc = S.n_cells * kDirBins;   // queue keys: (cell, direction octant)
+  const bool staged = nc <= kScanLdsKeys;
   const int chunk = (nc + kScanThreads - 1) / kScanThreads;
   const int c0 = min(nc, (int)threadIdx.x * chunk), c1 = min(nc, c0 + chunk);
   uint32_t sc = 0, st = 0;
   for (int c = c0; c < c1; ++c) {
     const uint32_t x = cnt[c];
+    if (staged) s_key[c] = x;
     sc += x;
     st += (x + kTile - 1) / kTile;
   }
-  s_cnt[threadIdx.x] = sc;
-  s_til[threadIdx.x] = st;
+  uint32_t ic = sc, it = st;
+  block_scan2(ic, it, s_wa, s_wb);
+  s_cnt[threadIdx.x] = ic;
+  s_til[threadIdx.x] = it;
   __syncthreads();
-  // Hillis-Steele inclusive scan over the per-thread sums
-  for (int off = 1; off < kScanThreads; off <<= 1) {
-    uint32_t a = 0, b = 0;
-    if ((int)threadIdx.x >= off) {
-      a = s_cnt[threadIdx.x - off];
-      b = s_til[threadIdx.x - off];
-    }
-    __syncthreads();
-    s_cnt[threadIdx.x] += a;
-    s_til[threadIdx.x] += b;
-    __syncthreads();
-  }
-  uint32_t run = s_cnt[threadIdx.x] - sc, trun = s_til[threadIdx.x] - st;
+  uint32_t run = ic - sc;
   for (int c = c0; c < c1; ++c) {
-    const uint32_t x = cnt[c];
     w.coff[c] = run;
-    const uint32_t nt = (x + kTile - 1) / kTile;
-    for (uint32_t q = 0; q < nt; ++q)
-      w.tiles[trun + q] = make_uint4((uint32_t)c, run + q * kTile, min((uint32_t)kTile, x - q * kTile), 0u);
-    run += x;
-    trun += nt;
+    run += staged ? s_key[c] : cnt[c];
+  }
+  // Tiles are written by the whole workgroup, tile t by thread t mod kScanThreads: the thread
+  // chunk holding t is the first whose inclusive tile sum exceeds t (a binary search of s_til),
+  // and the key within the chunk follows by walking its counts. One key may hold thousands of
+  // tiles (the camera rays of a frame enter a few cells), which a per-key loop would write
+  // serially.
+  const uint32_t n_tiles = s_til[kScanThreads - 1];
+  for (uint32_t t = threadIdx.x; t < n_tiles; t += kScanThreads) {
+    int lo = 0, hi = kScanThreads - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (s_til[mid] > t)
+        hi = mid;
+      else
+        lo = mid + 1;
+    }
+    uint32_t tb = lo ? s_til[lo - 1] : 0u, cb = lo ? s_cnt[lo - 1] : 0u;
+    const int e1 = min(nc, lo * chunk + chunk);
+    for (int c = lo * chunk; c < e1; ++c) {
+      const uint32_t x = staged ? s_key[c] : cnt[c], nt = (x + kTile - 1) / kTile;
+      if (t < tb + nt) {
+        const uint32_t q = t - tb;
+        w.tiles[t] = make_uint4((uint32_t)c, cb + q * kTile, min((uint32_t)kTile, x - q * kTile), 0u);
+        break;
+      }
+      tb += nt;
+      cb += x;
+    }
   }
   if (threadIdx.x == kScanThreads - 1) {
     w.ctl->n_queue = s_cnt[kScanThreads - 1];
@@ -1072,6 +1129,23 @@ __global__ __launch_bounds__(kWG) void k_gather_cats(DevWS w, int par) {
 // Shadow rays that reached the sun (eq. 3 direct term, weight stored when the ray was spawned,
 // attenuated by every glass slab crossed). A slot holds one shadow ray at a time, so no two
 // threads of this kernel touch the same radiance row.
+// row[q] = f(q, row[q]) over the nq quads (4 bins each) of a path's spectral row, C quads at a
+// time, every load of a chunk (the row's quads and whatever tables f reads) issued before the
+// chunk's stores: rows and tables are all float memory, so a load that followed a store in
+// program order could not be issued before it and would wait a full memory round trip.
+template <int C, class F>
+__device__ __forceinline__ void row_update(float4* row, int nq, F f) {
+  for (int q0 = 0; q0 < nq; q0 += C) {
+    float4 v[C];
+#pragma unroll
+    for (int q = 0; q < C; ++q)
+      if (q0 + q < nq) v[q] = f(q0 + q, row[q0 + q]);
+#pragma unroll
+    for (int q = 0; q < C; ++q)
+      if (q0 + q < nq) row[q0 + q] = v[q];
+  }
+}
+
 __global__ __launch_bounds__(kWG) void k_resolve(DevScene S, DevWS w, int depth) {
   const int p = depth & 1;
   const uint32_t n_clear = w.ctl->cat_count[p][kCatShadowClear];
@@ -1083,34 +1157,40 @@ __global__ __launch_bounds__(kWG) void k_resolve(DevScene S, DevWS w, int depth)
     if (i < n_clear) {
       const uint32_t s = cat_list(w, p, kCatShadowClear)[i];
       const float4* e = (const float4*)(w.nee + (size_t)s * Bp);
-      float4* l = (float4*)(w.lacc + (size_t)s * Bp);
-      for (int q = 0; q < nq; ++q) {
+      row_update<12>((float4*)(w.lacc + (size_t)s * Bp), nq, [&](int q, float4 l) {
         const float4 a = e[q];
-        float4 b = l[q];
-        b.x += a.x; b.y += a.y; b.z += a.z; b.w += a.w;
-        l[q] = b;
-      }
+        return make_float4(l.x + a.x, l.y + a.y, l.z + a.z, l.w + a.w);
+      });
     } else {
       const uint32_t s = cat_list(w, p, kCatShadowGlass)[i - n_clear];
       const uint32_t nc = min(w.shcnt[s], (uint32_t)kMaxCross);
-      const float* e = w.nee + (size_t)s * Bp;
-      float* l = w.lacc + (size_t)s * Bp;
+      const float4* e = (const float4*)(w.nee + (size_t)s * Bp);
       int mq[kMaxCross];
       float cq[kMaxCross];
       crossings(S, w, s, nc, mq, cq);
-      for (int j = 0; j < S.n_bins; ++j) {
-        float V = 1.0f;
+      const float4* lam = (const float4*)S.lambda;
+      row_update<4>((float4*)(w.lacc + (size_t)s * Bp), nq, [&](int q, float4 l) {
+        float4 V = make_float4(1.0f, 1.0f, 1.0f, 1.0f);
+        const float4 la = lam[q];
 #pragma unroll
-        for (int q = 0; q < kMaxCross; ++q) {
-          if ((uint32_t)q < nc) {
-            const int m = mq[q];
-            float Rq, Tq;
-            slab(S.ntab[m * Bp + j], S.ktab[m * Bp + j], S.lambda[j], S.thick[m], cq[q], Rq, Tq);
-            V *= Tq;
+        for (int c = 0; c < kMaxCross; ++c) {
+          if ((uint32_t)c < nc) {
+            const int m = mq[c];
+            const float4 nn = ((const float4*)(S.ntab + m * Bp))[q], kk = ((const float4*)(S.ktab + m * Bp))[q];
+            float R0, T0, R1, T1, R2, T2, R3, T3;
+            slab(nn.x, kk.x, la.x, S.thick[m], cq[c], R0, T0);
+            slab(nn.y, kk.y, la.y, S.thick[m], cq[c], R1, T1);
+            slab(nn.z, kk.z, la.z, S.thick[m], cq[c], R2, T2);
+            slab(nn.w, kk.w, la.w, S.thick[m], cq[c], R3, T3);
+            V.x *= T0;
+            V.y *= T1;
+            V.z *= T2;
+            V.w *= T3;
           }
         }
-        l[j] += e[j] * V;
-      }
+        const float4 a = e[q];
+        return make_float4(l.x + a.x * V.x, l.y + a.y * V.y, l.z + a.z * V.z, l.w + a.w * V.w);
+      });
     }
   }
 }
@@ -1125,13 +1205,10 @@ __global__ __launch_bounds__(kWG) void k_escape(DevScene S, DevWS w, int depth) 
   for (uint32_t i = blockIdx.x * kWG + threadIdx.x; i < n; i += gridDim.x * kWG) {
     const uint32_t s = cat_list(w, p, kCatEscape)[i];
     const float4* b4 = (const float4*)(w.beta + (size_t)s * Bp);
-    float4* l = (float4*)(w.lacc + (size_t)s * Bp);
-    for (int q = 0; q < nq; ++q) {
+    row_update<12>((float4*)(w.lacc + (size_t)s * Bp), nq, [&](int q, float4 l) {
       const float4 a = b4[q], e = env[q];
-      float4 b = l[q];
-      b.x += a.x * e.x; b.y += a.y * e.y; b.z += a.z * e.z; b.w += a.w * e.w;
-      l[q] = b;
-    }
+      return make_float4(l.x + a.x * e.x, l.y + a.y * e.y, l.z + a.z * e.z, l.w + a.w * e.w);
+    });
   }
 }
 
@@ -1323,25 +1400,39 @@ __global__ __launch_bounds__(kWG) void k_shade_glass(DevScene S, DevWS w, int de
       const uint4 rn = philox(make_uint4(w.pix[s], w.smp[s], (uint32_t)depth | pm.purpose, w.views[w.view[s]].view_id),
                               key0, key1);
       const float u0 = unif24(rn.x);
-      const float* nt = S.ntab + V.m * Bp;
-      const float* kt = S.ktab + V.m * Bp;
+      const float4* nt = (const float4*)(S.ntab + V.m * Bp);
+      const float4* kt = (const float4*)(S.ktab + V.m * Bp);
+      const float4* lam = (const float4*)S.lambda;
       const float th = S.thick[V.m];
+      // slab R and T of the four bins of quad q (padding bins hold benign table values)
+      auto slab4 = [&](int q, float (&R)[4], float (&T)[4]) {
+        const float4 nn = nt[q], kk = kt[q], la = lam[q];
+        slab(nn.x, kk.x, la.x, th, V.cos_o, R[0], T[0]);
+        slab(nn.y, kk.y, la.y, th, V.cos_o, R[1], T[1]);
+        slab(nn.z, kk.z, la.z, th, V.cos_o, R[2], T[2]);
+        slab(nn.w, kk.w, la.w, th, V.cos_o, R[3], T[3]);
+      };
       float mr = 0.0f, mt = 0.0f;
-      for (int j = 0; j < B; ++j) {
-        float Rj, Tj;
-        slab(nt[j], kt[j], S.lambda[j], th, V.cos_o, Rj, Tj);
-        mr += Rj;
-        mt += Tj;
+#pragma unroll 4
+      for (int q = 0; q < Bp / 4; ++q) {
+        float R[4], T[4];
+        slab4(q, R, T);
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          if (4 * q + c < B) {
+            mr += R[c];
+            mt += T[c];
+          }
       }
       const float Pr = mr / (mr + mt);
       const bool refl = u0 < Pr;
       const float inv_p = refl ? 1.0f / Pr : 1.0f / (1.0f - Pr);
-      float* b = w.beta + (size_t)s * Bp;
-      for (int j = 0; j < B; ++j) {
-        float Rj, Tj;
-        slab(nt[j], kt[j], S.lambda[j], th, V.cos_o, Rj, Tj);
-        b[j] *= (refl ? Rj : Tj) * inv_p;
-      }
+      row_update<4>((float4*)(w.beta + (size_t)s * Bp), Bp / 4, [&](int q, float4 b) {
+        float R[4], T[4];
+        slab4(q, R, T);
+        return make_float4(b.x * ((refl ? R[0] : T[0]) * inv_p), b.y * ((refl ? R[1] : T[1]) * inv_p),
+                           b.z * ((refl ? R[2] : T[2]) * inv_p), b.w * ((refl ? R[3] : T[3]) * inv_p));
+      });
       const F3 nd = refl ? V.d - V.ng * (2.0f * V.dn) : V.d;
       const F3 no = refl ? V.p + V.n * V.eps : V.p - V.n * V.eps;
       w.rays[2 * s] = make_float4(no.x, no.y, no.z, __uint_as_float(V.id));
@@ -1369,10 +1460,25 @@ __global__ __launch_bounds__(kWG) void k_accumulate(DevScene S, DevWS w, uint32_
     const ViewDesc& V = w.views[w.view[s]];
     const size_t plane = (size_t)V.width * V.height;
     float* img = V.image + w.pix[s];
-    const float* l = w.lacc + (size_t)s * Bp;
-    for (int j = 0; j < B; ++j) {
-      const float c = l[j] * V.inv_spp;
-      if (c != 0.0f) unsafeAtomicAdd(img + (size_t)j * plane, c);
+    // 48 bins of the slot's row are loaded before the first of their atomics: the image and the
+    // rows are both float memory, so a load issued after an atomic would wait for it
+    constexpr int kChunk = 12;
+    const float4* l4 = (const float4*)(w.lacc + (size_t)s * Bp);
+    for (int q0 = 0; q0 < Bp / 4; q0 += kChunk) {
+      float4 l[kChunk];
+#pragma unroll
+      for (int q = 0; q < kChunk; ++q)
+        l[q] = q0 + q < Bp / 4 ? l4[q0 + q] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+      for (int q = 0; q < kChunk; ++q) {
+        const float c4[4] = {l[q].x, l[q].y, l[q].z, l[q].w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int j = 4 * (q0 + q) + e;
+          const float c = c4[e] * V.inv_spp;
+          if (j < B && c != 0.0f) unsafeAtomicAdd(img + (size_t)j * plane, c);
+        }
+      }
     }
   }
 }
