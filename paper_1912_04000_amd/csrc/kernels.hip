@@ -1231,19 +1231,33 @@ __device__ __forceinline__ void record_vertex(const PathMode& pm, const DevWS& w
 // NQ > 0: the spectral rows have exactly NQ float4 quads (compile time), so the bin loops unroll,
 // their loads issue together and the Fresnel factors of the first pass stay in registers for
 // the throughput update; NQ = 0 handles any bin count.
-template <int NQ>
-__global__ __launch_bounds__(kWG) void k_shade_opaque(DevScene S, DevWS w, int depth, int max_depth, uint32_t key0,
+// Spectral tables of the templated shading kernels (kLds): n, k and ρ of every material (n_mat
+// rows of Bp floats each), then the sun's spectrum, staged in dynamic LDS when they take at most
+// kShadeLdsFloats; otherwise read from memory.
+constexpr int kShadeLdsFloats = 8192;
+
+template <int NQ, bool kLds>
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2))) void k_shade_opaque(DevScene S, DevWS w, int depth, int max_depth, uint32_t key0,
                                                       uint32_t key1, int gen, PathMode pm) {
   __shared__ uint32_t s_st[3];
   __shared__ float s_planes[3 * (kMaxGrid + 1)];  // the grid's slab planes, for locating new rays
+  extern __shared__ float4 s_tab4[];
+  // Fresnel factors of the templated kernels, one column per thread: kept here rather than in
+  // registers between the lobe choice and the throughput update
+  __shared__ float s_F[NQ > 0 ? 4 * NQ : 1][kWG];
+  const int B = S.n_bins, Bp = w.Bp, nq = NQ > 0 ? NQ : Bp / 4;
   stats_init(s_st, 3);
   for (int q = threadIdx.x; q < S.gx + S.gy + S.gz + 3; q += kWG) s_planes[q] = S.planes[q];
+  if constexpr (kLds) {
+    float* s_tab = (float*)s_tab4;
+    const int mb = S.n_mat * Bp;
+    for (int q = threadIdx.x; q < 3 * mb + Bp; q += kWG)
+      s_tab[q] = q < mb ? S.ntab[q] : q < 2 * mb ? S.ktab[q - mb] : q < 3 * mb ? S.rho[q - 2 * mb] : S.sunE[q - 3 * mb];
+  }
   __syncthreads();
   const int p = depth & 1;
   const uint32_t n = w.ctl->cat_count[p][kCatOpaque];
   const uint32_t* list = cat_list(w, p, kCatOpaque);
-  const int B = S.n_bins, Bp = w.Bp, nq = NQ > 0 ? NQ : Bp / 4;
-  constexpr int kUnroll = NQ > 0 ? NQ : 1;
   const size_t W = w.W;
   const int gp = gen & 1;
   const uint32_t n_iter = (n + kWG - 1) / kWG * kWG;
@@ -1258,10 +1272,6 @@ __global__ __launch_bounds__(kWG) void k_shade_opaque(DevScene S, DevWS w, int d
       const uint4 rn = philox(make_uint4(w.pix[s], w.smp[s], (uint32_t)depth | pm.purpose, w.views[w.view[s]].view_id),
                               key0, key1);
       const float u0 = unif24(rn.x), u1 = unif24(rn.y), u2 = unif24(rn.z);
-      const float4* nt = (const float4*)(S.ntab + V.m * Bp);
-      const float4* kt = (const float4*)(S.ktab + V.m * Bp);
-      const float4* rt = (const float4*)(S.rho + V.m * Bp);
-      const float4* E4 = (const float4*)S.sunE;
       float4* b4 = (float4*)(w.beta + (size_t)s * Bp);
       float4* e4 = (float4*)(w.nee + (size_t)s * Bp);
       const F3 ws = f3(S.sun[0], S.sun[1], S.sun[2]);
@@ -1269,30 +1279,119 @@ __global__ __launch_bounds__(kWG) void k_shade_opaque(DevScene S, DevWS w, int d
       const bool nee = cs > 0.0f;
       const float kn = cs * (1.0f / 3.14159265358979f);
       float a_sum = 0.0f, b_sum = 0.0f;
-      float Fk[NQ > 0 ? 4 * NQ : 1];
-#pragma unroll kUnroll
-      for (int q = 0; q < nq; ++q) {
-        const float4 nn = nt[q], kk = kt[q], rr = rt[q];
-        float F[4] = {fresnel(nn.x, kk.x, V.cos_o), fresnel(nn.y, kk.y, V.cos_o), fresnel(nn.z, kk.z, V.cos_o),
-                      fresnel(nn.w, kk.w, V.cos_o)};
-        if (NQ > 0) {
-#pragma unroll
-          for (int c = 0; c < 4; ++c) Fk[(4 * q + c) % (4 * (NQ > 0 ? NQ : 1))] = F[c];
+      bool cont = false, mirror = false;
+      float inv_p = 0.0f;
+      // lobe choice from the band means of F and (1 - F) rho
+      auto choose = [&]() {
+        const float am = a_sum / (float)B, bm = b_sum / (float)B;
+        cont = depth < max_depth && am + bm > 0.0f;
+        if (cont) {
+          const float Ps = am / (am + bm);
+          mirror = u0 < Ps;
+          inv_p = mirror ? 1.0f / Ps : 1.0f / (1.0f - Ps);
         }
-        const float rho[4] = {rr.x, rr.y, rr.z, rr.w};
-        float dif[4];
+      };
+      if constexpr (NQ > 0) {
+        // The vertex's β row is read before any row is written and the tables come from LDS; the
+        // direct term and the throughput update then work from registers. (Rows are float memory
+        // like the tables, so a load that followed a store in program order would wait for it.)
+        const float4 *nt, *kt, *rt, *E4;
+        if constexpr (kLds) {
+          const int mb = S.n_mat * Bp / 4;
+          nt = s_tab4 + V.m * Bp / 4;
+          kt = nt + mb;
+          rt = nt + 2 * mb;
+          E4 = s_tab4 + 3 * mb;
+        } else {
+          nt = (const float4*)(S.ntab + V.m * Bp);
+          kt = (const float4*)(S.ktab + V.m * Bp);
+          rt = (const float4*)(S.rho + V.m * Bp);
+          E4 = (const float4*)S.sunE;
+        }
+        float Dk[4 * NQ];
+        float4 bq[NQ];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          dif[c] = (1.0f - F[c]) * rho[c];
-          if (4 * q + c < B) {
-            a_sum += F[c];
-            b_sum += dif[c];
+        for (int q = 0; q < NQ; ++q)
+          bq[q] = b4[q];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          const float4 nn = nt[q], kk = kt[q], rr = rt[q];
+          const float n4[4] = {nn.x, nn.y, nn.z, nn.w}, k4[4] = {kk.x, kk.y, kk.z, kk.w},
+                      r4[4] = {rr.x, rr.y, rr.z, rr.w};
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const float F = fresnel(n4[c], k4[c], V.cos_o);
+            s_F[4 * q + c][threadIdx.x] = F;
+            Dk[4 * q + c] = (1.0f - F) * r4[c];
+            if (q < NQ - 1 || 4 * q + c < B) {  // padding bins sit in the last quad only
+              a_sum += F;
+              b_sum += Dk[4 * q + c];
+            }
           }
         }
+        choose();
         if (nee) {
-          const float4 bb = b4[q], EE = E4[q];
-          e4[q] = make_float4(bb.x * dif[0] * kn * EE.x, bb.y * dif[1] * kn * EE.y, bb.z * dif[2] * kn * EE.z,
-                              bb.w * dif[3] * kn * EE.w);
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) {
+            const float* D = Dk + 4 * q;
+            const float4 EE = E4[q];
+            e4[q] = make_float4(bq[q].x * D[0] * kn * EE.x, bq[q].y * D[1] * kn * EE.y,
+                                bq[q].z * D[2] * kn * EE.z, bq[q].w * D[3] * kn * EE.w);
+          }
+        }
+        if (cont) {
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) {
+            const float* D = Dk + 4 * q;
+            float G[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) G[c] = mirror ? s_F[4 * q + c][threadIdx.x] : D[c];
+            float4 bb = bq[q];
+            bb.x *= G[0] * inv_p;
+            bb.y *= G[1] * inv_p;
+            bb.z *= G[2] * inv_p;
+            bb.w *= G[3] * inv_p;
+            b4[q] = bb;
+          }
+        }
+      } else {
+        const float4* nt = (const float4*)(S.ntab + V.m * Bp);
+        const float4* kt = (const float4*)(S.ktab + V.m * Bp);
+        const float4* rt = (const float4*)(S.rho + V.m * Bp);
+        const float4* E4 = (const float4*)S.sunE;
+        for (int q = 0; q < nq; ++q) {
+          const float4 nn = nt[q], kk = kt[q], rr = rt[q];
+          const float F[4] = {fresnel(nn.x, kk.x, V.cos_o), fresnel(nn.y, kk.y, V.cos_o),
+                              fresnel(nn.z, kk.z, V.cos_o), fresnel(nn.w, kk.w, V.cos_o)};
+          const float rho[4] = {rr.x, rr.y, rr.z, rr.w};
+          float dif[4];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            dif[c] = (1.0f - F[c]) * rho[c];
+            if (4 * q + c < B) {
+              a_sum += F[c];
+              b_sum += dif[c];
+            }
+          }
+          if (nee) {
+            const float4 bb = b4[q], EE = E4[q];
+            e4[q] = make_float4(bb.x * dif[0] * kn * EE.x, bb.y * dif[1] * kn * EE.y, bb.z * dif[2] * kn * EE.z,
+                                bb.w * dif[3] * kn * EE.w);
+          }
+        }
+        choose();
+        if (cont) {
+          for (int q = 0; q < nq; ++q) {
+            const float4 nn = nt[q], kk = kt[q], rr = rt[q];
+            const float F0 = fresnel(nn.x, kk.x, V.cos_o), F1 = fresnel(nn.y, kk.y, V.cos_o),
+                        F2 = fresnel(nn.z, kk.z, V.cos_o), F3v = fresnel(nn.w, kk.w, V.cos_o);
+            float4 bb = b4[q];
+            bb.x *= (mirror ? F0 : (1.0f - F0) * rr.x) * inv_p;
+            bb.y *= (mirror ? F1 : (1.0f - F1) * rr.y) * inv_p;
+            bb.z *= (mirror ? F2 : (1.0f - F2) * rr.z) * inv_p;
+            bb.w *= (mirror ? F3v : (1.0f - F3v) * rr.w) * inv_p;
+            b4[q] = bb;
+          }
         }
       }
       if (nee) {
@@ -1304,34 +1403,7 @@ __global__ __launch_bounds__(kWG) void k_shade_opaque(DevScene S, DevWS w, int d
         sh_cell = start_cell_pl(S, s_planes, so, ws);
         sh_dir = dir_bin(ws);
       }
-      const float am = a_sum / (float)B, bm = b_sum / (float)B;
-      if (depth < max_depth && am + bm > 0.0f) {
-        const float Ps = am / (am + bm);
-        const bool mirror = u0 < Ps;
-        const float inv_p = mirror ? 1.0f / Ps : 1.0f / (1.0f - Ps);
-#pragma unroll kUnroll
-        for (int q = 0; q < nq; ++q) {
-          const float4 nn = nt[q], kk = kt[q], rr = rt[q];
-          float F0, F1, F2, F3v;
-          if (NQ > 0) {
-            const int b0 = (4 * q) % (4 * (NQ > 0 ? NQ : 1));
-            F0 = Fk[b0];
-            F1 = Fk[b0 + 1];
-            F2 = Fk[b0 + 2];
-            F3v = Fk[b0 + 3];
-          } else {
-            F0 = fresnel(nn.x, kk.x, V.cos_o);
-            F1 = fresnel(nn.y, kk.y, V.cos_o);
-            F2 = fresnel(nn.z, kk.z, V.cos_o);
-            F3v = fresnel(nn.w, kk.w, V.cos_o);
-          }
-          float4 bb = b4[q];
-          bb.x *= (mirror ? F0 : (1.0f - F0) * rr.x) * inv_p;
-          bb.y *= (mirror ? F1 : (1.0f - F1) * rr.y) * inv_p;
-          bb.z *= (mirror ? F2 : (1.0f - F2) * rr.z) * inv_p;
-          bb.w *= (mirror ? F3v : (1.0f - F3v) * rr.w) * inv_p;
-          b4[q] = bb;
-        }
+      if (cont) {
         F3 nd;
         if (mirror) {
           nd = V.d - V.ng * (2.0f * V.dn);
@@ -1557,11 +1629,20 @@ hipError_t launch_shade_opaque(const Launch& L, const DevScene& S, const DevWS& 
                                uint64_t seed, int gen, const PathMode& pm) {
   const dim3 g(grid_for(w.W, 4096)), b(kWG);
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+  const size_t tab = (size_t)3 * S.n_mat * w.Bp + w.Bp;  // LDS tables of the templated kernels
+  const bool lds = tab <= (size_t)kShadeLdsFloats;
+  const size_t bytes = lds ? tab * sizeof(float) : 0;
+#define SDD_SHADE(nq, l) hipLaunchKernelGGL((k_shade_opaque<nq, l>), g, b, bytes, L.stream, S, w, depth, max_depth, k0, k1, gen, pm)
   switch (w.Bp / 4) {
-    case 2: hipLaunchKernelGGL(k_shade_opaque<2>, g, b, 0, L.stream, S, w, depth, max_depth, k0, k1, gen, pm); break;
-    case 10: hipLaunchKernelGGL(k_shade_opaque<10>, g, b, 0, L.stream, S, w, depth, max_depth, k0, k1, gen, pm); break;
-    default: hipLaunchKernelGGL(k_shade_opaque<0>, g, b, 0, L.stream, S, w, depth, max_depth, k0, k1, gen, pm);
+    case 2:
+      if (lds) SDD_SHADE(2, true); else SDD_SHADE(2, false);
+      break;
+    case 10:
+      if (lds) SDD_SHADE(10, true); else SDD_SHADE(10, false);
+      break;
+    default: SDD_SHADE(0, false);
   }
+#undef SDD_SHADE
   return hipGetLastError();
 }
 
