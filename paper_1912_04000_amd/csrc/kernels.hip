@@ -1228,9 +1228,8 @@ __device__ __forceinline__ void record_vertex(const PathMode& pm, const DevWS& w
   }
 }
 
-// NQ > 0: the spectral rows have exactly NQ float4 quads (compile time), so the bin loops unroll,
-// their loads issue together and the Fresnel factors of the first pass stay in registers for
-// the throughput update; NQ = 0 handles any bin count.
+// NQ > 0: the spectral rows have exactly NQ float4 quads (compile time), so the bin loops unroll
+// and their loads issue together; NQ = 0 handles any bin count.
 // Spectral tables of the templated shading kernels (kLds): n, k and ρ of every material (n_mat
 // rows of Bp floats each), then the sun's spectrum, staged in dynamic LDS when they take at most
 // kShadeLdsFloats; otherwise read from memory.

@@ -240,6 +240,33 @@ def test_render_parity_variants(ctx, spp, depth, grid, wave, rounds):
     assert ok.mean() > 0.9
 
 
+@pytest.mark.parametrize("bins,copies", [(40, 24), (8, 120)])
+def test_render_parity_many_materials(ctx, bins, copies):
+    """More material rows than the opaque shading kernel stages in LDS (8192 floats of n, k and
+    rho tables): that kernel then reads the tables from memory. The nave's materials are copied
+    with perturbed albedo and assigned at random, so neighbouring triangles differ."""
+    import dataclasses
+    import paper_1912_04000_amd as sd
+    sc = scenegen.nave_scene(bins)
+    M = sc.n_mat
+    rng = np.random.default_rng(17)
+    bp = (bins + 3) // 4 * 4
+    sc = dataclasses.replace(
+        sc, mat=(sc.mat + M * rng.integers(0, copies, size=sc.mat.shape)).astype(np.uint16),
+        mat_type=np.tile(sc.mat_type, copies), thickness_m=np.tile(sc.thickness_m, copies),
+        n_tab=np.tile(sc.n_tab, (copies, 1)), k_tab=np.tile(sc.k_tab, (copies, 1)),
+        rho_tab=(np.tile(sc.rho_tab, (copies, 1)) *
+                 rng.uniform(0.6, 1.0, size=(M * copies, 1))).astype(sc.rho_tab.dtype)).check()
+    assert 3 * sc.n_mat * bp + bp > 8192
+    cam = scenegen.nave_camera(48, 40)
+    S = _scene(ctx, sc, (2, 2, 2))
+    img = ctx.render(S, sd.camera(cam.eye, cam.target, cam.up, cam.vfov_deg, cam.width, cam.height),
+                     sd.render_params(spp=2, max_depth=5, seed=5)).cpu().numpy()
+    ref = oracle.render(sc, cam, spp=2, max_depth=5, seed=5)
+    ok = _pixel_parity(img, ref.image, ref.tied, f"{sc.n_mat} materials, {bins} bins")
+    assert ok.mean() > 0.9
+
+
 def test_white_furnace_gpu(ctx):
     import paper_1912_04000_amd as sd
     sc = scenegen.furnace_scene(n_bins=4)
