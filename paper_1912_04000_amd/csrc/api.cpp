@@ -300,6 +300,24 @@ int run_paths(sdd_ctx* ctx, const sdd_scene* scene, const sdd_render_params* p, 
   return SDD_OK;
 }
 
+// True when every image element receives at most one path of the items [k0, k0 + n): no view's
+// share of them exceeds one sample plane, and the images of the views they touch do not overlap.
+static bool wave_pixels_unique(const std::vector<ViewDesc>& views, uint64_t k0, uint64_t n, int B) {
+  std::vector<std::pair<uintptr_t, uintptr_t>> spans;
+  for (const auto& v : views) {
+    const uint64_t P = (uint64_t)v.width * v.height, b = v.item_base, e = b + P * (uint64_t)v.spp;
+    const uint64_t lo = std::max(k0, b), hi = std::min(k0 + n, e);
+    if (lo >= hi) continue;
+    if (hi - lo > P) return false;
+    const uintptr_t a = (uintptr_t)v.image;
+    spans.emplace_back(a, a + (uintptr_t)(P * (uint64_t)B * sizeof(float)));
+  }
+  std::sort(spans.begin(), spans.end());
+  for (size_t i = 1; i < spans.size(); ++i)
+    if (spans[i].first < spans[i - 1].second) return false;
+  return true;
+}
+
 int enqueue_frame(sdd_ctx* ctx, const sdd_scene* scene, const std::vector<ViewDesc>& views,
                   const sdd_render_params* p, const Plan& plan, const DevWS& w, uint64_t total, bool timing,
                   sdd_cache* cache = nullptr, const sdd_train_params* tp = nullptr) {
@@ -315,15 +333,27 @@ int enqueue_frame(sdd_ctx* ctx, const sdd_scene* scene, const std::vector<ViewDe
   int gen = 0;
   const PathMode render_mode{0u, 0, nullptr, nullptr};
   uint64_t wavefront = 0;
-  for (uint64_t k0 = 0; k0 < total; k0 += W, ++wavefront) {
-    const uint32_t n = (uint32_t)std::min<uint64_t>(W, total - k0);
+  for (uint64_t k0 = 0; k0 < total; ++wavefront) {
+    uint32_t n = (uint32_t)std::min<uint64_t>(W, total - k0);
+    // A wavefront that would run past the end of its view's sample plane by less than half its
+    // size stops there: then each pixel receives at most one of its paths (the image update
+    // needs no atomics), and the number of wavefronts of a frame does not grow.
+    for (const auto& v : views) {
+      const uint64_t P = (uint64_t)v.width * v.height;
+      if (k0 < v.item_base || k0 >= v.item_base + P * (uint64_t)v.spp) continue;
+      const uint64_t to_plane = P - (k0 - v.item_base) % P;
+      if (to_plane < n && 2 * to_plane >= W) n = (uint32_t)to_plane;
+      break;
+    }
+    const bool unique = wave_pixels_unique(views, k0, n, scene->hdr.n_bins);
     rc = run_paths(ctx, scene, p, L, S, w, k0, n, gen, timing, render_mode, cache, [&]() -> int {
       if (timing) record(ctx, ctx->ev_shade, ctx->ev_used_shade, true);
-      HIP_TRY(ctx, launch_accumulate(L, S, w, n));
+      HIP_TRY(ctx, launch_accumulate(L, S, w, n, unique));
       if (timing) record(ctx, ctx->ev_shade, ctx->ev_used_shade, false);
       return SDD_OK;
     });
     if (rc) return rc;
+    k0 += n;
     ctx->acc.wavefronts++;
     if (cache && tp && tp->train_paths > 0 &&
         (tp->every > 0 ? wavefront % (uint64_t)tp->every == 0 : wavefront == 0)) {

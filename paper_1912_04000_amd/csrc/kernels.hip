@@ -293,7 +293,10 @@ template <bool kTrain>
 __global__ __launch_bounds__(kWG) void k_raygen(DevScene S, DevWS w, uint64_t k0, uint32_t n, uint32_t key0,
                                                 uint32_t key1, int gen, PathMode pm) {
   __shared__ uint32_t s_st[1];
+  __shared__ float s_planes[3 * (kMaxGrid + 1)];  // the grid's slab planes, for locating the rays
   stats_init(s_st, 1);
+  for (int q = threadIdx.x; q < S.gx + S.gy + S.gz + 3; q += kWG) s_planes[q] = S.planes[q];
+  __syncthreads();
   const uint32_t i = blockIdx.x * kWG + threadIdx.x;
   const bool valid = i < n;
   uint32_t cell = kInvalidCell, qdir = 0;
@@ -313,8 +316,14 @@ __global__ __launch_bounds__(kWG) void k_raygen(DevScene S, DevWS w, uint64_t k0
       const ViewDesc& V1 = w.views[v];
       const uint64_t local = k - V1.item_base;
       const uint64_t P = (uint64_t)V1.width * V1.height;
-      s = (uint32_t)(local / P) + V1.first_sample;
-      pix = (uint32_t)(local % P);
+      if ((local >> 32) == 0 && (P >> 32) == 0) {  // 32-bit division where it suffices
+        const uint32_t l32 = (uint32_t)local, p32 = (uint32_t)P;
+        s = l32 / p32 + V1.first_sample;
+        pix = l32 % p32;
+      } else {
+        s = (uint32_t)(local / P) + V1.first_sample;
+        pix = (uint32_t)(local % P);
+      }
     }
     const ViewDesc& V = w.views[v];
     const uint32_t px = pix % (uint32_t)V.width, py = pix / (uint32_t)V.width;
@@ -331,14 +340,21 @@ __global__ __launch_bounds__(kWG) void k_raygen(DevScene S, DevWS w, uint64_t k0
     w.pix[i] = pix;
     w.smp[i] = s;
     w.view[i] = (uint32_t)v;
-    float4* b4 = (float4*)(w.beta + (size_t)i * w.Bp);
-    float4* l4 = (float4*)(w.lacc + (size_t)i * w.Bp);
-    for (int q = 0; q < w.Bp / 4; ++q) {
+    cell = start_cell_pl(S, s_planes, o, d);
+    qdir = dir_bin(d);
+  }
+  // Throughput rows at one and radiance rows at zero: the workgroup's paths own one contiguous
+  // stretch of each row array, written by the whole workgroup in consecutive quads (per-path row
+  // loops would address 64 rows, one cache line each, per store instruction).
+  {
+    const uint32_t i0 = blockIdx.x * kWG, np = min((uint32_t)kWG, n - min(n, i0));
+    const uint32_t nq4 = np * (uint32_t)(w.Bp / 4);
+    float4* b4 = (float4*)(w.beta + (size_t)i0 * w.Bp);
+    float4* l4 = (float4*)(w.lacc + (size_t)i0 * w.Bp);
+    for (uint32_t q = threadIdx.x; q < nq4; q += kWG) {
       b4[q] = make_float4(1.0f, 1.0f, 1.0f, 1.0f);
       l4[q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     }
-    cell = start_cell(S, o, d);
-    qdir = dir_bin(d);
   }
   const int p = gen & 1;
   __shared__ uint32_t s_app[kWG / 64];
@@ -1524,15 +1540,18 @@ __global__ __launch_bounds__(kWG) void k_shade_glass(DevScene S, DevWS w, int de
 
 // End of a wavefront: every path's gathered radiance, divided by the view's spp, into its
 // pixel of the spectral image [B][H][W]. Slots are visited in order, so a wave adds to
-// consecutive pixels of one bin plane at a time.
+// consecutive pixels of one bin plane at a time. kUnique: no pixel receives two paths of the
+// wavefront, so plain loads and stores replace the atomics.
+template <bool kUnique>
 __global__ __launch_bounds__(kWG) void k_accumulate(DevScene S, DevWS w, uint32_t n) {
   const int B = S.n_bins, Bp = w.Bp;
   for (uint32_t s = blockIdx.x * kWG + threadIdx.x; s < n; s += gridDim.x * kWG) {
     const ViewDesc& V = w.views[w.view[s]];
     const size_t plane = (size_t)V.width * V.height;
     float* img = V.image + w.pix[s];
-    // 48 bins of the slot's row are loaded before the first of their atomics: the image and the
-    // rows are both float memory, so a load issued after an atomic would wait for it
+    // 48 bins of the slot's row (and, kUnique, of its pixel) are loaded before the first store
+    // or atomic of them: the image and the rows are both float memory, so a load issued after a
+    // store or atomic would wait for it
     constexpr int kChunk = 12;
     const float4* l4 = (const float4*)(w.lacc + (size_t)s * Bp);
     for (int q0 = 0; q0 < Bp / 4; q0 += kChunk) {
@@ -1540,6 +1559,14 @@ __global__ __launch_bounds__(kWG) void k_accumulate(DevScene S, DevWS w, uint32_
 #pragma unroll
       for (int q = 0; q < kChunk; ++q)
         l[q] = q0 + q < Bp / 4 ? l4[q0 + q] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      float cur[kUnique ? 4 * kChunk : 1];
+      if constexpr (kUnique) {
+#pragma unroll
+        for (int e = 0; e < 4 * kChunk; ++e) {
+          const int j = 4 * q0 + e;
+          cur[e] = j < B ? img[(size_t)j * plane] : 0.0f;
+        }
+      }
 #pragma unroll
       for (int q = 0; q < kChunk; ++q) {
         const float c4[4] = {l[q].x, l[q].y, l[q].z, l[q].w};
@@ -1547,7 +1574,12 @@ __global__ __launch_bounds__(kWG) void k_accumulate(DevScene S, DevWS w, uint32_
         for (int e = 0; e < 4; ++e) {
           const int j = 4 * (q0 + q) + e;
           const float c = c4[e] * V.inv_spp;
-          if (j < B && c != 0.0f) unsafeAtomicAdd(img + (size_t)j * plane, c);
+          if (j < B && c != 0.0f) {
+            if constexpr (kUnique)
+              img[(size_t)j * plane] = cur[4 * q + e] + c;
+            else
+              unsafeAtomicAdd(img + (size_t)j * plane, c);
+          }
         }
       }
     }
@@ -1652,8 +1684,11 @@ hipError_t launch_shade_glass(const Launch& L, const DevScene& S, const DevWS& w
   return hipGetLastError();
 }
 
-hipError_t launch_accumulate(const Launch& L, const DevScene& S, const DevWS& w, uint32_t n) {
-  hipLaunchKernelGGL(k_accumulate, dim3(grid_for(n, 8192)), dim3(kWG), 0, L.stream, S, w, n);
+hipError_t launch_accumulate(const Launch& L, const DevScene& S, const DevWS& w, uint32_t n, bool unique) {
+  if (unique)
+    hipLaunchKernelGGL(k_accumulate<true>, dim3(grid_for(n, 8192)), dim3(kWG), 0, L.stream, S, w, n);
+  else
+    hipLaunchKernelGGL(k_accumulate<false>, dim3(grid_for(n, 8192)), dim3(kWG), 0, L.stream, S, w, n);
   return hipGetLastError();
 }
 
