@@ -575,10 +575,27 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(DevScene S, DevWS w, int 
   for (int c = threadIdx.x; c < nc; c += kScanThreads) other[c] = 0;
 }
 
+// Each thread moves kPer entries per pass, all their loads issued before any store (the lists and
+// the queue are all uint32 memory: a load after a store would wait for it).
 __global__ void k_scatter(DevWS w, int gen) {
+  constexpr int kPer = 4;
   const uint32_t n = w.ctl->list_count[gen & 1];
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-    w.queue[w.coff[w.ldst[i]] + w.lrank[i]] = w.lsrc[i];
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t i0 = blockIdx.x * blockDim.x + threadIdx.x; i0 < n; i0 += kPer * stride) {
+    uint32_t key[kPer], rank[kPer], src[kPer], base[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const uint32_t i = i0 + k * stride;
+      key[k] = i < n ? w.ldst[i] : 0u;
+      rank[k] = i < n ? w.lrank[i] : 0u;
+      src[k] = i < n ? w.lsrc[i] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) base[k] = i0 + k * stride < n ? w.coff[key[k]] : 0u;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k)
+      if (i0 + k * stride < n) w.queue[base[k] + rank[k]] = src[k];
+  }
 }
 
 // ==========================================================================================
