@@ -1202,7 +1202,7 @@ __global__ __launch_bounds__(kWG) void k_resolve(DevScene S, DevWS w, int depth)
       float cq[kMaxCross];
       crossings(S, w, s, nc, mq, cq);
       const float4* lam = (const float4*)S.lambda;
-      row_update<4>((float4*)(w.lacc + (size_t)s * Bp), nq, [&](int q, float4 l) {
+      row_update<12>((float4*)(w.lacc + (size_t)s * Bp), nq, [&](int q, float4 l) {
         float4 V = make_float4(1.0f, 1.0f, 1.0f, 1.0f);
         const float4 la = lam[q];
 #pragma unroll
@@ -1531,7 +1531,7 @@ __global__ __launch_bounds__(kWG) void k_shade_glass(DevScene S, DevWS w, int de
       const float Pr = mr / (mr + mt);
       const bool refl = u0 < Pr;
       const float inv_p = refl ? 1.0f / Pr : 1.0f / (1.0f - Pr);
-      row_update<4>((float4*)(w.beta + (size_t)s * Bp), Bp / 4, [&](int q, float4 b) {
+      row_update<12>((float4*)(w.beta + (size_t)s * Bp), Bp / 4, [&](int q, float4 b) {
         float R[4], T[4];
         slab4(q, R, T);
         return make_float4(b.x * ((refl ? R[0] : T[0]) * inv_p), b.y * ((refl ? R[1] : T[1]) * inv_p),
