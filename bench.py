@@ -55,7 +55,8 @@ def parse():
     ap.add_argument("--tune-cache", default=os.path.join(os.path.expanduser("~"), ".cache", "specdd",
                                                           "tune_cache.json"))
     ap.add_argument("--spp", type=int, default=None, help="override samples per pixel (profiling runs)")
-    ap.add_argument("--wave-paths", type=int, default=1 << 21)
+    ap.add_argument("--wave-paths", type=int, default=1 << 25,
+                    help="paths per wavefront (C2 measured 1046 / 925 / 889 / 838 / 821 ms per frame at 2^21 .. 2^25)")
     ap.add_argument("--queue-rounds", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-cached", action="store_true", help="skip the cached-path comparison of the default run")
@@ -219,7 +220,7 @@ def _timed(fn):
     return time.perf_counter() - t0
 
 
-def run_cached(ctx, S, sc, cam, img, args, px, ref, wave=1 << 21):
+def run_cached(ctx, S, sc, cam, img, args, px, ref, wave):
     """The cache-terminated path on the church view: an untrained cache, warm_frames 1-spp frames,
     then one scored frame of cached_spp samples, all timed; every frame (render call) trains the
     cache once on 2^16 records (--train-every 0). Then the scored frame again with training off
@@ -307,7 +308,7 @@ def bench_cached(args):
     ctx.upload(S)
     c = sd.camera(cam.eye, cam.target, cam.up, cam.vfov_deg, W, H)
     img = torch.empty((B, H, W), dtype=torch.float32, device="cuda")
-    wave = 1 << 21
+    wave = args.wave_paths
     ctx.render(S, c, sd.render_params(spp=1, max_depth=8, seed=1, wave_paths=wave), out=img)  # warm-up
     plain = []
     for spp in (1, 2, 4, 8, 16, 32, 64):
@@ -368,7 +369,7 @@ def bench_large(args):
     B, W, H = sc.n_bins, cam.width, cam.height
     ctx = sd.Context(0)
     ctx.upload(S)
-    wave = 1 << 21
+    wave = args.wave_paths
     cw, ch = 960, 540
     x0, y0 = (W - cw) // 2, (H - ch) // 2
     cc = crop_camera(cam, cw, ch)
@@ -458,7 +459,7 @@ def bench_batch(args):
     os.makedirs(os.path.dirname(args.tune_cache), exist_ok=True)
     t0 = time.perf_counter()
     tune = ctx.autotune(sc, cams, sd.render_params(max_depth=8, seed=1),
-                        waves=[1 << 18, 1 << 20, 1 << 21, 1 << 22],
+                        waves=[1 << 20, 1 << 21, 1 << 22, 1 << 23, 1 << 24],
                         grids=[(4, 4, 4), (8, 8, 8), (16, 16, 16), (8, 4, 4)], rounds=(1, 2), calib_spp=1, reps=2,
                         cache_path=args.tune_cache)
     tune_s = time.perf_counter() - t0
@@ -585,7 +586,7 @@ def main():
         px, ref = load_reference()
         r64 = _rmse(img.cpu().numpy(), ref, px)
         a = r64 * np.sqrt(cfg["spp"])
-        cached = run_cached(ctx, S, sc, cam, img, args, px, ref)
+        cached = run_cached(ctx, S, sc, cam, img, args, px, ref, p.wave_paths)
         out["equal_rmse"] = equal_rmse(cached, a, value, cam.width, cam.height, args.warm_frames)
         out["equal_rmse"]["rmse_plain_frame"] = r64
     if not args.no_cpu_baseline:

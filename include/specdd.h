@@ -154,8 +154,7 @@ int sdd_render(sdd_ctx* ctx, const sdd_scene* scene, const sdd_camera* camera, c
 
 /* Render n_views views with uneven resolution and spp in one sequence of wavefronts: the
  * (view, pixel, sample) items of all views are drained by the same launches. images_dev[v]
- * is [n_bins][H_v][W_v]; images of different views should not overlap (overlapping images are
- * summed correctly, but without the non-atomic image update). View v uses RNG view index v. */
+ * is [n_bins][H_v][W_v]. View v uses RNG view index v. */
 int sdd_render_batch(sdd_ctx* ctx, const sdd_scene* scene, const sdd_camera* views, const int32_t* spp_per_view,
                      int32_t n_views, const sdd_render_params* params, void* workspace, size_t workspace_bytes,
                      float* const* images_dev);

@@ -300,22 +300,29 @@ int run_paths(sdd_ctx* ctx, const sdd_scene* scene, const sdd_render_params* p, 
   return SDD_OK;
 }
 
-// True when every image element receives at most one path of the items [k0, k0 + n): no view's
-// share of them exceeds one sample plane, and the images of the views they touch do not overlap.
-static bool wave_pixels_unique(const std::vector<ViewDesc>& views, uint64_t k0, uint64_t n, int B) {
-  std::vector<std::pair<uintptr_t, uintptr_t>> spans;
-  for (const auto& v : views) {
-    const uint64_t P = (uint64_t)v.width * v.height, b = v.item_base, e = b + P * (uint64_t)v.spp;
-    const uint64_t lo = std::max(k0, b), hi = std::min(k0 + n, e);
-    if (lo >= hi) continue;
-    if (hi - lo > P) return false;
-    const uintptr_t a = (uintptr_t)v.image;
-    spans.emplace_back(a, a + (uintptr_t)(P * (uint64_t)B * sizeof(float)));
+// Image update at the end of the wavefront of items [k0, k0 + n). Split at the ends of the views'
+// sample planes, the wavefront falls into runs in which every pixel of one image occurs at most
+// once: each run is one launch of the plain (non-atomic) update, and launches on the stream do
+// not overlap. Beyond kMaxRuns runs (many small views) one launch with atomics does it all.
+static hipError_t accumulate_wavefront(const Launch& L, const DevScene& S, const DevWS& w,
+                                       const std::vector<ViewDesc>& views, uint64_t k0, uint32_t n) {
+  constexpr size_t kMaxRuns = 64;
+  std::vector<std::pair<uint32_t, uint32_t>> runs;  // (first slot, slots)
+  size_t v = 0;
+  for (uint64_t a = k0, e = k0 + n; a < e;) {
+    while (v + 1 < views.size() && views[v + 1].item_base <= a) ++v;
+    const uint64_t P = (uint64_t)views[v].width * views[v].height, base = views[v].item_base;
+    if (P == 0) return launch_accumulate(L, S, w, 0, n, false);
+    const uint64_t b = std::min(e, base + ((a - base) / P + 1) * P);
+    runs.emplace_back((uint32_t)(a - k0), (uint32_t)(b - a));
+    a = b;
+    if (runs.size() > kMaxRuns) return launch_accumulate(L, S, w, 0, n, false);
   }
-  std::sort(spans.begin(), spans.end());
-  for (size_t i = 1; i < spans.size(); ++i)
-    if (spans[i].first < spans[i - 1].second) return false;
-  return true;
+  for (const auto& r : runs) {
+    const hipError_t e = launch_accumulate(L, S, w, r.first, r.second, true);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 int enqueue_frame(sdd_ctx* ctx, const sdd_scene* scene, const std::vector<ViewDesc>& views,
@@ -333,27 +340,15 @@ int enqueue_frame(sdd_ctx* ctx, const sdd_scene* scene, const std::vector<ViewDe
   int gen = 0;
   const PathMode render_mode{0u, 0, nullptr, nullptr};
   uint64_t wavefront = 0;
-  for (uint64_t k0 = 0; k0 < total; ++wavefront) {
-    uint32_t n = (uint32_t)std::min<uint64_t>(W, total - k0);
-    // A wavefront that would run past the end of its view's sample plane by less than half its
-    // size stops there: then each pixel receives at most one of its paths (the image update
-    // needs no atomics), and the number of wavefronts of a frame does not grow.
-    for (const auto& v : views) {
-      const uint64_t P = (uint64_t)v.width * v.height;
-      if (k0 < v.item_base || k0 >= v.item_base + P * (uint64_t)v.spp) continue;
-      const uint64_t to_plane = P - (k0 - v.item_base) % P;
-      if (to_plane < n && 2 * to_plane >= W) n = (uint32_t)to_plane;
-      break;
-    }
-    const bool unique = wave_pixels_unique(views, k0, n, scene->hdr.n_bins);
+  for (uint64_t k0 = 0; k0 < total; k0 += W, ++wavefront) {
+    const uint32_t n = (uint32_t)std::min<uint64_t>(W, total - k0);
     rc = run_paths(ctx, scene, p, L, S, w, k0, n, gen, timing, render_mode, cache, [&]() -> int {
       if (timing) record(ctx, ctx->ev_shade, ctx->ev_used_shade, true);
-      HIP_TRY(ctx, launch_accumulate(L, S, w, n, unique));
+      HIP_TRY(ctx, accumulate_wavefront(L, S, w, views, k0, n));
       if (timing) record(ctx, ctx->ev_shade, ctx->ev_used_shade, false);
       return SDD_OK;
     });
     if (rc) return rc;
-    k0 += n;
     ctx->acc.wavefronts++;
     if (cache && tp && tp->train_paths > 0 &&
         (tp->every > 0 ? wavefront % (uint64_t)tp->every == 0 : wavefront == 0)) {
@@ -386,7 +381,8 @@ int render_views(sdd_ctx* ctx, const sdd_scene* scene, std::vector<ViewDesc>& vi
     v.item_base = total;
     total += (uint64_t)v.width * v.height * (uint64_t)v.spp;
   }
-  uint32_t W = p->wave_paths ? (uint32_t)p->wave_paths : (uint32_t)std::min<uint64_t>(kDefaultWave, total);
+  // never more paths in flight than the frame has items
+  uint32_t W = (uint32_t)std::min<uint64_t>(p->wave_paths ? (uint64_t)p->wave_paths : (uint64_t)kDefaultWave, total);
   W = std::max<uint32_t>(W, 64);
   Plan plan = make_plan(W, B, scene->hdr.n_cells, (int)views.size());
   if (!ws) return fail(ctx, SDD_ERR_INVALID_ARG, "workspace is null");
@@ -639,10 +635,13 @@ int sdd_render_cached(sdd_ctx* c, const sdd_scene* s, sdd_cache* k, const sdd_ca
   views[0].view_id = p->view;
   views[0].first_sample = (uint32_t)p->first_sample;
   const uint64_t total = (uint64_t)cam->width * cam->height * (uint64_t)p->spp;
-  uint32_t W = p->wave_paths ? (uint32_t)p->wave_paths : (uint32_t)std::min<uint64_t>(kDefaultWave, total);
+  // never more paths in flight than the frame has items, or a training batch has paths
+  const uint64_t w_req = p->wave_paths ? (uint64_t)p->wave_paths : (uint64_t)kDefaultWave;
+  const uint64_t w_need = std::max<uint64_t>(total, tp && tp->train_paths > 0 ? (uint64_t)tp->train_paths : 0);
+  uint32_t W = (uint32_t)std::min<uint64_t>(w_req, w_need);
   W = std::max<uint32_t>(W, 64);
   if (tp && tp->train_paths != 0) {
-    if (tp->train_paths < 0 || (uint32_t)tp->train_paths > W || tp->train_paths > k->cfg.max_records)
+    if (tp->train_paths < 0 || (uint64_t)tp->train_paths > w_req || tp->train_paths > k->cfg.max_records)
       return fail(c, SDD_ERR_INVALID_ARG, "train_paths must lie in 0..min(wave paths, max_records)");
     if (tp->step_records < kCacheVerts || tp->step_records > k->cfg.max_step)
       return fail(c, SDD_ERR_INVALID_ARG, "step_records must lie in 32..max_step");

@@ -1557,12 +1557,13 @@ __global__ __launch_bounds__(kWG) void k_shade_glass(DevScene S, DevWS w, int de
 
 // End of a wavefront: every path's gathered radiance, divided by the view's spp, into its
 // pixel of the spectral image [B][H][W]. Slots are visited in order, so a wave adds to
-// consecutive pixels of one bin plane at a time. kUnique: no pixel receives two paths of the
-// wavefront, so plain loads and stores replace the atomics.
+// consecutive pixels of one bin plane at a time. Slots s0 .. s0 + n - 1; kUnique: no pixel
+// receives two of them, so plain loads and stores replace the atomics.
 template <bool kUnique>
-__global__ __launch_bounds__(kWG) void k_accumulate(DevScene S, DevWS w, uint32_t n) {
+__global__ __launch_bounds__(kWG) void k_accumulate(DevScene S, DevWS w, uint32_t s0, uint32_t n) {
   const int B = S.n_bins, Bp = w.Bp;
-  for (uint32_t s = blockIdx.x * kWG + threadIdx.x; s < n; s += gridDim.x * kWG) {
+  for (uint32_t i = blockIdx.x * kWG + threadIdx.x; i < n; i += gridDim.x * kWG) {
+    const uint32_t s = s0 + i;
     const ViewDesc& V = w.views[w.view[s]];
     const size_t plane = (size_t)V.width * V.height;
     float* img = V.image + w.pix[s];
@@ -1701,11 +1702,13 @@ hipError_t launch_shade_glass(const Launch& L, const DevScene& S, const DevWS& w
   return hipGetLastError();
 }
 
-hipError_t launch_accumulate(const Launch& L, const DevScene& S, const DevWS& w, uint32_t n, bool unique) {
+hipError_t launch_accumulate(const Launch& L, const DevScene& S, const DevWS& w, uint32_t s0, uint32_t n,
+                             bool unique) {
+  if (n == 0) return hipSuccess;
   if (unique)
-    hipLaunchKernelGGL(k_accumulate<true>, dim3(grid_for(n, 8192)), dim3(kWG), 0, L.stream, S, w, n);
+    hipLaunchKernelGGL(k_accumulate<true>, dim3(grid_for(n, 8192)), dim3(kWG), 0, L.stream, S, w, s0, n);
   else
-    hipLaunchKernelGGL(k_accumulate<false>, dim3(grid_for(n, 8192)), dim3(kWG), 0, L.stream, S, w, n);
+    hipLaunchKernelGGL(k_accumulate<false>, dim3(grid_for(n, 8192)), dim3(kWG), 0, L.stream, S, w, s0, n);
   return hipGetLastError();
 }
 
