@@ -537,13 +537,16 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(DevScene S, DevWS w, int 
     w.coff[c] = run;
     run += staged ? s_key[c] : cnt[c];
   }
-  // Tiles are written by the whole workgroup, tile t by thread t mod kScanThreads: the thread
-  // chunk holding t is the first whose inclusive tile sum exceeds t (a binary search of s_til),
-  // and the key within the chunk follows by walking its counts. One key may hold thousands of
-  // tiles (the camera rays of a frame enter a few cells), which a per-key loop would write
-  // serially.
+  // Tiles are written by the whole workgroup, each thread a contiguous block of them: the key of
+  // its first tile comes from a binary search of the per-thread tile sums and a walk over that
+  // chunk's counts, the following tiles from walking on through the keys. One key may hold
+  // thousands of tiles (the camera rays of a frame enter a few cells), which a per-key loop
+  // would write serially.
   const uint32_t n_tiles = s_til[kScanThreads - 1];
-  for (uint32_t t = threadIdx.x; t < n_tiles; t += kScanThreads) {
+  const uint32_t per = (n_tiles + kScanThreads - 1) / kScanThreads;
+  uint32_t t = min(n_tiles, (uint32_t)threadIdx.x * per);
+  const uint32_t t_end = min(n_tiles, t + per);
+  if (t < t_end) {
     int lo = 0, hi = kScanThreads - 1;
     while (lo < hi) {
       const int mid = (lo + hi) >> 1;
@@ -553,16 +556,19 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(DevScene S, DevWS w, int 
         lo = mid + 1;
     }
     uint32_t tb = lo ? s_til[lo - 1] : 0u, cb = lo ? s_cnt[lo - 1] : 0u;
-    const int e1 = min(nc, lo * chunk + chunk);
-    for (int c = lo * chunk; c < e1; ++c) {
-      const uint32_t x = staged ? s_key[c] : cnt[c], nt = (x + kTile - 1) / kTile;
-      if (t < tb + nt) {
-        const uint32_t q = t - tb;
-        w.tiles[t] = make_uint4((uint32_t)c, cb + q * kTile, min((uint32_t)kTile, x - q * kTile), 0u);
-        break;
+    int c = lo * chunk;
+    uint32_t x = staged ? s_key[c] : cnt[c], nt = (x + kTile - 1) / kTile;
+    for (; t < t_end; ++t) {
+      // keys with no tile left are passed over; t < n_tiles keeps c below nc
+      while (t >= tb + nt && c + 1 < nc) {
+        tb += nt;
+        cb += x;
+        ++c;
+        x = staged ? s_key[c] : cnt[c];
+        nt = (x + kTile - 1) / kTile;
       }
-      tb += nt;
-      cb += x;
+      const uint32_t q = t - tb;
+      w.tiles[t] = make_uint4((uint32_t)c, cb + q * kTile, min((uint32_t)kTile, x - q * kTile), 0u);
     }
   }
   if (threadIdx.x == kScanThreads - 1) {
