@@ -3,7 +3,7 @@
 
 Workload (default): the seeded procedural church of 979,664 triangles (40 coloured glass windows),
 1920x1080 pixels, 40 wavelength bins over 380-780 nm, 64 samples per pixel, 8 surface vertices
-per path, 8x4x4 cells, 2^21 paths in flight. One step = one full plain frame (132.7 M spectral
+per path, 8x4x4 cells, 2^25 paths in flight. One step = one full plain frame (132.7 M spectral
 path samples, each carrying all 40 bins); `value` is the plain path's samples/s. The same line
 carries `equal_rmse`: the cache-terminated path on the same view (untrained cache, eight 1-spp
 online-training frames, then a 64-spp frame, all timed) scored against the oracle's 1024-spp

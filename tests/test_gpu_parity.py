@@ -267,6 +267,22 @@ def test_render_parity_many_materials(ctx, bins, copies):
     assert ok.mean() > 0.9
 
 
+def test_image_update_with_atomics(ctx):
+    """A wavefront holding more than 64 sample planes of one view (an 8 x 8 view at 80 spp in one
+    wavefront) updates the image with atomics instead of one plain launch per plane."""
+    import paper_1912_04000_amd as sd
+    sc = scenegen.nave_scene(8)
+    cam = scenegen.nave_camera(8, 8)
+    S = _scene(ctx, sc, (2, 2, 2))
+    ctx.reset_stats()
+    img = ctx.render(S, sd.camera(cam.eye, cam.target, cam.up, cam.vfov_deg, cam.width, cam.height),
+                     sd.render_params(spp=80, max_depth=4, seed=3, wave_paths=1 << 16)).cpu().numpy()
+    ref = oracle.render(sc, cam, spp=80, max_depth=4, seed=3)
+    assert ctx.stats()["wavefronts"] == 1
+    ok = _pixel_parity(img, ref.image, ref.tied, "80 planes in one wavefront")
+    assert ok.mean() > 0.9
+
+
 def test_white_furnace_gpu(ctx):
     import paper_1912_04000_amd as sd
     sc = scenegen.furnace_scene(n_bins=4)
@@ -328,7 +344,7 @@ def test_workspace_too_small_is_reported(ctx):
 
 # ---------------------------------------------------------------------------------------------
 # Full size: the benchmarked configuration (979,664-triangle church, 1920x1080, 40 bins, 64 spp,
-# depth 8, 8x4x4 cells, 2^21 paths in flight), compared on sampled pixels the oracle recomputes.
+# depth 8, 8x4x4 cells, 2^25 paths in flight), compared on sampled pixels the oracle recomputes.
 # ---------------------------------------------------------------------------------------------
 
 @pytest.fixture(scope="module")
@@ -346,7 +362,7 @@ def test_render_c2_full_size_sampled_parity(ctx, church):
     import torch
     sc, cam, S, c = church
     say("C2 full frame, 64 spp")
-    img = ctx.render(S, c, sd.render_params(spp=64, max_depth=8, seed=1, wave_paths=1 << 21))
+    img = ctx.render(S, c, sd.render_params(spp=64, max_depth=8, seed=1, wave_paths=1 << 25))
     rng = np.random.default_rng(0)
     px = np.sort(rng.choice(cam.width * cam.height, 4000, replace=False))
     g = img.reshape(40, -1)[:, torch.from_numpy(px).cuda()].cpu().numpy()
@@ -366,7 +382,7 @@ def test_render_c2_one_spp_sampled_parity(ctx, church):
     import paper_1912_04000_amd as sd
     import torch
     sc, cam, S, c = church
-    img = ctx.render(S, c, sd.render_params(spp=1, max_depth=8, seed=7, wave_paths=1 << 21, first_sample=5))
+    img = ctx.render(S, c, sd.render_params(spp=1, max_depth=8, seed=7, wave_paths=1 << 25, first_sample=5))
     rng = np.random.default_rng(1)
     px = np.sort(rng.choice(cam.width * cam.height, 20000, replace=False))
     g = img.reshape(40, -1)[:, torch.from_numpy(px).cuda()].cpu().numpy()
