@@ -315,8 +315,8 @@ int sdd_cache_train(sdd_ctx* ctx, sdd_cache* cache, const float* x, const float*
 /* Mean loss over the rows of the backward passes since the previous call (waits; NaN if none). */
 int sdd_cache_loss(sdd_ctx* ctx, sdd_cache* cache, double* mean_loss);
 
-/* Online training inside sdd_render_cached. Once per call (every = 0: after the first
- * wavefront) or after every `every`-th wavefront, train_paths training paths are traced at
+/* Online training inside sdd_render_cached. Once per call (every = 0: before the first
+ * wavefront) or before wavefronts 0, every, 2 every, ..., train_paths training paths are traced at
  * full depth: path g (counted across calls by the cache) starts
  * at a pixel of the view drawn from Philox counter (g, g >> 32, 2 << 24, view), draws its
  * decisions with purpose 1 (bit 24 of the counter's depth word), restarts its throughput at one
@@ -327,7 +327,7 @@ typedef struct {
   int32_t train_paths;         /* 0 .. min(max_records, wave_paths)                            */
   int32_t step_records;        /* 32 .. max_step                                               */
   int32_t steps;               /* >= 1                                                         */
-  int32_t every;               /* 0: one batch per call; k >= 1: after every k-th wavefront     */
+  int32_t every;               /* 0: one batch per call; k >= 1: before every k-th wavefront    */
 } sdd_train_params;
 
 /* Render in cached mode (params->mode = SDD_MODE_CACHED, max_depth >= 3, use_graph = 0):

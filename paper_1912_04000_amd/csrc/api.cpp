@@ -342,17 +342,12 @@ int enqueue_frame(sdd_ctx* ctx, const sdd_scene* scene, const std::vector<ViewDe
   uint64_t wavefront = 0;
   for (uint64_t k0 = 0; k0 < total; k0 += W, ++wavefront) {
     const uint32_t n = (uint32_t)std::min<uint64_t>(W, total - k0);
-    rc = run_paths(ctx, scene, p, L, S, w, k0, n, gen, timing, render_mode, cache, [&]() -> int {
-      if (timing) record(ctx, ctx->ev_shade, ctx->ev_used_shade, true);
-      HIP_TRY(ctx, accumulate_wavefront(L, S, w, views, k0, n));
-      if (timing) record(ctx, ctx->ev_shade, ctx->ev_used_shade, false);
-      return SDD_OK;
-    });
-    if (rc) return rc;
-    ctx->acc.wavefronts++;
+    // A training batch (full-depth paths recording their third vertex, then Adam steps) runs
+    // before the wavefronts it is scheduled for, so that they are rendered with the updated
+    // cache whatever the wavefront size; it shares the workspace, which the wavefront's ray
+    // generation then starts afresh.
     if (cache && tp && tp->train_paths > 0 &&
         (tp->every > 0 ? wavefront % (uint64_t)tp->every == 0 : wavefront == 0)) {
-      // training batch: full-depth paths recording their third vertex, then Adam steps
       const uint32_t nt = (uint32_t)tp->train_paths;
       const PathMode train_mode{1u << 24, kCacheDepth, cache->dev.rx, cache->dev.rw};
       rc = run_paths(ctx, scene, p, L, S, w, cache->train_paths_done, nt, gen, timing, train_mode, cache,
@@ -369,6 +364,14 @@ int enqueue_frame(sdd_ctx* ctx, const sdd_scene* scene, const std::vector<ViewDe
       cache->train_paths_done += nt;
       ctx->acc.train_batches++;
     }
+    rc = run_paths(ctx, scene, p, L, S, w, k0, n, gen, timing, render_mode, cache, [&]() -> int {
+      if (timing) record(ctx, ctx->ev_shade, ctx->ev_used_shade, true);
+      HIP_TRY(ctx, accumulate_wavefront(L, S, w, views, k0, n));
+      if (timing) record(ctx, ctx->ev_shade, ctx->ev_used_shade, false);
+      return SDD_OK;
+    });
+    if (rc) return rc;
+    ctx->acc.wavefronts++;
   }
   return SDD_OK;
 }
