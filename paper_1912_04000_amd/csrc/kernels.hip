@@ -85,6 +85,36 @@ __device__ uint32_t wave_key_rank(bool valid, uint32_t key, uint32_t* cell_count
   return cb + my_off;
 }
 
+// Append of up to two entries per lane (src0 to queue key0 if v0, src1 to key1 if v1) with ONE
+// list-counter atomic per wave: the counter is a single address that every wave of a launch
+// increments, and atomics on one cache line are served one at a time (about 10 ns each on the
+// MI355X), so the list allocation, not the entry writes, bounds a kernel that appends per wave
+// iteration. Every lane of the wave must call it.
+__device__ void wave_append2(bool v0, uint32_t src0, uint32_t key0, bool v1, uint32_t src1, uint32_t key1,
+                             uint32_t* list_count, uint32_t* cell_count, uint32_t* lsrc, uint32_t* ldst,
+                             uint32_t* lrank) {
+  const uint64_t m0 = __ballot(v0), m1 = __ballot(v1);
+  const uint32_t c0 = (uint32_t)__popcll(m0), c = c0 + (uint32_t)__popcll(m1);
+  if (c == 0) return;
+  uint32_t base = 0;
+  if (lane_id() == 0) base = atomicAdd(list_count, c);
+  const uint32_t r0 = wave_key_rank(v0, key0, cell_count);
+  const uint32_t r1 = wave_key_rank(v1, key1, cell_count);
+  base = __shfl(base, 0);
+  if (v0) {
+    const uint32_t pos = base + count_below(m0);
+    lsrc[pos] = src0;
+    ldst[pos] = key0;
+    lrank[pos] = r0;
+  }
+  if (v1) {
+    const uint32_t pos = base + c0 + count_below(m1);
+    lsrc[pos] = src1;
+    ldst[pos] = key1;
+    lrank[pos] = r1;
+  }
+}
+
 // Workgroup-level append of up to two (src, key) entries per lane (all threads of the
 // workgroup call it; s_scr holds kWG / 64 words of LDS): the positions in the produced-entry
 // list come from one list-counter atomic per workgroup and a prefix over its waves, the ranks
@@ -1468,10 +1498,9 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2))) void k
         if (ext_cell == kInvalidCell) w.hit[s] = make_float4(INFINITY, __uint_as_float(0xFFFFFFFFu), 0.0f, 0.0f);
       }
     }
-    wave_append(has_ext && ext_cell != kInvalidCell, s | kFirstVisit, qkey(ext_cell, ext_dir), &w.ctl->list_count[gp],
-                ccount_of(S, w, gp), w.lsrc, w.ldst, w.lrank);
-    wave_append(has_sh && sh_cell != kInvalidCell, ((uint32_t)W + s) | kFirstVisit, qkey(sh_cell, sh_dir),
-                &w.ctl->list_count[gp], ccount_of(S, w, gp), w.lsrc, w.ldst, w.lrank);
+    wave_append2(has_ext && ext_cell != kInvalidCell, s | kFirstVisit, qkey(ext_cell, ext_dir),
+                 has_sh && sh_cell != kInvalidCell, ((uint32_t)W + s) | kFirstVisit, qkey(sh_cell, sh_dir),
+                 &w.ctl->list_count[gp], ccount_of(S, w, gp), w.lsrc, w.ldst, w.lrank);
     // rays that miss the grid box finish at once
     if (has_sh && sh_cell == kInvalidCell) w.catb[(size_t)W + s] = (uint8_t)(kCatShadowClear + 1);
     if (has_ext && ext_cell == kInvalidCell && S.env_nonzero) w.catb[s] = (uint8_t)(kCatEscape + 1);
