@@ -98,7 +98,7 @@ Plan make_plan(uint32_t W, int B, int n_cells, int n_views) {
   sz[L_LDST] = 8ull * W;
   sz[L_LRANK] = 8ull * W;
   sz[L_QUEUE] = 8ull * W;
-  sz[L_CCOUNT] = 8ull * n_cells * kDirBins;
+  sz[L_CCOUNT] = 8ull * n_cells * kDirBins * kKeyStride;
   sz[L_COFF] = 4ull * n_cells * kDirBins;
   sz[L_TILES] = 16ull * p.max_tiles;
   sz[L_SPILL] = 4ull * (kMaxStack - kShortStack) * (size_t)tb * kWG;
@@ -336,7 +336,7 @@ int enqueue_frame(sdd_ctx* ctx, const sdd_scene* scene, const std::vector<ViewDe
   if (rc) return rc;
   for (auto& v : views) HIP_TRY(ctx, launch_fill_f32(ctx->stream, v.image, (size_t)B * v.width * v.height, 0.0f));
   HIP_TRY(ctx, launch_fill_u32(ctx->stream, (uint32_t*)w.ctl, offsetof(Ctl, st_paths) / 4, 0u));
-  HIP_TRY(ctx, launch_fill_u32(ctx->stream, w.ccount, 2ull * scene->hdr.n_cells * kDirBins, 0u));
+  HIP_TRY(ctx, launch_fill_u32(ctx->stream, w.ccount, 2ull * scene->hdr.n_cells * kDirBins * kKeyStride, 0u));
   int gen = 0;
   const PathMode render_mode{0u, 0, nullptr, nullptr};
   uint64_t wavefront = 0;
@@ -687,7 +687,7 @@ static int query(sdd_ctx* c, const sdd_scene* s, const float* orig, const float*
   DevScene S = device_view(s);
   Launch L{c->stream, plan.trace_blocks};
   HIP_TRY(c, launch_fill_u32(c->stream, (uint32_t*)w.ctl, sizeof(Ctl) / 4, 0u));
-  HIP_TRY(c, launch_fill_u32(c->stream, w.ccount, 2ull * s->hdr.n_cells * kDirBins, 0u));
+  HIP_TRY(c, launch_fill_u32(c->stream, w.ccount, 2ull * s->hdr.n_cells * kDirBins * kKeyStride, 0u));
   c->last_ctl = w.ctl;
   int gen = 0;
   for (int64_t a = 0; a < n; a += W) {

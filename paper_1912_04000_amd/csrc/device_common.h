@@ -61,7 +61,7 @@ __device__ __forceinline__ uint32_t dir_bin(F3 d) {
 }
 __device__ __forceinline__ uint32_t qkey(uint32_t cell, uint32_t dbin) { return cell * (uint32_t)kDirBins + dbin; }
 __device__ __forceinline__ uint32_t* ccount_of(const DevScene& S, const DevWS& w, int parity) {
-  return w.ccount + (size_t)parity * S.n_cells * kDirBins;
+  return w.ccount + (size_t)parity * S.n_cells * kDirBins * kKeyStride;
 }
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }

@@ -21,6 +21,10 @@ constexpr int kMaxGrid = 64;
 constexpr int kLdsCells = 256;      // cell tables up to this size are staged in LDS by the traversal
 constexpr int kXcds = 8;            // MI355X: 8 XCDs, workgroups dispatched round-robin
 constexpr int kDirBins = 24;        // ray queues per cell: direction octant x dominant axis
+// Queue-key counters sit kKeyStride words apart, one 64-byte line each: their atomics are served
+// one at a time per line, and the keys that camera or shadow rays share would otherwise crowd
+// a few lines.
+constexpr int kKeyStride = 16;
 constexpr uint32_t kBlocked = 0xFFFFFFFFu;
 constexpr uint32_t kFirstVisit = 0x80000000u;
 constexpr uint32_t kShadowBit = 0x80000000u;  // in the ray's slot word

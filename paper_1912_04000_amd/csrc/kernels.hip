@@ -45,7 +45,7 @@ __device__ void wave_append(bool valid, uint32_t src, uint32_t cell, uint32_t* l
     pending &= ~same;
   }
   uint32_t cb = 0;
-  if (is_leader) cb = atomicAdd(&cell_count[cell], gcount);
+  if (is_leader) cb = atomicAdd(&cell_count[(size_t)cell * kKeyStride], gcount);
   cb = __shfl(cb, (int)my_leader);
   base = __shfl(base, (int)leader);
   if (valid) {
@@ -80,7 +80,7 @@ __device__ uint32_t wave_key_rank(bool valid, uint32_t key, uint32_t* cell_count
     pending &= ~same;
   }
   uint32_t cb = 0;
-  if (is_leader) cb = atomicAdd(&cell_count[key], gcount);
+  if (is_leader) cb = atomicAdd(&cell_count[(size_t)key * kKeyStride], gcount);
   cb = __shfl(cb, (int)my_leader);
   return cb + my_off;
 }
@@ -552,7 +552,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(DevScene S, DevWS w, int 
   const int c0 = min(nc, (int)threadIdx.x * chunk), c1 = min(nc, c0 + chunk);
   uint32_t sc = 0, st = 0;
   for (int c = c0; c < c1; ++c) {
-    const uint32_t x = cnt[c];
+    const uint32_t x = cnt[(size_t)c * kKeyStride];
     if (staged) s_key[c] = x;
     sc += x;
     st += (x + kTile - 1) / kTile;
@@ -565,7 +565,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(DevScene S, DevWS w, int 
   uint32_t run = ic - sc;
   for (int c = c0; c < c1; ++c) {
     w.coff[c] = run;
-    run += staged ? s_key[c] : cnt[c];
+    run += staged ? s_key[c] : cnt[(size_t)c * kKeyStride];
   }
   // Tiles are written by the whole workgroup, each thread a contiguous block of them: the key of
   // its first tile comes from a binary search of the per-thread tile sums and a walk over that
@@ -587,14 +587,14 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(DevScene S, DevWS w, int 
     }
     uint32_t tb = lo ? s_til[lo - 1] : 0u, cb = lo ? s_cnt[lo - 1] : 0u;
     int c = lo * chunk;
-    uint32_t x = staged ? s_key[c] : cnt[c], nt = (x + kTile - 1) / kTile;
+    uint32_t x = staged ? s_key[c] : cnt[(size_t)c * kKeyStride], nt = (x + kTile - 1) / kTile;
     for (; t < t_end; ++t) {
       // keys with no tile left are passed over; t < n_tiles keeps c below nc
       while (t >= tb + nt && c + 1 < nc) {
         tb += nt;
         cb += x;
         ++c;
-        x = staged ? s_key[c] : cnt[c];
+        x = staged ? s_key[c] : cnt[(size_t)c * kKeyStride];
         nt = (x + kTile - 1) / kTile;
       }
       const uint32_t q = t - tb;
@@ -608,7 +608,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(DevScene S, DevWS w, int 
   }
   if (threadIdx.x < kXcds) w.ctl->tile_next[threadIdx.x] = 0;
   uint32_t* other = ccount_of(S, w, p ^ 1);
-  for (int c = threadIdx.x; c < nc; c += kScanThreads) other[c] = 0;
+  for (int c = threadIdx.x; c < nc; c += kScanThreads) other[(size_t)c * kKeyStride] = 0;
 }
 
 // Each thread moves kPer entries per pass, all their loads issued before any store (the lists and
