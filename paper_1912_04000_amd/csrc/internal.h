@@ -29,6 +29,7 @@ constexpr uint32_t kBlocked = 0xFFFFFFFFu;
 constexpr uint32_t kFirstVisit = 0x80000000u;
 constexpr uint32_t kShadowBit = 0x80000000u;  // in the ray's slot word
 constexpr uint32_t kInvalidCell = 0xFFFFFFFFu;
+constexpr uint32_t kNoKey = 0xFFFFFFFFu;  // produced-list entry without destination queue (skipped)
 constexpr uint32_t kEmptyChild = 0xFFFFFFFFu;
 // Traversal stack entries: an inner node index, or a leaf as flag | count << 27 | first triangle.
 constexpr uint32_t kStackLeaf = 0x80000000u;

@@ -85,36 +85,6 @@ __device__ uint32_t wave_key_rank(bool valid, uint32_t key, uint32_t* cell_count
   return cb + my_off;
 }
 
-// Append of up to two entries per lane (src0 to queue key0 if v0, src1 to key1 if v1) with ONE
-// list-counter atomic per wave: the counter is a single address that every wave of a launch
-// increments, and atomics on one cache line are served one at a time (about 10 ns each on the
-// MI355X), so the list allocation, not the entry writes, bounds a kernel that appends per wave
-// iteration. Every lane of the wave must call it.
-__device__ void wave_append2(bool v0, uint32_t src0, uint32_t key0, bool v1, uint32_t src1, uint32_t key1,
-                             uint32_t* list_count, uint32_t* cell_count, uint32_t* lsrc, uint32_t* ldst,
-                             uint32_t* lrank) {
-  const uint64_t m0 = __ballot(v0), m1 = __ballot(v1);
-  const uint32_t c0 = (uint32_t)__popcll(m0), c = c0 + (uint32_t)__popcll(m1);
-  if (c == 0) return;
-  uint32_t base = 0;
-  if (lane_id() == 0) base = atomicAdd(list_count, c);
-  const uint32_t r0 = wave_key_rank(v0, key0, cell_count);
-  const uint32_t r1 = wave_key_rank(v1, key1, cell_count);
-  base = __shfl(base, 0);
-  if (v0) {
-    const uint32_t pos = base + count_below(m0);
-    lsrc[pos] = src0;
-    ldst[pos] = key0;
-    lrank[pos] = r0;
-  }
-  if (v1) {
-    const uint32_t pos = base + c0 + count_below(m1);
-    lsrc[pos] = src1;
-    ldst[pos] = key1;
-    lrank[pos] = r1;
-  }
-}
-
 // Workgroup-level append of up to two (src, key) entries per lane (all threads of the
 // workgroup call it; s_scr holds kWG / 64 words of LDS): the positions in the produced-entry
 // list come from one list-counter atomic per workgroup and a prefix over its waves, the ranks
@@ -612,7 +582,8 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(DevScene S, DevWS w, int 
 }
 
 // Each thread moves kPer entries per pass, all their loads issued before any store (the lists and
-// the queue are all uint32 memory: a load after a store would wait for it).
+// the queue are all uint32 memory: a load after a store would wait for it); entries marked kNoKey
+// (no ray) are passed over.
 __global__ void k_scatter(DevWS w, int gen) {
   constexpr int kPer = 4;
   const uint32_t n = w.ctl->list_count[gen & 1];
@@ -627,10 +598,10 @@ __global__ void k_scatter(DevWS w, int gen) {
       src[k] = i < n ? w.lsrc[i] : 0u;
     }
 #pragma unroll
-    for (int k = 0; k < kPer; ++k) base[k] = i0 + k * stride < n ? w.coff[key[k]] : 0u;
+    for (int k = 0; k < kPer; ++k) base[k] = i0 + k * stride < n && key[k] != kNoKey ? w.coff[key[k]] : 0u;
 #pragma unroll
     for (int k = 0; k < kPer; ++k)
-      if (i0 + k * stride < n) w.queue[base[k] + rank[k]] = src[k];
+      if (i0 + k * stride < n && key[k] != kNoKey) w.queue[base[k] + rank[k]] = src[k];
   }
 }
 
@@ -1328,6 +1299,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2))) void k
   const uint32_t* list = cat_list(w, p, kCatOpaque);
   const size_t W = w.W;
   const int gp = gen & 1;
+  if (blockIdx.x == 0 && threadIdx.x == 0) w.ctl->list_count[gp] = 2 * n;
   const uint32_t n_iter = (n + kWG - 1) / kWG * kWG;
   for (uint32_t a = blockIdx.x * kWG + threadIdx.x; a < n_iter; a += gridDim.x * kWG) {
     const bool valid = a < n;
@@ -1498,9 +1470,21 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2))) void k
         if (ext_cell == kInvalidCell) w.hit[s] = make_float4(INFINITY, __uint_as_float(0xFFFFFFFFu), 0.0f, 0.0f);
       }
     }
-    wave_append2(has_ext && ext_cell != kInvalidCell, s | kFirstVisit, qkey(ext_cell, ext_dir),
-                 has_sh && sh_cell != kInvalidCell, ((uint32_t)W + s) | kFirstVisit, qkey(sh_cell, sh_dir),
-                 &w.ctl->list_count[gp], ccount_of(S, w, gp), w.lsrc, w.ldst, w.lrank);
+    // Vertex a's new rays take produced-list entries 2a (extension) and 2a + 1 (shadow), an entry
+    // without a ray marked kNoKey: no list-counter atomic, which every wave of the launch would
+    // queue on (atomics on one cache line are served one at a time). The list is empty when
+    // opaque shading starts; its length is set to 2n below and glass shading appends after it.
+    {
+      const bool ve = has_ext && ext_cell != kInvalidCell, vs = has_sh && sh_cell != kInvalidCell;
+      const uint32_t ke = ve ? qkey(ext_cell, ext_dir) : kNoKey, ks = vs ? qkey(sh_cell, sh_dir) : kNoKey;
+      uint32_t* cc = ccount_of(S, w, gp);
+      const uint32_t re = wave_key_rank(ve, ke, cc), rs = wave_key_rank(vs, ks, cc);
+      if (valid) {
+        ((uint2*)w.lsrc)[a] = make_uint2(s | kFirstVisit, ((uint32_t)W + s) | kFirstVisit);
+        ((uint2*)w.ldst)[a] = make_uint2(ke, ks);
+        ((uint2*)w.lrank)[a] = make_uint2(re, rs);
+      }
+    }
     // rays that miss the grid box finish at once
     if (has_sh && sh_cell == kInvalidCell) w.catb[(size_t)W + s] = (uint8_t)(kCatShadowClear + 1);
     if (has_ext && ext_cell == kInvalidCell && S.env_nonzero) w.catb[s] = (uint8_t)(kCatEscape + 1);
