@@ -267,7 +267,7 @@ int run_paths(sdd_ctx* ctx, const sdd_scene* scene, const sdd_render_params* p, 
   const int rounds = p->queue_rounds ? p->queue_rounds : kDefaultRounds;
   const int D = p->max_depth;
   const bool query = cache && pm.purpose == 0 && D >= kCacheDepth;
-  HIP_TRY(ctx, launch_fill_u32(ctx->stream, &w.ctl->cat_count[0][0], 2 * 8, 0u));
+  HIP_TRY(ctx, launch_fill_u32(ctx->stream, &w.ctl->cat_count[0][0], 2 * 8 * kKeyStride, 0u));
   HIP_TRY(ctx, launch_fill_u32(ctx->stream, (uint32_t*)w.catb, ((size_t)2 * w.W + 3) / 4, 0u));
   HIP_TRY(ctx, launch_raygen(L, S, w, k0, n, p->seed, gen, pm));
   int rc = trace_phase(ctx, L, S, w, gen, rounds, 1, timing);
@@ -692,7 +692,7 @@ static int query(sdd_ctx* c, const sdd_scene* s, const float* orig, const float*
   int gen = 0;
   for (int64_t a = 0; a < n; a += W) {
     uint32_t m = (uint32_t)std::min<int64_t>(W, n - a);
-    HIP_TRY(c, launch_fill_u32(c->stream, &w.ctl->cat_count[0][0], 2 * 8, 0u));
+    HIP_TRY(c, launch_fill_u32(c->stream, &w.ctl->cat_count[0][0], 2 * 8 * kKeyStride, 0u));
     HIP_TRY(c, launch_fill_u32(c->stream, (uint32_t*)w.catb, ((size_t)2 * w.W + 3) / 4, 0u));
     HIP_TRY(c, launch_pack_rays(L, S, w, orig + 3 * a, dir + 3 * a, skip ? skip + a : nullptr, m, shadow ? 1 : 0, gen));
     rc = trace_phase(c, L, S, w, gen, kQueryRounds, 0, false);

@@ -356,7 +356,7 @@ __global__ __launch_bounds__(kCWG) __attribute__((amdgpu_waves_per_eu(2))) void 
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, v = lane & 31;
   bf16x8 W[3][2][4], w4[4];
   load_weights(C, lane, W, w4);
-  const uint32_t n_o = w.ctl->cat_count[p][kCatOpaque], n_g = w.ctl->cat_count[p][kCatGlass];
+  const uint32_t n_o = w.ctl->cat_count[p][kCatOpaque * kKeyStride], n_g = w.ctl->cat_count[p][kCatGlass * kKeyStride];
   const uint32_t n = n_o + n_g;
   const uint32_t* lo = w.cat + ((size_t)p * kCats + kCatOpaque) * w.W;
   const uint32_t* lg = w.cat + ((size_t)p * kCats + kCatGlass) * w.W;

@@ -118,8 +118,13 @@ struct Ctl {
   uint32_t list_count[2];   // produced (ray, cell, rank) entries per generation parity
   uint32_t n_queue;         // entries in the cell-sorted queue of the current round
   uint32_t n_tiles;         // tiles of the current round
-  uint32_t tile_next[8];    // per-XCD tile counters of the current round (reset by k_scan)
-  uint32_t cat_count[2][8]; // finished-ray lists per bounce parity and category (kCats used)
+  uint32_t pad0[12];        // to the end of the first 64-byte line
+  // per-XCD tile counters of the current round (reset by k_scan), one 64-byte line each: every
+  // tile taken is an atomic on one of them, and atomics on one line are served one at a time
+  uint32_t tile_next[8 * kKeyStride];
+  // finished-ray list lengths per bounce parity and category (kCats used), category c at
+  // [c * kKeyStride]: one 64-byte line per counter
+  uint32_t cat_count[2][8 * kKeyStride];
   // statistics (accumulated until collected)
   unsigned long long st_paths, st_vertices, st_ext, st_shadow, st_visits, st_migr, st_escape, st_glass;
   unsigned long long err_cross, err_nonfinite, err_stack;

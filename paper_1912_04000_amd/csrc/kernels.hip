@@ -292,9 +292,7 @@ __device__ __forceinline__ uint32_t* cat_list(const DevWS& w, int par, int cat) 
 template <bool kTrain>
 __global__ __launch_bounds__(kWG) void k_raygen(DevScene S, DevWS w, uint64_t k0, uint32_t n, uint32_t key0,
                                                 uint32_t key1, int gen, PathMode pm) {
-  __shared__ uint32_t s_st[1];
   __shared__ float s_planes[3 * (kMaxGrid + 1)];  // the grid's slab planes, for locating the rays
-  stats_init(s_st, 1);
   for (int q = threadIdx.x; q < S.gx + S.gy + S.gz + 3; q += kWG) s_planes[q] = S.planes[q];
   __syncthreads();
   const uint32_t i = blockIdx.x * kWG + threadIdx.x;
@@ -356,17 +354,27 @@ __global__ __launch_bounds__(kWG) void k_raygen(DevScene S, DevWS w, uint64_t k0
       l4[q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     }
   }
+  // Path i's entry in the produced list is entry i (the list is empty before ray generation, its
+  // only producer): no list-counter atomic, one per workgroup on one cache line. A path whose ray
+  // misses the grid leaves an entry marked kNoKey, which the scatter passes over.
   const int p = gen & 1;
-  __shared__ uint32_t s_app[kWG / 64];
-  block_append2(s_app, valid && cell != kInvalidCell, i | kFirstVisit, qkey(cell, qdir), false, 0u, 0u,
-                &w.ctl->list_count[p], ccount_of(S, w, p), w.lsrc, w.ldst, w.lrank);
+  const bool in_grid = valid && cell != kInvalidCell;
+  const uint32_t key = in_grid ? qkey(cell, qdir) : kNoKey;
+  const uint32_t rank = wave_key_rank(in_grid, key, ccount_of(S, w, p));
+  if (valid) {
+    w.lsrc[i] = i | kFirstVisit;
+    w.ldst[i] = key;
+    w.lrank[i] = rank;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) w.ctl->list_count[p] = n;
   // camera rays that miss the grid box escape at once
   if (valid && cell == kInvalidCell && S.env_nonzero) w.catb[i] = (uint8_t)(kCatEscape + 1);
-  __syncthreads();
-  stats_add_ballot(s_st, 0, valid);
-  __syncthreads();
-  stats_flush(s_st, 0, &w.ctl->st_paths);
-  if (threadIdx.x == 0 && s_st[0]) atomicAdd(&w.ctl->st_ext, (unsigned long long)s_st[0]);
+  // n paths, each with its camera ray: counted once, not with an atomic per workgroup on the
+  // statistics' cache line
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    atomicAdd(&w.ctl->st_paths, (unsigned long long)n);
+    atomicAdd(&w.ctl->st_ext, (unsigned long long)n);
+  }
 }
 
 // User rays (closest-hit or shadow queries).
@@ -576,7 +584,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(DevScene S, DevWS w, int 
     w.ctl->n_tiles = s_til[kScanThreads - 1];
     w.ctl->list_count[p ^ 1] = 0;
   }
-  if (threadIdx.x < kXcds) w.ctl->tile_next[threadIdx.x] = 0;
+  if (threadIdx.x < kXcds) w.ctl->tile_next[threadIdx.x * kKeyStride] = 0;
   uint32_t* other = ccount_of(S, w, p ^ 1);
   for (int c = threadIdx.x; c < nc; c += kScanThreads) other[(size_t)c * kKeyStride] = 0;
 }
@@ -891,7 +899,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(7))) void k
         const uint32_t X = (xcd + donor) % kXcds;
         const uint32_t b = (uint32_t)(((uint64_t)n_tiles * X) / kXcds);
         const uint32_t e = (uint32_t)(((uint64_t)n_tiles * (X + 1)) / kXcds);
-        const uint32_t q = b + atomicAdd(&w.ctl->tile_next[X], 1u);
+        const uint32_t q = b + atomicAdd(&w.ctl->tile_next[X * kKeyStride], 1u);
         if (q < e) {
           t = q;
           break;
@@ -1136,7 +1144,7 @@ __global__ __launch_bounds__(kWG) void k_gather_cats(DevWS w, int par) {
         s_wsum[c][q] = tot;
         tot += x;
       }
-      s_base[c] = tot ? atomicAdd(&w.ctl->cat_count[par][c], tot) : 0u;
+      s_base[c] = tot ? atomicAdd(&w.ctl->cat_count[par][c * kKeyStride], tot) : 0u;
     }
     __syncthreads();
 #pragma unroll
@@ -1188,9 +1196,9 @@ __device__ __forceinline__ void row_update(float4* row, int nq, F f) {
 
 __global__ __launch_bounds__(kWG) void k_resolve(DevScene S, DevWS w, int depth) {
   const int p = depth & 1;
-  const uint32_t n_clear = w.ctl->cat_count[p][kCatShadowClear];
-  const uint32_t n_glass = w.ctl->cat_count[p][kCatShadowGlass];
-  if (blockIdx.x == 0 && threadIdx.x < kCats) w.ctl->cat_count[p ^ 1][threadIdx.x] = 0;  // lists of the next bounce
+  const uint32_t n_clear = w.ctl->cat_count[p][kCatShadowClear * kKeyStride];
+  const uint32_t n_glass = w.ctl->cat_count[p][kCatShadowGlass * kKeyStride];
+  if (blockIdx.x == 0 && threadIdx.x < kCats) w.ctl->cat_count[p ^ 1][threadIdx.x * kKeyStride] = 0;  // next bounce
   const uint32_t n = n_clear + n_glass;
   const int Bp = w.Bp, nq = Bp / 4;
   for (uint32_t i = blockIdx.x * kWG + threadIdx.x; i < n; i += gridDim.x * kWG) {
@@ -1239,7 +1247,7 @@ __global__ __launch_bounds__(kWG) void k_resolve(DevScene S, DevWS w, int depth)
 // k_resolve: the same slot may also have had a shadow ray resolved there.
 __global__ __launch_bounds__(kWG) void k_escape(DevScene S, DevWS w, int depth) {
   const int p = depth & 1;
-  const uint32_t n = w.ctl->cat_count[p][kCatEscape];
+  const uint32_t n = w.ctl->cat_count[p][kCatEscape * kKeyStride];
   const int Bp = w.Bp, nq = Bp / 4;
   const float4* env = (const float4*)S.env;
   for (uint32_t i = blockIdx.x * kWG + threadIdx.x; i < n; i += gridDim.x * kWG) {
@@ -1295,7 +1303,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2))) void k
   }
   __syncthreads();
   const int p = depth & 1;
-  const uint32_t n = w.ctl->cat_count[p][kCatOpaque];
+  const uint32_t n = w.ctl->cat_count[p][kCatOpaque * kKeyStride];
   const uint32_t* list = cat_list(w, p, kCatOpaque);
   const size_t W = w.W;
   const int gp = gen & 1;
@@ -1508,7 +1516,7 @@ __global__ __launch_bounds__(kWG) void k_shade_glass(DevScene S, DevWS w, int de
   for (int q = threadIdx.x; q < S.gx + S.gy + S.gz + 3; q += kWG) s_planes[q] = S.planes[q];
   __syncthreads();
   const int p = depth & 1;
-  const uint32_t n = w.ctl->cat_count[p][kCatGlass];
+  const uint32_t n = w.ctl->cat_count[p][kCatGlass * kKeyStride];
   const uint32_t* list = cat_list(w, p, kCatGlass);
   const int B = S.n_bins, Bp = w.Bp;
   const int gp = gen & 1;
