@@ -1520,6 +1520,10 @@ __global__ __launch_bounds__(kWG) void k_shade_glass(DevScene S, DevWS w, int de
   const uint32_t* list = cat_list(w, p, kCatGlass);
   const int B = S.n_bins, Bp = w.Bp;
   const int gp = gen & 1;
+  // vertex a's new ray takes produced-list entry base + a, after the 2 n_opaque entries of opaque
+  // shading (launched before this kernel in the same bounce); no list-counter atomic
+  const uint32_t base = 2 * w.ctl->cat_count[p][kCatOpaque * kKeyStride];
+  if (blockIdx.x == 0 && threadIdx.x == 0) w.ctl->list_count[gp] = base + n;
   const uint32_t n_iter = (n + kWG - 1) / kWG * kWG;
   for (uint32_t a = blockIdx.x * kWG + threadIdx.x; a < n_iter; a += gridDim.x * kWG) {
     const bool valid = a < n;
@@ -1572,8 +1576,16 @@ __global__ __launch_bounds__(kWG) void k_shade_glass(DevScene S, DevWS w, int de
       ext_dir = dir_bin(nd);
       if (ext_cell == kInvalidCell) w.hit[s] = make_float4(INFINITY, __uint_as_float(0xFFFFFFFFu), 0.0f, 0.0f);
     }
-    wave_append(valid && ext_cell != kInvalidCell, s | kFirstVisit, qkey(ext_cell, ext_dir), &w.ctl->list_count[gp],
-                ccount_of(S, w, gp), w.lsrc, w.ldst, w.lrank);
+    {
+      const bool ve = valid && ext_cell != kInvalidCell;
+      const uint32_t ke = ve ? qkey(ext_cell, ext_dir) : kNoKey;
+      const uint32_t re = wave_key_rank(ve, ke, ccount_of(S, w, gp));
+      if (valid) {
+        w.lsrc[base + a] = s | kFirstVisit;
+        w.ldst[base + a] = ke;
+        w.lrank[base + a] = re;
+      }
+    }
     if (valid && ext_cell == kInvalidCell && S.env_nonzero) w.catb[s] = (uint8_t)(kCatEscape + 1);
     stats_add_ballot(s_st, 0, valid);
   }
