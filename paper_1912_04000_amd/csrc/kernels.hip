@@ -1194,6 +1194,23 @@ __device__ __forceinline__ void row_update(float4* row, int nq, F f) {
   }
 }
 
+// dst[q] = f(q) over nq quads, C at a time, every load of a chunk (whatever f reads) issued before
+// the chunk's stores; with store false nothing is written (f still runs, in quad order).
+template <int C, class F>
+__device__ __forceinline__ void row_write(float4* dst, int nq, bool store, F f) {
+  for (int q0 = 0; q0 < nq; q0 += C) {
+    float4 v[C];
+#pragma unroll
+    for (int q = 0; q < C; ++q)
+      if (q0 + q < nq) v[q] = f(q0 + q);
+    if (store) {
+#pragma unroll
+      for (int q = 0; q < C; ++q)
+        if (q0 + q < nq) dst[q0 + q] = v[q];
+    }
+  }
+}
+
 __global__ __launch_bounds__(kWG) void k_resolve(DevScene S, DevWS w, int depth) {
   const int p = depth & 1;
   const uint32_t n_clear = w.ctl->cat_count[p][kCatShadowClear * kKeyStride];
@@ -1407,7 +1424,9 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2))) void k
         const float4* kt = (const float4*)(S.ktab + V.m * Bp);
         const float4* rt = (const float4*)(S.rho + V.m * Bp);
         const float4* E4 = (const float4*)S.sunE;
-        for (int q = 0; q < nq; ++q) {
+        // four quads at a time: their tables, β and sun spectrum are read before their NEE quads
+        // are stored, and likewise for the throughput update
+        row_write<4>(e4, nq, nee, [&](int q) {
           const float4 nn = nt[q], kk = kt[q], rr = rt[q];
           const float F[4] = {fresnel(nn.x, kk.x, V.cos_o), fresnel(nn.y, kk.y, V.cos_o),
                               fresnel(nn.z, kk.z, V.cos_o), fresnel(nn.w, kk.w, V.cos_o)};
@@ -1421,26 +1440,26 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2))) void k
               b_sum += dif[c];
             }
           }
+          float4 out = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
           if (nee) {
             const float4 bb = b4[q], EE = E4[q];
-            e4[q] = make_float4(bb.x * dif[0] * kn * EE.x, bb.y * dif[1] * kn * EE.y, bb.z * dif[2] * kn * EE.z,
-                                bb.w * dif[3] * kn * EE.w);
+            out = make_float4(bb.x * dif[0] * kn * EE.x, bb.y * dif[1] * kn * EE.y, bb.z * dif[2] * kn * EE.z,
+                              bb.w * dif[3] * kn * EE.w);
           }
-        }
+          return out;
+        });
         choose();
-        if (cont) {
-          for (int q = 0; q < nq; ++q) {
+        if (cont)
+          row_update<4>(b4, nq, [&](int q, float4 bb) {
             const float4 nn = nt[q], kk = kt[q], rr = rt[q];
             const float F0 = fresnel(nn.x, kk.x, V.cos_o), F1 = fresnel(nn.y, kk.y, V.cos_o),
                         F2 = fresnel(nn.z, kk.z, V.cos_o), F3v = fresnel(nn.w, kk.w, V.cos_o);
-            float4 bb = b4[q];
             bb.x *= (mirror ? F0 : (1.0f - F0) * rr.x) * inv_p;
             bb.y *= (mirror ? F1 : (1.0f - F1) * rr.y) * inv_p;
             bb.z *= (mirror ? F2 : (1.0f - F2) * rr.z) * inv_p;
             bb.w *= (mirror ? F3v : (1.0f - F3v) * rr.w) * inv_p;
-            b4[q] = bb;
-          }
-        }
+            return bb;
+          });
       }
       if (nee) {
         has_sh = true;
