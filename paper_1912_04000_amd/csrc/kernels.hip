@@ -1500,7 +1500,9 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2))) void k
     // Vertex a's new rays take produced-list entries 2a (extension) and 2a + 1 (shadow), an entry
     // without a ray marked kNoKey: no list-counter atomic, which every wave of the launch would
     // queue on (atomics on one cache line are served one at a time). The list is empty when
-    // opaque shading starts; its length is set to 2n below and glass shading appends after it.
+    // opaque shading starts: the scan of the last traversal round cleared it, and that round
+    // walks its rays to the end instead of queuing migrations. Its length is set to 2n above;
+    // glass shading, launched next, writes its entries after these.
     {
       const bool ve = has_ext && ext_cell != kInvalidCell, vs = has_sh && sh_cell != kInvalidCell;
       const uint32_t ke = ve ? qkey(ext_cell, ext_dir) : kNoKey, ks = vs ? qkey(sh_cell, sh_dir) : kNoKey;
