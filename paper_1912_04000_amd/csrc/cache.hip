@@ -706,7 +706,8 @@ __global__ void k_cache_grid_bwd(CacheDev C, uint32_t v0, uint32_t step_max) {
 }
 
 // Adam bookkeeping of one step: skipped (flag 0) when the step has no records; else the step
-// count advances and the bias corrections 1/(1 - b^t) are formed in FP64.
+// count advances and the bias corrections 1/(1 - b^t) are formed as -1/expm1(t log1p(b - 1)),
+// which keeps FP32 accuracy when b^t is close to 1 (b - 1 is exact for b in [1/2, 1]).
 __global__ void k_cache_adam_prep(CacheDev C, uint32_t v0, uint32_t step_max, float* opt, float b1, float b2) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   const uint32_t nv = step_range(C, v0, step_max);
@@ -716,8 +717,8 @@ __global__ void k_cache_adam_prep(CacheDev C, uint32_t v0, uint32_t step_max, fl
   }
   const uint32_t t = __float_as_uint(opt[0]) + 1u;
   opt[0] = __uint_as_float(t);
-  opt[1] = (float)(1.0 / (1.0 - pow((double)b1, (double)t)));
-  opt[2] = (float)(1.0 / (1.0 - pow((double)b2, (double)t)));
+  opt[1] = -1.0f / expm1f((float)t * log1pf(b1 - 1.0f));
+  opt[2] = -1.0f / expm1f((float)t * log1pf(b2 - 1.0f));
   opt[3] = 1.0f;
 }
 

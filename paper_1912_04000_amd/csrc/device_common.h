@@ -96,32 +96,94 @@ __device__ __forceinline__ void wave_add(unsigned long long* ctr, uint32_t x) {
 }
 
 
-// Geometry of the hit of slot s: vertex position, face-forward normal, geometric normal.
-// Distance and barycentrics of the winning triangle re-evaluated in FP64 with the sheared
-// formulation of the watertight test: the FP32 test of the traversal decides which triangle is
-// hit, this pass (run by whoever reads the hit) removes the cancellation that makes FP32
-// distances and barycentrics inaccurate for grazing rays. t, bu, bv are left as passed in when
-// the FP64 determinant is zero.
-__device__ __forceinline__ void refine_hit(F3 of, F3 df, F3 v0, F3 v1, F3 v2, float& t, float& bu, float& bv) {
-  const double o[3] = {of.x, of.y, of.z}, d[3] = {df.x, df.y, df.z};
-  const double ad[3] = {fabs(d[0]), fabs(d[1]), fabs(d[2])};
-  const int kz = (ad[0] >= ad[1] && ad[0] >= ad[2]) ? 0 : (ad[1] >= ad[2] ? 1 : 2);
-  const int kx = kz == 2 ? 0 : kz + 1, ky = kx == 2 ? 0 : kx + 1;
-  const double Sx = d[kx] / d[kz], Sy = d[ky] / d[kz], Sz = 1.0 / d[kz];
-  const double A[3] = {v0.x - o[0], v0.y - o[1], v0.z - o[2]};
-  const double B[3] = {v1.x - o[0], v1.y - o[1], v1.z - o[2]};
-  const double C[3] = {v2.x - o[0], v2.y - o[1], v2.z - o[2]};
-  const double Ax = A[kx] - Sx * A[kz], Ay = A[ky] - Sy * A[kz];
-  const double Bx = B[kx] - Sx * B[kz], By = B[ky] - Sy * B[kz];
-  const double Cx = C[kx] - Sx * C[kz], Cy = C[ky] - Sy * C[kz];
-  const double U = Cx * By - Cy * Bx, V = Ax * Cy - Ay * Cx, W = Bx * Ay - By * Ax;
-  const double det = U + V + W;
-  if (det == 0.0) return;
-  const double T = Sz * (U * A[kz] + V * B[kz] + W * C[kz]);
-  const double inv_det = 1.0 / det;
-  t = (float)(T * inv_det);
-  bu = (float)(V * inv_det);
-  bv = (float)(W * inv_det);
+// Error-free transformations in FP32 (round to nearest): a + b = s + e exactly (Knuth's
+// TwoSum) and a * b = p + e exactly (the FMA residual of the product).
+__device__ __forceinline__ float two_sum(float a, float b, float& e) {
+#pragma clang fp contract(off)
+  const float s = a + b;
+  const float bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+  return s;
+}
+__device__ __forceinline__ float two_prod(float a, float b, float& e) {
+  const float p = a * b;
+  e = __builtin_fmaf(a, b, -p);
+  return p;
+}
+// Compensated dot product (Ogita, Rump, Oishi 2005, Dot2) of x = xh + xl and y = yh + yl: the
+// high parts' products and sum are formed exactly, the terms with a low part added once, so the
+// result hi + lo is as accurate as if computed in twice the working precision.
+__device__ __forceinline__ float dot2(F3 xh, F3 xl, F3 yh, F3 yl, float& lo) {
+#pragma clang fp contract(off)
+  float r0, r1, r2, q1, q2;
+  const float h0 = two_prod(xh.x, yh.x, r0), h1 = two_prod(xh.y, yh.y, r1), h2 = two_prod(xh.z, yh.z, r2);
+  float p = two_sum(h0, h1, q1);
+  p = two_sum(p, h2, q2);
+  lo = (q1 + q2) + ((r0 + r1) + r2) + (dot3(xl, yh) + dot3(xh, yl));
+  return p;
+}
+
+// a*b - c*d for a = ah + al, b = bh + bl, c = ch + cl, d = dh + dl (exact sums of two floats),
+// returned as hi + lo: the products of the high parts and their difference are formed exactly,
+// the terms with one low part added once, so the result is accurate to about twice the working
+// precision even when the difference cancels.
+__device__ __forceinline__ float cross_term(float ah, float al, float bh, float bl, float ch, float cl, float dh,
+                                            float dl, float& lo) {
+#pragma clang fp contract(off)
+  float p1l, p2l, sl;
+  const float p1 = two_prod(ah, bh, p1l), p2 = two_prod(ch, dh, p2l);
+  const float sh = two_sum(p1, -p2, sl);
+  const float c = (sl + (p1l - p2l)) + ((ah * bl + al * bh) - (ch * dl + cl * dh));
+  const float hi = sh + c;      // |c| is below ulp(sh) unless sh == 0: fast two-sum
+  lo = c - (hi - sh);
+  return hi;
+}
+
+// Distance and barycentrics of the winning triangle, re-evaluated by whoever reads the hit.
+// The traversal's FP32 watertight test decides WHICH triangle is hit; its sheared coordinates
+// carry the rounding of v - o, which is of the size of the ray's origin and, for a hit at
+// incidence cosine c, moves the distance by about eps |o| / c. Here the plane of the triangle
+// is intersected in FP32 arithmetic made exact where it cancels: the edges v1 - v0, v2 - v0 and
+// o - v0 are kept as exact sums of two floats, the normal is their compensated cross product
+// (kept as a sum of two floats too), the two dot products are compensated, and the hit point relative to v0,
+// q = (o - v0) + t d, is formed from the exact parts. On return t is the distance, q the hit
+// point minus v0 and (bu, bv) the barycentrics of v1 and v2. t, q, bu, bv keep their incoming
+// values when the ray is parallel to the triangle's plane.
+__device__ __forceinline__ void refine_hit(F3 o, F3 d, F3 v0, F3 v1, F3 v2, float& t, F3& q, float& bu,
+                                           float& bv) {
+#pragma clang fp contract(off)
+  F3 e1, e1l, e2, e2l, ah, al;
+  e1.x = two_sum(v1.x, -v0.x, e1l.x);
+  e1.y = two_sum(v1.y, -v0.y, e1l.y);
+  e1.z = two_sum(v1.z, -v0.z, e1l.z);
+  e2.x = two_sum(v2.x, -v0.x, e2l.x);
+  e2.y = two_sum(v2.y, -v0.y, e2l.y);
+  e2.z = two_sum(v2.z, -v0.z, e2l.z);
+  F3 nl;
+  const F3 n = f3(cross_term(e1.y, e1l.y, e2.z, e2l.z, e1.z, e1l.z, e2.y, e2l.y, nl.x),
+                  cross_term(e1.z, e1l.z, e2.x, e2l.x, e1.x, e1l.x, e2.z, e2l.z, nl.y),
+                  cross_term(e1.x, e1l.x, e2.y, e2l.y, e1.y, e1l.y, e2.x, e2l.x, nl.z));
+  ah.x = two_sum(o.x, -v0.x, al.x);
+  ah.y = two_sum(o.y, -v0.y, al.y);
+  ah.z = two_sum(o.z, -v0.z, al.z);
+  float num_lo, den_lo;
+  const float num = dot2(ah, al, n, nl, num_lo);
+  const float den = dot2(d, f3(0.0f, 0.0f, 0.0f), n, nl, den_lo);
+  if (den == 0.0f) return;
+  // (o - v0 + t d) . n = 0:  t = -(num + num_lo) / (den + den_lo), kept as th + tl
+  const float th = -num / den;
+  const float r = __builtin_fmaf(-th, den, -num) - num_lo - th * den_lo;
+  const float tl = r / den;
+  // q = (ah + al) + (th + tl) d: the large parts ah + th d cancel exactly in two_sum
+  float px, py, pz, ex, ey, ez;
+  const float mx = two_prod(th, d.x, px), my = two_prod(th, d.y, py), mz = two_prod(th, d.z, pz);
+  const float sx = two_sum(ah.x, mx, ex), sy = two_sum(ah.y, my, ey), sz = two_sum(ah.z, mz, ez);
+  q = f3(sx + (ex + px + al.x + tl * d.x), sy + (ey + py + al.y + tl * d.y), sz + (ez + pz + al.z + tl * d.z));
+  t = th + tl;
+  // q = bu e1 + bv e2:  bu = (q x e2) . n / |n|^2,  bv = (e1 x q) . n / |n|^2
+  const float inv_nn = 1.0f / dot3(n, n);
+  bu = dot3(cross3(q, e2), n) * inv_nn;
+  bv = dot3(cross3(e1, q), n) * inv_nn;
 }
 
 struct Vertex {
@@ -146,8 +208,9 @@ __device__ __forceinline__ Vertex load_vertex(const DevScene& S, const DevWS& w,
   V.cos_o = fabsf(V.dn);
   const float4 rorg = w.rays[2 * s];
   float t = h.x, bu = 1.0f / 3.0f, bv = 1.0f / 3.0f;
-  refine_hit(f3(rorg.x, rorg.y, rorg.z), V.d, v0, v1, v2, t, bu, bv);
-  V.p = v0 * (1.0f - bu - bv) + v1 * bu + v2 * bv;
+  F3 q = ((v1 - v0) + (v2 - v0)) * (1.0f / 3.0f);
+  refine_hit(f3(rorg.x, rorg.y, rorg.z), V.d, v0, v1, v2, t, q, bu, bv);
+  V.p = v0 + q;
   V.eps = 1e-5f * (1.0f + maxabs3(V.p));
   return V;
 }
