@@ -108,6 +108,17 @@ int sdd_set_stream(sdd_ctx* ctx, void* hip_stream);
  * context stream and bind the scene to it; dev_buf must stay valid while the scene is used. */
 int sdd_scene_upload(sdd_ctx* ctx, sdd_scene* scene, void* dev_buf, size_t bytes);
 
+/* Change the lighting of a built scene without rebuilding its cells: the directional sun (a plane
+ * wave, section 3; its direct term is eq. 3) as the direction TOWARD the sun (normalised here,
+ * non-zero and finite) and the irradiance E_j of every bin (host array [n_bins], finite >= 0);
+ * or the radiance of rays that leave the scene (host array [n_bins], finite >= 0, or NULL for
+ * zero). The scene's host image is updated and, if it was uploaded, its device copy too, on the
+ * context stream; the call waits for the copy. Renders enqueued before the call use the old
+ * values. Errors: SDD_ERR_INVALID_ARG (null pointer, bad values, scene uploaded on another
+ * device), SDD_ERR_HIP. */
+int sdd_set_sun(sdd_ctx* ctx, sdd_scene* scene, const float dir_to_sun[3], const float* irradiance);
+int sdd_set_env(sdd_ctx* ctx, sdd_scene* scene, const float* radiance);
+
 /* Pinhole observer (section 1: the observer is the camera position and properties). Pixel
  * (x, y) has y = 0 at the top; its sample s is jittered inside the pixel. */
 typedef struct {
@@ -344,8 +355,12 @@ int sdd_render_cached(sdd_ctx* ctx, const sdd_scene* scene, sdd_cache* cache, co
  * 1 if the slot's path reached its third vertex else 0), target [n][max_bins]. */
 int sdd_cache_get_records(sdd_ctx* ctx, sdd_cache* cache, int64_t n, float* rec_x, float* rec_w, float* target);
 
-/* Wait for the context stream, then report device-side errors (capacity overflow, non-finite
- * values) of the work enqueued since the previous sdd_finish. */
+/* Wait for the context stream, then report device-side errors of the work enqueued since the
+ * previous sdd_finish: SDD_ERR_QUEUE_OVERFLOW when a shadow ray reached the sun through more
+ * glass slabs than the kMaxCross = 8 it records (its visibility then misses the extra slabs),
+ * else SDD_ERR_DEVICE when non-finite radiance reached an image (it is stored as computed; huge
+ * finite inputs can overflow). The counts are in sdd_stats (err_cross_overflow, err_nonfinite).
+ * The flags are cleared by the call. */
 int sdd_finish(sdd_ctx* ctx);
 
 typedef struct {

@@ -120,6 +120,8 @@ SIGNATURES = [
     ("sdd_set_stream", _i32, [_vp, _vp]),
     ("sdd_scene_upload", _i32, [_vp, _vp, _vp, _sz]),
     ("sdd_workspace_bytes", _i32, [_vp, _vp, _vp]),
+    ("sdd_set_sun", _i32, [_vp, _vp, _vp, _vp]),
+    ("sdd_set_env", _i32, [_vp, _vp, _vp]),
     ("sdd_render", _i32, [_vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     ("sdd_render_batch", _i32, [_vp, _vp, _vp, _vp, _i32, _vp, _vp, _sz, _vp]),
     ("sdd_query_workspace_bytes", _i32, [_vp, _i64, _vp]),
@@ -327,6 +329,17 @@ class Context:
         self._err(lib().sdd_scene_upload(self.handle, scene.handle, C.c_void_p(view.data_ptr()), nbytes))
         scene.device_buffer = buf
         return scene
+
+    def set_sun(self, scene: Scene, dir_to_sun, irradiance):
+        d = (C.c_float * 3)(*[float(x) for x in dir_to_sun])
+        E = np.ascontiguousarray(irradiance, dtype=np.float32)
+        assert E.shape == (scene.n_bins,)
+        self._err(lib().sdd_set_sun(self.handle, scene.handle, d, _ptr(E)))
+
+    def set_env(self, scene: Scene, radiance=None):
+        L = None if radiance is None else np.ascontiguousarray(radiance, dtype=np.float32)
+        assert L is None or L.shape == (scene.n_bins,)
+        self._err(lib().sdd_set_env(self.handle, scene.handle, _ptr(L)))
 
     def workspace(self, nbytes):
         if self._ws is None or self._ws.numel() < nbytes:

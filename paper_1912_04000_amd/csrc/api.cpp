@@ -556,6 +556,49 @@ int sdd_scene_upload(sdd_ctx* c, sdd_scene* s, void* dev_buf, size_t bytes) {
   return SDD_OK;
 }
 
+// Rewrite the sun or environment rows of a scene: the host image, and the uploaded copy on the
+// context stream (waits, as sdd_scene_upload does). Renders enqueued earlier keep the old values.
+static int write_scene_rows(sdd_ctx* c, sdd_scene* s, size_t off, const float* row) {
+  const SceneHeader& H = s->hdr;
+  float* dst = (float*)(s->image.data() + off);
+  for (int j = 0; j < H.bins_pad; ++j) dst[j] = j < H.n_bins && row ? row[j] : 0.0f;
+  std::memcpy(s->image.data(), &s->hdr, sizeof(SceneHeader));
+  if (s->dev) {
+    if (s->dev_device != c->device) return fail(c, SDD_ERR_INVALID_ARG, "scene was uploaded on another device");
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipMemcpyAsync((uint8_t*)s->dev + off, dst, (size_t)H.bins_pad * 4, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(s->dev, s->image.data(), sizeof(SceneHeader), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+  }
+  return SDD_OK;
+}
+
+int sdd_set_sun(sdd_ctx* c, sdd_scene* s, const float dir_to_sun[3], const float* irradiance) {
+  if (!c) return fail(nullptr, SDD_ERR_INVALID_ARG, "ctx is null");
+  if (!s || !dir_to_sun || !irradiance) return fail(c, SDD_ERR_INVALID_ARG, "null argument");
+  const double l = std::sqrt((double)dir_to_sun[0] * dir_to_sun[0] + (double)dir_to_sun[1] * dir_to_sun[1] +
+                             (double)dir_to_sun[2] * dir_to_sun[2]);
+  if (!(l > 1e-12) || !std::isfinite(l)) return fail(c, SDD_ERR_INVALID_ARG, "sun direction must be non-zero and finite");
+  for (int j = 0; j < s->hdr.n_bins; ++j)
+    if (!(irradiance[j] >= 0) || !std::isfinite(irradiance[j]))
+      return fail(c, SDD_ERR_INVALID_ARG, "sun irradiance must be finite >= 0");
+  for (int a = 0; a < 3; ++a) s->hdr.sun[a] = (float)(dir_to_sun[a] / l);
+  return write_scene_rows(c, s, s->hdr.off_sunE, irradiance);
+}
+
+int sdd_set_env(sdd_ctx* c, sdd_scene* s, const float* radiance) {
+  if (!c) return fail(nullptr, SDD_ERR_INVALID_ARG, "ctx is null");
+  if (!s) return fail(c, SDD_ERR_INVALID_ARG, "scene is null");
+  int nz = 0;
+  for (int j = 0; radiance && j < s->hdr.n_bins; ++j) {
+    if (!(radiance[j] >= 0) || !std::isfinite(radiance[j]))
+      return fail(c, SDD_ERR_INVALID_ARG, "env radiance must be finite >= 0");
+    nz |= radiance[j] != 0.0f;
+  }
+  s->hdr.env_nonzero = nz;
+  return write_scene_rows(c, s, s->hdr.off_env, radiance);
+}
+
 int sdd_workspace_bytes(const sdd_scene* s, const sdd_render_params* p, size_t* bytes) {
   if (!s || !bytes) return fail(nullptr, SDD_ERR_INVALID_ARG, "null argument");
   std::string e = check_params(p);
@@ -747,6 +790,8 @@ int sdd_finish(sdd_ctx* c) {
     c->acc.tri_tests += h.st_tris;
     c->acc.cache_queries += h.st_queries;
     if (h.err_cross) status = fail(c, SDD_ERR_QUEUE_OVERFLOW, "a shadow ray crossed more glass slabs than recorded");
+    else if (h.err_nonfinite)
+      status = fail(c, SDD_ERR_DEVICE, std::to_string(h.err_nonfinite) + " non-finite radiance values reached the image");
     c->last_ctl = nullptr;
   }
   for (size_t i = 0; i < c->ev_used_trace; ++i) {

@@ -4,8 +4,10 @@
 //   producer (raygen / shade / pack)  -> (ray, start cell, rank in cell) entries
 //   k_scan     one workgroup: per-cell offsets, cell-sorted tile list
 //   k_scatter  entries -> cell-sorted queue
-//   k_trace    a tile = up to 256 rays of ONE cell: the cell's top BVH nodes are staged in LDS,
-//              each lane traverses its ray inside the cell's slab interval; rays that leave the
+//   k_trace    a tile = up to 256 rays of ONE queue key (cell, direction class), one ray per
+//              lane; the grid's slab planes, the cell table and each lane's short traversal
+//              stack live in LDS, the 4-wide BVH nodes and triangles are read from memory (L2).
+//              A lane traverses its ray inside the cell's slab interval; rays that leave the
 //              cell are re-queued for the next cell (the interface conditions between the
 //              paper's sub-domains, section 5) or, in the final round, walk on in place.
 //   shade      per-bin SoA spectral shading: complex Fresnel (eq. 1), thin-slab Beer-Lambert
@@ -407,7 +409,7 @@ __global__ __launch_bounds__(kWG) void k_pack_rays(DevScene S, DevWS w, const fl
 }
 
 // Hit records hold the FP32 distance and the triangle id; the distance and barycentrics handed
-// out are re-evaluated in FP64 here.
+// out are re-evaluated here with the compensated FP32 plane intersection of refine_hit.
 __global__ void k_unpack_hits(DevScene S, DevWS w, uint32_t n, float* t, int32_t* id, float* u, float* v) {
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const float4 h = w.hit[i];
@@ -417,8 +419,9 @@ __global__ void k_unpack_hits(DevScene S, DevWS w, uint32_t n, float* t, int32_t
       const float4* g = S.gtris + (size_t)tid * 3;
       const float4 A = g[0], B = g[1], C = g[2], ro = w.rays[2 * i], rd = w.rays[2 * i + 1];
       bu = bv = 1.0f / 3.0f;
+      F3 q;
       refine_hit(f3(ro.x, ro.y, ro.z), f3(rd.x, rd.y, rd.z), f3(A.x, A.y, A.z), f3(B.x, B.y, B.z), f3(C.x, C.y, C.z),
-                 th, bu, bv);
+                 th, q, bu, bv);
     }
     t[i] = th;
     id[i] = (int32_t)tid;
@@ -858,10 +861,11 @@ __device__ __forceinline__ uint32_t cpos_cell(const DevScene& S, uint32_t cpos) 
 // Lane phases of k_trace.
 enum : int { kLaneIdle = 0, kLaneEnter = 1, kLaneTrav = 2, kLaneLeave = 3, kLaneDone = 4 };
 
-// One tile = up to kTile rays of one queue key (cell, direction bin). The 256 lanes of the
-// workgroup each hold one ray at a time and take the next ray of the tile as soon as theirs is
-// finished, so a wave does not wait for its slowest ray; a lane steps one BVH node per loop
-// iteration. A ray's cell is traversed inside the cell's half-open slab interval; in every round
+// One tile = up to kTile rays of one queue key (cell, direction bin). The kWG lanes of the
+// workgroup take the tile's rays through a workgroup counter; with kTile == kWG every lane gets
+// at most one ray, so all lanes start the tile together (the coherence of their node fetches
+// was measured to matter more than refilling idle lanes) and a lane steps one BVH node or one
+// triangle per loop iteration. A ray's cell is traversed inside the cell's half-open slab interval; in every round
 // but the last the ray then migrates to the queue of the next cell, in the last round it walks
 // on in place. Finished rays go to LDS lists that the workgroup flushes to the global category
 // lists and the migration list once the tile is drained.
@@ -1622,6 +1626,7 @@ __global__ __launch_bounds__(kWG) void k_shade_glass(DevScene S, DevWS w, int de
 template <bool kUnique>
 __global__ __launch_bounds__(kWG) void k_accumulate(DevScene S, DevWS w, uint32_t s0, uint32_t n) {
   const int B = S.n_bins, Bp = w.Bp;
+  uint32_t n_bad = 0;  // bins of this thread's paths whose radiance is not finite
   for (uint32_t i = blockIdx.x * kWG + threadIdx.x; i < n; i += gridDim.x * kWG) {
     const uint32_t s = s0 + i;
     const ViewDesc& V = w.views[w.view[s]];
@@ -1652,6 +1657,7 @@ __global__ __launch_bounds__(kWG) void k_accumulate(DevScene S, DevWS w, uint32_
         for (int e = 0; e < 4; ++e) {
           const int j = 4 * (q0 + q) + e;
           const float c = c4[e] * V.inv_spp;
+          n_bad += (j < B && !isfinite(c)) ? 1u : 0u;
           if (j < B && c != 0.0f) {
             if constexpr (kUnique)
               img[(size_t)j * plane] = cur[4 * q + e] + c;
@@ -1662,6 +1668,9 @@ __global__ __launch_bounds__(kWG) void k_accumulate(DevScene S, DevWS w, uint32_
       }
     }
   }
+  // non-finite radiance (an overflow of huge but finite inputs, for example) is added to the
+  // image as it is and counted; sdd_finish reports it. One atomic per wave that saw any.
+  wave_add(&w.ctl->err_nonfinite, n_bad);
 }
 
 // ==========================================================================================

@@ -1,0 +1,141 @@
+"""Device-side error reporting and lighting changes through the C ABI, on the GPU.
+
+  * A shadow ray that crosses more glass slabs than the kMaxCross = 8 it records makes
+    sdd_finish return SDD_ERR_QUEUE_OVERFLOW (the kernel's own bounded handling: it counts and
+    skips the extra crossings).
+  * Radiance that overflows FP32 (huge but finite environment radiance carried by a throughput
+    above one) makes sdd_finish return SDD_ERR_DEVICE; the next render is clean again.
+  * sdd_set_sun / sdd_set_env change the lighting of an uploaded scene without rebuilding it:
+    the render then matches the oracle with the new lighting, and a scene built with that
+    lighting from the start, bit for bit.
+"""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import scenegen
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1912_04000_amd as sd
+    return sd.Context(0)
+
+
+def _scene(ctx, sc, grid=(2, 2, 2)):
+    import paper_1912_04000_amd as sd
+    S = sd.Scene.from_description(sc, grid=grid)
+    ctx.upload(S)
+    return S
+
+
+def _stacked_glass(n_layers):
+    """An opaque floor under n_layers glass quads stacked 10 cm apart, sun overhead."""
+    B = 4
+    s = 5.0
+    tris, mats = [((-s, -s, 0), (s, -s, 0), (s, s, 0)), ((-s, -s, 0), (s, s, 0), (-s, s, 0))], [0, 0]
+    for i in range(n_layers):
+        z, h = 1.0 + 0.1 * i, 2.0
+        tris += [((-h, -h, z), (h, -h, z), (h, h, z)), ((-h, -h, z), (h, h, z), (-h, h, z))]
+        mats += [1, 1]
+    return scenegen.Scene(
+        verts=np.asarray(tris, dtype=np.float32), mat=np.asarray(mats, dtype=np.uint16),
+        mat_type=np.array([0, 1], dtype=np.int32), thickness_m=np.array([0.0, 0.005], dtype=np.float32),
+        n_tab=np.array([[1.6] * B, [1.52] * B], dtype=np.float32), k_tab=np.array([[0.02] * B, [1e-6] * B],
+                                                                                 dtype=np.float32),
+        rho_tab=np.array([[0.8] * B, [0.0] * B], dtype=np.float32), lambda_min_nm=380.0, lambda_max_nm=780.0,
+        sun_dir=np.array([0.05, 0.03, 1.0], dtype=np.float32) / np.float32(np.linalg.norm([0.05, 0.03, 1.0])),
+        sun_E=np.ones(B, dtype=np.float32), env=np.zeros(B, dtype=np.float32), name="stack").check()
+
+
+@pytest.mark.parametrize("layers,expect", [(8, 0), (9, -4)])
+def test_glass_crossing_overflow_is_reported(ctx, layers, expect):
+    import paper_1912_04000_amd as sd
+    sc = _stacked_glass(layers)
+    S = _scene(ctx, sc)
+    cam = sd.camera((0.31, 0.17, 0.5), (0.33, 0.19, 0.0), (0, 1, 0), 20, 8, 8)
+    p = sd.render_params(spp=1, max_depth=1, seed=1)
+    ctx.reset_stats()
+    if expect == 0:
+        img = ctx.render(S, cam, p).cpu().numpy()
+        ref = oracle.render(sc, scenegen.Camera((0.31, 0.17, 0.5), (0.33, 0.19, 0.0), (0, 1, 0), 20, 8, 8), spp=1,
+                            max_depth=1, seed=1)
+        ok = ref.tied == 0
+        np.testing.assert_allclose(img[:, ok], ref.image[:, ok], rtol=1e-4)
+        assert ctx.stats()["err_cross_overflow"] == 0
+    else:
+        with pytest.raises(sd.SddError) as e:
+            ctx.render(S, cam, p)
+        say(f"{layers} glass layers: {e.value}")
+        assert e.value.code == expect
+        assert ctx.stats()["err_cross_overflow"] > 0
+    # the flags are cleared: a render of another scene reports nothing
+    S2 = _scene(ctx, _stacked_glass(2))
+    ctx.render(S2, cam, p)
+
+
+def test_nonfinite_radiance_is_reported_then_cleared(ctx):
+    """Two bins, n = 1.2 and 3.0 (F very different), rho = 1: the mirror lobe is taken with
+    probability mean F and multiplies bin 1 by F_1 / mean F > 1.9; the environment radiance of
+    bin 1 is 3e38, so a mirrored path that escapes carries more than the largest float."""
+    import paper_1912_04000_amd as sd
+    sc = scenegen.plane_scene(n_bins=2, n=1.6, k=0.0, rho=1.0, sun_dir=(0, 0, 1), env=1.0)
+    sc = dataclasses.replace(sc, n_tab=np.array([[1.2, 3.0], [1.52, 1.52]], dtype=np.float32),
+                             env=np.array([1.0, 3.0e38], dtype=np.float32)).check()
+    sc.sun_E[:] = 0
+    S = _scene(ctx, sc)
+    cam = sd.camera((0.1, -3.0, 3.0), (0.2, 0.1, 0.0), (0, 0, 1), 30, 16, 16)
+    ctx.reset_stats()
+    with pytest.raises(sd.SddError) as e:
+        ctx.render(S, cam, sd.render_params(spp=8, max_depth=2, seed=2))
+    say(f"overflow: {e.value}; stats err_nonfinite={ctx.stats()['err_nonfinite']}")
+    assert e.value.code == -7
+    assert ctx.stats()["err_nonfinite"] > 0
+    ctx.set_env(S, np.array([1.0, 2.0], dtype=np.float32))
+    img = ctx.render(S, cam, sd.render_params(spp=8, max_depth=2, seed=2)).cpu().numpy()
+    assert np.isfinite(img).all()
+
+
+def test_set_sun_and_env_match_oracle_and_rebuilt_scene(ctx):
+    import paper_1912_04000_amd as sd
+    sc = scenegen.nave_scene(8)
+    cam = scenegen.nave_camera(40, 32)
+    c = sd.camera(cam.eye, cam.target, cam.up, cam.vfov_deg, cam.width, cam.height)
+    S = _scene(ctx, sc)
+    p = sd.render_params(spp=2, max_depth=4, seed=6)
+    before = ctx.render(S, c, p).cpu().numpy()
+    # a lower sun from another azimuth, a bluish spectrum, and a sky
+    sun2 = scenegen.sun_direction(elevation_deg=22.0, azimuth_deg=-70.0)
+    E2 = (sc.sun_E * np.linspace(1.3, 0.7, 8)).astype(np.float32)
+    env2 = np.linspace(0.05, 0.02, 8).astype(np.float32)
+    ctx.set_sun(S, sun2, E2)
+    ctx.set_env(S, env2)
+    after = ctx.render(S, c, p).cpu().numpy()
+    sc2 = dataclasses.replace(sc, sun_dir=sun2, sun_E=E2, env=env2).check()
+    fresh = ctx.render(_scene(ctx, sc2), c, p).cpu().numpy()
+    np.testing.assert_array_equal(after, fresh)
+    assert np.abs(after - before).max() > 1e-2 * before.max()
+    ref = oracle.render(sc2, cam, spp=2, max_depth=4, seed=6)
+    mean_bin = ref.image.reshape(8, -1).mean(axis=1)
+    tol = 1e-4 * np.maximum(np.abs(ref.image), 1e-3 * mean_bin[:, None, None])
+    ok = ref.tied == 0
+    assert ok.mean() > 0.9
+    assert not ((np.abs(after - ref.image) > tol) & ok[None]).any()
+    # back to the original lighting: the first image again
+    ctx.set_sun(S, sc.sun_dir, sc.sun_E)
+    ctx.set_env(S, None)
+    np.testing.assert_array_equal(ctx.render(S, c, p).cpu().numpy(), before)
+    with pytest.raises(sd.SddError):
+        ctx.set_sun(S, (0.0, 0.0, 0.0), E2)
+    with pytest.raises(sd.SddError):
+        ctx.set_env(S, np.array([1.0] * 7 + [np.nan], dtype=np.float32))
