@@ -87,7 +87,9 @@ def _make_cache(ctx, kw, n_mat, lo, hi, B, **extra):
 
 @pytest.mark.parametrize("kw,B,n", [(SMALL, 8, 200), (SMALL, 13, 77),
                                     (dict(levels_pos=12, log2_table_pos=19, nmin_pos=16.0, nmax_pos=2048.0,
-                                          levels_dir=12, log2_table_dir=14, nmin_dir=4.0, nmax_dir=256.0), 40, 160)])
+                                          levels_dir=12, log2_table_dir=14, nmin_dir=4.0, nmax_dir=256.0), 40, 160),
+                                    (dict(levels_pos=12, log2_table_pos=19, nmin_pos=16.0, nmax_pos=2048.0,
+                                          levels_dir=12, log2_table_dir=14, nmin_dir=4.0, nmax_dir=256.0), 80, 97)])
 def test_cache_eval_matches_oracle(ctx, kw, B, n):
     lo, hi, n_mat = [-3.0, -1.0, 0.0], [17.0, 11.0, 8.5], 5
     P = _params(kw, n_mat, 3)
