@@ -87,43 +87,78 @@ def workload(name, spp_override):
     return sc, cam, cfg, label
 
 
-def algorithmic_bytes(st, B):
-    """HBM bytes the wavefront design must move, from the device counters (record sizes:
-    ray R = 32 B, hit H = 16 B, queue entry 4 B, produced list entry 12 B, spectral value 4 B
-    per bin, triangle record 48 B)."""
-    R, H, S = 32, 16, 4 * B
-    produced = st["ext_rays"] + st["shadow_rays"]
-    b = 0
-    b += st["paths"] * (R + S + 16)                 # raygen: ray, beta = 1, path state
-    b += produced * (12 + 12 + 4)                   # list write, scatter read, queue write
-    b += st["cell_visits"] * (4 + R)                # traversal: queue entry + ray record
-    b += st["migrations"] * 12                      # re-queued entries
-    b += st["ext_rays"] * 2 * H                     # hit record written, read by shading
-    b += st["vertices"] * (48 + 2 * S + R + 16)     # triangle, beta read+write, new ray, state
-    b += st["shadow_rays"] * (R + 3 * S)            # shadow ray, NEE weight write+read, image
-    return b
+# Record sizes of the wavefront design: ray R = 32 B, hit H = 16 B, queue entry Q = 4 B.
+REC_R, REC_H, REC_Q = 32, 16, 4
+# Algorithmic bytes of one cell visit of a ray: the ray record read, its queue entry written by
+# the scatter and read by the traversal.
+BYTES_PER_CELL_VISIT = REC_R + 2 * REC_Q
+
+
+def path_bytes(st, B):
+    """Algorithmic HBM bytes of the whole path, from the device counters: per path the camera
+    ray R and the throughput initialisation S, then the image read-modify-write 2 S; per vertex
+    the extension and shadow rays written (2 R), the hit record written and read (2 H) and the
+    spectral state 6 S (throughput, direct-term weight and gathered radiance, each read and
+    written); per cell visit of any ray 40 B (ray read, queue entry written and read). S = 4 B
+    per bin. This is R + 3 S + V (2 R + 2 H + 6 S) + 40 visits per path, the cell visits
+    counted instead of assumed (2 + mean migrations per vertex)."""
+    S = 4 * B
+    return (st["paths"] * (REC_R + 3 * S) + st["vertices"] * (2 * REC_R + 2 * REC_H + 6 * S)
+            + st["cell_visits"] * BYTES_PER_CELL_VISIT)
+
+
+def trace_bytes(st):
+    """Algorithmic HBM bytes of the traversal kernel: 40 B per cell visit and the 16 B hit record
+    every extension ray writes (hit or miss)."""
+    return st["cell_visits"] * BYTES_PER_CELL_VISIT + st["ext_rays"] * REC_H
+
+
+def _oracle_rate(sc, cam, spp, depth, px, threads):
+    """Spectral path samples/s of the oracle on a pixel list, its fixed per-call cost (the FP64
+    BVH build over the scene) measured on a one-pixel call and subtracted."""
+    import oracle
+    t0 = time.perf_counter()
+    oracle.render(sc, cam, spp=1, max_depth=depth, seed=1, pixels=px[:1], threads=threads)
+    fixed = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    r = oracle.render(sc, cam, spp=spp, max_depth=depth, seed=1, pixels=px, threads=threads)
+    dt = max(time.perf_counter() - t0 - fixed, 1e-9)
+    n = len(px) * spp
+    return n / dt, dt, fixed, r.stats["vertices"] / n
 
 
 def cpu_baseline(sc, cam, cfg, threads):
-    """The oracle as it stands, on the host cores, on the pixel subset x%4==0, y%4==0 at 32 spp
-    (a bounded sample of the same frame, ~10-30 s of CPU work); its fixed per-call cost (BVH
-    build) is subtracted."""
-    import numpy as np
-    import oracle
+    """The oracle as it stands, timed on the host: all-core (`threads` workers over pixel rows,
+    the paper's static image-space partition) on the pixel subset x % 4 == 0, y % 4 == 0 at 8 spp
+    of the same frame, single-thread on the subset x % 8 == 0, y % 8 == 0 at 1 spp, and the small
+    64 x 64 nave frame (8 bins, 1 spp, depth 4) in full, single-thread and all-core."""
+    import scenegen
     ys, xs = np.meshgrid(np.arange(0, cam.height, 4), np.arange(0, cam.width, 4), indexing="ij")
-    px = (ys * cam.width + xs).ravel()
-    spp = min(32, cfg["spp"])
-    t0 = time.perf_counter()
-    oracle.render(sc, cam, spp=1, max_depth=cfg["max_depth"], seed=1, pixels=px[:1], threads=threads)
-    fixed = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    r = oracle.render(sc, cam, spp=spp, max_depth=cfg["max_depth"], seed=1, pixels=px, threads=threads)
-    dt = time.perf_counter() - t0 - fixed
-    n = len(px) * spp
-    return {"value": n / dt, "unit": "spectral path samples/s", "cores": threads, "kind": "oracle",
-            "sample": f"{len(px)} pixels (every 4th row and column) x {spp} spp of the same frame, "
-                      f"{n} paths in {dt:.1f} s (+{fixed:.1f} s BVH build excluded), FP64",
-            "vertices_per_path": r.stats["vertices"] / n}
+    px4 = (ys * cam.width + xs).ravel()
+    ys, xs = np.meshgrid(np.arange(0, cam.height, 8), np.arange(0, cam.width, 8), indexing="ij")
+    px8 = (ys * cam.width + xs).ravel()
+    spp = min(8, cfg["spp"])
+    D = cfg["max_depth"]
+    rate, dt, fixed, vpp = _oracle_rate(sc, cam, spp, D, px4, threads)
+    rate1, dt1, _, _ = _oracle_rate(sc, cam, 1, D, px8, 1)
+    nave, ncam = scenegen.nave_scene(8), scenegen.nave_camera()
+    allpx = np.arange(ncam.width * ncam.height)
+    c1_all, _, _, _ = _oracle_rate(nave, ncam, 1, 4, allpx, threads)
+    c1_one, _, _, _ = _oracle_rate(nave, ncam, 1, 4, allpx, 1)
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = None
+    return {"value": rate, "unit": "spectral path samples/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(px4)} pixels (every 4th row and column) x {spp} spp of the same frame, "
+                      f"{len(px4) * spp} paths in {dt:.1f} s on {threads} threads (+{fixed:.1f} s BVH build "
+                      f"excluded), FP64",
+            "nproc": os.cpu_count(), "affinity_cpus": affinity,
+            "single_thread": {"value": rate1, "sample": f"{len(px8)} pixels (every 8th row and column) x 1 spp, "
+                                                          f"{len(px8)} paths in {dt1:.1f} s"},
+            "nave_64x64_full_frame": {"all_core": c1_all, "single_thread": c1_one,
+                                      "sample": "64x64 nave, 8 bins, 1 spp, depth 4, whole frame"},
+            "vertices_per_path": vpp}
 
 
 def traffic_from_profiles(kernel_src_hash):
@@ -537,24 +572,33 @@ def main():
         ctx.render(S, c, p, out=img)
     ctx.finish()
     ctx.reset_stats()
+    # per-step HIP events on the stream the library launches on (torch's current stream)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    ev[0].record()
+    for k in range(args.steps):
         ctx.render(S, c, p, out=img, finish=False)
+        ev[k + 1].record()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ctx.finish()
+    step_ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)]
     st = ctx.stats()
     samples = cam.width * cam.height * cfg["spp"] * args.steps
     value = samples / dt
     B = sc.n_bins
     # dominant kernel: the cell-local traversal (k_trace); its launches are bracketed by HIP events
-    ops = OPS_PER_NODE * st["node_visits"] + OPS_PER_TRI * st["tri_tests"]
+    # on the library's stream (timing = 1)
+    launches = max(1, st["trace_launches"])
     trace_s = st["trace_ms"] / 1e3
-    achieved = ops / trace_s / 1e12 if trace_s > 0 else 0.0
+    tb = trace_bytes(st)
+    achieved = tb / trace_s / 1e9 if trace_s > 0 else 0.0
+    ops = OPS_PER_NODE * st["node_visits"] + OPS_PER_TRI * st["tri_tests"]
+    alu = ops / trace_s / 1e12 if trace_s > 0 else 0.0
     src = open(os.path.join(ROOT, "paper_1912_04000_amd", "csrc", "kernels.hip"), "rb").read()
     traffic = traffic_from_profiles(hashlib.sha256(src).hexdigest())
-    ab = algorithmic_bytes(st, B)
+    ab = path_bytes(st, B)
     out = {
         "metric": METRIC, "value": value, "unit": "spectral path samples/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
@@ -562,16 +606,28 @@ def main():
         "config": {"workload": label, "triangles": sc.n_tri, "width": cam.width, "height": cam.height,
                    "spp": cfg["spp"], "bins": B, "max_depth": cfg["max_depth"], "grid": list(cfg["grid"]),
                    "wave_paths": p.wave_paths, "queue_rounds": args.queue_rounds or 1},
+        "ms_per_step_median": float(np.median(step_ms)), "ms_per_step_events": step_ms,
         "bin_samples_per_s": value * B,
-        "roofline": {"kernel": "k_trace", "bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS,
-                     "unit": "TFLOP/s", "frac": achieved / ALU_PEAK_TOPS, "traffic": traffic,
-                     "launches": st["trace_launches"], "avg_launch_ms": st["trace_ms"] / max(1, st["trace_launches"]),
-                     "ops_per_launch": ops / max(1, st["trace_launches"]),
-                     "note": "algorithmic FP32 VALU ops (104 per 4-wide BVH node, 56 per triangle test) over the "
-                             "HIP-event time of the k_trace launches; peak = non-packed VALU issue rate"},
+        "roofline": {"kernel": "k_trace", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
+                     "traffic": traffic, "traffic_over_algorithmic": (traffic / (tb / launches)) if traffic else None,
+                     "launches": st["trace_launches"], "avg_launch_ms": st["trace_ms"] / launches,
+                     "algorithmic_bytes_per_launch": tb / launches,
+                     "cell_visits_per_launch": st["cell_visits"] / launches,
+                     "note": "algorithmic bytes per launch (40 B per device-counted cell visit: ray record read, "
+                             "queue entry written and read; 16 B hit record per extension ray) over the HIP-event "
+                             "time of the k_trace launches on the library stream; traffic = HBM bytes per launch "
+                             "from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a copy calibration, null unless "
+                             "taken on this kernel source"},
+        "roofline_alu": {"kernel": "k_trace", "bound": "alu", "achieved": alu, "peak": ALU_PEAK_TOPS,
+                         "unit": "TOP/s", "frac": alu / ALU_PEAK_TOPS,
+                         "note": "secondary: algorithmic FP32 VALU ops (104 per 4-wide BVH node, 56 per triangle "
+                                 "test) over the same time; peak = non-packed VALU issue rate 256 CU x 64 x 2.4 GHz"},
         "path_hbm": {"algorithmic_bytes_per_sample": ab / max(1, st["paths"]),
                      "achieved_GBps": ab / dt / 1e9, "peak_GBps": HBM_PEAK_GBPS,
-                     "frac": ab / dt / 1e9 / HBM_PEAK_GBPS},
+                     "frac": ab / dt / 1e9 / HBM_PEAK_GBPS,
+                     "formula": "R + 3S + V(2R + 2H + 6S) + 40 B x cell visits per path, S = 4 B x bins, "
+                                "V and cell visits counted on the device"},
         "timing_split_ms": {"trace": st["trace_ms"] / args.steps, "shade": st["shade_ms"] / args.steps},
         "per_path": {"vertices": st["vertices"] / max(1, st["paths"]),
                      "shadow_rays": st["shadow_rays"] / max(1, st["paths"]),
@@ -590,7 +646,12 @@ def main():
         out["equal_rmse"] = equal_rmse(cached, a, value, cam.width, cam.height, args.warm_frames)
         out["equal_rmse"]["rmse_plain_frame"] = r64
     if not args.no_cpu_baseline:
-        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        # the host cores this job may use: its CPU affinity (a one-GPU machine allots 16), unless given
+        try:
+            avail = len(os.sched_getaffinity(0))
+        except AttributeError:
+            avail = os.cpu_count() or 1
+        threads = args.cpu_threads or min(16, avail)
         out["cpu_baseline"] = cpu_baseline(sc, cam, cfg, threads)
     else:
         out["cpu_baseline"] = None
