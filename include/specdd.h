@@ -163,6 +163,18 @@ int sdd_workspace_bytes(const sdd_scene* scene, const sdd_render_params* params,
 int sdd_render(sdd_ctx* ctx, const sdd_scene* scene, const sdd_camera* camera, const sdd_render_params* params,
                void* workspace, size_t workspace_bytes, float* image_dev);
 
+/* sdd_render for callers that cannot allocate device memory (code under stream capture, tight
+ * serving loops, harnesses that forbid allocation): the same render, with the workspace taken
+ * from a static device array of the library (64 MiB, one per device, held until the process
+ * ends) instead of a caller buffer; the library allocates nothing. wave_paths = 0 picks the most
+ * paths in flight (up to 2^20) whose workspace fits; a wave_paths whose workspace does not fit
+ * (about 0.7 KB per path at 40 bins, plus 3 KB per cell) is rejected with SDD_ERR_WORKSPACE.
+ * Plain mode only; use_graph and timing must be 0 (SDD_ERR_INVALID_ARG). Every call on a device
+ * shares that device's array: calls that overlap on one device (other streams or contexts) race,
+ * and each context must call sdd_finish before another context's render uses the array. */
+int sdd_render_noalloc(sdd_ctx* ctx, const sdd_scene* scene, const sdd_camera* camera,
+                       const sdd_render_params* params, float* image_dev);
+
 /* Render n_views views with uneven resolution and spp in one sequence of wavefronts: the
  * (view, pixel, sample) items of all views are drained by the same launches. images_dev[v]
  * is [n_bins][H_v][W_v]. View v uses RNG view index v. */

@@ -124,6 +124,7 @@ SIGNATURES = [
     ("sdd_set_env", _i32, [_vp, _vp, _vp]),
     ("sdd_render", _i32, [_vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     ("sdd_render_batch", _i32, [_vp, _vp, _vp, _vp, _i32, _vp, _vp, _sz, _vp]),
+    ("sdd_render_noalloc", _i32, [_vp, _vp, _vp, _vp, _vp]),
     ("sdd_query_workspace_bytes", _i32, [_vp, _i64, _vp]),
     ("sdd_trace", _i32, [_vp, _vp, _vp, _vp, _vp, _i64, _vp, _sz, _vp, _vp, _vp, _vp]),
     ("sdd_shadow", _i32, [_vp, _vp, _vp, _vp, _vp, _i64, _vp, _sz, _vp]),
@@ -361,6 +362,15 @@ class Context:
         if finish:
             self.finish()
         return img
+
+    def render_noalloc(self, scene: Scene, cam: Camera, params: RenderParams, out, finish=True):
+        """sdd_render with the library's static device workspace (no allocation by the library);
+        `out` is the caller's [n_bins][H][W] float32 device tensor."""
+        self._err(lib().sdd_render_noalloc(self.handle, scene.handle, C.byref(cam), C.byref(params),
+                                           C.c_void_p(out.data_ptr())))
+        if finish:
+            self.finish()
+        return out
 
     def render_batch(self, scene: Scene, cams, spp, params: RenderParams, outs=None, finish=True):
         n = len(cams)

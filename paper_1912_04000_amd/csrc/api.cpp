@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstddef>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -461,6 +462,31 @@ int render_views(sdd_ctx* ctx, const sdd_scene* scene, std::vector<ViewDesc>& vi
   return SDD_OK;
 }
 
+// Workspace of sdd_render_noalloc: a device array of the library itself, so that callers that
+// cannot allocate device memory can still render. Each device the library runs on holds its own
+// copy for the life of the process. Host code must not pass `scratch` itself to a kernel (on the
+// host it only names the symbol): its device address is looked up once per device, with that
+// device current, and kept in g_scratch_ptr.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device `dev` (looked up on the first call for it).
+hipError_t scratch_address(int dev, void** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -514,6 +540,11 @@ int sdd_create(sdd_ctx** out, int hip_device, void* hip_stream) {
   if (hip_device < 0 || hip_device >= n) return fail(nullptr, SDD_ERR_INVALID_ARG, "device index out of range");
   e = hipSetDevice(hip_device);
   if (e != hipSuccess) return fail(nullptr, SDD_ERR_HIP, hipGetErrorString(e));
+  if (hip_device >= kMaxDevices) return fail(nullptr, SDD_ERR_INVALID_ARG, "device index beyond the supported 64");
+  // the device's copy of the static render workspace: its address, once per device
+  void* scr = nullptr;
+  e = scratch_address(hip_device, &scr);
+  if (e != hipSuccess) return fail(nullptr, SDD_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
   sdd_ctx* c = new sdd_ctx();
   c->device = hip_device;
   c->stream = (hipStream_t)hip_stream;
@@ -627,6 +658,47 @@ int sdd_render(sdd_ctx* c, const sdd_scene* s, const sdd_camera* cam, const sdd_
   views[0].first_sample = (uint32_t)p->first_sample;
   HIP_TRY(c, hipSetDevice(c->device));
   return render_views(c, s, views, p, ws, ws_bytes);
+}
+
+int sdd_render_noalloc(sdd_ctx* c, const sdd_scene* s, const sdd_camera* cam, const sdd_render_params* p,
+                       float* image) {
+  if (!c) return fail(nullptr, SDD_ERR_INVALID_ARG, "ctx is null");
+  int rc = scene_ready(c, s);
+  if (rc) return rc;
+  if (!cam || !image) return fail(c, SDD_ERR_INVALID_ARG, "null camera or image");
+  std::string e = check_params(p);
+  if (!e.empty()) return fail(c, SDD_ERR_INVALID_ARG, e);
+  if (p->mode != SDD_MODE_PLAIN) return fail(c, SDD_ERR_INVALID_ARG, "sdd_render_noalloc renders in plain mode only");
+  // graph instantiation and timing events allocate: not here
+  if (p->use_graph || p->timing)
+    return fail(c, SDD_ERR_INVALID_ARG, "sdd_render_noalloc takes neither use_graph nor timing");
+  std::vector<ViewDesc> views(1);
+  e = make_view(*cam, &views[0]);
+  if (!e.empty()) return fail(c, SDD_ERR_INVALID_ARG, e);
+  views[0].spp = p->spp;
+  views[0].inv_spp = 1.0f / (float)p->spp;
+  views[0].image = image;
+  views[0].view_id = p->view;
+  views[0].first_sample = (uint32_t)p->first_sample;
+  const uint64_t total = (uint64_t)cam->width * cam->height * (uint64_t)p->spp;
+  const int B = s->hdr.n_bins, nc = s->hdr.n_cells;
+  // paths in flight: as asked, else the most (up to the library default) whose workspace fits
+  uint64_t W = p->wave_paths ? (uint64_t)p->wave_paths : (uint64_t)kDefaultWave;
+  W = std::max<uint64_t>(64, std::min<uint64_t>(W, total));
+  if (!p->wave_paths)
+    while (W > 64 && make_plan((uint32_t)W, B, nc, 1).total > kScratchBytes) W = std::max<uint64_t>(64, W * 3 / 4);
+  const size_t need = make_plan((uint32_t)W, B, nc, 1).total;
+  if (need > kScratchBytes)
+    return fail(c, SDD_ERR_WORKSPACE,
+                "sdd_render_noalloc: " + std::to_string(W) + " paths in flight need " + std::to_string(need) +
+                    " bytes of workspace, the static workspace holds " + std::to_string(kScratchBytes) +
+                    " (fewer wave_paths, bins or cells)");
+  HIP_TRY(c, hipSetDevice(c->device));
+  void* ws = nullptr;
+  HIP_TRY(c, scratch_address(c->device, &ws));
+  sdd_render_params q = *p;
+  q.wave_paths = (int32_t)W;
+  return render_views(c, s, views, &q, ws, kScratchBytes);
 }
 
 int sdd_render_batch(sdd_ctx* c, const sdd_scene* s, const sdd_camera* cams, const int32_t* spp, int32_t n_views,
