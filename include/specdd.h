@@ -119,6 +119,41 @@ int sdd_scene_upload(sdd_ctx* ctx, sdd_scene* scene, void* dev_buf, size_t bytes
 int sdd_set_sun(sdd_ctx* ctx, sdd_scene* scene, const float dir_to_sun[3], const float* irradiance);
 int sdd_set_env(sdd_ctx* ctx, sdd_scene* scene, const float* radiance);
 
+/* The sun of a date and clock time at a site (section 3: the sun is a plane wave whose spectrum
+ * at the ground changes with the hour, through the incidence angle in the atmosphere, and with
+ * the date, through the Earth-Sun distance; Rayleigh scattering theory gives the spectrum).
+ * Solar declination, equation of time and (r0/r)^2 from Spencer's (1971) series in the day angle
+ * 2 pi (d - 1) / 365; the position from the latitude and the hour angle of true solar time;
+ * air mass m from Kasten and Young (1989); Rayleigh optical depth of the standard atmosphere
+ * tau(l) = 0.008569 l^-4 (1 + 0.0113 l^-2 + 0.00013 l^-4) (l in um, Hansen and Travis 1974)
+ * times pressure_ratio; E_j = B(l_j, T) / B(555 nm, T) (r0/r)^2 exp(-tau(l_j) m) at the bin
+ * centres while the sun is above the horizon, else 0. */
+typedef struct {
+  int32_t day_of_year;         /* 1 .. 366                                                     */
+  float clock_hours;           /* local clock time, [0, 24]                                    */
+  float utc_offset_hours;      /* zone of the clock, [-14, 14] (e.g. 2 for CEST)               */
+  float latitude_deg;          /* site, [-90, 90], north positive                              */
+  float longitude_deg;         /* site, [-180, 180], east positive                             */
+  float scene_x_azimuth_deg;   /* compass azimuth (clockwise from north) of the scene's +x
+                                  axis; +z is up and +y = z x x (90: x east, y north)          */
+  float temperature_k;         /* blackbody temperature of the sun, 1e3 .. 1e5 (5778)          */
+  float pressure_ratio;        /* surface pressure over 1013.25 hPa, [0, 10]                   */
+} sdd_daylight;
+
+typedef struct {
+  float elevation_deg, azimuth_deg; /* sun above the horizon / compass azimuth                 */
+  float air_mass;                   /* relative optical air mass (+inf below the horizon)      */
+  float distance_factor;            /* (r0 / r)^2                                              */
+} sdd_daylight_info;
+
+/* Host computation (needs no GPU): direction toward the sun in the scene frame (unit) and the
+ * irradiance [n_bins] at the bin centres of [lambda_min, lambda_max]; info may be NULL.
+ * Errors: SDD_ERR_INVALID_ARG for parameters out of range or null outputs. */
+int sdd_daylight_sun(const sdd_daylight* params, int32_t n_bins, float lambda_min_nm, float lambda_max_nm,
+                     float dir_to_sun[3], float* irradiance, sdd_daylight_info* info);
+/* sdd_daylight_sun for the scene's bins, then sdd_set_sun with the result. */
+int sdd_set_daylight(sdd_ctx* ctx, sdd_scene* scene, const sdd_daylight* params, sdd_daylight_info* info);
+
 /* Pinhole observer (section 1: the observer is the camera position and properties). Pixel
  * (x, y) has y = 0 at the top; its sample s is jittered inside the pixel. */
 typedef struct {
@@ -366,6 +401,22 @@ int sdd_render_cached(sdd_ctx* ctx, const sdd_scene* scene, sdd_cache* cache, co
  * (position, material id as uint32 bits), rec_w [n][4] = (direction toward the previous vertex,
  * 1 if the slot's path reached its third vertex else 0), target [n][max_bins]. */
 int sdd_cache_get_records(sdd_ctx* ctx, sdd_cache* cache, int64_t n, float* rec_x, float* rec_w, float* target);
+
+/* Colorimetry of a spectral image (section 6 maps the spectral renderings to RGB by colorimetry;
+ * section 1: the observer's visual adaptation is a colorimetric matter). image_dev is device
+ * memory [n_bins][n_pixels] FP32 (an image [n_bins][H][W] has n_pixels = H W) sampled at the bin
+ * centres lambda_min + (j + 1/2)(lambda_max - lambda_min) / n_bins (nm). The CIE 1931 2-degree
+ * colour-matching functions come from the multi-lobe analytic fit of Wyman, Sloan and Shirley
+ * (JCGT 2013). Outputs (device, either may be NULL but not both):
+ *   xyz_dev [3][n_pixels]:  XYZ = exposure sum_j I_j cmf(l_j) / sum_j ybar(l_j)
+ *                           (a flat spectrum of radiance 1 gives Y = exposure);
+ *   srgb_dev [n_pixels][3]: sRGB (IEC 61966-2-1, D65 white) of XYZ, clamped to [0, 1] and
+ *                           encoded with the sRGB transfer function.
+ * Enqueued on the context stream. Errors: SDD_ERR_INVALID_ARG (null image or no output,
+ * n_bins outside 1..128, 0 < lambda_min < lambda_max violated, n_pixels < 1, exposure not finite
+ * >= 0), SDD_ERR_HIP. */
+int sdd_spectral_to_srgb(sdd_ctx* ctx, const float* image_dev, int32_t n_bins, float lambda_min_nm,
+                         float lambda_max_nm, int64_t n_pixels, float exposure, float* xyz_dev, float* srgb_dev);
 
 /* Wait for the context stream, then report device-side errors of the work enqueued since the
  * previous sdd_finish: SDD_ERR_QUEUE_OVERFLOW when a shadow ray reached the sun through more

@@ -40,6 +40,36 @@ class SceneDesc(C.Structure):
                 ("grid", C.c_int32 * 3)]
 
 
+class Daylight(C.Structure):
+    _fields_ = [("day_of_year", C.c_int32), ("clock_hours", C.c_float), ("utc_offset_hours", C.c_float),
+                ("latitude_deg", C.c_float), ("longitude_deg", C.c_float), ("scene_x_azimuth_deg", C.c_float),
+                ("temperature_k", C.c_float), ("pressure_ratio", C.c_float)]
+
+
+class DaylightInfo(C.Structure):
+    _fields_ = [("elevation_deg", C.c_float), ("azimuth_deg", C.c_float), ("air_mass", C.c_float),
+                ("distance_factor", C.c_float)]
+
+
+def daylight(day_of_year=172, clock_hours=12.0, utc_offset_hours=0.0, latitude_deg=49.14, longitude_deg=2.38,
+             scene_x_azimuth_deg=90.0, temperature_k=5778.0, pressure_ratio=1.0) -> Daylight:
+    d = Daylight()
+    d.day_of_year, d.clock_hours, d.utc_offset_hours = int(day_of_year), clock_hours, utc_offset_hours
+    d.latitude_deg, d.longitude_deg, d.scene_x_azimuth_deg = latitude_deg, longitude_deg, scene_x_azimuth_deg
+    d.temperature_k, d.pressure_ratio = temperature_k, pressure_ratio
+    return d
+
+
+def daylight_sun(params: Daylight, n_bins, lambda_min_nm=380.0, lambda_max_nm=780.0):
+    """The library's sun for a date and time (host computation): (direction [3], E [n_bins], info)."""
+    d = (C.c_float * 3)()
+    E = np.zeros(n_bins, dtype=np.float32)
+    info = DaylightInfo()
+    _check(lib().sdd_daylight_sun(C.byref(params), int(n_bins), float(lambda_min_nm), float(lambda_max_nm), d,
+                                  _ptr(E), C.byref(info)))
+    return np.array(d[:], dtype=np.float32), E, {n: getattr(info, n) for n, _ in DaylightInfo._fields_}
+
+
 class SceneInfo(C.Structure):
     _fields_ = [("n_tri", C.c_int64), ("n_refs", C.c_int64), ("n_nodes", C.c_int64), ("n_cells", C.c_int64),
                 ("n_empty_cells", C.c_int64), ("max_depth", C.c_int32), ("max_leaf", C.c_int32),
@@ -122,6 +152,8 @@ SIGNATURES = [
     ("sdd_workspace_bytes", _i32, [_vp, _vp, _vp]),
     ("sdd_set_sun", _i32, [_vp, _vp, _vp, _vp]),
     ("sdd_set_env", _i32, [_vp, _vp, _vp]),
+    ("sdd_daylight_sun", _i32, [_vp, _i32, C.c_float, C.c_float, _vp, _vp, _vp]),
+    ("sdd_set_daylight", _i32, [_vp, _vp, _vp, _vp]),
     ("sdd_render", _i32, [_vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     ("sdd_render_batch", _i32, [_vp, _vp, _vp, _vp, _i32, _vp, _vp, _sz, _vp]),
     ("sdd_render_noalloc", _i32, [_vp, _vp, _vp, _vp, _vp]),
@@ -130,6 +162,7 @@ SIGNATURES = [
     ("sdd_shadow", _i32, [_vp, _vp, _vp, _vp, _vp, _i64, _vp, _sz, _vp]),
     ("sdd_philox", _i32, [_vp, _vp, _vp, _i64, _vp]),
     ("sdd_finish", _i32, [_vp]),
+    ("sdd_spectral_to_srgb", _i32, [_vp, _vp, _i32, C.c_float, C.c_float, _i64, C.c_float, _vp, _vp]),
     ("sdd_get_stats", _i32, [_vp, _vp]),
     ("sdd_reset_stats", _i32, [_vp]),
     ("sdd_last_error", C.c_char_p, [_vp]),
@@ -337,6 +370,11 @@ class Context:
         assert E.shape == (scene.n_bins,)
         self._err(lib().sdd_set_sun(self.handle, scene.handle, d, _ptr(E)))
 
+    def set_daylight(self, scene: Scene, params: Daylight) -> dict:
+        info = DaylightInfo()
+        self._err(lib().sdd_set_daylight(self.handle, scene.handle, C.byref(params), C.byref(info)))
+        return {n: getattr(info, n) for n, _ in DaylightInfo._fields_}
+
     def set_env(self, scene: Scene, radiance=None):
         L = None if radiance is None else np.ascontiguousarray(radiance, dtype=np.float32)
         assert L is None or L.shape == (scene.n_bins,)
@@ -475,6 +513,24 @@ class Context:
 
     def finish(self):
         self._err(lib().sdd_finish(self.handle))
+
+    def spectral_to_srgb(self, image, lambda_min_nm=380.0, lambda_max_nm=780.0, exposure=1.0, want_xyz=True,
+                         want_srgb=True, finish=True, xyz_out=None, srgb_out=None):
+        """Colorimetry of a device image [B][H][W]: (XYZ [3][H][W] or None, sRGB [H][W][3] or None)."""
+        torch = self.torch
+        assert image.dtype == torch.float32 and image.is_contiguous() and image.dim() == 3
+        B, H, W = image.shape
+        xyz = xyz_out if xyz_out is not None else (
+            torch.empty((3, H, W), dtype=torch.float32, device=self.device) if want_xyz else None)
+        rgb = srgb_out if srgb_out is not None else (
+            torch.empty((H, W, 3), dtype=torch.float32, device=self.device) if want_srgb else None)
+        self._err(lib().sdd_spectral_to_srgb(self.handle, C.c_void_p(image.data_ptr()), int(B), float(lambda_min_nm),
+                                             float(lambda_max_nm), int(H * W), float(exposure),
+                                             None if xyz is None else C.c_void_p(xyz.data_ptr()),
+                                             None if rgb is None else C.c_void_p(rgb.data_ptr())))
+        if finish:
+            self.finish()
+        return xyz, rgb
 
     # -- learned radiance cache ------------------------------------------------------------
     def cache(self, cfg: CacheConfig, seed=None):

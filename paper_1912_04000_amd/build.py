@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libspecdd.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-SOURCES = ["api.cpp", "scene_build.cpp", "autotune.cpp", "cache_api.cpp", "kernels.hip", "cache.hip"]
+SOURCES = ["api.cpp", "scene_build.cpp", "autotune.cpp", "cache_api.cpp", "kernels.hip", "cache.hip", "color.hip", "daylight.cpp"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-munsafe-fp-atomics",
     # packed FP32 instructions are kept out of every kernel
