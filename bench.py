@@ -372,6 +372,34 @@ def bench_cached(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_colorimetry(ctx, img, sc, reps=20):
+    """The frame's colour image (spectral -> CIE XYZ -> sRGB, one HBM pass): HIP-event time of
+    `reps` launches on the library stream, against the algorithmic bytes per launch (the B
+    planes read, 3 XYZ planes and the 3-channel sRGB image written)."""
+    import torch
+    B, H, W = img.shape
+    xyz = torch.empty((3, H, W), dtype=torch.float32, device="cuda")
+    rgb = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
+    run = lambda: ctx.spectral_to_srgb(img, sc.lambda_min_nm, sc.lambda_max_nm, 1.0, finish=False, xyz_out=xyz,
+                                       srgb_out=rgb)
+    run()
+    ctx.finish()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        run()
+    e1.record()
+    torch.cuda.synchronize()
+    ctx.finish()
+    ms = e0.elapsed_time(e1) / reps
+    nbytes = H * W * (4 * B + 12 + 12)
+    gbps = nbytes / (ms * 1e-3) / 1e9
+    return {"kernel": "k_spectral_to_srgb", "bound": "hbm", "avg_launch_ms": ms, "achieved": gbps,
+            "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": gbps / HBM_PEAK_GBPS,
+            "algorithmic_bytes_per_launch": nbytes, "launches": reps,
+            "note": "per pixel 4 B x bins read, 12 B XYZ and 12 B sRGB written; HIP events on the library stream"}
+
+
 def crop_camera(cam, cw, ch):
     """The centred cw x ch window of a view as a camera of its own (same eye, axis and pixel
     footprint): tan(vfov'/2) = tan(vfov/2) ch / H."""
@@ -636,6 +664,7 @@ def main():
                      "tri_tests_per_ray": st["tri_tests"] / max(1, st["ext_rays"] + st["shadow_rays"])},
         "scene_build_s": build_s,
     }
+    out["colorimetry"] = bench_colorimetry(ctx, img, sc)
     if args.workload == "church" and not args.no_cached:
         # the cached half of the metric on the same view: the plain frame just timed (64 spp,
         # seed 1) fixes a = RMSE_64 sqrt(64) of the plain estimator's RMSE = a / sqrt(spp)

@@ -839,6 +839,19 @@ int sdd_philox(sdd_ctx* c, const uint32_t ctr[4], const uint32_t key[2], int64_t
   return SDD_OK;
 }
 
+int sdd_spectral_to_srgb(sdd_ctx* c, const float* image, int32_t n_bins, float lmin, float lmax, int64_t n_pixels,
+                         float exposure, float* xyz, float* srgb) {
+  if (!c) return fail(nullptr, SDD_ERR_INVALID_ARG, "ctx is null");
+  if (!image || (!xyz && !srgb)) return fail(c, SDD_ERR_INVALID_ARG, "null image, or no output");
+  if (n_bins < 1 || n_bins > kMaxBins) return fail(c, SDD_ERR_INVALID_ARG, "n_bins must lie in 1..128");
+  if (!(lmin > 0.0f) || !(lmax > lmin) || !std::isfinite(lmax)) return fail(c, SDD_ERR_INVALID_ARG, "need 0 < lambda_min < lambda_max");
+  if (n_pixels < 1) return fail(c, SDD_ERR_INVALID_ARG, "n_pixels must be >= 1");
+  if (!(exposure >= 0.0f) || !std::isfinite(exposure)) return fail(c, SDD_ERR_INVALID_ARG, "exposure must be finite >= 0");
+  HIP_TRY(c, hipSetDevice(c->device));
+  HIP_TRY(c, launch_spectral_to_srgb(c->stream, image, n_bins, lmin, lmax, (uint64_t)n_pixels, exposure, xyz, srgb));
+  return SDD_OK;
+}
+
 int sdd_finish(sdd_ctx* c) {
   if (!c) return fail(nullptr, SDD_ERR_INVALID_ARG, "ctx is null");
   HIP_TRY(c, hipSetDevice(c->device));

@@ -248,6 +248,10 @@ hipError_t launch_unpack_hits(const Launch& L, const DevScene& S, const DevWS& w
 hipError_t launch_resolve_vis(const Launch& L, const DevScene& S, const DevWS& w, uint32_t n, float* vis);
 hipError_t launch_philox(hipStream_t s, const uint32_t ctr[4], const uint32_t key[2], uint64_t n, uint32_t* out);
 
+// colorimetry (color.hip)
+hipError_t launch_spectral_to_srgb(hipStream_t s, const float* img, int B, float lmin, float lmax, uint64_t n,
+                                   float exposure, float* xyz, float* srgb);
+
 // radiance cache (cache.hip)
 hipError_t launch_cache_init(hipStream_t s, const CacheDev& C, uint64_t seed);
 hipError_t launch_cache_sync(hipStream_t s, const CacheDev& C);

@@ -139,3 +139,33 @@ def test_set_sun_and_env_match_oracle_and_rebuilt_scene(ctx):
         ctx.set_sun(S, (0.0, 0.0, 0.0), E2)
     with pytest.raises(sd.SddError):
         ctx.set_env(S, np.array([1.0] * 7 + [np.nan], dtype=np.float32))
+
+
+@pytest.mark.parametrize("day,hour", [(172, 16.0), (355, 11.0), (80, 18.3)])
+def test_daylight_render_matches_oracle(ctx, day, hour):
+    """sdd_set_daylight at the abbey's site (49.14 N, 2.38 E, clock zone UTC+1/+2, nave axis
+    east-west): the render matches the oracle rendering with the oracle's own daylight sun."""
+    import paper_1912_04000_amd as sd
+    from oracle import daylight as dl
+    sc = scenegen.nave_scene(8)
+    cam = scenegen.nave_camera(40, 32)
+    S = _scene(ctx, sc)
+    kw = dict(day_of_year=day, clock_hours=hour, utc_offset_hours=2.0 if 90 < day < 300 else 1.0,
+              latitude_deg=49.14, longitude_deg=2.38, scene_x_azimuth_deg=90.0)
+    info = ctx.set_daylight(S, sd.daylight(**kw))
+    kw32 = {k: (v if isinstance(v, int) else float(np.float32(v))) for k, v in kw.items()}
+    d, E, oinfo = dl.sun(dl.Daylight(**kw32), 8)
+    say(f"day {day} {hour} h: elevation {info['elevation_deg']:.2f} azimuth {info['azimuth_deg']:.1f} "
+        f"air mass {info['air_mass']:.2f}")
+    assert oinfo["elevation_deg"] > 0
+    sc2 = dataclasses.replace(sc, sun_dir=d.astype(np.float32), sun_E=E.astype(np.float32)).check()
+    p = sd.render_params(spp=2, max_depth=4, seed=8)
+    img = ctx.render(S, sd.camera(cam.eye, cam.target, cam.up, cam.vfov_deg, cam.width, cam.height), p).cpu().numpy()
+    ref = oracle.render(sc2, cam, spp=2, max_depth=4, seed=8)
+    mean_bin = ref.image.reshape(8, -1).mean(axis=1)
+    tol = 1e-4 * np.maximum(np.abs(ref.image), 1e-3 * mean_bin[:, None, None])
+    ok = ref.tied == 0
+    assert ok.mean() > 0.9
+    bad = (np.abs(img - ref.image) > tol) & ok[None]
+    assert not bad.any(), np.argwhere(bad)[:5]
+    assert ref.image.max() > 0
