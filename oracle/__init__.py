@@ -6,7 +6,8 @@ code with it; the two meet only on the seeded inputs of ``scenegen``.
 
 Contents:
   * ``oracle.cpp`` -- FP64 C++17: Philox4x32-10, unpolarised complex Fresnel (section 3,
-    eq. 1 for n + ik), thin-slab Beer-Lambert glass, Moeller-Trumbore closest hit / shadow
+    eq. 1 for n + ik), thin-slab Beer-Lambert glass (absorbing by k, or by a spectral
+    transmittance map read at the hit's texture coordinates, section 3), Moeller-Trumbore closest hit / shadow
     visibility (brute force or a median-split BVH), and the path estimator whose direct term
     is eq. 3 (section 4), with tie flags for paths that FP32 rounding could flip.
   * ``philox_generic.py`` -- a word-size-generic Philox used to pin the C++ generator.
@@ -42,7 +43,9 @@ class _Scene(C.Structure):
                 ("mat_type", C.c_void_p), ("thickness_m", C.c_void_p), ("n_tab", C.c_void_p),
                 ("k_tab", C.c_void_p), ("rho_tab", C.c_void_p), ("n_bins", C.c_int32),
                 ("lambda_min_nm", C.c_double), ("lambda_max_nm", C.c_double), ("sun_dir", C.c_void_p),
-                ("sun_E", C.c_void_p), ("env", C.c_void_p)]
+                ("sun_E", C.c_void_p), ("env", C.c_void_p), ("uv", C.c_void_p), ("n_tex", C.c_int32),
+                ("tex_dims", C.c_void_p), ("tex_offset", C.c_void_p), ("texels", C.c_void_p),
+                ("mat_tex", C.c_void_p)]
 
 
 class _Camera(C.Structure):
@@ -110,7 +113,18 @@ def _scene_struct(sc):
     s = _Scene(_p(keep["verts"]).value, sc.n_tri, _p(keep["mat"]).value, sc.n_mat, _p(keep["mat_type"]).value,
                _p(keep["thickness"]).value, _p(keep["n"]).value, _p(keep["k"]).value, _p(keep["rho"]).value,
                sc.n_bins, float(sc.lambda_min_nm), float(sc.lambda_max_nm), _p(keep["sun_dir"]).value,
-               _p(keep["sun_E"]).value, _p(keep["env"]).value)
+               _p(keep["sun_E"]).value, _p(keep["env"]).value, None, 0, None, None, None, None)
+    tex = getattr(sc, "textures", None)
+    if tex:
+        keep["uv"] = np.ascontiguousarray(sc.uv, dtype=np.float32)
+        keep["tex_dims"] = np.ascontiguousarray([[t.shape[1], t.shape[0]] for t in tex], dtype=np.int32)
+        sizes = [t.size for t in tex]
+        keep["tex_offset"] = np.ascontiguousarray(np.concatenate([[0], np.cumsum(sizes)[:-1]]), dtype=np.int64)
+        keep["texels"] = np.ascontiguousarray(np.concatenate([np.asarray(t, dtype=np.float32).ravel() for t in tex]))
+        keep["mat_tex"] = np.ascontiguousarray(sc.mat_tex, dtype=np.int32)
+        s.uv, s.n_tex = _p(keep["uv"]).value, len(tex)
+        s.tex_dims, s.tex_offset = _p(keep["tex_dims"]).value, _p(keep["tex_offset"]).value
+        s.texels, s.mat_tex = _p(keep["texels"]).value, _p(keep["mat_tex"]).value
     return s, keep
 
 

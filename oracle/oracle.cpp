@@ -114,6 +114,22 @@ void slab(double n, double k, double lambda_nm, double d_m, double cos_t, double
   *T = (1.0 - R1) * (1.0 - R1) * tau / den;
 }
 
+// The same slab when its internal transmittance at normal incidence tau0 is given directly (a
+// measured spectral transmittance map of the glass, section 3) instead of by k: Beer-Lambert
+// over the internal path d / cos(theta_t) makes it tau0^(1 / cos(theta_t)); the faces still
+// reflect by the Fresnel factor of n + ik.
+void slab_tau0(double n, double k, double tau0, double cos_t, double* R, double* T) {
+  cos_t = std::min(1.0, std::max(0.0, cos_t));
+  double sin_t = std::sqrt(std::max(0.0, 1.0 - cos_t * cos_t));
+  double sin_i = sin_t / n;
+  double cos_i = std::sqrt(std::max(0.0, 1.0 - sin_i * sin_i));
+  double tau = std::pow(tau0, 1.0 / cos_i);
+  double R1 = fresnel(n, k, cos_t);
+  double den = 1.0 - R1 * R1 * tau * tau;
+  *R = R1 + (1.0 - R1) * (1.0 - R1) * tau * tau * R1 / den;
+  *T = (1.0 - R1) * (1.0 - R1) * tau / den;
+}
+
 // ------------------------------------------------------------------------------------------
 // Scene in FP64
 // ------------------------------------------------------------------------------------------
@@ -296,7 +312,7 @@ Hit closest_hit(const Scene& S, V3 o, V3 d, int skip, const Tie& tie, bool* tied
 
 // Shadow ray toward the sun: any opaque hit (t > 0) blocks; every glass triangle crossed
 // multiplies the visibility by its slab transmittance at that crossing.
-struct GlassCross { int mat; double cos_t; };
+struct GlassCross { int mat; double cos_t; int tri; double u, v; };
 
 bool shadow_visibility(const Scene& S, const std::vector<int>& mat_type, V3 o, V3 d, int skip, const Tie& tie,
                        std::vector<GlassCross>* crossings, bool* tied) {
@@ -318,7 +334,7 @@ bool shadow_visibility(const Scene& S, const std::vector<int>& mat_type, V3 o, V
       if (ed > m && t > tiny) robust_block = true;
     } else {
       V3 ng = normalize(cross(T.v1 - T.v0, T.v2 - T.v0));
-      crossings->push_back({T.mat, std::fabs(dot(d, ng))});
+      crossings->push_back({T.mat, std::fabs(dot(d, ng)), i, u, v});
     }
   });
   if (robust_block) return false;
@@ -348,7 +364,48 @@ typedef struct {
   const float* sun_dir;      // [3] toward the sun
   const float* sun_E;        // [B]
   const float* env;          // [B]
+  // spectral transmittance maps of glass (n_tex = 0: none)
+  const float* uv;           // [N][3][2] texture coordinates of the triangle's vertices
+  int32_t n_tex;
+  const int32_t* tex_dims;   // [n_tex][2] width, height
+  const int64_t* tex_offset; // [n_tex] float offset of the map in texels
+  const float* texels;       // maps [h][w][B]: internal transmittance at normal incidence
+  const int32_t* mat_tex;    // [n_mat] map of the material, -1 none
 } orc_scene;
+
+// Internal transmittance at normal incidence of map t, bin j, at texture coordinates (s, t):
+// bilinear interpolation between texel centres ((i + 1/2) / w, (k + 1/2) / h), the map repeated
+// periodically in both directions.
+static double tex_tau0(const orc_scene* sc, int t, double s, double tt, int j) {
+  const int w = sc->tex_dims[2 * t], h = sc->tex_dims[2 * t + 1], B = sc->n_bins;
+  const float* T = sc->texels + sc->tex_offset[t];
+  double x = s * w - 0.5, y = tt * h - 0.5;
+  double fx0 = std::floor(x), fy0 = std::floor(y);
+  double fx = x - fx0, fy = y - fy0;
+  auto wrap = [](long long i, int n) { long long r = i % n; return (int)(r < 0 ? r + n : r); };
+  int i0 = wrap((long long)fx0, w), i1 = wrap((long long)fx0 + 1, w);
+  int k0 = wrap((long long)fy0, h), k1 = wrap((long long)fy0 + 1, h);
+  auto at = [&](int k, int i) { return (double)T[((int64_t)k * w + i) * B + j]; };
+  return (1 - fx) * (1 - fy) * at(k0, i0) + fx * (1 - fy) * at(k0, i1) + (1 - fx) * fy * at(k1, i0) +
+         fx * fy * at(k1, i1);
+}
+
+// Slab response of glass material m at bin j for a hit on triangle tri with barycentrics
+// (u, v): the material's map at the interpolated texture coordinates when it has one, else
+// Beer-Lambert with its k.
+static void glass_slab(const orc_scene* sc, int m, int j, double lambda_nm, double cos_t, int tri, double u, double v,
+                       double* R, double* T) {
+  const int B = sc->n_bins;
+  const int t = (sc->n_tex > 0 && sc->mat_tex) ? sc->mat_tex[m] : -1;
+  if (t < 0) {
+    slab(sc->n_tab[m * B + j], sc->k_tab[m * B + j], lambda_nm, sc->thickness_m[m], cos_t, R, T);
+    return;
+  }
+  const float* q = sc->uv + 6 * (int64_t)tri;
+  const double w0 = 1.0 - u - v;
+  const double s = w0 * q[0] + u * q[2] + v * q[4], tt = w0 * q[1] + u * q[3] + v * q[5];
+  slab_tau0(sc->n_tab[m * B + j], sc->k_tab[m * B + j], tex_tau0(sc, t, s, tt, j), cos_t, R, T);
+}
 
 typedef struct {
   double eye[3], target[3], up[3];
@@ -461,7 +518,7 @@ int orc_shadow(const orc_scene* sc, const float* orig, const float* dir, const i
       if (vis)
         for (const GlassCross& g : cr) {
           double R, T;
-          slab(sc->n_tab[g.mat * B + j], sc->k_tab[g.mat * B + j], lam[j], sc->thickness_m[g.mat], g.cos_t, &R, &T);
+          glass_slab(sc, g.mat, j, lam[j], g.cos_t, g.tri, g.u, g.v, &R, &T);
           V *= T;
         }
       out_vis[i * B + j] = V;
@@ -582,8 +639,7 @@ int orc_render(const orc_scene* sc, const orc_camera* cam, const orc_params* prm
                 double V = 1.0;
                 for (const GlassCross& g : cr) {
                   double R, Tt;
-                  slab(sc->n_tab[g.mat * B + j], sc->k_tab[g.mat * B + j], lam[j], sc->thickness_m[g.mat], g.cos_t,
-                       &R, &Tt);
+                  glass_slab(sc, g.mat, j, lam[j], g.cos_t, g.tri, g.u, g.v, &R, &Tt);
                   V *= Tt;
                 }
                 L[j] += beta[j] * (1.0 - F[j]) * rt[j] / M_PI * E[j] * cs * V;
@@ -621,7 +677,7 @@ int orc_render(const orc_scene* sc, const orc_camera* cam, const orc_params* prm
           double mr = 0, mt_ = 0;
           for (int j = 0; j < B; ++j) {
             double R, Tt;
-            slab(nt[j], kt[j], lam[j], sc->thickness_m[m], cos_o, &R, &Tt);
+            glass_slab(sc, m, j, lam[j], cos_o, h.id, h.u, h.v, &R, &Tt);
             F[j] = R;       // slab reflectance per bin
             F[B + j] = Tt;  // slab transmittance per bin
             mr += R;

@@ -87,6 +87,12 @@ class Scene:
     env: np.ndarray              # float32 [B] radiance of escaping rays
     name: str = ""
     info: dict = field(default_factory=dict)
+    # spectral transmittance maps of glass (optional): per-triangle texture coordinates, the maps
+    # (internal transmittance at normal incidence per texel and bin, in [0, 1]) and the map of
+    # each material (-1: none; the glass then absorbs by its k)
+    uv: np.ndarray | None = None         # float32 [N][3][2]
+    textures: list | None = None         # list of float32 [h][w][B]
+    mat_tex: np.ndarray | None = None    # int32 [n_mat]
 
     @property
     def n_bins(self) -> int:
@@ -108,6 +114,15 @@ class Scene:
         assert self.sun_E.shape == (self.n_bins,) and self.env.shape == (self.n_bins,)
         for a in ("verts", "mat", "mat_type", "thickness_m", "n_tab", "k_tab", "rho_tab", "sun_dir", "sun_E", "env"):
             setattr(self, a, np.ascontiguousarray(getattr(self, a)))
+        if self.textures is not None:
+            assert self.uv is not None and self.mat_tex is not None
+            self.uv = np.ascontiguousarray(self.uv, dtype=np.float32)
+            assert self.uv.shape == (self.n_tri, 3, 2)
+            self.mat_tex = np.ascontiguousarray(self.mat_tex, dtype=np.int32)
+            assert self.mat_tex.shape == (self.n_mat,) and self.mat_tex.max() < len(self.textures)
+            self.textures = [np.ascontiguousarray(t, dtype=np.float32) for t in self.textures]
+            for t in self.textures:
+                assert t.ndim == 3 and t.shape[2] == self.n_bins and t.min() >= 0 and t.max() <= 1
         return self
 
 
@@ -204,6 +219,56 @@ def nave_scene(n_bins: int = 8, seed: int = SCENE_SEED, lambda_min_nm: float = 3
         sun_dir=sun_direction(35.0, -90.0), sun_E=sun_irradiance(n_bins, lambda_min_nm, lambda_max_nm),
         env=np.zeros(n_bins, dtype=np.float32), name="nave",
     ).check()
+
+
+def glass_map(rng, lam_nm, d_m, width=12, height=16, n_spots=6):
+    """A seeded stand-in for a measured map of medieval glass (section 3: the spectral
+    transmittance measured at points of the samples, accessed by texture coordinates): internal
+    transmittance at normal incidence tau0 = exp(-4 pi k d / lambda) with k varying smoothly over
+    the pane (a few Gaussian absorption bumps whose strength drifts across it) and darker round
+    spots (micro-bubbles and inclusions). Returns float32 [height][width][B] in (0, 1]."""
+    B = len(lam_nm)
+    s = (np.arange(width) + 0.5) / width
+    t = (np.arange(height) + 0.5) / height
+    S, T = np.meshgrid(s, t)
+    k = np.full((height, width, B), 1e-7)
+    for _ in range(rng.integers(1, 4)):
+        a = rng.uniform(2e-6, 2e-5)
+        mu, sig = rng.uniform(400, 760), rng.uniform(15, 60)
+        drift = 1.0 + 0.5 * np.sin(2 * np.pi * (rng.uniform() + S * rng.uniform(0.5, 1.5) + T * rng.uniform(0.2, 1.0)))
+        k += a * drift[..., None] * np.exp(-0.5 * ((lam_nm[None, None, :] - mu) / sig) ** 2)
+    for _ in range(n_spots):
+        cs, ct, r = rng.uniform(0, 1), rng.uniform(0, 1), rng.uniform(0.03, 0.12)
+        k += 1.2e-5 * np.exp(-0.5 * (((S - cs) ** 2 + (T - ct) ** 2) / r**2))[..., None]
+    return np.exp(-4 * np.pi * k * d_m / (lam_nm * 1e-9)).astype(np.float32)
+
+
+def quad_uv(n_tri):
+    """Texture coordinates of _quad_grid quads taken one by one ((0,0) (1,0) (1,1) | (0,0) (1,1) (0,1))
+    for n_tri // 2 quads, others 0."""
+    q = np.array([[(0, 0), (1, 0), (1, 1)], [(0, 0), (1, 1), (0, 1)]], dtype=np.float32)
+    return np.tile(q, (n_tri // 2, 1, 1))
+
+
+def with_glass_maps(sc: Scene, seed=0x6A55, width=12, height=16) -> Scene:
+    """The scene with a seeded transmittance map on every glass material and texture coordinates
+    (0..1 over each glass quad, whose two triangles come in _quad_grid order). Opaque triangles get
+    zero texture coordinates (unused)."""
+    import dataclasses
+    rng = np.random.default_rng(seed)
+    lam = bin_centres(sc.n_bins, sc.lambda_min_nm, sc.lambda_max_nm)
+    uv = np.zeros((sc.n_tri, 3, 2), dtype=np.float32)
+    mat_tex = np.full(sc.n_mat, -1, dtype=np.int32)
+    tex = []
+    for m in range(sc.n_mat):
+        if sc.mat_type[m] != MAT_GLASS:
+            continue
+        idx = np.nonzero(sc.mat == m)[0]
+        assert len(idx) % 2 == 0
+        uv[idx] = quad_uv(len(idx))
+        mat_tex[m] = len(tex)
+        tex.append(glass_map(rng, lam, float(sc.thickness_m[m]), width, height))
+    return dataclasses.replace(sc, uv=uv, textures=tex, mat_tex=mat_tex).check()
 
 
 def nave_camera(width: int = 64, height: int = 64) -> Camera:
