@@ -400,6 +400,37 @@ def bench_colorimetry(ctx, img, sc, reps=20):
             "note": "per pixel 4 B x bins read, 12 B XYZ and 12 B sRGB written; HIP events on the library stream"}
 
 
+def bench_glass_maps(ctx, sc, cam, cfg, wave, spp=8):
+    """The same church with a seeded spectral transmittance map on each window (glass absorbing
+    by the map at the hit's texture coordinates instead of by k): samples/s of an spp-sample frame
+    against the plain scene at the same spp, HIP-event timed on the library stream."""
+    import torch
+    import paper_1912_04000_amd as sd
+    import scenegen
+    st = scenegen.with_glass_maps(sc)
+    S = sd.Scene.from_description(st, grid=cfg["grid"])
+    ctx.upload(S)
+    S0 = sd.Scene.from_description(sc, grid=cfg["grid"])
+    ctx.upload(S0)
+    c = sd.camera(cam.eye, cam.target, cam.up, cam.vfov_deg, cam.width, cam.height)
+    img = torch.empty((sc.n_bins, cam.height, cam.width), dtype=torch.float32, device="cuda")
+    p = sd.render_params(spp=spp, max_depth=cfg["max_depth"], seed=1, wave_paths=wave)
+    out = {}
+    for name, scene in (("maps", S), ("plain", S0)):
+        ctx.render(scene, c, p, out=img)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ctx.render(scene, c, p, out=img, finish=False)
+        e1.record()
+        torch.cuda.synchronize()
+        ctx.finish()
+        out[name] = cam.width * cam.height * spp / (e0.elapsed_time(e1) * 1e-3)
+    return {"samples_per_s": out["maps"], "plain_samples_per_s_same_spp": out["plain"],
+            "relative_cost": out["plain"] / out["maps"], "spp": spp,
+            "maps": f"{len(st.textures)} maps of {st.textures[0].shape[1]}x{st.textures[0].shape[0]} texels x "
+                    f"{sc.n_bins} bins"}
+
+
 def crop_camera(cam, cw, ch):
     """The centred cw x ch window of a view as a camera of its own (same eye, axis and pixel
     footprint): tan(vfov'/2) = tan(vfov/2) ch / H."""
@@ -665,6 +696,8 @@ def main():
         "scene_build_s": build_s,
     }
     out["colorimetry"] = bench_colorimetry(ctx, img, sc)
+    if args.workload == "church":
+        out["glass_maps"] = bench_glass_maps(ctx, sc, cam, cfg, p.wave_paths)
     if args.workload == "church" and not args.no_cached:
         # the cached half of the metric on the same view: the plain frame just timed (64 spp,
         # seed 1) fixes a = RMSE_64 sqrt(64) of the plain estimator's RMSE = a / sqrt(spp)

@@ -57,6 +57,19 @@ typedef struct {
   float thickness_m;   /* glass slab thickness in metres (ignored for opaque) */
 } sdd_material;
 
+/* A spectral transmittance map of glass (section 3: the spectral transmittance measured at points
+ * of the medieval samples, read through texture coordinates): width x height texels, each the
+ * slab's internal transmittance at normal incidence tau0_j in [0, 1] for every bin, HOST array
+ * [height][width][n_bins]. At a hit with texture coordinates (s, t) the map is interpolated
+ * bilinearly between texel centres ((i + 1/2) / width, (k + 1/2) / height) and repeats with
+ * period 1 in s and t; the slab then transmits tau0^(1 / cos theta_t) per pass instead of
+ * exp(-4 pi k d / (lambda cos theta_t)) (Beer-Lambert), its faces still reflecting by the
+ * Fresnel factor of n + ik. */
+typedef struct {
+  int32_t width, height;       /* >= 1, width * height <= 2^24                                 */
+  const float* tau0;           /* [height][width][n_bins]                                       */
+} sdd_texture;
+
 /* Scene description: the paper's three actors are objects, lighting and observer (section 1);
  * this struct carries the first two, the observer is an sdd_camera per render.
  * All pointers are HOST memory, read during sdd_scene_create only. */
@@ -75,6 +88,11 @@ typedef struct {
   const float* sun_irradiance; /* [n_bins] E_j of the directional source (eq. 3), >= 0        */
   const float* env_radiance;   /* [n_bins] radiance of rays that leave the scene, or NULL (0)  */
   int32_t grid[3];             /* cell grid (the paper's sub-domains, section 5), 1 .. 64 each */
+  /* optional spectral transmittance maps of glass (n_tex = 0: none, the pointers are ignored) */
+  const float* uv;             /* [n_tri][3][2] texture coordinates of each triangle's vertices */
+  int32_t n_tex;               /* 0 .. 65535                                                    */
+  const sdd_texture* textures; /* [n_tex]                                                       */
+  const int32_t* mat_texture;  /* [n_mat] map of each material, -1 none; glass materials only   */
 } sdd_scene_desc;
 
 /* Statistics of a built scene. */

@@ -37,7 +37,12 @@ class SceneDesc(C.Structure):
                 ("n_mat", C.c_int32), ("n_tab", C.c_void_p), ("k_tab", C.c_void_p), ("rho_tab", C.c_void_p),
                 ("n_bins", C.c_int32), ("lambda_min_nm", C.c_float), ("lambda_max_nm", C.c_float),
                 ("sun_dir", C.c_float * 3), ("sun_irradiance", C.c_void_p), ("env_radiance", C.c_void_p),
-                ("grid", C.c_int32 * 3)]
+                ("grid", C.c_int32 * 3), ("uv", C.c_void_p), ("n_tex", C.c_int32), ("textures", C.c_void_p),
+                ("mat_texture", C.c_void_p)]
+
+
+class Texture(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("tau0", C.c_void_p)]
 
 
 class Daylight(C.Structure):
@@ -222,7 +227,7 @@ def _ptr(a):
 
 
 def make_desc(verts, mat, mat_type, thickness_m, n_tab, k_tab, rho_tab, lambda_min_nm, lambda_max_nm, sun_dir, sun_E,
-              env=None, grid=(2, 2, 2)):
+              env=None, grid=(2, 2, 2), uv=None, textures=None, mat_tex=None):
     """sdd_scene_desc over host arrays; returns the struct and the arrays it points into."""
     keep = dict(
         verts=np.ascontiguousarray(verts, dtype=np.float32), mat=np.ascontiguousarray(mat, dtype=np.uint16),
@@ -248,21 +253,35 @@ def make_desc(verts, mat, mat_type, thickness_m, n_tab, k_tab, rho_tab, lambda_m
     d.sun_irradiance = _ptr(keep["E"])
     d.env_radiance = _ptr(keep["env"]) if keep["env"] is not None else None
     d.grid[:] = [int(g) for g in grid]
+    if textures:
+        keep["uv"] = np.ascontiguousarray(uv, dtype=np.float32)
+        keep["tex_data"] = [np.ascontiguousarray(t, dtype=np.float32) for t in textures]
+        tx = (Texture * len(textures))()
+        for i, t in enumerate(keep["tex_data"]):
+            tx[i].height, tx[i].width = int(t.shape[0]), int(t.shape[1])
+            tx[i].tau0 = _ptr(t)
+        keep["tex"] = tx
+        keep["mat_tex"] = np.ascontiguousarray(mat_tex, dtype=np.int32)
+        d.uv = _ptr(keep["uv"])
+        d.n_tex = len(textures)
+        d.textures = C.cast(tx, C.c_void_p)
+        d.mat_texture = _ptr(keep["mat_tex"])
     return d, keep
 
 
 def desc_from(sc, grid=(2, 2, 2)):
     return make_desc(sc.verts, sc.mat, sc.mat_type, sc.thickness_m, sc.n_tab, sc.k_tab, sc.rho_tab, sc.lambda_min_nm,
-                     sc.lambda_max_nm, sc.sun_dir, sc.sun_E, sc.env, grid)
+                     sc.lambda_max_nm, sc.sun_dir, sc.sun_E, sc.env, grid, getattr(sc, "uv", None),
+                     getattr(sc, "textures", None), getattr(sc, "mat_tex", None))
 
 
 class Scene:
     """Host-built cell-decomposed scene (``sdd_scene``), optionally uploaded to a device buffer."""
 
     def __init__(self, verts, mat, mat_type, thickness_m, n_tab, k_tab, rho_tab, lambda_min_nm, lambda_max_nm,
-                 sun_dir, sun_E, env=None, grid=(2, 2, 2)):
+                 sun_dir, sun_E, env=None, grid=(2, 2, 2), uv=None, textures=None, mat_tex=None):
         d, self._keep = make_desc(verts, mat, mat_type, thickness_m, n_tab, k_tab, rho_tab, lambda_min_nm,
-                                  lambda_max_nm, sun_dir, sun_E, env, grid)
+                                  lambda_max_nm, sun_dir, sun_E, env, grid, uv, textures, mat_tex)
         self.n_bins = d.n_bins
         h = C.c_void_p()
         _check(lib().sdd_scene_create(C.byref(d), C.byref(h)))
@@ -275,7 +294,8 @@ class Scene:
     def from_description(cls, sc, grid=(2, 2, 2)):
         """Build from any object carrying the scene arrays by name (verts, mat, mat_type, ...)."""
         return cls(sc.verts, sc.mat, sc.mat_type, sc.thickness_m, sc.n_tab, sc.k_tab, sc.rho_tab, sc.lambda_min_nm,
-                   sc.lambda_max_nm, sc.sun_dir, sc.sun_E, sc.env, grid)
+                   sc.lambda_max_nm, sc.sun_dir, sc.sun_E, sc.env, grid, getattr(sc, "uv", None),
+                   getattr(sc, "textures", None), getattr(sc, "mat_tex", None))
 
     def info(self) -> dict:
         i = SceneInfo()

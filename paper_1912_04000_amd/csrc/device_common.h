@@ -189,6 +189,7 @@ __device__ __forceinline__ void refine_hit(F3 o, F3 d, F3 v0, F3 v1, F3 v2, floa
 struct Vertex {
   F3 p, n, ng, d;
   float dn, cos_o, eps;
+  float bu, bv;  // barycentrics of v1 and v2
   uint32_t id;
   int m;
 };
@@ -211,6 +212,8 @@ __device__ __forceinline__ Vertex load_vertex(const DevScene& S, const DevWS& w,
   F3 q = ((v1 - v0) + (v2 - v0)) * (1.0f / 3.0f);
   refine_hit(f3(rorg.x, rorg.y, rorg.z), V.d, v0, v1, v2, t, q, bu, bv);
   V.p = v0 + q;
+  V.bu = bu;
+  V.bv = bv;
   V.eps = 1e-5f * (1.0f + maxabs3(V.p));
   return V;
 }

@@ -64,8 +64,15 @@ struct SceneHeader {
   int32_t max_leaf;
   int32_t bins_pad;    // row stride of the spectral tables: n_bins rounded up to a multiple of 4
   int32_t pad[4];
+  // spectral transmittance maps of glass: texture coordinates per triangle (two float4: u0 v0 u1
+  // v1 | u2 v2 0 0), map table (texel offset in floats, width, height, 0), texels [h][w][Bp]
+  // (internal transmittance at normal incidence), map of each material (-1 none)
+  uint64_t off_uv, off_texinfo, off_texel, off_mtex;
+  int32_t n_tex;
+  int32_t pad2[3];
 };
-static_assert(sizeof(SceneHeader) <= 256, "header fits in 256 bytes");
+constexpr size_t kHeaderBytes = 512;   // the header's room at the start of the scene image
+static_assert(sizeof(SceneHeader) <= kHeaderBytes, "header fits its room");
 
 // Node of a cell BVH: four children, their boxes stored in the parent (128 bytes, one cache
 // line), one float4 per box coordinate over the four children:
@@ -90,6 +97,11 @@ struct DevScene {
   const float* lambda;
   const float* sunE;
   const float* env;
+  const float4* guv;    // [n_tri][2] texture coordinates (only when n_tex > 0)
+  const int4* texinfo;  // [n_tex] (texel offset in floats, width, height, 0)
+  const float* texel;   // maps [h][w][Bp]
+  const int32_t* mtex;  // [n_mat] map of the material, -1 none
+  int32_t n_tex;
   int32_t gx, gy, gz, n_cells;
   float lo[3], hi[3];
   float inv_cs[3];

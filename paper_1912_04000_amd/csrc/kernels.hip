@@ -255,6 +255,64 @@ __device__ __forceinline__ void slab(float n, float k, float lambda_nm, float d_
   T = q * tau * inv_den;
 }
 
+// The slab when its internal transmittance at normal incidence tau0 comes from a measured map
+// (section 3): tau = tau0^(1 / cos(theta_t)) per pass, faces reflecting by F of n + ik.
+__device__ __forceinline__ void slab_tau0(float n, float k, float tau0, float c, float& R, float& T) {
+  c = fminf(1.0f, fmaxf(0.0f, c));
+  const float st = fsqrt(fmaxf(0.0f, 1.0f - c * c));
+  const float si = st * frcp(n);
+  const float ci = fsqrt(fmaxf(0.0f, 1.0f - si * si));
+  const float tau = tau0 > 0.0f ? __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(tau0) * frcp(ci)) : 0.0f;
+  const float R1 = fresnel(n, k, c);
+  const float inv_den = frcp(1.0f - R1 * R1 * tau * tau);
+  const float q = (1.0f - R1) * (1.0f - R1);
+  R = R1 + q * tau * tau * R1 * inv_den;
+  T = q * tau * inv_den;
+}
+
+// Texture coordinates of a point with barycentrics (bu, bv) on triangle tri.
+__device__ __forceinline__ void hit_st(const DevScene& S, uint32_t tri, float bu, float bv, float& s, float& t) {
+  const float4 a = S.guv[2 * (size_t)tri], b = S.guv[2 * (size_t)tri + 1];
+  const float w0 = 1.0f - bu - bv;
+  s = w0 * a.x + bu * a.z + bv * b.x;
+  t = w0 * a.y + bu * a.w + bv * b.y;
+}
+
+// Map lookup geometry: the four texels around (s, t) (bilinear between texel centres, periodic
+// repeat) as float4-row indices of quad 0, and the two weights.
+struct TexTap {
+  const float4* base;
+  uint32_t r00, r10, r01, r11;  // texel index * quads per texel
+  float fx, fy;
+};
+__device__ __forceinline__ TexTap tex_tap(const DevScene& S, int tex, float s, float t) {
+  const int4 ti = S.texinfo[tex];  // (texel offset in floats, width, height, 0)
+  // one period: s - floor(s) is exact, so the map repeats without any integer overflow
+  const float x = (s - floorf(s)) * (float)ti.y - 0.5f, y = (t - floorf(t)) * (float)ti.z - 0.5f;
+  const float x0 = floorf(x), y0 = floorf(y);   // in [-1, size - 1]
+  const int i0 = x0 < 0.0f ? ti.y - 1 : min((int)x0, ti.y - 1);
+  const int k0 = y0 < 0.0f ? ti.z - 1 : min((int)y0, ti.z - 1);
+  const int i1 = i0 + 1 == ti.y ? 0 : i0 + 1, k1 = k0 + 1 == ti.z ? 0 : k0 + 1;
+  const uint32_t nq = (uint32_t)S.bins_pad / 4;
+  TexTap T;
+  T.base = (const float4*)(S.texel + ti.x);
+  T.r00 = ((uint32_t)k0 * ti.y + i0) * nq;
+  T.r10 = ((uint32_t)k0 * ti.y + i1) * nq;
+  T.r01 = ((uint32_t)k1 * ti.y + i0) * nq;
+  T.r11 = ((uint32_t)k1 * ti.y + i1) * nq;
+  T.fx = x - x0;
+  T.fy = y - y0;
+  return T;
+}
+// tau0 of the four bins of quad q at the tap
+__device__ __forceinline__ float4 tex_quad(const TexTap& T, int q) {
+  const float4 a = T.base[T.r00 + q], b = T.base[T.r10 + q], c = T.base[T.r01 + q], d = T.base[T.r11 + q];
+  const float w00 = (1.0f - T.fx) * (1.0f - T.fy), w10 = T.fx * (1.0f - T.fy), w01 = (1.0f - T.fx) * T.fy,
+              w11 = T.fx * T.fy;
+  return make_float4(w00 * a.x + w10 * b.x + w01 * c.x + w11 * d.x, w00 * a.y + w10 * b.y + w01 * c.y + w11 * d.y,
+                     w00 * a.z + w10 * b.z + w01 * c.z + w11 * d.z, w00 * a.w + w10 * b.w + w01 * c.w + w11 * d.w);
+}
+
 // ==========================================================================================
 // fills / philox test kernel
 // ==========================================================================================
@@ -431,21 +489,36 @@ __global__ void k_unpack_hits(DevScene S, DevWS w, uint32_t n, float* t, int32_t
 }
 
 // Glass crossings of the shadow ray of slot s (at most kMaxCross recorded, material and
-// triangle id each): the material and |cos| between the ray and the slab's normal of each.
+// triangle id each): the material and |cos| between the ray and the slab's normal of each, and
+// for a material with a transmittance map (tx >= 0) the texture coordinates of the crossing,
+// from the crossing triangle re-intersected with the shadow ray.
 __device__ __forceinline__ void crossings(const DevScene& S, const DevWS& w, uint32_t s, uint32_t nc, int* mq,
-                                          float* cq) {
-  const float4 rd = w.rays[2 * ((size_t)w.W + s) + 1];
+                                          float* cq, int* tx, float* sq, float* tq) {
+  const float4 ro = w.rays[2 * ((size_t)w.W + s)], rd = w.rays[2 * ((size_t)w.W + s) + 1];
   const F3 d = f3(rd.x, rd.y, rd.z);
 #pragma unroll
   for (int q = 0; q < kMaxCross; ++q) {
     mq[q] = 0;
     cq[q] = 1.0f;
+    tx[q] = -1;
+    sq[q] = tq[q] = 0.0f;
     if ((uint32_t)q < nc) {
       const float2 x = w.shx[(size_t)q * w.W + s];
-      const float4* g = S.gtris + (size_t)__float_as_uint(x.y) * 3;
+      const uint32_t tri = __float_as_uint(x.y);
+      const float4* g = S.gtris + (size_t)tri * 3;
       const float4 A = g[0], B = g[1], C = g[2];
+      const F3 v0 = f3(A.x, A.y, A.z), v1 = f3(B.x, B.y, B.z), v2 = f3(C.x, C.y, C.z);
       mq[q] = __float_as_int(x.x);
-      cq[q] = fabsf(dot3(d, geo_normal(f3(A.x, A.y, A.z), f3(B.x, B.y, B.z), f3(C.x, C.y, C.z))));
+      cq[q] = fabsf(dot3(d, geo_normal(v0, v1, v2)));
+      if (S.n_tex > 0) {
+        tx[q] = S.mtex[mq[q]];
+        if (tx[q] >= 0) {
+          float t = 0.0f, bu = 1.0f / 3.0f, bv = 1.0f / 3.0f;
+          F3 qq;
+          refine_hit(f3(ro.x, ro.y, ro.z), d, v0, v1, v2, t, qq, bu, bv);
+          hit_st(S, tri, bu, bv, sq[q], tq[q]);
+        }
+      }
     }
   }
 }
@@ -454,9 +527,9 @@ __global__ void k_resolve_vis(DevScene S, DevWS w, uint32_t n, float* vis) {
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const uint32_t c = w.shcnt[i];
     const uint32_t nc = c == kBlocked ? 0u : min(c, (uint32_t)kMaxCross);
-    int mq[kMaxCross];
-    float cq[kMaxCross];
-    crossings(S, w, i, nc, mq, cq);
+    int mq[kMaxCross], tx[kMaxCross];
+    float cq[kMaxCross], sq[kMaxCross], tq[kMaxCross];
+    crossings(S, w, i, nc, mq, cq, tx, sq, tq);
     for (int j = 0; j < S.n_bins; ++j) {
       float V = 0.0f;
       if (c != kBlocked) {
@@ -466,7 +539,13 @@ __global__ void k_resolve_vis(DevScene S, DevWS w, uint32_t n, float* vis) {
           if ((uint32_t)q < nc) {
             const int m = mq[q];
             float R, T;
-            slab(S.ntab[m * S.bins_pad + j], S.ktab[m * S.bins_pad + j], S.lambda[j], S.thick[m], cq[q], R, T);
+            if (tx[q] >= 0) {
+              const float4 t4 = tex_quad(tex_tap(S, tx[q], sq[q], tq[q]), j >> 2);
+              const float tau0 = (j & 3) == 0 ? t4.x : ((j & 3) == 1 ? t4.y : ((j & 3) == 2 ? t4.z : t4.w));
+              slab_tau0(S.ntab[m * S.bins_pad + j], S.ktab[m * S.bins_pad + j], tau0, cq[q], R, T);
+            } else {
+              slab(S.ntab[m * S.bins_pad + j], S.ktab[m * S.bins_pad + j], S.lambda[j], S.thick[m], cq[q], R, T);
+            }
             V *= T;
           }
         }
@@ -1234,9 +1313,9 @@ __global__ __launch_bounds__(kWG) void k_resolve(DevScene S, DevWS w, int depth)
       const uint32_t s = cat_list(w, p, kCatShadowGlass)[i - n_clear];
       const uint32_t nc = min(w.shcnt[s], (uint32_t)kMaxCross);
       const float4* e = (const float4*)(w.nee + (size_t)s * Bp);
-      int mq[kMaxCross];
-      float cq[kMaxCross];
-      crossings(S, w, s, nc, mq, cq);
+      int mq[kMaxCross], tx[kMaxCross];
+      float cq[kMaxCross], sq[kMaxCross], tq[kMaxCross];
+      crossings(S, w, s, nc, mq, cq, tx, sq, tq);
       const float4* lam = (const float4*)S.lambda;
       row_update<12>((float4*)(w.lacc + (size_t)s * Bp), nq, [&](int q, float4 l) {
         float4 V = make_float4(1.0f, 1.0f, 1.0f, 1.0f);
@@ -1247,10 +1326,18 @@ __global__ __launch_bounds__(kWG) void k_resolve(DevScene S, DevWS w, int depth)
             const int m = mq[c];
             const float4 nn = ((const float4*)(S.ntab + m * Bp))[q], kk = ((const float4*)(S.ktab + m * Bp))[q];
             float R0, T0, R1, T1, R2, T2, R3, T3;
-            slab(nn.x, kk.x, la.x, S.thick[m], cq[c], R0, T0);
-            slab(nn.y, kk.y, la.y, S.thick[m], cq[c], R1, T1);
-            slab(nn.z, kk.z, la.z, S.thick[m], cq[c], R2, T2);
-            slab(nn.w, kk.w, la.w, S.thick[m], cq[c], R3, T3);
+            if (tx[c] >= 0) {
+              const float4 t4 = tex_quad(tex_tap(S, tx[c], sq[c], tq[c]), q);
+              slab_tau0(nn.x, kk.x, t4.x, cq[c], R0, T0);
+              slab_tau0(nn.y, kk.y, t4.y, cq[c], R1, T1);
+              slab_tau0(nn.z, kk.z, t4.z, cq[c], R2, T2);
+              slab_tau0(nn.w, kk.w, t4.w, cq[c], R3, T3);
+            } else {
+              slab(nn.x, kk.x, la.x, S.thick[m], cq[c], R0, T0);
+              slab(nn.y, kk.y, la.y, S.thick[m], cq[c], R1, T1);
+              slab(nn.z, kk.z, la.z, S.thick[m], cq[c], R2, T2);
+              slab(nn.w, kk.w, la.w, S.thick[m], cq[c], R3, T3);
+            }
             V.x *= T0;
             V.y *= T1;
             V.z *= T2;
@@ -1564,13 +1651,32 @@ __global__ __launch_bounds__(kWG) void k_shade_glass(DevScene S, DevWS w, int de
       const float4* kt = (const float4*)(S.ktab + V.m * Bp);
       const float4* lam = (const float4*)S.lambda;
       const float th = S.thick[V.m];
+      // the glass's transmittance map at the hit's texture coordinates, if it has one
+      const int tx = S.n_tex > 0 ? S.mtex[V.m] : -1;
+      TexTap tap;
+      tap.base = nullptr;
+      tap.r00 = tap.r10 = tap.r01 = tap.r11 = 0;
+      tap.fx = tap.fy = 0.0f;
+      if (tx >= 0) {
+        float ss, tt;
+        hit_st(S, V.id, V.bu, V.bv, ss, tt);
+        tap = tex_tap(S, tx, ss, tt);
+      }
       // slab R and T of the four bins of quad q (padding bins hold benign table values)
       auto slab4 = [&](int q, float (&R)[4], float (&T)[4]) {
         const float4 nn = nt[q], kk = kt[q], la = lam[q];
-        slab(nn.x, kk.x, la.x, th, V.cos_o, R[0], T[0]);
-        slab(nn.y, kk.y, la.y, th, V.cos_o, R[1], T[1]);
-        slab(nn.z, kk.z, la.z, th, V.cos_o, R[2], T[2]);
-        slab(nn.w, kk.w, la.w, th, V.cos_o, R[3], T[3]);
+        if (tx >= 0) {
+          const float4 t4 = tex_quad(tap, q);
+          slab_tau0(nn.x, kk.x, t4.x, V.cos_o, R[0], T[0]);
+          slab_tau0(nn.y, kk.y, t4.y, V.cos_o, R[1], T[1]);
+          slab_tau0(nn.z, kk.z, t4.z, V.cos_o, R[2], T[2]);
+          slab_tau0(nn.w, kk.w, t4.w, V.cos_o, R[3], T[3]);
+        } else {
+          slab(nn.x, kk.x, la.x, th, V.cos_o, R[0], T[0]);
+          slab(nn.y, kk.y, la.y, th, V.cos_o, R[1], T[1]);
+          slab(nn.z, kk.z, la.z, th, V.cos_o, R[2], T[2]);
+          slab(nn.w, kk.w, la.w, th, V.cos_o, R[3], T[3]);
+        }
       };
       float mr = 0.0f, mt = 0.0f;
 #pragma unroll 4

@@ -293,6 +293,30 @@ std::string build_scene(const sdd_scene_desc& d, sdd_scene* out) {
   double sl = std::sqrt((double)d.sun_dir[0] * d.sun_dir[0] + (double)d.sun_dir[1] * d.sun_dir[1] +
                         (double)d.sun_dir[2] * d.sun_dir[2]);
   if (!(sl > 1e-12) || !std::isfinite(sl)) return "sun direction must be non-zero and finite";
+  // spectral transmittance maps of glass
+  const int NT = d.n_tex;
+  uint64_t texel_floats = 0;
+  if (NT < 0 || NT > 65535) return "n_tex out of range (0..65535)";
+  if (NT > 0) {
+    if (!d.uv || !d.textures || !d.mat_texture) return "maps need uv, textures and mat_texture";
+    for (int t = 0; t < NT; ++t) {
+      const sdd_texture& T = d.textures[t];
+      if (!T.tau0 || T.width < 1 || T.height < 1 || (int64_t)T.width * T.height > (1 << 24))
+        return "map " + std::to_string(t) + ": bad size or null data";
+      const int64_t nv = (int64_t)T.width * T.height * B;
+      for (int64_t i = 0; i < nv; ++i)
+        if (!(T.tau0[i] >= 0.0f && T.tau0[i] <= 1.0f)) return "map " + std::to_string(t) + ": values must lie in [0,1]";
+      texel_floats += (uint64_t)T.width * T.height * ((B + 3) & ~3);
+    }
+    if (texel_floats > (uint64_t)INT32_MAX) return "maps too large (more than 2^31 texel values)";
+    for (int m = 0; m < M; ++m) {
+      const int t = d.mat_texture[m];
+      if (t < -1 || t >= NT) return "mat_texture out of range";
+      if (t >= 0 && d.materials[m].type != SDD_MAT_GLASS) return "only glass materials take a transmittance map";
+    }
+    for (int64_t i = 0; i < 6 * N; ++i)
+      if (!(std::fabs(d.uv[i]) <= 1e6f)) return "texture coordinates must be finite, |uv| <= 1e6";
+  }
   double maxabs = 0;
   float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   for (int64_t i = 0; i < N; ++i) {
@@ -466,7 +490,7 @@ std::string build_scene(const sdd_scene_desc& d, sdd_scene* out) {
   if (d.env_radiance)
     for (int j = 0; j < B; ++j) env_nz |= d.env_radiance[j] != 0.0f;
   H.env_nonzero = env_nz;
-  size_t off = 256;
+  size_t off = kHeaderBytes;
   H.off_planes = off; off = align256(off + planes.size() * 4);
   H.off_cells = off;  off = align256(off + (size_t)n_cells * 16);
   H.off_nodes = off;  off = align256(off + n_nodes * 128);
@@ -483,6 +507,11 @@ std::string build_scene(const sdd_scene_desc& d, sdd_scene* out) {
   H.off_lambda = off; off = align256(off + (size_t)Bp * 4);
   H.off_sunE = off;   off = align256(off + (size_t)Bp * 4);
   H.off_env = off;    off = align256(off + (size_t)Bp * 4);
+  H.n_tex = NT;
+  H.off_uv = off;      off = align256(off + (NT > 0 ? (size_t)N * 32 : 0));
+  H.off_texinfo = off; off = align256(off + (size_t)NT * 16);
+  H.off_texel = off;   off = align256(off + texel_floats * 4);
+  H.off_mtex = off;    off = align256(off + (size_t)M * 4);
   H.bins_pad = Bp;
   H.n_nodes = n_nodes;
   H.n_refs = n_refs;
@@ -562,6 +591,28 @@ std::string build_scene(const sdd_scene_desc& d, sdd_scene* out) {
     sL[j] = (j < B && d.env_radiance) ? d.env_radiance[j] : 0.0f;
   }
 
+  int32_t* mtex = (int32_t*)(img + H.off_mtex);
+  for (int m = 0; m < M; ++m) mtex[m] = NT > 0 ? d.mat_texture[m] : -1;
+  if (NT > 0) {
+    float* uv = (float*)(img + H.off_uv);
+    for (int64_t t = 0; t < N; ++t) {
+      const float* q = d.uv + 6 * t;
+      float* o = uv + 8 * t;
+      for (int k = 0; k < 6; ++k) o[k] = q[k];
+      o[6] = o[7] = 0.0f;
+    }
+    int4* ti = (int4*)(img + H.off_texinfo);
+    float* tx = (float*)(img + H.off_texel);
+    uint64_t at = 0;
+    for (int t = 0; t < NT; ++t) {
+      const sdd_texture& T = d.textures[t];
+      ti[t] = make_int4((int)at, T.width, T.height, 0);
+      for (int64_t p = 0; p < (int64_t)T.width * T.height; ++p)
+        for (int j = 0; j < Bp; ++j) tx[at + p * Bp + j] = j < B ? T.tau0[p * B + j] : 1.0f;
+      at += (uint64_t)T.width * T.height * Bp;
+    }
+  }
+
   out->hdr = H;
   sdd_scene_info& I = out->info;
   std::memset(&I, 0, sizeof(I));
@@ -598,6 +649,11 @@ DevScene device_view(const sdd_scene* s) {
   S.lambda = (const float*)(b + H.off_lambda);
   S.sunE = (const float*)(b + H.off_sunE);
   S.env = (const float*)(b + H.off_env);
+  S.guv = (const float4*)(b + H.off_uv);
+  S.texinfo = (const int4*)(b + H.off_texinfo);
+  S.texel = (const float*)(b + H.off_texel);
+  S.mtex = (const int32_t*)(b + H.off_mtex);
+  S.n_tex = H.n_tex;
   S.gx = H.grid[0];
   S.gy = H.grid[1];
   S.gz = H.grid[2];

@@ -226,7 +226,8 @@ def glass_map(rng, lam_nm, d_m, width=12, height=16, n_spots=6):
     transmittance measured at points of the samples, accessed by texture coordinates): internal
     transmittance at normal incidence tau0 = exp(-4 pi k d / lambda) with k varying smoothly over
     the pane (a few Gaussian absorption bumps whose strength drifts across it) and darker round
-    spots (micro-bubbles and inclusions). Returns float32 [height][width][B] in (0, 1]."""
+    spots (clusters of micro-bubbles and inclusions) a few texels wide. Returns float32
+    [height][width][B] in (0, 1]."""
     B = len(lam_nm)
     s = (np.arange(width) + 0.5) / width
     t = (np.arange(height) + 0.5) / height
@@ -235,11 +236,13 @@ def glass_map(rng, lam_nm, d_m, width=12, height=16, n_spots=6):
     for _ in range(rng.integers(1, 4)):
         a = rng.uniform(2e-6, 2e-5)
         mu, sig = rng.uniform(400, 760), rng.uniform(15, 60)
-        drift = 1.0 + 0.5 * np.sin(2 * np.pi * (rng.uniform() + S * rng.uniform(0.5, 1.5) + T * rng.uniform(0.2, 1.0)))
+        drift = 1.0 + 0.3 * np.sin(2 * np.pi * (rng.uniform() + S * rng.uniform(0.3, 1.0) + T * rng.uniform(0.2, 0.8)))
         k += a * drift[..., None] * np.exp(-0.5 * ((lam_nm[None, None, :] - mu) / sig) ** 2)
+    # spots a few texels wide: a map only resolves features larger than its texel spacing, and
+    # its log-transmittance gradient sets how much the FP32 rounding of path vertices moves it
     for _ in range(n_spots):
-        cs, ct, r = rng.uniform(0, 1), rng.uniform(0, 1), rng.uniform(0.03, 0.12)
-        k += 1.2e-5 * np.exp(-0.5 * (((S - cs) ** 2 + (T - ct) ** 2) / r**2))[..., None]
+        cs, ct, r = rng.uniform(0, 1), rng.uniform(0, 1), rng.uniform(0.15, 0.3)
+        k += 6e-6 * np.exp(-0.5 * (((S - cs) ** 2 + (T - ct) ** 2) / r**2))[..., None]
     return np.exp(-4 * np.pi * k * d_m / (lam_nm * 1e-9)).astype(np.float32)
 
 

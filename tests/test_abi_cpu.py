@@ -158,3 +158,25 @@ def test_binding_classes_keep_their_methods():
         assert hasattr(b.Context, m)
     for m in ("eval", "backward", "step", "train", "params", "grads", "records"):
         assert hasattr(b.Cache, m)
+
+
+def test_glass_map_validation():
+    """Transmittance maps: values outside [0, 1], a map on an opaque material, missing texture
+    coordinates and out-of-range map indices are refused at scene build (no GPU needed)."""
+    import dataclasses
+    import paper_1912_04000_amd as sd
+    sc = scenegen.with_glass_maps(scenegen.nave_scene(8))
+    sd.Scene.from_description(sc)   # valid
+    bad = [t.copy() for t in sc.textures]
+    bad[0][0, 0, 0] = 1.5
+    cases = [dataclasses.replace(sc, textures=bad),
+             dataclasses.replace(sc, mat_tex=np.array([0, -1, 0], dtype=np.int32)),
+             dataclasses.replace(sc, mat_tex=np.array([-1, -1, 1], dtype=np.int32))]
+    for c in cases:
+        with pytest.raises(sd.SddError):
+            sd.Scene(c.verts, c.mat, c.mat_type, c.thickness_m, c.n_tab, c.k_tab, c.rho_tab, c.lambda_min_nm,
+                     c.lambda_max_nm, c.sun_dir, c.sun_E, c.env, (2, 2, 2), c.uv, c.textures, c.mat_tex)
+    with pytest.raises(sd.SddError):
+        sd.Scene(sc.verts, sc.mat, sc.mat_type, sc.thickness_m, sc.n_tab, sc.k_tab, sc.rho_tab, sc.lambda_min_nm,
+                 sc.lambda_max_nm, sc.sun_dir, sc.sun_E, sc.env, (2, 2, 2), np.full_like(sc.uv, np.nan), sc.textures,
+                 sc.mat_tex)
