@@ -60,6 +60,8 @@ def parse():
     ap.add_argument("--queue-rounds", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-cached", action="store_true", help="skip the cached-path comparison of the default run")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the colorimetry and glass-map measurements (profiling runs of the frame alone)")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="GiB: only run a plain device-to-device copy of that size (PMC calibration)")
@@ -695,9 +697,10 @@ def main():
                      "tri_tests_per_ray": st["tri_tests"] / max(1, st["ext_rays"] + st["shadow_rays"])},
         "scene_build_s": build_s,
     }
-    out["colorimetry"] = bench_colorimetry(ctx, img, sc)
-    if args.workload == "church":
-        out["glass_maps"] = bench_glass_maps(ctx, sc, cam, cfg, p.wave_paths)
+    if not args.no_extras:
+        out["colorimetry"] = bench_colorimetry(ctx, img, sc)
+        if args.workload == "church":
+            out["glass_maps"] = bench_glass_maps(ctx, sc, cam, cfg, p.wave_paths)
     if args.workload == "church" and not args.no_cached:
         # the cached half of the metric on the same view: the plain frame just timed (64 spp,
         # seed 1) fixes a = RMSE_64 sqrt(64) of the plain estimator's RMSE = a / sqrt(spp)

@@ -74,9 +74,11 @@ struct SceneHeader {
 constexpr size_t kHeaderBytes = 512;   // the header's room at the start of the scene image
 static_assert(sizeof(SceneHeader) <= kHeaderBytes, "header fits its room");
 
-// Node of a cell BVH: four children, their boxes stored in the parent (128 bytes, one cache
-// line), one float4 per box coordinate over the four children:
-//   lo.x[4] | hi.x[4] | lo.y[4] | hi.y[4] | lo.z[4] | hi.z[4] | word[4] | 0
+// Node of a cell BVH: four children, their boxes stored in the parent as 8-bit bounds on a grid of
+// the node's own box (64 bytes, two nodes per 128-byte cache line), four 16-byte words:
+//   origin.xyz (FP32) | e_x e_y e_z (bytes) ; child word[4] ; lo.x[4] hi.x[4] lo.y[4] hi.y[4]
+//   (bytes) ; lo.z[4] hi.z[4] (bytes) 0 0
+// bound = origin + q 2^(e - 127); lo rounded down, hi up, so a stored box contains its child.
 // word: an inner child's node index (cell-relative, < 2^27), a leaf as count << 27 | first
 // cell triangle (count 1..15), or kEmptyChild for no child.
 // Cell triangle (48 bytes): (v0, global id) (v1, material id) (v2, 0).

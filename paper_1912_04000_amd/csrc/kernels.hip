@@ -779,23 +779,32 @@ __device__ __forceinline__ bool wt_test(const RayPre& R, F3 v0, F3 v1, F3 v2, fl
 }
 
 // The four child boxes of a 4-wide node against [tmin, tmax] (robust slab test, Ize 2013: the far
-// distance is scaled by 1 + 2 gamma_5 so that rounding never culls a box the ray touches; a slab
-// distance carries the subtraction, the product and the 1-ulp reciprocal, four roundings, and
-// gamma_5 keeps one in reserve): the entry distance of each hit child and its word, +inf and
-// kEmptyChild for a missed or empty one.
-__device__ __forceinline__ void box4(const RayPre& R, float4 lx, float4 hx, float4 ly, float4 hy, float4 lz, float4 hz,
-                                     float4 words, float tmin, float tmax, float (&t)[kWide], uint32_t (&w)[kWide]) {
+// distance is scaled by 1 + 2 gamma_5 so that rounding never culls a box the ray touches): the
+// entry distance of each hit child and its word, +inf and kEmptyChild for a missed or empty one.
+// The node holds its children's bounds as bytes q on a grid origin + q 2^(e - 127) per axis
+// (64-byte node, see the scene builder), so a slab distance is a + q b with a = (origin - o) / d
+// and b = 2^(e - 127) / d, one FMA per bound (b is exact: a power of two times 1/d). A distance
+// carries the subtraction, the product, the 1-ulp reciprocal and the FMA, four roundings, and
+// gamma_5 keeps one in reserve.
+__device__ __forceinline__ void box4(const RayPre& R, float4 q0, float4 q1, float4 q2, float4 q3, float tmin,
+                                     float tmax, float (&t)[kWide], uint32_t (&w)[kWide]) {
   constexpr float kSlop = 1.0f + 2.0f * 5.0f * 5.9604645e-8f / (1.0f - 5.0f * 5.9604645e-8f);
-  const float LX[4] = {lx.x, lx.y, lx.z, lx.w}, HX[4] = {hx.x, hx.y, hx.z, hx.w};
-  const float LY[4] = {ly.x, ly.y, ly.z, ly.w}, HY[4] = {hy.x, hy.y, hy.z, hy.w};
-  const float LZ[4] = {lz.x, lz.y, lz.z, lz.w}, HZ[4] = {hz.x, hz.y, hz.z, hz.w};
-  const uint32_t W[4] = {__float_as_uint(words.x), __float_as_uint(words.y), __float_as_uint(words.z),
-                         __float_as_uint(words.w)};
+  const uint32_t e = __float_as_uint(q0.w);
+  const float bx = __uint_as_float((e & 0xFFu) << 23) * R.inv.x;
+  const float by = __uint_as_float(((e >> 8) & 0xFFu) << 23) * R.inv.y;
+  const float bz = __uint_as_float(((e >> 16) & 0xFFu) << 23) * R.inv.z;
+  const float ax = (q0.x - R.o.x) * R.inv.x, ay = (q0.y - R.o.y) * R.inv.y, az = (q0.z - R.o.z) * R.inv.z;
+  const uint32_t LX = __float_as_uint(q2.x), HX = __float_as_uint(q2.y), LY = __float_as_uint(q2.z),
+                 HY = __float_as_uint(q2.w), LZ = __float_as_uint(q3.x), HZ = __float_as_uint(q3.y);
+  const uint32_t W[4] = {__float_as_uint(q1.x), __float_as_uint(q1.y), __float_as_uint(q1.z), __float_as_uint(q1.w)};
 #pragma unroll
   for (int c = 0; c < kWide; ++c) {
-    const float x0 = (LX[c] - R.o.x) * R.inv.x, x1 = (HX[c] - R.o.x) * R.inv.x;
-    const float y0 = (LY[c] - R.o.y) * R.inv.y, y1 = (HY[c] - R.o.y) * R.inv.y;
-    const float z0 = (LZ[c] - R.o.z) * R.inv.z, z1 = (HZ[c] - R.o.z) * R.inv.z;
+    const float x0 = __builtin_fmaf((float)((LX >> (8 * c)) & 0xFFu), bx, ax);
+    const float x1 = __builtin_fmaf((float)((HX >> (8 * c)) & 0xFFu), bx, ax);
+    const float y0 = __builtin_fmaf((float)((LY >> (8 * c)) & 0xFFu), by, ay);
+    const float y1 = __builtin_fmaf((float)((HY >> (8 * c)) & 0xFFu), by, ay);
+    const float z0 = __builtin_fmaf((float)((LZ >> (8 * c)) & 0xFFu), bz, az);
+    const float z1 = __builtin_fmaf((float)((HZ >> (8 * c)) & 0xFFu), bz, az);
     const float n = fmaxf(fmaxf(fminf(x0, x1), fminf(y0, y1)), fmaxf(fminf(z0, z1), tmin));
     const float f = fminf(fminf(fmaxf(x0, x1), fmaxf(y0, y1)), fmaxf(z0, z1)) * kSlop;
     const bool hit = n <= fminf(f, tmax) && W[c] != kEmptyChild;
@@ -864,23 +873,18 @@ __device__ __forceinline__ bool trav_step(const DevScene& S, const DevWS& w, con
       node = e;
     }
   }
-  // One load serves both kinds of step: a triangle (three float4) or a 4-wide node (seven), so
-  // a wave whose lanes do different kinds of work waits for one memory round trip per step.
+  // One load serves both kinds of step: a triangle (three float4) or a 4-wide node (four), so a
+  // wave whose lanes do different kinds of work waits for one memory round trip per step.
   const bool is_tri = (pend >> 27) != 0;
   const uint32_t tri = pend & kStackLeafMaxIndex;
   if (is_tri) pend = pend + 1u - (1u << 27);  // next triangle, one fewer left (indices stay below 2^27)
-  const float4* src = is_tri ? S.ctris + ((size_t)cinfo.z + tri) * 3 : S.nodes + ((size_t)cinfo.x + node) * 8;
+  const float4* src = is_tri ? S.ctris + ((size_t)cinfo.z + tri) * 3 : S.nodes + ((size_t)cinfo.x + node) * 4;
   const float4 q0 = src[0], q1 = src[1], q2 = src[2];
-  float4 q3 = q0, q4 = q0, q5 = q0, q6 = q0;
-  if (!is_tri) {
-    q3 = src[3];
-    q4 = src[4];
-    q5 = src[5];
-    q6 = src[6];
-  }
+  float4 q3 = q0;
+  if (!is_tri) q3 = src[3];
   // an empty statement that reads every load: they are issued together here instead of the
-  // node-only ones being moved into the node branch (a second round trip)
-  asm volatile("" ::"v"(q0.x), "v"(q1.x), "v"(q2.x), "v"(q3.x), "v"(q4.x), "v"(q5.x), "v"(q6.x));
+  // node-only one being moved into the node branch (a second round trip)
+  asm volatile("" ::"v"(q0.x), "v"(q1.x), "v"(q2.x), "v"(q3.x));
   if (is_tri) {
     const uint32_t id = __float_as_uint(q0.w);
     if (id == skip) return true;
@@ -909,7 +913,7 @@ __device__ __forceinline__ bool trav_step(const DevScene& S, const DevWS& w, con
   work = kStepNode;
   float kt[kWide];
   uint32_t kw[kWide];
-  box4(R, q0, q1, q2, q3, q4, q5, q6, fmaxf(t_lo, 0.0f), shadow ? t_hi : st.tbest, kt, kw);
+  box4(R, q0, q1, q2, q3, fmaxf(t_lo, 0.0f), shadow ? t_hi : st.tbest, kt, kw);
   sort4(kt, kw);
   node = kNoNode;
   if (kw[0] != kEmptyChild) {

@@ -259,6 +259,67 @@ void build_cell(std::vector<Ref>& refs, CellBVH& out) {
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// A 4-wide node in 64 bytes (four 16-byte words): the child boxes quantised to 8 bits per bound
+// on a grid of the node's own box (after Ylitie, Karras and Laine, "Efficient incoherent ray
+// traversal on GPUs through compressed wide BVHs", HPG 2017):
+//   word 0: origin x, y, z (the node box's low corner, FP32) | exponents e_x, e_y, e_z (bytes 0..2)
+//   word 1: the four child words (inner node index, count << 27 | first triangle, or empty)
+//   word 2: lo.x, hi.x, lo.y, hi.y of the four children, one byte per child (child c in byte c)
+//   word 3: lo.z, hi.z of the four children | 0 | 0
+// A child's bound is origin + q 2^(e - 127); e is the smallest power of two with 255 steps
+// covering the node box, lo rounded down and hi rounded up, so the stored box always contains
+// the child's box. Empty children have zero bytes and the empty word. Returns false if the
+// containment check (exact, in double) fails.
+bool quantize_node(const WNode& n, uint32_t* o) {
+  double L[3], Hh[3];
+  for (int a = 0; a < 3; ++a) {
+    L[a] = INFINITY;
+    Hh[a] = -INFINITY;
+  }
+  for (int k = 0; k < kWide; ++k) {
+    if (n.c[k].idx == kEmptyChild) continue;
+    for (int a = 0; a < 3; ++a) {
+      L[a] = std::min(L[a], (double)n.c[k].box.lo[a]);
+      Hh[a] = std::max(Hh[a], (double)n.c[k].box.hi[a]);
+    }
+  }
+  uint32_t ebytes = 0;
+  double scale[3];
+  float origin[3];
+  for (int a = 0; a < 3; ++a) {
+    if (!(L[a] <= Hh[a])) L[a] = Hh[a] = 0.0;   // a node without children (not produced)
+    origin[a] = (float)L[a];                   // the children's bounds are floats: exact
+    const double ext = Hh[a] - L[a];
+    int e = -126;
+    while (e < 127 && std::ldexp(255.0, e) < ext) ++e;
+    scale[a] = std::ldexp(1.0, e);
+    ebytes |= (uint32_t)(e + 127) << (8 * a);
+  }
+  uint32_t q[6] = {0, 0, 0, 0, 0, 0};   // lo.x hi.x lo.y hi.y lo.z hi.z
+  uint32_t words[kWide];
+  for (int k = 0; k < kWide; ++k) {
+    const Child& c = n.c[k];
+    words[k] = c.idx == kEmptyChild ? kEmptyChild : (c.cnt > 0 ? (c.cnt << 27) | c.idx : c.idx);
+    if (c.idx == kEmptyChild) continue;
+    for (int a = 0; a < 3; ++a) {
+      const double ql = std::floor((c.box.lo[a] - L[a]) / scale[a]);
+      const double qh = std::ceil((c.box.hi[a] - L[a]) / scale[a]);
+      const uint32_t bl = (uint32_t)std::min(255.0, std::max(0.0, ql));
+      const uint32_t bh = (uint32_t)std::min(255.0, std::max(0.0, qh));
+      if (!(L[a] + bl * scale[a] <= (double)c.box.lo[a]) || !(L[a] + bh * scale[a] >= (double)c.box.hi[a]))
+        return false;
+      q[2 * a] |= bl << (8 * k);
+      q[2 * a + 1] |= bh << (8 * k);
+    }
+  }
+  std::memcpy(o, origin, 12);
+  o[3] = ebytes;
+  std::memcpy(o + 4, words, 16);
+  for (int j = 0; j < 6; ++j) o[8 + j] = q[j];
+  o[14] = o[15] = 0;
+  return true;
+}
+
 }  // namespace
 
 std::string build_scene(const sdd_scene_desc& d, sdd_scene* out) {
@@ -493,7 +554,7 @@ std::string build_scene(const sdd_scene_desc& d, sdd_scene* out) {
   size_t off = kHeaderBytes;
   H.off_planes = off; off = align256(off + planes.size() * 4);
   H.off_cells = off;  off = align256(off + (size_t)n_cells * 16);
-  H.off_nodes = off;  off = align256(off + n_nodes * 128);
+  H.off_nodes = off;  off = align256(off + n_nodes * 64);
   H.off_ctris = off;  off = align256(off + n_refs * 48);
   H.off_gtris = off;  off = align256(off + (size_t)N * 48);
   H.off_mtype = off;  off = align256(off + (size_t)M * 4);
@@ -528,22 +589,8 @@ std::string build_scene(const sdd_scene_desc& d, sdd_scene* out) {
     ctab[c] = make_int4((int)nb, (int)cb.nodes.size(), (int)tb, (int)cb.tris.size());
     for (size_t i = 0; i < cb.nodes.size(); ++i) {
       const WNode& n = cb.nodes[i];
-      float* o = nodes + (nb + i) * 32;
-      uint32_t words[kWide];
-      for (int k = 0; k < kWide; ++k) {
-        const Child& c = n.c[k];
-        const bool none = c.idx == kEmptyChild;
-        // an empty slot: a zero box and the all-ones word (the traversal skips it by the word)
-        o[0 + k] = none ? 0.0f : c.box.lo[0];
-        o[4 + k] = none ? 0.0f : c.box.hi[0];
-        o[8 + k] = none ? 0.0f : c.box.lo[1];
-        o[12 + k] = none ? 0.0f : c.box.hi[1];
-        o[16 + k] = none ? 0.0f : c.box.lo[2];
-        o[20 + k] = none ? 0.0f : c.box.hi[2];
-        words[k] = none ? kEmptyChild : (c.cnt > 0 ? (c.cnt << 27) | c.idx : c.idx);
-      }
-      std::memcpy(o + 24, words, 16);
-      std::memset(o + 28, 0, 16);
+      uint32_t* o = (uint32_t*)(nodes + (nb + i) * 16);
+      if (!quantize_node(n, o)) return "internal: a quantised child box does not contain its child";
     }
     for (size_t i = 0; i < cb.tris.size(); ++i) {
       int32_t t = cb.tris[i];

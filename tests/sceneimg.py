@@ -23,9 +23,7 @@ class SceneImage:
         self.planes = [pl[:g[0] + 1], pl[g[0] + 1:g[0] + g[1] + 2], pl[g[0] + g[1] + 2:]]
         self.cells = np.frombuffer(buf, dtype="<i4", count=4 * int(h["n_cells"]), offset=int(h["off_cells"])).reshape(-1, 4)
         nn = int(h["n_nodes"])
-        raw = np.frombuffer(buf, dtype="<f4", count=32 * nn, offset=int(h["off_nodes"])).reshape(nn, 32)
-        self.node_f = raw
-        self.node_u = raw.view("<u4")
+        self.node_u = np.frombuffer(buf, dtype="<u4", count=16 * nn, offset=int(h["off_nodes"])).reshape(nn, 16)
         nr = int(h["n_refs"])
         ct = np.frombuffer(buf, dtype="<f4", count=12 * nr, offset=int(h["off_ctris"])).reshape(nr, 3, 4)
         self.ctri_v = ct[:, :, :3]
@@ -38,16 +36,21 @@ class SceneImage:
         self.lam = np.frombuffer(buf, dtype="<f4", count=B, offset=int(h["off_lambda"]))
 
     def child(self, node, c):
-        """(box lo[3], box hi[3], idx, cnt) of child c (0..3) of a (global) 4-wide node: one float4
-        per box coordinate over the children, then the child words (inner: node index; leaf:
-        count << 27 | first triangle; EMPTY: no child)."""
-        f = self.node_f[node]
-        word = int(self.node_u[node][24 + c])
-        lo = np.array([f[c], f[8 + c], f[16 + c]])
-        hi = np.array([f[4 + c], f[12 + c], f[20 + c]])
+        """(box lo[3], box hi[3], idx, cnt, step[3]) of child c (0..3) of a (global) 4-wide node of
+        64 bytes: origin (3 floats) | exponents (bytes) ; child words ; lo.x hi.x lo.y hi.y bytes ;
+        lo.z hi.z bytes. A bound is origin + q 2^(e - 127) (inner: node index; leaf: count << 27 |
+        first triangle; EMPTY: no child); step is the grid spacing per axis."""
+        u = self.node_u[node]
+        origin = u[0:3].copy().view("<f4").astype(np.float64)
+        e = int(u[3])
+        step = np.array([2.0 ** (((e >> (8 * a)) & 255) - 127) for a in range(3)])
+        q = [(int(u[8 + j]) >> (8 * c)) & 255 for j in range(6)]
+        lo = origin + np.array([q[0], q[2], q[4]], dtype=np.float64) * step
+        hi = origin + np.array([q[1], q[3], q[5]], dtype=np.float64) * step
+        word = int(u[4 + c])
         if word == EMPTY:
-            return lo, hi, EMPTY, 0
-        return lo, hi, word & ((1 << 27) - 1), word >> 27
+            return lo, hi, EMPTY, 0, step
+        return lo, hi, word & ((1 << 27) - 1), word >> 27, step
 
     def cell_of_point(self, p):
         idx = []

@@ -91,25 +91,28 @@ def test_scene_structure(grid):
         if nt == 0:
             assert nn == 0
             continue
-        # walk the tree: leaf ranges partition the cell's triangle list, child boxes nest
+        # walk the tree: leaf ranges partition the cell's triangle list; a child's quantised box
+        # lies within its parent's, grown by one grid step of the child's node (the two boxes sit
+        # on different grids)
         covered = np.zeros(nt, dtype=int)
         stack = [(0, None, None)]
         while stack:
             node, plo, phi = stack.pop()
             for ch in range(4):
-                lo, hi, idx, cnt = im.child(nb + node, ch)
+                lo, hi, idx, cnt, step = im.child(nb + node, ch)
                 if idx == EMPTY:
                     continue
+                assert np.all(hi >= lo)
                 if plo is not None:
-                    assert np.all(lo >= plo) and np.all(hi <= phi)
+                    assert np.all(lo >= plo - step) and np.all(hi <= phi + step)
                 if cnt > 0:
                     covered[idx:idx + cnt] += 1
                     tv = im.ctri_v[tb + idx:tb + idx + cnt]
                     tmin, tmax = tv.min(axis=1), tv.max(axis=1)
                     # every triangle box meets the leaf box (boxes are clipped to the cell) ...
                     assert np.all(tmax >= lo - 1e-6) and np.all(tmin <= hi + 1e-6)
-                    # ... and the leaf box is no larger than its triangles' box
-                    assert np.all(lo >= tmin.min(0) - 1e-6) and np.all(hi <= tmax.max(0) + 1e-6)
+                    # ... and the leaf box is at most one grid step larger than its triangles' box
+                    assert np.all(lo >= tmin.min(0) - step - 1e-6) and np.all(hi <= tmax.max(0) + step + 1e-6)
                 else:
                     assert idx > node  # breadth-first order: children after parents
                     stack.append((idx, lo, hi))
