@@ -58,7 +58,15 @@ class _Params(C.Structure):
                 ("threads", C.c_int32), ("force_bvh", C.c_int32), ("tie_t_rel", C.c_double),
                 ("tie_edge_abs", C.c_double), ("tie_edge_rel_t", C.c_double), ("tie_lobe", C.c_double),
                 ("tie_cos_sun", C.c_double), ("cached", C.c_int32), ("first_sample", C.c_int32),
-                ("purpose", C.c_uint32), ("record_depth", C.c_int32), ("sample_per_entry", C.c_int32)]
+                ("purpose", C.c_uint32), ("record_depth", C.c_int32), ("sample_per_entry", C.c_int32),
+                ("ph_pos", C.c_void_p), ("ph_dir", C.c_void_p), ("ph_flux", C.c_void_p), ("n_photons", C.c_int64),
+                ("ph_radius", C.c_double), ("tie_radius", C.c_double), ("ph_unc", C.c_void_p)]
+
+
+class _PhotonParams(C.Structure):
+    _fields_ = [("n_photons", C.c_int64), ("max_depth", C.c_int32), ("seed", C.c_uint64), ("threads", C.c_int32),
+                ("tie_t_rel", C.c_double), ("tie_edge_abs", C.c_double), ("tie_edge_rel_t", C.c_double),
+                ("tie_lobe", C.c_double), ("tie_cos_sun", C.c_double)]
 
 
 class _Queries(C.Structure):
@@ -83,6 +91,8 @@ def lib():
         L.orc_shadow.restype = i32
         L.orc_render.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp, vp]
         L.orc_render.restype = i32
+        L.orc_photons.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, vp]
+        L.orc_photons.restype = i64
         _lib = L
     return _lib
 
@@ -193,11 +203,12 @@ class RenderResult:
     tied: np.ndarray       # number of tied samples per pixel
     stats: dict
     queries: dict | None = None
+    photon_unc: np.ndarray | None = None   # like image: caustic radiance of photons near the radius
 
 
 def render(scene, camera, spp=1, max_depth=4, seed=1, view=0, pixels=None, threads=None,
            tie: TieParams = TieParams(), force_bvh=-1, cached=False, first_sample=0, purpose=0,
-           sample_per_entry=False) -> RenderResult:
+           sample_per_entry=False, photons=None, radius=0.0, tie_radius=1e-4) -> RenderResult:
     """Reference spectral image (mean of spp path samples per pixel), FP64 accumulation.
     With cached=True the paths stop at the vertex after bounce 2 and the query there
     (position, direction toward the previous vertex, material, throughput) is returned.
@@ -209,7 +220,12 @@ def render(scene, camera, spp=1, max_depth=4, seed=1, view=0, pixels=None, threa
     th = threads or min(8, os.cpu_count() or 1)
     prm = _Params(int(spp), int(max_depth), int(seed), int(view), int(th), int(force_bvh), tie.t_rel, tie.edge_abs,
                   tie.edge_rel_t, tie.lobe, tie.cos_sun, 1 if cached else 0, int(first_sample), int(purpose), 0,
-                  1 if sample_per_entry else 0)
+                  1 if sample_per_entry else 0, None, None, None, 0, float(radius), float(tie_radius), None)
+    unc = None
+    if photons is not None and len(photons["id"]) > 0:
+        keep_ph = [np.ascontiguousarray(photons[k], dtype=np.float64) for k in ("pos", "dir", "flux")]
+        prm.ph_pos, prm.ph_dir, prm.ph_flux = (_p(a).value for a in keep_ph)
+        prm.n_photons = len(photons["id"])
     B = scene.n_bins
     if pixels is None:
         npx = camera.width * camera.height
@@ -220,6 +236,9 @@ def render(scene, camera, spp=1, max_depth=4, seed=1, view=0, pixels=None, threa
     img = np.zeros((B, npx))
     tied = np.zeros(npx, dtype=np.int32)
     st = np.zeros(4, dtype=np.int64)
+    if prm.n_photons > 0:
+        unc = np.zeros((B, npx))
+        prm.ph_unc = _p(unc).value
     q = None
     qs = None
     if cached:
@@ -233,8 +252,36 @@ def render(scene, camera, spp=1, max_depth=4, seed=1, view=0, pixels=None, threa
     if pixels is None:
         img = img.reshape(B, camera.height, camera.width)
         tied = tied.reshape(camera.height, camera.width)
+        if unc is not None:
+            unc = unc.reshape(B, camera.height, camera.width)
     stats = dict(paths=int(st[0]), vertices=int(st[1]), shadow_rays=int(st[2]), tied_paths=int(st[3]))
-    return RenderResult(img, tied, stats, q)
+    return RenderResult(img, tied, stats, q, unc)
+
+
+def photons(scene, n_photons, max_depth=8, seed=1, threads=None, tie: TieParams = TieParams()):
+    """Caustic photon map (see orc_photons): records of photons stored at opaque vertices after at
+    least one reflection, ordered by (photon, vertex): pos [n][3], dir [n][3] (direction of
+    travel), flux [n][B], id [n] (photon index), depth [n] (vertex); tied [n_photons] flags
+    photons whose path FP32 rounding could change; area = the windows' projected area A."""
+    s, keep = _scene_struct(scene)
+    B = scene.n_bins
+    th = threads or min(8, os.cpu_count() or 1)
+    pp = _PhotonParams(int(n_photons), int(max_depth), int(seed), int(th), tie.t_rel, tie.edge_abs, tie.edge_rel_t,
+                       tie.lobe, tie.cos_sun)
+    cap = max(1024, int(n_photons) // 2)
+    while True:
+        pos, dirs = np.zeros((cap, 3)), np.zeros((cap, 3))
+        flux = np.zeros((cap, B))
+        pid, dep = np.zeros(cap, dtype=np.int64), np.zeros(cap, dtype=np.int32)
+        tied = np.zeros(int(n_photons), dtype=np.uint8)
+        area = C.c_double()
+        n = lib().orc_photons(C.byref(s), C.byref(pp), cap, _p(pos), _p(dirs), _p(flux), _p(pid), _p(dep), _p(tied),
+                              C.byref(area))
+        if n <= cap:
+            break
+        cap = int(n)
+    return dict(pos=pos[:n], dir=dirs[:n], flux=flux[:n], id=pid[:n], depth=dep[:n], tied=tied.astype(bool),
+                area=area.value)
 
 
 def training_records(scene, camera, pixels, first_path, max_depth=8, seed=1, view=0, record_depth=3, threads=None,
@@ -250,7 +297,8 @@ def training_records(scene, camera, pixels, first_path, max_depth=8, seed=1, vie
                   float(camera.vfov_deg), int(camera.width), int(camera.height))
     th = threads or min(8, os.cpu_count() or 1)
     prm = _Params(1, int(max_depth), int(seed), int(view), int(th), -1, tie.t_rel, tie.edge_abs, tie.edge_rel_t,
-                  tie.lobe, tie.cos_sun, 0, int(first_path), 1 << 24, int(record_depth), 1)
+                  tie.lobe, tie.cos_sun, 0, int(first_path), 1 << 24, int(record_depth), 1, None, None, None, 0, 0.0, 0.0,
+                  None)
     B = scene.n_bins
     px = np.ascontiguousarray(pixels, dtype=np.int64)
     n = px.shape[0]

@@ -425,6 +425,14 @@ typedef struct {
   uint32_t purpose;          // random-number purpose: added to the depth word (0 or 1 << 24)
   int32_t record_depth;      // > 0: training paths; record that vertex and restart beta and L there
   int32_t sample_per_entry;  // 1: entry i of the pixel list is one path with sample first_sample + i
+  // caustic photon map (n_photons = 0: none): density estimate added at every opaque vertex
+  const double* ph_pos;      // [n][3] where a photon was stored
+  const double* ph_dir;      // [n][3] its direction of travel on arrival
+  const double* ph_flux;     // [n][B] its flux
+  int64_t n_photons;
+  double ph_radius;
+  double tie_radius;         // relative margin of the gather radius: photons within it are uncertain
+  double* ph_unc;            // [B][n_pix] or null: the caustic radiance those photons could change
 } orc_params;
 
 void orc_philox4x32_10(const uint32_t* ctr, const uint32_t* key, uint32_t* out) {
@@ -571,6 +579,10 @@ int orc_render(const orc_scene* sc, const orc_camera* cam, const orc_params* prm
 
   auto render_pixel = [&](int64_t i, std::vector<double>& acc, std::vector<double>& L, std::vector<double>& beta,
                           std::vector<double>& F, std::vector<GlassCross>& cr, int64_t* nv, int64_t* ns, int32_t* ntie) {
+    thread_local std::vector<double> acc_ph, acc_unc, Lu, acc_u;
+    acc_ph.assign(B, 0.0);
+    acc_unc.assign(B, 0.0);
+    acc_u.assign(B, 0.0);
     int64_t pix = pixels ? pixels[i] : i;
     int px = (int)(pix % W), py = (int)(pix / W);
     std::fill(acc.begin(), acc.end(), 0.0);
@@ -578,6 +590,7 @@ int orc_render(const orc_scene* sc, const orc_camera* cam, const orc_params* prm
       const int s = prm->sample_per_entry ? prm->first_sample + (int)i : prm->first_sample + si;
       bool tied = false;
       std::fill(L.begin(), L.end(), 0.0);
+      Lu.assign(B, 0.0);
       std::fill(beta.begin(), beta.end(), 1.0);
       U4 rn = philox4x32_10({{(uint32_t)pix, (uint32_t)s, prm->purpose, prm->view}}, k0, k1);
       double sx = (2.0 * (px + unif(rn.x[0])) / W - 1.0) * tf * W / H;
@@ -628,6 +641,32 @@ int orc_render(const orc_scene* sc, const orc_camera* cam, const orc_params* prm
         const float* rt = sc->rho_tab + m * B;
         if (mat_type[m] == 0) {
           for (int j = 0; j < B; ++j) F[j] = fresnel(nt[j], kt[j], cos_o);
+          if (prm->n_photons > 0) {
+            // caustic radiance: (1 - F) rho / pi times the flux of the photons within the gather
+            // radius that arrived from the side the path sees, over the disc area pi r^2; photons
+            // within r (1 +- tie_radius) could fall on either side of r in FP32: their flux bounds
+            // how far another rounding of the same estimate can go
+            const double r = prm->ph_radius, r2 = r * r;
+            const double lo2 = r2 * (1.0 - prm->tie_radius) * (1.0 - prm->tie_radius);
+            const double hi2 = r2 * (1.0 + prm->tie_radius) * (1.0 + prm->tie_radius);
+            std::fill(acc_ph.begin(), acc_ph.end(), 0.0);
+            std::fill(acc_unc.begin(), acc_unc.end(), 0.0);
+            for (int64_t q = 0; q < prm->n_photons; ++q) {
+              const double* pp = prm->ph_pos + 3 * q;
+              const double dx = pp[0] - p.x, dy = pp[1] - p.y, dz = pp[2] - p.z;
+              const double d2 = dx * dx + dy * dy + dz * dz;
+              if (d2 > hi2) continue;
+              const double* pd = prm->ph_dir + 3 * q;
+              const double side = pd[0] * n.x + pd[1] * n.y + pd[2] * n.z;
+              if (std::fabs(side) <= tie.cos_sun) tied = true;
+              if (d2 < r2 && side < 0.0)
+                for (int j = 0; j < B; ++j) acc_ph[j] += prm->ph_flux[q * B + j];
+              if (d2 >= lo2 && side < 0.0)
+                for (int j = 0; j < B; ++j) acc_unc[j] += prm->ph_flux[q * B + j];
+            }
+            for (int j = 0; j < B; ++j) Lu[j] += beta[j] * (1.0 - F[j]) * rt[j] / M_PI * acc_unc[j] / (M_PI * r2);
+            for (int j = 0; j < B; ++j) L[j] += beta[j] * (1.0 - F[j]) * rt[j] / M_PI * acc_ph[j] / (M_PI * r2);
+          }
           // next-event estimation toward the sun (eq. 3)
           double cs = dot(n, ws);
           if (cs != 0.0 && std::fabs(cs) <= tie.cos_sun) tied = true;
@@ -697,9 +736,12 @@ int orc_render(const orc_scene* sc, const orc_camera* cam, const orc_params* prm
         skip = h.id;
       }
       for (int j = 0; j < B; ++j) acc[j] += L[j];
+      for (int j = 0; j < B; ++j) acc_u[j] += Lu[j];
       if (tied) ++*ntie;
     }
     for (int j = 0; j < B; ++j) image[(int64_t)j * npx + i] = acc[j] / spp;
+    if (prm->ph_unc)
+      for (int j = 0; j < B; ++j) prm->ph_unc[(int64_t)j * npx + i] = acc_u[j] / spp;
   };
 
   int nt = std::max(1, prm->threads);
@@ -729,6 +771,179 @@ int orc_render(const orc_scene* sc, const orc_camera* cam, const orc_params* prm
     stats[3] = st_tied;
   }
   return 0;
+}
+
+// ------------------------------------------------------------------------------------------
+// Caustic photon map (section 4: photon maps filled from the light sources, one of them for
+// caustics). Photons leave the sun (a plane wave, section 3) through the windows: photon i picks
+// a glass triangle with probability proportional to its area projected on the sun's direction and
+// a uniform point p on it (random-number counter (i, i >> 32, 0 | 4 << 24, 0)); it carries the
+// flux E_j A / N of the sun's beam through the windows' total projected area A, times the
+// transmittance of whatever lies between p and the sun (a shadow ray from p, as for the direct
+// term). Its first vertex is p on that window. At vertex d (counter (i, i >> 32, d | 4 << 24, 0)):
+//   glass:  reflect with probability P_r = mean R / (mean R + mean T) (weight R / P_r), else
+//           transmit straight (weight T / (1 - P_r)), as for camera paths;
+//   opaque: if the photon has been reflected at least once (by a glass face or a mirror lobe) it
+//           is stored with its flux and direction (light reaching a diffuse surface only by
+//           transmission through thin glass is the direct term, which the paths' eq. 3 already
+//           counts); then the mirror lobe is taken with P_s = mean F / (mean F + mean (1-F) rho)
+//           (weight F / P_s), else the photon ends (a diffuse bounce leaves the caustic paths).
+// Vertex max_depth stores but does not scatter. Records come out ordered by (photon, vertex).
+// ------------------------------------------------------------------------------------------
+typedef struct {
+  int64_t n_photons;
+  int32_t max_depth;
+  uint64_t seed;
+  int32_t threads;
+  double tie_t_rel, tie_edge_abs, tie_edge_rel_t, tie_lobe, tie_cos_sun;
+} orc_photon_params;
+
+int64_t orc_photons(const orc_scene* sc, const orc_photon_params* pp, int64_t cap, double* pos, double* dir,
+                    double* flux, int64_t* pid, int32_t* pdepth, uint8_t* tied_out, double* area_out) {
+  Scene S;
+  load_scene(sc, -1, &S);
+  const int B = sc->n_bins;
+  const Tie tie{pp->tie_t_rel, pp->tie_edge_abs, pp->tie_edge_rel_t, pp->tie_lobe, pp->tie_cos_sun};
+  std::vector<int> mat_type(sc->mat_type, sc->mat_type + sc->n_mat);
+  std::vector<double> lam(B), E(B);
+  for (int j = 0; j < B; ++j) {
+    lam[j] = sc->lambda_min_nm + (j + 0.5) * (sc->lambda_max_nm - sc->lambda_min_nm) / B;
+    E[j] = sc->sun_E[j];
+  }
+  const V3 ws = normalize({sc->sun_dir[0], sc->sun_dir[1], sc->sun_dir[2]});
+  // windows: glass triangles and the prefix sums of their projected areas
+  std::vector<int> wtri;
+  std::vector<double> cdf{0.0};
+  for (int64_t t = 0; t < sc->n_tri; ++t) {
+    const Tri& T = S.tris[t];
+    if (mat_type[T.mat] != 1 || T.degenerate) continue;
+    const V3 c = cross(T.v1 - T.v0, T.v2 - T.v0);
+    wtri.push_back((int)t);
+    cdf.push_back(cdf.back() + 0.5 * std::fabs(dot(c, ws)));
+  }
+  const double A = cdf.back();
+  if (area_out) *area_out = A;
+  if (wtri.empty() || !(A > 0.0) || pp->n_photons <= 0) return 0;
+  const uint32_t k0 = (uint32_t)pp->seed, k1 = (uint32_t)(pp->seed >> 32);
+  const uint32_t kPurpose = 4u << 24;
+  struct Rec { V3 p, d; int64_t id; int depth; std::vector<double> f; };
+  const int nt = std::max(1, pp->threads);
+  std::vector<std::vector<Rec>> out(nt);
+  auto work = [&](int th, int64_t a, int64_t b) {
+    std::vector<double> beta(B), F(B), R(B), Tt(B);
+    std::vector<GlassCross> cr;
+    for (int64_t i = a; i < b; ++i) {
+      bool tied = false;
+      const uint32_t c0 = (uint32_t)i, c1 = (uint32_t)((uint64_t)i >> 32);
+      U4 rn = philox4x32_10({{c0, c1, 0u | kPurpose, 0u}}, k0, k1);
+      const double x = unif(rn.x[0]) * A;
+      int w = (int)(std::upper_bound(cdf.begin(), cdf.end(), x) - cdf.begin()) - 1;
+      w = std::min(std::max(w, 0), (int)wtri.size() - 1);
+      int tri = wtri[w];
+      const Tri& T0 = S.tris[tri];
+      const double r = std::sqrt(unif(rn.x[1])), u2 = unif(rn.x[2]);
+      double bu = r * (1.0 - u2), bv = r * u2;
+      V3 p = T0.v0 * (1.0 - bu - bv) + T0.v1 * bu + T0.v2 * bv;
+      V3 d = ws * -1.0;
+      // incoming visibility: from p toward the sun, stopped by opaque, attenuated by other glass
+      {
+        const V3 ng = normalize(cross(T0.v1 - T0.v0, T0.v2 - T0.v0));
+        const double dn = dot(d, ng);
+        const V3 n = dn > 0 ? ng * -1.0 : ng;
+        const double eps = 1e-5 * (1.0 + maxabs(p));
+        if (!shadow_visibility(S, mat_type, p + n * eps, ws, tri, tie, &cr, &tied)) {
+          if (tied_out) tied_out[i] = tied;
+          continue;
+        }
+        for (int j = 0; j < B; ++j) {
+          double V = 1.0;
+          for (const GlassCross& g : cr) {
+            double Rr, Tr;
+            glass_slab(sc, g.mat, j, lam[j], g.cos_t, g.tri, g.u, g.v, &Rr, &Tr);
+            V *= Tr;
+          }
+          beta[j] = E[j] * A / (double)pp->n_photons * V;
+        }
+      }
+      bool reflected = false;
+      for (int dep = 1; dep <= pp->max_depth; ++dep) {
+        const Tri& T = S.tris[tri];
+        const V3 ng = normalize(cross(T.v1 - T.v0, T.v2 - T.v0));
+        const double dn = dot(d, ng);
+        const V3 n = dn > 0 ? ng * -1.0 : ng;
+        const double cos_o = std::fabs(dn);
+        if (cos_o <= tie.cos_sun) tied = true;
+        const double eps = 1e-5 * (1.0 + maxabs(p));
+        const int m = T.mat;
+        U4 rv = philox4x32_10({{c0, c1, (uint32_t)dep | kPurpose, 0u}}, k0, k1);
+        const double u0 = unif(rv.x[0]);
+        V3 o;
+        if (mat_type[m] == 0) {
+          if (reflected) out[th].push_back({p, d, i, dep, beta});
+          if (dep == pp->max_depth) break;
+          double a = 0, b = 0;
+          for (int j = 0; j < B; ++j) {
+            F[j] = fresnel(sc->n_tab[m * B + j], sc->k_tab[m * B + j], cos_o);
+            a += F[j];
+            b += (1.0 - F[j]) * sc->rho_tab[m * B + j];
+          }
+          a /= B;
+          b /= B;
+          if (a + b == 0.0) break;
+          const double Ps = a / (a + b);
+          if (std::fabs(u0 - Ps) <= tie.lobe) tied = true;
+          if (!(u0 < Ps)) break;   // the diffuse lobe ends the photon's caustic path
+          for (int j = 0; j < B; ++j) beta[j] *= F[j] / Ps;
+          d = d - ng * (2.0 * dn);
+          o = p + n * eps;
+          reflected = true;
+        } else {
+          if (dep == pp->max_depth) break;
+          double mr = 0, mt = 0;
+          for (int j = 0; j < B; ++j) {
+            glass_slab(sc, m, j, lam[j], cos_o, tri, bu, bv, &R[j], &Tt[j]);
+            mr += R[j];
+            mt += Tt[j];
+          }
+          const double Pr = mr / (mr + mt);
+          if (std::fabs(u0 - Pr) <= tie.lobe) tied = true;
+          if (u0 < Pr) {
+            for (int j = 0; j < B; ++j) beta[j] *= R[j] / Pr;
+            d = d - ng * (2.0 * dn);
+            o = p + n * eps;
+            reflected = true;
+          } else {
+            for (int j = 0; j < B; ++j) beta[j] *= Tt[j] / (1.0 - Pr);
+            o = p - n * eps;
+          }
+        }
+        Hit h = closest_hit(S, o, d, tri, tie, &tied);
+        if (!h.hit) break;
+        tri = h.id;
+        bu = h.u;
+        bv = h.v;
+        const Tri& Tn = S.tris[tri];
+        p = Tn.v0 * (1.0 - bu - bv) + Tn.v1 * bu + Tn.v2 * bv;
+      }
+      if (tied_out) tied_out[i] = tied;
+    }
+  };
+  std::vector<std::thread> ths;
+  for (int k = 0; k < nt; ++k) ths.emplace_back(work, k, pp->n_photons * k / nt, pp->n_photons * (k + 1) / nt);
+  for (auto& t : ths) t.join();
+  int64_t n = 0;
+  for (auto& v : out)
+    for (const Rec& r : v) {
+      if (n < cap) {
+        pos[3 * n] = r.p.x; pos[3 * n + 1] = r.p.y; pos[3 * n + 2] = r.p.z;
+        dir[3 * n] = r.d.x; dir[3 * n + 1] = r.d.y; dir[3 * n + 2] = r.d.z;
+        for (int j = 0; j < B; ++j) flux[n * B + j] = r.f[j];
+        pid[n] = r.id;
+        pdepth[n] = r.depth;
+      }
+      ++n;
+    }
+  return n;
 }
 
 }  // extern "C"
