@@ -776,8 +776,10 @@ int orc_render(const orc_scene* sc, const orc_camera* cam, const orc_params* prm
 // ------------------------------------------------------------------------------------------
 // Caustic photon map (section 4: photon maps filled from the light sources, one of them for
 // caustics). Photons leave the sun (a plane wave, section 3) through the windows: photon i picks
-// a glass triangle with probability proportional to its area projected on the sun's direction and
-// a uniform point p on it (random-number counter (i, i >> 32, 0 | 4 << 24, 0)); it carries the
+// a glass triangle with probability proportional to its area projected on the sun's direction (the
+// window whose threshold floor(cdf_w / A 2^24) is the last not above the 24-bit random integer
+// x >> 8, cdf_w the projected area of the windows before it) and a uniform point p on it
+// (random-number counter (i, i >> 32, 0 | 4 << 24, 0)); it carries the
 // flux E_j A / N of the sun's beam through the windows' total projected area A, times the
 // transmittance of whatever lies between p and the sun (a shadow ray from p, as for the direct
 // term). Its first vertex is p on that window. At vertex d (counter (i, i >> 32, d | 4 << 24, 0)):
@@ -824,6 +826,8 @@ int64_t orc_photons(const orc_scene* sc, const orc_photon_params* pp, int64_t ca
   const double A = cdf.back();
   if (area_out) *area_out = A;
   if (wtri.empty() || !(A > 0.0) || pp->n_photons <= 0) return 0;
+  std::vector<uint32_t> thr(wtri.size());
+  for (size_t w = 0; w < wtri.size(); ++w) thr[w] = (uint32_t)std::floor(cdf[w] / A * 16777216.0);
   const uint32_t k0 = (uint32_t)pp->seed, k1 = (uint32_t)(pp->seed >> 32);
   const uint32_t kPurpose = 4u << 24;
   struct Rec { V3 p, d; int64_t id; int depth; std::vector<double> f; };
@@ -836,8 +840,9 @@ int64_t orc_photons(const orc_scene* sc, const orc_photon_params* pp, int64_t ca
       bool tied = false;
       const uint32_t c0 = (uint32_t)i, c1 = (uint32_t)((uint64_t)i >> 32);
       U4 rn = philox4x32_10({{c0, c1, 0u | kPurpose, 0u}}, k0, k1);
-      const double x = unif(rn.x[0]) * A;
-      int w = (int)(std::upper_bound(cdf.begin(), cdf.end(), x) - cdf.begin()) - 1;
+      // window w when its integer threshold floor(cdf_w / A 2^24) <= (x >> 8) < the next one
+      const uint32_t x24 = rn.x[0] >> 8;
+      int w = (int)(std::upper_bound(thr.begin(), thr.end(), x24) - thr.begin()) - 1;
       w = std::min(std::max(w, 0), (int)wtri.size() - 1);
       int tri = wtri[w];
       const Tri& T0 = S.tris[tri];
