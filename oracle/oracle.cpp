@@ -813,15 +813,22 @@ int64_t orc_photons(const orc_scene* sc, const orc_photon_params* pp, int64_t ca
     E[j] = sc->sun_E[j];
   }
   const V3 ws = normalize({sc->sun_dir[0], sc->sun_dir[1], sc->sun_dir[2]});
-  // windows: glass triangles and the prefix sums of their projected areas
+  // windows: glass triangles and the prefix sums of their projected areas, taken on the sun's
+  // unit direction rounded to FP32 (the form a scene stores it in)
+  const double sl = std::sqrt((double)sc->sun_dir[0] * sc->sun_dir[0] + (double)sc->sun_dir[1] * sc->sun_dir[1] +
+                              (double)sc->sun_dir[2] * sc->sun_dir[2]);
+  const V3 ws32{(double)(float)(sc->sun_dir[0] / sl), (double)(float)(sc->sun_dir[1] / sl),
+                (double)(float)(sc->sun_dir[2] / sl)};
   std::vector<int> wtri;
   std::vector<double> cdf{0.0};
   for (int64_t t = 0; t < sc->n_tri; ++t) {
     const Tri& T = S.tris[t];
     if (mat_type[T.mat] != 1 || T.degenerate) continue;
     const V3 c = cross(T.v1 - T.v0, T.v2 - T.v0);
+    const double a = 0.5 * std::fabs(dot(c, ws32));
+    if (!(a > 0.0)) continue;
     wtri.push_back((int)t);
-    cdf.push_back(cdf.back() + 0.5 * std::fabs(dot(c, ws)));
+    cdf.push_back(cdf.back() + a);
   }
   const double A = cdf.back();
   if (area_out) *area_out = A;
