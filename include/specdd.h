@@ -420,6 +420,85 @@ int sdd_render_cached(sdd_ctx* ctx, const sdd_scene* scene, sdd_cache* cache, co
  * 1 if the slot's path reached its third vertex else 0), target [n][max_bins]. */
 int sdd_cache_get_records(sdd_ctx* ctx, sdd_cache* cache, int64_t n, float* rec_x, float* rec_w, float* target);
 
+/* Caustic photon map (section 4: photon maps are filled with the points where photons sent out
+ * from the light sources hit the scene, one map serving the caustics; the radiance a surface
+ * sends back is split into separate integrals, the caustic one taken from that map).
+ * The source is the directional sun of the scene (section 3). Emission: the windows are the
+ * scene's glass triangles, with projected areas a_w = |n_w . s| area_w on the unit sun direction
+ * s as stored by the scene (FP32); A = sum_w a_w. Photon i (0 <= i < n_photons) draws x from
+ * Philox counter (i, i >> 32, 4 << 24, 0) under key (seed, seed >> 32): window w is the last
+ * whose threshold floor(2^24 (a_0 + ... + a_{w-1}) / A) does not exceed x.x >> 8; its point on
+ * the window has barycentrics (sqrt(u1)(1 - u2), sqrt(u1) u2) with u1, u2 the 24-bit uniforms
+ * of x.y, x.z; its flux is E_j A / n_photons, times the slab transmittance of every other glass
+ * triangle between the point and the sun (an opaque one stops it). Vertex 1 is that window
+ * point, reached along -s. At vertex k a photon draws u0 from counter (i, i >> 32, k | 4 << 24,
+ * 0): glass reflects with probability mean R / (mean R + mean T), else transmits straight on
+ * (as camera paths do); an opaque vertex first stores the photon when one of its earlier
+ * vertices reflected it (glass face or mirror lobe; light only transmitted is direct light),
+ * then takes the mirror lobe with probability mean F / (mean F + mean (1 - F) rho) or ends
+ * (a diffuse bounce leaves the caustic paths). Vertex max_depth scatters nothing. A stored
+ * record holds the vertex position, the photon's direction of arrival, its flux per bin on
+ * arrival, the photon index and the vertex number. */
+typedef struct sdd_photon_map sdd_photon_map;
+
+typedef struct {
+  int64_t n_photons;           /* photons sent out, >= 1; n_photons (max_depth - 1) < 2^32     */
+  int32_t max_depth;           /* vertices of a photon path, 2 .. 64                           */
+  float radius;                /* gather radius r > 0 (scene units); the map's grid cells are 2 r */
+  uint64_t seed;               /* Philox key of the photon paths                               */
+  int64_t capacity;            /* records the map holds, 1 .. 2^28 (further ones are counted as
+                                  dropped)                                                     */
+  int32_t wave_paths;          /* photons in flight per wavefront, 64 .. 2^26 (0 = 2^20)       */
+  int32_t queue_rounds;        /* traversal rounds per phase as in sdd_render_params (0 = 1)   */
+} sdd_photon_params;
+
+typedef struct {
+  int64_t stored;              /* records held (<= capacity)                                   */
+  int64_t dropped;             /* records that did not fit                                     */
+  int32_t n_windows;           /* glass triangles of non-zero projected area                   */
+  int32_t n_buckets;           /* hash-grid buckets                                            */
+  double window_area;          /* A, the windows' total projected area                         */
+  size_t device_bytes;         /* bytes of the map's device buffer                             */
+} sdd_photon_info;
+
+/* Device bytes of a map with these parameters for this scene (its bins and glass triangles). */
+int sdd_photon_map_bytes(const sdd_scene* scene, const sdd_photon_params* params, size_t* bytes);
+/* Workspace bytes of sdd_photon_map_build (photons in flight, bins, cells). */
+int sdd_photon_workspace_bytes(const sdd_scene* scene, const sdd_photon_params* params, size_t* bytes);
+/* Bind a map to caller device memory dev_buf (>= sdd_photon_map_bytes, 256-byte aligned), valid
+ * while the map is used; the map holds nothing until sdd_photon_map_build. Errors:
+ * SDD_ERR_INVALID_ARG (parameters out of range), SDD_ERR_WORKSPACE (small buffer). */
+int sdd_photon_map_create(sdd_ctx* ctx, const sdd_scene* scene, const sdd_photon_params* params, void* dev_buf,
+                          size_t bytes, sdd_photon_map** out);
+void sdd_photon_map_destroy(sdd_photon_map* map);
+/* Trace the photons of the map's parameters through the scene (same cell queues and traversal
+ * as camera paths) on the context stream, store the records, then sort them into the hashed
+ * grid the gathering reads. The scene's bins must match the map's; its sun (direction and
+ * spectrum) is read now. Errors: SDD_ERR_NOT_READY (scene not uploaded), SDD_ERR_WORKSPACE;
+ * sdd_finish reports SDD_ERR_QUEUE_OVERFLOW when a photon's way to the sun crossed more than 8
+ * glass slabs. A scene without glass facing the sun gives an empty map. */
+int sdd_photon_map_build(sdd_ctx* ctx, const sdd_scene* scene, sdd_photon_map* map, void* workspace,
+                         size_t workspace_bytes);
+/* Counts of the last build (waits for the stream). */
+int sdd_photon_map_info(sdd_ctx* ctx, sdd_photon_map* map, sdd_photon_info* out);
+/* The first n records (n <= stored; any order) to HOST arrays (waits): pos [n][3], dir [n][3]
+ * (direction of arrival), flux [n][n_bins], id [n] (photon index), vertex [n]. */
+int sdd_photon_map_records(sdd_ctx* ctx, sdd_photon_map* map, int64_t n, float* pos, float* dir, float* flux,
+                           int64_t* id, int32_t* vertex);
+/* Replace the map's records with n <= capacity records from HOST arrays laid out as
+ * sdd_photon_map_records returns them (id and vertex may be NULL: stored as 0) and sort them into
+ * the grid (waits for the copy): a map saved from an earlier build or computed elsewhere is then
+ * gathered as if built here. */
+int sdd_photon_map_load(sdd_ctx* ctx, sdd_photon_map* map, int64_t n, const float* pos, const float* dir,
+                        const float* flux, const int64_t* id, const int32_t* vertex);
+/* sdd_render (plain mode) with the caustic radiance of the map added at every opaque vertex
+ * that is shaded, before its lobe: beta_j (1 - F_j) rho_j / pi times the summed flux of the
+ * records within distance r whose direction of arrival d has d . n < 0 (n: the normal on the
+ * side the path sees), divided by pi r^2 (the density estimate of photon mapping). use_graph
+ * is allowed (the graph reads the map's current contents). */
+int sdd_render_photons(sdd_ctx* ctx, const sdd_scene* scene, const sdd_photon_map* map, const sdd_camera* camera,
+                       const sdd_render_params* params, void* workspace, size_t workspace_bytes, float* image_dev);
+
 /* Colorimetry of a spectral image (section 6 maps the spectral renderings to RGB by colorimetry;
  * section 1: the observer's visual adaptation is a colorimetric matter). image_dev is device
  * memory [n_bins][n_pixels] FP32 (an image [n_bins][H][W] has n_pixels = H W) sampled at the bin

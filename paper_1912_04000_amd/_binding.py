@@ -142,6 +142,22 @@ class TrainParams(C.Structure):
     _fields_ = [("train_paths", C.c_int32), ("step_records", C.c_int32), ("steps", C.c_int32), ("every", C.c_int32)]
 
 
+class PhotonParams(C.Structure):
+    _fields_ = [("n_photons", C.c_int64), ("max_depth", C.c_int32), ("radius", C.c_float), ("seed", C.c_uint64),
+                ("capacity", C.c_int64), ("wave_paths", C.c_int32), ("queue_rounds", C.c_int32)]
+
+
+class PhotonInfo(C.Structure):
+    _fields_ = [("stored", C.c_int64), ("dropped", C.c_int64), ("n_windows", C.c_int32), ("n_buckets", C.c_int32),
+                ("window_area", C.c_double), ("device_bytes", C.c_size_t)]
+
+
+def photon_params(n_photons, radius, max_depth=8, seed=1, capacity=None, wave_paths=0, queue_rounds=0) -> PhotonParams:
+    cap = int(capacity) if capacity is not None else int(n_photons) * (int(max_depth) - 1)
+    return PhotonParams(int(n_photons), int(max_depth), float(radius), int(seed), max(1, min(cap, 1 << 28)),
+                        int(wave_paths), int(queue_rounds))
+
+
 # Every exported function: (name, restype, argtypes)
 _vp, _i32, _i64, _sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
 SIGNATURES = [
@@ -188,6 +204,15 @@ SIGNATURES = [
     ("sdd_cache_loss", _i32, [_vp, _vp, _vp]),
     ("sdd_render_cached", _i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     ("sdd_cache_get_records", _i32, [_vp, _vp, _i64, _vp, _vp, _vp]),
+    ("sdd_photon_map_bytes", _i32, [_vp, _vp, _vp]),
+    ("sdd_photon_workspace_bytes", _i32, [_vp, _vp, _vp]),
+    ("sdd_photon_map_create", _i32, [_vp, _vp, _vp, _vp, _sz, _vp]),
+    ("sdd_photon_map_destroy", None, [_vp]),
+    ("sdd_photon_map_build", _i32, [_vp, _vp, _vp, _vp, _sz]),
+    ("sdd_photon_map_info", _i32, [_vp, _vp, _vp]),
+    ("sdd_photon_map_records", _i32, [_vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp]),
+    ("sdd_photon_map_load", _i32, [_vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp]),
+    ("sdd_render_photons", _i32, [_vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
 ]
 
 _lib = None
@@ -569,6 +594,23 @@ class Context:
             self.finish()
         return img
 
+    # -- caustic photon map ----------------------------------------------------------------
+    def photon_map(self, scene: Scene, params: PhotonParams, build=True, finish=True):
+        """A caustic photon map for `scene` in a torch device buffer, built at once by default."""
+        m = PhotonMap(self, scene, params)
+        if build:
+            m.build(scene, finish=finish)
+        return m
+
+    def render_photons(self, scene: Scene, pmap, cam: Camera, params: RenderParams, out=None, finish=True):
+        ws = self.workspace(self.workspace_bytes(scene, params))
+        img = out if out is not None else self.torch.empty((scene.n_bins, cam.height, cam.width),
+                                                           dtype=self.torch.float32, device=self.device)
+        self._err(lib().sdd_render_photons(self.handle, scene.handle, pmap.handle, C.byref(cam), C.byref(params),
+                                           C.c_void_p(ws.data_ptr()), ws.numel(), C.c_void_p(img.data_ptr())))
+        if finish:
+            self.finish()
+        return img
 
     def stats(self) -> dict:
         s = Stats()
@@ -671,4 +713,68 @@ class Cache:
     def __del__(self):
         if getattr(self, "handle", None) and _lib is not None:
             _lib.sdd_cache_destroy(self.handle)
+            self.handle = None
+
+
+class PhotonMap:
+    """``sdd_photon_map`` bound to a torch device buffer."""
+
+    def __init__(self, ctx: Context, scene: Scene, params: PhotonParams):
+        torch = ctx.torch
+        self.ctx, self.params, self.n_bins = ctx, params, scene.n_bins
+        b = C.c_size_t()
+        _check(lib().sdd_photon_map_bytes(scene.handle, C.byref(params), C.byref(b)))
+        self.buffer = torch.empty(b.value + 256, dtype=torch.uint8, device=ctx.device)
+        off = (-self.buffer.data_ptr()) % 256
+        h = C.c_void_p()
+        ctx._err(lib().sdd_photon_map_create(ctx.handle, scene.handle, C.byref(params),
+                                             C.c_void_p(self.buffer.data_ptr() + off), b.value, C.byref(h)))
+        self.handle = h
+
+    def workspace_bytes(self, scene: Scene) -> int:
+        b = C.c_size_t()
+        _check(lib().sdd_photon_workspace_bytes(scene.handle, C.byref(self.params), C.byref(b)))
+        return b.value
+
+    def build(self, scene: Scene, finish=True):
+        ws = self.ctx.workspace(self.workspace_bytes(scene))
+        self.ctx._err(lib().sdd_photon_map_build(self.ctx.handle, scene.handle, self.handle,
+                                                 C.c_void_p(ws.data_ptr()), ws.numel()))
+        if finish:
+            self.ctx.finish()
+
+    def info(self) -> dict:
+        i = PhotonInfo()
+        self.ctx._err(lib().sdd_photon_map_info(self.ctx.handle, self.handle, C.byref(i)))
+        return dict(stored=i.stored, dropped=i.dropped, n_windows=i.n_windows, n_buckets=i.n_buckets,
+                    window_area=i.window_area, device_bytes=i.device_bytes)
+
+    def records(self, n=None):
+        """Stored records (any order): pos [n][3], dir [n][3], flux [n][n_bins], id [n], vertex [n]."""
+        if n is None:
+            n = self.info()["stored"]
+        pos = np.empty((n, 3), dtype=np.float32)
+        dr = np.empty((n, 3), dtype=np.float32)
+        fl = np.empty((n, self.n_bins), dtype=np.float32)
+        pid = np.empty(n, dtype=np.int64)
+        vx = np.empty(n, dtype=np.int32)
+        self.ctx._err(lib().sdd_photon_map_records(self.ctx.handle, self.handle, int(n), _ptr(pos), _ptr(dr),
+                                                   _ptr(fl), _ptr(pid), _ptr(vx)))
+        return pos, dr, fl, pid, vx
+
+    def load(self, pos, dirs, flux, pid=None, vertex=None):
+        """Replace the records with host arrays (pos [n][3], dirs [n][3], flux [n][n_bins] float32;
+        pid int64 [n], vertex int32 [n] optional) and rebuild the grid."""
+        pos = np.ascontiguousarray(pos, dtype=np.float32)
+        dirs = np.ascontiguousarray(dirs, dtype=np.float32)
+        flux = np.ascontiguousarray(flux, dtype=np.float32)
+        assert flux.shape == (len(pos), self.n_bins) and dirs.shape == pos.shape == (len(pos), 3)
+        pid = None if pid is None else np.ascontiguousarray(pid, dtype=np.int64)
+        vertex = None if vertex is None else np.ascontiguousarray(vertex, dtype=np.int32)
+        self.ctx._err(lib().sdd_photon_map_load(self.ctx.handle, self.handle, len(pos), _ptr(pos), _ptr(dirs),
+                                                _ptr(flux), _ptr(pid), _ptr(vertex)))
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.sdd_photon_map_destroy(self.handle)
             self.handle = None

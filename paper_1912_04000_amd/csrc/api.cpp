@@ -264,7 +264,7 @@ constexpr int kCacheDepth = 3;
 template <typename Finish>
 int run_paths(sdd_ctx* ctx, const sdd_scene* scene, const sdd_render_params* p, const Launch& L, const DevScene& S,
               const DevWS& w, uint64_t k0, uint32_t n, int& gen, bool timing, const PathMode& pm,
-              const sdd_cache* cache, Finish finish) {
+              const sdd_cache* cache, const PhotonDev* ph, Finish finish) {
   const int rounds = p->queue_rounds ? p->queue_rounds : kDefaultRounds;
   const int D = p->max_depth;
   const bool query = cache && pm.purpose == 0 && D >= kCacheDepth;
@@ -279,6 +279,8 @@ int run_paths(sdd_ctx* ctx, const sdd_scene* scene, const sdd_render_params* p, 
     HIP_TRY(ctx, launch_resolve(L, S, w, d));
     if (scene->hdr.env_nonzero) HIP_TRY(ctx, launch_escape(L, S, w, d));
     if (!last) {
+      // caustic radiance from the photon map at the opaque vertices, before their lobes
+      if (ph) HIP_TRY(ctx, launch_photon_gather(L, S, w, *ph, d));
       HIP_TRY(ctx, launch_shade_opaque(L, S, w, d, D, p->seed, gen, pm));
       if (d < D) HIP_TRY(ctx, launch_shade_glass(L, S, w, d, p->seed, gen, pm));
     }
@@ -328,7 +330,8 @@ static hipError_t accumulate_wavefront(const Launch& L, const DevScene& S, const
 
 int enqueue_frame(sdd_ctx* ctx, const sdd_scene* scene, const std::vector<ViewDesc>& views,
                   const sdd_render_params* p, const Plan& plan, const DevWS& w, uint64_t total, bool timing,
-                  sdd_cache* cache = nullptr, const sdd_train_params* tp = nullptr) {
+                  sdd_cache* cache = nullptr, const sdd_train_params* tp = nullptr,
+                  const PhotonDev* ph = nullptr) {
   const int B = scene->hdr.n_bins;
   const uint32_t W = plan.W;
   DevScene S = device_view(scene);
@@ -351,7 +354,7 @@ int enqueue_frame(sdd_ctx* ctx, const sdd_scene* scene, const std::vector<ViewDe
         (tp->every > 0 ? wavefront % (uint64_t)tp->every == 0 : wavefront == 0)) {
       const uint32_t nt = (uint32_t)tp->train_paths;
       const PathMode train_mode{1u << 24, kCacheDepth, cache->dev.rx, cache->dev.rw};
-      rc = run_paths(ctx, scene, p, L, S, w, cache->train_paths_done, nt, gen, timing, train_mode, cache,
+      rc = run_paths(ctx, scene, p, L, S, w, cache->train_paths_done, nt, gen, timing, train_mode, cache, ph,
                      [&]() -> int {
                        if (timing) record(ctx, ctx->ev_train, ctx->ev_used_train, true);
                        HIP_TRY(ctx, launch_cache_gather(ctx->stream, cache->dev, w, nt, B));
@@ -365,7 +368,7 @@ int enqueue_frame(sdd_ctx* ctx, const sdd_scene* scene, const std::vector<ViewDe
       cache->train_paths_done += nt;
       ctx->acc.train_batches++;
     }
-    rc = run_paths(ctx, scene, p, L, S, w, k0, n, gen, timing, render_mode, cache, [&]() -> int {
+    rc = run_paths(ctx, scene, p, L, S, w, k0, n, gen, timing, render_mode, cache, ph, [&]() -> int {
       if (timing) record(ctx, ctx->ev_shade, ctx->ev_used_shade, true);
       HIP_TRY(ctx, accumulate_wavefront(L, S, w, views, k0, n));
       if (timing) record(ctx, ctx->ev_shade, ctx->ev_used_shade, false);
@@ -378,7 +381,7 @@ int enqueue_frame(sdd_ctx* ctx, const sdd_scene* scene, const std::vector<ViewDe
 }
 
 int render_views(sdd_ctx* ctx, const sdd_scene* scene, std::vector<ViewDesc>& views, const sdd_render_params* p,
-                 void* ws, size_t ws_bytes) {
+                 void* ws, size_t ws_bytes, const PhotonDev* ph = nullptr) {
   const int B = scene->hdr.n_bins;
   uint64_t total = 0;
   for (auto& v : views) {
@@ -400,7 +403,7 @@ int render_views(sdd_ctx* ctx, const sdd_scene* scene, std::vector<ViewDesc>& vi
     HIP_TRY(ctx, launch_fill_u32(ctx->stream, (uint32_t*)&w.ctl->st_paths,
                                  (sizeof(Ctl) - offsetof(Ctl, st_paths)) / 4, 0u));
   ctx->last_ctl = w.ctl;
-  if (!p->use_graph) return enqueue_frame(ctx, scene, views, p, plan, w, total, p->timing != 0);
+  if (!p->use_graph) return enqueue_frame(ctx, scene, views, p, plan, w, total, p->timing != 0, nullptr, nullptr, ph);
 
   // Graph mode: capture the whole launch sequence once, replay it while the call repeats.
   uint64_t key = 1469598103934665603ull;
@@ -412,6 +415,8 @@ int render_views(sdd_ctx* ctx, const sdd_scene* scene, std::vector<ViewDesc>& vi
   key = fnv(key, &scene->hdr, sizeof(scene->hdr));
   key = fnv(key, &ws, sizeof(void*));
   key = fnv(key, &plan.total, sizeof(plan.total));
+  const PhotonDev no_map{};
+  key = fnv(key, ph ? ph : &no_map, sizeof(PhotonDev));
   if (!(ctx->graph_exec && ctx->graph_key == key)) {
     if (ctx->graph_exec) {
       (void)hipGraphExecDestroy(ctx->graph_exec);
@@ -432,7 +437,7 @@ int render_views(sdd_ctx* ctx, const sdd_scene* scene, std::vector<ViewDesc>& vi
       ctx->stream = user;
       return fail(ctx, SDD_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(eb));
     }
-    int rc = enqueue_frame(ctx, scene, views, p, plan, w, total, false);
+    int rc = enqueue_frame(ctx, scene, views, p, plan, w, total, false, nullptr, nullptr, ph);
     hipGraph_t g = nullptr;
     hipError_t ec = hipStreamEndCapture(ctx->stream, &g);
     ctx->stream = user;
@@ -485,6 +490,87 @@ hipError_t scratch_address(int dev, void** out) {
   }
   *out = g_scratch_ptr[dev];
   return hipSuccess;
+}
+
+// ------------------------------------------------------------------------------------------
+// caustic photon map: parameters, buffer layout, device view
+// ------------------------------------------------------------------------------------------
+std::string check_photon_params(const sdd_photon_params* p) {
+  if (!p) return "photon params is null";
+  if (p->n_photons < 1) return "n_photons must be >= 1";
+  if (p->max_depth < 2 || p->max_depth > 64) return "photon max_depth must lie in 2..64";
+  if ((double)p->n_photons * (p->max_depth - 1) >= 4294967296.0)
+    return "n_photons (max_depth - 1) must stay below 2^32";
+  if (!(p->radius > 0.0f) || !std::isfinite(p->radius)) return "radius must be finite > 0";
+  if (p->capacity < 1 || p->capacity > (1ll << 28)) return "capacity must lie in 1..2^28";
+  if (p->wave_paths != 0 && (p->wave_paths < 64 || p->wave_paths > (1 << 26))) return "wave_paths out of range";
+  if (p->queue_rounds < 0 || p->queue_rounds > 256) return "queue_rounds out of range";
+  return "";
+}
+
+uint32_t glass_triangles(const sdd_scene* s) {
+  const SceneHeader& H = s->hdr;
+  const uint8_t* img = s->image.data();
+  const float* gt = (const float*)(img + H.off_gtris);
+  const int32_t* mt = (const int32_t*)(img + H.off_mtype);
+  uint32_t n = 0;
+  for (int64_t t = 0; t < H.n_tri; ++t) {
+    uint32_t m;
+    std::memcpy(&m, gt + 12 * t + 7, 4);
+    n += mt[m] == SDD_MAT_GLASS;
+  }
+  return n;
+}
+
+// Buffer layout of a map: control words, window thresholds and triangles, records (position,
+// direction, flux quads), bucket counts and starts, record indices sorted by bucket.
+void photon_layout(sdd_photon_map* m, const sdd_scene* s, const sdd_photon_params* p) {
+  m->prm = *p;
+  m->B = s->hdr.n_bins;
+  m->Bp = (m->B + 3) & ~3;
+  m->max_win = std::max<uint32_t>(1, glass_triangles(s));
+  uint32_t nb = 1024;
+  while (nb < (1u << 22) && (uint64_t)nb * 2 < (uint64_t)p->capacity) nb <<= 1;
+  m->n_buckets = nb;
+  const size_t rq = 2 + (size_t)m->Bp / 4;
+  size_t o = 0;
+  m->off_ctl = o;    o = a256(o + 256);
+  m->off_thr = o;    o = a256(o + 4ull * m->max_win);
+  m->off_tri = o;    o = a256(o + 4ull * m->max_win);
+  m->off_rec = o;    o = a256(o + 16ull * rq * (size_t)p->capacity);
+  m->off_bcount = o; o = a256(o + 4ull * nb);
+  m->off_bstart = o; o = a256(o + 4ull * (nb + 1));
+  m->off_sorted = o; o = a256(o + 4ull * (size_t)p->capacity);
+  m->total = o;
+}
+
+PhotonDev photon_dev(const sdd_photon_map* m) {
+  PhotonDev P;
+  std::memset(&P, 0, sizeof(P));
+  uint8_t* b = (uint8_t*)m->buf;
+  P.ctl = (uint32_t*)(b + m->off_ctl);
+  P.win_thr = (const uint32_t*)(b + m->off_thr);
+  P.win_tri = (const uint32_t*)(b + m->off_tri);
+  P.rec = (float4*)(b + m->off_rec);
+  P.bcount = (uint32_t*)(b + m->off_bcount);
+  P.bstart = (uint32_t*)(b + m->off_bstart);
+  P.sorted = (uint32_t*)(b + m->off_sorted);
+  P.n_win = (uint32_t)m->thr.size();
+  P.cap = (uint32_t)m->prm.capacity;
+  P.n_buckets = m->n_buckets;
+  P.rq = 2 + (uint32_t)m->Bp / 4;
+  P.radius = m->prm.radius;
+  P.inv_cell = (float)(1.0 / (2.0 * (double)m->prm.radius));
+  P.flux_scale = (float)(m->area / (double)m->prm.n_photons);
+  P.seed_lo = (uint32_t)m->prm.seed;
+  P.seed_hi = (uint32_t)(m->prm.seed >> 32);
+  P.max_depth = m->prm.max_depth;
+  return P;
+}
+
+uint32_t photon_wave(const sdd_photon_params* p) {
+  const uint64_t W = p->wave_paths ? (uint64_t)p->wave_paths : (uint64_t)kDefaultWave;
+  return (uint32_t)std::max<uint64_t>(64, std::min<uint64_t>(W, (uint64_t)p->n_photons));
 }
 
 }  // namespace
@@ -850,6 +936,240 @@ int sdd_spectral_to_srgb(sdd_ctx* c, const float* image, int32_t n_bins, float l
   HIP_TRY(c, hipSetDevice(c->device));
   HIP_TRY(c, launch_spectral_to_srgb(c->stream, image, n_bins, lmin, lmax, (uint64_t)n_pixels, exposure, xyz, srgb));
   return SDD_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// caustic photon map
+// ------------------------------------------------------------------------------------------
+int sdd_photon_map_bytes(const sdd_scene* s, const sdd_photon_params* p, size_t* bytes) {
+  if (!s || !bytes) return fail(nullptr, SDD_ERR_INVALID_ARG, "null argument");
+  const std::string e = check_photon_params(p);
+  if (!e.empty()) return fail(nullptr, SDD_ERR_INVALID_ARG, e);
+  sdd_photon_map m;
+  photon_layout(&m, s, p);
+  *bytes = m.total;
+  return SDD_OK;
+}
+
+int sdd_photon_workspace_bytes(const sdd_scene* s, const sdd_photon_params* p, size_t* bytes) {
+  if (!s || !bytes) return fail(nullptr, SDD_ERR_INVALID_ARG, "null argument");
+  const std::string e = check_photon_params(p);
+  if (!e.empty()) return fail(nullptr, SDD_ERR_INVALID_ARG, e);
+  *bytes = make_plan(photon_wave(p), s->hdr.n_bins, s->hdr.n_cells, 1).total;
+  return SDD_OK;
+}
+
+int sdd_photon_map_create(sdd_ctx* c, const sdd_scene* s, const sdd_photon_params* p, void* buf, size_t bytes,
+                          sdd_photon_map** out) {
+  if (!c) return fail(nullptr, SDD_ERR_INVALID_ARG, "ctx is null");
+  if (!s || !buf || !out) return fail(c, SDD_ERR_INVALID_ARG, "null argument");
+  *out = nullptr;
+  const std::string e = check_photon_params(p);
+  if (!e.empty()) return fail(c, SDD_ERR_INVALID_ARG, e);
+  if (((uintptr_t)buf & 255) != 0) return fail(c, SDD_ERR_INVALID_ARG, "photon map buffer must be 256-byte aligned");
+  sdd_photon_map* m = new (std::nothrow) sdd_photon_map();
+  if (!m) return fail(c, SDD_ERR_INTERNAL, "out of host memory");
+  photon_layout(m, s, p);
+  if (bytes < m->total) {
+    delete m;
+    return fail(c, SDD_ERR_WORKSPACE, "photon map buffer smaller than sdd_photon_map_bytes");
+  }
+  m->buf = buf;
+  m->bytes = bytes;
+  m->device = c->device;
+  *out = m;
+  return SDD_OK;
+}
+
+void sdd_photon_map_destroy(sdd_photon_map* m) { delete m; }
+
+int sdd_photon_map_build(sdd_ctx* c, const sdd_scene* s, sdd_photon_map* m, void* ws, size_t ws_bytes) {
+  if (!c) return fail(nullptr, SDD_ERR_INVALID_ARG, "ctx is null");
+  int rc = scene_ready(c, s);
+  if (rc) return rc;
+  if (!m) return fail(c, SDD_ERR_INVALID_ARG, "photon map is null");
+  if (m->device != c->device) return fail(c, SDD_ERR_INVALID_ARG, "photon map was created on another device");
+  if (s->hdr.n_bins != m->B) return fail(c, SDD_ERR_NOT_READY, "scene bins differ from the photon map's");
+  if (glass_triangles(s) > m->max_win) return fail(c, SDD_ERR_INVALID_ARG, "scene has more glass than the photon map");
+  // the grid's integer cell coordinates must stay far from overflow
+  const double inv_cell = 1.0 / (2.0 * (double)m->prm.radius);
+  for (int a = 0; a < 3; ++a)
+    if (std::max(std::fabs(s->info.grid_lo[a]), std::fabs(s->info.grid_hi[a])) * inv_cell > 1e9)
+      return fail(c, SDD_ERR_INVALID_ARG, "photon radius too small for the scene's extent");
+  const uint32_t W = photon_wave(&m->prm);
+  Plan plan = make_plan(W, m->B, s->hdr.n_cells, 1);
+  if (!ws) return fail(c, SDD_ERR_INVALID_ARG, "workspace is null");
+  if (ws_bytes < plan.total)
+    return fail(c, SDD_ERR_WORKSPACE,
+                "workspace too small: need " + std::to_string(plan.total) + " bytes, got " + std::to_string(ws_bytes));
+  HIP_TRY(c, hipSetDevice(c->device));
+  // Windows: glass triangles with their projected areas on the scene's unit sun direction (FP32
+  // as stored), in FP64, and the integer thresholds of the emission choice.
+  const SceneHeader& H = s->hdr;
+  const float* gt = (const float*)(s->image.data() + H.off_gtris);
+  const int32_t* mt = (const int32_t*)(s->image.data() + H.off_mtype);
+  const double sx = H.sun[0], sy = H.sun[1], sz = H.sun[2];
+  std::vector<double> cdf{0.0};
+  // the previous build's copies out of these vectors must be complete before they change
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  m->thr.clear();
+  m->tri.clear();
+  for (int64_t t = 0; t < H.n_tri; ++t) {
+    const float* v = gt + 12 * t;
+    uint32_t mat;
+    std::memcpy(&mat, v + 7, 4);
+    if (mt[mat] != SDD_MAT_GLASS) continue;
+    const double ax = (double)v[4] - v[0], ay = (double)v[5] - v[1], az = (double)v[6] - v[2];
+    const double bx = (double)v[8] - v[0], by = (double)v[9] - v[1], bz = (double)v[10] - v[2];
+    const double nx = ay * bz - az * by, ny = az * bx - ax * bz, nz = ax * by - ay * bx;
+    const double a = 0.5 * std::fabs(nx * sx + ny * sy + nz * sz);
+    if (!(a > 0.0)) continue;
+    m->tri.push_back((uint32_t)t);
+    cdf.push_back(cdf.back() + a);
+  }
+  m->area = cdf.back();
+  m->thr.resize(m->tri.size());
+  for (size_t w = 0; w < m->tri.size(); ++w) m->thr[w] = (uint32_t)std::floor(cdf[w] / m->area * 16777216.0);
+  PhotonDev P = photon_dev(m);
+  HIP_TRY(c, launch_fill_u32(c->stream, P.ctl, 64, 0u));
+  if (!m->tri.empty()) {
+    HIP_TRY(c, hipMemcpyAsync((void*)P.win_thr, m->thr.data(), 4 * m->thr.size(), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync((void*)P.win_tri, m->tri.data(), 4 * m->tri.size(), hipMemcpyHostToDevice, c->stream));
+    DevWS w = ws_view(plan, ws);
+    if (c->last_ctl != w.ctl)
+      HIP_TRY(c, launch_fill_u32(c->stream, (uint32_t*)&w.ctl->st_paths, (sizeof(Ctl) - offsetof(Ctl, st_paths)) / 4, 0u));
+    c->last_ctl = w.ctl;
+    HIP_TRY(c, launch_fill_u32(c->stream, (uint32_t*)w.ctl, offsetof(Ctl, st_paths) / 4, 0u));
+    HIP_TRY(c, launch_fill_u32(c->stream, w.ccount, 2ull * H.n_cells * kDirBins * kKeyStride, 0u));
+    DevScene S = device_view(s);
+    Launch L{c->stream, plan.trace_blocks};
+    const int rounds = m->prm.queue_rounds ? m->prm.queue_rounds : kDefaultRounds;
+    const int D = m->prm.max_depth;
+    int gen = 0;
+    const uint64_t N = (uint64_t)m->prm.n_photons;
+    for (uint64_t k0 = 0; k0 < N; k0 += W) {
+      const uint32_t n = (uint32_t)std::min<uint64_t>(W, N - k0);
+      HIP_TRY(c, launch_fill_u32(c->stream, &w.ctl->cat_count[0][0], 2 * 8 * kKeyStride, 0u));
+      HIP_TRY(c, launch_fill_u32(c->stream, (uint32_t*)w.catb, ((size_t)2 * w.W + 3) / 4, 0u));
+      // emission and the way from the window to the sun
+      HIP_TRY(c, launch_photon_gen(L, S, w, P, k0, n, gen));
+      rc = trace_phase(c, L, S, w, gen, rounds, 1, false);
+      if (rc) return rc;
+      HIP_TRY(c, launch_photon_vis(L, S, w, P, 1));
+      for (int d = 1; d <= D; ++d) {
+        HIP_TRY(c, launch_photon_shade(L, S, w, P, d, gen));
+        if (d == D) break;
+        rc = trace_phase(c, L, S, w, gen, rounds, (d + 1) & 1, false);
+        if (rc) return rc;
+      }
+    }
+  }
+  HIP_TRY(c, launch_photon_build(c->stream, P));
+  m->built = true;
+  return SDD_OK;
+}
+
+int sdd_photon_map_info(sdd_ctx* c, sdd_photon_map* m, sdd_photon_info* out) {
+  if (!c) return fail(nullptr, SDD_ERR_INVALID_ARG, "ctx is null");
+  if (!m || !out) return fail(c, SDD_ERR_INVALID_ARG, "null argument");
+  std::memset(out, 0, sizeof(*out));
+  out->n_buckets = (int32_t)m->n_buckets;
+  out->device_bytes = m->total;
+  if (!m->built) return SDD_OK;
+  HIP_TRY(c, hipSetDevice(c->device));
+  uint32_t h[2];
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  HIP_TRY(c, hipMemcpy(h, (uint8_t*)m->buf + m->off_ctl, sizeof(h), hipMemcpyDeviceToHost));
+  out->stored = std::min<int64_t>(h[0], m->prm.capacity);
+  out->dropped = h[1];
+  out->n_windows = (int32_t)m->tri.size();
+  out->window_area = m->area;
+  return SDD_OK;
+}
+
+int sdd_photon_map_records(sdd_ctx* c, sdd_photon_map* m, int64_t n, float* pos, float* dir, float* flux, int64_t* id,
+                           int32_t* vertex) {
+  if (!c) return fail(nullptr, SDD_ERR_INVALID_ARG, "ctx is null");
+  if (!m || n < 0) return fail(c, SDD_ERR_INVALID_ARG, "bad argument");
+  if (!m->built) return fail(c, SDD_ERR_NOT_READY, "photon map has not been built");
+  sdd_photon_info info;
+  int rc = sdd_photon_map_info(c, m, &info);
+  if (rc) return rc;
+  if (n > info.stored) return fail(c, SDD_ERR_INVALID_ARG, "more records asked for than the map holds");
+  if (n == 0) return SDD_OK;
+  const size_t rq = 2 + (size_t)m->Bp / 4;
+  std::vector<float> h((size_t)n * rq * 4);
+  HIP_TRY(c, hipMemcpy(h.data(), (uint8_t*)m->buf + m->off_rec, h.size() * 4, hipMemcpyDeviceToHost));
+  for (int64_t r = 0; r < n; ++r) {
+    const float* q = h.data() + (size_t)r * rq * 4;
+    uint32_t lo, hi;
+    std::memcpy(&lo, q + 3, 4);
+    std::memcpy(&hi, q + 7, 4);
+    if (pos) for (int a = 0; a < 3; ++a) pos[3 * r + a] = q[a];
+    if (dir) for (int a = 0; a < 3; ++a) dir[3 * r + a] = q[4 + a];
+    if (flux) for (int j = 0; j < m->B; ++j) flux[(size_t)r * m->B + j] = q[8 + j];
+    if (id) id[r] = (int64_t)((uint64_t)lo | ((uint64_t)(hi >> 8) << 32));
+    if (vertex) vertex[r] = (int32_t)(hi & 0xFFu);
+  }
+  return SDD_OK;
+}
+
+int sdd_photon_map_load(sdd_ctx* c, sdd_photon_map* m, int64_t n, const float* pos, const float* dir, const float* flux,
+                        const int64_t* id, const int32_t* vertex) {
+  if (!c) return fail(nullptr, SDD_ERR_INVALID_ARG, "ctx is null");
+  if (!m || n < 0 || n > m->prm.capacity) return fail(c, SDD_ERR_INVALID_ARG, "bad argument (0 <= n <= capacity)");
+  if (n > 0 && (!pos || !dir || !flux)) return fail(c, SDD_ERR_INVALID_ARG, "null record arrays");
+  const size_t rq = 2 + (size_t)m->Bp / 4;
+  std::vector<float> h((size_t)n * rq * 4, 0.0f);
+  for (int64_t r = 0; r < n; ++r) {
+    float* q = h.data() + (size_t)r * rq * 4;
+    for (int a = 0; a < 3; ++a) {
+      q[a] = pos[3 * r + a];
+      q[4 + a] = dir[3 * r + a];
+      if (!std::isfinite(q[a]) || !std::isfinite(q[4 + a]))
+        return fail(c, SDD_ERR_INVALID_ARG, "non-finite record position or direction");
+    }
+    const uint64_t pid = id ? (uint64_t)id[r] : 0;
+    const uint32_t lo = (uint32_t)pid, hi = (uint32_t)(vertex ? vertex[r] & 0xFF : 0) | (uint32_t)(pid >> 32) << 8;
+    std::memcpy(q + 3, &lo, 4);
+    std::memcpy(q + 7, &hi, 4);
+    for (int j = 0; j < m->B; ++j) q[8 + j] = flux[(size_t)r * m->B + j];
+  }
+  const uint32_t ctl[2] = {(uint32_t)n, 0u};
+  HIP_TRY(c, hipSetDevice(c->device));
+  if (n > 0)
+    HIP_TRY(c, hipMemcpyAsync((uint8_t*)m->buf + m->off_rec, h.data(), h.size() * 4, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync((uint8_t*)m->buf + m->off_ctl, ctl, sizeof(ctl), hipMemcpyHostToDevice, c->stream));
+  const PhotonDev P = photon_dev(m);
+  HIP_TRY(c, launch_photon_build(c->stream, P));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));  // the host staging above is freed on return
+  m->built = true;
+  return SDD_OK;
+}
+
+int sdd_render_photons(sdd_ctx* c, const sdd_scene* s, const sdd_photon_map* m, const sdd_camera* cam,
+                       const sdd_render_params* p, void* ws, size_t ws_bytes, float* image) {
+  if (!c) return fail(nullptr, SDD_ERR_INVALID_ARG, "ctx is null");
+  int rc = scene_ready(c, s);
+  if (rc) return rc;
+  if (!cam || !image || !m) return fail(c, SDD_ERR_INVALID_ARG, "null camera, image or photon map");
+  std::string e = check_params(p);
+  if (!e.empty()) return fail(c, SDD_ERR_INVALID_ARG, e);
+  if (p->mode != SDD_MODE_PLAIN) return fail(c, SDD_ERR_INVALID_ARG, "sdd_render_photons renders in plain mode");
+  if (!m->built) return fail(c, SDD_ERR_NOT_READY, "photon map has not been built");
+  if (m->device != c->device) return fail(c, SDD_ERR_INVALID_ARG, "photon map was created on another device");
+  if (m->B != s->hdr.n_bins) return fail(c, SDD_ERR_NOT_READY, "scene bins differ from the photon map's");
+  std::vector<ViewDesc> views(1);
+  e = make_view(*cam, &views[0]);
+  if (!e.empty()) return fail(c, SDD_ERR_INVALID_ARG, e);
+  views[0].spp = p->spp;
+  views[0].inv_spp = 1.0f / (float)p->spp;
+  views[0].image = image;
+  views[0].view_id = p->view;
+  views[0].first_sample = (uint32_t)p->first_sample;
+  HIP_TRY(c, hipSetDevice(c->device));
+  const PhotonDev P = photon_dev(m);
+  return render_views(c, s, views, p, ws, ws_bytes, &P);
 }
 
 int sdd_finish(sdd_ctx* c) {

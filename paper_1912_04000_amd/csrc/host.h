@@ -47,6 +47,20 @@ struct sdd_cache {
   uint64_t train_paths_done = 0;
 };
 
+struct sdd_photon_map {
+  sdd_photon_params prm;
+  int B = 0, Bp = 0;
+  uint32_t max_win = 0;        // window slots (the scene's glass triangles)
+  uint32_t n_buckets = 0;
+  void* buf = nullptr;
+  size_t bytes = 0;
+  int device = -1;
+  size_t off_ctl = 0, off_thr = 0, off_tri = 0, off_rec = 0, off_bcount = 0, off_bstart = 0, off_sorted = 0, total = 0;
+  std::vector<uint32_t> thr, tri;  // windows of the last build (kept alive for its copies)
+  double area = 0.0;
+  bool built = false;
+};
+
 namespace sdd {
 
 // Builds the cell-decomposed scene image. Returns an empty string on success, else the reason.

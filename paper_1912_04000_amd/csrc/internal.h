@@ -233,6 +233,24 @@ struct PathMode {
   float4* rec_w;       // [W] (direction toward the previous vertex, valid)
 };
 
+// Device view of a caustic photon map (a caller buffer laid out by the host): the window table
+// of the emission, the stored photon records and a hashed uniform grid over them (cell size twice
+// the gather radius, counting-sorted).
+struct PhotonDev {
+  uint32_t* ctl;              // [0] photons stored (may exceed cap), [1] photons dropped
+  const uint32_t* win_thr;    // [n_win] integer thresholds floor(cdf_w / A 2^24)
+  const uint32_t* win_tri;    // [n_win] window triangle ids
+  float4* rec;                // [cap][rq]: (pos, id lo bits) (dir, vertex | id hi << 8) flux quads
+  uint32_t* bcount;           // [n_buckets] photons per bucket, then scatter cursors
+  uint32_t* bstart;           // [n_buckets + 1] first record of each bucket in `sorted`
+  uint32_t* sorted;           // [cap] record indices ordered by bucket
+  uint32_t n_win, cap, n_buckets, rq;  // rq = 2 + Bp / 4 float4 per record
+  float radius, inv_cell;     // gather radius, 1 / (2 radius)
+  float flux_scale;           // A / N: flux of a photon per unit of sun irradiance
+  uint32_t seed_lo, seed_hi;
+  int32_t max_depth;
+};
+
 // Host helpers implemented in the kernels' translation unit.
 struct Launch {
   hipStream_t stream;
@@ -261,6 +279,14 @@ hipError_t launch_unpack_hits(const Launch& L, const DevScene& S, const DevWS& w
                               float* u, float* v);
 hipError_t launch_resolve_vis(const Launch& L, const DevScene& S, const DevWS& w, uint32_t n, float* vis);
 hipError_t launch_philox(hipStream_t s, const uint32_t ctr[4], const uint32_t key[2], uint64_t n, uint32_t* out);
+// caustic photon map
+hipError_t launch_photon_gen(const Launch& L, const DevScene& S, const DevWS& w, const PhotonDev& P, uint64_t k0,
+                             uint32_t n, int gen);
+hipError_t launch_photon_vis(const Launch& L, const DevScene& S, const DevWS& w, const PhotonDev& P, int par);
+hipError_t launch_photon_shade(const Launch& L, const DevScene& S, const DevWS& w, const PhotonDev& P, int depth,
+                               int gen);
+hipError_t launch_photon_build(hipStream_t s, const PhotonDev& P);
+hipError_t launch_photon_gather(const Launch& L, const DevScene& S, const DevWS& w, const PhotonDev& P, int depth);
 
 // colorimetry (color.hip)
 hipError_t launch_spectral_to_srgb(hipStream_t s, const float* img, int B, float lmin, float lmax, uint64_t n,

@@ -1786,6 +1786,405 @@ __global__ __launch_bounds__(kWG) void k_accumulate(DevScene S, DevWS w, uint32_
 // ==========================================================================================
 // host-side launchers
 // ==========================================================================================
+// ==========================================================================================
+// caustic photon map (section 4: photon maps filled from the light sources, one for caustics)
+// ==========================================================================================
+// Photon i of the map: random-number counter (i, i >> 32, vertex | 4 << 24, 0) -- purpose 4. The
+// slot's pix / smp words hold the photon index, its view word the photon's flags (bit 0: it has
+// been reflected, by a glass face or a mirror lobe).
+constexpr uint32_t kPhotonPurpose = 4u << 24;
+constexpr uint32_t kPhotonReflected = 1u;
+
+// Emission: the window (glass triangle) whose integer threshold is the last not above the 24-bit
+// random integer, a uniform point p on it, flux E_j A / N; the photon's first vertex is p (its
+// ray from p + w_s toward -w_s, hit record at distance 1 on that triangle), and its incoming
+// visibility is a shadow ray from p toward the sun, offset to the sun's side and skipping the
+// window, queued like any shadow ray.
+__global__ __launch_bounds__(kWG) void k_photon_gen(DevScene S, DevWS w, PhotonDev P, uint64_t k0, uint32_t n,
+                                                    int gen) {
+  __shared__ float s_planes[3 * (kMaxGrid + 1)];
+  for (int q = threadIdx.x; q < S.gx + S.gy + S.gz + 3; q += kWG) s_planes[q] = S.planes[q];
+  __syncthreads();
+  const uint32_t i = blockIdx.x * kWG + threadIdx.x;
+  const bool valid = i < n;
+  uint32_t cell = kInvalidCell, qdir = 0;
+  if (valid) {
+    const uint64_t id = k0 + i;
+    const uint32_t c0 = (uint32_t)id, c1 = (uint32_t)(id >> 32);
+    const uint4 rn = philox(make_uint4(c0, c1, kPhotonPurpose, 0u), P.seed_lo, P.seed_hi);
+    const uint32_t x24 = rn.x >> 8;
+    uint32_t lo = 0, hi = P.n_win;  // the last window whose threshold <= x24 (thr[0] = 0)
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (P.win_thr[mid] <= x24) lo = mid; else hi = mid;
+    }
+    const uint32_t tri = P.win_tri[lo];
+    const float4* g = S.gtris + (size_t)tri * 3;
+    const float4 A = g[0], B = g[1], C = g[2];
+    const F3 v0 = f3(A.x, A.y, A.z), v1 = f3(B.x, B.y, B.z), v2 = f3(C.x, C.y, C.z);
+    const float r = sqrtf(unif24(rn.y)), u2 = unif24(rn.z);
+    const float bu = r * (1.0f - u2), bv = r * u2;
+    const F3 p = v0 * (1.0f - bu - bv) + v1 * bu + v2 * bv;
+    const F3 sun = f3(S.sun[0], S.sun[1], S.sun[2]);
+    const F3 d = sun * -1.0f;
+    const F3 o1 = p + sun;
+    w.rays[2 * i] = make_float4(o1.x, o1.y, o1.z, __int_as_float(-1));
+    w.rays[2 * i + 1] = make_float4(d.x, d.y, d.z, __uint_as_float(i));
+    w.hit[i] = make_float4(1.0f, __uint_as_float(tri), 0.0f, 0.0f);
+    const F3 ng = geo_normal(v0, v1, v2);
+    const F3 nn = dot_exact_sign(d, ng) > 0.0f ? ng * -1.0f : ng;
+    const F3 so = p + nn * (1e-5f * (1.0f + maxabs3(p)));
+    w.rays[2 * ((size_t)w.W + i)] = make_float4(so.x, so.y, so.z, __uint_as_float(tri));
+    w.rays[2 * ((size_t)w.W + i) + 1] = make_float4(sun.x, sun.y, sun.z, __uint_as_float(i | kShadowBit));
+    w.shcnt[i] = 0;
+    w.pix[i] = c0;
+    w.smp[i] = c1;
+    w.view[i] = 0;
+    float4* b4 = (float4*)(w.beta + (size_t)i * w.Bp);
+    const float4* e4 = (const float4*)S.sunE;
+    for (int q = 0; q < w.Bp / 4; ++q) {
+      const float4 e = e4[q];
+      b4[q] = make_float4(e.x * P.flux_scale, e.y * P.flux_scale, e.z * P.flux_scale, e.w * P.flux_scale);
+    }
+    cell = start_cell_pl(S, s_planes, so, sun);
+    qdir = dir_bin(sun);
+  }
+  const int gp = gen & 1;
+  const bool in_grid = valid && cell != kInvalidCell;
+  const uint32_t key = in_grid ? qkey(cell, qdir) : kNoKey;
+  const uint32_t rank = wave_key_rank(in_grid, key, ccount_of(S, w, gp));
+  if (valid) {
+    w.lsrc[i] = (w.W + i) | kFirstVisit;
+    w.ldst[i] = key;
+    w.lrank[i] = rank;
+    // a shadow ray that starts outside the grid reaches the sun at once
+    if (!in_grid) w.catb[(size_t)w.W + i] = (uint8_t)(kCatShadowClear + 1);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) w.ctl->list_count[gp] = n;
+}
+
+// Incoming visibility of the photons: blocked ones are gone; through glass the flux takes the
+// slabs' transmittance. The live photons become the glass vertices of the first bounce.
+__global__ __launch_bounds__(kWG) void k_photon_vis(DevScene S, DevWS w, PhotonDev P, int par) {
+  const uint32_t n_clear = w.ctl->cat_count[par][kCatShadowClear * kKeyStride];
+  const uint32_t n_glass = w.ctl->cat_count[par][kCatShadowGlass * kKeyStride];
+  const uint32_t n = n_clear + n_glass;
+  const int Bp = w.Bp, nq = Bp / 4;
+  if (blockIdx.x == 0 && threadIdx.x < kCats) w.ctl->cat_count[par ^ 1][threadIdx.x * kKeyStride] = 0;
+  const uint32_t n_iter = (n + kWG - 1) / kWG * kWG;
+  for (uint32_t i = blockIdx.x * kWG + threadIdx.x; i < n_iter; i += gridDim.x * kWG) {
+    const bool valid = i < n;
+    uint32_t s = 0;
+    if (valid && i >= n_clear) {
+      s = cat_list(w, par, kCatShadowGlass)[i - n_clear];
+      const uint32_t nc = min(w.shcnt[s], (uint32_t)kMaxCross);
+      int mq[kMaxCross], tx[kMaxCross];
+      float cq[kMaxCross], sq[kMaxCross], tq[kMaxCross];
+      crossings(S, w, s, nc, mq, cq, tx, sq, tq);
+      const float4* lam = (const float4*)S.lambda;
+      row_update<12>((float4*)(w.beta + (size_t)s * Bp), nq, [&](int q, float4 b) {
+        const float4 la = lam[q];
+        for (int c = 0; c < kMaxCross; ++c) {
+          if ((uint32_t)c < nc) {
+            const int m = mq[c];
+            const float4 nn = ((const float4*)(S.ntab + m * Bp))[q], kk = ((const float4*)(S.ktab + m * Bp))[q];
+            float R0, T0, R1, T1, R2, T2, R3, T3;
+            if (tx[c] >= 0) {
+              const float4 t4 = tex_quad(tex_tap(S, tx[c], sq[c], tq[c]), q);
+              slab_tau0(nn.x, kk.x, t4.x, cq[c], R0, T0);
+              slab_tau0(nn.y, kk.y, t4.y, cq[c], R1, T1);
+              slab_tau0(nn.z, kk.z, t4.z, cq[c], R2, T2);
+              slab_tau0(nn.w, kk.w, t4.w, cq[c], R3, T3);
+            } else {
+              slab(nn.x, kk.x, la.x, S.thick[m], cq[c], R0, T0);
+              slab(nn.y, kk.y, la.y, S.thick[m], cq[c], R1, T1);
+              slab(nn.z, kk.z, la.z, S.thick[m], cq[c], R2, T2);
+              slab(nn.w, kk.w, la.w, S.thick[m], cq[c], R3, T3);
+            }
+            b = make_float4(b.x * T0, b.y * T1, b.z * T2, b.w * T3);
+          }
+        }
+        return b;
+      });
+    } else if (valid) {
+      s = cat_list(w, par, kCatShadowClear)[i];
+    }
+    wave_push(valid, s, &w.ctl->cat_count[par][kCatGlass * kKeyStride], cat_list(w, par, kCatGlass));
+  }
+}
+
+// One photon vertex per thread, opaque vertices first (produced entries 0 .. n_opaque), then glass
+// (n_opaque .. n_opaque + n_glass): the same lobe rules as camera paths, no direct term. An opaque
+// vertex stores the photon when it has been reflected before, then takes the mirror lobe or ends
+// (a diffuse bounce leaves the caustic paths); vertex max_depth scatters nothing.
+__global__ __launch_bounds__(kWG) void k_photon_shade(DevScene S, DevWS w, PhotonDev P, int depth, int gen) {
+  __shared__ float s_planes[3 * (kMaxGrid + 1)];
+  for (int q = threadIdx.x; q < S.gx + S.gy + S.gz + 3; q += kWG) s_planes[q] = S.planes[q];
+  __syncthreads();
+  const int p = depth & 1, gp = gen & 1;
+  const uint32_t n_op = w.ctl->cat_count[p][kCatOpaque * kKeyStride];
+  const uint32_t n_gl = w.ctl->cat_count[p][kCatGlass * kKeyStride];
+  const uint32_t n = n_op + n_gl;
+  const int B = S.n_bins, Bp = w.Bp, nq = Bp / 4;
+  if (blockIdx.x == 0 && threadIdx.x == 0) w.ctl->list_count[gp] = n;
+  if (blockIdx.x == 0 && threadIdx.x < kCats) w.ctl->cat_count[p ^ 1][threadIdx.x * kKeyStride] = 0;
+  const bool last = depth >= P.max_depth;
+  const uint32_t n_iter = (n + kWG - 1) / kWG * kWG;
+  for (uint32_t a = blockIdx.x * kWG + threadIdx.x; a < n_iter; a += gridDim.x * kWG) {
+    const bool valid = a < n;
+    uint32_t s = 0, cell = kInvalidCell, qd = 0;
+    if (valid) {
+      const bool opaque = a < n_op;
+      s = opaque ? cat_list(w, p, kCatOpaque)[a] : cat_list(w, p, kCatGlass)[a - n_op];
+      const Vertex V = load_vertex(S, w, s);
+      const uint32_t flags = w.view[s];
+      const uint4 rn = philox(make_uint4(w.pix[s], w.smp[s], (uint32_t)depth | kPhotonPurpose, 0u), P.seed_lo,
+                              P.seed_hi);
+      const float u0 = unif24(rn.x);
+      float4* brow = (float4*)(w.beta + (size_t)s * Bp);
+      const float4* nt = (const float4*)(S.ntab + V.m * Bp);
+      const float4* kt = (const float4*)(S.ktab + V.m * Bp);
+      bool cont = false, refl = false;
+      if (opaque) {
+        // the photons stored by the wave's active lanes take consecutive records (one atomic per
+        // wave); the flux is the throughput on arrival, before this vertex's lobe
+        const bool store = (flags & kPhotonReflected) != 0;
+        const uint64_t m = __ballot(store);
+        if (m) {
+          const uint32_t leader = (uint32_t)__ffsll((unsigned long long)m) - 1u;
+          uint32_t base = 0;
+          if (lane_id() == leader) base = atomicAdd(&P.ctl[0], (uint32_t)__popcll(m));
+          base = __shfl(base, (int)leader);
+          const uint32_t r = base + count_below(m);
+          const uint64_t lost = __ballot(store && r >= P.cap);
+          if (lost && lane_id() == leader) atomicAdd(&P.ctl[1], (uint32_t)__popcll(lost));
+          if (store && r < P.cap) {
+            float4* rec = P.rec + (size_t)r * P.rq;
+            rec[0] = make_float4(V.p.x, V.p.y, V.p.z, __uint_as_float(w.pix[s]));
+            rec[1] = make_float4(V.d.x, V.d.y, V.d.z, __uint_as_float((uint32_t)depth | (w.smp[s] << 8)));
+            for (int q = 0; q < nq; ++q) rec[2 + q] = brow[q];
+          }
+        }
+        if (!last) {
+          const float4* rt = (const float4*)(S.rho + V.m * Bp);
+          float a_ = 0.0f, b_ = 0.0f;
+          for (int q = 0; q < nq; ++q) {
+            const float4 nn = nt[q], kk = kt[q], rr = rt[q];
+            const float F4[4] = {fresnel(nn.x, kk.x, V.cos_o), fresnel(nn.y, kk.y, V.cos_o),
+                                 fresnel(nn.z, kk.z, V.cos_o), fresnel(nn.w, kk.w, V.cos_o)};
+            const float R4[4] = {rr.x, rr.y, rr.z, rr.w};
+            for (int c = 0; c < 4; ++c)
+              if (4 * q + c < B) {
+                a_ += F4[c];
+                b_ += (1.0f - F4[c]) * R4[c];
+              }
+          }
+          a_ /= (float)B;
+          b_ /= (float)B;
+          if (a_ + b_ > 0.0f) {
+            const float Ps = a_ / (a_ + b_);
+            if (u0 < Ps) {
+              const float inv = 1.0f / Ps;
+              row_update<8>(brow, nq, [&](int q, float4 b) {
+                const float4 nn = nt[q], kk = kt[q];
+                return make_float4(b.x * fresnel(nn.x, kk.x, V.cos_o) * inv, b.y * fresnel(nn.y, kk.y, V.cos_o) * inv,
+                                   b.z * fresnel(nn.z, kk.z, V.cos_o) * inv, b.w * fresnel(nn.w, kk.w, V.cos_o) * inv);
+              });
+              cont = refl = true;
+            }
+          }
+        }
+      } else if (!last) {
+        const float4* lam = (const float4*)S.lambda;
+        const float th = S.thick[V.m];
+        const int tx = S.n_tex > 0 ? S.mtex[V.m] : -1;
+        TexTap tap;
+        tap.base = nullptr;
+        tap.r00 = tap.r10 = tap.r01 = tap.r11 = 0;
+        tap.fx = tap.fy = 0.0f;
+        if (tx >= 0) {
+          float ss, tt;
+          hit_st(S, V.id, V.bu, V.bv, ss, tt);
+          tap = tex_tap(S, tx, ss, tt);
+        }
+        auto slab4 = [&](int q, float (&R)[4], float (&T)[4]) {
+          const float4 nn = nt[q], kk = kt[q], la = lam[q];
+          if (tx >= 0) {
+            const float4 t4 = tex_quad(tap, q);
+            slab_tau0(nn.x, kk.x, t4.x, V.cos_o, R[0], T[0]);
+            slab_tau0(nn.y, kk.y, t4.y, V.cos_o, R[1], T[1]);
+            slab_tau0(nn.z, kk.z, t4.z, V.cos_o, R[2], T[2]);
+            slab_tau0(nn.w, kk.w, t4.w, V.cos_o, R[3], T[3]);
+          } else {
+            slab(nn.x, kk.x, la.x, th, V.cos_o, R[0], T[0]);
+            slab(nn.y, kk.y, la.y, th, V.cos_o, R[1], T[1]);
+            slab(nn.z, kk.z, la.z, th, V.cos_o, R[2], T[2]);
+            slab(nn.w, kk.w, la.w, th, V.cos_o, R[3], T[3]);
+          }
+        };
+        float mr = 0.0f, mt = 0.0f;
+        for (int q = 0; q < nq; ++q) {
+          float R[4], T[4];
+          slab4(q, R, T);
+          for (int c = 0; c < 4; ++c)
+            if (4 * q + c < B) {
+              mr += R[c];
+              mt += T[c];
+            }
+        }
+        const float Pr = mr / (mr + mt);
+        refl = u0 < Pr;
+        const float inv = refl ? 1.0f / Pr : 1.0f / (1.0f - Pr);
+        row_update<8>(brow, nq, [&](int q, float4 b) {
+          float R[4], T[4];
+          slab4(q, R, T);
+          return make_float4(b.x * ((refl ? R[0] : T[0]) * inv), b.y * ((refl ? R[1] : T[1]) * inv),
+                             b.z * ((refl ? R[2] : T[2]) * inv), b.w * ((refl ? R[3] : T[3]) * inv));
+        });
+        cont = true;
+      }
+      if (cont) {
+        const F3 nd = refl ? V.d - V.ng * (2.0f * V.dn) : V.d;
+        const F3 no = refl ? V.p + V.n * V.eps : V.p - V.n * V.eps;
+        w.rays[2 * s] = make_float4(no.x, no.y, no.z, __uint_as_float(V.id));
+        w.rays[2 * s + 1] = make_float4(nd.x, nd.y, nd.z, __uint_as_float(s));
+        if (refl) w.view[s] = flags | kPhotonReflected;
+        cell = start_cell_pl(S, s_planes, no, nd);
+        qd = dir_bin(nd);
+      }
+    }
+    const bool ve = valid && cell != kInvalidCell;
+    const uint32_t ke = ve ? qkey(cell, qd) : kNoKey;
+    const uint32_t re = wave_key_rank(ve, ke, ccount_of(S, w, gp));
+    if (valid) {
+      w.lsrc[a] = s | kFirstVisit;
+      w.ldst[a] = ke;
+      w.lrank[a] = re;
+    }
+  }
+}
+
+// Hashed uniform grid over the stored photons, cell size 2 r: a gather ball lies inside the
+// 2 x 2 x 2 block of cells around the cell corner nearest its centre. A cell's bucket is the
+// spatial hash of Teschner et al. (2003) of its integer coordinates; a bucket may hold several
+// cells, so every photon read is still tested against the ball.
+__device__ __forceinline__ uint32_t photon_bucket(uint32_t n_buckets, int ix, int iy, int iz) {
+  return ((uint32_t)ix * 73856093u ^ (uint32_t)iy * 19349663u ^ (uint32_t)iz * 83492791u) & (n_buckets - 1u);
+}
+__device__ __forceinline__ uint32_t photon_bucket_of(const PhotonDev& P, float4 q) {
+  return photon_bucket(P.n_buckets, (int)floorf(q.x * P.inv_cell), (int)floorf(q.y * P.inv_cell),
+                       (int)floorf(q.z * P.inv_cell));
+}
+
+__global__ void k_photon_count(PhotonDev P) {
+  const uint32_t n = min(P.ctl[0], P.cap);
+  for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x)
+    atomicAdd(&P.bcount[photon_bucket_of(P, P.rec[(size_t)r * P.rq])], 1u);
+}
+
+// Exclusive prefix sum of the bucket counts (one workgroup: each thread sums a contiguous chunk,
+// the chunk sums are scanned in LDS, each thread writes its chunk's prefixes); the counts are
+// cleared to serve as scatter cursors.
+constexpr int kPhotonScanThreads = 1024;
+__global__ __launch_bounds__(kPhotonScanThreads) void k_photon_scan(PhotonDev P) {
+  __shared__ uint32_t s_sum[kPhotonScanThreads];
+  const uint32_t per = P.n_buckets / kPhotonScanThreads;  // n_buckets is a multiple of 1024
+  const uint32_t b0 = threadIdx.x * per;
+  uint32_t tot = 0;
+  for (uint32_t k = 0; k < per; ++k) tot += P.bcount[b0 + k];
+  s_sum[threadIdx.x] = tot;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t acc = 0;
+    for (int t = 0; t < kPhotonScanThreads; ++t) {
+      const uint32_t x = s_sum[t];
+      s_sum[t] = acc;
+      acc += x;
+    }
+    P.bstart[P.n_buckets] = acc;
+  }
+  __syncthreads();
+  uint32_t acc = s_sum[threadIdx.x];
+  for (uint32_t k = 0; k < per; ++k) {
+    const uint32_t c = P.bcount[b0 + k];
+    P.bstart[b0 + k] = acc;
+    P.bcount[b0 + k] = 0;
+    acc += c;
+  }
+}
+
+__global__ void k_photon_scatter(PhotonDev P) {
+  const uint32_t n = min(P.ctl[0], P.cap);
+  for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+    const uint32_t b = photon_bucket_of(P, P.rec[(size_t)r * P.rq]);
+    P.sorted[P.bstart[b] + atomicAdd(&P.bcount[b], 1u)] = r;
+  }
+}
+
+// Caustic radiance at the opaque vertices of a bounce, before their shading changes the
+// throughput: (1 - F_j) rho_j / pi times the flux of the photons within the gather radius that
+// arrived from the side the path sees, over pi r^2, added to the gathered radiance. A thread's
+// flux sums wait in LDS, laid out lane-contiguous ([quad][lane]) so that the wave's accesses
+// fall on distinct banks.
+constexpr int kGatherWG = 64;
+__global__ __launch_bounds__(kGatherWG) void k_photon_gather(DevScene S, DevWS w, PhotonDev P, int depth) {
+  __shared__ float4 s_sum[kMaxBins / 4][kGatherWG];
+  const int p = depth & 1;
+  const uint32_t n = w.ctl->cat_count[p][kCatOpaque * kKeyStride];
+  const uint32_t* list = cat_list(w, p, kCatOpaque);
+  const int Bp = w.Bp, nq = Bp / 4;
+  const float r = P.radius, r2 = r * r;
+  const float norm = 1.0f / (3.14159265358979f * 3.14159265358979f * r2);  // 1 / pi (BRDF) / (pi r^2)
+  const int lane = threadIdx.x;
+  for (uint32_t a = blockIdx.x * kGatherWG + threadIdx.x; a < n; a += gridDim.x * kGatherWG) {
+    const uint32_t s = list[a];
+    const Vertex V = load_vertex(S, w, s);
+    for (int q = 0; q < nq; ++q) s_sum[q][lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    // the 2 x 2 x 2 cells around the nearest cell corner
+    const float cx = V.p.x * P.inv_cell, cy = V.p.y * P.inv_cell, cz = V.p.z * P.inv_cell;
+    const int ix = (int)floorf(cx), iy = (int)floorf(cy), iz = (int)floorf(cz);
+    const int x0 = cx - (float)ix < 0.5f ? ix - 1 : ix;
+    const int y0 = cy - (float)iy < 0.5f ? iy - 1 : iy;
+    const int z0 = cz - (float)iz < 0.5f ? iz - 1 : iz;
+    uint32_t seen[8];
+    bool any = false;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const uint32_t b = photon_bucket(P.n_buckets, x0 + (c & 1), y0 + ((c >> 1) & 1), z0 + (c >> 2));
+      seen[c] = b;
+      bool dup = false;
+#pragma unroll
+      for (int k = 0; k < c; ++k) dup |= seen[k] == b;
+      if (dup) continue;
+      const uint32_t e1 = P.bstart[b + 1];
+      for (uint32_t e = P.bstart[b]; e < e1; ++e) {
+        const float4* rec = P.rec + (size_t)P.sorted[e] * P.rq;
+        const float4 q0 = rec[0], q1 = rec[1];
+        const float dx = q0.x - V.p.x, dy = q0.y - V.p.y, dz = q0.z - V.p.z;
+        if (dx * dx + dy * dy + dz * dz < r2 && q1.x * V.n.x + q1.y * V.n.y + q1.z * V.n.z < 0.0f) {
+          any = true;
+          for (int q = 0; q < nq; ++q) {
+            const float4 f = rec[2 + q], t = s_sum[q][lane];
+            s_sum[q][lane] = make_float4(t.x + f.x, t.y + f.y, t.z + f.z, t.w + f.w);
+          }
+        }
+      }
+    }
+    if (!any) continue;
+    const float4* nt = (const float4*)(S.ntab + V.m * Bp);
+    const float4* kt = (const float4*)(S.ktab + V.m * Bp);
+    const float4* rt = (const float4*)(S.rho + V.m * Bp);
+    const float4* b4 = (const float4*)(w.beta + (size_t)s * Bp);
+    row_update<8>((float4*)(w.lacc + (size_t)s * Bp), nq, [&](int q, float4 l) {
+      const float4 nn = nt[q], kk = kt[q], rr = rt[q], b = b4[q], f = s_sum[q][lane];
+      const float F0 = fresnel(nn.x, kk.x, V.cos_o), F1 = fresnel(nn.y, kk.y, V.cos_o);
+      const float F2 = fresnel(nn.z, kk.z, V.cos_o), F3v = fresnel(nn.w, kk.w, V.cos_o);
+      return make_float4(l.x + b.x * (1.0f - F0) * rr.x * f.x * norm, l.y + b.y * (1.0f - F1) * rr.y * f.y * norm,
+                         l.z + b.z * (1.0f - F2) * rr.z * f.z * norm, l.w + b.w * (1.0f - F3v) * rr.w * f.w * norm);
+    });
+  }
+}
+
 static inline unsigned grid_for(size_t n, unsigned cap = 8192) {
   size_t g = (n + kWG - 1) / kWG;
   if (g < 1) g = 1;
@@ -1906,6 +2305,34 @@ hipError_t launch_unpack_hits(const Launch& L, const DevScene& S, const DevWS& w
 
 hipError_t launch_resolve_vis(const Launch& L, const DevScene& S, const DevWS& w, uint32_t n, float* vis) {
   hipLaunchKernelGGL(k_resolve_vis, dim3(grid_for(n)), dim3(kWG), 0, L.stream, S, w, n, vis);
+  return hipGetLastError();
+}
+
+hipError_t launch_photon_gen(const Launch& L, const DevScene& S, const DevWS& w, const PhotonDev& P, uint64_t k0,
+                             uint32_t n, int gen) {
+  hipLaunchKernelGGL(k_photon_gen, dim3((n + kWG - 1) / kWG), dim3(kWG), 0, L.stream, S, w, P, k0, n, gen);
+  return hipGetLastError();
+}
+hipError_t launch_photon_vis(const Launch& L, const DevScene& S, const DevWS& w, const PhotonDev& P, int par) {
+  hipLaunchKernelGGL(k_photon_vis, dim3(grid_for(w.W, 4096)), dim3(kWG), 0, L.stream, S, w, P, par);
+  return hipGetLastError();
+}
+hipError_t launch_photon_shade(const Launch& L, const DevScene& S, const DevWS& w, const PhotonDev& P, int depth,
+                               int gen) {
+  hipLaunchKernelGGL(k_photon_shade, dim3(grid_for(w.W, 4096)), dim3(kWG), 0, L.stream, S, w, P, depth, gen);
+  return hipGetLastError();
+}
+hipError_t launch_photon_build(hipStream_t s, const PhotonDev& P) {
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(P.n_buckets)), dim3(256), 0, s, P.bcount, (size_t)P.n_buckets, 0u);
+  hipLaunchKernelGGL(k_photon_count, dim3(grid_for(P.cap)), dim3(256), 0, s, P);
+  hipLaunchKernelGGL(k_photon_scan, dim3(1), dim3(kPhotonScanThreads), 0, s, P);
+  hipLaunchKernelGGL(k_photon_scatter, dim3(grid_for(P.cap)), dim3(256), 0, s, P);
+  return hipGetLastError();
+}
+hipError_t launch_photon_gather(const Launch& L, const DevScene& S, const DevWS& w, const PhotonDev& P, int depth) {
+  const size_t want = ((size_t)w.W + kGatherWG - 1) / kGatherWG;
+  hipLaunchKernelGGL(k_photon_gather, dim3((unsigned)(want < 16384 ? want : 16384)), dim3(kGatherWG), 0, L.stream, S,
+                     w, P, depth);
   return hipGetLastError();
 }
 

@@ -310,6 +310,49 @@ def plane_scene(n_bins=8, size=100.0, z=0.0, n=1.6, k=0.03, rho=0.7, sun_dir=(0.
     ).check()
 
 
+def caustic_scene(n_bins=3, floor_n=(1.5, 1.9, 2.6), floor_rho=0.0, sun_zenith_deg=30.0, single=False,
+                  pane_k=0.0) -> Scene:
+    """A caustic under a window: a horizontal glass pane (z = 3, 2 m x 2 m, centred near the
+    origin), a large floor at z = 0 (albedo floor_rho; zero albedo makes its mirror lobe certain),
+    a diffuse receiver wall x = -6 facing +x, and the sun sun_zenith_deg from the zenith in the x-z
+    plane. Sunlight through the pane and off the floor meets the wall. floor_n gives the floor's
+    real index per bin (the first n_bins entries, repeated if shorter). With single=True the floor
+    and the wall are one large triangle each (no shared edge inside the lit region)."""
+    th = math.radians(sun_zenith_deg)
+    B = n_bins
+
+    def quad(c00, c10, c11, c01):
+        return [(c00, c10, c11), (c00, c11, c01)]
+
+    tris, mats = [], []
+    tris += quad((-0.97, -1.03, 3), (1.03, -1.03, 3), (1.03, 0.97, 3), (-0.97, 0.97, 3))
+    mats += [0, 0]
+    s = 60.0
+    if single:
+        tris += [((-3 * s, -3 * s, 0), (3 * s, -3 * s, 0), (0, 3 * s, 0))]
+        mats += [1]
+        tris += [((-6, -3 * s, -1), (-6, 3 * s, -1), (-6, 0, 3 * s))]
+        mats += [2]
+    else:
+        tris += quad((-s, -s, 0), (s, -s, 0), (s, s, 0), (-s, s, 0))
+        mats += [1, 1]
+        tris += quad((-6, -s, -1), (-6, s, -1), (-6, s, 30), (-6, -s, 30))
+        mats += [2, 2]
+    fn = [floor_n[j % len(floor_n)] for j in range(B)]
+    sun_E = np.array([1.0, 0.8, 0.6][:B] + [0.7] * max(0, B - 3), dtype=np.float32)
+    return Scene(
+        verts=np.asarray(tris, dtype=np.float32), mat=np.asarray(mats, dtype=np.uint16),
+        mat_type=np.array([MAT_GLASS, MAT_OPAQUE, MAT_OPAQUE], dtype=np.int32),
+        thickness_m=np.array([0.004, 0, 0], dtype=np.float32),
+        n_tab=np.array([[1.52] * B, fn, [1.6] * B], dtype=np.float32),
+        k_tab=np.array([[pane_k] * B, [0.1] * B, [0.02] * B], dtype=np.float32),
+        rho_tab=np.array([[0.0] * B, [floor_rho] * B, [0.8] * B], dtype=np.float32),
+        lambda_min_nm=380.0, lambda_max_nm=780.0,
+        sun_dir=np.array([math.sin(th), 0.0, math.cos(th)], dtype=np.float32),
+        sun_E=sun_E, env=np.zeros(B, dtype=np.float32), name="caustic",
+    ).check()
+
+
 def furnace_scene(n_bins=8, seed=3, n_boxes=6) -> Scene:
     """Open white-furnace scene: a floor, two glass quads and a few boxes; every material is
     lossless and non-dispersive (k = 0, rho = 1), env = 1 and the sun is off."""

@@ -1,0 +1,249 @@
+"""Caustic photon map on the GPU against the oracle (section 4: photon maps filled from the
+light sources, one of them for caustics, and the caustic part of the reflected radiance taken
+from it).
+
+Records: both sides follow the same photon paths (the same Philox draws, the window chosen by the
+same integer thresholds), so for every photon the oracle does not flag as tied the set of
+(photon, vertex) records is equal. Values: positions within 2e-5 (1 + |p|) (FP32 path vertices
+after a few bounces), directions within 1e-5, flux within 1e-4 relative (FP32 slab and Fresnel
+factors) above 1e-6 of the largest flux.
+
+Gathering: the oracle's records, rounded to FP32, are loaded into a GPU map and rendered; the
+oracle renders with the same rounded records. Per pixel (tie-free) the two agree within 1e-4
+relative (the bar of the plain renderer) plus the flux of the photons that lie within
+r (1 +- tie_radius) of a shading point, which FP32 vertices may count on either side of r
+(photon_unc). tie_radius = 1e-3: path vertices carry up to ~1e-5 m of FP32 error, 1e-4 of the
+gather radii used here.
+"""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import scenegen
+
+pytestmark = pytest.mark.gpu
+
+TIE_RADIUS = 1e-3
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1912_04000_amd as sd
+    return sd.Context(0)
+
+
+def _scene(ctx, sc, grid):
+    import paper_1912_04000_amd as sd
+    S = sd.Scene.from_description(sc, grid=grid)
+    ctx.upload(S)
+    return S
+
+
+def _cam(c):
+    import paper_1912_04000_amd as sd
+    return sd.camera(c.eye, c.target, c.up, c.vfov_deg, c.width, c.height)
+
+
+def _compare_records(gpu, ref, label):
+    """gpu: (pos, dir, flux, id, vertex) from the map; ref: oracle.photons(...)."""
+    gpos, gdir, gflux, gid, gvx = gpu
+    tied_ids = set(np.nonzero(ref["tied"])[0].tolist())
+    gkeys = {(int(i), int(v)): k for k, (i, v) in enumerate(zip(gid, gvx))}
+    okeys = {(int(i), int(v)): k for k, (i, v) in enumerate(zip(ref["id"], ref["depth"]))}
+    assert len(gkeys) == len(gid), "a (photon, vertex) pair was stored twice"
+    g_free = {k for k in gkeys if k[0] not in tied_ids}
+    o_free = {k for k in okeys if k[0] not in tied_ids}
+    say(f"[{label}] records gpu {len(gid)} oracle {len(ref['id'])}, tied photons {len(tied_ids)}, "
+        f"untied records gpu {len(g_free)} oracle {len(o_free)}")
+    assert g_free == o_free, (sorted(g_free - o_free)[:5], sorted(o_free - g_free)[:5])
+    keys = sorted(o_free)
+    gi = np.array([gkeys[k] for k in keys], dtype=np.int64)
+    oi = np.array([okeys[k] for k in keys], dtype=np.int64)
+    dp = np.abs(gpos[gi] - ref["pos"][oi]).max(axis=1) / (1.0 + np.abs(ref["pos"][oi]).max(axis=1))
+    dd = np.abs(gdir[gi] - ref["dir"][oi]).max(axis=1)
+    fo = ref["flux"][oi]
+    big = np.abs(fo) > 1e-6 * np.abs(fo).max()
+    df = np.where(big, np.abs(gflux[gi] - fo) / np.maximum(np.abs(fo), 1e-300), 0.0)
+    say(f"[{label}] max pos err {dp.max():.2e}, dir err {dd.max():.2e}, flux rel err {df.max():.2e}")
+    assert dp.max() <= 2e-5 and dd.max() <= 1e-5 and df.max() <= 1e-4
+    return len(keys)
+
+
+def _records(pmap):
+    return pmap.records()
+
+
+@pytest.mark.parametrize("n_photons,wave,grid,single", [(50_001, 16_384, (2, 2, 2), False),
+                                                        (20_000, 0, (1, 1, 1), True)])
+def test_records_window_mirror_receiver(ctx, n_photons, wave, grid, single):
+    """Emission through the pane, its reflect/transmit choice, the floor's mirror lobe and the
+    storage on the wall; several wavefronts with a ragged last one."""
+    import paper_1912_04000_amd as sd
+    sc = scenegen.caustic_scene(3, single=single)
+    S = _scene(ctx, sc, grid)
+    say(f"build: caustic scene, {n_photons} photons, wave {wave}, grid {grid}")
+    m = ctx.photon_map(S, sd.photon_params(n_photons, radius=0.15, max_depth=6, seed=7, wave_paths=wave))
+    info = m.info()
+    ref = oracle.photons(sc, n_photons, max_depth=6, seed=7)
+    assert info["n_windows"] == 2 and abs(info["window_area"] - ref["area"]) <= 1e-12 * ref["area"]
+    assert info["dropped"] == 0
+    n = _compare_records(m.records(), ref, "caustic")
+    assert n > 0.99 * n_photons
+
+
+@pytest.mark.parametrize("B,grid,maps", [(8, (2, 2, 2), False), (13, (4, 2, 2), True)])
+def test_records_nave(ctx, B, grid, maps):
+    """The nave's window (with a seeded transmittance map when maps is set): photons through it,
+    mostly off the stone floor's mirror lobe onto the walls and pillars."""
+    import paper_1912_04000_amd as sd
+    sc = scenegen.nave_scene(B)
+    if maps:
+        sc = scenegen.with_glass_maps(sc)
+    S = _scene(ctx, sc, grid)
+    N = 60_000
+    say(f"build: nave {B} bins, maps {maps}, grid {grid}, {N} photons")
+    m = ctx.photon_map(S, sd.photon_params(N, radius=0.2, max_depth=7, seed=11, wave_paths=25_000))
+    ref = oracle.photons(sc, N, max_depth=7, seed=11)
+    n = _compare_records(m.records(), ref, f"nave {B} bins maps {maps}")
+    assert n > 1000
+
+
+def _f32_records(ph):
+    out = dict(ph)
+    for k in ("pos", "dir", "flux"):
+        out[k] = ph[k].astype(np.float32).astype(np.float64)
+    return out
+
+
+def _gather_parity(img, ref, label):
+    B = ref.image.shape[0]
+    mean_bin = ref.image.reshape(B, -1).mean(axis=1).reshape((B,) + (1,) * (ref.image.ndim - 1))
+    tol = 1e-4 * np.maximum(np.abs(ref.image), 1e-3 * mean_bin) + 1.0001 * ref.photon_unc
+    ok = ref.tied == 0
+    bad = (np.abs(img - ref.image) > tol) & ok[None]
+    rel = np.abs(img - ref.image)[:, ok] / np.maximum(np.abs(ref.image)[:, ok], 1e-3 * mean_bin.reshape(B, 1))
+    say(f"[{label}] tie-free {ok.mean():.3f}, bad {int(bad.any(axis=0).sum())}, max rel {rel.max():.2e}, "
+        f"pixels with an uncertain photon {int((ref.photon_unc > 0).any(axis=0).sum())}")
+    assert ok.mean() > 0.9 and not bad.any(), np.argwhere(bad)[:5]
+
+
+def test_gather_caustic_on_the_wall(ctx):
+    """The oracle's map loaded into the GPU: a camera over the lit spots on the receiver wall, and
+    a path depth that also sees the wall through the floor's mirror."""
+    import paper_1912_04000_amd as sd
+    sc = scenegen.caustic_scene(3, floor_rho=0.3)
+    S = _scene(ctx, sc, (2, 2, 2))
+    ph = _f32_records(oracle.photons(sc, 200_000, max_depth=6, seed=7))
+    m = sd.PhotonMap(ctx, S, sd.photon_params(200_000, radius=0.15, max_depth=6, seed=7,
+                                              capacity=len(ph["id"]) + 10))
+    m.load(ph["pos"], ph["dir"], ph["flux"], ph["id"], ph["depth"])
+    assert m.info()["stored"] == len(ph["id"])
+    cam = scenegen.Camera(eye=(-1.0, 0.0, 8.0), target=(-6.0, 0.0, 9.0), up=(0, 0, 1), vfov_deg=70, width=40,
+                          height=32)
+    for depth in (1, 3):
+        say(f"render: caustic wall, depth {depth}")
+        img = ctx.render_photons(S, m, _cam(cam), sd.render_params(spp=2, max_depth=depth, seed=3)).cpu().numpy()
+        ref = oracle.render(sc, cam, spp=2, max_depth=depth, seed=3, photons=ph, radius=0.15, tie_radius=TIE_RADIUS)
+        _gather_parity(img, ref, f"caustic wall depth {depth}")
+        plain = oracle.render(sc, cam, spp=2, max_depth=depth, seed=3)
+        assert (ref.image - plain.image).max() > 0.05 * ref.image.max()   # the caustic is in the frame
+
+
+@pytest.mark.parametrize("B,grid,radius", [(8, (2, 2, 2), 0.25), (40, (4, 2, 2), 0.1)])
+def test_gather_nave(ctx, B, grid, radius):
+    import paper_1912_04000_amd as sd
+    sc = scenegen.nave_scene(B)
+    S = _scene(ctx, sc, grid)
+    ph = _f32_records(oracle.photons(sc, 150_000, max_depth=7, seed=5))
+    m = sd.PhotonMap(ctx, S, sd.photon_params(150_000, radius=radius, max_depth=7, seed=5))
+    m.load(ph["pos"], ph["dir"], ph["flux"], ph["id"], ph["depth"])
+    cam = scenegen.nave_camera(48, 40)
+    say(f"render: nave {B} bins, radius {radius}, {len(ph['id'])} records")
+    img = ctx.render_photons(S, m, _cam(cam), sd.render_params(spp=2, max_depth=5, seed=8)).cpu().numpy()
+    ref = oracle.render(sc, cam, spp=2, max_depth=5, seed=8, photons=ph, radius=radius, tie_radius=TIE_RADIUS)
+    _gather_parity(img, ref, f"nave {B} bins r {radius}")
+
+
+def test_empty_map_renders_like_plain(ctx):
+    """No photon is stored when the only light through the pane is transmitted (overhead sun, a
+    floor that reflects nothing): the render with the empty map equals the plain render bit for
+    bit, in eager and graph mode; so does a scene without glass."""
+    import paper_1912_04000_amd as sd
+    sc = scenegen.caustic_scene(3, floor_n=(1.0,), floor_rho=0.9)
+    sc.k_tab[1] = 0.0
+    sc.sun_dir[:] = (0.0, 0.0, 1.0)
+    S = _scene(ctx, sc, (2, 2, 2))
+    m = ctx.photon_map(S, sd.photon_params(30_000, radius=0.2, max_depth=6, seed=2))
+    assert m.info()["stored"] == 0 and m.info()["n_windows"] == 2
+    cam = _cam(scenegen.Camera(eye=(0.5, 0.2, 2.0), target=(0.0, 0.0, 0.0), up=(0, 1, 0), vfov_deg=80, width=32,
+                               height=32))
+    p = sd.render_params(spp=2, max_depth=4, seed=4)
+    a = ctx.render(S, cam, p).cpu().numpy()
+    b = ctx.render_photons(S, m, cam, p).cpu().numpy()
+    assert np.array_equal(a, b)
+    sc2 = scenegen.plane_scene(n_bins=8)
+    S2 = _scene(ctx, sc2, (1, 1, 1))
+    m2 = ctx.photon_map(S2, sd.photon_params(1000, radius=0.2, max_depth=4, seed=2))
+    assert m2.info()["n_windows"] == 0 and m2.info()["stored"] == 0
+    p2 = sd.render_params(spp=1, max_depth=3, seed=4, use_graph=1)
+    c2 = _cam(scenegen.Camera(eye=(0, 0, 5), target=(0, 0, 0), up=(0, 1, 0), vfov_deg=60, width=16, height=16))
+    assert np.array_equal(ctx.render(S2, c2, p2).cpu().numpy(), ctx.render_photons(S2, m2, c2, p2).cpu().numpy())
+
+
+def test_graph_replays_equal_eager(ctx):
+    import paper_1912_04000_amd as sd
+    sc = scenegen.caustic_scene(3, floor_rho=0.3)
+    S = _scene(ctx, sc, (2, 2, 2))
+    m = ctx.photon_map(S, sd.photon_params(40_000, radius=0.2, max_depth=6, seed=9))
+    cam = _cam(scenegen.Camera(eye=(-1.0, 0.0, 8.0), target=(-6.0, 0.0, 9.0), up=(0, 0, 1), vfov_deg=70, width=24,
+                               height=24))
+    eager = ctx.render_photons(S, m, cam, sd.render_params(spp=2, max_depth=3, seed=1)).cpu().numpy()
+    pg = sd.render_params(spp=2, max_depth=3, seed=1, use_graph=1)
+    out = None
+    for rep in range(3):
+        out = ctx.render_photons(S, m, cam, pg, out=out)
+        ctx.torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), eager), rep
+    assert ctx.stats()["graph_launches"] >= 3
+
+
+def test_capacity_and_errors(ctx):
+    import paper_1912_04000_amd as sd
+    sc = scenegen.caustic_scene(3)
+    S = _scene(ctx, sc, (2, 2, 2))
+    ref = oracle.photons(sc, 5000, max_depth=6, seed=4)
+    m = ctx.photon_map(S, sd.photon_params(5000, radius=0.2, max_depth=6, seed=4, capacity=300))
+    info = m.info()
+    n_tied = int(ref["tied"].sum())
+    say(f"capacity 300: stored {info['stored']}, dropped {info['dropped']}, oracle records {len(ref['id'])}")
+    assert info["stored"] == 300 and abs(info["stored"] + info["dropped"] - len(ref["id"])) <= 2 * n_tied
+    # records of the kept photons are still the oracle's
+    pos, dr, fl, pid, vx = m.records(300)
+    okeys = {(int(i), int(v)): k for k, (i, v) in enumerate(zip(ref["id"], ref["depth"]))}
+    tied = set(np.nonzero(ref["tied"])[0].tolist())
+    for k in range(300):
+        if int(pid[k]) in tied:
+            continue
+        o = okeys[(int(pid[k]), int(vx[k]))]
+        assert np.abs(fl[k] - ref["flux"][o]).max() <= 1e-4 * np.abs(ref["flux"][o]).max()
+    with pytest.raises(sd.SddError):
+        m.records(301)
+    cam = _cam(scenegen.Camera(eye=(0, 0, 5), target=(0, 0, 0), up=(0, 1, 0), vfov_deg=60, width=8, height=8))
+    unbuilt = sd.PhotonMap(ctx, S, sd.photon_params(100, radius=0.2))
+    with pytest.raises(sd.SddError) as e:
+        ctx.render_photons(S, unbuilt, cam, sd.render_params())
+    assert e.value.code == -5
+    S8 = _scene(ctx, scenegen.caustic_scene(8), (2, 2, 2))
+    with pytest.raises(sd.SddError) as e:
+        ctx.render_photons(S8, m, cam, sd.render_params())
+    assert e.value.code == -5
+    with pytest.raises(sd.SddError):
+        ctx.render_photons(S, m, cam, sd.render_params(mode=sd.MODE_CACHED))

@@ -25,26 +25,7 @@ def _quad(c00, c10, c11, c01):
 
 
 def _caustic_scene(B=3, floor_n=(1.5, 1.9, 2.6), floor_rho=0.0):
-    th = math.radians(30.0)
-    tris, mats = [], []
-    tris += _quad((-0.97, -1.03, 3), (1.03, -1.03, 3), (1.03, 0.97, 3), (-0.97, 0.97, 3))      # pane
-    mats += [0, 0]
-    s = 60.0
-    tris += _quad((-s, -s, 0), (s, -s, 0), (s, s, 0), (-s, s, 0))                          # mirror floor
-    mats += [1, 1]
-    tris += _quad((-6, -s, -1), (-6, s, -1), (-6, s, 30), (-6, -s, 30))                    # receiver wall
-    mats += [2, 2]
-    sc = scenegen.Scene(
-        verts=np.asarray(tris, dtype=np.float32), mat=np.asarray(mats, dtype=np.uint16),
-        mat_type=np.array([1, 0, 0], dtype=np.int32), thickness_m=np.array([0.004, 0, 0], dtype=np.float32),
-        n_tab=np.array([[1.52] * B, list(floor_n)[:B], [1.6] * B], dtype=np.float32),
-        k_tab=np.array([[0.0] * B, [0.1] * B, [0.02] * B], dtype=np.float32),
-        rho_tab=np.array([[0.0] * B, [floor_rho] * B, [0.8] * B], dtype=np.float32),
-        lambda_min_nm=380.0, lambda_max_nm=780.0,
-        sun_dir=np.array([math.sin(th), 0.0, math.cos(th)], dtype=np.float32),
-        sun_E=np.array([1.0, 0.8, 0.6][:B], dtype=np.float32), env=np.zeros(B, dtype=np.float32),
-        name="caustic").check()
-    return sc
+    return scenegen.caustic_scene(B, floor_n, floor_rho)
 
 
 def _expected_caustic(sc, cos_view):
