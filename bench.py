@@ -61,7 +61,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-cached", action="store_true", help="skip the cached-path comparison of the default run")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the colorimetry and glass-map measurements (profiling runs of the frame alone)")
+                    help="skip the colorimetry, glass-map and photon-map measurements (profiling runs of the "
+                         "frame alone)")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="GiB: only run a plain device-to-device copy of that size (PMC calibration)")
@@ -433,6 +434,68 @@ def bench_glass_maps(ctx, sc, cam, cfg, wave, spp=8):
                     f"{sc.n_bins} bins"}
 
 
+def bench_photons(ctx, S, sc, cam, cfg, wave, n_photons=4_000_000, radius=0.1, spp=8):
+    """Caustic photon map (section 4) of the benchmarked view: HIP-event time of building an
+    n_photons map (emission through the windows, photon paths through the cell queues, storage,
+    hashed-grid sort), then of an spp-sample frame that gathers from it at every shaded opaque
+    vertex against the same frame without it. Gather roofline: algorithmic bytes from the device
+    counters (per gathering vertex its list entry, hit, ray and triangle, 100 B; per vertex that
+    found a record its throughput row read and radiance row read and written, 12 Bp B; per record
+    found its grid entry, direction and flux row, 32 + 4 Bp B; grid bounds and the entries tested
+    outside the ball are search overhead, not counted) over the HIP-event time of the gather
+    launches (both passes)."""
+    import torch
+    import paper_1912_04000_amd as sd
+    Bp = (sc.n_bins + 3) // 4 * 4
+    pp = sd.photon_params(n_photons, radius=radius, max_depth=cfg["max_depth"], seed=1, capacity=n_photons // 4)
+    m = sd.PhotonMap(ctx, S, pp)
+    m.build(S)                                   # first touch of the map and the workspace
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    m.build(S, finish=False)
+    e1.record()
+    torch.cuda.synchronize()
+    ctx.finish()
+    build_ms = e0.elapsed_time(e1)
+    info = m.info()
+    c = sd.camera(cam.eye, cam.target, cam.up, cam.vfov_deg, cam.width, cam.height)
+    img = torch.empty((sc.n_bins, cam.height, cam.width), dtype=torch.float32, device="cuda")
+    p = sd.render_params(spp=spp, max_depth=cfg["max_depth"], seed=1, wave_paths=wave, timing=1)
+    rate, st = {}, None
+    for name in ("photons", "plain"):
+        run = ((lambda: ctx.render_photons(S, m, c, p, out=img, finish=False)) if name == "photons" else
+               (lambda: ctx.render(S, c, p, out=img, finish=False)))
+        run()
+        ctx.finish()
+        ctx.reset_stats()
+        e0.record()
+        run()
+        e1.record()
+        torch.cuda.synchronize()
+        ctx.finish()
+        rate[name] = cam.width * cam.height * spp / (e0.elapsed_time(e1) * 1e-3)
+        if name == "photons":
+            st = ctx.stats()
+    launches = max(1, st["photon_launches"])
+    alg = (st["photon_vertices"] * 100 + st["photon_lit_vertices"] * 12 * Bp
+           + st["photons_found"] * (32 + 4 * Bp))
+    gbps = alg / (st["photon_ms"] * 1e-3) / 1e9 if st["photon_ms"] > 0 else 0.0
+    return {"photons": n_photons, "radius_m": radius, "max_depth": cfg["max_depth"],
+            "build_ms": build_ms, "photons_per_s": n_photons / (build_ms * 1e-3),
+            "records": info["stored"], "dropped": info["dropped"], "windows": info["n_windows"],
+            "spp": spp, "samples_per_s": rate["photons"], "plain_samples_per_s_same_spp": rate["plain"],
+            "relative_cost": rate["plain"] / rate["photons"],
+            "gather": {"kernel": "k_photon_gather", "bound": "hbm", "launches": st["photon_launches"],
+                       "avg_launch_ms": st["photon_ms"] / launches, "achieved": gbps, "peak": HBM_PEAK_GBPS,
+                       "unit": "GB/s", "frac": gbps / HBM_PEAK_GBPS,
+                       "algorithmic_bytes_per_launch": alg / launches,
+                       "vertices_per_launch": st["photon_vertices"] / launches,
+                       "records_found_per_vertex": st["photons_found"] / max(1, st["photon_vertices"]),
+                       "entries_tested_per_vertex": st["photon_candidates"] / max(1, st["photon_vertices"]),
+                       "entries_tested_max": st["photon_candidates_max"],
+                       "lit_fraction": st["photon_lit_vertices"] / max(1, st["photon_vertices"])}}
+
+
 def crop_camera(cam, cw, ch):
     """The centred cw x ch window of a view as a camera of its own (same eye, axis and pixel
     footprint): tan(vfov'/2) = tan(vfov/2) ch / H."""
@@ -701,6 +764,7 @@ def main():
         out["colorimetry"] = bench_colorimetry(ctx, img, sc)
         if args.workload == "church":
             out["glass_maps"] = bench_glass_maps(ctx, sc, cam, cfg, p.wave_paths)
+            out["photon_map"] = bench_photons(ctx, S, sc, cam, cfg, p.wave_paths)
     if args.workload == "church" and not args.no_cached:
         # the cached half of the metric on the same view: the plain frame just timed (64 spp,
         # seed 1) fixes a = RMSE_64 sqrt(64) of the plain estimator's RMSE = a / sqrt(spp)

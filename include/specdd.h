@@ -444,7 +444,7 @@ typedef struct sdd_photon_map sdd_photon_map;
 typedef struct {
   int64_t n_photons;           /* photons sent out, >= 1; n_photons (max_depth - 1) < 2^32     */
   int32_t max_depth;           /* vertices of a photon path, 2 .. 64                           */
-  float radius;                /* gather radius r > 0 (scene units); the map's grid cells are 2 r */
+  float radius;                /* gather radius r > 0 (scene units), also the map's grid cell   */
   uint64_t seed;               /* Philox key of the photon paths                               */
   int64_t capacity;            /* records the map holds, 1 .. 2^28 (further ones are counted as
                                   dropped)                                                     */
@@ -541,6 +541,13 @@ typedef struct {
   double query_ms;             /* HIP-event time of the cache-query launches (timing = 1)     */
   double train_ms;             /* HIP-event time of the training-batch finishing steps:
                                   target gathering, compaction and Adam steps (timing = 1)  */
+  uint64_t photon_vertices;    /* opaque vertices that gathered from a photon map             */
+  uint64_t photons_found;      /* photon records within the gather radius, summed over them   */
+  uint64_t photon_lit_vertices; /* of those vertices, the ones that found at least one record  */
+  uint64_t photon_candidates;  /* grid entries tested by them (the found ones included)       */
+  uint64_t photon_candidates_max; /* most entries tested for one vertex                        */
+  uint64_t photon_launches;    /* photon-gather launches                                       */
+  double photon_ms;            /* HIP-event time of the photon-gather launches (timing = 1)   */
 } sdd_stats;
 
 /* Counters accumulated since the previous sdd_reset_stats (valid after sdd_finish). */

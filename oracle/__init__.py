@@ -66,7 +66,7 @@ class _Params(C.Structure):
 class _PhotonParams(C.Structure):
     _fields_ = [("n_photons", C.c_int64), ("max_depth", C.c_int32), ("seed", C.c_uint64), ("threads", C.c_int32),
                 ("tie_t_rel", C.c_double), ("tie_edge_abs", C.c_double), ("tie_edge_rel_t", C.c_double),
-                ("tie_lobe", C.c_double), ("tie_cos_sun", C.c_double)]
+                ("tie_lobe", C.c_double), ("tie_cos_sun", C.c_double), ("stride", C.c_int64)]
 
 
 class _Queries(C.Structure):
@@ -258,16 +258,17 @@ def render(scene, camera, spp=1, max_depth=4, seed=1, view=0, pixels=None, threa
     return RenderResult(img, tied, stats, q, unc)
 
 
-def photons(scene, n_photons, max_depth=8, seed=1, threads=None, tie: TieParams = TieParams()):
+def photons(scene, n_photons, max_depth=8, seed=1, threads=None, tie: TieParams = TieParams(), stride=1):
     """Caustic photon map (see orc_photons): records of photons stored at opaque vertices after at
     least one reflection, ordered by (photon, vertex): pos [n][3], dir [n][3] (direction of
     travel), flux [n][B], id [n] (photon index), depth [n] (vertex); tied [n_photons] flags
-    photons whose path FP32 rounding could change; area = the windows' projected area A."""
+    photons whose path FP32 rounding could change; area = the windows' projected area A. With
+    stride k only photons 0, k, 2k, ... are traced (their records are those of the full map)."""
     s, keep = _scene_struct(scene)
     B = scene.n_bins
     th = threads or min(8, os.cpu_count() or 1)
     pp = _PhotonParams(int(n_photons), int(max_depth), int(seed), int(th), tie.t_rel, tie.edge_abs, tie.edge_rel_t,
-                       tie.lobe, tie.cos_sun)
+                       tie.lobe, tie.cos_sun, int(stride))
     cap = max(1024, int(n_photons) // 2)
     while True:
         pos, dirs = np.zeros((cap, 3)), np.zeros((cap, 3))

@@ -791,6 +791,8 @@ int orc_render(const orc_scene* sc, const orc_camera* cam, const orc_params* prm
 //           counts); then the mirror lobe is taken with P_s = mean F / (mean F + mean (1-F) rho)
 //           (weight F / P_s), else the photon ends (a diffuse bounce leaves the caustic paths).
 // Vertex max_depth stores but does not scatter. Records come out ordered by (photon, vertex).
+// With stride k > 1 only the photons i = 0, k, 2k, ... are traced (a sample of the same map:
+// every photon still carries E_j A / N).
 // ------------------------------------------------------------------------------------------
 typedef struct {
   int64_t n_photons;
@@ -798,6 +800,7 @@ typedef struct {
   uint64_t seed;
   int32_t threads;
   double tie_t_rel, tie_edge_abs, tie_edge_rel_t, tie_lobe, tie_cos_sun;
+  int64_t stride;
 } orc_photon_params;
 
 int64_t orc_photons(const orc_scene* sc, const orc_photon_params* pp, int64_t cap, double* pos, double* dir,
@@ -843,7 +846,8 @@ int64_t orc_photons(const orc_scene* sc, const orc_photon_params* pp, int64_t ca
   auto work = [&](int th, int64_t a, int64_t b) {
     std::vector<double> beta(B), F(B), R(B), Tt(B);
     std::vector<GlassCross> cr;
-    for (int64_t i = a; i < b; ++i) {
+    const int64_t k = std::max<int64_t>(1, pp->stride);
+    for (int64_t i = (a + k - 1) / k * k; i < b; i += k) {
       bool tied = false;
       const uint32_t c0 = (uint32_t)i, c1 = (uint32_t)((uint64_t)i >> 32);
       U4 rn = philox4x32_10({{c0, c1, 0u | kPurpose, 0u}}, k0, k1);

@@ -99,7 +99,10 @@ class Stats(C.Structure):
         "node_visits", "tri_tests")] + [
         ("trace_ms", C.c_double), ("shade_ms", C.c_double), ("graph_launches", C.c_uint64), ("graph_ms", C.c_double),
         ("cache_queries", C.c_uint64), ("query_launches", C.c_uint64), ("train_batches", C.c_uint64),
-        ("query_ms", C.c_double), ("train_ms", C.c_double)]
+        ("query_ms", C.c_double), ("train_ms", C.c_double), ("photon_vertices", C.c_uint64),
+        ("photons_found", C.c_uint64), ("photon_lit_vertices", C.c_uint64), ("photon_candidates", C.c_uint64),
+        ("photon_candidates_max", C.c_uint64), ("photon_launches", C.c_uint64),
+        ("photon_ms", C.c_double)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

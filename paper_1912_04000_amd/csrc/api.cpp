@@ -270,6 +270,7 @@ int run_paths(sdd_ctx* ctx, const sdd_scene* scene, const sdd_render_params* p, 
   const bool query = cache && pm.purpose == 0 && D >= kCacheDepth;
   HIP_TRY(ctx, launch_fill_u32(ctx->stream, &w.ctl->cat_count[0][0], 2 * 8 * kKeyStride, 0u));
   HIP_TRY(ctx, launch_fill_u32(ctx->stream, (uint32_t*)w.catb, ((size_t)2 * w.W + 3) / 4, 0u));
+  if (ph) HIP_TRY(ctx, launch_fill_u32(ctx->stream, w.ctl->ph_heavy, 2, 0u));
   HIP_TRY(ctx, launch_raygen(L, S, w, k0, n, p->seed, gen, pm));
   int rc = trace_phase(ctx, L, S, w, gen, rounds, 1, timing);
   if (rc) return rc;
@@ -280,7 +281,12 @@ int run_paths(sdd_ctx* ctx, const sdd_scene* scene, const sdd_render_params* p, 
     if (scene->hdr.env_nonzero) HIP_TRY(ctx, launch_escape(L, S, w, d));
     if (!last) {
       // caustic radiance from the photon map at the opaque vertices, before their lobes
-      if (ph) HIP_TRY(ctx, launch_photon_gather(L, S, w, *ph, d));
+      if (ph) {
+        if (timing) record(ctx, ctx->ev_photon, ctx->ev_used_photon, true);
+        HIP_TRY(ctx, launch_photon_gather(L, S, w, *ph, d));
+        if (timing) record(ctx, ctx->ev_photon, ctx->ev_used_photon, false);
+        ctx->acc.photon_launches++;
+      }
       HIP_TRY(ctx, launch_shade_opaque(L, S, w, d, D, p->seed, gen, pm));
       if (d < D) HIP_TRY(ctx, launch_shade_glass(L, S, w, d, p->seed, gen, pm));
     }
@@ -427,6 +433,7 @@ int render_views(sdd_ctx* ctx, const sdd_scene* scene, std::vector<ViewDesc>& vi
       ctx->graph = nullptr;
     }
     const uint64_t t0 = ctx->acc.trace_launches, s0 = ctx->acc.shade_launches, f0 = ctx->acc.wavefronts;
+    const uint64_t g0 = ctx->acc.photon_launches;
     // The caller's stream may be the null stream, which cannot be captured: record the sequence
     // on the context's own stream (nothing runs there), then launch the graph on the caller's.
     if (!ctx->capture_stream) HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
@@ -452,10 +459,12 @@ int render_views(sdd_ctx* ctx, const sdd_scene* scene, std::vector<ViewDesc>& vi
     ctx->graph_trace_launches = ctx->acc.trace_launches - t0;
     ctx->graph_shade_launches = ctx->acc.shade_launches - s0;
     ctx->graph_wavefronts = ctx->acc.wavefronts - f0;
+    ctx->graph_photon_launches = ctx->acc.photon_launches - g0;
     // the capture only recorded the launches; count them when the graph actually runs
     ctx->acc.trace_launches = t0;
     ctx->acc.shade_launches = s0;
     ctx->acc.wavefronts = f0;
+    ctx->acc.photon_launches = g0;
   }
   if (p->timing) record(ctx, ctx->ev_graph, ctx->ev_used_graph, true);
   HIP_TRY(ctx, hipGraphLaunch(ctx->graph_exec, ctx->stream));
@@ -463,6 +472,7 @@ int render_views(sdd_ctx* ctx, const sdd_scene* scene, std::vector<ViewDesc>& vi
   ctx->acc.trace_launches += ctx->graph_trace_launches;
   ctx->acc.shade_launches += ctx->graph_shade_launches;
   ctx->acc.wavefronts += ctx->graph_wavefronts;
+  ctx->acc.photon_launches += ctx->graph_photon_launches;
   ctx->acc.graph_launches++;
   return SDD_OK;
 }
@@ -523,14 +533,17 @@ uint32_t glass_triangles(const sdd_scene* s) {
 }
 
 // Buffer layout of a map: control words, window thresholds and triangles, records (position,
-// direction, flux quads), bucket counts and starts, record indices sorted by bucket.
+// direction, flux quads), bucket counts and starts, and the records' positions and directions
+// again in bucket order (what the gathering scans).
 void photon_layout(sdd_photon_map* m, const sdd_scene* s, const sdd_photon_params* p) {
   m->prm = *p;
   m->B = s->hdr.n_bins;
   m->Bp = (m->B + 3) & ~3;
   m->max_win = std::max<uint32_t>(1, glass_triangles(s));
-  uint32_t nb = 1024;
-  while (nb < (1u << 22) && (uint64_t)nb * 2 < (uint64_t)p->capacity) nb <<= 1;
+  // grid cells of the gather radius, about two buckets per record (2^12 .. 2^22)
+  int total = 12;
+  while (total < 22 && std::ldexp(1.0, total) < 2.0 * (double)p->capacity) ++total;
+  const uint32_t nb = 1u << total;
   m->n_buckets = nb;
   const size_t rq = 2 + (size_t)m->Bp / 4;
   size_t o = 0;
@@ -540,7 +553,9 @@ void photon_layout(sdd_photon_map* m, const sdd_scene* s, const sdd_photon_param
   m->off_rec = o;    o = a256(o + 16ull * rq * (size_t)p->capacity);
   m->off_bcount = o; o = a256(o + 4ull * nb);
   m->off_bstart = o; o = a256(o + 4ull * (nb + 1));
-  m->off_sorted = o; o = a256(o + 4ull * (size_t)p->capacity);
+  m->off_cand = o;   o = a256(o + 16ull * (size_t)p->capacity);
+  m->off_bsum = o;   o = a256(o + 4ull * (nb / kPhotonScanChunk + 1));
+  m->off_occ = o;    o = a256(o + 4ull * kPhotonOccWords);
   m->total = o;
 }
 
@@ -554,13 +569,15 @@ PhotonDev photon_dev(const sdd_photon_map* m) {
   P.rec = (float4*)(b + m->off_rec);
   P.bcount = (uint32_t*)(b + m->off_bcount);
   P.bstart = (uint32_t*)(b + m->off_bstart);
-  P.sorted = (uint32_t*)(b + m->off_sorted);
+  P.cand = (float4*)(b + m->off_cand);
+  P.bsum = (uint32_t*)(b + m->off_bsum);
+  P.occ = (uint32_t*)(b + m->off_occ);
   P.n_win = (uint32_t)m->thr.size();
   P.cap = (uint32_t)m->prm.capacity;
   P.n_buckets = m->n_buckets;
   P.rq = 2 + (uint32_t)m->Bp / 4;
   P.radius = m->prm.radius;
-  P.inv_cell = (float)(1.0 / (2.0 * (double)m->prm.radius));
+  P.inv_cell = (float)(1.0 / (double)m->prm.radius);
   P.flux_scale = (float)(m->area / (double)m->prm.n_photons);
   P.seed_lo = (uint32_t)m->prm.seed;
   P.seed_hi = (uint32_t)(m->prm.seed >> 32);
@@ -648,6 +665,7 @@ void sdd_destroy(sdd_ctx* c) {
   for (auto& p : c->ev_graph) { (void)hipEventDestroy(p.first); (void)hipEventDestroy(p.second); }
   for (auto& p : c->ev_query) { (void)hipEventDestroy(p.first); (void)hipEventDestroy(p.second); }
   for (auto& p : c->ev_train) { (void)hipEventDestroy(p.first); (void)hipEventDestroy(p.second); }
+  for (auto& p : c->ev_photon) { (void)hipEventDestroy(p.first); (void)hipEventDestroy(p.second); }
   if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
   if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
@@ -992,7 +1010,7 @@ int sdd_photon_map_build(sdd_ctx* c, const sdd_scene* s, sdd_photon_map* m, void
   if (s->hdr.n_bins != m->B) return fail(c, SDD_ERR_NOT_READY, "scene bins differ from the photon map's");
   if (glass_triangles(s) > m->max_win) return fail(c, SDD_ERR_INVALID_ARG, "scene has more glass than the photon map");
   // the grid's integer cell coordinates must stay far from overflow
-  const double inv_cell = 1.0 / (2.0 * (double)m->prm.radius);
+  const double inv_cell = 1.0 / (double)m->prm.radius;
   for (int a = 0; a < 3; ++a)
     if (std::max(std::fabs(s->info.grid_lo[a]), std::fabs(s->info.grid_hi[a])) * inv_cell > 1e9)
       return fail(c, SDD_ERR_INVALID_ARG, "photon radius too small for the scene's extent");
@@ -1194,6 +1212,11 @@ int sdd_finish(sdd_ctx* c) {
     c->acc.node_visits += h.st_nodes;
     c->acc.tri_tests += h.st_tris;
     c->acc.cache_queries += h.st_queries;
+    c->acc.photon_vertices += h.st_ph_vertices;
+    c->acc.photons_found += h.st_ph_found;
+    c->acc.photon_lit_vertices += h.st_ph_lit;
+    c->acc.photon_candidates += h.st_ph_cand;
+    c->acc.photon_candidates_max = std::max<uint64_t>(c->acc.photon_candidates_max, h.st_ph_cand_max);
     if (h.err_cross) status = fail(c, SDD_ERR_QUEUE_OVERFLOW, "a shadow ray crossed more glass slabs than recorded");
     else if (h.err_nonfinite)
       status = fail(c, SDD_ERR_DEVICE, std::to_string(h.err_nonfinite) + " non-finite radiance values reached the image");
@@ -1219,7 +1242,12 @@ int sdd_finish(sdd_ctx* c) {
     float ms = 0;
     if (hipEventElapsedTime(&ms, c->ev_train[i].first, c->ev_train[i].second) == hipSuccess) c->acc.train_ms += ms;
   }
+  for (size_t i = 0; i < c->ev_used_photon; ++i) {
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, c->ev_photon[i].first, c->ev_photon[i].second) == hipSuccess) c->acc.photon_ms += ms;
+  }
   c->ev_used_trace = c->ev_used_shade = c->ev_used_graph = c->ev_used_query = c->ev_used_train = 0;
+  c->ev_used_photon = 0;
   return status;
 }
 

@@ -32,8 +32,9 @@ struct sdd_ctx {
   hipStream_t capture_stream = nullptr;   // own stream (default priority) used only to record graphs
   uint64_t graph_key = 0;
   uint64_t graph_trace_launches = 0, graph_shade_launches = 0, graph_wavefronts = 0;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_query, ev_train;
-  size_t ev_used_query = 0, ev_used_train = 0;
+  uint64_t graph_photon_launches = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_query, ev_train, ev_photon;
+  size_t ev_used_query = 0, ev_used_train = 0, ev_used_photon = 0;
 };
 
 struct sdd_cache {
@@ -55,7 +56,7 @@ struct sdd_photon_map {
   void* buf = nullptr;
   size_t bytes = 0;
   int device = -1;
-  size_t off_ctl = 0, off_thr = 0, off_tri = 0, off_rec = 0, off_bcount = 0, off_bstart = 0, off_sorted = 0, total = 0;
+  size_t off_ctl = 0, off_thr = 0, off_tri = 0, off_rec = 0, off_bcount = 0, off_bstart = 0, off_cand = 0, off_bsum = 0, off_occ = 0, total = 0;
   std::vector<uint32_t> thr, tri;  // windows of the last build (kept alive for its copies)
   double area = 0.0;
   bool built = false;

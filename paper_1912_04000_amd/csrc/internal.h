@@ -17,6 +17,8 @@ constexpr int kMaxStack = 72;       // builder caps BVH depth so the stack never
 constexpr int kWide = 4;            // children per BVH node
 constexpr int kMaxCross = 8;        // glass crossings recorded per shadow ray
 constexpr int kMaxBins = 128;
+constexpr int kPhotonScanChunk = 4096;  // photon-map buckets per workgroup of the bucket scan
+constexpr int kPhotonOccWords = 1024;   // occupancy bitmap of the photon map's hashed super-cells
 constexpr int kMaxGrid = 64;
 constexpr int kLdsCells = 256;      // cell tables up to this size are staged in LDS by the traversal
 constexpr int kXcds = 8;            // MI355X: 8 XCDs, workgroups dispatched round-robin
@@ -132,7 +134,8 @@ struct Ctl {
   uint32_t list_count[2];   // produced (ray, cell, rank) entries per generation parity
   uint32_t n_queue;         // entries in the cell-sorted queue of the current round
   uint32_t n_tiles;         // tiles of the current round
-  uint32_t pad0[12];        // to the end of the first 64-byte line
+  uint32_t ph_heavy[2];     // photon gathering: vertices deferred to the wave-wide pass, per bounce parity
+  uint32_t pad0[10];        // to the end of the first 64-byte line
   // per-XCD tile counters of the current round (reset by k_scan), one 64-byte line each: every
   // tile taken is an atomic on one of them, and atomics on one line are served one at a time
   uint32_t tile_next[8 * kKeyStride];
@@ -144,7 +147,12 @@ struct Ctl {
   unsigned long long err_cross, err_nonfinite, err_stack;
   unsigned long long st_nodes, st_tris;  // BVH nodes visited, triangle tests (traversal work)
   unsigned long long st_queries;         // vertices answered by the radiance cache
-  unsigned long long pad1[2];
+  unsigned long long st_ph_vertices;     // opaque vertices that gathered from a photon map
+  unsigned long long st_ph_found;        // photon records found within the gather radius (summed)
+  unsigned long long st_ph_lit;          // gathering vertices that found at least one record
+  unsigned long long st_ph_cand;         // bucket entries tested by the gathering (summed)
+  unsigned long long st_ph_cand_max;     // most bucket entries tested for one vertex
+  unsigned long long pad1[5];            // to a whole number of 64-byte lines
 };
 
 // Device view of a workspace.
@@ -242,10 +250,12 @@ struct PhotonDev {
   const uint32_t* win_tri;    // [n_win] window triangle ids
   float4* rec;                // [cap][rq]: (pos, id lo bits) (dir, vertex | id hi << 8) flux quads
   uint32_t* bcount;           // [n_buckets] photons per bucket, then scatter cursors
-  uint32_t* bstart;           // [n_buckets + 1] first record of each bucket in `sorted`
-  uint32_t* sorted;           // [cap] record indices ordered by bucket
+  uint32_t* bstart;           // [n_buckets + 1] first entry of each bucket in `cand`
+  float4* cand;               // [cap] in bucket order: (pos, record index bits)
+  uint32_t* bsum;             // [n_buckets / kPhotonScanChunk + 1] scan partial sums
+  uint32_t* occ;              // [kPhotonOccWords] bit h: some record lies in a super-cell of hash h
   uint32_t n_win, cap, n_buckets, rq;  // rq = 2 + Bp / 4 float4 per record
-  float radius, inv_cell;     // gather radius, 1 / (2 radius)
+  float radius, inv_cell;     // gather radius = grid cell size, 1 / radius
   float flux_scale;           // A / N: flux of a photon per unit of sun irradiance
   uint32_t seed_lo, seed_hi;
   int32_t max_depth;

@@ -2064,124 +2064,375 @@ __global__ __launch_bounds__(kWG) void k_photon_shade(DevScene S, DevWS w, Photo
   }
 }
 
-// Hashed uniform grid over the stored photons, cell size 2 r: a gather ball lies inside the
-// 2 x 2 x 2 block of cells around the cell corner nearest its centre. A cell's bucket is the
-// spatial hash of Teschner et al. (2003) of its integer coordinates; a bucket may hold several
-// cells, so every photon read is still tested against the ball.
-__device__ __forceinline__ uint32_t photon_bucket(uint32_t n_buckets, int ix, int iy, int iz) {
-  return ((uint32_t)ix * 73856093u ^ (uint32_t)iy * 19349663u ^ (uint32_t)iz * 83492791u) & (n_buckets - 1u);
+// Uniform grid over the stored photons with cells of the gather radius r: a gather ball meets
+// the 3 x 3 x 3 block of cells around its centre's cell, of which only those whose box lies
+// closer than r to the centre are read. Cell (i, j, k) goes to the bucket whose low 6 bits are
+// (i mod 4, j mod 4, k mod 4), so the 27 cells of one block are 27 distinct buckets, and whose
+// high bits are the spatial hash of Teschner et al. (2003) of the 4 x 4 x 4 super-cell
+// (i >> 2, j >> 2, k >> 2), which spreads the occupied super-cells over the table; cells that
+// share a bucket are still told apart by testing every entry read against the ball.
+__device__ __forceinline__ uint32_t super_hash(int sx, int sy, int sz) {
+  return (uint32_t)sx * 73856093u ^ (uint32_t)sy * 19349663u ^ (uint32_t)sz * 83492791u;
 }
+__device__ __forceinline__ uint32_t photon_bucket(const PhotonDev& P, int ix, int iy, int iz) {
+  const uint32_t lo = ((uint32_t)ix & 3u) | (((uint32_t)iy & 3u) << 2) | (((uint32_t)iz & 3u) << 4);
+  return lo | ((super_hash(ix >> 2, iy >> 2, iz >> 2) << 6) & (P.n_buckets - 1u));
+}
+// occupancy bit of the super-cell holding cell (i, j, k)
+constexpr uint32_t kOccMask = kPhotonOccWords * 32u - 1u;
+__device__ __forceinline__ uint32_t occ_bit(int sx, int sy, int sz) { return super_hash(sx, sy, sz) & kOccMask; }
 __device__ __forceinline__ uint32_t photon_bucket_of(const PhotonDev& P, float4 q) {
-  return photon_bucket(P.n_buckets, (int)floorf(q.x * P.inv_cell), (int)floorf(q.y * P.inv_cell),
-                       (int)floorf(q.z * P.inv_cell));
+  return photon_bucket(P, (int)floorf(q.x * P.inv_cell), (int)floorf(q.y * P.inv_cell), (int)floorf(q.z * P.inv_cell));
 }
 
 __global__ void k_photon_count(PhotonDev P) {
   const uint32_t n = min(P.ctl[0], P.cap);
-  for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x)
-    atomicAdd(&P.bcount[photon_bucket_of(P, P.rec[(size_t)r * P.rq])], 1u);
+  for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+    const float4 q = P.rec[(size_t)r * P.rq];
+    const int ix = (int)floorf(q.x * P.inv_cell), iy = (int)floorf(q.y * P.inv_cell), iz = (int)floorf(q.z * P.inv_cell);
+    atomicAdd(&P.bcount[photon_bucket(P, ix, iy, iz)], 1u);
+    const uint32_t h = occ_bit(ix >> 2, iy >> 2, iz >> 2);
+    atomicOr(&P.occ[h >> 5], 1u << (h & 31u));
+  }
 }
 
-// Exclusive prefix sum of the bucket counts (one workgroup: each thread sums a contiguous chunk,
-// the chunk sums are scanned in LDS, each thread writes its chunk's prefixes); the counts are
-// cleared to serve as scatter cursors.
-constexpr int kPhotonScanThreads = 1024;
-__global__ __launch_bounds__(kPhotonScanThreads) void k_photon_scan(PhotonDev P) {
-  __shared__ uint32_t s_sum[kPhotonScanThreads];
-  const uint32_t per = P.n_buckets / kPhotonScanThreads;  // n_buckets is a multiple of 1024
-  const uint32_t b0 = threadIdx.x * per;
-  uint32_t tot = 0;
-  for (uint32_t k = 0; k < per; ++k) tot += P.bcount[b0 + k];
-  s_sum[threadIdx.x] = tot;
+// Exclusive prefix sum of the bucket counts in three passes: the sum of each chunk of
+// kPhotonScanChunk buckets, the scan of the chunk sums (one workgroup), then each chunk's own
+// scan from its offset; the counts are cleared to serve as scatter cursors.
+constexpr int kPhotonScanThreads = 256;
+constexpr int kPhotonScanPer = kPhotonScanChunk / kPhotonScanThreads;
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* s_w, uint32_t& total) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint32_t incl = x;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(incl, o);
+    if (lane >= o) incl += y;
+  }
+  if (lane == 63) s_w[wv] = incl;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t acc = 0;
-    for (int t = 0; t < kPhotonScanThreads; ++t) {
-      const uint32_t x = s_sum[t];
-      s_sum[t] = acc;
-      acc += x;
-    }
-    P.bstart[P.n_buckets] = acc;
+  uint32_t before = 0;
+  total = 0;
+  for (int q = 0; q < kPhotonScanThreads / 64; ++q) {
+    before += q < wv ? s_w[q] : 0u;
+    total += s_w[q];
   }
   __syncthreads();
-  uint32_t acc = s_sum[threadIdx.x];
-  for (uint32_t k = 0; k < per; ++k) {
-    const uint32_t c = P.bcount[b0 + k];
+  return before + incl - x;
+}
+__global__ __launch_bounds__(kPhotonScanThreads) void k_photon_chunk_sums(PhotonDev P) {
+  __shared__ uint32_t s_w[kPhotonScanThreads / 64];
+  const uint32_t b0 = blockIdx.x * kPhotonScanChunk + threadIdx.x * kPhotonScanPer;
+  uint32_t t = 0;
+#pragma unroll
+  for (int k = 0; k < kPhotonScanPer; ++k) t += P.bcount[b0 + k];
+  uint32_t total;
+  block_excl_scan(t, s_w, total);
+  if (threadIdx.x == 0) P.bsum[blockIdx.x] = total;
+}
+__global__ __launch_bounds__(kPhotonScanThreads) void k_photon_scan_sums(PhotonDev P, uint32_t n_chunks) {
+  __shared__ uint32_t s_w[kPhotonScanThreads / 64];
+  uint32_t carry = 0;
+  for (uint32_t c0 = 0; c0 < n_chunks; c0 += kPhotonScanThreads) {
+    const uint32_t c = c0 + threadIdx.x;
+    const uint32_t x = c < n_chunks ? P.bsum[c] : 0u;
+    uint32_t total;
+    const uint32_t ex = block_excl_scan(x, s_w, total);
+    if (c < n_chunks) P.bsum[c] = carry + ex;
+    carry += total;
+  }
+  if (threadIdx.x == 0) P.bstart[P.n_buckets] = carry;
+}
+__global__ __launch_bounds__(kPhotonScanThreads) void k_photon_chunk_scan(PhotonDev P) {
+  __shared__ uint32_t s_w[kPhotonScanThreads / 64];
+  const uint32_t b0 = blockIdx.x * kPhotonScanChunk + threadIdx.x * kPhotonScanPer;
+  uint32_t c[kPhotonScanPer], t = 0;
+#pragma unroll
+  for (int k = 0; k < kPhotonScanPer; ++k) {
+    c[k] = P.bcount[b0 + k];
+    t += c[k];
+  }
+  uint32_t total;
+  uint32_t acc = P.bsum[blockIdx.x] + block_excl_scan(t, s_w, total);
+#pragma unroll
+  for (int k = 0; k < kPhotonScanPer; ++k) {
     P.bstart[b0 + k] = acc;
     P.bcount[b0 + k] = 0;
-    acc += c;
+    acc += c[k];
   }
 }
 
+// Records into bucket order: each bucket's entries hold the position the gathering tests
+// (contiguous per bucket) and the record's index, through which the direction and flux of a
+// record within the radius are read.
 __global__ void k_photon_scatter(PhotonDev P) {
   const uint32_t n = min(P.ctl[0], P.cap);
   for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
-    const uint32_t b = photon_bucket_of(P, P.rec[(size_t)r * P.rq]);
-    P.sorted[P.bstart[b] + atomicAdd(&P.bcount[b], 1u)] = r;
+    const float4 q0 = P.rec[(size_t)r * P.rq];
+    const uint32_t b = photon_bucket_of(P, q0);
+    const uint32_t e = P.bstart[b] + atomicAdd(&P.bcount[b], 1u);
+    P.cand[e] = make_float4(q0.x, q0.y, q0.z, __uint_as_float(r));
   }
 }
 
+// The cells of the 3 x 3 x 3 block around a point that a ball of radius r (one cell) about it
+// can reach: per axis the squared gap (in cells) to the lower neighbour, the own cell and the
+// upper neighbour; a cell is read when the gaps of its three axes sum below one (with a margin
+// of 1e-3 for the rounding of the point's cell coordinates).
+struct CellBlock {
+  int ix, iy, iz;
+  float gx[3], gy[3], gz[3];
+};
+__device__ __forceinline__ CellBlock cell_block(const PhotonDev& P, F3 p) {
+  CellBlock C;
+  const float cx = p.x * P.inv_cell, cy = p.y * P.inv_cell, cz = p.z * P.inv_cell;
+  const float fx = floorf(cx), fy = floorf(cy), fz = floorf(cz);
+  C.ix = (int)fx;
+  C.iy = (int)fy;
+  C.iz = (int)fz;
+  const float ux = cx - fx, uy = cy - fy, uz = cz - fz;  // exact, in [0, 1)
+  C.gx[0] = ux * ux; C.gx[1] = 0.0f; C.gx[2] = (1.0f - ux) * (1.0f - ux);
+  C.gy[0] = uy * uy; C.gy[1] = 0.0f; C.gy[2] = (1.0f - uy) * (1.0f - uy);
+  C.gz[0] = uz * uz; C.gz[1] = 0.0f; C.gz[2] = (1.0f - uz) * (1.0f - uz);
+  return C;
+}
+constexpr float kCellReach = 1.001f;
+
 // Caustic radiance at the opaque vertices of a bounce, before their shading changes the
 // throughput: (1 - F_j) rho_j / pi times the flux of the photons within the gather radius that
-// arrived from the side the path sees, over pi r^2, added to the gathered radiance. A thread's
-// flux sums wait in LDS, laid out lane-contiguous ([quad][lane]) so that the wave's accesses
-// fall on distinct banks.
+// arrived from the side the path sees, over pi r^2, added to the gathered radiance. A vertex
+// whose block of cells touches no occupied super-cell (a bitmap in LDS) has nothing to gather; one
+// whose own cell holds more than kGatherHeavy entries goes to the wave-wide pass. Otherwise the
+// cells are read one 3 x 3 slab at a time (nine ranges loaded together), four entries at a time;
+// an entry within the ball reads its record's direction, and its flux when it arrived from the
+// side the path sees.
+// NQ > 0: rows of NQ quads, the flux sums in registers; NQ = 0: any row length, the sums in
+// dynamic LDS laid out lane-contiguous ([quad][lane], distinct banks across the wave).
 constexpr int kGatherWG = 64;
+constexpr uint32_t kGatherHeavy = 24;  // entries in the vertex's own cell above which it goes wave-wide
+
+__device__ __forceinline__ float gap_of(const float (&g)[3], int o) { return o == 0 ? g[0] : (o == 1 ? 0.0f : g[2]); }
+
+template <int NQ>
 __global__ __launch_bounds__(kGatherWG) void k_photon_gather(DevScene S, DevWS w, PhotonDev P, int depth) {
-  __shared__ float4 s_sum[kMaxBins / 4][kGatherWG];
+  extern __shared__ float4 s_dyn[];
+  __shared__ uint32_t s_occ[kPhotonOccWords];
+  for (int q = threadIdx.x; q < kPhotonOccWords; q += kGatherWG) s_occ[q] = P.occ[q];
+  __syncthreads();
   const int p = depth & 1;
   const uint32_t n = w.ctl->cat_count[p][kCatOpaque * kKeyStride];
   const uint32_t* list = cat_list(w, p, kCatOpaque);
-  const int Bp = w.Bp, nq = Bp / 4;
+  const int Bp = w.Bp, nq = NQ > 0 ? NQ : Bp / 4;
   const float r = P.radius, r2 = r * r;
   const float norm = 1.0f / (3.14159265358979f * 3.14159265358979f * r2);  // 1 / pi (BRDF) / (pi r^2)
   const int lane = threadIdx.x;
+  if (blockIdx.x == 0 && lane == 0) w.ctl->ph_heavy[p ^ 1] = 0;  // the other parity's pass is done
+  float4 acc_r[NQ > 0 ? NQ : 1];
+  auto acc = [&](int q) -> float4& { return NQ > 0 ? acc_r[q] : s_dyn[q * kGatherWG + lane]; };
+  uint32_t n_found = 0, n_vert = 0, n_lit = 0, n_cand = 0, m_cand = 0;
   for (uint32_t a = blockIdx.x * kGatherWG + threadIdx.x; a < n; a += gridDim.x * kGatherWG) {
     const uint32_t s = list[a];
+    ++n_vert;
     const Vertex V = load_vertex(S, w, s);
-    for (int q = 0; q < nq; ++q) s_sum[q][lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    // the 2 x 2 x 2 cells around the nearest cell corner
-    const float cx = V.p.x * P.inv_cell, cy = V.p.y * P.inv_cell, cz = V.p.z * P.inv_cell;
-    const int ix = (int)floorf(cx), iy = (int)floorf(cy), iz = (int)floorf(cz);
-    const int x0 = cx - (float)ix < 0.5f ? ix - 1 : ix;
-    const int y0 = cy - (float)iy < 0.5f ? iy - 1 : iy;
-    const int z0 = cz - (float)iz < 0.5f ? iz - 1 : iz;
-    uint32_t seen[8];
+    const CellBlock C = cell_block(P, V.p);
+    // nothing to gather when no record lies in the super-cells that the block's cells touch
+    bool occupied = false;
+    {
+      const int sx0 = (C.ix - 1) >> 2, sx1 = (C.ix + 1) >> 2, sy0 = (C.iy - 1) >> 2, sy1 = (C.iy + 1) >> 2;
+      const int sz0 = (C.iz - 1) >> 2, sz1 = (C.iz + 1) >> 2;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const uint32_t h = occ_bit((c & 1) ? sx1 : sx0, (c & 2) ? sy1 : sy0, (c & 4) ? sz1 : sz0);
+        occupied |= (s_occ[h >> 5] >> (h & 31u)) & 1u;
+      }
+    }
+    if (!occupied) continue;
+    // a vertex whose own cell holds many entries goes to the wave-wide pass (one wave per
+    // vertex), which keeps a wave of this pass from waiting on its one lane in a dense caustic
+    const uint32_t b_own = photon_bucket(P, C.ix, C.iy, C.iz);
+    const bool heavy = P.bstart[b_own + 1] - P.bstart[b_own] > kGatherHeavy;
+    const uint64_t hm = __ballot(heavy);
+    if (hm) {
+      const uint32_t leader = (uint32_t)__ffsll((unsigned long long)hm) - 1u;
+      uint32_t base = 0;
+      if ((uint32_t)lane == leader) base = atomicAdd(&w.ctl->ph_heavy[p], (uint32_t)__popcll(hm));
+      base = __shfl(base, (int)leader);
+      if (heavy) w.queue[base + count_below(hm)] = s;
+    }
+    if (heavy) continue;
+    uint32_t v_cand = 0;
+    for (int q = 0; q < nq; ++q) acc(q) = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     bool any = false;
+#pragma unroll 1
+    for (int oz = 0; oz < 3; ++oz) {
+      const float gz = gap_of(C.gz, oz);
+      uint32_t e0[9], e1[9];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      const uint32_t b = photon_bucket(P.n_buckets, x0 + (c & 1), y0 + ((c >> 1) & 1), z0 + (c >> 2));
-      seen[c] = b;
-      bool dup = false;
+      for (int k = 0; k < 9; ++k) {
+        const int ox = k % 3, oy = k / 3;
+        const bool vis = C.gx[ox] + C.gy[oy] + gz < kCellReach;
+        const uint32_t b = photon_bucket(P, C.ix + ox - 1, C.iy + oy - 1, C.iz + oz - 1);
+        e0[k] = vis ? P.bstart[b] : 0u;
+        e1[k] = vis ? P.bstart[b + 1] : 0u;
+      }
 #pragma unroll
-      for (int k = 0; k < c; ++k) dup |= seen[k] == b;
-      if (dup) continue;
-      const uint32_t e1 = P.bstart[b + 1];
-      for (uint32_t e = P.bstart[b]; e < e1; ++e) {
-        const float4* rec = P.rec + (size_t)P.sorted[e] * P.rq;
-        const float4 q0 = rec[0], q1 = rec[1];
-        const float dx = q0.x - V.p.x, dy = q0.y - V.p.y, dz = q0.z - V.p.z;
-        if (dx * dx + dy * dy + dz * dz < r2 && q1.x * V.n.x + q1.y * V.n.y + q1.z * V.n.z < 0.0f) {
-          any = true;
-          for (int q = 0; q < nq; ++q) {
-            const float4 f = rec[2 + q], t = s_sum[q][lane];
-            s_sum[q][lane] = make_float4(t.x + f.x, t.y + f.y, t.z + f.z, t.w + f.w);
+      for (int k = 0; k < 9; ++k) v_cand += e1[k] - e0[k];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        const uint32_t end = e1[k];
+        for (uint32_t e = e0[k]; e < end; e += 4) {
+          float4 q0[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) q0[j] = P.cand[min(e + (uint32_t)j, end - 1u)];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const float dx = q0[j].x - V.p.x, dy = q0[j].y - V.p.y, dz = q0[j].z - V.p.z;
+            if (e + (uint32_t)j < end && dx * dx + dy * dy + dz * dz < r2) {
+              // the direction and the flux row in one round trip (nearly every record within
+              // the ball arrived from the side the path sees)
+              const float4* R = P.rec + (size_t)__float_as_uint(q0[j].w) * P.rq;
+              if constexpr (NQ > 0) {
+                float4 x[NQ];
+                const float4 q1 = R[1];
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) x[q] = R[2 + q];
+                if (q1.x * V.n.x + q1.y * V.n.y + q1.z * V.n.z < 0.0f) {
+#pragma unroll
+                  for (int q = 0; q < NQ; ++q)
+                    acc_r[q] = make_float4(acc_r[q].x + x[q].x, acc_r[q].y + x[q].y, acc_r[q].z + x[q].z,
+                                           acc_r[q].w + x[q].w);
+                  any = true;
+                  ++n_found;
+                }
+              } else {
+                const float4 q1 = R[1];
+                if (q1.x * V.n.x + q1.y * V.n.y + q1.z * V.n.z < 0.0f) {
+                  for (int q = 0; q < nq; ++q) {
+                    const float4 x = R[2 + q], t = acc(q);
+                    acc(q) = make_float4(t.x + x.x, t.y + x.y, t.z + x.z, t.w + x.w);
+                  }
+                  any = true;
+                  ++n_found;
+                }
+              }
+            }
           }
         }
       }
     }
+    n_cand += v_cand;
+    m_cand = max(m_cand, v_cand);
     if (!any) continue;
+    ++n_lit;
     const float4* nt = (const float4*)(S.ntab + V.m * Bp);
     const float4* kt = (const float4*)(S.ktab + V.m * Bp);
     const float4* rt = (const float4*)(S.rho + V.m * Bp);
     const float4* b4 = (const float4*)(w.beta + (size_t)s * Bp);
-    row_update<8>((float4*)(w.lacc + (size_t)s * Bp), nq, [&](int q, float4 l) {
-      const float4 nn = nt[q], kk = kt[q], rr = rt[q], b = b4[q], f = s_sum[q][lane];
+    row_update<2>((float4*)(w.lacc + (size_t)s * Bp), nq, [&](int q, float4 l) {
+      const float4 nn = nt[q], kk = kt[q], rr = rt[q], b = b4[q], f = acc(q);
       const float F0 = fresnel(nn.x, kk.x, V.cos_o), F1 = fresnel(nn.y, kk.y, V.cos_o);
       const float F2 = fresnel(nn.z, kk.z, V.cos_o), F3v = fresnel(nn.w, kk.w, V.cos_o);
       return make_float4(l.x + b.x * (1.0f - F0) * rr.x * f.x * norm, l.y + b.y * (1.0f - F1) * rr.y * f.y * norm,
                          l.z + b.z * (1.0f - F2) * rr.z * f.z * norm, l.w + b.w * (1.0f - F3v) * rr.w * f.w * norm);
     });
+  }
+  // one atomic per wave and counter (the workgroup is one wave)
+  for (int o = 32; o > 0; o >>= 1) {
+    n_found += __shfl_xor(n_found, o);
+    n_vert += __shfl_xor(n_vert, o);
+    n_lit += __shfl_xor(n_lit, o);
+    n_cand += __shfl_xor(n_cand, o);
+    m_cand = max(m_cand, (uint32_t)__shfl_xor(m_cand, o));
+  }
+  if (lane == 0 && n_vert) {
+    atomicAdd(&w.ctl->st_ph_vertices, (unsigned long long)n_vert);
+    atomicAdd(&w.ctl->st_ph_found, (unsigned long long)n_found);
+    if (n_lit) atomicAdd(&w.ctl->st_ph_lit, (unsigned long long)n_lit);
+    atomicAdd(&w.ctl->st_ph_cand, (unsigned long long)n_cand);
+    atomicMax(&w.ctl->st_ph_cand_max, (unsigned long long)m_cand);
+  }
+}
+
+// The deferred vertices of a bounce (their slots in the queue buffer, which no kernel uses
+// between two traversal phases), one wave each: for every reachable cell the lanes test its
+// entries k = lane, lane + 64, ... (consecutive entries across the wave), each summing the flux of
+// the ones it finds, then the wave adds its 64 partial sums per bin in a fixed butterfly order and
+// lane q updates quad q of the gathered radiance.
+template <int NQ>
+__global__ __launch_bounds__(kGatherWG) void k_photon_gather_heavy(DevScene S, DevWS w, PhotonDev P, int depth) {
+  const int p = depth & 1;
+  const uint32_t n = w.ctl->ph_heavy[p];
+  const int Bp = w.Bp, nq = Bp / 4;
+  const float r = P.radius, r2 = r * r;
+  const float norm = 1.0f / (3.14159265358979f * 3.14159265358979f * r2);
+  const int lane = threadIdx.x;
+  constexpr int kQ = NQ > 0 ? NQ : kMaxBins / 4;
+  uint32_t n_found = 0, n_lit = 0;
+  for (uint32_t h = blockIdx.x; h < n; h += gridDim.x) {
+    const uint32_t s = w.queue[h];
+    const Vertex V = load_vertex(S, w, s);
+    const CellBlock C = cell_block(P, V.p);
+    float4 acc[kQ];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) acc[q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    uint32_t v_found = 0;
+#pragma unroll 1
+    for (int c = 0; c < 27; ++c) {
+      const int ox = c % 3, oy = (c / 3) % 3, oz = c / 9;
+      if (!(gap_of(C.gx, ox) + gap_of(C.gy, oy) + gap_of(C.gz, oz) < kCellReach)) continue;
+      const uint32_t b = photon_bucket(P, C.ix + ox - 1, C.iy + oy - 1, C.iz + oz - 1);
+      const uint32_t e0 = P.bstart[b], cnt = P.bstart[b + 1] - e0;
+      for (uint32_t k = (uint32_t)lane; k < cnt; k += kGatherWG) {
+        const float4 q0 = P.cand[(size_t)e0 + k];
+        const float dx = q0.x - V.p.x, dy = q0.y - V.p.y, dz = q0.z - V.p.z;
+        if (dx * dx + dy * dy + dz * dz < r2) {
+          const float4* R = P.rec + (size_t)__float_as_uint(q0.w) * P.rq;
+          const float4 q1 = R[1];
+          if (q1.x * V.n.x + q1.y * V.n.y + q1.z * V.n.z < 0.0f) {
+#pragma unroll
+            for (int q = 0; q < kQ; ++q)
+              if (q < nq) {
+                const float4 x = R[2 + q];
+                acc[q] = make_float4(acc[q].x + x.x, acc[q].y + x.y, acc[q].z + x.z, acc[q].w + x.w);
+              }
+            ++v_found;
+          }
+        }
+      }
+    }
+    n_found += v_found;
+    for (int o = 32; o > 0; o >>= 1) v_found += __shfl_xor(v_found, o);
+    n_lit += v_found != 0;  // the same on every lane: added once, by lane 0 below
+    // butterfly sums: every lane ends with the wave's totals, quad q kept by lane q
+    float4 mine = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      if (q < nq) {
+        float4 t = acc[q];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1)
+          t = make_float4(t.x + __shfl_xor(t.x, o), t.y + __shfl_xor(t.y, o), t.z + __shfl_xor(t.z, o),
+                          t.w + __shfl_xor(t.w, o));
+        if (lane == q) mine = t;
+      }
+    }
+    if (lane < nq) {
+      const int q = lane;
+      const float4 nn = ((const float4*)(S.ntab + V.m * Bp))[q], kk = ((const float4*)(S.ktab + V.m * Bp))[q];
+      const float4 rr = ((const float4*)(S.rho + V.m * Bp))[q];
+      const float4 b = ((const float4*)(w.beta + (size_t)s * Bp))[q];
+      float4* lp = (float4*)(w.lacc + (size_t)s * Bp) + q;
+      const float4 l = *lp, f = mine;
+      const float F0 = fresnel(nn.x, kk.x, V.cos_o), F1 = fresnel(nn.y, kk.y, V.cos_o);
+      const float F2 = fresnel(nn.z, kk.z, V.cos_o), F3v = fresnel(nn.w, kk.w, V.cos_o);
+      *lp = make_float4(l.x + b.x * (1.0f - F0) * rr.x * f.x * norm, l.y + b.y * (1.0f - F1) * rr.y * f.y * norm,
+                        l.z + b.z * (1.0f - F2) * rr.z * f.z * norm, l.w + b.w * (1.0f - F3v) * rr.w * f.w * norm);
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) n_found += __shfl_xor(n_found, o);
+  if (lane == 0 && n_found) {
+    atomicAdd(&w.ctl->st_ph_found, (unsigned long long)n_found);
+    atomicAdd(&w.ctl->st_ph_lit, (unsigned long long)n_lit);
   }
 }
 
@@ -2323,16 +2574,33 @@ hipError_t launch_photon_shade(const Launch& L, const DevScene& S, const DevWS& 
   return hipGetLastError();
 }
 hipError_t launch_photon_build(hipStream_t s, const PhotonDev& P) {
+  const uint32_t n_chunks = P.n_buckets / kPhotonScanChunk;  // n_buckets is a multiple of the chunk
   hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(P.n_buckets)), dim3(256), 0, s, P.bcount, (size_t)P.n_buckets, 0u);
+  hipLaunchKernelGGL(k_fill_u32, dim3(4), dim3(256), 0, s, P.occ, (size_t)kPhotonOccWords, 0u);
   hipLaunchKernelGGL(k_photon_count, dim3(grid_for(P.cap)), dim3(256), 0, s, P);
-  hipLaunchKernelGGL(k_photon_scan, dim3(1), dim3(kPhotonScanThreads), 0, s, P);
+  hipLaunchKernelGGL(k_photon_chunk_sums, dim3(n_chunks), dim3(kPhotonScanThreads), 0, s, P);
+  hipLaunchKernelGGL(k_photon_scan_sums, dim3(1), dim3(kPhotonScanThreads), 0, s, P, n_chunks);
+  hipLaunchKernelGGL(k_photon_chunk_scan, dim3(n_chunks), dim3(kPhotonScanThreads), 0, s, P);
   hipLaunchKernelGGL(k_photon_scatter, dim3(grid_for(P.cap)), dim3(256), 0, s, P);
   return hipGetLastError();
 }
 hipError_t launch_photon_gather(const Launch& L, const DevScene& S, const DevWS& w, const PhotonDev& P, int depth) {
   const size_t want = ((size_t)w.W + kGatherWG - 1) / kGatherWG;
-  hipLaunchKernelGGL(k_photon_gather, dim3((unsigned)(want < 16384 ? want : 16384)), dim3(kGatherWG), 0, L.stream, S,
-                     w, P, depth);
+  const dim3 g((unsigned)(want < 16384 ? want : 16384)), b(kGatherWG), gh(16384);
+  switch (w.Bp / 4) {
+    case 2:
+      hipLaunchKernelGGL(k_photon_gather<2>, g, b, 0, L.stream, S, w, P, depth);
+      hipLaunchKernelGGL(k_photon_gather_heavy<2>, gh, b, 0, L.stream, S, w, P, depth);
+      break;
+    case 10:
+      hipLaunchKernelGGL(k_photon_gather<10>, g, b, 0, L.stream, S, w, P, depth);
+      hipLaunchKernelGGL(k_photon_gather_heavy<10>, gh, b, 0, L.stream, S, w, P, depth);
+      break;
+    default:
+      hipLaunchKernelGGL(k_photon_gather<0>, g, b, (size_t)(w.Bp / 4) * kGatherWG * sizeof(float4), L.stream, S, w,
+                         P, depth);
+      hipLaunchKernelGGL(k_photon_gather_heavy<0>, gh, b, 0, L.stream, S, w, P, depth);
+  }
   return hipGetLastError();
 }
 
