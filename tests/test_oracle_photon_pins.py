@@ -100,3 +100,16 @@ def test_emission_flux_and_area():
     wr, wt = T[0] / P_r, T[1] * F / (1 - P_r)
     sd = np.abs(wr - wt) * math.sqrt(P_r * (1 - P_r) / 400_000) * sc.sun_E.astype(np.float64) * A
     assert np.all(np.abs(tot - exp) <= 5 * sd + 1e-12), (tot, exp, sd)
+
+
+def test_stride_sample_is_the_full_maps_records():
+    """Tracing every k-th photon reproduces exactly the records those photons leave in the full
+    map (each photon is traced from its own counter; its flux is E A / N for the full N)."""
+    sc = scenegen.nave_scene(8)
+    full = oracle.photons(sc, 30_000, max_depth=6, seed=3)
+    part = oracle.photons(sc, 30_000, max_depth=6, seed=3, stride=7)
+    sel = full["id"] % 7 == 0
+    assert sel.sum() == len(part["id"]) > 50
+    for k in ("id", "depth", "pos", "dir", "flux"):
+        assert np.array_equal(full[k][sel], part[k]), k
+    assert np.array_equal(full["tied"][::7], part["tied"][::7]) and part["area"] == full["area"]
