@@ -60,13 +60,16 @@ class _Params(C.Structure):
                 ("tie_cos_sun", C.c_double), ("cached", C.c_int32), ("first_sample", C.c_int32),
                 ("purpose", C.c_uint32), ("record_depth", C.c_int32), ("sample_per_entry", C.c_int32),
                 ("ph_pos", C.c_void_p), ("ph_dir", C.c_void_p), ("ph_flux", C.c_void_p), ("n_photons", C.c_int64),
-                ("ph_radius", C.c_double), ("tie_radius", C.c_double), ("ph_unc", C.c_void_p)]
+                ("ph_radius", C.c_double), ("tie_radius", C.c_double), ("ph_unc", C.c_void_p),
+                ("gl_pos", C.c_void_p), ("gl_dir", C.c_void_p), ("gl_flux", C.c_void_p), ("n_global", C.c_int64),
+                ("gl_radius", C.c_double), ("gl_depth", C.c_int32), ("pad_gl", C.c_int32)]
 
 
 class _PhotonParams(C.Structure):
     _fields_ = [("n_photons", C.c_int64), ("max_depth", C.c_int32), ("seed", C.c_uint64), ("threads", C.c_int32),
                 ("tie_t_rel", C.c_double), ("tie_edge_abs", C.c_double), ("tie_edge_rel_t", C.c_double),
-                ("tie_lobe", C.c_double), ("tie_cos_sun", C.c_double), ("stride", C.c_int64)]
+                ("tie_lobe", C.c_double), ("tie_cos_sun", C.c_double), ("stride", C.c_int64),
+                ("global_map", C.c_int32), ("pad", C.c_int32)]
 
 
 class _Queries(C.Structure):
@@ -208,24 +211,34 @@ class RenderResult:
 
 def render(scene, camera, spp=1, max_depth=4, seed=1, view=0, pixels=None, threads=None,
            tie: TieParams = TieParams(), force_bvh=-1, cached=False, first_sample=0, purpose=0,
-           sample_per_entry=False, photons=None, radius=0.0, tie_radius=1e-4) -> RenderResult:
+           sample_per_entry=False, photons=None, radius=0.0, tie_radius=1e-4, global_photons=None,
+           global_radius=0.0, global_depth=0) -> RenderResult:
     """Reference spectral image (mean of spp path samples per pixel), FP64 accumulation.
     With cached=True the paths stop at the vertex after bounce 2 and the query there
     (position, direction toward the previous vertex, material, throughput) is returned.
     purpose is added to the depth word of every random-number counter; with sample_per_entry
-    entry i of ``pixels`` is one path (spp = 1) with sample index first_sample + i."""
+    entry i of ``pixels`` is one path (spp = 1) with sample index first_sample + i.
+    photons / radius: a caustic map gathered at every opaque vertex; global_photons /
+    global_radius / global_depth: from vertex global_depth on, the diffuse radiance of every opaque
+    vertex comes from the global map (no direct term or caustic map there) and the path continues
+    by the mirror lobe only (global_depth 0 with a map given: as 0, no global mode)."""
     s, keep = _scene_struct(scene)
     cam = _Camera((C.c_double * 3)(*camera.eye), (C.c_double * 3)(*camera.target), (C.c_double * 3)(*camera.up),
                   float(camera.vfov_deg), int(camera.width), int(camera.height))
     th = threads or min(8, os.cpu_count() or 1)
     prm = _Params(int(spp), int(max_depth), int(seed), int(view), int(th), int(force_bvh), tie.t_rel, tie.edge_abs,
                   tie.edge_rel_t, tie.lobe, tie.cos_sun, 1 if cached else 0, int(first_sample), int(purpose), 0,
-                  1 if sample_per_entry else 0, None, None, None, 0, float(radius), float(tie_radius), None)
+                  1 if sample_per_entry else 0, None, None, None, 0, float(radius), float(tie_radius), None,
+                  None, None, None, 0, float(global_radius), int(global_depth), 0)
     unc = None
     if photons is not None and len(photons["id"]) > 0:
         keep_ph = [np.ascontiguousarray(photons[k], dtype=np.float64) for k in ("pos", "dir", "flux")]
         prm.ph_pos, prm.ph_dir, prm.ph_flux = (_p(a).value for a in keep_ph)
         prm.n_photons = len(photons["id"])
+    if global_photons is not None and len(global_photons["id"]) > 0:
+        keep_gl = [np.ascontiguousarray(global_photons[k], dtype=np.float64) for k in ("pos", "dir", "flux")]
+        prm.gl_pos, prm.gl_dir, prm.gl_flux = (_p(a).value for a in keep_gl)
+        prm.n_global = len(global_photons["id"])
     B = scene.n_bins
     if pixels is None:
         npx = camera.width * camera.height
@@ -236,7 +249,7 @@ def render(scene, camera, spp=1, max_depth=4, seed=1, view=0, pixels=None, threa
     img = np.zeros((B, npx))
     tied = np.zeros(npx, dtype=np.int32)
     st = np.zeros(4, dtype=np.int64)
-    if prm.n_photons > 0:
+    if prm.n_photons > 0 or prm.n_global > 0:
         unc = np.zeros((B, npx))
         prm.ph_unc = _p(unc).value
     q = None
@@ -258,17 +271,19 @@ def render(scene, camera, spp=1, max_depth=4, seed=1, view=0, pixels=None, threa
     return RenderResult(img, tied, stats, q, unc)
 
 
-def photons(scene, n_photons, max_depth=8, seed=1, threads=None, tie: TieParams = TieParams(), stride=1):
+def photons(scene, n_photons, max_depth=8, seed=1, threads=None, tie: TieParams = TieParams(), stride=1,
+            global_map=False):
     """Caustic photon map (see orc_photons): records of photons stored at opaque vertices after at
     least one reflection, ordered by (photon, vertex): pos [n][3], dir [n][3] (direction of
     travel), flux [n][B], id [n] (photon index), depth [n] (vertex); tied [n_photons] flags
     photons whose path FP32 rounding could change; area = the windows' projected area A. With
-    stride k only photons 0, k, 2k, ... are traced (their records are those of the full map)."""
+    stride k only photons 0, k, 2k, ... are traced (their records are those of the full map).
+    global_map: every opaque vertex stores, and the diffuse lobe continues the photon."""
     s, keep = _scene_struct(scene)
     B = scene.n_bins
     th = threads or min(8, os.cpu_count() or 1)
     pp = _PhotonParams(int(n_photons), int(max_depth), int(seed), int(th), tie.t_rel, tie.edge_abs, tie.edge_rel_t,
-                       tie.lobe, tie.cos_sun, int(stride))
+                       tie.lobe, tie.cos_sun, int(stride), 1 if global_map else 0, 0)
     cap = max(1024, int(n_photons) // 2)
     while True:
         pos, dirs = np.zeros((cap, 3)), np.zeros((cap, 3))

@@ -432,7 +432,17 @@ typedef struct {
   int64_t n_photons;
   double ph_radius;
   double tie_radius;         // relative margin of the gather radius: photons within it are uncertain
-  double* ph_unc;            // [B][n_pix] or null: the caustic radiance those photons could change
+  double* ph_unc;            // [B][n_pix] or null: the radiance those photons could change
+  // global photon map (gl_depth = 0: none): at every opaque vertex from vertex gl_depth on, the
+  // diffuse radiance leaving it is the map's density estimate (no direct term, no caustic map),
+  // and the path goes on only by the mirror lobe
+  const double* gl_pos;
+  const double* gl_dir;
+  const double* gl_flux;
+  int64_t n_global;
+  double gl_radius;
+  int32_t gl_depth;
+  int32_t pad_gl;
 } orc_params;
 
 void orc_philox4x32_10(const uint32_t* ctr, const uint32_t* key, uint32_t* out) {
@@ -641,36 +651,44 @@ int orc_render(const orc_scene* sc, const orc_camera* cam, const orc_params* prm
         const float* rt = sc->rho_tab + m * B;
         if (mat_type[m] == 0) {
           for (int j = 0; j < B; ++j) F[j] = fresnel(nt[j], kt[j], cos_o);
-          if (prm->n_photons > 0) {
-            // caustic radiance: (1 - F) rho / pi times the flux of the photons within the gather
-            // radius that arrived from the side the path sees, over the disc area pi r^2; photons
-            // within r (1 +- tie_radius) could fall on either side of r in FP32: their flux bounds
-            // how far another rounding of the same estimate can go
-            const double r = prm->ph_radius, r2 = r * r;
+          // density estimate of a photon map: (1 - F) rho / pi times the flux of the photons
+          // within the gather radius that arrived from the side the path sees, over the disc
+          // area pi r^2; photons within r (1 +- tie_radius) could fall on either side of r in
+          // FP32: their flux bounds how far another rounding of the same estimate can go
+          auto density = [&](const double* mp, const double* md, const double* mf, int64_t nm, double r) {
+            const double r2 = r * r;
             const double lo2 = r2 * (1.0 - prm->tie_radius) * (1.0 - prm->tie_radius);
             const double hi2 = r2 * (1.0 + prm->tie_radius) * (1.0 + prm->tie_radius);
             std::fill(acc_ph.begin(), acc_ph.end(), 0.0);
             std::fill(acc_unc.begin(), acc_unc.end(), 0.0);
-            for (int64_t q = 0; q < prm->n_photons; ++q) {
-              const double* pp = prm->ph_pos + 3 * q;
+            for (int64_t q = 0; q < nm; ++q) {
+              const double* pp = mp + 3 * q;
               const double dx = pp[0] - p.x, dy = pp[1] - p.y, dz = pp[2] - p.z;
               const double d2 = dx * dx + dy * dy + dz * dz;
               if (d2 > hi2) continue;
-              const double* pd = prm->ph_dir + 3 * q;
+              const double* pd = md + 3 * q;
               const double side = pd[0] * n.x + pd[1] * n.y + pd[2] * n.z;
               if (std::fabs(side) <= tie.cos_sun) tied = true;
               if (d2 < r2 && side < 0.0)
-                for (int j = 0; j < B; ++j) acc_ph[j] += prm->ph_flux[q * B + j];
+                for (int j = 0; j < B; ++j) acc_ph[j] += mf[q * B + j];
               if (d2 >= lo2 && side < 0.0)
-                for (int j = 0; j < B; ++j) acc_unc[j] += prm->ph_flux[q * B + j];
+                for (int j = 0; j < B; ++j) acc_unc[j] += mf[q * B + j];
             }
             for (int j = 0; j < B; ++j) Lu[j] += beta[j] * (1.0 - F[j]) * rt[j] / M_PI * acc_unc[j] / (M_PI * r2);
             for (int j = 0; j < B; ++j) L[j] += beta[j] * (1.0 - F[j]) * rt[j] / M_PI * acc_ph[j] / (M_PI * r2);
+          };
+          const bool gm = prm->gl_depth > 0 && dep >= prm->gl_depth;
+          if (gm) {
+            // the global map holds the light arriving here by every route (the sun's direct
+            // light, caustics, interreflections): its estimate is the whole diffuse part
+            if (prm->n_global > 0) density(prm->gl_pos, prm->gl_dir, prm->gl_flux, prm->n_global, prm->gl_radius);
+          } else if (prm->n_photons > 0) {
+            density(prm->ph_pos, prm->ph_dir, prm->ph_flux, prm->n_photons, prm->ph_radius);
           }
           // next-event estimation toward the sun (eq. 3)
           double cs = dot(n, ws);
-          if (cs != 0.0 && std::fabs(cs) <= tie.cos_sun) tied = true;
-          if (cs > 0.0) {
+          if (!gm && cs != 0.0 && std::fabs(cs) <= tie.cos_sun) tied = true;
+          if (!gm && cs > 0.0) {
             ++*ns;
             bool vis = shadow_visibility(S, mat_type, p + n * eps, ws, h.id, tie, &cr, &tied);
             if (vis) {
@@ -696,6 +714,8 @@ int orc_render(const orc_scene* sc, const orc_camera* cam, const orc_params* prm
           if (u0 < Ps) {
             for (int j = 0; j < B; ++j) beta[j] *= F[j] / Ps;
             d = d - ng * (2.0 * dn);
+          } else if (gm) {
+            break;   // the diffuse lobe's light came from the global map
           } else {
             for (int j = 0; j < B; ++j) beta[j] *= (1.0 - F[j]) * rt[j] / (1.0 - Ps);
             double phi = 2.0 * M_PI * u1, rr = std::sqrt(u2);
@@ -791,6 +811,10 @@ int orc_render(const orc_scene* sc, const orc_camera* cam, const orc_params* prm
 //           counts); then the mirror lobe is taken with P_s = mean F / (mean F + mean (1-F) rho)
 //           (weight F / P_s), else the photon ends (a diffuse bounce leaves the caustic paths).
 // Vertex max_depth stores but does not scatter. Records come out ordered by (photon, vertex).
+// Global map (global = 1): an opaque vertex stores every photon, and a photon that does not take
+// the mirror lobe takes the cosine-weighted diffuse lobe (direction from the vertex's second and
+// third uniforms, as for camera paths; weight (1 - F(cos of the new direction)) rho / (1 - P_s),
+// the adjoint of the camera paths' diffuse weight) instead of ending.
 // With stride k > 1 only the photons i = 0, k, 2k, ... are traced (a sample of the same map:
 // every photon still carries E_j A / N).
 // ------------------------------------------------------------------------------------------
@@ -801,6 +825,8 @@ typedef struct {
   int32_t threads;
   double tie_t_rel, tie_edge_abs, tie_edge_rel_t, tie_lobe, tie_cos_sun;
   int64_t stride;
+  int32_t global;            // 1: global map (stored at every opaque vertex, diffuse lobe too)
+  int32_t pad;
 } orc_photon_params;
 
 int64_t orc_photons(const orc_scene* sc, const orc_photon_params* pp, int64_t cap, double* pos, double* dir,
@@ -895,7 +921,7 @@ int64_t orc_photons(const orc_scene* sc, const orc_photon_params* pp, int64_t ca
         const double u0 = unif(rv.x[0]);
         V3 o;
         if (mat_type[m] == 0) {
-          if (reflected) out[th].push_back({p, d, i, dep, beta});
+          if (reflected || pp->global) out[th].push_back({p, d, i, dep, beta});
           if (dep == pp->max_depth) break;
           double a = 0, b = 0;
           for (int j = 0; j < B; ++j) {
@@ -908,11 +934,32 @@ int64_t orc_photons(const orc_scene* sc, const orc_photon_params* pp, int64_t ca
           if (a + b == 0.0) break;
           const double Ps = a / (a + b);
           if (std::fabs(u0 - Ps) <= tie.lobe) tied = true;
-          if (!(u0 < Ps)) break;   // the diffuse lobe ends the photon's caustic path
-          for (int j = 0; j < B; ++j) beta[j] *= F[j] / Ps;
-          d = d - ng * (2.0 * dn);
+          if (u0 < Ps) {
+            for (int j = 0; j < B; ++j) beta[j] *= F[j] / Ps;
+            d = d - ng * (2.0 * dn);
+            reflected = true;
+          } else if (!pp->global) {
+            break;   // the diffuse lobe ends the photon's caustic path
+          } else {
+            const double u1 = unif(rv.x[1]), u2 = unif(rv.x[2]);
+            const double phi = 2.0 * M_PI * u1, rr = std::sqrt(u2);
+            const double lx = rr * std::cos(phi), ly = rr * std::sin(phi), lz = std::sqrt(std::max(0.0, 1.0 - u2));
+            // The diffuse lobe's Fresnel factor belongs to the direction the light leaves in (for
+            // camera paths the direction toward the viewer): a photon carries power the other
+            // way, so its weight takes F at its new direction, cos = lz (the adjoint of the
+            // camera paths' (1 - F(view)) rho)
+            for (int j = 0; j < B; ++j)
+              beta[j] *= (1.0 - fresnel(sc->n_tab[m * B + j], sc->k_tab[m * B + j], lz)) * sc->rho_tab[m * B + j] /
+                         (1.0 - Ps);
+            if (n.z != 0.0 && std::fabs(n.z) <= tie.cos_sun) tied = true;
+            const double sgn = std::copysign(1.0, n.z);
+            const double aa = -1.0 / (sgn + n.z);
+            const double bb = n.x * n.y * aa;
+            const V3 t1{1.0 + sgn * n.x * n.x * aa, sgn * bb, -sgn * n.x};
+            const V3 t2{bb, sgn + n.y * n.y * aa, -n.y};
+            d = t1 * lx + t2 * ly + n * lz;
+          }
           o = p + n * eps;
-          reflected = true;
         } else {
           if (dep == pp->max_depth) break;
           double mr = 0, mt = 0;

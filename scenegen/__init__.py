@@ -353,6 +353,47 @@ def caustic_scene(n_bins=3, floor_n=(1.5, 1.9, 2.6), floor_rho=0.0, sun_zenith_d
     ).check()
 
 
+def window_box_scene(n_bins=4, size=(4.0, 4.0, 3.0), window=(1.2, 1.2), rho=0.6, sun_zenith_deg=25.0,
+                     sun_azimuth_deg=30.0, n=1.5, k=0.02, glass_k=2e-7) -> Scene:
+    """A closed room lit only through a ceiling window: floor, four walls and a ceiling of one
+    diffuse material (index n + ik, albedo rho, constant over the bins), the ceiling pierced by a
+    centred glass pane of the given size; the sun enters only through the pane. Floor at z = 0,
+    the room spans [0, sx] x [0, sy] x [0, sz]."""
+    sx, sy, sz = size
+    wx, wy = window
+    x0, x1 = (sx - wx) / 2, (sx + wx) / 2
+    y0, y1 = (sy - wy) / 2, (sy + wy) / 2
+    tris, mats = [], []
+
+    def quad(c00, c10, c11, c01, m):
+        tris.extend([(c00, c10, c11), (c00, c11, c01)])
+        mats.extend([m, m])
+
+    quad((0, 0, 0), (sx, 0, 0), (sx, sy, 0), (0, sy, 0), 0)            # floor
+    quad((0, 0, 0), (0, sy, 0), (0, sy, sz), (0, 0, sz), 0)            # walls
+    quad((sx, 0, 0), (sx, 0, sz), (sx, sy, sz), (sx, sy, 0), 0)
+    quad((0, 0, 0), (0, 0, sz), (sx, 0, sz), (sx, 0, 0), 0)
+    quad((0, sy, 0), (sx, sy, 0), (sx, sy, sz), (0, sy, sz), 0)
+    # ceiling around the opening: four rectangles
+    quad((0, 0, sz), (0, y0, sz), (sx, y0, sz), (sx, 0, sz), 0)
+    quad((0, y1, sz), (0, sy, sz), (sx, sy, sz), (sx, y1, sz), 0)
+    quad((0, y0, sz), (0, y1, sz), (x0, y1, sz), (x0, y0, sz), 0)
+    quad((x1, y0, sz), (x1, y1, sz), (sx, y1, sz), (sx, y0, sz), 0)
+    quad((x0, y0, sz), (x1, y0, sz), (x1, y1, sz), (x0, y1, sz), 1)   # the pane
+    B = n_bins
+    return Scene(
+        verts=np.asarray(tris, dtype=np.float32), mat=np.asarray(mats, dtype=np.uint16),
+        mat_type=np.array([MAT_OPAQUE, MAT_GLASS], dtype=np.int32),
+        thickness_m=np.array([0.0, 0.005], dtype=np.float32),
+        n_tab=np.array([[n] * B, [1.52] * B], dtype=np.float32),
+        k_tab=np.array([[k] * B, [glass_k] * B], dtype=np.float32),
+        rho_tab=np.array([[rho] * B, [0.0] * B], dtype=np.float32),
+        lambda_min_nm=380.0, lambda_max_nm=780.0,
+        sun_dir=sun_direction(90.0 - sun_zenith_deg, sun_azimuth_deg),
+        sun_E=sun_irradiance(B), env=np.zeros(B, dtype=np.float32), name="window_box",
+    ).check()
+
+
 def furnace_scene(n_bins=8, seed=3, n_boxes=6) -> Scene:
     """Open white-furnace scene: a floor, two glass quads and a few boxes; every material is
     lossless and non-dispersive (k = 0, rho = 1), env = 1 and the sun is off."""
