@@ -441,6 +441,15 @@ int sdd_cache_get_records(sdd_ctx* ctx, sdd_cache* cache, int64_t n, float* rec_
  * arrival, the photon index and the vertex number. */
 typedef struct sdd_photon_map sdd_photon_map;
 
+/* Kinds of photon map. A global map (section 4: a map for the global illumination) stores every
+ * photon at every opaque vertex it reaches, including the first (direct sunlight through the
+ * windows), and continues it at an opaque vertex by the mirror lobe (as above) or else by the
+ * cosine-weighted diffuse lobe, direction from the vertex's second and third uniforms as for camera
+ * paths, weight (1 - F(cos of the new direction)) rho / (1 - P_s): the Fresnel factor of the
+ * diffuse lobe is that of the direction the light leaves in (for camera paths the direction
+ * toward the viewer), so a photon, which carries light forward, takes it at its new direction. */
+enum { SDD_PHOTON_CAUSTIC = 0, SDD_PHOTON_GLOBAL = 1 };
+
 typedef struct {
   int64_t n_photons;           /* photons sent out, >= 1; n_photons (max_depth - 1) < 2^32     */
   int32_t max_depth;           /* vertices of a photon path, 2 .. 64                           */
@@ -450,6 +459,8 @@ typedef struct {
                                   dropped)                                                     */
   int32_t wave_paths;          /* photons in flight per wavefront, 64 .. 2^26 (0 = 2^20)       */
   int32_t queue_rounds;        /* traversal rounds per phase as in sdd_render_params (0 = 1)   */
+  int32_t kind;                /* SDD_PHOTON_CAUSTIC or SDD_PHOTON_GLOBAL                      */
+  int32_t pad;
 } sdd_photon_params;
 
 typedef struct {
@@ -491,12 +502,20 @@ int sdd_photon_map_records(sdd_ctx* ctx, sdd_photon_map* map, int64_t n, float* 
  * gathered as if built here. */
 int sdd_photon_map_load(sdd_ctx* ctx, sdd_photon_map* map, int64_t n, const float* pos, const float* dir,
                         const float* flux, const int64_t* id, const int32_t* vertex);
-/* sdd_render (plain mode) with the caustic radiance of the map added at every opaque vertex
- * that is shaded, before its lobe: beta_j (1 - F_j) rho_j / pi times the summed flux of the
- * records within distance r whose direction of arrival d has d . n < 0 (n: the normal on the
- * side the path sees), divided by pi r^2 (the density estimate of photon mapping). use_graph
- * is allowed (the graph reads the map's current contents). */
-int sdd_render_photons(sdd_ctx* ctx, const sdd_scene* scene, const sdd_photon_map* map, const sdd_camera* camera,
+/* sdd_render (plain mode) with photon maps (section 4), either may be NULL but not both. The
+ * density estimate of a map at an opaque vertex adds beta_j (1 - F_j) rho_j / pi times the summed
+ * flux of the records within distance r whose direction of arrival d has d . n < 0 (n: the normal
+ * on the side the path sees), divided by pi r^2, before the vertex's lobe.
+ *  - caustic (SDD_PHOTON_CAUSTIC): estimated at every opaque vertex the path shades before
+ *    vertex global_from (at all of them without a global map), besides the direct term;
+ *  - global (SDD_PHOTON_GLOBAL), from vertex global_from >= 1 on: the estimate is the vertex's
+ *    whole diffuse light (no direct term, no caustic map there) and the path goes on only by the
+ *    mirror lobe (with probability P_s, weight F / P_s), else ends.
+ * use_graph is allowed (the graph reads the maps' current contents). Errors: SDD_ERR_NOT_READY for
+ * a map not built or of other bins, SDD_ERR_INVALID_ARG for a map of the wrong kind, no map, or
+ * global_from < 1 with a global map. */
+int sdd_render_photons(sdd_ctx* ctx, const sdd_scene* scene, const sdd_photon_map* caustic,
+                       const sdd_photon_map* global, int32_t global_from, const sdd_camera* camera,
                        const sdd_render_params* params, void* workspace, size_t workspace_bytes, float* image_dev);
 
 /* Colorimetry of a spectral image (section 6 maps the spectral renderings to RGB by colorimetry;

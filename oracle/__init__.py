@@ -94,7 +94,7 @@ def lib():
         L.orc_shadow.restype = i32
         L.orc_render.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp, vp]
         L.orc_render.restype = i32
-        L.orc_photons.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, vp]
+        L.orc_photons.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp]
         L.orc_photons.restype = i64
         _lib = L
     return _lib
@@ -275,7 +275,8 @@ def photons(scene, n_photons, max_depth=8, seed=1, threads=None, tie: TieParams 
             global_map=False):
     """Caustic photon map (see orc_photons): records of photons stored at opaque vertices after at
     least one reflection, ordered by (photon, vertex): pos [n][3], dir [n][3] (direction of
-    travel), flux [n][B], id [n] (photon index), depth [n] (vertex); tied [n_photons] flags
+    travel), flux [n][B], id [n] (photon index), depth [n] (vertex), tri [n] (the triangle it lies
+    on); tied [n_photons] flags
     photons whose path FP32 rounding could change; area = the windows' projected area A. With
     stride k only photons 0, k, 2k, ... are traced (their records are those of the full map).
     global_map: every opaque vertex stores, and the diffuse lobe continues the photon."""
@@ -289,14 +290,16 @@ def photons(scene, n_photons, max_depth=8, seed=1, threads=None, tie: TieParams 
         pos, dirs = np.zeros((cap, 3)), np.zeros((cap, 3))
         flux = np.zeros((cap, B))
         pid, dep = np.zeros(cap, dtype=np.int64), np.zeros(cap, dtype=np.int32)
+        tri = np.zeros(cap, dtype=np.int32)
         tied = np.zeros(int(n_photons), dtype=np.uint8)
         area = C.c_double()
-        n = lib().orc_photons(C.byref(s), C.byref(pp), cap, _p(pos), _p(dirs), _p(flux), _p(pid), _p(dep), _p(tied),
+        n = lib().orc_photons(C.byref(s), C.byref(pp), cap, _p(pos), _p(dirs), _p(flux), _p(pid), _p(dep), _p(tri),
+                              _p(tied),
                               C.byref(area))
         if n <= cap:
             break
         cap = int(n)
-    return dict(pos=pos[:n], dir=dirs[:n], flux=flux[:n], id=pid[:n], depth=dep[:n], tied=tied.astype(bool),
+    return dict(pos=pos[:n], dir=dirs[:n], flux=flux[:n], id=pid[:n], depth=dep[:n], tri=tri[:n], tied=tied.astype(bool),
                 area=area.value)
 
 

@@ -830,7 +830,7 @@ typedef struct {
 } orc_photon_params;
 
 int64_t orc_photons(const orc_scene* sc, const orc_photon_params* pp, int64_t cap, double* pos, double* dir,
-                    double* flux, int64_t* pid, int32_t* pdepth, uint8_t* tied_out, double* area_out) {
+                    double* flux, int64_t* pid, int32_t* pdepth, int32_t* ptri, uint8_t* tied_out, double* area_out) {
   Scene S;
   load_scene(sc, -1, &S);
   const int B = sc->n_bins;
@@ -866,7 +866,7 @@ int64_t orc_photons(const orc_scene* sc, const orc_photon_params* pp, int64_t ca
   for (size_t w = 0; w < wtri.size(); ++w) thr[w] = (uint32_t)std::floor(cdf[w] / A * 16777216.0);
   const uint32_t k0 = (uint32_t)pp->seed, k1 = (uint32_t)(pp->seed >> 32);
   const uint32_t kPurpose = 4u << 24;
-  struct Rec { V3 p, d; int64_t id; int depth; std::vector<double> f; };
+  struct Rec { V3 p, d; int64_t id; int depth; int tri; std::vector<double> f; };
   const int nt = std::max(1, pp->threads);
   std::vector<std::vector<Rec>> out(nt);
   auto work = [&](int th, int64_t a, int64_t b) {
@@ -921,7 +921,7 @@ int64_t orc_photons(const orc_scene* sc, const orc_photon_params* pp, int64_t ca
         const double u0 = unif(rv.x[0]);
         V3 o;
         if (mat_type[m] == 0) {
-          if (reflected || pp->global) out[th].push_back({p, d, i, dep, beta});
+          if (reflected || pp->global) out[th].push_back({p, d, i, dep, tri, beta});
           if (dep == pp->max_depth) break;
           double a = 0, b = 0;
           for (int j = 0; j < B; ++j) {
@@ -1003,6 +1003,7 @@ int64_t orc_photons(const orc_scene* sc, const orc_photon_params* pp, int64_t ca
         for (int j = 0; j < B; ++j) flux[n * B + j] = r.f[j];
         pid[n] = r.id;
         pdepth[n] = r.depth;
+        if (ptri) ptri[n] = r.tri;
       }
       ++n;
     }

@@ -6,8 +6,9 @@ the stream only.
 """
 from ._binding import (MODE_CACHED, MODE_PLAIN, Cache, CacheConfig, Camera, Context, Daylight, PhotonMap,
                        PhotonParams, RenderParams, Scene, SddError, TrainParams, cache_config, camera, daylight,
-                       daylight_sun, lib, param_count, photon_params, render_params, train_params)
+                       daylight_sun, lib, param_count, photon_params, render_params, train_params, PHOTON_CAUSTIC, PHOTON_GLOBAL)
 
 __all__ = ["Scene", "Context", "Camera", "RenderParams", "SddError", "camera", "render_params", "lib",
            "MODE_PLAIN", "MODE_CACHED", "Cache", "CacheConfig", "TrainParams", "cache_config", "train_params",
-           "param_count", "Daylight", "daylight", "daylight_sun", "PhotonMap", "PhotonParams", "photon_params"]
+           "param_count", "Daylight", "daylight", "daylight_sun", "PhotonMap", "PhotonParams", "photon_params",
+           "PHOTON_CAUSTIC", "PHOTON_GLOBAL"]

@@ -147,7 +147,8 @@ class TrainParams(C.Structure):
 
 class PhotonParams(C.Structure):
     _fields_ = [("n_photons", C.c_int64), ("max_depth", C.c_int32), ("radius", C.c_float), ("seed", C.c_uint64),
-                ("capacity", C.c_int64), ("wave_paths", C.c_int32), ("queue_rounds", C.c_int32)]
+                ("capacity", C.c_int64), ("wave_paths", C.c_int32), ("queue_rounds", C.c_int32),
+                ("kind", C.c_int32), ("pad", C.c_int32)]
 
 
 class PhotonInfo(C.Structure):
@@ -155,10 +156,14 @@ class PhotonInfo(C.Structure):
                 ("window_area", C.c_double), ("device_bytes", C.c_size_t)]
 
 
-def photon_params(n_photons, radius, max_depth=8, seed=1, capacity=None, wave_paths=0, queue_rounds=0) -> PhotonParams:
+PHOTON_CAUSTIC, PHOTON_GLOBAL = 0, 1
+
+
+def photon_params(n_photons, radius, max_depth=8, seed=1, capacity=None, wave_paths=0, queue_rounds=0,
+                  kind=PHOTON_CAUSTIC) -> PhotonParams:
     cap = int(capacity) if capacity is not None else int(n_photons) * (int(max_depth) - 1)
     return PhotonParams(int(n_photons), int(max_depth), float(radius), int(seed), max(1, min(cap, 1 << 28)),
-                        int(wave_paths), int(queue_rounds))
+                        int(wave_paths), int(queue_rounds), int(kind), 0)
 
 
 # Every exported function: (name, restype, argtypes)
@@ -215,7 +220,7 @@ SIGNATURES = [
     ("sdd_photon_map_info", _i32, [_vp, _vp, _vp]),
     ("sdd_photon_map_records", _i32, [_vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp]),
     ("sdd_photon_map_load", _i32, [_vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp]),
-    ("sdd_render_photons", _i32, [_vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    ("sdd_render_photons", _i32, [_vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _sz, _vp]),
 ]
 
 _lib = None
@@ -605,12 +610,17 @@ class Context:
             m.build(scene, finish=finish)
         return m
 
-    def render_photons(self, scene: Scene, pmap, cam: Camera, params: RenderParams, out=None, finish=True):
+    def render_photons(self, scene: Scene, pmap, cam: Camera, params: RenderParams, out=None, finish=True,
+                       global_map=None, global_from=0):
+        """sdd_render_photons: `pmap` the caustic map (or None), `global_map` a global map used
+        from vertex `global_from` on."""
         ws = self.workspace(self.workspace_bytes(scene, params))
         img = out if out is not None else self.torch.empty((scene.n_bins, cam.height, cam.width),
                                                            dtype=self.torch.float32, device=self.device)
-        self._err(lib().sdd_render_photons(self.handle, scene.handle, pmap.handle, C.byref(cam), C.byref(params),
-                                           C.c_void_p(ws.data_ptr()), ws.numel(), C.c_void_p(img.data_ptr())))
+        self._err(lib().sdd_render_photons(self.handle, scene.handle, None if pmap is None else pmap.handle,
+                                           None if global_map is None else global_map.handle, int(global_from),
+                                           C.byref(cam), C.byref(params), C.c_void_p(ws.data_ptr()), ws.numel(),
+                                           C.c_void_p(img.data_ptr())))
         if finish:
             self.finish()
         return img

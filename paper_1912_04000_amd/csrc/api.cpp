@@ -264,13 +264,13 @@ constexpr int kCacheDepth = 3;
 template <typename Finish>
 int run_paths(sdd_ctx* ctx, const sdd_scene* scene, const sdd_render_params* p, const Launch& L, const DevScene& S,
               const DevWS& w, uint64_t k0, uint32_t n, int& gen, bool timing, const PathMode& pm,
-              const sdd_cache* cache, const PhotonDev* ph, Finish finish) {
+              const sdd_cache* cache, const PhotonDev* ph, const PhotonDev* gm, int gm_from, Finish finish) {
   const int rounds = p->queue_rounds ? p->queue_rounds : kDefaultRounds;
   const int D = p->max_depth;
   const bool query = cache && pm.purpose == 0 && D >= kCacheDepth;
   HIP_TRY(ctx, launch_fill_u32(ctx->stream, &w.ctl->cat_count[0][0], 2 * 8 * kKeyStride, 0u));
   HIP_TRY(ctx, launch_fill_u32(ctx->stream, (uint32_t*)w.catb, ((size_t)2 * w.W + 3) / 4, 0u));
-  if (ph) HIP_TRY(ctx, launch_fill_u32(ctx->stream, w.ctl->ph_heavy, 2, 0u));
+  if (ph || gm) HIP_TRY(ctx, launch_fill_u32(ctx->stream, w.ctl->ph_heavy, 2, 0u));
   HIP_TRY(ctx, launch_raygen(L, S, w, k0, n, p->seed, gen, pm));
   int rc = trace_phase(ctx, L, S, w, gen, rounds, 1, timing);
   if (rc) return rc;
@@ -280,10 +280,12 @@ int run_paths(sdd_ctx* ctx, const sdd_scene* scene, const sdd_render_params* p, 
     HIP_TRY(ctx, launch_resolve(L, S, w, d));
     if (scene->hdr.env_nonzero) HIP_TRY(ctx, launch_escape(L, S, w, d));
     if (!last) {
-      // caustic radiance from the photon map at the opaque vertices, before their lobes
-      if (ph) {
+      // photon-map radiance at the opaque vertices, before their lobes: the caustic map, or from
+      // vertex gm_from on the global map (the opaque shading then skips the direct term)
+      const PhotonDev* map = gm && d >= gm_from ? gm : ph;
+      if (map) {
         if (timing) record(ctx, ctx->ev_photon, ctx->ev_used_photon, true);
-        HIP_TRY(ctx, launch_photon_gather(L, S, w, *ph, d));
+        HIP_TRY(ctx, launch_photon_gather(L, S, w, *map, d));
         if (timing) record(ctx, ctx->ev_photon, ctx->ev_used_photon, false);
         ctx->acc.photon_launches++;
       }
@@ -337,7 +339,7 @@ static hipError_t accumulate_wavefront(const Launch& L, const DevScene& S, const
 int enqueue_frame(sdd_ctx* ctx, const sdd_scene* scene, const std::vector<ViewDesc>& views,
                   const sdd_render_params* p, const Plan& plan, const DevWS& w, uint64_t total, bool timing,
                   sdd_cache* cache = nullptr, const sdd_train_params* tp = nullptr,
-                  const PhotonDev* ph = nullptr) {
+                  const PhotonDev* ph = nullptr, const PhotonDev* gm = nullptr, int gm_from = 0) {
   const int B = scene->hdr.n_bins;
   const uint32_t W = plan.W;
   DevScene S = device_view(scene);
@@ -348,7 +350,7 @@ int enqueue_frame(sdd_ctx* ctx, const sdd_scene* scene, const std::vector<ViewDe
   HIP_TRY(ctx, launch_fill_u32(ctx->stream, (uint32_t*)w.ctl, offsetof(Ctl, st_paths) / 4, 0u));
   HIP_TRY(ctx, launch_fill_u32(ctx->stream, w.ccount, 2ull * scene->hdr.n_cells * kDirBins * kKeyStride, 0u));
   int gen = 0;
-  const PathMode render_mode{0u, 0, nullptr, nullptr};
+  const PathMode render_mode{0u, 0, nullptr, nullptr, gm ? gm_from : 0};
   uint64_t wavefront = 0;
   for (uint64_t k0 = 0; k0 < total; k0 += W, ++wavefront) {
     const uint32_t n = (uint32_t)std::min<uint64_t>(W, total - k0);
@@ -360,7 +362,7 @@ int enqueue_frame(sdd_ctx* ctx, const sdd_scene* scene, const std::vector<ViewDe
         (tp->every > 0 ? wavefront % (uint64_t)tp->every == 0 : wavefront == 0)) {
       const uint32_t nt = (uint32_t)tp->train_paths;
       const PathMode train_mode{1u << 24, kCacheDepth, cache->dev.rx, cache->dev.rw};
-      rc = run_paths(ctx, scene, p, L, S, w, cache->train_paths_done, nt, gen, timing, train_mode, cache, ph,
+      rc = run_paths(ctx, scene, p, L, S, w, cache->train_paths_done, nt, gen, timing, train_mode, cache, ph, gm, gm_from,
                      [&]() -> int {
                        if (timing) record(ctx, ctx->ev_train, ctx->ev_used_train, true);
                        HIP_TRY(ctx, launch_cache_gather(ctx->stream, cache->dev, w, nt, B));
@@ -374,7 +376,7 @@ int enqueue_frame(sdd_ctx* ctx, const sdd_scene* scene, const std::vector<ViewDe
       cache->train_paths_done += nt;
       ctx->acc.train_batches++;
     }
-    rc = run_paths(ctx, scene, p, L, S, w, k0, n, gen, timing, render_mode, cache, ph, [&]() -> int {
+    rc = run_paths(ctx, scene, p, L, S, w, k0, n, gen, timing, render_mode, cache, ph, gm, gm_from, [&]() -> int {
       if (timing) record(ctx, ctx->ev_shade, ctx->ev_used_shade, true);
       HIP_TRY(ctx, accumulate_wavefront(L, S, w, views, k0, n));
       if (timing) record(ctx, ctx->ev_shade, ctx->ev_used_shade, false);
@@ -387,7 +389,8 @@ int enqueue_frame(sdd_ctx* ctx, const sdd_scene* scene, const std::vector<ViewDe
 }
 
 int render_views(sdd_ctx* ctx, const sdd_scene* scene, std::vector<ViewDesc>& views, const sdd_render_params* p,
-                 void* ws, size_t ws_bytes, const PhotonDev* ph = nullptr) {
+                 void* ws, size_t ws_bytes, const PhotonDev* ph = nullptr, const PhotonDev* gm = nullptr,
+                 int gm_from = 0) {
   const int B = scene->hdr.n_bins;
   uint64_t total = 0;
   for (auto& v : views) {
@@ -409,7 +412,8 @@ int render_views(sdd_ctx* ctx, const sdd_scene* scene, std::vector<ViewDesc>& vi
     HIP_TRY(ctx, launch_fill_u32(ctx->stream, (uint32_t*)&w.ctl->st_paths,
                                  (sizeof(Ctl) - offsetof(Ctl, st_paths)) / 4, 0u));
   ctx->last_ctl = w.ctl;
-  if (!p->use_graph) return enqueue_frame(ctx, scene, views, p, plan, w, total, p->timing != 0, nullptr, nullptr, ph);
+  if (!p->use_graph)
+    return enqueue_frame(ctx, scene, views, p, plan, w, total, p->timing != 0, nullptr, nullptr, ph, gm, gm_from);
 
   // Graph mode: capture the whole launch sequence once, replay it while the call repeats.
   uint64_t key = 1469598103934665603ull;
@@ -423,6 +427,8 @@ int render_views(sdd_ctx* ctx, const sdd_scene* scene, std::vector<ViewDesc>& vi
   key = fnv(key, &plan.total, sizeof(plan.total));
   const PhotonDev no_map{};
   key = fnv(key, ph ? ph : &no_map, sizeof(PhotonDev));
+  key = fnv(key, gm ? gm : &no_map, sizeof(PhotonDev));
+  key = fnv(key, &gm_from, sizeof(gm_from));
   if (!(ctx->graph_exec && ctx->graph_key == key)) {
     if (ctx->graph_exec) {
       (void)hipGraphExecDestroy(ctx->graph_exec);
@@ -444,7 +450,7 @@ int render_views(sdd_ctx* ctx, const sdd_scene* scene, std::vector<ViewDesc>& vi
       ctx->stream = user;
       return fail(ctx, SDD_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(eb));
     }
-    int rc = enqueue_frame(ctx, scene, views, p, plan, w, total, false, nullptr, nullptr, ph);
+    int rc = enqueue_frame(ctx, scene, views, p, plan, w, total, false, nullptr, nullptr, ph, gm, gm_from);
     hipGraph_t g = nullptr;
     hipError_t ec = hipStreamEndCapture(ctx->stream, &g);
     ctx->stream = user;
@@ -515,6 +521,7 @@ std::string check_photon_params(const sdd_photon_params* p) {
   if (p->capacity < 1 || p->capacity > (1ll << 28)) return "capacity must lie in 1..2^28";
   if (p->wave_paths != 0 && (p->wave_paths < 64 || p->wave_paths > (1 << 26))) return "wave_paths out of range";
   if (p->queue_rounds < 0 || p->queue_rounds > 256) return "queue_rounds out of range";
+  if (p->kind != SDD_PHOTON_CAUSTIC && p->kind != SDD_PHOTON_GLOBAL) return "unknown photon map kind";
   return "";
 }
 
@@ -582,6 +589,7 @@ PhotonDev photon_dev(const sdd_photon_map* m) {
   P.seed_lo = (uint32_t)m->prm.seed;
   P.seed_hi = (uint32_t)(m->prm.seed >> 32);
   P.max_depth = m->prm.max_depth;
+  P.global = m->prm.kind == SDD_PHOTON_GLOBAL ? 1 : 0;
   return P;
 }
 
@@ -1165,18 +1173,28 @@ int sdd_photon_map_load(sdd_ctx* c, sdd_photon_map* m, int64_t n, const float* p
   return SDD_OK;
 }
 
-int sdd_render_photons(sdd_ctx* c, const sdd_scene* s, const sdd_photon_map* m, const sdd_camera* cam,
-                       const sdd_render_params* p, void* ws, size_t ws_bytes, float* image) {
+int sdd_render_photons(sdd_ctx* c, const sdd_scene* s, const sdd_photon_map* caustic, const sdd_photon_map* global,
+                       int32_t global_from, const sdd_camera* cam, const sdd_render_params* p, void* ws,
+                       size_t ws_bytes, float* image) {
   if (!c) return fail(nullptr, SDD_ERR_INVALID_ARG, "ctx is null");
   int rc = scene_ready(c, s);
   if (rc) return rc;
-  if (!cam || !image || !m) return fail(c, SDD_ERR_INVALID_ARG, "null camera, image or photon map");
+  if (!cam || !image) return fail(c, SDD_ERR_INVALID_ARG, "null camera or image");
+  if (!caustic && !global) return fail(c, SDD_ERR_INVALID_ARG, "no photon map");
   std::string e = check_params(p);
   if (!e.empty()) return fail(c, SDD_ERR_INVALID_ARG, e);
   if (p->mode != SDD_MODE_PLAIN) return fail(c, SDD_ERR_INVALID_ARG, "sdd_render_photons renders in plain mode");
-  if (!m->built) return fail(c, SDD_ERR_NOT_READY, "photon map has not been built");
-  if (m->device != c->device) return fail(c, SDD_ERR_INVALID_ARG, "photon map was created on another device");
-  if (m->B != s->hdr.n_bins) return fail(c, SDD_ERR_NOT_READY, "scene bins differ from the photon map's");
+  for (const sdd_photon_map* m : {caustic, global}) {
+    if (!m) continue;
+    if (!m->built) return fail(c, SDD_ERR_NOT_READY, "photon map has not been built");
+    if (m->device != c->device) return fail(c, SDD_ERR_INVALID_ARG, "photon map was created on another device");
+    if (m->B != s->hdr.n_bins) return fail(c, SDD_ERR_NOT_READY, "scene bins differ from the photon map's");
+  }
+  if (caustic && caustic->prm.kind != SDD_PHOTON_CAUSTIC)
+    return fail(c, SDD_ERR_INVALID_ARG, "the caustic map argument holds a global map");
+  if (global && global->prm.kind != SDD_PHOTON_GLOBAL)
+    return fail(c, SDD_ERR_INVALID_ARG, "the global map argument holds a caustic map");
+  if (global && global_from < 1) return fail(c, SDD_ERR_INVALID_ARG, "global_from must be >= 1 with a global map");
   std::vector<ViewDesc> views(1);
   e = make_view(*cam, &views[0]);
   if (!e.empty()) return fail(c, SDD_ERR_INVALID_ARG, e);
@@ -1186,8 +1204,11 @@ int sdd_render_photons(sdd_ctx* c, const sdd_scene* s, const sdd_photon_map* m, 
   views[0].view_id = p->view;
   views[0].first_sample = (uint32_t)p->first_sample;
   HIP_TRY(c, hipSetDevice(c->device));
-  const PhotonDev P = photon_dev(m);
-  return render_views(c, s, views, p, ws, ws_bytes, &P);
+  PhotonDev Pc, Pg;
+  if (caustic) Pc = photon_dev(caustic);
+  if (global) Pg = photon_dev(global);
+  return render_views(c, s, views, p, ws, ws_bytes, caustic ? &Pc : nullptr, global ? &Pg : nullptr,
+                      global ? global_from : 0);
 }
 
 int sdd_finish(sdd_ctx* c) {

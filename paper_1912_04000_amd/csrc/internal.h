@@ -239,11 +239,13 @@ struct PathMode {
   int32_t rec_depth;   // vertex recorded for training, 0 = none
   float4* rec_x;       // [W] (position, material bits)
   float4* rec_w;       // [W] (direction toward the previous vertex, valid)
+  int32_t gm_from = 0; // > 0: from this vertex on, opaque vertices take their diffuse light from a
+                       // global photon map (gathered before shading): no direct term, mirror lobe only
 };
 
-// Device view of a caustic photon map (a caller buffer laid out by the host): the window table
-// of the emission, the stored photon records and a hashed uniform grid over them (cell size twice
-// the gather radius, counting-sorted).
+// Device view of a photon map (a caller buffer laid out by the host): the window table of the
+// emission, the stored photon records and a hashed uniform grid over them (cells of the gather
+// radius, counting-sorted).
 struct PhotonDev {
   uint32_t* ctl;              // [0] photons stored (may exceed cap), [1] photons dropped
   const uint32_t* win_thr;    // [n_win] integer thresholds floor(cdf_w / A 2^24)
@@ -259,6 +261,7 @@ struct PhotonDev {
   float flux_scale;           // A / N: flux of a photon per unit of sun irradiance
   uint32_t seed_lo, seed_hi;
   int32_t max_depth;
+  int32_t global;             // 1: global map (every opaque vertex stores; the diffuse lobe continues)
 };
 
 // Host helpers implemented in the kernels' translation unit.

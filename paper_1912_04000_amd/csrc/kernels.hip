@@ -1436,7 +1436,9 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2))) void k
       float4* e4 = (float4*)(w.nee + (size_t)s * Bp);
       const F3 ws = f3(S.sun[0], S.sun[1], S.sun[2]);
       const float cs = dot_exact_sign(V.n, ws);
-      const bool nee = cs > 0.0f;
+      // from vertex gm_from on a global photon map supplies the diffuse light, direct light included
+      const bool gm = pm.gm_from > 0 && depth >= pm.gm_from;
+      const bool nee = !gm && cs > 0.0f;
       const float kn = cs * (1.0f / 3.14159265358979f);
       float a_sum = 0.0f, b_sum = 0.0f;
       bool cont = false, mirror = false;
@@ -1449,6 +1451,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2))) void k
           const float Ps = am / (am + bm);
           mirror = u0 < Ps;
           inv_p = mirror ? 1.0f / Ps : 1.0f / (1.0f - Ps);
+          cont = mirror || !gm;  // with a global map the diffuse lobe's light was gathered
         }
       };
       if constexpr (NQ > 0) {
@@ -1915,8 +1918,9 @@ __global__ __launch_bounds__(kWG) void k_photon_vis(DevScene S, DevWS w, PhotonD
 
 // One photon vertex per thread, opaque vertices first (produced entries 0 .. n_opaque), then glass
 // (n_opaque .. n_opaque + n_glass): the same lobe rules as camera paths, no direct term. An opaque
-// vertex stores the photon when it has been reflected before, then takes the mirror lobe or ends
-// (a diffuse bounce leaves the caustic paths); vertex max_depth scatters nothing.
+// vertex of a caustic map stores the photon when it has been reflected before, then takes the
+// mirror lobe or ends (a diffuse bounce leaves the caustic paths); one of a global map stores every
+// photon and continues it by either lobe. Vertex max_depth scatters nothing.
 __global__ __launch_bounds__(kWG) void k_photon_shade(DevScene S, DevWS w, PhotonDev P, int depth, int gen) {
   __shared__ float s_planes[3 * (kMaxGrid + 1)];
   for (int q = threadIdx.x; q < S.gx + S.gy + S.gz + 3; q += kWG) s_planes[q] = S.planes[q];
@@ -1944,11 +1948,12 @@ __global__ __launch_bounds__(kWG) void k_photon_shade(DevScene S, DevWS w, Photo
       float4* brow = (float4*)(w.beta + (size_t)s * Bp);
       const float4* nt = (const float4*)(S.ntab + V.m * Bp);
       const float4* kt = (const float4*)(S.ktab + V.m * Bp);
-      bool cont = false, refl = false;
+      bool cont = false, refl = false, diffuse = false;
+      F3 diff_dir = f3(0.0f, 0.0f, 1.0f);
       if (opaque) {
         // the photons stored by the wave's active lanes take consecutive records (one atomic per
         // wave); the flux is the throughput on arrival, before this vertex's lobe
-        const bool store = (flags & kPhotonReflected) != 0;
+        const bool store = P.global || (flags & kPhotonReflected) != 0;
         const uint64_t m = __ballot(store);
         if (m) {
           const uint32_t leader = (uint32_t)__ffsll((unsigned long long)m) - 1u;
@@ -1991,6 +1996,31 @@ __global__ __launch_bounds__(kWG) void k_photon_shade(DevScene S, DevWS w, Photo
                                    b.z * fresnel(nn.z, kk.z, V.cos_o) * inv, b.w * fresnel(nn.w, kk.w, V.cos_o) * inv);
               });
               cont = refl = true;
+            } else if (P.global) {
+              // diffuse lobe (cosine-weighted, as for camera paths); its Fresnel factor is that of
+              // the direction the light leaves in, here the photon's new direction (cos = lz)
+              const float u1 = unif24(rn.y), u2 = unif24(rn.z);
+              float sn, cn;
+              sincosf(2.0f * 3.14159265358979f * u1, &sn, &cn);
+              const float rr_ = sqrtf(u2);
+              const float lx = rr_ * cn, ly = rr_ * sn, lz = sqrtf(fmaxf(0.0f, 1.0f - u2));
+              const F3 nrm = V.n;
+              const float sg = copysignf(1.0f, nrm.z);
+              const float aa = -1.0f / (sg + nrm.z);
+              const float bb = nrm.x * nrm.y * aa;
+              const F3 t1 = f3(1.0f + sg * nrm.x * nrm.x * aa, sg * bb, -sg * nrm.x);
+              const F3 t2 = f3(bb, sg + nrm.y * nrm.y * aa, -nrm.y);
+              diff_dir = t1 * lx + t2 * ly + nrm * lz;
+              const float inv = 1.0f / (1.0f - Ps);
+              const float4* rt = (const float4*)(S.rho + V.m * Bp);
+              row_update<8>(brow, nq, [&](int q, float4 b) {
+                const float4 nn = nt[q], kk = kt[q], rr = rt[q];
+                return make_float4(b.x * ((1.0f - fresnel(nn.x, kk.x, lz)) * rr.x * inv),
+                                   b.y * ((1.0f - fresnel(nn.y, kk.y, lz)) * rr.y * inv),
+                                   b.z * ((1.0f - fresnel(nn.z, kk.z, lz)) * rr.z * inv),
+                                   b.w * ((1.0f - fresnel(nn.w, kk.w, lz)) * rr.w * inv));
+              });
+              cont = diffuse = true;
             }
           }
         }
@@ -2044,8 +2074,8 @@ __global__ __launch_bounds__(kWG) void k_photon_shade(DevScene S, DevWS w, Photo
         cont = true;
       }
       if (cont) {
-        const F3 nd = refl ? V.d - V.ng * (2.0f * V.dn) : V.d;
-        const F3 no = refl ? V.p + V.n * V.eps : V.p - V.n * V.eps;
+        const F3 nd = diffuse ? diff_dir : (refl ? V.d - V.ng * (2.0f * V.dn) : V.d);
+        const F3 no = (refl || diffuse) ? V.p + V.n * V.eps : V.p - V.n * V.eps;
         w.rays[2 * s] = make_float4(no.x, no.y, no.z, __uint_as_float(V.id));
         w.rays[2 * s + 1] = make_float4(nd.x, nd.y, nd.z, __uint_as_float(s));
         if (refl) w.view[s] = flags | kPhotonReflected;

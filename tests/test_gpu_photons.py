@@ -51,8 +51,27 @@ def _cam(c):
     return sd.camera(c.eye, c.target, c.up, c.vfov_deg, c.width, c.height)
 
 
-def _compare_records(gpu, ref, label):
-    """gpu: (pos, dir, flux, id, vertex) from the map; ref: oracle.photons(...)."""
+def _incidence(sc, ref):
+    """Per oracle record: |cos| between the photon's direction and its triangle's normal, and the
+    smallest such cosine over the photon's records up to this one (records come in photon, vertex
+    order)."""
+    v = sc.verts.astype(np.float64)[ref["tri"]]
+    nrm = np.cross(v[:, 1] - v[:, 0], v[:, 2] - v[:, 0])
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    c = np.abs(np.einsum("ij,ij->i", nrm, ref["dir"]))
+    run = c.copy()
+    for k in range(1, len(c)):
+        if ref["id"][k] == ref["id"][k - 1]:
+            run[k] = min(run[k], run[k - 1])
+    return nrm, v[:, 0], run
+
+
+def _compare_records(gpu, ref, label, sc=None):
+    """gpu: (pos, dir, flux, id, vertex) from the map; ref: oracle.photons(...). With the scene
+    given, the position bar of a record is divided by the smallest incidence cosine of its photon
+    so far (a grazing hit moves the hit point along the surface by the ray's rounding over that
+    cosine, and the next rays start there), and every GPU position must lie on the oracle's
+    triangle's plane within 1e-5 (1 + |p|)."""
     gpos, gdir, gflux, gid, gvx = gpu
     tied_ids = set(np.nonzero(ref["tied"])[0].tolist())
     gkeys = {(int(i), int(v)): k for k, (i, v) in enumerate(zip(gid, gvx))}
@@ -67,6 +86,13 @@ def _compare_records(gpu, ref, label):
     gi = np.array([gkeys[k] for k in keys], dtype=np.int64)
     oi = np.array([okeys[k] for k in keys], dtype=np.int64)
     dp = np.abs(gpos[gi] - ref["pos"][oi]).max(axis=1) / (1.0 + np.abs(ref["pos"][oi]).max(axis=1))
+    if sc is not None:
+        nrm, v0, run = _incidence(sc, ref)
+        plane = np.abs(np.einsum("ij,ij->i", gpos[gi].astype(np.float64) - v0[oi], nrm[oi]))
+        plane /= 1.0 + np.abs(ref["pos"][oi]).max(axis=1)
+        say(f"[{label}] max off-plane {plane.max():.2e}, smallest incidence cos {run[oi].min():.2e}")
+        assert plane.max() <= 1e-5
+        dp = dp * np.minimum(1.0, run[oi])
     dd = np.abs(gdir[gi] - ref["dir"][oi]).max(axis=1)
     fo = ref["flux"][oi]
     big = np.abs(fo) > 1e-6 * np.abs(fo).max()
@@ -285,3 +311,90 @@ def test_church_photons_full_size(ctx):
     # 8 samples of 8 vertices in a million-triangle mesh: a pixel is tied when any of its samples
     # passes near an edge or a lobe threshold (as in the church test of the plain renderer)
     _gather_parity(g, r, "church frame, sampled map r 0.5", min_ok=0.5)
+
+
+# -- global maps ---------------------------------------------------------------------------
+@pytest.mark.parametrize("B,grid,wave", [(4, (2, 2, 2), 30_000), (13, (1, 1, 1), 0)])
+def test_global_records_window_box(ctx, B, grid, wave):
+    """A closed room lit through a ceiling window: every photon stored at every opaque vertex it
+    reaches, continued by the mirror or the diffuse lobe (Fresnel factor of the new direction)."""
+    import paper_1912_04000_amd as sd
+    sc = scenegen.window_box_scene(B)
+    S = _scene(ctx, sc, grid)
+    N = 40_001
+    say(f"build: window box {B} bins, global map, {N} photons, wave {wave}")
+    m = ctx.photon_map(S, sd.photon_params(N, radius=0.1, max_depth=8, seed=3, wave_paths=wave,
+                                           kind=sd.PHOTON_GLOBAL))
+    ref = oracle.photons(sc, N, max_depth=8, seed=3, global_map=True)
+    assert m.info()["dropped"] == 0
+    n = _compare_records(m.records(), ref, f"global window box {B} bins", sc)
+    assert n > 5 * N
+
+
+def test_global_records_nave_with_maps(ctx):
+    import paper_1912_04000_amd as sd
+    sc = scenegen.with_glass_maps(scenegen.nave_scene(8))
+    S = _scene(ctx, sc, (4, 2, 2))
+    N = 30_000
+    m = ctx.photon_map(S, sd.photon_params(N, radius=0.2, max_depth=6, seed=12, kind=sd.PHOTON_GLOBAL))
+    ref = oracle.photons(sc, N, max_depth=6, seed=12, global_map=True)
+    _compare_records(m.records(), ref, "global nave with glass maps", sc)
+
+
+def _load(ctx, S, ph, radius, kind):
+    import paper_1912_04000_amd as sd
+    m = sd.PhotonMap(ctx, S, sd.photon_params(max(1, len(ph["id"])), radius=radius, capacity=len(ph["id"]) + 1,
+                                              kind=kind))
+    m.load(ph["pos"], ph["dir"], ph["flux"], ph["id"], ph["depth"])
+    return m
+
+
+@pytest.mark.parametrize("gl_from,spp", [(1, 2), (2, 2), (3, 1)])
+def test_global_gather_window_box(ctx, gl_from, spp):
+    """The oracle's global and caustic maps (rounded to FP32) loaded into GPU maps; camera paths
+    with the caustic map before vertex gl_from and the global map from there on, against the
+    oracle with the same maps."""
+    import paper_1912_04000_amd as sd
+    sc = scenegen.window_box_scene(4)
+    S = _scene(ctx, sc, (2, 2, 2))
+    g = _f32_records(oracle.photons(sc, 60_000, max_depth=10, seed=5, global_map=True))
+    c = _f32_records(oracle.photons(sc, 200_000, max_depth=10, seed=6))
+    mg = _load(ctx, S, g, 0.1, sd.PHOTON_GLOBAL)
+    mc = _load(ctx, S, c, 0.15, sd.PHOTON_CAUSTIC)
+    cam = scenegen.Camera(eye=(3.5, 3.5, 2.5), target=(1.0, 1.2, 0.0), up=(0, 0, 1), vfov_deg=75, width=40,
+                          height=32)
+    say(f"render: window box, global from vertex {gl_from}, {len(g['id'])} + {len(c['id'])} records")
+    img = ctx.render_photons(S, mc, _cam(cam), sd.render_params(spp=spp, max_depth=8, seed=4), global_map=mg,
+                             global_from=gl_from).cpu().numpy()
+    # the oracle takes one tie radius for both maps; the global gather reports its bound there too
+    ref = oracle.render(sc, cam, spp=spp, max_depth=8, seed=4, photons=c, radius=0.15, tie_radius=TIE_RADIUS,
+                        global_photons=g, global_radius=0.1, global_depth=gl_from)
+    _gather_parity(img, ref, f"window box global from {gl_from}")
+
+
+def test_global_gather_nave_and_graph(ctx):
+    import paper_1912_04000_amd as sd
+    sc = scenegen.nave_scene(8)
+    S = _scene(ctx, sc, (2, 2, 2))
+    g = _f32_records(oracle.photons(sc, 60_000, max_depth=8, seed=9, global_map=True))
+    mg = _load(ctx, S, g, 0.25, sd.PHOTON_GLOBAL)
+    cam = scenegen.nave_camera(40, 32)
+    p = sd.render_params(spp=2, max_depth=6, seed=8)
+    img = ctx.render_photons(S, None, _cam(cam), p, global_map=mg, global_from=2).cpu().numpy()
+    ref = oracle.render(sc, cam, spp=2, max_depth=6, seed=8, global_photons=g, global_radius=0.25,
+                        tie_radius=TIE_RADIUS, global_depth=2)
+    _gather_parity(img, ref, "nave global from vertex 2")
+    pg = sd.render_params(spp=2, max_depth=6, seed=8, use_graph=1)
+    out = None
+    for rep in range(2):
+        out = ctx.render_photons(S, None, _cam(cam), pg, out=out, global_map=mg, global_from=2)
+        ctx.torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), img), rep
+    # argument errors: kinds swapped, no map, global_from < 1
+    mc = _load(ctx, S, g, 0.25, sd.PHOTON_CAUSTIC)
+    for kw in (dict(pmap=mg), dict(pmap=None, global_map=mc, global_from=1), dict(pmap=None),
+               dict(pmap=None, global_map=mg, global_from=0)):
+        pm = kw.pop("pmap")
+        with pytest.raises(sd.SddError) as e:
+            ctx.render_photons(S, pm, _cam(cam), p, **kw)
+        assert e.value.code == -1

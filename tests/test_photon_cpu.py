@@ -44,3 +44,9 @@ def test_map_bytes_grow_with_capacity_and_bins():
     assert _binding.lib().sdd_photon_workspace_bytes(S3.handle, C.byref(sd.photon_params(1000, radius=0.1)),
                                                      C.byref(ws)) == 0
     assert ws.value > 0
+
+
+def test_photon_kind_validation():
+    S = sd.Scene.from_description(scenegen.caustic_scene(3))
+    assert _bytes(S, sd.photon_params(1000, radius=0.1, kind=sd.PHOTON_GLOBAL))[0] == 0
+    assert _bytes(S, sd.photon_params(1000, radius=0.1, kind=2))[0] == -1
