@@ -496,6 +496,46 @@ def bench_photons(ctx, S, sc, cam, cfg, wave, n_photons=4_000_000, radius=0.1, s
                        "lit_fraction": st["photon_lit_vertices"] / max(1, st["photon_vertices"])}}
 
 
+def bench_global_map(ctx, S, sc, cam, cfg, wave, n_photons=2_000_000, radius=0.15, spp=8, gm_from=2):
+    """Global photon map (section 4) of the benchmarked view: HIP-event time of building it, then
+    of an spp-sample frame whose paths take the diffuse light of vertex gm_from on from it (final
+    gathering over the first bounce), against the plain frame at the same spp."""
+    import torch
+    import paper_1912_04000_amd as sd
+    pp = sd.photon_params(n_photons, radius=radius, max_depth=cfg["max_depth"], seed=1, capacity=6 * n_photons,
+                          kind=sd.PHOTON_GLOBAL)
+    m = sd.PhotonMap(ctx, S, pp)
+    m.build(S)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    m.build(S, finish=False)
+    e1.record()
+    torch.cuda.synchronize()
+    ctx.finish()
+    build_ms = e0.elapsed_time(e1)
+    info = m.info()
+    c = sd.camera(cam.eye, cam.target, cam.up, cam.vfov_deg, cam.width, cam.height)
+    img = torch.empty((sc.n_bins, cam.height, cam.width), dtype=torch.float32, device="cuda")
+    p = sd.render_params(spp=spp, max_depth=cfg["max_depth"], seed=1, wave_paths=wave, timing=1)
+    run = lambda: ctx.render_photons(S, None, c, p, out=img, finish=False, global_map=m, global_from=gm_from)
+    run()
+    ctx.finish()
+    ctx.reset_stats()
+    e0.record()
+    run()
+    e1.record()
+    torch.cuda.synchronize()
+    ctx.finish()
+    st = ctx.stats()
+    ms = e0.elapsed_time(e1)
+    return {"photons": n_photons, "radius_m": radius, "max_depth": cfg["max_depth"], "from_vertex": gm_from,
+            "build_ms": build_ms, "photons_per_s": n_photons / (build_ms * 1e-3), "records": info["stored"],
+            "spp": spp, "samples_per_s": cam.width * cam.height * spp / (ms * 1e-3),
+            "gather_ms_per_launch": st["photon_ms"] / max(1, st["photon_launches"]),
+            "records_found_per_vertex": st["photons_found"] / max(1, st["photon_vertices"]),
+            "vertices_per_launch": st["photon_vertices"] / max(1, st["photon_launches"])}
+
+
 def crop_camera(cam, cw, ch):
     """The centred cw x ch window of a view as a camera of its own (same eye, axis and pixel
     footprint): tan(vfov'/2) = tan(vfov/2) ch / H."""
@@ -765,6 +805,7 @@ def main():
         if args.workload == "church":
             out["glass_maps"] = bench_glass_maps(ctx, sc, cam, cfg, p.wave_paths)
             out["photon_map"] = bench_photons(ctx, S, sc, cam, cfg, p.wave_paths)
+            out["global_map"] = bench_global_map(ctx, S, sc, cam, cfg, p.wave_paths)
     if args.workload == "church" and not args.no_cached:
         # the cached half of the metric on the same view: the plain frame just timed (64 spp,
         # seed 1) fixes a = RMSE_64 sqrt(64) of the plain estimator's RMSE = a / sqrt(spp)

@@ -398,3 +398,37 @@ def test_global_gather_nave_and_graph(ctx):
         with pytest.raises(sd.SddError) as e:
             ctx.render_photons(S, pm, _cam(cam), p, **kw)
         assert e.value.code == -1
+
+
+def test_church_global_map_full_size(ctx):
+    """The benchmarked church's global map as bench.py builds it (2M photons, depth 8, radius
+    0.15 m, 2^20 photons in flight): records of every 32nd photon against the oracle's sample; then
+    that sample loaded with a 0.5 m radius and gathered from vertex 2 on in the benchmarked frame
+    (1920x1080, 8 spp, depth 8, 2^24 paths in flight) on 200 sampled pixels."""
+    import paper_1912_04000_amd as sd
+    import torch
+    sc = scenegen.church_scene(40)
+    S = _scene(ctx, sc, (8, 4, 4))
+    N = 2_000_000
+    say("build: church global map, 2M photons")
+    m = ctx.photon_map(S, sd.photon_params(N, radius=0.15, max_depth=8, seed=1, capacity=6 * N,
+                                           kind=sd.PHOTON_GLOBAL))
+    info = m.info()
+    assert info["dropped"] == 0
+    pos, dr, fl, pid, vx = m.records()
+    keep = pid % 32 == 0
+    say(f"church global map: {info['stored']} records; oracle sample ...")
+    ref = oracle.photons(sc, N, max_depth=8, seed=1, stride=32, global_map=True)
+    _compare_records((pos[keep], dr[keep], fl[keep], pid[keep], vx[keep]), ref, "church global, every 32nd photon",
+                     sc)
+    ph = _f32_records(ref)
+    m2 = _load(ctx, S, ph, 0.5, sd.PHOTON_GLOBAL)
+    cam = scenegen.church_camera()
+    say("render: church 1920x1080 8 spp depth 8, global map from vertex 2")
+    img = ctx.render_photons(S, None, _cam(cam), sd.render_params(spp=8, max_depth=8, seed=5, wave_paths=1 << 24),
+                             global_map=m2, global_from=2)
+    px = np.sort(np.random.default_rng(22).choice(cam.width * cam.height, 200, replace=False))
+    g = img.reshape(40, -1)[:, torch.from_numpy(px).cuda()].cpu().numpy()
+    r = oracle.render(sc, cam, spp=8, max_depth=8, seed=5, pixels=px, global_photons=ph, global_radius=0.5,
+                      tie_radius=TIE_RADIUS, global_depth=2)
+    _gather_parity(g, r, "church frame, global sample map from vertex 2", min_ok=0.5)
