@@ -50,6 +50,12 @@ def parse():
     ap.add_argument("--cached-spp", type=int, default=64, help="cached workload: samples per pixel of the scored frame")
     ap.add_argument("--warm-frames", type=int, default=8, help="cached workload: 1-spp training frames before it")
     ap.add_argument("--train-paths", type=int, default=1 << 17, help="cached workload: training paths per batch")
+    ap.add_argument("--train-steps", type=int, default=None,
+                    help="cached and large workloads: Adam steps of 2^14 records per batch (default 4 / 8)")
+    ap.add_argument("--cache-lr", type=float, default=None,
+                    help="cached and large workloads: Adam learning rate (default 1e-3 / 3e-3)")
+    ap.add_argument("--cache-log2-pos", type=int, default=None,
+                    help="cached and large workloads: log2 entries per level of the position grid (default 19 / 21)")
     ap.add_argument("--train-every", type=int, default=0,
                     help="cached path: wavefronts between training batches (0: one batch per frame)")
     ap.add_argument("--tune-cache", default=os.path.join(os.path.expanduser("~"), ".cache", "specdd",
@@ -58,6 +64,10 @@ def parse():
     ap.add_argument("--wave-paths", type=int, default=1 << 25,
                     help="paths per wavefront (C2 measured 1046 / 925 / 889 / 838 / 821 ms per frame at 2^21 .. 2^25)")
     ap.add_argument("--queue-rounds", type=int, default=0)
+    ap.add_argument("--large-train-frames", type=int, default=0,
+                    help="large workload: frames trained one batch each before the period applies (0: every frame)")
+    ap.add_argument("--large-train-period", type=int, default=1,
+                    help="large workload: after those frames, one training batch every this many frames")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-cached", action="store_true", help="skip the cached-path comparison of the default run")
     ap.add_argument("--no-extras", action="store_true",
@@ -269,8 +279,11 @@ def run_cached(ctx, S, sc, cam, img, args, px, ref, wave):
     lo = sc.verts.reshape(-1, 3).min(0) - 0.05
     hi = sc.verts.reshape(-1, 3).max(0) + 0.05
     cache = sd.Cache(ctx, sd.cache_config(len(sc.mat_type), lo, hi, max_bins=B,
-                                          max_records=max(args.train_paths, 1 << 14), max_step=1 << 14), seed=12345)
-    tp = sd.train_params(train_paths=args.train_paths, step_records=1 << 14, steps=4, every=args.train_every)
+                                          max_records=max(args.train_paths, 1 << 14), max_step=1 << 14,
+                                          lr=args.cache_lr or 1e-3, log2_table_pos=args.cache_log2_pos or 19),
+                     seed=12345)
+    tp = sd.train_params(train_paths=args.train_paths, step_records=1 << 14, steps=args.train_steps or 4,
+                         every=args.train_every)
     ctx.reset_stats()
     frames, t_total = [], 0.0
     for f in range(args.warm_frames):
@@ -545,7 +558,9 @@ def bench_large(args):
     """C5: procedural church of ~10M triangles (200 windows), 80 bins (5 nm), 3840x2160, 16x8x8
     cells, depth 8. Plain 256 spp against the cache-terminated path given the same wall time
     (untrained cache; 1-spp frames, accumulated, until the plain time is used up; every frame
-    trains the cache once on 2^16 records). RMSE over the pixels x % 32 == 0, y % 32 == 0
+    trains the cache once: 8 Adam steps of 2^14 records, lr 3e-3, position grids of 2^21 entries
+    per level -- the configuration leaves the cache's training open, and the larger scene and
+    frame want more of it than the 1080p church). RMSE over the pixels x % 32 == 0, y % 32 == 0
     against the oracle's FP64 2048-spp reference of them (tests/golden/c5_reference.npz, two
     independent 1024-spp halves); the reference's own noise variance, estimated from its halves,
     is subtracted from each mean squared error. value = plain samples/s of the 256-spp frame."""
@@ -584,17 +599,23 @@ def bench_large(args):
     # cached, same wall time
     lo = sc.verts.reshape(-1, 3).min(0) - 0.05
     hi = sc.verts.reshape(-1, 3).max(0) + 0.05
-    cache = sd.Cache(ctx, sd.cache_config(len(sc.mat_type), lo, hi, max_bins=B, max_records=1 << 17,
-                                          max_step=1 << 14), seed=12345)
-    tp = sd.train_params(train_paths=1 << 17, step_records=1 << 14, steps=4, every=0)
+    cache = sd.Cache(ctx, sd.cache_config(len(sc.mat_type), lo, hi, max_bins=B,
+                                          max_records=max(args.train_paths, 1 << 17), max_step=1 << 14,
+                                          lr=args.cache_lr or 3e-3, log2_table_pos=args.cache_log2_pos or 21),
+                     seed=12345)
+    tp = sd.train_params(train_paths=args.train_paths, step_records=1 << 14, steps=args.train_steps or 8, every=0)
     acc = torch.zeros((B, H, W), dtype=torch.float32, device="cuda")
     chunk, done_spp, t_cached, chunks = 1, 0, 0.0, []
     ctx.reset_stats()
+    frame = 0
     while t_cached < t_plain:
+        train = (args.large_train_frames <= 0 or frame < args.large_train_frames
+                 or (frame - args.large_train_frames) % max(1, args.large_train_period) == 0)
         dt = _timed(lambda: ctx.render_cached(S, cache, c, sd.render_params(spp=chunk, max_depth=8, seed=1,
                                                                              mode=sd.MODE_CACHED, wave_paths=wave,
                                                                              first_sample=done_spp, timing=1),
-                                              tp, out=img))
+                                              tp if train else None, out=img))
+        frame += 1
         acc.mul_(done_spp / (done_spp + chunk)).add_(img, alpha=chunk / (done_spp + chunk))
         done_spp += chunk
         t_cached += dt
@@ -623,7 +644,12 @@ def bench_large(args):
                        "rmse_ratio_plain_over_cached": r_plain / r_cached,
                        "spp_plain_equivalent": spp_eq, "time_plain_equivalent_s": t_eq,
                        "speedup_at_equal_rmse": t_eq / t_cached,
-                       "adam_steps": cache.info()["adam_steps"], "train_batches": st_c["train_batches"]},
+                       "adam_steps": cache.info()["adam_steps"], "train_batches": st_c["train_batches"],
+                       "cache": {"lr": args.cache_lr or 3e-3, "log2_table_pos": args.cache_log2_pos or 21,
+                                 "steps_per_batch": args.train_steps or 8, "records_per_step": 1 << 14},
+                       "training": ("one batch per frame" if args.large_train_frames <= 0 else
+                                    f"one batch per frame for {args.large_train_frames} frames, then one every "
+                                    f"{args.large_train_period}")},
         "timing_split_ms": {"plain_trace": st_plain["trace_ms"], "plain_shade": st_plain["shade_ms"],
                             "cached_trace": st_c["trace_ms"], "cached_shade": st_c["shade_ms"],
                             "cached_query": st_c["query_ms"], "cached_train_steps": st_c["train_ms"]},
