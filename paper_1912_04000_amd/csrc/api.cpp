@@ -563,6 +563,7 @@ void photon_layout(sdd_photon_map* m, const sdd_scene* s, const sdd_photon_param
   m->off_cand = o;   o = a256(o + 16ull * (size_t)p->capacity);
   m->off_bsum = o;   o = a256(o + 4ull * (nb / kPhotonScanChunk + 1));
   m->off_occ = o;    o = a256(o + 4ull * kPhotonOccWords);
+  m->off_srec = o;   o = a256(o + 16ull * rq * (size_t)p->capacity);
   m->total = o;
 }
 
@@ -579,6 +580,7 @@ PhotonDev photon_dev(const sdd_photon_map* m) {
   P.cand = (float4*)(b + m->off_cand);
   P.bsum = (uint32_t*)(b + m->off_bsum);
   P.occ = (uint32_t*)(b + m->off_occ);
+  P.srec = (float4*)(b + m->off_srec);
   P.n_win = (uint32_t)m->thr.size();
   P.cap = (uint32_t)m->prm.capacity;
   P.n_buckets = m->n_buckets;

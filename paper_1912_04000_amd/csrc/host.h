@@ -56,7 +56,7 @@ struct sdd_photon_map {
   void* buf = nullptr;
   size_t bytes = 0;
   int device = -1;
-  size_t off_ctl = 0, off_thr = 0, off_tri = 0, off_rec = 0, off_bcount = 0, off_bstart = 0, off_cand = 0, off_bsum = 0, off_occ = 0, total = 0;
+  size_t off_ctl = 0, off_thr = 0, off_tri = 0, off_rec = 0, off_bcount = 0, off_bstart = 0, off_cand = 0, off_bsum = 0, off_occ = 0, off_srec = 0, total = 0;
   std::vector<uint32_t> thr, tri;  // windows of the last build (kept alive for its copies)
   double area = 0.0;
   bool built = false;

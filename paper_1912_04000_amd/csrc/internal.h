@@ -253,7 +253,8 @@ struct PhotonDev {
   float4* rec;                // [cap][rq]: (pos, id lo bits) (dir, vertex | id hi << 8) flux quads
   uint32_t* bcount;           // [n_buckets] photons per bucket, then scatter cursors
   uint32_t* bstart;           // [n_buckets + 1] first entry of each bucket in `cand`
-  float4* cand;               // [cap] in bucket order: (pos, record index bits)
+  float4* cand;               // [cap] in bucket order: (pos, index into srec)
+  float4* srec;               // [cap][rq] the records again, in bucket order (what a gather reads)
   uint32_t* bsum;             // [n_buckets / kPhotonScanChunk + 1] scan partial sums
   uint32_t* occ;              // [kPhotonOccWords] bit h: some record lies in a super-cell of hash h
   uint32_t n_win, cap, n_buckets, rq;  // rq = 2 + Bp / 4 float4 per record

@@ -2193,15 +2193,19 @@ __global__ __launch_bounds__(kPhotonScanThreads) void k_photon_chunk_scan(Photon
 }
 
 // Records into bucket order: each bucket's entries hold the position the gathering tests
-// (contiguous per bucket) and the record's index, through which the direction and flux of a
-// record within the radius are read.
+// (contiguous per bucket) and the index of the record's copy in bucket order, through which the
+// direction and flux of a record within the radius are read; the records a gather finds then
+// lie next to each other in memory, bucket by bucket.
 __global__ void k_photon_scatter(PhotonDev P) {
   const uint32_t n = min(P.ctl[0], P.cap);
   for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
-    const float4 q0 = P.rec[(size_t)r * P.rq];
+    const float4* src = P.rec + (size_t)r * P.rq;
+    const float4 q0 = src[0];
     const uint32_t b = photon_bucket_of(P, q0);
     const uint32_t e = P.bstart[b] + atomicAdd(&P.bcount[b], 1u);
-    P.cand[e] = make_float4(q0.x, q0.y, q0.z, __uint_as_float(r));
+    P.cand[e] = make_float4(q0.x, q0.y, q0.z, __uint_as_float(e));
+    float4* dst = P.srec + (size_t)e * P.rq;
+    for (uint32_t q = 0; q < P.rq; ++q) dst[q] = src[q];
   }
 }
 
@@ -2320,7 +2324,7 @@ __global__ __launch_bounds__(kGatherWG) void k_photon_gather(DevScene S, DevWS w
             if (e + (uint32_t)j < end && dx * dx + dy * dy + dz * dz < r2) {
               // the direction and the flux row in one round trip (nearly every record within
               // the ball arrived from the side the path sees)
-              const float4* R = P.rec + (size_t)__float_as_uint(q0[j].w) * P.rq;
+              const float4* R = P.srec + (size_t)__float_as_uint(q0[j].w) * P.rq;
               if constexpr (NQ > 0) {
                 float4 x[NQ];
                 const float4 q1 = R[1];
@@ -2416,7 +2420,7 @@ __global__ __launch_bounds__(kGatherWG) void k_photon_gather_heavy(DevScene S, D
         const float4 q0 = P.cand[(size_t)e0 + k];
         const float dx = q0.x - V.p.x, dy = q0.y - V.p.y, dz = q0.z - V.p.z;
         if (dx * dx + dy * dy + dz * dz < r2) {
-          const float4* R = P.rec + (size_t)__float_as_uint(q0.w) * P.rq;
+          const float4* R = P.srec + (size_t)__float_as_uint(q0.w) * P.rq;
           const float4 q1 = R[1];
           if (q1.x * V.n.x + q1.y * V.n.y + q1.z * V.n.z < 0.0f) {
 #pragma unroll
