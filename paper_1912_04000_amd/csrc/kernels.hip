@@ -4,8 +4,8 @@
 //   producer (raygen / shade / pack)  -> (ray, start cell, rank in cell) entries
 //   k_scan     one workgroup: per-cell offsets, cell-sorted tile list
 //   k_scatter  entries -> cell-sorted queue
-//   k_trace    a tile = up to 256 rays of ONE queue key (cell, direction class), one ray per
-//              lane; the grid's slab planes, the cell table and each lane's short traversal
+//   k_trace    a tile = up to 256 rays of ONE queue key (cell, direction class), handed out
+//              in parts of 64, one ray per lane of a wave; the grid's slab planes, the cell table and each lane's short traversal
 //              stack live in LDS, the 4-wide BVH nodes and triangles are read from memory (L2).
 //              A lane traverses its ray inside the cell's slab interval; rays that leave the
 //              cell are re-queued for the next cell (the interface conditions between the
@@ -942,68 +942,70 @@ __device__ __forceinline__ uint32_t cpos_cell(const DevScene& S, uint32_t cpos) 
 }
 
 // Lane phases of k_trace.
-enum : int { kLaneIdle = 0, kLaneEnter = 1, kLaneTrav = 2, kLaneLeave = 3, kLaneDone = 4 };
+enum : int { kLaneEnter = 1, kLaneTrav = 2, kLaneLeave = 3, kLaneDone = 4 };
 
-// One tile = up to kTile rays of one queue key (cell, direction bin). The kWG lanes of the
-// workgroup take the tile's rays through a workgroup counter; with kTile == kWG every lane gets
-// at most one ray, so all lanes start the tile together (the coherence of their node fetches
-// was measured to matter more than refilling idle lanes) and a lane steps one BVH node or one
-// triangle per loop iteration. A ray's cell is traversed inside the cell's half-open slab interval; in every round
-// but the last the ray then migrates to the queue of the next cell, in the last round it walks
-// on in place. Finished rays go to LDS lists that the workgroup flushes to the global category
-// lists and the migration list once the tile is drained.
+// One tile = up to kTile rays of one queue key (cell, direction bin), handed out as kTile / 64
+// parts of 64 rays, one part per wave: the 64 lanes of a wave start their part together, one
+// ray each (lanes that traverse the same cell in the same direction class fetch the same nodes
+// in the same instruction), and a wave whose rays are done takes its next part without waiting
+// for the other waves of its workgroup. A lane steps one BVH node or one triangle per loop
+// iteration. A ray's cell is traversed inside the cell's half-open slab interval; in every
+// round but the last the ray then migrates to the queue of the next cell, in the last round it
+// walks on in place. Finished rays write their category byte; migrating rays are appended to
+// the next round's lists by the wave once its part is drained.
+constexpr uint32_t kTileParts = kTile / 64;
+
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(7))) void k_trace(DevScene S, DevWS w, int gen, int hops) {
   __shared__ uint32_t s_stack[kShortStack * kWG];
-  __shared__ uint32_t s_next[2];
-  __shared__ uint32_t s_fetch, s_nreq;
-  __shared__ uint32_t s_rsrc[kTile], s_rkey[kTile];
+  __shared__ uint32_t s_rsrc[kWG], s_rkey[kWG];
   // the grid's slab planes, and its cell table when small enough, staged in LDS: a ray entering
   // a cell then waits for LDS instead of a memory round trip
   __shared__ float s_planes[3 * (kMaxGrid + 1)];
   __shared__ int4 s_cells[kLdsCells];
+  // the workgroup's work counters: frequent ones summed per wave in scalar registers, rare ones
+  // (migrations, escapes, glass crossings, unrecorded crossings) added here by their lanes
+  __shared__ uint32_t s_st[7];
   const int n_planes = S.gx + S.gy + S.gz + 3;
   const bool cells_lds = S.n_cells <= kLdsCells;
   for (int q = threadIdx.x; q < n_planes; q += kWG) s_planes[q] = S.planes[q];
   if (cells_lds)
     for (int q = threadIdx.x; q < S.n_cells; q += kWG) s_cells[q] = S.cells[q];
+  stats_init(s_st, 7);
   __syncthreads();
-  const uint32_t n_tiles = w.ctl->n_tiles;
+  const uint32_t n_parts = w.ctl->n_tiles * kTileParts;
   const uint32_t xcd = blockIdx.x % kXcds;
+  const uint32_t lane = lane_id();
   const uint32_t gtid = blockIdx.x * kWG + threadIdx.x;
   uint32_t* spill = w.spill + gtid;
   uint32_t* stack = s_stack + threadIdx.x;
   const int np = (gen + 1) & 1;
-  // work counters: wave-uniform sums of ballots (scalar registers)
-  uint32_t n_visit = 0, n_migr = 0, n_esc = 0, n_glass = 0, n_xover = 0, n_nodes = 0, n_tris = 0;
-  // Tiles are handed out dynamically: each XCD owns a contiguous range of the cell-sorted tiles
-  // (its L2 then holds few cells at a time) and its workgroups take the next tile of that range
-  // from a counter; a workgroup whose range is exhausted takes tiles from the other XCDs' ranges.
-  uint32_t donor = 0;   // thread 0 only: how many ranges it has exhausted
-  for (int it = 0;; ++it) {
-    if (threadIdx.x == 0) {
-      uint32_t t = 0xFFFFFFFFu;
-      for (; donor < (uint32_t)kXcds; ++donor) {
-        const uint32_t X = (xcd + donor) % kXcds;
-        const uint32_t b = (uint32_t)(((uint64_t)n_tiles * X) / kXcds);
-        const uint32_t e = (uint32_t)(((uint64_t)n_tiles * (X + 1)) / kXcds);
-        const uint32_t q = b + atomicAdd(&w.ctl->tile_next[X * kKeyStride], 1u);
-        if (q < e) {
-          t = q;
-          break;
-        }
+  uint32_t n_visit = 0, n_nodes = 0, n_tris = 0;
+  // Parts are handed out dynamically: each XCD owns a contiguous range of the cell-sorted tiles
+  // (its L2 then holds few cells at a time) and its waves take the next part of that range from
+  // a counter; a wave whose range is exhausted takes parts from the other XCDs' ranges.
+  uint32_t donor = 0;   // how many ranges this wave has exhausted (wave-uniform)
+  for (;;) {
+    uint32_t t = 0xFFFFFFFFu;
+    for (; donor < (uint32_t)kXcds; ++donor) {
+      const uint32_t X = (xcd + donor) % kXcds;
+      const uint32_t b = (uint32_t)(((uint64_t)n_parts * X) / kXcds);
+      const uint32_t e = (uint32_t)(((uint64_t)n_parts * (X + 1)) / kXcds);
+      uint32_t q = 0;
+      if (lane == 0) q = atomicAdd(&w.ctl->tile_next[X * kKeyStride], 1u);
+      q = b + __builtin_amdgcn_readfirstlane(q);
+      if (q < e) {
+        t = q;
+        break;
       }
-      s_next[it & 1] = t;
-      s_fetch = 0;
-      s_nreq = 0;
     }
-    __syncthreads();
-    const uint32_t t = __builtin_amdgcn_readfirstlane(s_next[it & 1]);
     if (t == 0xFFFFFFFFu) break;
-    const uint4 tile = w.tiles[t];
+    const uint4 tile = w.tiles[t / kTileParts];
+    const uint32_t r0 = (t % kTileParts) * 64u;
+    if (r0 >= tile.z) continue;  // a part past the end of a partly filled tile
     const int tcell = (int)(tile.x / kDirBins);
     const uint32_t tdir = tile.x % kDirBins;
     const int4 tinfo = S.cells[tcell];
-    int phase = kLaneIdle;
+    int phase = kLaneDone;
     RayPre R;
     R.o = R.inv = f3(0.0f, 0.0f, 0.0f);
     R.k = 0;
@@ -1022,30 +1024,23 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(7))) void k
     st.best_id = 0xFFFFFFFFu;
     st.blocked = false;
     st.ncross = 0;
+    s_rsrc[threadIdx.x] = 0xFFFFFFFFu;
+    if (r0 + lane < tile.z) {
+      const uint32_t entry = w.queue[tile.y + r0 + lane];
+      const uint32_t r = entry & ~kFirstVisit;
+      first = (entry & kFirstVisit) != 0;
+      const float4 ro = w.rays[2 * r], rd = w.rays[2 * r + 1];
+      skip = __float_as_uint(ro.w);
+      const uint32_t sw = __float_as_uint(rd.w);
+      shadow = (sw & kShadowBit) != 0;
+      slot = sw & ~kShadowBit;
+      R = make_pre(f3(ro.x, ro.y, ro.z), f3(rd.x, rd.y, rd.z));
+      cpos = (uint32_t)(tcell % S.gx) | (uint32_t)((tcell / S.gx) % S.gy) << 6 |
+             (uint32_t)(tcell / (S.gx * S.gy)) << 12;
+      st.ncross = shadow ? w.shcnt[slot] : 0u;
+      phase = kLaneEnter;
+    }
     for (;;) {
-      if (phase == kLaneIdle) {
-        const uint32_t i = atomicAdd(&s_fetch, 1u);
-        if (i < tile.z) {
-          const uint32_t entry = w.queue[tile.y + i];
-          const uint32_t r = entry & ~kFirstVisit;
-          first = (entry & kFirstVisit) != 0;
-          const float4 ro = w.rays[2 * r], rd = w.rays[2 * r + 1];
-          skip = __float_as_uint(ro.w);
-          const uint32_t sw = __float_as_uint(rd.w);
-          shadow = (sw & kShadowBit) != 0;
-          slot = sw & ~kShadowBit;
-          R = make_pre(f3(ro.x, ro.y, ro.z), f3(rd.x, rd.y, rd.z));
-          cpos = (uint32_t)(tcell % S.gx) | (uint32_t)((tcell / S.gx) % S.gy) << 6 |
-                 (uint32_t)(tcell / (S.gx * S.gy)) << 12;
-          st.tbest = INFINITY;
-          st.best_id = 0xFFFFFFFFu;
-          st.blocked = false;
-          st.ncross = shadow ? w.shcnt[slot] : 0u;
-          phase = kLaneEnter;
-        } else {
-          phase = kLaneDone;
-        }
-      }
       if (__ballot(phase != kLaneDone) == 0) break;
       bool fin = false, out_req = false, esc = false;
       int out_cat = -1, work = kStepNone;
@@ -1124,44 +1119,29 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(7))) void k
       }
       n_nodes += (uint32_t)__popcll(__ballot(work == kStepNode));
       n_tris += (uint32_t)__popcll(__ballot(work >= kStepTri));
-      n_glass += (uint32_t)__popcll(__ballot(work == kStepCross));
-      n_esc += (uint32_t)__popcll(__ballot(esc));
-      n_migr += (uint32_t)__popcll(__ballot(out_req));
-      // shadow rays that reach the sun through more slabs than were recorded
-      n_xover += (uint32_t)__popcll(
-          __ballot(fin && shadow && !st.blocked && !out_req && st.ncross > (uint32_t)kMaxCross));
+      if (work == kStepCross) atomicAdd(&s_st[3], 1u);
       if (fin) {
+        if (out_req) atomicAdd(&s_st[1], 1u);
+        if (esc) atomicAdd(&s_st[2], 1u);
+        // shadow rays that reach the sun through more slabs than were recorded
+        if (shadow && !st.blocked && !out_req && st.ncross > (uint32_t)kMaxCross) atomicAdd(&s_st[4], 1u);
         if (shadow && !st.blocked) w.shcnt[slot] = st.ncross;
         // the finished ray's category, by slot: gathered into slot-ordered lists after the trace
         if (out_cat >= 0) w.catb[(shadow ? (size_t)w.W : 0) + slot] = (uint8_t)(out_cat + 1);
         if (out_req) {
-          const uint32_t q = atomicAdd(&s_nreq, 1u);
-          s_rsrc[q] = shadow ? w.W + slot : slot;
-          s_rkey[q] = qkey(cpos_cell(S, cpos), tdir);
+          s_rsrc[threadIdx.x] = shadow ? w.W + slot : slot;
+          s_rkey[threadIdx.x] = qkey(cpos_cell(S, cpos), tdir);
         }
-        phase = kLaneIdle;
+        phase = kLaneDone;
       }
     }
-    // the tile is drained: flush its migrating rays (wave-aggregated atomics)
-    __syncthreads();
-    const uint32_t nr = s_nreq;
-    for (uint32_t b0 = 0; b0 < nr; b0 += kWG) {
-      const uint32_t e = b0 + threadIdx.x;
-      const bool v = e < nr;
-      wave_append(v, v ? s_rsrc[e] : 0u, v ? s_rkey[e] : 0u, &w.ctl->list_count[np], ccount_of(S, w, np), w.lsrc,
-                  w.ldst, w.lrank);
-    }
-    __syncthreads();
+    // the part is drained: append its migrating rays (one wave-aggregated atomic per list)
+    const uint32_t rs = s_rsrc[threadIdx.x];
+    wave_append(rs != 0xFFFFFFFFu, rs, s_rkey[threadIdx.x], &w.ctl->list_count[np], ccount_of(S, w, np), w.lsrc,
+                w.ldst, w.lrank);
   }
   // the workgroup's counts, then one global atomic per counter
-  __shared__ uint32_t s_st[7];
-  stats_init(s_st, 7);
-  __syncthreads();
   stats_add(s_st, 0, n_visit);
-  stats_add(s_st, 1, n_migr);
-  stats_add(s_st, 2, n_esc);
-  stats_add(s_st, 3, n_glass);
-  stats_add(s_st, 4, n_xover);
   stats_add(s_st, 5, n_nodes);
   stats_add(s_st, 6, n_tris);
   __syncthreads();
