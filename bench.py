@@ -64,6 +64,8 @@ def parse():
     ap.add_argument("--wave-paths", type=int, default=1 << 25,
                     help="paths per wavefront (C2 measured 1046 / 925 / 889 / 838 / 821 ms per frame at 2^21 .. 2^25)")
     ap.add_argument("--queue-rounds", type=int, default=0)
+    ap.add_argument("--cell-order", type=int, default=1, choices=[0, 1],
+                    help="tile order of the traversal: 0 cell index, 1 fullest cells first")
     ap.add_argument("--large-train-frames", type=int, default=0,
                     help="large workload: frames trained one batch each before the period applies (0: every frame)")
     ap.add_argument("--large-train-period", type=int, default=1,
@@ -672,15 +674,15 @@ def bench_batch(args):
     os.makedirs(os.path.dirname(args.tune_cache), exist_ok=True)
     t0 = time.perf_counter()
     tune = ctx.autotune(sc, cams, sd.render_params(max_depth=8, seed=1),
-                        waves=[1 << 20, 1 << 21, 1 << 22, 1 << 23, 1 << 24],
-                        grids=[(4, 4, 4), (8, 8, 8), (16, 16, 16), (8, 4, 4)], rounds=(1, 2), calib_spp=1, reps=2,
-                        cache_path=args.tune_cache)
+                        waves=[1 << 22, 1 << 23, 1 << 24],
+                        grids=[(4, 4, 4), (8, 8, 8), (16, 16, 16), (8, 4, 4)], rounds=(1, 2), orders=(0, 1),
+                        calib_spp=1, reps=2, cache_path=args.tune_cache)
     tune_s = time.perf_counter() - t0
     best = tune["best"]
     S = sd.Scene.from_description(sc, grid=tuple(best["grid"]))
     ctx.upload(S)
     p = sd.render_params(max_depth=8, seed=1, wave_paths=best["wave_paths"], queue_rounds=best["queue_rounds"],
-                         use_graph=1, timing=1)
+                         cell_order=best["cell_order"], use_graph=1, timing=1)
     outs = [torch.empty((sc.n_bins, c.height, c.width), dtype=torch.float32, device="cuda") for c in cams]
     for _ in range(max(1, args.warmup)):   # the first call captures the graph
         ctx.render_batch(S, cams, spp, p, outs=outs)
@@ -744,7 +746,7 @@ def main():
     c = sd.camera(cam.eye, cam.target, cam.up, cam.vfov_deg, cam.width, cam.height)
     wave = min(args.wave_paths, cam.width * cam.height * cfg["spp"])
     p = sd.render_params(spp=cfg["spp"], max_depth=cfg["max_depth"], seed=1, wave_paths=max(64, wave),
-                         queue_rounds=args.queue_rounds, timing=1)
+                         queue_rounds=args.queue_rounds, timing=1, cell_order=args.cell_order)
     img = torch.empty((sc.n_bins, cam.height, cam.width), dtype=torch.float32, device="cuda")
     for _ in range(args.warmup):
         ctx.render(S, c, p, out=img)
@@ -783,7 +785,8 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": f"synthetic (seeded procedural scene, {sc.n_tri} triangles)",
         "config": {"workload": label, "triangles": sc.n_tri, "width": cam.width, "height": cam.height,
                    "spp": cfg["spp"], "bins": B, "max_depth": cfg["max_depth"], "grid": list(cfg["grid"]),
-                   "wave_paths": p.wave_paths, "queue_rounds": args.queue_rounds or 1},
+                   "wave_paths": p.wave_paths, "queue_rounds": args.queue_rounds or 1,
+                   "cell_order": args.cell_order},
         "ms_per_step_median": float(np.median(step_ms)), "ms_per_step_events": step_ms,
         "bin_samples_per_s": value * B,
         "roofline": {"kernel": "k_trace", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS,

@@ -202,6 +202,12 @@ typedef struct {
                                   graph the first time and replayed (one graph launch) while
                                   the same call (scene, views, images, workspace, parameters)
                                   repeats; timing then covers the whole graph               */
+  int32_t cell_order;          /* order in which the traversal takes the cells' queued rays
+                                  (section 5: the sub-model with the most waiting rays is taken
+                                  next): 0 cell index order, 1 fullest cells first (by the octave
+                                  of their queued rays, cell index inside an octave; grids of
+                                  more than 4096 cells keep index order). Results do not depend
+                                  on it.                                                     */
 } sdd_render_params;
 
 /* Workspace bytes for rendering with these parameters (paths in flight, bins, cells). */
@@ -266,13 +272,15 @@ typedef struct {
   int32_t queue_rounds[4];
   int32_t calib_spp;           /* samples per pixel of every view in calibration renders    */
   int32_t reps;                /* timed repetitions per candidate (the fastest is kept)     */
+  int32_t n_orders;            /* cell_order values to try, 0..2 (0: the base parameters')  */
+  int32_t cell_orders[2];
 } sdd_tune_space;
 
 typedef struct {
   int32_t grid[3];
   int32_t wave_paths;
   int32_t queue_rounds;
-  int32_t pad;
+  int32_t cell_order;
   double samples_per_s;
 } sdd_tune_point;
 
@@ -283,7 +291,7 @@ typedef struct {
   sdd_tune_point tried[128];
 } sdd_tune_result;
 
-/* Autotuner: picks the cell grid, wavefront size and queue rounds with the highest throughput
+/* Autotuner: picks the cell grid, wavefront size, queue rounds and cell order with the highest throughput
  * on short calibration renders of the given views (calib_spp samples each), timed with HIP
  * events. The scene is rebuilt on the host for every grid and uploaded to scene_buf; grids whose
  * scene does not fit scene_bytes, and wavefront sizes whose workspace does not fit ws_bytes, are

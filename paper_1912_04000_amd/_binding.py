@@ -89,7 +89,8 @@ class Camera(C.Structure):
 class RenderParams(C.Structure):
     _fields_ = [("spp", C.c_int32), ("max_depth", C.c_int32), ("seed", C.c_uint64), ("mode", C.c_int32),
                 ("wave_paths", C.c_int32), ("queue_rounds", C.c_int32), ("view", C.c_uint32),
-                ("timing", C.c_int32), ("first_sample", C.c_int32), ("use_graph", C.c_int32)]
+                ("timing", C.c_int32), ("first_sample", C.c_int32), ("use_graph", C.c_int32),
+                ("cell_order", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -111,16 +112,17 @@ class Stats(C.Structure):
 class TuneSpace(C.Structure):
     _fields_ = [("n_waves", C.c_int32), ("wave_paths", C.c_int32 * 8), ("n_grids", C.c_int32),
                 ("grids", (C.c_int32 * 3) * 8), ("n_rounds", C.c_int32), ("queue_rounds", C.c_int32 * 4),
-                ("calib_spp", C.c_int32), ("reps", C.c_int32)]
+                ("calib_spp", C.c_int32), ("reps", C.c_int32), ("n_orders", C.c_int32),
+                ("cell_orders", C.c_int32 * 2)]
 
 
 class TunePoint(C.Structure):
-    _fields_ = [("grid", C.c_int32 * 3), ("wave_paths", C.c_int32), ("queue_rounds", C.c_int32), ("pad", C.c_int32),
-                ("samples_per_s", C.c_double)]
+    _fields_ = [("grid", C.c_int32 * 3), ("wave_paths", C.c_int32), ("queue_rounds", C.c_int32),
+                ("cell_order", C.c_int32), ("samples_per_s", C.c_double)]
 
     def as_dict(self):
         return dict(grid=list(self.grid), wave_paths=self.wave_paths, queue_rounds=self.queue_rounds,
-                    samples_per_s=self.samples_per_s)
+                    cell_order=self.cell_order, samples_per_s=self.samples_per_s)
 
 
 class TuneResult(C.Structure):
@@ -383,8 +385,9 @@ def train_params(train_paths=0, step_records=1 << 14, steps=4, every=0) -> Train
 
 
 def render_params(spp=1, max_depth=4, seed=1, mode=MODE_PLAIN, wave_paths=0, queue_rounds=0, view=0, timing=0,
-                  first_sample=0, use_graph=0):
+                  first_sample=0, use_graph=0, cell_order=0):
     p = RenderParams()
+    p.cell_order = int(cell_order)
     p.first_sample = int(first_sample)
     p.use_graph = int(use_graph)
     p.spp, p.max_depth, p.seed, p.mode = int(spp), int(max_depth), int(seed), int(mode)
@@ -479,9 +482,10 @@ class Context:
         return outs
 
     def autotune(self, scene_description, cams, base: RenderParams, waves, grids, rounds=(1, 2), calib_spp=1,
-                 reps=2, cache_path=None, scene_bytes=None, ws_bytes=None):
-        """Measure (grid, wavefront size, queue rounds) candidates on calibration renders of the
-        views and return the fastest (the library's autotuner; cached in cache_path)."""
+                 reps=2, cache_path=None, scene_bytes=None, ws_bytes=None, orders=()):
+        """Measure (grid, wavefront size, queue rounds, cell order) candidates on calibration
+        renders of the views and return the fastest (the library's autotuner; cached in
+        cache_path). An empty `orders` keeps the base parameters' cell order."""
         torch = self.torch
         d, keep = desc_from(scene_description)
         sp = TuneSpace()
@@ -495,6 +499,9 @@ class Context:
         for i, r in enumerate(rounds):
             sp.queue_rounds[i] = int(r)
         sp.calib_spp, sp.reps = int(calib_spp), int(reps)
+        sp.n_orders = len(orders)
+        for i, o in enumerate(orders):
+            sp.cell_orders[i] = int(o)
         if scene_bytes is None:
             # finest grid bounds the scene size (more duplicated references): measure it once
             finest = max(grids, key=lambda g: g[0] * g[1] * g[2])

@@ -187,6 +187,7 @@ std::string check_params(const sdd_render_params* p) {
   if (p->wave_paths != 0 && (p->wave_paths < 64 || p->wave_paths > (1 << 26))) return "wave_paths out of range";
   if (p->queue_rounds < 0 || p->queue_rounds > 256) return "queue_rounds out of range";
   if (p->first_sample < 0) return "first_sample must be >= 0";
+  if (p->cell_order != 0 && p->cell_order != 1) return "cell_order must be 0 or 1";
   return "";
 }
 
@@ -343,7 +344,7 @@ int enqueue_frame(sdd_ctx* ctx, const sdd_scene* scene, const std::vector<ViewDe
   const int B = scene->hdr.n_bins;
   const uint32_t W = plan.W;
   DevScene S = device_view(scene);
-  Launch L{ctx->stream, plan.trace_blocks};
+  Launch L{ctx->stream, plan.trace_blocks, p->cell_order};
   int rc = store_views(ctx, views, w);
   if (rc) return rc;
   for (auto& v : views) HIP_TRY(ctx, launch_fill_f32(ctx->stream, v.image, (size_t)B * v.width * v.height, 0.0f));

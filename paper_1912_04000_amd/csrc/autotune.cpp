@@ -1,4 +1,5 @@
-// Autotuner: cell grid x wavefront size x queue rounds, measured on short calibration renders.
+// Autotuner: cell grid x wavefront size x queue rounds x cell order, measured on short calibration
+// renders.
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -50,7 +51,8 @@ bool read_cache(const char* path, uint64_t key, sdd_tune_point* out) {
     const char* w = std::strstr(line, "\"wave_paths\": ");
     const char* r = std::strstr(line, "\"queue_rounds\": ");
     const char* s = std::strstr(line, "\"samples_per_s\": ");
-    if (g && w && r && s &&
+    const char* o = std::strstr(line, "\"cell_order\": ");
+    if (g && w && r && s && o && std::sscanf(o, "\"cell_order\": %d", &out->cell_order) == 1 &&
         std::sscanf(g, "\"grid\": [%d, %d, %d]", &out->grid[0], &out->grid[1], &out->grid[2]) == 3 &&
         std::sscanf(w, "\"wave_paths\": %d", &out->wave_paths) == 1 &&
         std::sscanf(r, "\"queue_rounds\": %d", &out->queue_rounds) == 1 &&
@@ -67,9 +69,9 @@ void write_cache(const char* path, uint64_t key, const sdd_tune_point& b, const 
   if (!f) return;
   std::fprintf(f,
                "{\"key\": \"%016llx\", \"device\": \"%s\", \"grid\": [%d, %d, %d], \"wave_paths\": %d, "
-               "\"queue_rounds\": %d, \"samples_per_s\": %.6e, \"candidates\": %d}\n",
+               "\"queue_rounds\": %d, \"cell_order\": %d, \"samples_per_s\": %.6e, \"candidates\": %d}\n",
                (unsigned long long)key, device.c_str(), b.grid[0], b.grid[1], b.grid[2], b.wave_paths, b.queue_rounds,
-               b.samples_per_s, n_tried);
+               b.cell_order, b.samples_per_s, n_tried);
   std::fclose(f);
 }
 
@@ -84,7 +86,7 @@ extern "C" int sdd_autotune(sdd_ctx* ctx, const sdd_scene_desc* desc, const sdd_
     return SDD_ERR_INVALID_ARG;
   }
   if (sp->n_waves < 1 || sp->n_waves > 8 || sp->n_grids < 1 || sp->n_grids > 8 || sp->n_rounds < 1 ||
-      sp->n_rounds > 4 || sp->calib_spp < 1 || sp->reps < 1) {
+      sp->n_rounds > 4 || sp->calib_spp < 1 || sp->reps < 1 || sp->n_orders < 0 || sp->n_orders > 2) {
     sdd::set_thread_error("sdd_autotune: search space out of range");
     return SDD_ERR_INVALID_ARG;
   }
@@ -120,11 +122,13 @@ extern "C" int sdd_autotune(sdd_ctx* ctx, const sdd_scene_desc* desc, const sdd_
       continue;
     }
     rc = sdd_scene_upload(ctx, scene, scene_buf, scene_bytes);
+    const int n_orders = sp->n_orders ? sp->n_orders : 1;
     for (int wi = 0; wi < sp->n_waves && rc == SDD_OK; ++wi)
-      for (int ri = 0; ri < sp->n_rounds && rc == SDD_OK; ++ri) {
+      for (int ri = 0; ri < sp->n_rounds * n_orders && rc == SDD_OK; ++ri) {
         sdd_render_params p = *base;
         p.wave_paths = sp->wave_paths[wi];
-        p.queue_rounds = sp->queue_rounds[ri];
+        p.queue_rounds = sp->queue_rounds[ri % sp->n_rounds];
+        if (sp->n_orders) p.cell_order = sp->cell_orders[ri / sp->n_rounds];
         p.use_graph = 0;
         p.timing = 0;
         p.spp = sp->calib_spp;
@@ -148,6 +152,7 @@ extern "C" int sdd_autotune(sdd_ctx* ctx, const sdd_scene_desc* desc, const sdd_
         for (int a = 0; a < 3; ++a) pt.grid[a] = d.grid[a];
         pt.wave_paths = p.wave_paths;
         pt.queue_rounds = p.queue_rounds;
+        pt.cell_order = p.cell_order;
         pt.samples_per_s = samples / (best_ms * 1e-3);
         if (out->n_tried < 128) out->tried[out->n_tried++] = pt;
         if (pt.samples_per_s > best) {

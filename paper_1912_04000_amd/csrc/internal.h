@@ -269,6 +269,7 @@ struct PhotonDev {
 struct Launch {
   hipStream_t stream;
   int trace_blocks;   // workgroups of the persistent traversal grid (multiple of kXcds)
+  int cell_order = 0; // tile list order of the queue scan: 0 cell index, 1 fullest cells first
 };
 
 hipError_t launch_fill_f32(hipStream_t s, float* p, size_t n, float v);

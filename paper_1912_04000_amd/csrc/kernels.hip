@@ -560,6 +560,7 @@ __global__ void k_resolve_vis(DevScene S, DevWS w, uint32_t n, float* vis) {
 // ==========================================================================================
 constexpr int kScanThreads = 1024;
 constexpr int kScanLdsKeys = 8192;  // queue keys whose counts are staged in LDS (beyond: read from memory)
+constexpr int kScanOrderCells = 4096;  // largest grid whose cells the scan can order fullest first
 
 // Inclusive sums over the workgroup of one value per thread: shuffles within each wave, then the
 // wave totals, scanned by the first wave through LDS.
@@ -601,19 +602,78 @@ __device__ __forceinline__ void block_scan2(uint32_t& a, uint32_t& b, uint32_t* 
   }
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan(DevScene S, DevWS w, int gen) {
+// Order of the cells in the tile list when it is built fullest first: the cells sorted by the
+// octave of their queued rays (s_oct: 1 + floor(log2 count), 0 for an empty cell), fullest octave
+// first, ascending cell index inside an octave (neighbouring cells of similar load stay together).
+// Written to s_perm[0 .. n_cells); the workgroup must call it together. Each octave that holds cells
+// costs one pass over the per-thread chunks of cells and one workgroup prefix sum.
+__device__ void cell_order_fullest(int n_cells, const uint8_t* s_oct, uint16_t* s_perm, uint32_t* s_hist,
+                                   uint32_t* s_wa, uint32_t* s_wb) {
+  if (threadIdx.x < 33) s_hist[threadIdx.x] = 0;
+  __syncthreads();
+  for (int c = threadIdx.x; c < n_cells; c += kScanThreads) atomicAdd(&s_hist[s_oct[c]], 1u);
+  __syncthreads();
+  const int chunk = (n_cells + kScanThreads - 1) / kScanThreads;
+  const int c0 = min(n_cells, (int)threadIdx.x * chunk), c1 = min(n_cells, c0 + chunk);
+  uint32_t base = 0;
+  for (int o = 32; o >= 0; --o) {
+    const uint32_t in_oct = s_hist[o];  // the same for every thread: no divergence at the barriers
+    if (in_oct == 0) continue;
+    uint32_t f = 0;
+    for (int c = c0; c < c1; ++c) f += s_oct[c] == o ? 1u : 0u;
+    uint32_t incl = f, unused = 0;
+    block_scan2(incl, unused, s_wa, s_wb);
+    uint32_t pos = base + incl - f;
+    for (int c = c0; c < c1; ++c)
+      if (s_oct[c] == o) s_perm[pos++] = (uint16_t)c;
+    base += in_oct;
+    __syncthreads();  // s_wa / s_wb are rewritten by the next octave's prefix sum
+  }
+}
+
+// One workgroup turns the queue-key counts of the produced entries into the key offsets of the
+// cell-sorted queue (coff) and the tile list: a tile is up to kTile entries of one key, the tiles
+// of a key consecutive, the keys in cell order (order 0) or, for order 1 and grids of at most
+// kScanOrderCells cells, with the cells taken fullest first (cell_order_fullest) and the
+// direction classes of a cell in ascending order. The traversal hands the tiles out in list order
+// over the XCDs' ranges, so the fullest cells are started first and the launch ends on the
+// smallest queues (the paper's sub-model with the most waiting rays is taken next, section 5).
+__global__ __launch_bounds__(kScanThreads) void k_scan(DevScene S, DevWS w, int gen, int order) {
   __shared__ uint32_t s_cnt[kScanThreads], s_til[kScanThreads], s_key[kScanLdsKeys];
   __shared__ uint32_t s_wa[kScanThreads / 64], s_wb[kScanThreads / 64];
+  __shared__ uint16_t s_perm[kScanOrderCells];
+  __shared__ uint8_t s_oct[kScanOrderCells];
+  __shared__ uint32_t s_hist[33];
   const int p = gen & 1;
   const uint32_t* cnt = ccount_of(S, w, p);
   const int nc = S.n_cells * kDirBins;   // queue keys: (cell, direction octant)
   const bool staged = nc <= kScanLdsKeys;
+  const bool ordered = order == 1 && S.n_cells <= kScanOrderCells;
+  auto count_of = [&](uint32_t k) -> uint32_t { return staged ? s_key[k] : cnt[(size_t)k * kKeyStride]; };
+  // counts staged in LDS by key
+  if (staged) {
+    for (int k = threadIdx.x; k < nc; k += kScanThreads) s_key[k] = cnt[(size_t)k * kKeyStride];
+    __syncthreads();
+  }
+  if (ordered) {
+    for (int c = threadIdx.x; c < S.n_cells; c += kScanThreads) {
+      uint32_t t = 0;
+      for (int b = 0; b < kDirBins; ++b) t += count_of(c * kDirBins + b);
+      s_oct[c] = (uint8_t)(t ? 32u - (uint32_t)__clz(t) : 0u);
+    }
+    __syncthreads();
+    cell_order_fullest(S.n_cells, s_oct, s_perm, s_hist, s_wa, s_wb);
+    __syncthreads();
+  }
+  // position c of the ordered key sequence -> queue key
+  auto key_at = [&](int c) -> uint32_t {
+    return ordered ? (uint32_t)s_perm[c / kDirBins] * kDirBins + (uint32_t)(c % kDirBins) : (uint32_t)c;
+  };
   const int chunk = (nc + kScanThreads - 1) / kScanThreads;
   const int c0 = min(nc, (int)threadIdx.x * chunk), c1 = min(nc, c0 + chunk);
   uint32_t sc = 0, st = 0;
   for (int c = c0; c < c1; ++c) {
-    const uint32_t x = cnt[(size_t)c * kKeyStride];
-    if (staged) s_key[c] = x;
+    const uint32_t x = count_of(key_at(c));
     sc += x;
     st += (x + kTile - 1) / kTile;
   }
@@ -624,8 +684,9 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(DevScene S, DevWS w, int 
   __syncthreads();
   uint32_t run = ic - sc;
   for (int c = c0; c < c1; ++c) {
-    w.coff[c] = run;
-    run += staged ? s_key[c] : cnt[(size_t)c * kKeyStride];
+    const uint32_t k = key_at(c);
+    w.coff[k] = run;
+    run += count_of(k);
   }
   // Tiles are written by the whole workgroup, each thread a contiguous block of them: the key of
   // its first tile comes from a binary search of the per-thread tile sums and a walk over that
@@ -647,18 +708,19 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(DevScene S, DevWS w, int 
     }
     uint32_t tb = lo ? s_til[lo - 1] : 0u, cb = lo ? s_cnt[lo - 1] : 0u;
     int c = lo * chunk;
-    uint32_t x = staged ? s_key[c] : cnt[(size_t)c * kKeyStride], nt = (x + kTile - 1) / kTile;
+    uint32_t k = key_at(c), x = count_of(k), nt = (x + kTile - 1) / kTile;
     for (; t < t_end; ++t) {
       // keys with no tile left are passed over; t < n_tiles keeps c below nc
       while (t >= tb + nt && c + 1 < nc) {
         tb += nt;
         cb += x;
         ++c;
-        x = staged ? s_key[c] : cnt[(size_t)c * kKeyStride];
+        k = key_at(c);
+        x = count_of(k);
         nt = (x + kTile - 1) / kTile;
       }
       const uint32_t q = t - tb;
-      w.tiles[t] = make_uint4((uint32_t)c, cb + q * kTile, min((uint32_t)kTile, x - q * kTile), 0u);
+      w.tiles[t] = make_uint4(k, cb + q * kTile, min((uint32_t)kTile, x - q * kTile), 0u);
     }
   }
   if (threadIdx.x == kScanThreads - 1) {
@@ -2487,7 +2549,7 @@ hipError_t launch_raygen(const Launch& L, const DevScene& S, const DevWS& w, uin
 }
 
 hipError_t launch_scan(const Launch& L, const DevScene& S, const DevWS& w, int gen) {
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, L.stream, S, w, gen);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, L.stream, S, w, gen, L.cell_order);
   return hipGetLastError();
 }
 

@@ -1,0 +1,90 @@
+"""Cell scheduling of the traversal: the tile list built fullest cells first (section 5: the
+sub-model with the most waiting rays is taken next) against the oracle, and against the cell
+index order, whose images it must reproduce bit for bit (a ray's result does not depend on which
+workgroup traces it or when, and the image update runs in slot order).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import scenegen
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1912_04000_amd as sd
+    return sd.Context(0)
+
+
+def _pixel_parity(img, ref, tied, label):
+    B = ref.shape[0]
+    mean_bin = ref.reshape(B, -1).mean(axis=1)
+    tol = 1e-4 * np.maximum(np.abs(ref), 1e-3 * mean_bin[:, None, None])
+    ok = tied == 0
+    bad = (np.abs(img - ref) > tol) & ok[None]
+    say(f"[{label}] pixels={ok.size} tie-free={ok.sum()} bad={bad.any(axis=0).sum()}")
+    assert not bad.any(), np.argwhere(bad)[:10]
+    return ok
+
+
+# (2, 2, 2): counts staged in LDS; (8, 8, 8): 12288 queue keys, read from memory; (3, 2, 5): a
+# ragged grid; three rounds: rays migrate through the queues between cells
+@pytest.mark.parametrize("grid,rounds,wave", [((2, 2, 2), 0, 0), ((8, 8, 8), 0, 777), ((3, 2, 5), 3, 0),
+                                              ((8, 8, 8), 4, 0)])
+def test_fullest_first_matches_oracle_and_index_order(ctx, grid, rounds, wave):
+    import paper_1912_04000_amd as sd
+    sc = scenegen.nave_scene(8)
+    cam = scenegen.nave_camera(48, 40)
+    S = sd.Scene.from_description(sc, grid=grid)
+    ctx.upload(S)
+    c = sd.camera(cam.eye, cam.target, cam.up, cam.vfov_deg, cam.width, cam.height)
+    say(f"fullest first: grid={grid} rounds={rounds} wave={wave}")
+    imgs = [ctx.render(S, c, sd.render_params(spp=2, max_depth=6, seed=5, wave_paths=wave, queue_rounds=rounds,
+                                               cell_order=order)).cpu().numpy() for order in (0, 1)]
+    assert np.array_equal(imgs[0], imgs[1])
+    ref = oracle.render(sc, cam, spp=2, max_depth=6, seed=5)
+    ok = _pixel_parity(imgs[1], ref.image, ref.tied, f"grid={grid} rounds={rounds}")
+    assert ok.mean() > 0.9
+
+
+def test_fullest_first_church_one_spp_identical(ctx):
+    """The church frame (8 x 4 x 4 cells, 2^25-path wavefronts) at 1 spp in both orders: the same
+    image bit for bit, and the same traversal work counted."""
+    import paper_1912_04000_amd as sd
+    sc = scenegen.church_scene(40)
+    cam = scenegen.church_camera()
+    S = sd.Scene.from_description(sc, grid=(8, 4, 4))
+    ctx.upload(S)
+    c = sd.camera(cam.eye, cam.target, cam.up, cam.vfov_deg, cam.width, cam.height)
+    imgs, stats = [], []
+    for order in (0, 1):
+        say(f"church 1 spp, cell_order={order}")
+        ctx.finish()
+        ctx.reset_stats()
+        imgs.append(ctx.render(S, c, sd.render_params(spp=1, max_depth=8, seed=3, wave_paths=1 << 25,
+                                                      cell_order=order)).cpu().numpy())
+        ctx.finish()
+        stats.append(ctx.stats())
+    assert np.array_equal(imgs[0], imgs[1])
+    for k in ("cell_visits", "node_visits", "tri_tests", "vertices", "shadow_rays"):
+        assert stats[0][k] == stats[1][k], (k, stats[0][k], stats[1][k])
+
+
+def test_cell_order_out_of_range_is_rejected(ctx):
+    import paper_1912_04000_amd as sd
+    sc = scenegen.nave_scene(8)
+    cam = scenegen.nave_camera(8, 8)
+    S = sd.Scene.from_description(sc, grid=(2, 2, 2))
+    ctx.upload(S)
+    c = sd.camera(cam.eye, cam.target, cam.up, cam.vfov_deg, cam.width, cam.height)
+    with pytest.raises(sd.SddError, match="cell_order"):
+        ctx.render(S, c, sd.render_params(spp=1, max_depth=2, seed=1, cell_order=2))
