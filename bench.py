@@ -64,6 +64,8 @@ def parse():
     ap.add_argument("--wave-paths", type=int, default=1 << 25,
                     help="paths per wavefront (C2 measured 1046 / 925 / 889 / 838 / 821 ms per frame at 2^21 .. 2^25)")
     ap.add_argument("--queue-rounds", type=int, default=0)
+    ap.add_argument("--persistent", type=int, default=0, choices=[0, 1],
+                    help="church/nave workloads: render with the one persistent kernel instead of the wavefronts")
     ap.add_argument("--cell-order", type=int, default=1, choices=[0, 1],
                     help="tile order of the traversal: 0 cell index, 1 fullest cells first")
     ap.add_argument("--large-train-frames", type=int, default=0,
@@ -698,6 +700,18 @@ def bench_batch(args):
     st = ctx.stats()
     samples = sum(c.width * c.height * s for c, s in zip(cams, spp)) * args.steps
     value = samples / dt
+    # the same batch as one persistent kernel (work list of (view, tile, sample) items), also one
+    # graph launch per step, on the tuned grid
+    pp = sd.render_params(max_depth=8, seed=1, use_graph=1, timing=1, persistent=1)
+    ctx.render_batch(S, cams, spp, pp, outs=outs)   # captures its graph
+    ctx.finish()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.render_batch(S, cams, spp, pp, outs=outs, finish=False)
+    torch.cuda.synchronize()
+    dt_p = time.perf_counter() - t1
+    ctx.finish()
     out = {
         "metric": METRIC, "value": value, "unit": "spectral path samples/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
@@ -708,6 +722,10 @@ def bench_batch(args):
                    "tune_from_cache": tune["from_cache"], "tune_seconds": tune_s,
                    "tune_candidates": len(tune["tried"])},
         "graph_ms_per_step": st["graph_ms"] / max(1, st["graph_launches"]),
+        "persistent": {"samples_per_s": samples / dt_p, "ms_per_step": dt_p / args.steps * 1e3,
+                       "relative_to_wavefront": (samples / dt_p) / value,
+                       "note": "the same 32 views as one persistent kernel per step (lanes taking (view, 8x8 "
+                               "tile, sample) items from a device work list), graph-launched, tuned grid"},
         "tune_table": tune["tried"],
     }
     print(json.dumps(out), flush=True)
@@ -745,8 +763,10 @@ def main():
     ctx.upload(S)
     c = sd.camera(cam.eye, cam.target, cam.up, cam.vfov_deg, cam.width, cam.height)
     wave = min(args.wave_paths, cam.width * cam.height * cfg["spp"])
-    p = sd.render_params(spp=cfg["spp"], max_depth=cfg["max_depth"], seed=1, wave_paths=max(64, wave),
-                         queue_rounds=args.queue_rounds, timing=1, cell_order=args.cell_order)
+    p = sd.render_params(spp=cfg["spp"], max_depth=cfg["max_depth"], seed=1,
+                         wave_paths=0 if args.persistent else max(64, wave),
+                         queue_rounds=args.queue_rounds, timing=1, cell_order=args.cell_order,
+                         persistent=args.persistent)
     img = torch.empty((sc.n_bins, cam.height, cam.width), dtype=torch.float32, device="cuda")
     for _ in range(args.warmup):
         ctx.render(S, c, p, out=img)
@@ -786,7 +806,7 @@ def main():
         "config": {"workload": label, "triangles": sc.n_tri, "width": cam.width, "height": cam.height,
                    "spp": cfg["spp"], "bins": B, "max_depth": cfg["max_depth"], "grid": list(cfg["grid"]),
                    "wave_paths": p.wave_paths, "queue_rounds": args.queue_rounds or 1,
-                   "cell_order": args.cell_order},
+                   "cell_order": args.cell_order, "persistent": args.persistent},
         "ms_per_step_median": float(np.median(step_ms)), "ms_per_step_events": step_ms,
         "bin_samples_per_s": value * B,
         "roofline": {"kernel": "k_trace", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS,

@@ -208,6 +208,16 @@ typedef struct {
                                   of their queued rays, cell index inside an octave; grids of
                                   more than 4096 cells keep index order). Results do not depend
                                   on it.                                                     */
+  int32_t persistent;          /* 1: the whole render (every view of a batch) is ONE persistent
+                                  kernel: its lanes take (view, 8 x 8 tile, sample) items from a
+                                  device work list, each lane carrying one path through all its
+                                  vertices (same random numbers and arithmetic, so the same
+                                  image up to the order of the float additions into a pixel),
+                                  then its next item; wave_paths is then the number of lanes
+                                  (rounded up to a multiple of 2048, at most 2^19; 0 = as many
+                                  as the device holds at once);
+                                  queue_rounds and cell_order are unused. Plain mode only (not
+                                  with photon maps, a cache or sdd_render_noalloc).           */
 } sdd_render_params;
 
 /* Workspace bytes for rendering with these parameters (paths in flight, bins, cells). */

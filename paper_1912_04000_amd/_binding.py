@@ -90,7 +90,7 @@ class RenderParams(C.Structure):
     _fields_ = [("spp", C.c_int32), ("max_depth", C.c_int32), ("seed", C.c_uint64), ("mode", C.c_int32),
                 ("wave_paths", C.c_int32), ("queue_rounds", C.c_int32), ("view", C.c_uint32),
                 ("timing", C.c_int32), ("first_sample", C.c_int32), ("use_graph", C.c_int32),
-                ("cell_order", C.c_int32)]
+                ("cell_order", C.c_int32), ("persistent", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -385,9 +385,10 @@ def train_params(train_paths=0, step_records=1 << 14, steps=4, every=0) -> Train
 
 
 def render_params(spp=1, max_depth=4, seed=1, mode=MODE_PLAIN, wave_paths=0, queue_rounds=0, view=0, timing=0,
-                  first_sample=0, use_graph=0, cell_order=0):
+                  first_sample=0, use_graph=0, cell_order=0, persistent=0):
     p = RenderParams()
     p.cell_order = int(cell_order)
+    p.persistent = int(persistent)
     p.first_sample = int(first_sample)
     p.use_graph = int(use_graph)
     p.spp, p.max_depth, p.seed, p.mode = int(spp), int(max_depth), int(seed), int(mode)

@@ -38,6 +38,26 @@ int fail(sdd_ctx* c, int code, const std::string& msg) {
 
 constexpr int kDefaultWave = 1 << 20;
 constexpr int kDefaultRounds = 1;
+// Persistent render: lanes of the one kernel (a multiple of kWG * kXcds; the traversal spill of a
+// plan covers at most 2048 workgroups)
+constexpr int kPersistDefaultLanes = 1536 * kWG;
+constexpr int kPersistMaxLanes = 2048 * kWG;
+constexpr uint32_t kPersistTileItems = 64;  // items of one 8 x 8 tile at one sample
+
+// Lanes of a persistent render: as asked, else as many as the device holds at once (the
+// kernel's occupancy times the compute units; kPersistDefaultLanes if the runtime cannot tell),
+// never more than the work list has items, a multiple of kWG * kXcds.
+uint32_t persist_lanes(const sdd_render_params* p, uint64_t total, int device) {
+  const uint64_t g = (uint64_t)kWG * kXcds;
+  uint64_t L = (uint64_t)p->wave_paths;
+  if (!L) {
+    const uint64_t resident = (uint64_t)persist_resident_blocks(device) * kWG;
+    L = resident >= g ? resident / g * g : (uint64_t)kPersistDefaultLanes;
+  }
+  L = std::min<uint64_t>(L, (total + g - 1) / g * g);
+  L = (L + g - 1) / g * g;
+  return (uint32_t)std::min<uint64_t>(std::max<uint64_t>(L, g), kPersistMaxLanes);
+}
 // Ray queries (sdd_trace / sdd_shadow) run one migration round before walking in place, so that
 // every query also exercises the migration between cell queues.
 constexpr int kQueryRounds = 2;
@@ -188,6 +208,9 @@ std::string check_params(const sdd_render_params* p) {
   if (p->queue_rounds < 0 || p->queue_rounds > 256) return "queue_rounds out of range";
   if (p->first_sample < 0) return "first_sample must be >= 0";
   if (p->cell_order != 0 && p->cell_order != 1) return "cell_order must be 0 or 1";
+  if (p->persistent != 0 && p->persistent != 1) return "persistent must be 0 or 1";
+  if (p->persistent && p->mode != SDD_MODE_PLAIN) return "persistent rendering is plain mode only";
+  if (p->persistent && p->wave_paths > kPersistMaxLanes) return "persistent rendering takes at most 2^19 lanes";
   return "";
 }
 
@@ -349,6 +372,15 @@ int enqueue_frame(sdd_ctx* ctx, const sdd_scene* scene, const std::vector<ViewDe
   if (rc) return rc;
   for (auto& v : views) HIP_TRY(ctx, launch_fill_f32(ctx->stream, v.image, (size_t)B * v.width * v.height, 0.0f));
   HIP_TRY(ctx, launch_fill_u32(ctx->stream, (uint32_t*)w.ctl, offsetof(Ctl, st_paths) / 4, 0u));
+  if (p->persistent) {
+    // one kernel: the work list's chunk counters (the per-XCD tile counters) start at zero above
+    if (timing) record(ctx, ctx->ev_trace, ctx->ev_used_trace, true);
+    HIP_TRY(ctx, launch_persist(L, S, w, total, p->seed, p->max_depth, W));
+    if (timing) record(ctx, ctx->ev_trace, ctx->ev_used_trace, false);
+    ctx->acc.trace_launches++;
+    ctx->acc.wavefronts++;
+    return SDD_OK;
+  }
   HIP_TRY(ctx, launch_fill_u32(ctx->stream, w.ccount, 2ull * scene->hdr.n_cells * kDirBins * kKeyStride, 0u));
   int gen = 0;
   const PathMode render_mode{0u, 0, nullptr, nullptr, gm ? gm_from : 0};
@@ -396,11 +428,15 @@ int render_views(sdd_ctx* ctx, const sdd_scene* scene, std::vector<ViewDesc>& vi
   uint64_t total = 0;
   for (auto& v : views) {
     v.item_base = total;
-    total += (uint64_t)v.width * v.height * (uint64_t)v.spp;
+    if (p->persistent)  // the work list: (8 x 8 tile, sample) items, 64 per tile and sample
+      total += (uint64_t)((v.width + 7) / 8) * ((v.height + 7) / 8) * kPersistTileItems * (uint64_t)v.spp;
+    else
+      total += (uint64_t)v.width * v.height * (uint64_t)v.spp;
   }
   // never more paths in flight than the frame has items
   uint32_t W = (uint32_t)std::min<uint64_t>(p->wave_paths ? (uint64_t)p->wave_paths : (uint64_t)kDefaultWave, total);
   W = std::max<uint32_t>(W, 64);
+  if (p->persistent) W = persist_lanes(p, total, ctx->device);
   Plan plan = make_plan(W, B, scene->hdr.n_cells, (int)views.size());
   if (!ws) return fail(ctx, SDD_ERR_INVALID_ARG, "workspace is null");
   if (ws_bytes < plan.total)
@@ -750,6 +786,11 @@ int sdd_workspace_bytes(const sdd_scene* s, const sdd_render_params* p, size_t* 
   std::string e = check_params(p);
   if (!e.empty()) return fail(nullptr, SDD_ERR_INVALID_ARG, e);
   uint32_t W = p->wave_paths ? (uint32_t)p->wave_paths : (uint32_t)kDefaultWave;
+  if (p->persistent) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    W = persist_lanes(p, UINT64_MAX / 2, dev);
+  }
   *bytes = make_plan(W, s->hdr.n_bins, s->hdr.n_cells, 64).total;
   return SDD_OK;
 }
@@ -785,8 +826,8 @@ int sdd_render_noalloc(sdd_ctx* c, const sdd_scene* s, const sdd_camera* cam, co
   if (!e.empty()) return fail(c, SDD_ERR_INVALID_ARG, e);
   if (p->mode != SDD_MODE_PLAIN) return fail(c, SDD_ERR_INVALID_ARG, "sdd_render_noalloc renders in plain mode only");
   // graph instantiation and timing events allocate: not here
-  if (p->use_graph || p->timing)
-    return fail(c, SDD_ERR_INVALID_ARG, "sdd_render_noalloc takes neither use_graph nor timing");
+  if (p->use_graph || p->timing || p->persistent)
+    return fail(c, SDD_ERR_INVALID_ARG, "sdd_render_noalloc takes neither use_graph, timing nor persistent");
   std::vector<ViewDesc> views(1);
   e = make_view(*cam, &views[0]);
   if (!e.empty()) return fail(c, SDD_ERR_INVALID_ARG, e);
@@ -1187,6 +1228,7 @@ int sdd_render_photons(sdd_ctx* c, const sdd_scene* s, const sdd_photon_map* cau
   std::string e = check_params(p);
   if (!e.empty()) return fail(c, SDD_ERR_INVALID_ARG, e);
   if (p->mode != SDD_MODE_PLAIN) return fail(c, SDD_ERR_INVALID_ARG, "sdd_render_photons renders in plain mode");
+  if (p->persistent) return fail(c, SDD_ERR_INVALID_ARG, "sdd_render_photons does not render persistent");
   for (const sdd_photon_map* m : {caustic, global}) {
     if (!m) continue;
     if (!m->built) return fail(c, SDD_ERR_NOT_READY, "photon map has not been built");

@@ -194,12 +194,12 @@ struct Vertex {
   int m;
 };
 
-__device__ __forceinline__ Vertex load_vertex(const DevScene& S, const DevWS& w, uint32_t s) {
+// The surface vertex where the ray (o, d) hits triangle id at the traversal's distance t: the
+// hit re-evaluated by refine_hit, the face-forward normal and the spawn offset.
+__device__ __forceinline__ Vertex make_vertex(const DevScene& S, F3 o, F3 d, uint32_t id, float t) {
   Vertex V;
-  const float4 h = w.hit[s];
-  V.id = __float_as_uint(h.y);
-  const float4 rdir = w.rays[2 * s + 1];
-  V.d = f3(rdir.x, rdir.y, rdir.z);
+  V.id = id;
+  V.d = d;
   const float4 A = S.gtris[(size_t)V.id * 3 + 0], Bv = S.gtris[(size_t)V.id * 3 + 1], C = S.gtris[(size_t)V.id * 3 + 2];
   const F3 v0 = f3(A.x, A.y, A.z), v1 = f3(Bv.x, Bv.y, Bv.z), v2 = f3(C.x, C.y, C.z);
   V.m = (int)__float_as_uint(Bv.w);
@@ -207,15 +207,21 @@ __device__ __forceinline__ Vertex load_vertex(const DevScene& S, const DevWS& w,
   V.dn = dot_exact_sign(V.d, V.ng);
   V.n = V.dn > 0.0f ? V.ng * -1.0f : V.ng;
   V.cos_o = fabsf(V.dn);
-  const float4 rorg = w.rays[2 * s];
-  float t = h.x, bu = 1.0f / 3.0f, bv = 1.0f / 3.0f;
+  float bu = 1.0f / 3.0f, bv = 1.0f / 3.0f;
   F3 q = ((v1 - v0) + (v2 - v0)) * (1.0f / 3.0f);
-  refine_hit(f3(rorg.x, rorg.y, rorg.z), V.d, v0, v1, v2, t, q, bu, bv);
+  refine_hit(o, V.d, v0, v1, v2, t, q, bu, bv);
   V.p = v0 + q;
   V.bu = bu;
   V.bv = bv;
   V.eps = 1e-5f * (1.0f + maxabs3(V.p));
   return V;
+}
+
+// The vertex of path slot s: its extension ray and hit record from the workspace.
+__device__ __forceinline__ Vertex load_vertex(const DevScene& S, const DevWS& w, uint32_t s) {
+  const float4 h = w.hit[s];
+  const float4 rorg = w.rays[2 * s], rdir = w.rays[2 * s + 1];
+  return make_vertex(S, f3(rorg.x, rorg.y, rorg.z), f3(rdir.x, rdir.y, rdir.z), __float_as_uint(h.y), h.x);
 }
 
 }  // namespace sdd

@@ -288,6 +288,9 @@ hipError_t launch_shade_glass(const Launch& L, const DevScene& S, const DevWS& w
                               const PathMode& pm);
 hipError_t launch_accumulate(const Launch& L, const DevScene& S, const DevWS& w, uint32_t s0, uint32_t n,
                              bool unique);
+uint32_t persist_resident_blocks(int device);
+hipError_t launch_persist(const Launch& L, const DevScene& S, const DevWS& w, uint64_t total, uint64_t seed,
+                          int max_depth, uint32_t lanes);
 hipError_t launch_pack_rays(const Launch& L, const DevScene& S, const DevWS& w, const float* orig, const float* dir,
                             const int32_t* skip, uint32_t n, int shadow, int gen);
 hipError_t launch_unpack_hits(const Launch& L, const DevScene& S, const DevWS& w, uint32_t n, float* t, int32_t* id,

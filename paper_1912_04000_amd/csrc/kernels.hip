@@ -488,6 +488,30 @@ __global__ void k_unpack_hits(DevScene S, DevWS w, uint32_t n, float* t, int32_t
   }
 }
 
+// Crossing c of slot s's shadow ray (from its record): material, incidence cosine and, for a
+// material with a transmittance map (tx >= 0), the texture coordinates of the crossing point.
+__device__ __forceinline__ void crossing_at(const DevScene& S, const DevWS& w, uint32_t s, uint32_t c, F3 o, F3 d,
+                                            int& m, float& cosv, int& tx, float& ss, float& tt) {
+  const float2 x = w.shx[(size_t)c * w.W + s];
+  const uint32_t tri = __float_as_uint(x.y);
+  const float4* g = S.gtris + (size_t)tri * 3;
+  const float4 A = g[0], B = g[1], C = g[2];
+  const F3 v0 = f3(A.x, A.y, A.z), v1 = f3(B.x, B.y, B.z), v2 = f3(C.x, C.y, C.z);
+  m = __float_as_int(x.x);
+  cosv = fabsf(dot3(d, geo_normal(v0, v1, v2)));
+  tx = -1;
+  ss = tt = 0.0f;
+  if (S.n_tex > 0) {
+    tx = S.mtex[m];
+    if (tx >= 0) {
+      float t = 0.0f, bu = 1.0f / 3.0f, bv = 1.0f / 3.0f;
+      F3 qq;
+      refine_hit(o, d, v0, v1, v2, t, qq, bu, bv);
+      hit_st(S, tri, bu, bv, ss, tt);
+    }
+  }
+}
+
 // Glass crossings of the shadow ray of slot s (at most kMaxCross recorded, material and
 // triangle id each): the material and |cos| between the ray and the slab's normal of each, and
 // for a material with a transmittance map (tx >= 0) the texture coordinates of the crossing,
@@ -495,31 +519,14 @@ __global__ void k_unpack_hits(DevScene S, DevWS w, uint32_t n, float* t, int32_t
 __device__ __forceinline__ void crossings(const DevScene& S, const DevWS& w, uint32_t s, uint32_t nc, int* mq,
                                           float* cq, int* tx, float* sq, float* tq) {
   const float4 ro = w.rays[2 * ((size_t)w.W + s)], rd = w.rays[2 * ((size_t)w.W + s) + 1];
-  const F3 d = f3(rd.x, rd.y, rd.z);
+  const F3 o = f3(ro.x, ro.y, ro.z), d = f3(rd.x, rd.y, rd.z);
 #pragma unroll
   for (int q = 0; q < kMaxCross; ++q) {
     mq[q] = 0;
     cq[q] = 1.0f;
     tx[q] = -1;
     sq[q] = tq[q] = 0.0f;
-    if ((uint32_t)q < nc) {
-      const float2 x = w.shx[(size_t)q * w.W + s];
-      const uint32_t tri = __float_as_uint(x.y);
-      const float4* g = S.gtris + (size_t)tri * 3;
-      const float4 A = g[0], B = g[1], C = g[2];
-      const F3 v0 = f3(A.x, A.y, A.z), v1 = f3(B.x, B.y, B.z), v2 = f3(C.x, C.y, C.z);
-      mq[q] = __float_as_int(x.x);
-      cq[q] = fabsf(dot3(d, geo_normal(v0, v1, v2)));
-      if (S.n_tex > 0) {
-        tx[q] = S.mtex[mq[q]];
-        if (tx[q] >= 0) {
-          float t = 0.0f, bu = 1.0f / 3.0f, bv = 1.0f / 3.0f;
-          F3 qq;
-          refine_hit(f3(ro.x, ro.y, ro.z), d, v0, v1, v2, t, qq, bu, bv);
-          hit_st(S, tri, bu, bv, sq[q], tq[q]);
-        }
-      }
-    }
+    if ((uint32_t)q < nc) crossing_at(S, w, s, (uint32_t)q, o, d, mq[q], cq[q], tx[q], sq[q], tq[q]);
   }
 }
 
@@ -1340,59 +1347,112 @@ __device__ __forceinline__ void row_write(float4* dst, int nq, bool store, F f) 
   }
 }
 
+// The direct term of slot s's shadow ray that reached the sun, into its radiance row: the weight
+// stored when the ray was spawned, times the transmittance of the nc glass slabs it crossed (none:
+// nc = 0), each slab's from its material, crossing angle and, with a transmittance map, the map
+// at the crossing point.
+__device__ __forceinline__ void add_direct(const DevScene& S, const DevWS& w, uint32_t s, uint32_t nc) {
+  const int Bp = w.Bp, nq = Bp / 4;
+  const float4* e = (const float4*)(w.nee + (size_t)s * Bp);
+  if (nc == 0) {
+    row_update<12>((float4*)(w.lacc + (size_t)s * Bp), nq, [&](int q, float4 l) {
+      const float4 a = e[q];
+      return make_float4(l.x + a.x, l.y + a.y, l.z + a.z, l.w + a.w);
+    });
+    return;
+  }
+  int mq[kMaxCross], tx[kMaxCross];
+  float cq[kMaxCross], sq[kMaxCross], tq[kMaxCross];
+  crossings(S, w, s, nc, mq, cq, tx, sq, tq);
+  const float4* lam = (const float4*)S.lambda;
+  row_update<12>((float4*)(w.lacc + (size_t)s * Bp), nq, [&](int q, float4 l) {
+    float4 V = make_float4(1.0f, 1.0f, 1.0f, 1.0f);
+    const float4 la = lam[q];
+#pragma unroll
+    for (int c = 0; c < kMaxCross; ++c) {
+      if ((uint32_t)c < nc) {
+        const int m = mq[c];
+        const float4 nn = ((const float4*)(S.ntab + m * Bp))[q], kk = ((const float4*)(S.ktab + m * Bp))[q];
+        float R0, T0, R1, T1, R2, T2, R3, T3;
+        if (tx[c] >= 0) {
+          const float4 t4 = tex_quad(tex_tap(S, tx[c], sq[c], tq[c]), q);
+          slab_tau0(nn.x, kk.x, t4.x, cq[c], R0, T0);
+          slab_tau0(nn.y, kk.y, t4.y, cq[c], R1, T1);
+          slab_tau0(nn.z, kk.z, t4.z, cq[c], R2, T2);
+          slab_tau0(nn.w, kk.w, t4.w, cq[c], R3, T3);
+        } else {
+          slab(nn.x, kk.x, la.x, S.thick[m], cq[c], R0, T0);
+          slab(nn.y, kk.y, la.y, S.thick[m], cq[c], R1, T1);
+          slab(nn.z, kk.z, la.z, S.thick[m], cq[c], R2, T2);
+          slab(nn.w, kk.w, la.w, S.thick[m], cq[c], R3, T3);
+        }
+        V.x *= T0;
+        V.y *= T1;
+        V.z *= T2;
+        V.w *= T3;
+      }
+    }
+    const float4 a = e[q];
+    return make_float4(l.x + a.x * V.x, l.y + a.y * V.y, l.z + a.z * V.z, l.w + a.w * V.w);
+  });
+}
+
+// add_direct for the persistent kernel, in few registers: the weight row is multiplied by one
+// crossed slab's transmittance at a time (crossing order), then added to the radiance row.
+__device__ __forceinline__ void add_direct_seq(const DevScene& S, const DevWS& w, uint32_t s, uint32_t nc) {
+  const int Bp = w.Bp, nq = Bp / 4;
+  float4* e = (float4*)(w.nee + (size_t)s * Bp);
+  const float4 ro = w.rays[2 * ((size_t)w.W + s)], rd = w.rays[2 * ((size_t)w.W + s) + 1];
+  const F3 o = f3(ro.x, ro.y, ro.z), d = f3(rd.x, rd.y, rd.z);
+  const float4* lam = (const float4*)S.lambda;
+  for (uint32_t c = 0; c < nc; ++c) {
+    int m, tx;
+    float cq, ss, tt;
+    crossing_at(S, w, s, c, o, d, m, cq, tx, ss, tt);
+    TexTap tap;
+    tap.base = nullptr;
+    tap.r00 = tap.r10 = tap.r01 = tap.r11 = 0;
+    tap.fx = tap.fy = 0.0f;
+    if (tx >= 0) tap = tex_tap(S, tx, ss, tt);
+    const float4* nt = (const float4*)(S.ntab + m * Bp);
+    const float4* kt = (const float4*)(S.ktab + m * Bp);
+    const float th = S.thick[m];
+    row_update<2>(e, nq, [&](int q, float4 a) {
+      const float4 nn = nt[q], kk = kt[q], la = lam[q];
+      float R0, T0, R1, T1, R2, T2, R3, T3;
+      if (tx >= 0) {
+        const float4 t4 = tex_quad(tap, q);
+        slab_tau0(nn.x, kk.x, t4.x, cq, R0, T0);
+        slab_tau0(nn.y, kk.y, t4.y, cq, R1, T1);
+        slab_tau0(nn.z, kk.z, t4.z, cq, R2, T2);
+        slab_tau0(nn.w, kk.w, t4.w, cq, R3, T3);
+      } else {
+        slab(nn.x, kk.x, la.x, th, cq, R0, T0);
+        slab(nn.y, kk.y, la.y, th, cq, R1, T1);
+        slab(nn.z, kk.z, la.z, th, cq, R2, T2);
+        slab(nn.w, kk.w, la.w, th, cq, R3, T3);
+      }
+      return make_float4(a.x * T0, a.y * T1, a.z * T2, a.w * T3);
+    });
+  }
+  row_update<4>((float4*)(w.lacc + (size_t)s * Bp), nq, [&](int q, float4 l) {
+    const float4 a = e[q];
+    return make_float4(l.x + a.x, l.y + a.y, l.z + a.z, l.w + a.w);
+  });
+}
+
 __global__ __launch_bounds__(kWG) void k_resolve(DevScene S, DevWS w, int depth) {
   const int p = depth & 1;
   const uint32_t n_clear = w.ctl->cat_count[p][kCatShadowClear * kKeyStride];
   const uint32_t n_glass = w.ctl->cat_count[p][kCatShadowGlass * kKeyStride];
   if (blockIdx.x == 0 && threadIdx.x < kCats) w.ctl->cat_count[p ^ 1][threadIdx.x * kKeyStride] = 0;  // next bounce
   const uint32_t n = n_clear + n_glass;
-  const int Bp = w.Bp, nq = Bp / 4;
   for (uint32_t i = blockIdx.x * kWG + threadIdx.x; i < n; i += gridDim.x * kWG) {
     if (i < n_clear) {
-      const uint32_t s = cat_list(w, p, kCatShadowClear)[i];
-      const float4* e = (const float4*)(w.nee + (size_t)s * Bp);
-      row_update<12>((float4*)(w.lacc + (size_t)s * Bp), nq, [&](int q, float4 l) {
-        const float4 a = e[q];
-        return make_float4(l.x + a.x, l.y + a.y, l.z + a.z, l.w + a.w);
-      });
+      add_direct(S, w, cat_list(w, p, kCatShadowClear)[i], 0u);
     } else {
       const uint32_t s = cat_list(w, p, kCatShadowGlass)[i - n_clear];
-      const uint32_t nc = min(w.shcnt[s], (uint32_t)kMaxCross);
-      const float4* e = (const float4*)(w.nee + (size_t)s * Bp);
-      int mq[kMaxCross], tx[kMaxCross];
-      float cq[kMaxCross], sq[kMaxCross], tq[kMaxCross];
-      crossings(S, w, s, nc, mq, cq, tx, sq, tq);
-      const float4* lam = (const float4*)S.lambda;
-      row_update<12>((float4*)(w.lacc + (size_t)s * Bp), nq, [&](int q, float4 l) {
-        float4 V = make_float4(1.0f, 1.0f, 1.0f, 1.0f);
-        const float4 la = lam[q];
-#pragma unroll
-        for (int c = 0; c < kMaxCross; ++c) {
-          if ((uint32_t)c < nc) {
-            const int m = mq[c];
-            const float4 nn = ((const float4*)(S.ntab + m * Bp))[q], kk = ((const float4*)(S.ktab + m * Bp))[q];
-            float R0, T0, R1, T1, R2, T2, R3, T3;
-            if (tx[c] >= 0) {
-              const float4 t4 = tex_quad(tex_tap(S, tx[c], sq[c], tq[c]), q);
-              slab_tau0(nn.x, kk.x, t4.x, cq[c], R0, T0);
-              slab_tau0(nn.y, kk.y, t4.y, cq[c], R1, T1);
-              slab_tau0(nn.z, kk.z, t4.z, cq[c], R2, T2);
-              slab_tau0(nn.w, kk.w, t4.w, cq[c], R3, T3);
-            } else {
-              slab(nn.x, kk.x, la.x, S.thick[m], cq[c], R0, T0);
-              slab(nn.y, kk.y, la.y, S.thick[m], cq[c], R1, T1);
-              slab(nn.z, kk.z, la.z, S.thick[m], cq[c], R2, T2);
-              slab(nn.w, kk.w, la.w, S.thick[m], cq[c], R3, T3);
-            }
-            V.x *= T0;
-            V.y *= T1;
-            V.z *= T2;
-            V.w *= T3;
-          }
-        }
-        const float4 a = e[q];
-        return make_float4(l.x + a.x * V.x, l.y + a.y * V.y, l.z + a.z * V.z, l.w + a.w * V.w);
-      });
+      add_direct(S, w, s, min(w.shcnt[s], (uint32_t)kMaxCross));
     }
   }
 }
@@ -1826,6 +1886,463 @@ __global__ __launch_bounds__(kWG) void k_accumulate(DevScene S, DevWS w, uint32_
   // non-finite radiance (an overflow of huge but finite inputs, for example) is added to the
   // image as it is and counted; sdd_finish reports it. One atomic per wave that saw any.
   wave_add(&w.ctl->err_nonfinite, n_bad);
+}
+
+// ==========================================================================================
+// persistent batched render: the whole batch of views in one kernel (plain mode)
+// ==========================================================================================
+// Work list: the path samples of every view as (view, tile, sample) items, a tile being 8 x 8
+// pixels, one item per (tile, sample) pair and pixel of the tile (64 per tile and sample, those
+// beyond a ragged view edge empty). View v owns items [item_base_v, item_base_v + T_v 64 spp_v),
+// T_v tiles, in sample-major order (all tiles of sample 0, then sample 1, ...), so that the
+// pixels of a tile at one sample are consecutive items and start together in one wave. The list
+// is this index space, decoded on the device from the views' prefix offsets; waves take it in
+// chunks of 64 items, each XCD from its own contiguous range first (an atomic on a per-XCD
+// counter per chunk), then from the others'.
+constexpr uint32_t kPersistTile = 8;
+constexpr uint32_t kPersistChunk = 64;
+
+// Item g of the work list: its view, pixel (row-major within the view) and sample; false for an
+// empty item (a tile pixel outside the view).
+__device__ __forceinline__ bool persist_item(const DevWS& w, uint64_t g, uint32_t& v, uint32_t& pix, uint32_t& smp) {
+  int lo = 0, hi = w.n_views - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (w.views[mid].item_base <= g)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  v = (uint32_t)lo;
+  const ViewDesc& V = w.views[lo];
+  const uint32_t tx = ((uint32_t)V.width + kPersistTile - 1) / kPersistTile;
+  const uint32_t ty = ((uint32_t)V.height + kPersistTile - 1) / kPersistTile;
+  const uint64_t local = g - V.item_base;
+  const uint32_t i = (uint32_t)(local % 64u);
+  const uint64_t ts = local / 64u;
+  const uint32_t nt = tx * ty;
+  uint32_t t;
+  if ((ts >> 32) == 0) {  // 32-bit division where it suffices
+    t = (uint32_t)ts % nt;
+    smp = (uint32_t)ts / nt + V.first_sample;
+  } else {
+    t = (uint32_t)(ts % nt);
+    smp = (uint32_t)(ts / nt) + V.first_sample;
+  }
+  const uint32_t px = (t % tx) * kPersistTile + i % kPersistTile;
+  const uint32_t py = (t / tx) * kPersistTile + i / kPersistTile;
+  pix = py * (uint32_t)V.width + px;
+  return px < (uint32_t)V.width && py < (uint32_t)V.height;
+}
+
+// The whole walk of each lane's ray through the cells, for the persistent kernel: a closest-hit
+// ray until its first hit (st.best_id, st.tbest) or the grid's exit, a shadow ray until an opaque
+// triangle blocks it (st.blocked) or it leaves the grid, its glass crossings recorded at slot
+// `slot` (st.ncross). The lanes of a wave step together, one BVH node or triangle each per
+// iteration, until every lane is done; lanes with go false only join the loop. Cells are entered
+// in the half-open slab intervals of the traversal kernel, the first one from t > 0.
+__device__ __forceinline__ void walk_ray(const DevScene& S, const DevWS& w, const float* s_planes, const int4* s_cells,
+                                         bool cells_lds, bool go, const RayPre& R, bool shadow, uint32_t skip,
+                                         uint32_t cell0, uint32_t slot, uint32_t* stack, uint32_t* spill,
+                                         TraceState& st, uint32_t& n_visit, uint32_t& n_nodes, uint32_t& n_tris,
+                                         uint32_t& n_cross) {
+  int phase = go && cell0 != kInvalidCell ? kLaneEnter : kLaneDone;
+  uint32_t cpos = 0;
+  if (phase == kLaneEnter)
+    cpos = (cell0 % (uint32_t)S.gx) | ((cell0 / (uint32_t)S.gx) % (uint32_t)S.gy) << 6 |
+           (cell0 / (uint32_t)(S.gx * S.gy)) << 12;
+  bool first = true;
+  float t_lo = 0.0f, tf = 0.0f;
+  int4 cinfo = make_int4(0, 0, 0, 0);
+  uint32_t node = 0, pend = 0;
+  int sp = 0;
+  for (;;) {
+    if (__ballot(phase != kLaneDone) == 0) break;
+    int work = kStepNone;
+    n_visit += (uint32_t)__popcll(__ballot(phase == kLaneEnter));
+    if (phase == kLaneEnter) {
+      float tn;
+      const int ix = (int)(cpos & 63u), iy = (int)((cpos >> 6) & 63u), iz = (int)((cpos >> 12) & 63u);
+      const int cell = (int)cpos_cell(S, cpos);
+      int axis;
+      cell_interval_pl(s_planes, S.gx, S.gy, ix, iy, iz, R.o, R.inv, tn, tf, axis);
+      cpos = (cpos & ~(3u << 26)) | (uint32_t)axis << 26;
+      t_lo = first ? -INFINITY : tn;
+      if (cells_lds) {
+        const __attribute__((address_space(3))) int* c = (const __attribute__((address_space(3))) int*)s_cells + 4 * cell;
+        cinfo = make_int4(c[0], c[1], c[2], c[3]);
+      } else {
+        const __attribute__((address_space(1))) int* c = (const __attribute__((address_space(1))) int*)S.cells + 4 * cell;
+        cinfo = make_int4(c[0], c[1], c[2], c[3]);
+      }
+      if (cinfo.y > 0 && t_lo < tf) {
+        if (!shadow) st.tbest = tf;
+        node = 0;
+        sp = 0;
+        pend = 0;
+        phase = kLaneTrav;
+      } else {
+        phase = kLaneLeave;
+      }
+    }
+    if (phase == kLaneTrav) {
+      if (!trav_step(S, w, R, shadow, cinfo, stack, spill, w.trace_threads, skip, t_lo, tf, slot, st, node, sp, pend,
+                     work))
+        phase = (shadow && st.blocked) || (!shadow && st.best_id != 0xFFFFFFFFu) ? kLaneDone : kLaneLeave;
+    }
+    if (phase == kLaneLeave) {
+      const int axis = (int)((cpos >> 26) & 3u);
+      const float dc = comp(R.inv, axis);
+      const int g = axis == 0 ? S.gx : (axis == 1 ? S.gy : S.gz);
+      const int ni = (int)((cpos >> (6 * axis)) & 63u) + (dc > 0.0f ? 1 : -1);
+      if (ni < 0 || ni >= g || !(tf < INFINITY)) {
+        phase = kLaneDone;
+      } else {
+        cpos = (cpos & ~(63u << (6 * axis))) | ((uint32_t)ni << (6 * axis));
+        first = false;
+        phase = kLaneEnter;
+      }
+    }
+    n_nodes += (uint32_t)__popcll(__ballot(work == kStepNode));
+    n_tris += (uint32_t)__popcll(__ballot(work >= kStepTri));
+    n_cross += (uint32_t)__popcll(__ballot(work == kStepCross));
+  }
+}
+
+// One persistent kernel renders a batch of views. Each lane carries one path at a time through
+// all its vertices with the arithmetic of the wavefront kernels (same random-number counters,
+// lobe rules, Fresnel and slab factors, hit re-evaluation), its spectral rows in the workspace
+// slot of its thread; a lane whose path ends adds the path's radiance / spp to its pixel
+// (atomics: other samples of the pixel may be in flight) and takes the next item of the work
+// list, so the wave's lanes stay busy until the list is exhausted. A loop iteration traces each
+// lane's current ray (extension or shadow) through the cells, then shades: at an opaque vertex
+// the direct-term weight and the continuation are computed, the shadow ray is traced in the next
+// iteration and the continuation after it; at glass the continuation directly.
+// Four waves per SIMD (128 registers, a little spilled): measured faster than three (161 registers,
+// none spilled) and five on the church frame.
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k_persist(DevScene S, DevWS w, uint64_t total, uint32_t key0, uint32_t key1,
+                                                 int max_depth) {
+  __shared__ uint32_t s_stack[kShortStack * kWG];
+  __shared__ float s_planes[3 * (kMaxGrid + 1)];
+  __shared__ int4 s_cells[kLdsCells];
+  __shared__ uint32_t s_st[10];
+  const int n_planes = S.gx + S.gy + S.gz + 3;
+  const bool cells_lds = S.n_cells <= kLdsCells;
+  for (int q = threadIdx.x; q < n_planes; q += kWG) s_planes[q] = S.planes[q];
+  if (cells_lds)
+    for (int q = threadIdx.x; q < S.n_cells; q += kWG) s_cells[q] = S.cells[q];
+  stats_init(s_st, 10);
+  __syncthreads();
+  const uint32_t slot = blockIdx.x * kWG + threadIdx.x;
+  uint32_t* stack = s_stack + threadIdx.x;
+  uint32_t* spill = w.spill + slot;
+  const int B = S.n_bins, Bp = w.Bp, nq = Bp / 4;
+  float4* b4 = (float4*)(w.beta + (size_t)slot * Bp);
+  float4* e4 = (float4*)(w.nee + (size_t)slot * Bp);
+  float4* l4 = (float4*)(w.lacc + (size_t)slot * Bp);
+  const F3 ws = f3(S.sun[0], S.sun[1], S.sun[2]);
+  const size_t W = w.W;
+  const uint32_t xcd = blockIdx.x % kXcds;
+  const uint64_t n_chunks = (total + kPersistChunk - 1) / kPersistChunk;
+  uint32_t donor = 0;      // ranges of the work list this wave has exhausted (wave-uniform)
+  uint64_t cb = 0, ce = 0; // items of the wave's current chunk not yet handed out (wave-uniform)
+  bool active = false;     // the lane carries a path
+  uint32_t view = 0, pix = 0, smp = 0;
+  int depth = 0;           // surface vertices of the path so far
+  bool shadow = false;     // the lane's current ray is a shadow ray
+  bool cont = false;       // a continuation ray waits behind the shadow ray
+  F3 ro = f3(0.0f, 0.0f, 0.0f), rd = ro, co = ro, cd = ro;
+  uint32_t skip = 0, cskip = 0;
+  uint32_t n_visit = 0, n_nodes = 0, n_tris = 0, n_cross = 0, n_bad = 0;
+  for (;;) {
+    // idle lanes take the next items of the work list, in lane order
+    for (;;) {
+      const uint64_t idle = __ballot(!active);
+      if (idle == 0) break;
+      if (cb == ce) {
+        bool got = false;
+        for (; donor < (uint32_t)kXcds; ++donor) {
+          const uint32_t X = (xcd + donor) % kXcds;
+          const uint64_t b = n_chunks * X / kXcds, e = n_chunks * (X + 1) / kXcds;
+          uint32_t q = 0;
+          if (lane_id() == 0) q = atomicAdd(&w.ctl->tile_next[X * kKeyStride], 1u);
+          q = __builtin_amdgcn_readfirstlane(q);
+          if (b + q < e) {
+            cb = (b + q) * kPersistChunk;
+            ce = min(total, cb + kPersistChunk);
+            got = true;
+            break;
+          }
+        }
+        if (!got) break;
+      }
+      const uint32_t rank = count_below(idle);
+      const uint64_t take = min((uint64_t)__popcll(idle), ce - cb);
+      bool started = false;
+      if (!active && rank < take) {
+        uint32_t v, px, sm;
+        if (persist_item(w, cb + rank, v, px, sm)) {
+          // camera ray (vertex 0), as in ray generation
+          view = v;
+          pix = px;
+          smp = sm;
+          const ViewDesc& V = w.views[v];
+          const uint32_t x = pix % (uint32_t)V.width, y = pix / (uint32_t)V.width;
+          const uint4 rn = philox(make_uint4(pix, smp, 0u, V.view_id), key0, key1);
+          const float sx = 2.0f * ((float)x + unif24(rn.x)) / (float)V.width - 1.0f;
+          const float sy = 1.0f - 2.0f * ((float)y + unif24(rn.y)) / (float)V.height;
+          const F3 fw = f3(V.fwd[0], V.fwd[1], V.fwd[2]);
+          const F3 rt = f3(V.right[0], V.right[1], V.right[2]);
+          const F3 up = f3(V.upv[0], V.upv[1], V.upv[2]);
+          rd = norm3(fw + rt * sx + up * sy);
+          ro = f3(V.eye[0], V.eye[1], V.eye[2]);
+          skip = 0xFFFFFFFFu;
+          shadow = false;
+          cont = false;
+          depth = 0;
+          for (int q = 0; q < nq; ++q) {
+            b4[q] = make_float4(1.0f, 1.0f, 1.0f, 1.0f);
+            l4[q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+          }
+          active = true;
+          started = true;
+        }
+      }
+      stats_add_ballot(s_st, 0, started);
+      cb += take;
+    }
+    if (__ballot(active) == 0) break;  // the list is exhausted and every path has ended
+    // trace every lane's current ray through the cells
+    const RayPre R = make_pre(ro, rd);
+    const uint32_t cell0 = active ? start_cell_pl(S, s_planes, ro, rd) : kInvalidCell;
+    TraceState st;
+    st.tbest = INFINITY;
+    st.best_id = 0xFFFFFFFFu;
+    st.blocked = false;
+    st.ncross = 0;
+    walk_ray(S, w, s_planes, s_cells, cells_lds, active, R, shadow, skip, cell0, slot, stack, spill, st, n_visit,
+             n_nodes, n_tris, n_cross);
+    stats_add_ballot(s_st, 1, active && !shadow);
+    stats_add_ballot(s_st, 2, active && shadow);
+    bool done = false, escaped = false, shaded = false, overflow = false;
+    if (active) {
+      if (shadow) {
+        // the direct term of the vertex, through the glass it crossed, unless an opaque triangle
+        // blocked the way to the sun
+        if (!st.blocked) {
+          overflow = st.ncross > (uint32_t)kMaxCross;
+          add_direct_seq(S, w, slot, min(st.ncross, (uint32_t)kMaxCross));
+        }
+        if (cont) {
+          ro = co;
+          rd = cd;
+          skip = cskip;
+          shadow = false;
+          cont = false;
+        } else {
+          done = true;
+        }
+      } else if (st.best_id == 0xFFFFFFFFu) {
+        // the path leaves the scene: environment radiance
+        if (S.env_nonzero) {
+          const float4* env = (const float4*)S.env;
+          row_update<4>(l4, nq, [&](int q, float4 l) {
+            const float4 a = b4[q], e = env[q];
+            return make_float4(l.x + a.x * e.x, l.y + a.y * e.y, l.z + a.z * e.z, l.w + a.w * e.w);
+          });
+        }
+        escaped = true;
+        done = true;
+      } else {
+        ++depth;
+        const Vertex V = make_vertex(S, ro, rd, st.best_id, st.tbest);
+        const uint4 rn = philox(make_uint4(pix, smp, (uint32_t)depth, w.views[view].view_id), key0, key1);
+        const float u0 = unif24(rn.x), u1 = unif24(rn.y), u2 = unif24(rn.z);
+        const float4* nt = (const float4*)(S.ntab + V.m * Bp);
+        const float4* kt = (const float4*)(S.ktab + V.m * Bp);
+        shaded = S.mtype[V.m] == 0 || depth < max_depth;  // glass at the last vertex ends the path unshaded
+        if (S.mtype[V.m] != 0) {
+          // glass: thin slab, reflect or transmit straight through; no direct term
+          if (depth < max_depth) {
+            const float4* lam = (const float4*)S.lambda;
+            const float th = S.thick[V.m];
+            const int tx = S.n_tex > 0 ? S.mtex[V.m] : -1;
+            TexTap tap;
+            tap.base = nullptr;
+            tap.r00 = tap.r10 = tap.r01 = tap.r11 = 0;
+            tap.fx = tap.fy = 0.0f;
+            if (tx >= 0) {
+              float ss, tt;
+              hit_st(S, V.id, V.bu, V.bv, ss, tt);
+              tap = tex_tap(S, tx, ss, tt);
+            }
+            auto slab4 = [&](int q, float (&Rr)[4], float (&Tt)[4]) {
+              const float4 nn = nt[q], kk = kt[q], la = lam[q];
+              if (tx >= 0) {
+                const float4 t4 = tex_quad(tap, q);
+                slab_tau0(nn.x, kk.x, t4.x, V.cos_o, Rr[0], Tt[0]);
+                slab_tau0(nn.y, kk.y, t4.y, V.cos_o, Rr[1], Tt[1]);
+                slab_tau0(nn.z, kk.z, t4.z, V.cos_o, Rr[2], Tt[2]);
+                slab_tau0(nn.w, kk.w, t4.w, V.cos_o, Rr[3], Tt[3]);
+              } else {
+                slab(nn.x, kk.x, la.x, th, V.cos_o, Rr[0], Tt[0]);
+                slab(nn.y, kk.y, la.y, th, V.cos_o, Rr[1], Tt[1]);
+                slab(nn.z, kk.z, la.z, th, V.cos_o, Rr[2], Tt[2]);
+                slab(nn.w, kk.w, la.w, th, V.cos_o, Rr[3], Tt[3]);
+              }
+            };
+            float mr = 0.0f, mt = 0.0f;
+            for (int q = 0; q < nq; ++q) {
+              float Rr[4], Tt[4];
+              slab4(q, Rr, Tt);
+#pragma unroll
+              for (int c = 0; c < 4; ++c)
+                if (4 * q + c < B) {
+                  mr += Rr[c];
+                  mt += Tt[c];
+                }
+            }
+            const float Pr = mr / (mr + mt);
+            const bool refl = u0 < Pr;
+            const float inv_p = refl ? 1.0f / Pr : 1.0f / (1.0f - Pr);
+            row_update<2>(b4, nq, [&](int q, float4 b) {
+              float Rr[4], Tt[4];
+              slab4(q, Rr, Tt);
+              return make_float4(b.x * ((refl ? Rr[0] : Tt[0]) * inv_p), b.y * ((refl ? Rr[1] : Tt[1]) * inv_p),
+                                 b.z * ((refl ? Rr[2] : Tt[2]) * inv_p), b.w * ((refl ? Rr[3] : Tt[3]) * inv_p));
+            });
+            rd = refl ? V.d - V.ng * (2.0f * V.dn) : V.d;
+            ro = refl ? V.p + V.n * V.eps : V.p - V.n * V.eps;
+            skip = V.id;
+          } else {
+            done = true;
+          }
+        } else {
+          // opaque: direct term toward the sun (a shadow ray), Fresnel-split lobe choice
+          const float4* rt = (const float4*)(S.rho + V.m * Bp);
+          const float4* E4 = (const float4*)S.sunE;
+          const float cs = dot_exact_sign(V.n, ws);
+          const bool nee = cs > 0.0f;
+          const float kn = cs * (1.0f / 3.14159265358979f);
+          float a_sum = 0.0f, b_sum = 0.0f;
+          row_write<2>(e4, nq, nee, [&](int q) {
+            const float4 nn = nt[q], kk = kt[q], rr = rt[q];
+            const float F[4] = {fresnel(nn.x, kk.x, V.cos_o), fresnel(nn.y, kk.y, V.cos_o),
+                                fresnel(nn.z, kk.z, V.cos_o), fresnel(nn.w, kk.w, V.cos_o)};
+            const float rho[4] = {rr.x, rr.y, rr.z, rr.w};
+            float dif[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+              dif[c] = (1.0f - F[c]) * rho[c];
+              if (4 * q + c < B) {
+                a_sum += F[c];
+                b_sum += dif[c];
+              }
+            }
+            float4 out = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (nee) {
+              const float4 bb = b4[q], EE = E4[q];
+              out = make_float4(bb.x * dif[0] * kn * EE.x, bb.y * dif[1] * kn * EE.y, bb.z * dif[2] * kn * EE.z,
+                                bb.w * dif[3] * kn * EE.w);
+            }
+            return out;
+          });
+          const float am = a_sum / (float)B, bm = b_sum / (float)B;
+          bool go_on = depth < max_depth && am + bm > 0.0f;
+          bool mirror = false;
+          float inv_p = 0.0f;
+          if (go_on) {
+            const float Ps = am / (am + bm);
+            mirror = u0 < Ps;
+            inv_p = mirror ? 1.0f / Ps : 1.0f / (1.0f - Ps);
+            row_update<2>(b4, nq, [&](int q, float4 bb) {
+              const float4 nn = nt[q], kk = kt[q], rr = rt[q];
+              const float F0 = fresnel(nn.x, kk.x, V.cos_o), F1 = fresnel(nn.y, kk.y, V.cos_o),
+                          F2 = fresnel(nn.z, kk.z, V.cos_o), F3v = fresnel(nn.w, kk.w, V.cos_o);
+              bb.x *= (mirror ? F0 : (1.0f - F0) * rr.x) * inv_p;
+              bb.y *= (mirror ? F1 : (1.0f - F1) * rr.y) * inv_p;
+              bb.z *= (mirror ? F2 : (1.0f - F2) * rr.z) * inv_p;
+              bb.w *= (mirror ? F3v : (1.0f - F3v) * rr.w) * inv_p;
+              return bb;
+            });
+            F3 nd;
+            if (mirror) {
+              nd = V.d - V.ng * (2.0f * V.dn);
+            } else {
+              float sn, cn;
+              sincosf(2.0f * 3.14159265358979f * u1, &sn, &cn);
+              const float rr = sqrtf(u2);
+              const float lx = rr * cn, ly = rr * sn, lz = sqrtf(fmaxf(0.0f, 1.0f - u2));
+              const F3 nrm = V.n;
+              const float sg = copysignf(1.0f, nrm.z);
+              const float aa = -1.0f / (sg + nrm.z);
+              const float bb = nrm.x * nrm.y * aa;
+              const F3 t1 = f3(1.0f + sg * nrm.x * nrm.x * aa, sg * bb, -sg * nrm.x);
+              const F3 t2 = f3(bb, sg + nrm.y * nrm.y * aa, -nrm.y);
+              nd = t1 * lx + t2 * ly + nrm * lz;
+            }
+            co = V.p + V.n * V.eps;
+            cd = nd;
+            cskip = V.id;
+          }
+          if (nee) {
+            // the shadow ray first (its record in the workspace serves the glass crossings), then
+            // the continuation
+            ro = V.p + V.n * V.eps;
+            rd = ws;
+            skip = V.id;
+            shadow = true;
+            cont = go_on;
+            w.rays[2 * (W + slot)] = make_float4(ro.x, ro.y, ro.z, __uint_as_float(V.id));
+            w.rays[2 * (W + slot) + 1] = make_float4(ws.x, ws.y, ws.z, __uint_as_float(slot | kShadowBit));
+          } else if (go_on) {
+            ro = co;
+            rd = cd;
+            skip = cskip;
+          } else {
+            done = true;
+          }
+        }
+      }
+    }
+    stats_add_ballot(s_st, 3, escaped);
+    stats_add_ballot(s_st, 4, shaded);
+    stats_add_ballot(s_st, 8, overflow);
+    if (done) {
+      // the path's radiance / spp into its pixel
+      const ViewDesc& V = w.views[view];
+      const size_t plane = (size_t)V.width * V.height;
+      float* img = V.image + pix;
+      for (int q = 0; q < nq; ++q) {
+        const float4 l = l4[q];
+        const float c4[4] = {l.x, l.y, l.z, l.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int j = 4 * q + e;
+          const float c = c4[e] * V.inv_spp;
+          n_bad += (j < B && !isfinite(c)) ? 1u : 0u;
+          if (j < B && c != 0.0f) unsafeAtomicAdd(img + (size_t)j * plane, c);
+        }
+      }
+      active = false;
+    }
+  }
+  stats_add(s_st, 5, n_visit);
+  stats_add(s_st, 6, n_nodes);
+  stats_add(s_st, 7, n_tris);
+  stats_add(s_st, 9, n_cross);
+  wave_add(&w.ctl->err_nonfinite, n_bad);
+  __syncthreads();
+  stats_flush(s_st, 0, &w.ctl->st_paths);
+  stats_flush(s_st, 1, &w.ctl->st_ext);
+  stats_flush(s_st, 2, &w.ctl->st_shadow);
+  stats_flush(s_st, 3, &w.ctl->st_escape);
+  stats_flush(s_st, 4, &w.ctl->st_vertices);
+  stats_flush(s_st, 5, &w.ctl->st_visits);
+  stats_flush(s_st, 6, &w.ctl->st_nodes);
+  stats_flush(s_st, 7, &w.ctl->st_tris);
+  stats_flush(s_st, 8, &w.ctl->err_cross);
+  stats_flush(s_st, 9, &w.ctl->st_glass);
 }
 
 // ==========================================================================================
@@ -2614,6 +3131,24 @@ hipError_t launch_accumulate(const Launch& L, const DevScene& S, const DevWS& w,
     hipLaunchKernelGGL(k_accumulate<true>, dim3(grid_for(n, 8192)), dim3(kWG), 0, L.stream, S, w, s0, n);
   else
     hipLaunchKernelGGL(k_accumulate<false>, dim3(grid_for(n, 8192)), dim3(kWG), 0, L.stream, S, w, s0, n);
+  return hipGetLastError();
+}
+
+// Workgroups of k_persist the device holds at once (its occupancy times the compute units), 0 if
+// the runtime cannot tell.
+uint32_t persist_resident_blocks(int device) {
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_persist), kWG, 0) !=
+          hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+    return 0;
+  return (uint32_t)(per_cu * cus);
+}
+
+hipError_t launch_persist(const Launch& L, const DevScene& S, const DevWS& w, uint64_t total, uint64_t seed,
+                          int max_depth, uint32_t lanes) {
+  hipLaunchKernelGGL(k_persist, dim3(lanes / kWG), dim3(kWG), 0, L.stream, S, w, total, (uint32_t)seed,
+                     (uint32_t)(seed >> 32), max_depth);
   return hipGetLastError();
 }
 
