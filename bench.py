@@ -251,16 +251,47 @@ def pmc_summary(args):
     print(json.dumps({k: round(v["hbm_bytes_per_launch"] / 1e6, 3) for k, v in kernels.items()}))
 
 
+_REF_NOISE_VAR = 0.0   # noise variance of the loaded reference's mean (subtracted from every MSE)
+
+
 def _rmse(img, ref, px):
-    """RMSE over (subset pixel, bin) of an image [B][H][W] against the reference [B][n]."""
+    """RMSE over (subset pixel, bin) of an image [B][H][W] against the reference [B][n], with the
+    reference's own noise variance (estimated from its two independent halves) subtracted."""
     B = ref.shape[0]
     sub = img.reshape(B, -1)[:, px]
-    return float(np.sqrt(np.mean((sub.astype(np.float64) - ref) ** 2)))
+    return float(np.sqrt(max(np.mean((sub.astype(np.float64) - ref) ** 2) - _REF_NOISE_VAR, 0.0)))
 
 
 def load_reference():
+    """The oracle's C4 reference (tests/golden/c4_reference.npz): pixel indices, the mean image
+    [B][n] of its two halves, and their noise variance, which _rmse subtracts from then on."""
+    global _REF_NOISE_VAR
     ref_f = np.load(os.path.join(ROOT, "tests", "golden", "c4_reference.npz"))
+    _REF_NOISE_VAR = float(ref_f["noise_var"]) if "noise_var" in ref_f.files else 0.0
     return ref_f["pixels"], ref_f["image"].astype(np.float64)
+
+
+def reference_note():
+    ref_f = np.load(os.path.join(ROOT, "tests", "golden", "c4_reference.npz"))
+    st = int(ref_f["stride"])
+    return (f"oracle FP64 {int(ref_f['spp'])} spp, pixels x%{st}==0 and y%{st}==0 ({len(ref_f['pixels'])}), "
+            f"its noise variance {float(ref_f['noise_var']) if 'noise_var' in ref_f.files else 0.0:.3e} subtracted")
+
+
+def plain_curve(ctx, S, c, img, px, ref, wave, spps, W, H):
+    """Plain frames (seed 1) at each spp, their RMSE against the reference, and the least-squares
+    fit RMSE = a / sqrt(spp) with the log-log slope (-0.5 for an unbiased estimator)."""
+    import paper_1912_04000_amd as sd
+    plain = []
+    for spp in spps:
+        dt = _timed(lambda: ctx.render(S, c, sd.render_params(spp=spp, max_depth=8, seed=1, wave_paths=wave,
+                                                              cell_order=1), out=img))
+        plain.append(dict(spp=spp, seconds=dt, rmse=_rmse(img.cpu().numpy(), ref, px)))
+    sp = np.array([q["spp"] for q in plain], dtype=np.float64)
+    rm = np.array([q["rmse"] for q in plain])
+    a = float(np.sum(rm * sp ** -0.5) / np.sum(1.0 / sp))   # least squares of rmse = a spp^-1/2
+    slope = float(np.polyfit(np.log(sp), np.log(np.maximum(rm, 1e-30)), 1)[0])
+    return plain, a, slope
 
 
 def _timed(fn):
@@ -344,8 +375,8 @@ def equal_rmse(cached, a, plain_rate, W, H, warm_frames):
 def bench_cached(args):
     """Equal-RMSE comparison of the plain full-depth path and the cache-terminated path on the
     church-1M view (the C2 frame, 40 bins, depth 8). Both are scored by RMSE against the
-    oracle's FP64 1024-spp reference on the pixel subset x % 16 == 0, y % 16 == 0
-    (tests/golden/c4_reference.npz). Plain: RMSE at spp = 1 .. 64 gives the least-squares fit
+    oracle's FP64 1024-spp reference on the pixel subset x % 4 == 0, y % 4 == 0
+    (tests/golden/c4_reference.npz, its own noise variance subtracted). Plain: RMSE at spp = 1 .. 256 gives the least-squares fit
     RMSE = a / sqrt(spp) and the frame rate. Cached: the cache starts untrained and is trained
     online once per frame (2^16 records, 4 Adam steps of 2^14, lr 1e-3) during warm_frames 1-spp
     frames and the scored frame; the time of every warm-up and scored frame counts.
@@ -365,14 +396,8 @@ def bench_cached(args):
     img = torch.empty((B, H, W), dtype=torch.float32, device="cuda")
     wave = args.wave_paths
     ctx.render(S, c, sd.render_params(spp=1, max_depth=8, seed=1, wave_paths=wave), out=img)  # warm-up
-    plain = []
-    for spp in (1, 2, 4, 8, 16, 32, 64):
-        dt = _timed(lambda: ctx.render(S, c, sd.render_params(spp=spp, max_depth=8, seed=1, wave_paths=wave), out=img))
-        plain.append(dict(spp=spp, seconds=dt, rmse=_rmse(img.cpu().numpy(), ref, px)))
-    sp = np.array([p["spp"] for p in plain], dtype=np.float64)
-    rm = np.array([p["rmse"] for p in plain])
-    a = float(np.sum(rm * sp ** -0.5) / np.sum(1.0 / sp))   # least squares of rmse = a spp^-1/2
-    plain_rate = W * H * 64 / plain[-1]["seconds"]
+    plain, a, slope = plain_curve(ctx, S, c, img, px, ref, wave, (1, 2, 4, 8, 16, 32, 64, 128, 256), W, H)
+    plain_rate = W * H * 64 / [q for q in plain if q["spp"] == 64][0]["seconds"]
     cached = run_cached(ctx, S, sc, cam, img, args, px, ref, wave)
     eq = equal_rmse(cached, a, plain_rate, W, H, args.warm_frames)
     out = {
@@ -384,10 +409,10 @@ def bench_cached(args):
         "config": {"workload": "church-1M cached vs plain at equal RMSE: 1920x1080, 40 bins, depth 8, cache at vertex 3, "
                                f"{args.warm_frames} 1-spp warm-up frames + one {args.cached_spp}-spp frame, "
                                "online training once per frame",
-                   "reference": "oracle FP64 1024 spp, pixels x%16==0 and y%16==0",
+                   "reference": reference_note(),
                    "train_paths_per_batch": args.train_paths, "train_every": args.train_every,
                    "records_per_batch": 4 << 14},
-        "equal_rmse": eq, "plain_curve": plain, "cached_frames": cached["frames"],
+        "equal_rmse": eq, "plain_curve": plain, "plain_loglog_slope": slope, "cached_frames": cached["frames"],
     }
     print(json.dumps(out), flush=True)
 
@@ -844,14 +869,20 @@ def main():
             out["photon_map"] = bench_photons(ctx, S, sc, cam, cfg, p.wave_paths)
             out["global_map"] = bench_global_map(ctx, S, sc, cam, cfg, p.wave_paths)
     if args.workload == "church" and not args.no_cached:
-        # the cached half of the metric on the same view: the plain frame just timed (64 spp,
-        # seed 1) fixes a = RMSE_64 sqrt(64) of the plain estimator's RMSE = a / sqrt(spp)
+        # the cached half of the metric on the same view: plain frames at 1 .. 256 spp fix a in the
+        # least-squares fit RMSE = a / sqrt(spp) of the plain estimator; the plain rate is the one
+        # just measured
         px, ref = load_reference()
         r64 = _rmse(img.cpu().numpy(), ref, px)
-        a = r64 * np.sqrt(cfg["spp"])
+        c = sd.camera(cam.eye, cam.target, cam.up, cam.vfov_deg, cam.width, cam.height)
+        curve, a, slope = plain_curve(ctx, S, c, img, px, ref, p.wave_paths, (1, 2, 4, 8, 16, 32, 64, 128, 256),
+                                      cam.width, cam.height)
         cached = run_cached(ctx, S, sc, cam, img, args, px, ref, p.wave_paths)
         out["equal_rmse"] = equal_rmse(cached, a, value, cam.width, cam.height, args.warm_frames)
         out["equal_rmse"]["rmse_plain_frame"] = r64
+        out["equal_rmse"]["plain_curve"] = [{"spp": q["spp"], "rmse": q["rmse"]} for q in curve]
+        out["equal_rmse"]["plain_loglog_slope"] = slope
+        out["equal_rmse"]["reference"] = reference_note()
     if not args.no_cpu_baseline:
         # the host cores this job may use: its CPU affinity (a one-GPU machine allots 16), unless given
         try:

@@ -62,15 +62,26 @@ __device__ __forceinline__ f32x16 zero16() {
   return z;
 }
 
+// Two floats -> a packed bf16 pair (round to nearest even), one v_cvt_pk_bf16_f32: converting
+// the two as a 2-vector keeps the compiler from converting them one by one and packing them
+// with a permute.
+typedef float f32x2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t cvt_pk(float a, float b) {
+  const f32x2v f = {a, b};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f, bf16x2v));
+}
+// Eight floats (x[o .. o + 7] of a D tile) -> one B operand.
+__device__ __forceinline__ bf16x8 pack8(const f32x16& x, int o) {
+  return as_bf8(make_uint4(cvt_pk(x[o], x[o + 1]), cvt_pk(x[o + 2], x[o + 3]), cvt_pk(x[o + 4], x[o + 5]),
+                           cvt_pk(x[o + 6], x[o + 7])));
+}
+
 // D tiles (two 32-unit output tiles) -> four B operands (bf16), optional ReLU.
 __device__ __forceinline__ void pack_b(const f32x16& a0, const f32x16& a1, bf16x8 b[4]) {
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    b[0][i] = (__bf16)a0[i];
-    b[1][i] = (__bf16)a0[8 + i];
-    b[2][i] = (__bf16)a1[i];
-    b[3][i] = (__bf16)a1[8 + i];
-  }
+  b[0] = pack8(a0, 0);
+  b[1] = pack8(a0, 8);
+  b[2] = pack8(a1, 0);
+  b[3] = pack8(a1, 8);
 }
 
 // One 64x64 layer: (a0, a1) = W . B over the four K blocks.
@@ -235,22 +246,19 @@ __device__ void build_u_table(const CacheDev& C, int B, float* u) {
 
 // h1 = relu(z + u_j) as B operands.
 __device__ __forceinline__ void hidden1(const f32x16& z0, const f32x16& z1, const float* uj, int h, bf16x8 b[4]) {
+  uint32_t w[4][4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const float4 u0 = *(const float4*)(uj + 8 * q + 4 * h);
     const float4 u1 = *(const float4*)(uj + 32 + 8 * q + 4 * h);
-    const int kb0 = q / 2, kb1 = 2 + q / 2, i0 = 4 * (q % 2);
-    b[kb0][i0 + 0] = (__bf16)(z0[4 * q + 0] + u0.x);
-    b[kb0][i0 + 1] = (__bf16)(z0[4 * q + 1] + u0.y);
-    b[kb0][i0 + 2] = (__bf16)(z0[4 * q + 2] + u0.z);
-    b[kb0][i0 + 3] = (__bf16)(z0[4 * q + 3] + u0.w);
-    b[kb1][i0 + 0] = (__bf16)(z1[4 * q + 0] + u1.x);
-    b[kb1][i0 + 1] = (__bf16)(z1[4 * q + 1] + u1.y);
-    b[kb1][i0 + 2] = (__bf16)(z1[4 * q + 2] + u1.z);
-    b[kb1][i0 + 3] = (__bf16)(z1[4 * q + 3] + u1.w);
+    const int kb0 = q / 2, kb1 = 2 + q / 2, i0 = 2 * (q % 2);
+    w[kb0][i0] = cvt_pk(z0[4 * q + 0] + u0.x, z0[4 * q + 1] + u0.y);
+    w[kb0][i0 + 1] = cvt_pk(z0[4 * q + 2] + u0.z, z0[4 * q + 3] + u0.w);
+    w[kb1][i0] = cvt_pk(z1[4 * q + 0] + u1.x, z1[4 * q + 1] + u1.y);
+    w[kb1][i0 + 1] = cvt_pk(z1[4 * q + 2] + u1.z, z1[4 * q + 3] + u1.w);
   }
 #pragma unroll
-  for (int kb = 0; kb < 4; ++kb) b[kb] = relu8(b[kb]);
+  for (int kb = 0; kb < 4; ++kb) b[kb] = relu8(as_bf8(make_uint4(w[kb][0], w[kb][1], w[kb][2], w[kb][3])));
 }
 
 // y = w4 . h4 over the lane's 32 units, then summed with the other half of the wave.
