@@ -436,7 +436,12 @@ int render_views(sdd_ctx* ctx, const sdd_scene* scene, std::vector<ViewDesc>& vi
   // never more paths in flight than the frame has items
   uint32_t W = (uint32_t)std::min<uint64_t>(p->wave_paths ? (uint64_t)p->wave_paths : (uint64_t)kDefaultWave, total);
   W = std::max<uint32_t>(W, 64);
-  if (p->persistent) W = persist_lanes(p, total, ctx->device);
+  if (p->persistent) {
+    // the work list is handed out in chunks of 64 items from 32-bit per-XCD counters
+    if (total / kPersistTileItems / kXcds >= (1ull << 31))
+      return fail(ctx, SDD_ERR_INVALID_ARG, "persistent render too large: at most 2^42 work items");
+    W = persist_lanes(p, total, ctx->device);
+  }
   Plan plan = make_plan(W, B, scene->hdr.n_cells, (int)views.size());
   if (!ws) return fail(ctx, SDD_ERR_INVALID_ARG, "workspace is null");
   if (ws_bytes < plan.total)
