@@ -1624,9 +1624,10 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2))) void k
         const float4* kt = (const float4*)(S.ktab + V.m * Bp);
         const float4* rt = (const float4*)(S.rho + V.m * Bp);
         const float4* E4 = (const float4*)S.sunE;
-        // four quads at a time: their tables, β and sun spectrum are read before their NEE quads
-        // are stored, and likewise for the throughput update
-        row_write<4>(e4, nq, nee, [&](int q) {
+        // eight quads at a time: their tables, β and sun spectrum are read before their NEE quads
+        // are stored, and likewise for the throughput update (each chunk is one memory round
+        // trip; at 80 bins 8 measured faster than 4 and 10)
+        row_write<8>(e4, nq, nee, [&](int q) {
           const float4 nn = nt[q], kk = kt[q], rr = rt[q];
           const float F[4] = {fresnel(nn.x, kk.x, V.cos_o), fresnel(nn.y, kk.y, V.cos_o),
                               fresnel(nn.z, kk.z, V.cos_o), fresnel(nn.w, kk.w, V.cos_o)};
@@ -1650,7 +1651,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2))) void k
         });
         choose();
         if (cont)
-          row_update<4>(b4, nq, [&](int q, float4 bb) {
+          row_update<8>(b4, nq, [&](int q, float4 bb) {
             const float4 nn = nt[q], kk = kt[q], rr = rt[q];
             const float F0 = fresnel(nn.x, kk.x, V.cos_o), F1 = fresnel(nn.y, kk.y, V.cos_o),
                         F2 = fresnel(nn.z, kk.z, V.cos_o), F3v = fresnel(nn.w, kk.w, V.cos_o);
