@@ -2,16 +2,20 @@
 //
 // Wavefront structure (one "phase" traces every ray produced by the previous step):
 //   producer (raygen / shade / pack)  -> (ray, start cell, rank in cell) entries
-//   k_scan     one workgroup: per-cell offsets, cell-sorted tile list
+//   k_scan     one workgroup: per-key offsets and the tile list, cells in index order or
+//              fullest first
 //   k_scatter  entries -> cell-sorted queue
-//   k_trace    a tile = up to 256 rays of ONE queue key (cell, direction class), handed out
-//              in parts of 64, one ray per lane of a wave; the grid's slab planes, the cell table and each lane's short traversal
-//              stack live in LDS, the 4-wide BVH nodes and triangles are read from memory (L2).
-//              A lane traverses its ray inside the cell's slab interval; rays that leave the
-//              cell are re-queued for the next cell (the interface conditions between the
-//              paper's sub-domains, section 5) or, in the final round, walk on in place.
-//   shade      per-bin SoA spectral shading: complex Fresnel (eq. 1), thin-slab Beer-Lambert
-//              glass, next-event estimation toward the directional sun (eq. 3).
+//   k_trace    a tile = up to 256 rays of ONE queue key (cell, direction class), handed out in
+//              parts of 64, one ray per lane of a wave; the grid's slab planes, the cell table
+//              and each lane's short traversal stack live in LDS, the 4-wide BVH nodes and
+//              triangles are read from memory (L2). A lane traverses its ray inside the cell's
+//              slab interval; rays that leave the cell are re-queued for the next cell (the
+//              interface conditions between the paper's sub-domains, section 5) or, in the
+//              final round, walk on in place.
+//   shade      per-bin spectral shading: complex Fresnel (eq. 1), thin-slab Beer-Lambert glass,
+//              next-event estimation toward the directional sun (eq. 3).
+// k_persist renders a whole batch in one persistent kernel instead (the same per-path
+// arithmetic, one path per lane at a time, no queues).
 #include "device_common.h"
 
 namespace sdd {
