@@ -538,6 +538,36 @@ def bench_photons(ctx, S, sc, cam, cfg, wave, n_photons=4_000_000, radius=0.1, s
                        "lit_fraction": st["photon_lit_vertices"] / max(1, st["photon_vertices"])}}
 
 
+def bench_batch_leg(ctx, S, sc, steps=2):
+    """The C3 batch on the church scene already uploaded (8x4x4 cells, the grid the autotuner
+    picks for it; --workload batch runs the tuner): 32 seeded views of uneven size and spp, one
+    graph launch per step of the wavefront sequence (2^24 paths, one round, fullest cells first),
+    then the same views as one graph-launched persistent kernel per step."""
+    import torch
+    import paper_1912_04000_amd as sd
+    import scenegen
+    views, spp = scenegen.batch_views(32)
+    cams = [sd.camera(v.eye, v.target, v.up, v.vfov_deg, v.width, v.height) for v in views]
+    outs = [torch.empty((sc.n_bins, c.height, c.width), dtype=torch.float32, device="cuda") for c in cams]
+    samples = sum(c.width * c.height * k for c, k in zip(cams, spp))
+    res = {}
+    for name, p in (("wavefront_graph", sd.render_params(max_depth=8, seed=1, wave_paths=1 << 24, queue_rounds=1,
+                                                          cell_order=1, use_graph=1)),
+                    ("persistent", sd.render_params(max_depth=8, seed=1, use_graph=1, persistent=1))):
+        ctx.render_batch(S, cams, spp, p, outs=outs)   # captures the graph
+        ctx.finish()
+        n = steps if name == "wavefront_graph" else 1
+        dt = _timed(lambda: [ctx.render_batch(S, cams, spp, p, outs=outs, finish=False) for _ in range(n)])
+        ctx.finish()
+        res[name] = {"samples_per_s": samples * n / dt, "ms_per_step": dt / n * 1e3, "steps": n}
+    res["views"] = len(cams)
+    res["samples_per_step"] = samples
+    res["persistent_relative"] = res["persistent"]["samples_per_s"] / res["wavefront_graph"]["samples_per_s"]
+    res["note"] = ("32 seeded views 256x256..1024x768, 4..64 spp, 40 bins, depth 8, church 8x4x4 cells; "
+                   "one graph launch per step")
+    return res
+
+
 def bench_global_map(ctx, S, sc, cam, cfg, wave, n_photons=2_000_000, radius=0.15, spp=8, gm_from=2):
     """Global photon map (section 4) of the benchmarked view: HIP-event time of building it, then
     of an spp-sample frame whose paths take the diffuse light of vertex gm_from on from it (final
@@ -584,6 +614,10 @@ def _progress(msg):
 
 
 def bench_large(args):
+    print(json.dumps(large_result(args)), flush=True)
+
+
+def large_result(args):
     """C5: procedural church of ~10M triangles (200 windows), 80 bins (5 nm), 3840x2160, 16x8x8
     cells, depth 8. Plain 256 spp against the cache-terminated path given the same wall time
     (untrained cache; 1-spp frames, accumulated, until the plain time is used up; every frame
@@ -684,7 +718,7 @@ def bench_large(args):
                             "cached_query": st_c["query_ms"], "cached_train_steps": st_c["train_ms"]},
         "cached_progress": chunks,
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def bench_batch(args):
@@ -868,6 +902,15 @@ def main():
             out["glass_maps"] = bench_glass_maps(ctx, sc, cam, cfg, p.wave_paths)
             out["photon_map"] = bench_photons(ctx, S, sc, cam, cfg, p.wave_paths)
             out["global_map"] = bench_global_map(ctx, S, sc, cam, cfg, p.wave_paths)
+            out["batch"] = bench_batch_leg(ctx, S, sc)
+            # the large configuration (C5) as one more leg: its own scene, context and workspace
+            try:
+                lg = large_result(args)
+                out["large"] = {"samples_per_s": lg["value"], "plain_s": lg["ms_per_step"] / 1e3,
+                                "config": lg["config"], "equal_time": lg["equal_time"],
+                                "timing_split_ms": lg["timing_split_ms"]}
+            except Exception as e:  # recorded, so that the church line above still prints
+                out["large"] = {"error": f"{type(e).__name__}: {e}"}
     if args.workload == "church" and not args.no_cached:
         # the cached half of the metric on the same view: plain frames at 1 .. 256 spp fix a in the
         # least-squares fit RMSE = a / sqrt(spp) of the plain estimator; the plain rate is the one
