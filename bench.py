@@ -737,13 +737,13 @@ def bench_batch(args):
     tune = ctx.autotune(sc, cams, sd.render_params(max_depth=8, seed=1),
                         waves=[1 << 22, 1 << 23, 1 << 24],
                         grids=[(4, 4, 4), (8, 8, 8), (16, 16, 16), (8, 4, 4)], rounds=(1, 2), orders=(0, 1),
-                        calib_spp=1, reps=2, cache_path=args.tune_cache)
+                        try_persistent=True, calib_spp=1, reps=2, cache_path=args.tune_cache)
     tune_s = time.perf_counter() - t0
     best = tune["best"]
     S = sd.Scene.from_description(sc, grid=tuple(best["grid"]))
     ctx.upload(S)
     p = sd.render_params(max_depth=8, seed=1, wave_paths=best["wave_paths"], queue_rounds=best["queue_rounds"],
-                         cell_order=best["cell_order"], use_graph=1, timing=1)
+                         cell_order=best["cell_order"], persistent=best["persistent"], use_graph=1, timing=1)
     outs = [torch.empty((sc.n_bins, c.height, c.width), dtype=torch.float32, device="cuda") for c in cams]
     for _ in range(max(1, args.warmup)):   # the first call captures the graph
         ctx.render_batch(S, cams, spp, p, outs=outs)

@@ -284,13 +284,16 @@ typedef struct {
   int32_t reps;                /* timed repetitions per candidate (the fastest is kept)     */
   int32_t n_orders;            /* cell_order values to try, 0..2 (0: the base parameters')  */
   int32_t cell_orders[2];
+  int32_t try_persistent;      /* 1: also time the one persistent kernel on every grid       */
 } sdd_tune_space;
 
 typedef struct {
   int32_t grid[3];
-  int32_t wave_paths;
+  int32_t wave_paths;          /* paths in flight; lanes of the kernel when persistent        */
   int32_t queue_rounds;
   int32_t cell_order;
+  int32_t persistent;          /* 1: the candidate is the persistent kernel                  */
+  int32_t pad;
   double samples_per_s;
 } sdd_tune_point;
 
@@ -301,7 +304,8 @@ typedef struct {
   sdd_tune_point tried[128];
 } sdd_tune_result;
 
-/* Autotuner: picks the cell grid, wavefront size, queue rounds and cell order with the highest throughput
+/* Autotuner: picks the cell grid, wavefront size, queue rounds and cell order (or the persistent
+ * kernel, when asked to try it) with the highest throughput
  * on short calibration renders of the given views (calib_spp samples each), timed with HIP
  * events. The scene is rebuilt on the host for every grid and uploaded to scene_buf; grids whose
  * scene does not fit scene_bytes, and wavefront sizes whose workspace does not fit ws_bytes, are

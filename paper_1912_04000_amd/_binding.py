@@ -113,16 +113,17 @@ class TuneSpace(C.Structure):
     _fields_ = [("n_waves", C.c_int32), ("wave_paths", C.c_int32 * 8), ("n_grids", C.c_int32),
                 ("grids", (C.c_int32 * 3) * 8), ("n_rounds", C.c_int32), ("queue_rounds", C.c_int32 * 4),
                 ("calib_spp", C.c_int32), ("reps", C.c_int32), ("n_orders", C.c_int32),
-                ("cell_orders", C.c_int32 * 2)]
+                ("cell_orders", C.c_int32 * 2), ("try_persistent", C.c_int32)]
 
 
 class TunePoint(C.Structure):
     _fields_ = [("grid", C.c_int32 * 3), ("wave_paths", C.c_int32), ("queue_rounds", C.c_int32),
-                ("cell_order", C.c_int32), ("samples_per_s", C.c_double)]
+                ("cell_order", C.c_int32), ("persistent", C.c_int32), ("pad", C.c_int32),
+                ("samples_per_s", C.c_double)]
 
     def as_dict(self):
         return dict(grid=list(self.grid), wave_paths=self.wave_paths, queue_rounds=self.queue_rounds,
-                    cell_order=self.cell_order, samples_per_s=self.samples_per_s)
+                    cell_order=self.cell_order, persistent=self.persistent, samples_per_s=self.samples_per_s)
 
 
 class TuneResult(C.Structure):
@@ -483,10 +484,11 @@ class Context:
         return outs
 
     def autotune(self, scene_description, cams, base: RenderParams, waves, grids, rounds=(1, 2), calib_spp=1,
-                 reps=2, cache_path=None, scene_bytes=None, ws_bytes=None, orders=()):
-        """Measure (grid, wavefront size, queue rounds, cell order) candidates on calibration
-        renders of the views and return the fastest (the library's autotuner; cached in
-        cache_path). An empty `orders` keeps the base parameters' cell order."""
+                 reps=2, cache_path=None, scene_bytes=None, ws_bytes=None, orders=(), try_persistent=False):
+        """Measure (grid, wavefront size, queue rounds, cell order) candidates, and with
+        try_persistent the persistent kernel on every grid, on calibration renders of the views
+        and return the fastest (the library's autotuner; cached in cache_path). An empty `orders`
+        keeps the base parameters' cell order."""
         torch = self.torch
         d, keep = desc_from(scene_description)
         sp = TuneSpace()
@@ -503,6 +505,7 @@ class Context:
         sp.n_orders = len(orders)
         for i, o in enumerate(orders):
             sp.cell_orders[i] = int(o)
+        sp.try_persistent = int(bool(try_persistent))
         if scene_bytes is None:
             # finest grid bounds the scene size (more duplicated references): measure it once
             finest = max(grids, key=lambda g: g[0] * g[1] * g[2])
@@ -516,6 +519,10 @@ class Context:
             probe = probe if "probe" in locals() else Scene.from_description(scene_description)
             _check(lib().sdd_workspace_bytes(probe.handle, C.byref(p), C.byref(b)))
             ws_bytes = b.value
+            if try_persistent:
+                p.wave_paths, p.persistent = 0, 1
+                _check(lib().sdd_workspace_bytes(probe.handle, C.byref(p), C.byref(b)))
+                ws_bytes = max(ws_bytes, b.value)
         sbuf = torch.empty(scene_bytes + 256, dtype=torch.uint8, device=self.device)
         soff = (-sbuf.data_ptr()) % 256
         ws = self.workspace(ws_bytes)

@@ -52,7 +52,9 @@ bool read_cache(const char* path, uint64_t key, sdd_tune_point* out) {
     const char* r = std::strstr(line, "\"queue_rounds\": ");
     const char* s = std::strstr(line, "\"samples_per_s\": ");
     const char* o = std::strstr(line, "\"cell_order\": ");
-    if (g && w && r && s && o && std::sscanf(o, "\"cell_order\": %d", &out->cell_order) == 1 &&
+    const char* pe = std::strstr(line, "\"persistent\": ");
+    if (g && w && r && s && o && pe && std::sscanf(o, "\"cell_order\": %d", &out->cell_order) == 1 &&
+        std::sscanf(pe, "\"persistent\": %d", &out->persistent) == 1 &&
         std::sscanf(g, "\"grid\": [%d, %d, %d]", &out->grid[0], &out->grid[1], &out->grid[2]) == 3 &&
         std::sscanf(w, "\"wave_paths\": %d", &out->wave_paths) == 1 &&
         std::sscanf(r, "\"queue_rounds\": %d", &out->queue_rounds) == 1 &&
@@ -69,9 +71,10 @@ void write_cache(const char* path, uint64_t key, const sdd_tune_point& b, const 
   if (!f) return;
   std::fprintf(f,
                "{\"key\": \"%016llx\", \"device\": \"%s\", \"grid\": [%d, %d, %d], \"wave_paths\": %d, "
-               "\"queue_rounds\": %d, \"cell_order\": %d, \"samples_per_s\": %.6e, \"candidates\": %d}\n",
+               "\"queue_rounds\": %d, \"cell_order\": %d, \"persistent\": %d, \"samples_per_s\": %.6e, "
+               "\"candidates\": %d}\n",
                (unsigned long long)key, device.c_str(), b.grid[0], b.grid[1], b.grid[2], b.wave_paths, b.queue_rounds,
-               b.cell_order, b.samples_per_s, n_tried);
+               b.cell_order, b.persistent, b.samples_per_s, n_tried);
   std::fclose(f);
 }
 
@@ -86,7 +89,8 @@ extern "C" int sdd_autotune(sdd_ctx* ctx, const sdd_scene_desc* desc, const sdd_
     return SDD_ERR_INVALID_ARG;
   }
   if (sp->n_waves < 1 || sp->n_waves > 8 || sp->n_grids < 1 || sp->n_grids > 8 || sp->n_rounds < 1 ||
-      sp->n_rounds > 4 || sp->calib_spp < 1 || sp->reps < 1 || sp->n_orders < 0 || sp->n_orders > 2) {
+      sp->n_rounds > 4 || sp->calib_spp < 1 || sp->reps < 1 || sp->n_orders < 0 || sp->n_orders > 2 ||
+      sp->try_persistent < 0 || sp->try_persistent > 1) {
     sdd::set_thread_error("sdd_autotune: search space out of range");
     return SDD_ERR_INVALID_ARG;
   }
@@ -123,43 +127,51 @@ extern "C" int sdd_autotune(sdd_ctx* ctx, const sdd_scene_desc* desc, const sdd_
     }
     rc = sdd_scene_upload(ctx, scene, scene_buf, scene_bytes);
     const int n_orders = sp->n_orders ? sp->n_orders : 1;
-    for (int wi = 0; wi < sp->n_waves && rc == SDD_OK; ++wi)
-      for (int ri = 0; ri < sp->n_rounds * n_orders && rc == SDD_OK; ++ri) {
-        sdd_render_params p = *base;
+    const int n_wave_cands = sp->n_waves * sp->n_rounds * n_orders;
+    for (int ci = 0; ci < n_wave_cands + sp->try_persistent && rc == SDD_OK; ++ci) {
+      sdd_render_params p = *base;
+      p.persistent = 0;
+      if (ci < n_wave_cands) {  // wavefront size x rounds x cell order
+        const int wi = ci / (sp->n_rounds * n_orders), ri = ci % (sp->n_rounds * n_orders);
         p.wave_paths = sp->wave_paths[wi];
         p.queue_rounds = sp->queue_rounds[ri % sp->n_rounds];
         if (sp->n_orders) p.cell_order = sp->cell_orders[ri / sp->n_rounds];
-        p.use_graph = 0;
-        p.timing = 0;
-        p.spp = sp->calib_spp;
-        size_t wsn = 0;
-        if (sdd_workspace_bytes(scene, &p, &wsn) != SDD_OK || wsn > ws_bytes) continue;
-        rc = sdd_render_batch(ctx, scene, views, spp.data(), n_views, &p, workspace, ws_bytes, images);  // warm-up
-        if (rc) break;
-        float best_ms = 1e30f;
-        for (int r = 0; r < sp->reps && rc == SDD_OK; ++r) {
-          (void)hipEventRecord(e0, stream);
-          rc = sdd_render_batch(ctx, scene, views, spp.data(), n_views, &p, workspace, ws_bytes, images);
-          (void)hipEventRecord(e1, stream);
-          if (rc) break;
-          rc = sdd_finish(ctx);
-          float ms = 0;
-          if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms < best_ms) best_ms = ms;
-        }
-        if (rc) break;
-        sdd_tune_point pt;
-        std::memset(&pt, 0, sizeof(pt));
-        for (int a = 0; a < 3; ++a) pt.grid[a] = d.grid[a];
-        pt.wave_paths = p.wave_paths;
-        pt.queue_rounds = p.queue_rounds;
-        pt.cell_order = p.cell_order;
-        pt.samples_per_s = samples / (best_ms * 1e-3);
-        if (out->n_tried < 128) out->tried[out->n_tried++] = pt;
-        if (pt.samples_per_s > best) {
-          best = pt.samples_per_s;
-          out->best = pt;
-        }
+      } else {  // the persistent kernel with its default lanes
+        p.persistent = 1;
+        p.wave_paths = 0;
       }
+      p.use_graph = 0;
+      p.timing = 0;
+      p.spp = sp->calib_spp;
+      size_t wsn = 0;
+      if (sdd_workspace_bytes(scene, &p, &wsn) != SDD_OK || wsn > ws_bytes) continue;
+      rc = sdd_render_batch(ctx, scene, views, spp.data(), n_views, &p, workspace, ws_bytes, images);  // warm-up
+      if (rc) break;
+      float best_ms = 1e30f;
+      for (int r = 0; r < sp->reps && rc == SDD_OK; ++r) {
+        (void)hipEventRecord(e0, stream);
+        rc = sdd_render_batch(ctx, scene, views, spp.data(), n_views, &p, workspace, ws_bytes, images);
+        (void)hipEventRecord(e1, stream);
+        if (rc) break;
+        rc = sdd_finish(ctx);
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms < best_ms) best_ms = ms;
+      }
+      if (rc) break;
+      sdd_tune_point pt;
+      std::memset(&pt, 0, sizeof(pt));
+      for (int a = 0; a < 3; ++a) pt.grid[a] = d.grid[a];
+      pt.wave_paths = p.wave_paths;
+      pt.queue_rounds = p.queue_rounds;
+      pt.cell_order = p.cell_order;
+      pt.persistent = p.persistent;
+      pt.samples_per_s = samples / (best_ms * 1e-3);
+      if (out->n_tried < 128) out->tried[out->n_tried++] = pt;
+      if (pt.samples_per_s > best) {
+        best = pt.samples_per_s;
+        out->best = pt;
+      }
+    }
     sdd_scene_destroy(scene);
   }
   (void)hipEventDestroy(e0);

@@ -465,13 +465,16 @@ def test_autotune_picks_a_measured_candidate_and_caches(ctx, tmp_path):
     cache = str(tmp_path / "tune_cache.json")
     base = sd.render_params(max_depth=4, seed=1)
     r1 = ctx.autotune(sc, cams, base, waves=[1024, 4096], grids=[(1, 1, 1), (2, 2, 2), (4, 2, 2)], rounds=(1, 2),
-                      orders=(0, 1), calib_spp=1, reps=1, cache_path=cache)
+                      orders=(0, 1), try_persistent=True, calib_spp=1, reps=1, cache_path=cache)
     say(f"autotune: {r1['best']} from {len(r1['tried'])} candidates")
-    assert not r1["from_cache"] and len(r1["tried"]) == 24
-    assert sorted({(t["queue_rounds"], t["cell_order"]) for t in r1["tried"]}) == [(1, 0), (1, 1), (2, 0), (2, 1)]
+    assert not r1["from_cache"] and len(r1["tried"]) == 27
+    wave = [t for t in r1["tried"] if not t["persistent"]]
+    assert sorted({(t["queue_rounds"], t["cell_order"]) for t in wave}) == [(1, 0), (1, 1), (2, 0), (2, 1)]
+    assert sorted(tuple(t["grid"]) for t in r1["tried"] if t["persistent"]) == [(1, 1, 1), (2, 2, 2), (4, 2, 2)]
     assert r1["best"]["samples_per_s"] == max(t["samples_per_s"] for t in r1["tried"])
     r2 = ctx.autotune(sc, cams, base, waves=[1024, 4096], grids=[(1, 1, 1), (2, 2, 2), (4, 2, 2)], rounds=(1, 2),
-                      orders=(0, 1), calib_spp=1, reps=1, cache_path=cache)
+                      orders=(0, 1), try_persistent=True, calib_spp=1, reps=1, cache_path=cache)
     assert r2["from_cache"] and r2["best"]["grid"] == r1["best"]["grid"]
     assert r2["best"]["wave_paths"] == r1["best"]["wave_paths"]
     assert r2["best"]["cell_order"] == r1["best"]["cell_order"]
+    assert r2["best"]["persistent"] == r1["best"]["persistent"]
