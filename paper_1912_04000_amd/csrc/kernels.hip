@@ -867,19 +867,25 @@ __device__ __forceinline__ void box4(const RayPre& R, float4 q0, float4 q1, floa
   const float by = __uint_as_float(((e >> 8) & 0xFFu) << 23) * R.inv.y;
   const float bz = __uint_as_float(((e >> 16) & 0xFFu) << 23) * R.inv.z;
   const float ax = (q0.x - R.o.x) * R.inv.x, ay = (q0.y - R.o.y) * R.inv.y, az = (q0.z - R.o.z) * R.inv.z;
+  // the near and far bound of each axis, chosen once per node by the sign of the ray's direction
+  // (a + q b is monotone in q, increasing for b > 0, so the near plane is the low one then and the
+  // high one otherwise; b has the sign of the finite reciprocal, never zero)
   const uint32_t LX = __float_as_uint(q2.x), HX = __float_as_uint(q2.y), LY = __float_as_uint(q2.z),
                  HY = __float_as_uint(q2.w), LZ = __float_as_uint(q3.x), HZ = __float_as_uint(q3.y);
+  const uint32_t NX = R.inv.x >= 0.0f ? LX : HX, FX = R.inv.x >= 0.0f ? HX : LX;
+  const uint32_t NY = R.inv.y >= 0.0f ? LY : HY, FY = R.inv.y >= 0.0f ? HY : LY;
+  const uint32_t NZ = R.inv.z >= 0.0f ? LZ : HZ, FZ = R.inv.z >= 0.0f ? HZ : LZ;
   const uint32_t W[4] = {__float_as_uint(q1.x), __float_as_uint(q1.y), __float_as_uint(q1.z), __float_as_uint(q1.w)};
 #pragma unroll
   for (int c = 0; c < kWide; ++c) {
-    const float x0 = __builtin_fmaf((float)((LX >> (8 * c)) & 0xFFu), bx, ax);
-    const float x1 = __builtin_fmaf((float)((HX >> (8 * c)) & 0xFFu), bx, ax);
-    const float y0 = __builtin_fmaf((float)((LY >> (8 * c)) & 0xFFu), by, ay);
-    const float y1 = __builtin_fmaf((float)((HY >> (8 * c)) & 0xFFu), by, ay);
-    const float z0 = __builtin_fmaf((float)((LZ >> (8 * c)) & 0xFFu), bz, az);
-    const float z1 = __builtin_fmaf((float)((HZ >> (8 * c)) & 0xFFu), bz, az);
-    const float n = fmaxf(fmaxf(fminf(x0, x1), fminf(y0, y1)), fmaxf(fminf(z0, z1), tmin));
-    const float f = fminf(fminf(fmaxf(x0, x1), fmaxf(y0, y1)), fmaxf(z0, z1)) * kSlop;
+    const float xn = __builtin_fmaf((float)((NX >> (8 * c)) & 0xFFu), bx, ax);
+    const float xf = __builtin_fmaf((float)((FX >> (8 * c)) & 0xFFu), bx, ax);
+    const float yn = __builtin_fmaf((float)((NY >> (8 * c)) & 0xFFu), by, ay);
+    const float yf = __builtin_fmaf((float)((FY >> (8 * c)) & 0xFFu), by, ay);
+    const float zn = __builtin_fmaf((float)((NZ >> (8 * c)) & 0xFFu), bz, az);
+    const float zf = __builtin_fmaf((float)((FZ >> (8 * c)) & 0xFFu), bz, az);
+    const float n = fmaxf(fmaxf(xn, yn), fmaxf(zn, tmin));
+    const float f = fminf(fminf(xf, yf), zf) * kSlop;
     const bool hit = n <= fminf(f, tmax) && W[c] != kEmptyChild;
     t[c] = hit ? n : INFINITY;
     w[c] = hit ? W[c] : kEmptyChild;
