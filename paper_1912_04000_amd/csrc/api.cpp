@@ -76,7 +76,7 @@ size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
 
 enum {
   L_PIX, L_SMP, L_VIEW, L_BETA, L_NEE, L_LACC, L_HIT, L_RAYS, L_SHCNT, L_SHX, L_CAT, L_CATB, L_LSRC, L_LDST, L_LRANK,
-  L_QUEUE, L_CCOUNT, L_COFF, L_TILES, L_SPILL, L_CTL, L_VIEWS, L_COUNT
+  L_QUEUE, L_CCOUNT, L_COFF, L_KSUM, L_KOFF, L_TILES, L_SPILL, L_CTL, L_VIEWS, L_COUNT
 };
 
 struct Plan {
@@ -119,8 +119,10 @@ Plan make_plan(uint32_t W, int B, int n_cells, int n_views) {
   sz[L_LDST] = 8ull * W;
   sz[L_LRANK] = 8ull * W;
   sz[L_QUEUE] = 8ull * W;
-  sz[L_CCOUNT] = 8ull * n_cells * kDirBins * kKeyStride;
-  sz[L_COFF] = 4ull * n_cells * kDirBins;
+  sz[L_CCOUNT] = 8ull * n_cells * kDirBins * kKeyWords;
+  sz[L_COFF] = 4ull * n_cells * kDirBins * kSubKeys;
+  sz[L_KSUM] = 4ull * n_cells * kDirBins;
+  sz[L_KOFF] = 4ull * n_cells * kDirBins;
   sz[L_TILES] = 16ull * p.max_tiles;
   sz[L_SPILL] = 4ull * (kMaxStack - kShortStack) * (size_t)tb * kWG;
   sz[L_CTL] = sizeof(Ctl);
@@ -156,6 +158,8 @@ DevWS ws_view(const Plan& p, void* base) {
   w.queue = (uint32_t*)(b + p.off[L_QUEUE]);
   w.ccount = (uint32_t*)(b + p.off[L_CCOUNT]);
   w.coff = (uint32_t*)(b + p.off[L_COFF]);
+  w.ksum = (uint32_t*)(b + p.off[L_KSUM]);
+  w.koff = (uint32_t*)(b + p.off[L_KOFF]);
   w.tiles = (uint4*)(b + p.off[L_TILES]);
   w.spill = (uint32_t*)(b + p.off[L_SPILL]);
   w.ctl = (Ctl*)(b + p.off[L_CTL]);
@@ -381,7 +385,7 @@ int enqueue_frame(sdd_ctx* ctx, const sdd_scene* scene, const std::vector<ViewDe
     ctx->acc.wavefronts++;
     return SDD_OK;
   }
-  HIP_TRY(ctx, launch_fill_u32(ctx->stream, w.ccount, 2ull * scene->hdr.n_cells * kDirBins * kKeyStride, 0u));
+  HIP_TRY(ctx, launch_fill_u32(ctx->stream, w.ccount, 2ull * scene->hdr.n_cells * kDirBins * kKeyWords, 0u));
   int gen = 0;
   const PathMode render_mode{0u, 0, nullptr, nullptr, gm ? gm_from : 0};
   uint64_t wavefront = 0;
@@ -963,7 +967,7 @@ static int query(sdd_ctx* c, const sdd_scene* s, const float* orig, const float*
   DevScene S = device_view(s);
   Launch L{c->stream, plan.trace_blocks};
   HIP_TRY(c, launch_fill_u32(c->stream, (uint32_t*)w.ctl, sizeof(Ctl) / 4, 0u));
-  HIP_TRY(c, launch_fill_u32(c->stream, w.ccount, 2ull * s->hdr.n_cells * kDirBins * kKeyStride, 0u));
+  HIP_TRY(c, launch_fill_u32(c->stream, w.ccount, 2ull * s->hdr.n_cells * kDirBins * kKeyWords, 0u));
   c->last_ctl = w.ctl;
   int gen = 0;
   for (int64_t a = 0; a < n; a += W) {
@@ -1115,7 +1119,7 @@ int sdd_photon_map_build(sdd_ctx* c, const sdd_scene* s, sdd_photon_map* m, void
       HIP_TRY(c, launch_fill_u32(c->stream, (uint32_t*)&w.ctl->st_paths, (sizeof(Ctl) - offsetof(Ctl, st_paths)) / 4, 0u));
     c->last_ctl = w.ctl;
     HIP_TRY(c, launch_fill_u32(c->stream, (uint32_t*)w.ctl, offsetof(Ctl, st_paths) / 4, 0u));
-    HIP_TRY(c, launch_fill_u32(c->stream, w.ccount, 2ull * H.n_cells * kDirBins * kKeyStride, 0u));
+    HIP_TRY(c, launch_fill_u32(c->stream, w.ccount, 2ull * H.n_cells * kDirBins * kKeyWords, 0u));
     DevScene S = device_view(s);
     // the build's traversal launches are short (photons end after a few vertices): a grid of
     // one workgroup per 1024 photons in flight (half a render wavefront's) gives each wave more

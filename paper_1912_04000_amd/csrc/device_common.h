@@ -60,8 +60,14 @@ __device__ __forceinline__ uint32_t dir_bin(F3 d) {
   return oct * 3u + dom;
 }
 __device__ __forceinline__ uint32_t qkey(uint32_t cell, uint32_t dbin) { return cell * (uint32_t)kDirBins + dbin; }
+// sub-range of a ray: its queue key and the block of its cell that holds its origin
+__device__ __forceinline__ uint32_t qsub(uint32_t key, uint32_t blk) { return key * (uint32_t)kSubKeys + blk; }
+// word of sub-range ks's counter in a counter array
+__device__ __forceinline__ size_t ctr_word(uint32_t ks) {
+  return (size_t)(ks / kSubKeys) * kKeyWords + ks % kSubKeys;
+}
 __device__ __forceinline__ uint32_t* ccount_of(const DevScene& S, const DevWS& w, int parity) {
-  return w.ccount + (size_t)parity * S.n_cells * kDirBins * kKeyStride;
+  return w.ccount + (size_t)parity * S.n_cells * kDirBins * kKeyWords;
 }
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }

@@ -27,6 +27,16 @@ constexpr int kDirBins = 24;        // ray queues per cell: direction octant x d
 // one at a time per line, and the keys that camera or shadow rays share would otherwise crowd
 // a few lines.
 constexpr int kKeyStride = 16;
+// Each queue key counts its rays in kSubKeys sub-ranges, one per block of a 2^L x 2^L x 2^L
+// split of the cell that holds the ray's origin (L = kSubLevels, blocks in Morton order), laid
+// out one after the other in the key's queue range: the rays of a tile, and of its 64-ray parts,
+// then start close together and descend the cell's BVH along similar paths. Tiles still span the
+// whole key. A key's sub-range counters are consecutive words of its own counter lines
+// (kKeyWords words per key), so the atomics on a line come from the producers of one key.
+constexpr int kSubLevels = 2;
+constexpr int kSubKeys = 1 << (3 * kSubLevels);
+constexpr int kKeyWords = kSubKeys > kKeyStride ? kSubKeys : kKeyStride;
+static_assert(64 % kSubKeys == 0, "a wave scans whole keys' sub-ranges");
 constexpr uint32_t kBlocked = 0xFFFFFFFFu;
 constexpr uint32_t kFirstVisit = 0x80000000u;
 constexpr uint32_t kShadowBit = 0x80000000u;  // in the ray's slot word
@@ -173,8 +183,10 @@ struct DevWS {
   uint32_t* ldst;    // [2W] destination cell
   uint32_t* lrank;   // [2W] rank inside the destination cell
   uint32_t* queue;   // [2W] cell-sorted entries of the current round
-  uint32_t* ccount;  // [2][n_cells]
-  uint32_t* coff;    // [n_cells]
+  uint32_t* ccount;  // [2][n_cells * kDirBins * kKeyWords]: sub-range counters, kKeyWords per key
+  uint32_t* coff;    // [n_cells * kDirBins * kSubKeys]: offset of each sub-range inside its key's range
+  uint32_t* ksum;    // [n_cells * kDirBins] rays per key
+  uint32_t* koff;    // [n_cells * kDirBins] queue offset of each key's range
   uint4* tiles;      // [max_tiles] (cell, start, count, 0)
   uint32_t* spill;   // [kMaxStack - kShortStack][trace_threads]
   Ctl* ctl;

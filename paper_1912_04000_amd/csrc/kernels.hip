@@ -51,7 +51,7 @@ __device__ void wave_append(bool valid, uint32_t src, uint32_t cell, uint32_t* l
     pending &= ~same;
   }
   uint32_t cb = 0;
-  if (is_leader) cb = atomicAdd(&cell_count[(size_t)cell * kKeyStride], gcount);
+  if (is_leader) cb = atomicAdd(&cell_count[ctr_word(cell)], gcount);
   cb = __shfl(cb, (int)my_leader);
   base = __shfl(base, (int)leader);
   if (valid) {
@@ -86,7 +86,7 @@ __device__ uint32_t wave_key_rank(bool valid, uint32_t key, uint32_t* cell_count
     pending &= ~same;
   }
   uint32_t cb = 0;
-  if (is_leader) cb = atomicAdd(&cell_count[(size_t)key * kKeyStride], gcount);
+  if (is_leader) cb = atomicAdd(&cell_count[ctr_word(key)], gcount);
   cb = __shfl(cb, (int)my_leader);
   return cb + my_off;
 }
@@ -148,8 +148,11 @@ __device__ __forceinline__ int locate_axis(const float* pl, int g, float lo, flo
 
 // Start cell of a ray: the cell holding its origin, or the cell where it enters the grid box.
 // Returns kInvalidCell if the ray misses the grid box entirely. `pl` is the plane table
-// (gx+1 | gy+1 | gz+1 entries, in global memory or a copy in LDS).
-__device__ uint32_t start_cell_pl(const DevScene& S, const float* pl, F3 o, F3 d) {
+// (gx+1 | gy+1 | gz+1 entries, in global memory or a copy in LDS). With `blk` given, it receives
+// the block of the cell's 2^L x 2^L x 2^L split (L = kSubLevels) that holds the origin or entry
+// point, as a Morton index (bit 3l + a: axis a at level l from the finest), which orders the rays
+// inside their queue key.
+__device__ uint32_t start_cell_pl(const DevScene& S, const float* pl, F3 o, F3 d, uint32_t* blk = nullptr) {
   const float* px = pl;
   const float* py = pl + S.gx + 1;
   const float* pz = pl + S.gx + 1 + S.gy + 1;
@@ -180,6 +183,20 @@ __device__ uint32_t start_cell_pl(const DevScene& S, const float* pl, F3 o, F3 d
   const int ix = locate_axis(px, S.gx, lo[0], S.inv_cs[0], p.x);
   const int iy = locate_axis(py, S.gy, lo[1], S.inv_cs[1], p.y);
   const int iz = locate_axis(pz, S.gz, lo[2], S.inv_cs[2], p.z);
+  if (blk) {
+    constexpr float kSplit = (float)(1 << kSubLevels);
+    const float lo3[3] = {px[ix], py[iy], pz[iz]}, hi3[3] = {px[ix + 1], py[iy + 1], pz[iz + 1]};
+    const float pp[3] = {p.x, p.y, p.z};
+    uint32_t m = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const float f = (pp[a] - lo3[a]) * kSplit / (hi3[a] - lo3[a]);
+      const uint32_t q = (uint32_t)min(max((int)f, 0), (1 << kSubLevels) - 1);
+#pragma unroll
+      for (int l = 0; l < kSubLevels; ++l) m |= ((q >> l) & 1u) << (3 * l + a);
+    }
+    *blk = m;
+  }
   return (uint32_t)((iz * S.gy + iy) * S.gx + ix);
 }
 
@@ -361,7 +378,7 @@ __global__ __launch_bounds__(kWG) void k_raygen(DevScene S, DevWS w, uint64_t k0
   __syncthreads();
   const uint32_t i = blockIdx.x * kWG + threadIdx.x;
   const bool valid = i < n;
-  uint32_t cell = kInvalidCell, qdir = 0;
+  uint32_t cell = kInvalidCell, qdir = 0, xo = 0;
   if (valid) {
     const uint64_t k = k0 + i;
     int v = 0;
@@ -402,7 +419,7 @@ __global__ __launch_bounds__(kWG) void k_raygen(DevScene S, DevWS w, uint64_t k0
     w.pix[i] = pix;
     w.smp[i] = s;
     w.view[i] = (uint32_t)v;
-    cell = start_cell_pl(S, s_planes, o, d);
+    cell = start_cell_pl(S, s_planes, o, d, &xo);
     qdir = dir_bin(d);
   }
   // Throughput rows at one and radiance rows at zero: the workgroup's paths own one contiguous
@@ -423,7 +440,7 @@ __global__ __launch_bounds__(kWG) void k_raygen(DevScene S, DevWS w, uint64_t k0
   // misses the grid leaves an entry marked kNoKey, which the scatter passes over.
   const int p = gen & 1;
   const bool in_grid = valid && cell != kInvalidCell;
-  const uint32_t key = in_grid ? qkey(cell, qdir) : kNoKey;
+  const uint32_t key = in_grid ? qsub(qkey(cell, qdir), xo) : kNoKey;
   const uint32_t rank = wave_key_rank(in_grid, key, ccount_of(S, w, p));
   if (valid) {
     w.lsrc[i] = i | kFirstVisit;
@@ -446,7 +463,7 @@ __global__ __launch_bounds__(kWG) void k_pack_rays(DevScene S, DevWS w, const fl
                                                    const int32_t* skip, uint32_t n, int shadow, int gen) {
   const uint32_t i = blockIdx.x * kWG + threadIdx.x;
   const bool valid = i < n;
-  uint32_t cell = kInvalidCell, qdir = 0;
+  uint32_t cell = kInvalidCell, qdir = 0, xo = 0;
   uint32_t r = 0;
   if (valid) {
     const F3 o = f3(orig[3 * i], orig[3 * i + 1], orig[3 * i + 2]);
@@ -457,7 +474,7 @@ __global__ __launch_bounds__(kWG) void k_pack_rays(DevScene S, DevWS w, const fl
     w.rays[2 * r + 1] = make_float4(d.x, d.y, d.z, __uint_as_float(shadow ? (i | kShadowBit) : i));
     const bool finite = isfinite(o.x) && isfinite(o.y) && isfinite(o.z) && isfinite(d.x) && isfinite(d.y) &&
                         isfinite(d.z) && (d.x != 0.0f || d.y != 0.0f || d.z != 0.0f);
-    if (finite) cell = start_cell(S, o, d);
+    if (finite) cell = start_cell_pl(S, S.planes, o, d, &xo);
     qdir = dir_bin(d);
     if (shadow)
       w.shcnt[i] = 0;
@@ -466,7 +483,7 @@ __global__ __launch_bounds__(kWG) void k_pack_rays(DevScene S, DevWS w, const fl
   }
   const int p = gen & 1;
   __shared__ uint32_t s_app[kWG / 64];
-  block_append2(s_app, valid && cell != kInvalidCell, r | kFirstVisit, qkey(cell, qdir), false, 0u, 0u,
+  block_append2(s_app, valid && cell != kInvalidCell, r | kFirstVisit, qsub(qkey(cell, qdir), xo), false, 0u, 0u,
                 &w.ctl->list_count[p], ccount_of(S, w, p), w.lsrc, w.ldst, w.lrank);
 }
 
@@ -642,8 +659,32 @@ __device__ void cell_order_fullest(int n_cells, const uint8_t* s_oct, uint16_t* 
   }
 }
 
-// One workgroup turns the queue-key counts of the produced entries into the key offsets of the
-// cell-sorted queue (coff) and the tile list: a tile is up to kTile entries of one key, the tiles
+// Sub-ranges of the queue keys, one thread each (runs before k_scan): a key's sub-range counts
+// are summed over its kSubKeys lanes (shuffles inside the wave), giving each sub-range's offset
+// inside its key's range (coff) and the key's count (ksum). It also clears the other parity's
+// counters, which the next generation's producers count into.
+__global__ __launch_bounds__(kWG) void k_subscan(DevScene S, DevWS w, int gen) {
+  const int p = gen & 1;
+  const uint32_t n = (uint32_t)S.n_cells * kDirBins * kSubKeys;
+  const uint32_t t = blockIdx.x * kWG + threadIdx.x;
+  const uint32_t j = lane_id() % kSubKeys;
+  const uint32_t x = t < n ? ccount_of(S, w, p)[ctr_word(t)] : 0u;
+  uint32_t incl = x;
+#pragma unroll
+  for (int off = 1; off < kSubKeys; off <<= 1) {
+    const uint32_t y = __shfl_up(incl, off);
+    if (j >= (uint32_t)off) incl += y;
+  }
+  if (t < n) {
+    w.coff[t] = incl - x;
+    if (j == kSubKeys - 1) w.ksum[t / kSubKeys] = incl;
+    ccount_of(S, w, p ^ 1)[ctr_word(t)] = 0;
+  }
+}
+
+// One workgroup turns the per-key counts of the produced entries into the key offsets of the
+// cell-sorted queue (koff; a key's sub-ranges follow one another inside its range, at coff) and
+// the tile list: a tile is up to kTile entries of one key (across its sub-ranges), the tiles
 // of a key consecutive, the keys in cell order (order 0) or, for order 1 and grids of at most
 // kScanOrderCells cells, with the cells taken fullest first (cell_order_fullest) and the
 // direction classes of a cell in ascending order. The traversal hands the tiles out in list order
@@ -656,14 +697,13 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(DevScene S, DevWS w, int 
   __shared__ uint8_t s_oct[kScanOrderCells];
   __shared__ uint32_t s_hist[33];
   const int p = gen & 1;
-  const uint32_t* cnt = ccount_of(S, w, p);
   const int nc = S.n_cells * kDirBins;   // queue keys: (cell, direction octant)
   const bool staged = nc <= kScanLdsKeys;
   const bool ordered = order == 1 && S.n_cells <= kScanOrderCells;
-  auto count_of = [&](uint32_t k) -> uint32_t { return staged ? s_key[k] : cnt[(size_t)k * kKeyStride]; };
+  auto count_of = [&](uint32_t k) -> uint32_t { return staged ? s_key[k] : w.ksum[k]; };
   // counts staged in LDS by key
   if (staged) {
-    for (int k = threadIdx.x; k < nc; k += kScanThreads) s_key[k] = cnt[(size_t)k * kKeyStride];
+    for (int k = threadIdx.x; k < nc; k += kScanThreads) s_key[k] = w.ksum[k];
     __syncthreads();
   }
   if (ordered) {
@@ -696,7 +736,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(DevScene S, DevWS w, int 
   uint32_t run = ic - sc;
   for (int c = c0; c < c1; ++c) {
     const uint32_t k = key_at(c);
-    w.coff[k] = run;
+    w.koff[k] = run;
     run += count_of(k);
   }
   // Tiles are written by the whole workgroup, each thread a contiguous block of them: the key of
@@ -740,8 +780,6 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(DevScene S, DevWS w, int 
     w.ctl->list_count[p ^ 1] = 0;
   }
   if (threadIdx.x < kXcds) w.ctl->tile_next[threadIdx.x * kKeyStride] = 0;
-  uint32_t* other = ccount_of(S, w, p ^ 1);
-  for (int c = threadIdx.x; c < nc; c += kScanThreads) other[(size_t)c * kKeyStride] = 0;
 }
 
 // Each thread moves kPer entries per pass, all their loads issued before any store (the lists and
@@ -761,7 +799,8 @@ __global__ void k_scatter(DevWS w, int gen) {
       src[k] = i < n ? w.lsrc[i] : 0u;
     }
 #pragma unroll
-    for (int k = 0; k < kPer; ++k) base[k] = i0 + k * stride < n && key[k] != kNoKey ? w.coff[key[k]] : 0u;
+    for (int k = 0; k < kPer; ++k)
+      base[k] = i0 + k * stride < n && key[k] != kNoKey ? w.koff[key[k] / kSubKeys] + w.coff[key[k]] : 0u;
 #pragma unroll
     for (int k = 0; k < kPer; ++k)
       if (i0 + k * stride < n && key[k] != kNoKey) w.queue[base[k] + rank[k]] = src[k];
@@ -1209,7 +1248,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(7))) void k
         if (out_cat >= 0) w.catb[(shadow ? (size_t)w.W : 0) + slot] = (uint8_t)(out_cat + 1);
         if (out_req) {
           s_rsrc[threadIdx.x] = shadow ? w.W + slot : slot;
-          s_rkey[threadIdx.x] = qkey(cpos_cell(S, cpos), tdir);
+          s_rkey[threadIdx.x] = qsub(qkey(cpos_cell(S, cpos), tdir), 0u);
         }
         phase = kLaneDone;
       }
@@ -1535,7 +1574,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2))) void k
   const uint32_t n_iter = (n + kWG - 1) / kWG * kWG;
   for (uint32_t a = blockIdx.x * kWG + threadIdx.x; a < n_iter; a += gridDim.x * kWG) {
     const bool valid = a < n;
-    uint32_t s = 0, ext_cell = kInvalidCell, sh_cell = kInvalidCell, ext_dir = 0, sh_dir = 0;
+    uint32_t s = 0, ext_cell = kInvalidCell, sh_cell = kInvalidCell, ext_dir = 0, sh_dir = 0, ext_xo = 0, sh_xo = 0;
     bool has_sh = false, has_ext = false;
     if (valid) {
       s = list[a];
@@ -1678,7 +1717,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2))) void k
         w.rays[2 * (W + s)] = make_float4(so.x, so.y, so.z, __uint_as_float(V.id));
         w.rays[2 * (W + s) + 1] = make_float4(ws.x, ws.y, ws.z, __uint_as_float(s | kShadowBit));
         w.shcnt[s] = 0;
-        sh_cell = start_cell_pl(S, s_planes, so, ws);
+        sh_cell = start_cell_pl(S, s_planes, so, ws, &sh_xo);
         sh_dir = dir_bin(ws);
       }
       if (cont) {
@@ -1703,7 +1742,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2))) void k
         has_ext = true;
         w.rays[2 * s] = make_float4(no.x, no.y, no.z, __uint_as_float(V.id));
         w.rays[2 * s + 1] = make_float4(nd.x, nd.y, nd.z, __uint_as_float(s));
-        ext_cell = start_cell_pl(S, s_planes, no, nd);
+        ext_cell = start_cell_pl(S, s_planes, no, nd, &ext_xo);
         ext_dir = dir_bin(nd);
         if (ext_cell == kInvalidCell) w.hit[s] = make_float4(INFINITY, __uint_as_float(0xFFFFFFFFu), 0.0f, 0.0f);
       }
@@ -1716,7 +1755,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2))) void k
     // glass shading, launched next, writes its entries after these.
     {
       const bool ve = has_ext && ext_cell != kInvalidCell, vs = has_sh && sh_cell != kInvalidCell;
-      const uint32_t ke = ve ? qkey(ext_cell, ext_dir) : kNoKey, ks = vs ? qkey(sh_cell, sh_dir) : kNoKey;
+      const uint32_t ke = ve ? qsub(qkey(ext_cell, ext_dir), ext_xo) : kNoKey;
+      const uint32_t ks = vs ? qsub(qkey(sh_cell, sh_dir), sh_xo) : kNoKey;
       uint32_t* cc = ccount_of(S, w, gp);
       const uint32_t re = wave_key_rank(ve, ke, cc), rs = wave_key_rank(vs, ks, cc);
       if (valid) {
@@ -1759,7 +1799,7 @@ __global__ __launch_bounds__(kWG) void k_shade_glass(DevScene S, DevWS w, int de
   const uint32_t n_iter = (n + kWG - 1) / kWG * kWG;
   for (uint32_t a = blockIdx.x * kWG + threadIdx.x; a < n_iter; a += gridDim.x * kWG) {
     const bool valid = a < n;
-    uint32_t s = 0, ext_cell = kInvalidCell, ext_dir = 0;
+    uint32_t s = 0, ext_cell = kInvalidCell, ext_dir = 0, ext_xo = 0;
     if (valid) {
       s = list[a];
       const Vertex V = load_vertex(S, w, s);
@@ -1823,13 +1863,13 @@ __global__ __launch_bounds__(kWG) void k_shade_glass(DevScene S, DevWS w, int de
       const F3 no = refl ? V.p + V.n * V.eps : V.p - V.n * V.eps;
       w.rays[2 * s] = make_float4(no.x, no.y, no.z, __uint_as_float(V.id));
       w.rays[2 * s + 1] = make_float4(nd.x, nd.y, nd.z, __uint_as_float(s));
-      ext_cell = start_cell_pl(S, s_planes, no, nd);
+      ext_cell = start_cell_pl(S, s_planes, no, nd, &ext_xo);
       ext_dir = dir_bin(nd);
       if (ext_cell == kInvalidCell) w.hit[s] = make_float4(INFINITY, __uint_as_float(0xFFFFFFFFu), 0.0f, 0.0f);
     }
     {
       const bool ve = valid && ext_cell != kInvalidCell;
-      const uint32_t ke = ve ? qkey(ext_cell, ext_dir) : kNoKey;
+      const uint32_t ke = ve ? qsub(qkey(ext_cell, ext_dir), ext_xo) : kNoKey;
       const uint32_t re = wave_key_rank(ve, ke, ccount_of(S, w, gp));
       if (valid) {
         w.lsrc[base + a] = s | kFirstVisit;
@@ -2380,7 +2420,7 @@ __global__ __launch_bounds__(kWG) void k_photon_gen(DevScene S, DevWS w, PhotonD
   __syncthreads();
   const uint32_t i = blockIdx.x * kWG + threadIdx.x;
   const bool valid = i < n;
-  uint32_t cell = kInvalidCell, qdir = 0;
+  uint32_t cell = kInvalidCell, qdir = 0, xo = 0;
   if (valid) {
     const uint64_t id = k0 + i;
     const uint32_t c0 = (uint32_t)id, c1 = (uint32_t)(id >> 32);
@@ -2419,12 +2459,12 @@ __global__ __launch_bounds__(kWG) void k_photon_gen(DevScene S, DevWS w, PhotonD
       const float4 e = e4[q];
       b4[q] = make_float4(e.x * P.flux_scale, e.y * P.flux_scale, e.z * P.flux_scale, e.w * P.flux_scale);
     }
-    cell = start_cell_pl(S, s_planes, so, sun);
+    cell = start_cell_pl(S, s_planes, so, sun, &xo);
     qdir = dir_bin(sun);
   }
   const int gp = gen & 1;
   const bool in_grid = valid && cell != kInvalidCell;
-  const uint32_t key = in_grid ? qkey(cell, qdir) : kNoKey;
+  const uint32_t key = in_grid ? qsub(qkey(cell, qdir), xo) : kNoKey;
   const uint32_t rank = wave_key_rank(in_grid, key, ccount_of(S, w, gp));
   if (valid) {
     w.lsrc[i] = (w.W + i) | kFirstVisit;
@@ -2506,7 +2546,7 @@ __global__ __launch_bounds__(kWG) void k_photon_shade(DevScene S, DevWS w, Photo
   const uint32_t n_iter = (n + kWG - 1) / kWG * kWG;
   for (uint32_t a = blockIdx.x * kWG + threadIdx.x; a < n_iter; a += gridDim.x * kWG) {
     const bool valid = a < n;
-    uint32_t s = 0, cell = kInvalidCell, qd = 0;
+    uint32_t s = 0, cell = kInvalidCell, qd = 0, xo = 0;
     if (valid) {
       const bool opaque = a < n_op;
       s = opaque ? cat_list(w, p, kCatOpaque)[a] : cat_list(w, p, kCatGlass)[a - n_op];
@@ -2649,12 +2689,12 @@ __global__ __launch_bounds__(kWG) void k_photon_shade(DevScene S, DevWS w, Photo
         w.rays[2 * s] = make_float4(no.x, no.y, no.z, __uint_as_float(V.id));
         w.rays[2 * s + 1] = make_float4(nd.x, nd.y, nd.z, __uint_as_float(s));
         if (refl) w.view[s] = flags | kPhotonReflected;
-        cell = start_cell_pl(S, s_planes, no, nd);
+        cell = start_cell_pl(S, s_planes, no, nd, &xo);
         qd = dir_bin(nd);
       }
     }
     const bool ve = valid && cell != kInvalidCell;
-    const uint32_t ke = ve ? qkey(cell, qd) : kNoKey;
+    const uint32_t ke = ve ? qsub(qkey(cell, qd), xo) : kNoKey;
     const uint32_t re = wave_key_rank(ve, ke, ccount_of(S, w, gp));
     if (valid) {
       w.lsrc[a] = s | kFirstVisit;
@@ -3077,6 +3117,8 @@ hipError_t launch_raygen(const Launch& L, const DevScene& S, const DevWS& w, uin
 }
 
 hipError_t launch_scan(const Launch& L, const DevScene& S, const DevWS& w, int gen) {
+  const size_t n_sub = (size_t)S.n_cells * kDirBins * kSubKeys;
+  hipLaunchKernelGGL(k_subscan, dim3((uint32_t)((n_sub + kWG - 1) / kWG)), dim3(kWG), 0, L.stream, S, w, gen);
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, L.stream, S, w, gen, L.cell_order);
   return hipGetLastError();
 }
