@@ -782,28 +782,42 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(DevScene S, DevWS w, int 
   if (threadIdx.x < kXcds) w.ctl->tile_next[threadIdx.x * kKeyStride] = 0;
 }
 
-// Each thread moves kPer entries per pass, all their loads issued before any store (the lists and
-// the queue are all uint32 memory: a load after a store would wait for it); entries marked kNoKey
-// (no ray) are passed over.
+// Each thread moves kPer pairs of entries (2j, 2j + 1) per pass, all their loads issued before
+// any store (the lists and the queue are all uint32 memory: a load after a store would wait for
+// it); entries marked kNoKey (no ray) are passed over. Opaque shading puts vertex a's extension
+// ray at entry 2a and its shadow ray at 2a + 1, so storing the even entries of a wave's pairs in
+// one instruction and the odd ones in the next writes the rays of 64 neighbouring vertices per
+// instruction, whose ranks in a shared sub-range are consecutive.
 __global__ void k_scatter(DevWS w, int gen) {
-  constexpr int kPer = 4;
+  constexpr int kPer = 2;
   const uint32_t n = w.ctl->list_count[gen & 1];
+  const uint32_t np = (n + 1) / 2;
   const uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t i0 = blockIdx.x * blockDim.x + threadIdx.x; i0 < n; i0 += kPer * stride) {
-    uint32_t key[kPer], rank[kPer], src[kPer], base[kPer];
+  const uint2* src2 = (const uint2*)w.lsrc;
+  const uint2* key2 = (const uint2*)w.ldst;
+  const uint2* rank2 = (const uint2*)w.lrank;
+  for (uint32_t j0 = blockIdx.x * blockDim.x + threadIdx.x; j0 < np; j0 += kPer * stride) {
+    uint2 key[kPer], rank[kPer], src[kPer];
+    uint32_t base[2 * kPer];
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
-      const uint32_t i = i0 + k * stride;
-      key[k] = i < n ? w.ldst[i] : 0u;
-      rank[k] = i < n ? w.lrank[i] : 0u;
-      src[k] = i < n ? w.lsrc[i] : 0u;
+      const uint32_t j = j0 + k * stride;
+      key[k] = j < np ? key2[j] : make_uint2(kNoKey, kNoKey);
+      rank[k] = j < np ? rank2[j] : make_uint2(0u, 0u);
+      src[k] = j < np ? src2[j] : make_uint2(0u, 0u);
+      // an odd count leaves the last pair's second entry outside the list
+      if (j == np - 1 && (n & 1u)) key[k].y = kNoKey;
     }
 #pragma unroll
-    for (int k = 0; k < kPer; ++k)
-      base[k] = i0 + k * stride < n && key[k] != kNoKey ? w.koff[key[k] / kSubKeys] + w.coff[key[k]] : 0u;
+    for (int k = 0; k < kPer; ++k) {
+      base[2 * k] = key[k].x != kNoKey ? w.koff[key[k].x / kSubKeys] + w.coff[key[k].x] : 0u;
+      base[2 * k + 1] = key[k].y != kNoKey ? w.koff[key[k].y / kSubKeys] + w.coff[key[k].y] : 0u;
+    }
 #pragma unroll
-    for (int k = 0; k < kPer; ++k)
-      if (i0 + k * stride < n && key[k] != kNoKey) w.queue[base[k] + rank[k]] = src[k];
+    for (int k = 0; k < kPer; ++k) {
+      if (key[k].x != kNoKey) w.queue[base[2 * k] + rank[k].x] = src[k].x;
+      if (key[k].y != kNoKey) w.queue[base[2 * k + 1] + rank[k].y] = src[k].y;
+    }
   }
 }
 
