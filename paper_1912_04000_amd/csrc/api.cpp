@@ -86,6 +86,7 @@ struct Plan {
   int n_views;
   int trace_blocks;
   uint32_t max_tiles;
+  uint32_t sub_shift, key_words;  // queue-key sub-ranges (3 x their levels), counter words per key
   size_t off[L_COUNT];
   size_t total;
 };
@@ -96,6 +97,8 @@ Plan make_plan(uint32_t W, int B, int n_cells, int n_views) {
   p.B = B;
   p.Bp = (B + 3) & ~3;
   p.n_cells = n_cells;
+  p.sub_shift = 3u * (uint32_t)sub_levels_for(n_cells);
+  p.key_words = std::max<uint32_t>(kKeyStride, 1u << p.sub_shift);
   p.n_views = n_views;
   size_t want = ((size_t)2 * W + kWG - 1) / kWG;
   int tb = (int)std::min<size_t>(2048, std::max<size_t>(kXcds, want));
@@ -119,8 +122,8 @@ Plan make_plan(uint32_t W, int B, int n_cells, int n_views) {
   sz[L_LDST] = 8ull * W;
   sz[L_LRANK] = 8ull * W;
   sz[L_QUEUE] = 8ull * W;
-  sz[L_CCOUNT] = 8ull * n_cells * kDirBins * kKeyWords;
-  sz[L_COFF] = 4ull * n_cells * kDirBins * kSubKeys;
+  sz[L_CCOUNT] = 8ull * n_cells * kDirBins * p.key_words;
+  sz[L_COFF] = (4ull * n_cells * kDirBins) << p.sub_shift;
   sz[L_KSUM] = 4ull * n_cells * kDirBins;
   sz[L_KOFF] = 4ull * n_cells * kDirBins;
   sz[L_TILES] = 16ull * p.max_tiles;
@@ -168,6 +171,8 @@ DevWS ws_view(const Plan& p, void* base) {
   w.max_tiles = p.max_tiles;
   w.trace_threads = (uint32_t)p.trace_blocks * kWG;
   w.n_views = p.n_views;
+  w.sub_shift = p.sub_shift;
+  w.key_words = p.key_words;
   w.Bp = p.Bp;
   return w;
 }
@@ -385,7 +390,7 @@ int enqueue_frame(sdd_ctx* ctx, const sdd_scene* scene, const std::vector<ViewDe
     ctx->acc.wavefronts++;
     return SDD_OK;
   }
-  HIP_TRY(ctx, launch_fill_u32(ctx->stream, w.ccount, 2ull * scene->hdr.n_cells * kDirBins * kKeyWords, 0u));
+  HIP_TRY(ctx, launch_fill_u32(ctx->stream, w.ccount, 2ull * scene->hdr.n_cells * kDirBins * w.key_words, 0u));
   int gen = 0;
   const PathMode render_mode{0u, 0, nullptr, nullptr, gm ? gm_from : 0};
   uint64_t wavefront = 0;
@@ -967,7 +972,7 @@ static int query(sdd_ctx* c, const sdd_scene* s, const float* orig, const float*
   DevScene S = device_view(s);
   Launch L{c->stream, plan.trace_blocks};
   HIP_TRY(c, launch_fill_u32(c->stream, (uint32_t*)w.ctl, sizeof(Ctl) / 4, 0u));
-  HIP_TRY(c, launch_fill_u32(c->stream, w.ccount, 2ull * s->hdr.n_cells * kDirBins * kKeyWords, 0u));
+  HIP_TRY(c, launch_fill_u32(c->stream, w.ccount, 2ull * s->hdr.n_cells * kDirBins * w.key_words, 0u));
   c->last_ctl = w.ctl;
   int gen = 0;
   for (int64_t a = 0; a < n; a += W) {
@@ -1119,7 +1124,7 @@ int sdd_photon_map_build(sdd_ctx* c, const sdd_scene* s, sdd_photon_map* m, void
       HIP_TRY(c, launch_fill_u32(c->stream, (uint32_t*)&w.ctl->st_paths, (sizeof(Ctl) - offsetof(Ctl, st_paths)) / 4, 0u));
     c->last_ctl = w.ctl;
     HIP_TRY(c, launch_fill_u32(c->stream, (uint32_t*)w.ctl, offsetof(Ctl, st_paths) / 4, 0u));
-    HIP_TRY(c, launch_fill_u32(c->stream, w.ccount, 2ull * H.n_cells * kDirBins * kKeyWords, 0u));
+    HIP_TRY(c, launch_fill_u32(c->stream, w.ccount, 2ull * H.n_cells * kDirBins * w.key_words, 0u));
     DevScene S = device_view(s);
     // the build's traversal launches are short (photons end after a few vertices): a grid of
     // one workgroup per 1024 photons in flight (half a render wavefront's) gives each wave more

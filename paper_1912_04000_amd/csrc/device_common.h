@@ -60,14 +60,17 @@ __device__ __forceinline__ uint32_t dir_bin(F3 d) {
   return oct * 3u + dom;
 }
 __device__ __forceinline__ uint32_t qkey(uint32_t cell, uint32_t dbin) { return cell * (uint32_t)kDirBins + dbin; }
-// sub-range of a ray: its queue key and the block of its cell that holds its origin
-__device__ __forceinline__ uint32_t qsub(uint32_t key, uint32_t blk) { return key * (uint32_t)kSubKeys + blk; }
+// sub-range of a ray: its queue key and the block of its cell that holds its origin (blk, the
+// Morton index at kMaxSubLevels levels, whose top 3 L bits are the index at L levels)
+__device__ __forceinline__ uint32_t qsub(const DevWS& w, uint32_t key, uint32_t blk) {
+  return (key << w.sub_shift) | (blk >> (3u * kMaxSubLevels - w.sub_shift));
+}
 // word of sub-range ks's counter in a counter array
-__device__ __forceinline__ size_t ctr_word(uint32_t ks) {
-  return (size_t)(ks / kSubKeys) * kKeyWords + ks % kSubKeys;
+__device__ __forceinline__ size_t ctr_word(const DevWS& w, uint32_t ks) {
+  return (size_t)(ks >> w.sub_shift) * w.key_words + (ks & ((1u << w.sub_shift) - 1u));
 }
 __device__ __forceinline__ uint32_t* ccount_of(const DevScene& S, const DevWS& w, int parity) {
-  return w.ccount + (size_t)parity * S.n_cells * kDirBins * kKeyWords;
+  return w.ccount + (size_t)parity * S.n_cells * kDirBins * w.key_words;
 }
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }

@@ -27,16 +27,21 @@ constexpr int kDirBins = 24;        // ray queues per cell: direction octant x d
 // one at a time per line, and the keys that camera or shadow rays share would otherwise crowd
 // a few lines.
 constexpr int kKeyStride = 16;
-// Each queue key counts its rays in kSubKeys sub-ranges, one per block of a 2^L x 2^L x 2^L
-// split of the cell that holds the ray's origin (L = kSubLevels, blocks in Morton order), laid
-// out one after the other in the key's queue range: the rays of a tile, and of its 64-ray parts,
-// then start close together and descend the cell's BVH along similar paths. Tiles still span the
-// whole key. A key's sub-range counters are consecutive words of its own counter lines
-// (kKeyWords words per key), so the atomics on a line come from the producers of one key.
-constexpr int kSubLevels = 2;
-constexpr int kSubKeys = 1 << (3 * kSubLevels);
-constexpr int kKeyWords = kSubKeys > kKeyStride ? kSubKeys : kKeyStride;
-static_assert(64 % kSubKeys == 0, "a wave scans whole keys' sub-ranges");
+// Each queue key counts its rays in sub-ranges, one per block of a 2^L x 2^L x 2^L split of the
+// cell that holds the ray's origin (blocks in Morton order), laid out one after the other in the
+// key's queue range: the rays of a tile, and of its 64-ray parts, then start close together and
+// descend the cell's BVH along similar paths. Tiles still span the whole key. L is the largest
+// level up to kMaxSubLevels that keeps the sub-ranges of all keys within kSubRangeBudget
+// (sub_levels_for), so finer grids, whose keys hold fewer rays, get fewer levels and the counters
+// stay small. A key's counters are consecutive words of its own counter lines (DevWS::key_words
+// per key), so the atomics on a line come from the producers of one key.
+constexpr int kMaxSubLevels = 3;
+constexpr uint64_t kSubRangeBudget = 1ull << 21;
+inline int sub_levels_for(int n_cells) {
+  int L = kMaxSubLevels;
+  while (L > 0 && ((uint64_t)n_cells * kDirBins << (3 * L)) > kSubRangeBudget) --L;
+  return L;
+}
 constexpr uint32_t kBlocked = 0xFFFFFFFFu;
 constexpr uint32_t kFirstVisit = 0x80000000u;
 constexpr uint32_t kShadowBit = 0x80000000u;  // in the ray's slot word
@@ -183,8 +188,8 @@ struct DevWS {
   uint32_t* ldst;    // [2W] destination cell
   uint32_t* lrank;   // [2W] rank inside the destination cell
   uint32_t* queue;   // [2W] cell-sorted entries of the current round
-  uint32_t* ccount;  // [2][n_cells * kDirBins * kKeyWords]: sub-range counters, kKeyWords per key
-  uint32_t* coff;    // [n_cells * kDirBins * kSubKeys]: offset of each sub-range inside its key's range
+  uint32_t* ccount;  // [2][n_cells * kDirBins * key_words]: sub-range counters, key_words per key
+  uint32_t* coff;    // [n_cells * kDirBins << sub_shift]: offset of each sub-range inside its key's range
   uint32_t* ksum;    // [n_cells * kDirBins] rays per key
   uint32_t* koff;    // [n_cells * kDirBins] queue offset of each key's range
   uint4* tiles;      // [max_tiles] (cell, start, count, 0)
@@ -196,7 +201,8 @@ struct DevWS {
   uint32_t trace_threads;
   int32_t n_views;
   int32_t Bp;        // row stride of the per-slot spectral rows
-  int32_t pad;
+  uint32_t sub_shift;  // 3 L: sub-ranges per queue key = 1 << sub_shift
+  uint32_t key_words;  // counter words per queue key: max(kKeyStride, 1 << sub_shift)
 };
 
 // ------------------------------------------------------------------------------------------

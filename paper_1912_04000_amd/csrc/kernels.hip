@@ -26,7 +26,7 @@ namespace sdd {
 // counters in one atomic instruction, so a wave waits for one atomic round trip however many
 // keys it holds. Every lane of the wave must call it.
 __device__ void wave_append(bool valid, uint32_t src, uint32_t cell, uint32_t* list_count, uint32_t* cell_count,
-                            uint32_t* lsrc, uint32_t* ldst, uint32_t* lrank) {
+                            const DevWS& w, uint32_t* lsrc, uint32_t* ldst, uint32_t* lrank) {
   const uint64_t m = __ballot(valid);
   if (m == 0) return;
   const uint32_t leader = (uint32_t)__ffsll((unsigned long long)m) - 1u;
@@ -51,7 +51,7 @@ __device__ void wave_append(bool valid, uint32_t src, uint32_t cell, uint32_t* l
     pending &= ~same;
   }
   uint32_t cb = 0;
-  if (is_leader) cb = atomicAdd(&cell_count[ctr_word(cell)], gcount);
+  if (is_leader) cb = atomicAdd(&cell_count[ctr_word(w, cell)], gcount);
   cb = __shfl(cb, (int)my_leader);
   base = __shfl(base, (int)leader);
   if (valid) {
@@ -64,7 +64,7 @@ __device__ void wave_append(bool valid, uint32_t src, uint32_t cell, uint32_t* l
 
 // Rank of each valid lane's entry inside its destination queue key: lanes grouped by key, one
 // atomic per distinct key of the wave (as in wave_append). Every lane of the wave must call it.
-__device__ uint32_t wave_key_rank(bool valid, uint32_t key, uint32_t* cell_count) {
+__device__ uint32_t wave_key_rank(bool valid, uint32_t key, uint32_t* cell_count, const DevWS& w) {
   const uint64_t m = __ballot(valid);
   if (m == 0) return 0;
   uint32_t my_leader = 0, my_off = 0, gcount = 0;
@@ -86,7 +86,7 @@ __device__ uint32_t wave_key_rank(bool valid, uint32_t key, uint32_t* cell_count
     pending &= ~same;
   }
   uint32_t cb = 0;
-  if (is_leader) cb = atomicAdd(&cell_count[ctr_word(key)], gcount);
+  if (is_leader) cb = atomicAdd(&cell_count[ctr_word(w, key)], gcount);
   cb = __shfl(cb, (int)my_leader);
   return cb + my_off;
 }
@@ -97,8 +97,8 @@ __device__ uint32_t wave_key_rank(bool valid, uint32_t key, uint32_t* cell_count
 // inside the destination queues from wave_key_rank. Meant for one-shot kernels: inside a loop
 // its two barriers cost more than the per-wave list atomics of wave_append they save.
 __device__ void block_append2(uint32_t* s_scr, bool v0, uint32_t src0, uint32_t key0, bool v1, uint32_t src1,
-                              uint32_t key1, uint32_t* list_count, uint32_t* cell_count, uint32_t* lsrc,
-                              uint32_t* ldst, uint32_t* lrank) {
+                              uint32_t key1, uint32_t* list_count, uint32_t* cell_count, const DevWS& w,
+                              uint32_t* lsrc, uint32_t* ldst, uint32_t* lrank) {
   constexpr int kWaves = kWG / 64;
   const uint32_t wv = threadIdx.x >> 6;
   const uint64_t m0 = __ballot(v0), m1 = __ballot(v1);
@@ -118,8 +118,8 @@ __device__ void block_append2(uint32_t* s_scr, bool v0, uint32_t src0, uint32_t 
   __syncthreads();
   // each wave reads only its own word, which no thread rewrites before the next call's barrier
   const uint32_t wbase = s_scr[wv];
-  const uint32_t r0 = wave_key_rank(v0, key0, cell_count);
-  const uint32_t r1 = wave_key_rank(v1, key1, cell_count);
+  const uint32_t r0 = wave_key_rank(v0, key0, cell_count, w);
+  const uint32_t r1 = wave_key_rank(v1, key1, cell_count, w);
   if (v0) {
     const uint32_t pos = wbase + count_below(m0);
     lsrc[pos] = src0;
@@ -149,9 +149,9 @@ __device__ __forceinline__ int locate_axis(const float* pl, int g, float lo, flo
 // Start cell of a ray: the cell holding its origin, or the cell where it enters the grid box.
 // Returns kInvalidCell if the ray misses the grid box entirely. `pl` is the plane table
 // (gx+1 | gy+1 | gz+1 entries, in global memory or a copy in LDS). With `blk` given, it receives
-// the block of the cell's 2^L x 2^L x 2^L split (L = kSubLevels) that holds the origin or entry
-// point, as a Morton index (bit 3l + a: axis a at level l from the finest), which orders the rays
-// inside their queue key.
+// the block of the cell's 2^L x 2^L x 2^L split (L = kMaxSubLevels) that holds the origin or
+// entry point, as a Morton index (bit 3l + a: axis a at level l from the finest), which orders
+// the rays inside their queue key.
 __device__ uint32_t start_cell_pl(const DevScene& S, const float* pl, F3 o, F3 d, uint32_t* blk = nullptr) {
   const float* px = pl;
   const float* py = pl + S.gx + 1;
@@ -184,16 +184,16 @@ __device__ uint32_t start_cell_pl(const DevScene& S, const float* pl, F3 o, F3 d
   const int iy = locate_axis(py, S.gy, lo[1], S.inv_cs[1], p.y);
   const int iz = locate_axis(pz, S.gz, lo[2], S.inv_cs[2], p.z);
   if (blk) {
-    constexpr float kSplit = (float)(1 << kSubLevels);
+    constexpr float kSplit = (float)(1 << kMaxSubLevels);
     const float lo3[3] = {px[ix], py[iy], pz[iz]}, hi3[3] = {px[ix + 1], py[iy + 1], pz[iz + 1]};
     const float pp[3] = {p.x, p.y, p.z};
     uint32_t m = 0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const float f = (pp[a] - lo3[a]) * kSplit / (hi3[a] - lo3[a]);
-      const uint32_t q = (uint32_t)min(max((int)f, 0), (1 << kSubLevels) - 1);
+      const uint32_t q = (uint32_t)min(max((int)f, 0), (1 << kMaxSubLevels) - 1);
 #pragma unroll
-      for (int l = 0; l < kSubLevels; ++l) m |= ((q >> l) & 1u) << (3 * l + a);
+      for (int l = 0; l < kMaxSubLevels; ++l) m |= ((q >> l) & 1u) << (3 * l + a);
     }
     *blk = m;
   }
@@ -440,8 +440,8 @@ __global__ __launch_bounds__(kWG) void k_raygen(DevScene S, DevWS w, uint64_t k0
   // misses the grid leaves an entry marked kNoKey, which the scatter passes over.
   const int p = gen & 1;
   const bool in_grid = valid && cell != kInvalidCell;
-  const uint32_t key = in_grid ? qsub(qkey(cell, qdir), xo) : kNoKey;
-  const uint32_t rank = wave_key_rank(in_grid, key, ccount_of(S, w, p));
+  const uint32_t key = in_grid ? qsub(w, qkey(cell, qdir), xo) : kNoKey;
+  const uint32_t rank = wave_key_rank(in_grid, key, ccount_of(S, w, p), w);
   if (valid) {
     w.lsrc[i] = i | kFirstVisit;
     w.ldst[i] = key;
@@ -483,8 +483,8 @@ __global__ __launch_bounds__(kWG) void k_pack_rays(DevScene S, DevWS w, const fl
   }
   const int p = gen & 1;
   __shared__ uint32_t s_app[kWG / 64];
-  block_append2(s_app, valid && cell != kInvalidCell, r | kFirstVisit, qsub(qkey(cell, qdir), xo), false, 0u, 0u,
-                &w.ctl->list_count[p], ccount_of(S, w, p), w.lsrc, w.ldst, w.lrank);
+  block_append2(s_app, valid && cell != kInvalidCell, r | kFirstVisit, qsub(w, qkey(cell, qdir), xo), false, 0u, 0u,
+                &w.ctl->list_count[p], ccount_of(S, w, p), w, w.lsrc, w.ldst, w.lrank);
 }
 
 // Hit records hold the FP32 distance and the triangle id; the distance and barycentrics handed
@@ -659,26 +659,61 @@ __device__ void cell_order_fullest(int n_cells, const uint8_t* s_oct, uint16_t* 
   }
 }
 
-// Sub-ranges of the queue keys, one thread each (runs before k_scan): a key's sub-range counts
-// are summed over its kSubKeys lanes (shuffles inside the wave), giving each sub-range's offset
-// inside its key's range (coff) and the key's count (ksum). It also clears the other parity's
-// counters, which the next generation's producers count into.
+// Sub-ranges of the queue keys (runs before k_scan): a key's sub-range counts are summed in queue
+// order, giving each sub-range's offset inside its key's range (coff) and the key's count
+// (ksum); up to 64 sub-ranges per key one thread each (shuffles inside the wave), more one
+// workgroup per key, each thread (1 << sub_shift) / kWG consecutive ones. It also clears the
+// other parity's counters, which the next generation's producers count into.
 __global__ __launch_bounds__(kWG) void k_subscan(DevScene S, DevWS w, int gen) {
   const int p = gen & 1;
-  const uint32_t n = (uint32_t)S.n_cells * kDirBins * kSubKeys;
-  const uint32_t t = blockIdx.x * kWG + threadIdx.x;
-  const uint32_t j = lane_id() % kSubKeys;
-  const uint32_t x = t < n ? ccount_of(S, w, p)[ctr_word(t)] : 0u;
-  uint32_t incl = x;
+  const uint32_t* cnt = ccount_of(S, w, p);
+  uint32_t* other = ccount_of(S, w, p ^ 1);
+  const uint32_t nsub = 1u << w.sub_shift;
+  if (nsub <= 64) {
+    const uint32_t n = (uint32_t)S.n_cells * kDirBins * nsub;
+    const uint32_t t = blockIdx.x * kWG + threadIdx.x;
+    const uint32_t j = lane_id() & (nsub - 1u);
+    const uint32_t x = t < n ? cnt[ctr_word(w, t)] : 0u;
+    uint32_t incl = x;
+    for (uint32_t off = 1; off < nsub; off <<= 1) {
+      const uint32_t y = __shfl_up(incl, off);
+      if (j >= off) incl += y;
+    }
+    if (t < n) {
+      w.coff[t] = incl - x;
+      if (j == nsub - 1u) w.ksum[t >> w.sub_shift] = incl;
+      other[ctr_word(w, t)] = 0;
+    }
+  } else {
+    constexpr int kMaxPer = (1 << (3 * kMaxSubLevels)) / kWG;
+    static_assert(kMaxPer >= 1 && (1 << (3 * kMaxSubLevels)) % kWG == 0, "whole sub-ranges per thread");
+    __shared__ uint32_t s_w[kWG / 64];
+    const uint32_t per = nsub / kWG;  // a power of two, 1 .. kMaxPer
+    const uint32_t k0 = blockIdx.x * nsub + threadIdx.x * per;
+    uint32_t x[kMaxPer], sum = 0;
 #pragma unroll
-  for (int off = 1; off < kSubKeys; off <<= 1) {
-    const uint32_t y = __shfl_up(incl, off);
-    if (j >= (uint32_t)off) incl += y;
-  }
-  if (t < n) {
-    w.coff[t] = incl - x;
-    if (j == kSubKeys - 1) w.ksum[t / kSubKeys] = incl;
-    ccount_of(S, w, p ^ 1)[ctr_word(t)] = 0;
+    for (int i = 0; i < kMaxPer; ++i) {
+      x[i] = (uint32_t)i < per ? cnt[ctr_word(w, k0 + i)] : 0u;
+      sum += x[i];
+    }
+    uint32_t incl = sum;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t y = __shfl_up(incl, off);
+      if (lane_id() >= (uint32_t)off) incl += y;
+    }
+    if (lane_id() == 63) s_w[threadIdx.x >> 6] = incl;
+    __syncthreads();
+    uint32_t run = incl - sum;
+    for (uint32_t q = 0; q < (threadIdx.x >> 6); ++q) run += s_w[q];
+#pragma unroll
+    for (int i = 0; i < kMaxPer; ++i)
+      if ((uint32_t)i < per) {
+        w.coff[k0 + i] = run;
+        run += x[i];
+        other[ctr_word(w, k0 + i)] = 0;
+      }
+    if (threadIdx.x == kWG - 1) w.ksum[blockIdx.x] = run;
   }
 }
 
@@ -810,8 +845,8 @@ __global__ void k_scatter(DevWS w, int gen) {
     }
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
-      base[2 * k] = key[k].x != kNoKey ? w.koff[key[k].x / kSubKeys] + w.coff[key[k].x] : 0u;
-      base[2 * k + 1] = key[k].y != kNoKey ? w.koff[key[k].y / kSubKeys] + w.coff[key[k].y] : 0u;
+      base[2 * k] = key[k].x != kNoKey ? w.koff[key[k].x >> w.sub_shift] + w.coff[key[k].x] : 0u;
+      base[2 * k + 1] = key[k].y != kNoKey ? w.koff[key[k].y >> w.sub_shift] + w.coff[key[k].y] : 0u;
     }
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
@@ -1262,15 +1297,15 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(7))) void k
         if (out_cat >= 0) w.catb[(shadow ? (size_t)w.W : 0) + slot] = (uint8_t)(out_cat + 1);
         if (out_req) {
           s_rsrc[threadIdx.x] = shadow ? w.W + slot : slot;
-          s_rkey[threadIdx.x] = qsub(qkey(cpos_cell(S, cpos), tdir), 0u);
+          s_rkey[threadIdx.x] = qsub(w, qkey(cpos_cell(S, cpos), tdir), 0u);
         }
         phase = kLaneDone;
       }
     }
     // the part is drained: append its migrating rays (one wave-aggregated atomic per list)
     const uint32_t rs = s_rsrc[threadIdx.x];
-    wave_append(rs != 0xFFFFFFFFu, rs, s_rkey[threadIdx.x], &w.ctl->list_count[np], ccount_of(S, w, np), w.lsrc,
-                w.ldst, w.lrank);
+    wave_append(rs != 0xFFFFFFFFu, rs, s_rkey[threadIdx.x], &w.ctl->list_count[np], ccount_of(S, w, np), w,
+                w.lsrc, w.ldst, w.lrank);
   }
   // the workgroup's counts, then one global atomic per counter
   stats_add(s_st, 0, n_visit);
@@ -1769,10 +1804,10 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2))) void k
     // glass shading, launched next, writes its entries after these.
     {
       const bool ve = has_ext && ext_cell != kInvalidCell, vs = has_sh && sh_cell != kInvalidCell;
-      const uint32_t ke = ve ? qsub(qkey(ext_cell, ext_dir), ext_xo) : kNoKey;
-      const uint32_t ks = vs ? qsub(qkey(sh_cell, sh_dir), sh_xo) : kNoKey;
+      const uint32_t ke = ve ? qsub(w, qkey(ext_cell, ext_dir), ext_xo) : kNoKey;
+      const uint32_t ks = vs ? qsub(w, qkey(sh_cell, sh_dir), sh_xo) : kNoKey;
       uint32_t* cc = ccount_of(S, w, gp);
-      const uint32_t re = wave_key_rank(ve, ke, cc), rs = wave_key_rank(vs, ks, cc);
+      const uint32_t re = wave_key_rank(ve, ke, cc, w), rs = wave_key_rank(vs, ks, cc, w);
       if (valid) {
         ((uint2*)w.lsrc)[a] = make_uint2(s | kFirstVisit, ((uint32_t)W + s) | kFirstVisit);
         ((uint2*)w.ldst)[a] = make_uint2(ke, ks);
@@ -1883,8 +1918,8 @@ __global__ __launch_bounds__(kWG) void k_shade_glass(DevScene S, DevWS w, int de
     }
     {
       const bool ve = valid && ext_cell != kInvalidCell;
-      const uint32_t ke = ve ? qsub(qkey(ext_cell, ext_dir), ext_xo) : kNoKey;
-      const uint32_t re = wave_key_rank(ve, ke, ccount_of(S, w, gp));
+      const uint32_t ke = ve ? qsub(w, qkey(ext_cell, ext_dir), ext_xo) : kNoKey;
+      const uint32_t re = wave_key_rank(ve, ke, ccount_of(S, w, gp), w);
       if (valid) {
         w.lsrc[base + a] = s | kFirstVisit;
         w.ldst[base + a] = ke;
@@ -2478,8 +2513,8 @@ __global__ __launch_bounds__(kWG) void k_photon_gen(DevScene S, DevWS w, PhotonD
   }
   const int gp = gen & 1;
   const bool in_grid = valid && cell != kInvalidCell;
-  const uint32_t key = in_grid ? qsub(qkey(cell, qdir), xo) : kNoKey;
-  const uint32_t rank = wave_key_rank(in_grid, key, ccount_of(S, w, gp));
+  const uint32_t key = in_grid ? qsub(w, qkey(cell, qdir), xo) : kNoKey;
+  const uint32_t rank = wave_key_rank(in_grid, key, ccount_of(S, w, gp), w);
   if (valid) {
     w.lsrc[i] = (w.W + i) | kFirstVisit;
     w.ldst[i] = key;
@@ -2708,8 +2743,8 @@ __global__ __launch_bounds__(kWG) void k_photon_shade(DevScene S, DevWS w, Photo
       }
     }
     const bool ve = valid && cell != kInvalidCell;
-    const uint32_t ke = ve ? qsub(qkey(cell, qd), xo) : kNoKey;
-    const uint32_t re = wave_key_rank(ve, ke, ccount_of(S, w, gp));
+    const uint32_t ke = ve ? qsub(w, qkey(cell, qd), xo) : kNoKey;
+    const uint32_t re = wave_key_rank(ve, ke, ccount_of(S, w, gp), w);
     if (valid) {
       w.lsrc[a] = s | kFirstVisit;
       w.ldst[a] = ke;
@@ -3131,14 +3166,15 @@ hipError_t launch_raygen(const Launch& L, const DevScene& S, const DevWS& w, uin
 }
 
 hipError_t launch_scan(const Launch& L, const DevScene& S, const DevWS& w, int gen) {
-  const size_t n_sub = (size_t)S.n_cells * kDirBins * kSubKeys;
-  hipLaunchKernelGGL(k_subscan, dim3((uint32_t)((n_sub + kWG - 1) / kWG)), dim3(kWG), 0, L.stream, S, w, gen);
+  const size_t n_keys = (size_t)S.n_cells * kDirBins, nsub = (size_t)1 << w.sub_shift;
+  const uint32_t g_sub = nsub <= 64 ? (uint32_t)((n_keys * nsub + kWG - 1) / kWG) : (uint32_t)n_keys;
+  hipLaunchKernelGGL(k_subscan, dim3(g_sub), dim3(kWG), 0, L.stream, S, w, gen);
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, L.stream, S, w, gen, L.cell_order);
   return hipGetLastError();
 }
 
 hipError_t launch_scatter(const Launch& L, const DevWS& w, int gen) {
-  hipLaunchKernelGGL(k_scatter, dim3(grid_for(2 * (size_t)w.W, 4096)), dim3(kWG), 0, L.stream, w, gen);
+  hipLaunchKernelGGL(k_scatter, dim3(grid_for((size_t)w.W, 4096)), dim3(kWG), 0, L.stream, w, gen);
   return hipGetLastError();
 }
 
