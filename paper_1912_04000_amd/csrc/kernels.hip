@@ -37,7 +37,7 @@ __device__ void wave_append(bool valid, uint32_t src, uint32_t cell, uint32_t* l
   uint64_t pending = m;
   while (pending) {
     const uint32_t l = (uint32_t)__ffsll((unsigned long long)pending) - 1u;
-    const uint32_t c = __shfl(cell, (int)l);
+    const uint32_t c = __builtin_amdgcn_readlane(cell, (int)l);  // l is wave-uniform
     const bool mine = valid && cell == c;
     const uint64_t same = __ballot(mine);
     if (mine) {
@@ -53,7 +53,7 @@ __device__ void wave_append(bool valid, uint32_t src, uint32_t cell, uint32_t* l
   uint32_t cb = 0;
   if (is_leader) cb = atomicAdd(&cell_count[ctr_word(w, cell)], gcount);
   cb = __shfl(cb, (int)my_leader);
-  base = __shfl(base, (int)leader);
+  base = __builtin_amdgcn_readlane(base, (int)leader);
   if (valid) {
     const uint32_t pos = base + count_below(m);
     lsrc[pos] = src;
@@ -72,7 +72,7 @@ __device__ uint32_t wave_key_rank(bool valid, uint32_t key, uint32_t* cell_count
   uint64_t pending = m;
   while (pending) {
     const uint32_t l = (uint32_t)__ffsll((unsigned long long)pending) - 1u;
-    const uint32_t c = __shfl(key, (int)l);
+    const uint32_t c = __builtin_amdgcn_readlane(key, (int)l);  // l is wave-uniform
     const bool mine = valid && key == c;
     const uint64_t same = __ballot(mine);
     if (mine) {
@@ -358,7 +358,7 @@ __device__ __forceinline__ void wave_push(bool pred, uint32_t val, uint32_t* cou
   const uint32_t leader = (uint32_t)__ffsll((unsigned long long)m) - 1u;
   uint32_t base = 0;
   if (lane_id() == leader) base = atomicAdd(count, (uint32_t)__popcll(m));
-  base = __shfl(base, (int)leader);
+  base = __builtin_amdgcn_readlane(base, (int)leader);
   if (pred) list[base + count_below(m)] = val;
 }
 
@@ -2618,7 +2618,7 @@ __global__ __launch_bounds__(kWG) void k_photon_shade(DevScene S, DevWS w, Photo
           const uint32_t leader = (uint32_t)__ffsll((unsigned long long)m) - 1u;
           uint32_t base = 0;
           if (lane_id() == leader) base = atomicAdd(&P.ctl[0], (uint32_t)__popcll(m));
-          base = __shfl(base, (int)leader);
+          base = __builtin_amdgcn_readlane(base, (int)leader);
           const uint32_t r = base + count_below(m);
           const uint64_t lost = __ballot(store && r >= P.cap);
           if (lost && lane_id() == leader) atomicAdd(&P.ctl[1], (uint32_t)__popcll(lost));
@@ -2949,7 +2949,7 @@ __global__ __launch_bounds__(kGatherWG) void k_photon_gather(DevScene S, DevWS w
       const uint32_t leader = (uint32_t)__ffsll((unsigned long long)hm) - 1u;
       uint32_t base = 0;
       if ((uint32_t)lane == leader) base = atomicAdd(&w.ctl->ph_heavy[p], (uint32_t)__popcll(hm));
-      base = __shfl(base, (int)leader);
+      base = __builtin_amdgcn_readlane(base, (int)leader);
       if (heavy) w.queue[base + count_below(hm)] = s;
     }
     if (heavy) continue;
