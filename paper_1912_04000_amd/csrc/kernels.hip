@@ -1,10 +1,13 @@
 // gfx950 kernels of the spectral path tracer.
 //
 // Wavefront structure (one "phase" traces every ray produced by the previous step):
-//   producer (raygen / shade / pack)  -> (ray, start cell, rank in cell) entries
+//   producer (raygen / shade / pack)  -> (ray, queue sub-range, rank in it) entries; a
+//              sub-range is a key (start cell, direction class) and the block of the cell that
+//              holds the ray's origin
+//   k_subscan  sub-range offsets inside their keys, key counts
 //   k_scan     one workgroup: per-key offsets and the tile list, cells in index order or
 //              fullest first
-//   k_scatter  entries -> cell-sorted queue
+//   k_scatter  entries -> cell-sorted queue, a key's rays ordered by origin block
 //   k_trace    a tile = up to 256 rays of ONE queue key (cell, direction class), handed out in
 //              parts of 64, one ray per lane of a wave; the grid's slab planes, the cell table
 //              and each lane's short traversal stack live in LDS, the 4-wide BVH nodes and
