@@ -97,7 +97,7 @@ Plan make_plan(uint32_t W, int B, int n_cells, int n_views) {
   p.B = B;
   p.Bp = (B + 3) & ~3;
   p.n_cells = n_cells;
-  p.sub_shift = 3u * (uint32_t)sub_levels_for(n_cells);
+  p.sub_shift = 3u * (uint32_t)sub_levels_for(n_cells) + kDirSubBits;
   p.key_words = std::max<uint32_t>(kKeyStride, 1u << p.sub_shift);
   p.n_views = n_views;
   size_t want = ((size_t)2 * W + kWG - 1) / kWG;

@@ -59,11 +59,23 @@ __device__ __forceinline__ uint32_t dir_bin(F3 d) {
   const uint32_t dom = (ax >= ay && ax >= az) ? 0u : (ay >= az ? 1u : 2u);
   return oct * 3u + dom;
 }
+// Sub-bin of a direction inside its class: whether each of the two components other than the
+// dominant one exceeds half of the dominant one in magnitude (bit 0: the first, bit 1: the second).
+__device__ __forceinline__ uint32_t dir_sub(F3 d) {
+  const float ax = fabsf(d.x), ay = fabsf(d.y), az = fabsf(d.z);
+  const bool xd = ax >= ay && ax >= az, yd = !xd && ay >= az;  // the dominant axis, as in dir_bin
+  const float m = xd ? ax : (yd ? ay : az), u = xd ? ay : ax, v = (xd || yd) ? az : ay;
+  return (u + u > m ? 1u : 0u) | (v + v > m ? 2u : 0u);
+}
+// direction class and sub-bin of a ray in one word: dir_bin | dir_sub << 8
+__device__ __forceinline__ uint32_t dir_code(F3 d) { return dir_bin(d) | dir_sub(d) << 8; }
 __device__ __forceinline__ uint32_t qkey(uint32_t cell, uint32_t dbin) { return cell * (uint32_t)kDirBins + dbin; }
-// sub-range of a ray: its queue key and the block of its cell that holds its origin (blk, the
-// Morton index at kMaxSubLevels levels, whose top 3 L bits are the index at L levels)
-__device__ __forceinline__ uint32_t qsub(const DevWS& w, uint32_t key, uint32_t blk) {
-  return (key << w.sub_shift) | (blk >> (3u * kMaxSubLevels - w.sub_shift));
+// sub-range of a ray: its queue key (cell, direction class), its direction sub-bin (dc, from
+// dir_code) and the block of its cell that holds its origin (blk, the Morton index at
+// kMaxSubLevels levels, whose top 3 L bits are the index at L levels)
+__device__ __forceinline__ uint32_t qsub(const DevWS& w, uint32_t cell, uint32_t dc, uint32_t blk) {
+  const uint32_t bs = w.sub_shift - kDirSubBits;
+  return (((qkey(cell, dc & 0xFFu) << kDirSubBits) | (dc >> 8)) << bs) | (blk >> (3u * kMaxSubLevels - bs));
 }
 // word of sub-range ks's counter in a counter array
 __device__ __forceinline__ size_t ctr_word(const DevWS& w, uint32_t ks) {

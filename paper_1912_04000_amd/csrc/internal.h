@@ -27,21 +27,28 @@ constexpr int kDirBins = 24;        // ray queues per cell: direction octant x d
 // one at a time per line, and the keys that camera or shadow rays share would otherwise crowd
 // a few lines.
 constexpr int kKeyStride = 16;
-// Each queue key counts its rays in sub-ranges, one per block of a 2^L x 2^L x 2^L split of the
-// cell that holds the ray's origin (blocks in Morton order), laid out one after the other in the
-// key's queue range: the rays of a tile, and of its 64-ray parts, then start close together and
-// descend the cell's BVH along similar paths. Tiles still span the whole key. L is the largest
-// level up to kMaxSubLevels that keeps the sub-ranges of all keys within kSubRangeBudget
-// (sub_levels_for), so finer grids, whose keys hold fewer rays, get fewer levels and the counters
-// stay small. A key's counters are consecutive words of its own counter lines (DevWS::key_words
-// per key), so the atomics on a line come from the producers of one key.
+// Each queue key counts its rays in sub-ranges, laid out one after the other in the key's queue
+// range: first by one of 2^kDirSubBits sub-bins of the ray's direction inside its direction
+// class (dir_sub), then by the block of a 2^L x 2^L x 2^L split of the cell that holds the ray's
+// origin (blocks in Morton order). The rays of a tile, and of its 64-ray parts, then start close
+// together in similar directions and descend the cell's BVH along similar paths. Tiles still
+// span the whole key. L is the largest level up to kMaxSubLevels that keeps the sub-ranges of all
+// keys within kSubRangeBudget (sub_levels_for), so finer grids, whose keys hold fewer rays, get
+// fewer levels and the counters stay small. A key's counters are consecutive words of its own
+// counter lines (DevWS::key_words per key), so the atomics on a line come from the producers of
+// one key.
 constexpr int kMaxSubLevels = 3;
-constexpr uint64_t kSubRangeBudget = 1ull << 21;
+constexpr int kDirSubBits = 2;
+constexpr uint64_t kSubRangeBudget = 1ull << 23;
 inline int sub_levels_for(int n_cells) {
   int L = kMaxSubLevels;
-  while (L > 0 && ((uint64_t)n_cells * kDirBins << (3 * L)) > kSubRangeBudget) --L;
+  while (L > 0 && ((uint64_t)n_cells * kDirBins << (3 * L + kDirSubBits)) > kSubRangeBudget) --L;
   return L;
 }
+// sub-ranges per key, 2^(3 L + kDirSubBits): whole waves' shares up to 64, whole workgroups' above
+static_assert(64 % (1 << kDirSubBits) == 0 && 64 % (1 << (3 + kDirSubBits)) == 0 &&
+                  (1 << (6 + kDirSubBits)) % 256 == 0,
+              "k_subscan takes a key's sub-ranges by wave or by workgroup");
 constexpr uint32_t kBlocked = 0xFFFFFFFFu;
 constexpr uint32_t kFirstVisit = 0x80000000u;
 constexpr uint32_t kShadowBit = 0x80000000u;  // in the ray's slot word
@@ -201,7 +208,7 @@ struct DevWS {
   uint32_t trace_threads;
   int32_t n_views;
   int32_t Bp;        // row stride of the per-slot spectral rows
-  uint32_t sub_shift;  // 3 L: sub-ranges per queue key = 1 << sub_shift
+  uint32_t sub_shift;  // 3 L + kDirSubBits: sub-ranges per queue key = 1 << sub_shift
   uint32_t key_words;  // counter words per queue key: max(kKeyStride, 1 << sub_shift)
 };
 

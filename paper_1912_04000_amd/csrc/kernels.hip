@@ -423,7 +423,7 @@ __global__ __launch_bounds__(kWG) void k_raygen(DevScene S, DevWS w, uint64_t k0
     w.smp[i] = s;
     w.view[i] = (uint32_t)v;
     cell = start_cell_pl(S, s_planes, o, d, &xo);
-    qdir = dir_bin(d);
+    qdir = dir_code(d);
   }
   // Throughput rows at one and radiance rows at zero: the workgroup's paths own one contiguous
   // stretch of each row array, written by the whole workgroup in consecutive quads (per-path row
@@ -443,7 +443,7 @@ __global__ __launch_bounds__(kWG) void k_raygen(DevScene S, DevWS w, uint64_t k0
   // misses the grid leaves an entry marked kNoKey, which the scatter passes over.
   const int p = gen & 1;
   const bool in_grid = valid && cell != kInvalidCell;
-  const uint32_t key = in_grid ? qsub(w, qkey(cell, qdir), xo) : kNoKey;
+  const uint32_t key = in_grid ? qsub(w, cell, qdir, xo) : kNoKey;
   const uint32_t rank = wave_key_rank(in_grid, key, ccount_of(S, w, p), w);
   if (valid) {
     w.lsrc[i] = i | kFirstVisit;
@@ -478,7 +478,7 @@ __global__ __launch_bounds__(kWG) void k_pack_rays(DevScene S, DevWS w, const fl
     const bool finite = isfinite(o.x) && isfinite(o.y) && isfinite(o.z) && isfinite(d.x) && isfinite(d.y) &&
                         isfinite(d.z) && (d.x != 0.0f || d.y != 0.0f || d.z != 0.0f);
     if (finite) cell = start_cell_pl(S, S.planes, o, d, &xo);
-    qdir = dir_bin(d);
+    qdir = dir_code(d);
     if (shadow)
       w.shcnt[i] = 0;
     else
@@ -486,7 +486,7 @@ __global__ __launch_bounds__(kWG) void k_pack_rays(DevScene S, DevWS w, const fl
   }
   const int p = gen & 1;
   __shared__ uint32_t s_app[kWG / 64];
-  block_append2(s_app, valid && cell != kInvalidCell, r | kFirstVisit, qsub(w, qkey(cell, qdir), xo), false, 0u, 0u,
+  block_append2(s_app, valid && cell != kInvalidCell, r | kFirstVisit, qsub(w, cell, qdir, xo), false, 0u, 0u,
                 &w.ctl->list_count[p], ccount_of(S, w, p), w, w.lsrc, w.ldst, w.lrank);
 }
 
@@ -688,8 +688,8 @@ __global__ __launch_bounds__(kWG) void k_subscan(DevScene S, DevWS w, int gen) {
       other[ctr_word(w, t)] = 0;
     }
   } else {
-    constexpr int kMaxPer = (1 << (3 * kMaxSubLevels)) / kWG;
-    static_assert(kMaxPer >= 1 && (1 << (3 * kMaxSubLevels)) % kWG == 0, "whole sub-ranges per thread");
+    constexpr int kMaxPer = (1 << (3 * kMaxSubLevels + kDirSubBits)) / kWG;
+    static_assert(kMaxPer >= 1 && (1 << (3 * kMaxSubLevels + kDirSubBits)) % kWG == 0, "whole sub-ranges per thread");
     __shared__ uint32_t s_w[kWG / 64];
     const uint32_t per = nsub / kWG;  // a power of two, 1 .. kMaxPer
     const uint32_t k0 = blockIdx.x * nsub + threadIdx.x * per;
@@ -1300,7 +1300,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(7))) void k
         if (out_cat >= 0) w.catb[(shadow ? (size_t)w.W : 0) + slot] = (uint8_t)(out_cat + 1);
         if (out_req) {
           s_rsrc[threadIdx.x] = shadow ? w.W + slot : slot;
-          s_rkey[threadIdx.x] = qsub(w, qkey(cpos_cell(S, cpos), tdir), 0u);
+          s_rkey[threadIdx.x] = qsub(w, cpos_cell(S, cpos), tdir, 0u);
         }
         phase = kLaneDone;
       }
@@ -1770,7 +1770,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2))) void k
         w.rays[2 * (W + s) + 1] = make_float4(ws.x, ws.y, ws.z, __uint_as_float(s | kShadowBit));
         w.shcnt[s] = 0;
         sh_cell = start_cell_pl(S, s_planes, so, ws, &sh_xo);
-        sh_dir = dir_bin(ws);
+        sh_dir = dir_code(ws);
       }
       if (cont) {
         F3 nd;
@@ -1795,7 +1795,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2))) void k
         w.rays[2 * s] = make_float4(no.x, no.y, no.z, __uint_as_float(V.id));
         w.rays[2 * s + 1] = make_float4(nd.x, nd.y, nd.z, __uint_as_float(s));
         ext_cell = start_cell_pl(S, s_planes, no, nd, &ext_xo);
-        ext_dir = dir_bin(nd);
+        ext_dir = dir_code(nd);
         if (ext_cell == kInvalidCell) w.hit[s] = make_float4(INFINITY, __uint_as_float(0xFFFFFFFFu), 0.0f, 0.0f);
       }
     }
@@ -1807,8 +1807,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2))) void k
     // glass shading, launched next, writes its entries after these.
     {
       const bool ve = has_ext && ext_cell != kInvalidCell, vs = has_sh && sh_cell != kInvalidCell;
-      const uint32_t ke = ve ? qsub(w, qkey(ext_cell, ext_dir), ext_xo) : kNoKey;
-      const uint32_t ks = vs ? qsub(w, qkey(sh_cell, sh_dir), sh_xo) : kNoKey;
+      const uint32_t ke = ve ? qsub(w, ext_cell, ext_dir, ext_xo) : kNoKey;
+      const uint32_t ks = vs ? qsub(w, sh_cell, sh_dir, sh_xo) : kNoKey;
       uint32_t* cc = ccount_of(S, w, gp);
       const uint32_t re = wave_key_rank(ve, ke, cc, w), rs = wave_key_rank(vs, ks, cc, w);
       if (valid) {
@@ -1916,12 +1916,12 @@ __global__ __launch_bounds__(kWG) void k_shade_glass(DevScene S, DevWS w, int de
       w.rays[2 * s] = make_float4(no.x, no.y, no.z, __uint_as_float(V.id));
       w.rays[2 * s + 1] = make_float4(nd.x, nd.y, nd.z, __uint_as_float(s));
       ext_cell = start_cell_pl(S, s_planes, no, nd, &ext_xo);
-      ext_dir = dir_bin(nd);
+      ext_dir = dir_code(nd);
       if (ext_cell == kInvalidCell) w.hit[s] = make_float4(INFINITY, __uint_as_float(0xFFFFFFFFu), 0.0f, 0.0f);
     }
     {
       const bool ve = valid && ext_cell != kInvalidCell;
-      const uint32_t ke = ve ? qsub(w, qkey(ext_cell, ext_dir), ext_xo) : kNoKey;
+      const uint32_t ke = ve ? qsub(w, ext_cell, ext_dir, ext_xo) : kNoKey;
       const uint32_t re = wave_key_rank(ve, ke, ccount_of(S, w, gp), w);
       if (valid) {
         w.lsrc[base + a] = s | kFirstVisit;
@@ -2512,11 +2512,11 @@ __global__ __launch_bounds__(kWG) void k_photon_gen(DevScene S, DevWS w, PhotonD
       b4[q] = make_float4(e.x * P.flux_scale, e.y * P.flux_scale, e.z * P.flux_scale, e.w * P.flux_scale);
     }
     cell = start_cell_pl(S, s_planes, so, sun, &xo);
-    qdir = dir_bin(sun);
+    qdir = dir_code(sun);
   }
   const int gp = gen & 1;
   const bool in_grid = valid && cell != kInvalidCell;
-  const uint32_t key = in_grid ? qsub(w, qkey(cell, qdir), xo) : kNoKey;
+  const uint32_t key = in_grid ? qsub(w, cell, qdir, xo) : kNoKey;
   const uint32_t rank = wave_key_rank(in_grid, key, ccount_of(S, w, gp), w);
   if (valid) {
     w.lsrc[i] = (w.W + i) | kFirstVisit;
@@ -2742,11 +2742,11 @@ __global__ __launch_bounds__(kWG) void k_photon_shade(DevScene S, DevWS w, Photo
         w.rays[2 * s + 1] = make_float4(nd.x, nd.y, nd.z, __uint_as_float(s));
         if (refl) w.view[s] = flags | kPhotonReflected;
         cell = start_cell_pl(S, s_planes, no, nd, &xo);
-        qd = dir_bin(nd);
+        qd = dir_code(nd);
       }
     }
     const bool ve = valid && cell != kInvalidCell;
-    const uint32_t ke = ve ? qsub(w, qkey(cell, qd), xo) : kNoKey;
+    const uint32_t ke = ve ? qsub(w, cell, qd, xo) : kNoKey;
     const uint32_t re = wave_key_rank(ve, ke, ccount_of(S, w, gp), w);
     if (valid) {
       w.lsrc[a] = s | kFirstVisit;
