@@ -220,7 +220,11 @@ typedef struct {
                                   with photon maps, a cache or sdd_render_noalloc).           */
 } sdd_render_params;
 
-/* Workspace bytes for rendering with these parameters (paths in flight, bins, cells). */
+/* Workspace bytes for rendering with these parameters (paths in flight, bins, cells). The ray
+ * queues order the rays of a (cell, direction class) by direction sub-bin and by the block of the
+ * cell they start in, up to 8 x 8 x 8 blocks for grids of at most 170 cells; a render given less
+ * than this size uses fewer blocks (the most that fit, down to none: about 3.5 KB per cell),
+ * which changes the traversal's speed but not the image. */
 int sdd_workspace_bytes(const sdd_scene* scene, const sdd_render_params* params, size_t* bytes);
 
 /* Render the spectral image of one view: image_dev is device memory [n_bins][height][width]
@@ -236,8 +240,9 @@ int sdd_render(sdd_ctx* ctx, const sdd_scene* scene, const sdd_camera* camera, c
  * serving loops, harnesses that forbid allocation): the same render, with the workspace taken
  * from a static device array of the library (64 MiB, one per device, held until the process
  * ends) instead of a caller buffer; the library allocates nothing. wave_paths = 0 picks the most
- * paths in flight (up to 2^20) whose workspace fits; a wave_paths whose workspace does not fit
- * (about 0.7 KB per path at 40 bins, plus 3 KB per cell) is rejected with SDD_ERR_WORKSPACE.
+ * paths in flight (up to 2^20) whose workspace fits, the queues' origin blocks (see
+ * sdd_workspace_bytes) taking what is left; a wave_paths whose workspace does not fit (about
+ * 0.7 KB per path at 40 bins, plus 3.5 KB per cell) is rejected with SDD_ERR_WORKSPACE.
  * Plain mode only; use_graph and timing must be 0 (SDD_ERR_INVALID_ARG). Every call on a device
  * shares that device's array: calls that overlap on one device (other streams or contexts) race,
  * and each context must call sdd_finish before another context's render uses the array. */

@@ -91,13 +91,14 @@ struct Plan {
   size_t total;
 };
 
-Plan make_plan(uint32_t W, int B, int n_cells, int n_views) {
+// levels: the queue keys' origin-block levels, < 0 for as many as the grid allows (sub_levels_for)
+Plan make_plan(uint32_t W, int B, int n_cells, int n_views, int levels = -1) {
   Plan p;
   p.W = W;
   p.B = B;
   p.Bp = (B + 3) & ~3;
   p.n_cells = n_cells;
-  p.sub_shift = 3u * (uint32_t)sub_levels_for(n_cells) + kDirSubBits;
+  p.sub_shift = 3u * (uint32_t)(levels < 0 ? sub_levels_for(n_cells) : levels) + kDirSubBits;
   p.key_words = std::max<uint32_t>(kKeyStride, 1u << p.sub_shift);
   p.n_views = n_views;
   size_t want = ((size_t)2 * W + kWG - 1) / kWG;
@@ -137,6 +138,17 @@ Plan make_plan(uint32_t W, int B, int n_cells, int n_views) {
   }
   p.total = o;
   return p;
+}
+
+// The plan with the most origin-block levels (up to what the grid allows) whose workspace fits in
+// `bytes`, else the one with none: the levels only order the rays inside a queue key, so a
+// smaller workspace costs traversal coherence, never results.
+Plan fit_plan(uint32_t W, int B, int n_cells, int n_views, size_t bytes) {
+  for (int L = sub_levels_for(n_cells); L > 0; --L) {
+    const Plan p = make_plan(W, B, n_cells, n_views, L);
+    if (p.total <= bytes) return p;
+  }
+  return make_plan(W, B, n_cells, n_views, 0);
 }
 
 DevWS ws_view(const Plan& p, void* base) {
@@ -451,7 +463,7 @@ int render_views(sdd_ctx* ctx, const sdd_scene* scene, std::vector<ViewDesc>& vi
       return fail(ctx, SDD_ERR_INVALID_ARG, "persistent render too large: at most 2^42 work items");
     W = persist_lanes(p, total, ctx->device);
   }
-  Plan plan = make_plan(W, B, scene->hdr.n_cells, (int)views.size());
+  Plan plan = fit_plan(W, B, scene->hdr.n_cells, (int)views.size(), ws_bytes);
   if (!ws) return fail(ctx, SDD_ERR_INVALID_ARG, "workspace is null");
   if (ws_bytes < plan.total)
     return fail(ctx, SDD_ERR_WORKSPACE,
@@ -856,8 +868,9 @@ int sdd_render_noalloc(sdd_ctx* c, const sdd_scene* s, const sdd_camera* cam, co
   uint64_t W = p->wave_paths ? (uint64_t)p->wave_paths : (uint64_t)kDefaultWave;
   W = std::max<uint64_t>(64, std::min<uint64_t>(W, total));
   if (!p->wave_paths)
-    while (W > 64 && make_plan((uint32_t)W, B, nc, 1).total > kScratchBytes) W = std::max<uint64_t>(64, W * 3 / 4);
-  const size_t need = make_plan((uint32_t)W, B, nc, 1).total;
+    while (W > 64 && fit_plan((uint32_t)W, B, nc, 1, kScratchBytes).total > kScratchBytes)
+      W = std::max<uint64_t>(64, W * 3 / 4);
+  const size_t need = fit_plan((uint32_t)W, B, nc, 1, kScratchBytes).total;
   if (need > kScratchBytes)
     return fail(c, SDD_ERR_WORKSPACE,
                 "sdd_render_noalloc: " + std::to_string(W) + " paths in flight need " + std::to_string(need) +
