@@ -65,15 +65,21 @@ __device__ void wave_append(bool valid, uint32_t src, uint32_t cell, uint32_t* l
   }
 }
 
-// Rank of each valid lane's entry inside its destination queue key: lanes grouped by key, one
-// atomic per distinct key of the wave (as in wave_append). Every lane of the wave must call it.
+// Rank of each valid lane's entry inside its destination queue sub-range. The lanes of the first
+// kRankGroups distinct keys (in lane order) are grouped, one atomic per group, the rest take one
+// atomic each: camera and shadow rays share few keys per wave and a group saves them atomics on
+// one address, which are served one at a time, while extension rays, spread over many
+// sub-ranges, would cost a grouping pass per lane and save nothing. Every lane of the wave must
+// call it.
+constexpr int kRankGroups = 8;
 __device__ uint32_t wave_key_rank(bool valid, uint32_t key, uint32_t* cell_count, const DevWS& w) {
   const uint64_t m = __ballot(valid);
   if (m == 0) return 0;
-  uint32_t my_leader = 0, my_off = 0, gcount = 0;
-  bool is_leader = false;
+  // a lane in no group leads its own group of one
+  uint32_t my_leader = lane_id(), my_off = 0, gcount = 1;
+  bool is_leader = valid;
   uint64_t pending = m;
-  while (pending) {
+  for (int g = 0; g < kRankGroups && pending; ++g) {
     const uint32_t l = (uint32_t)__ffsll((unsigned long long)pending) - 1u;
     const uint32_t c = __builtin_amdgcn_readlane(key, (int)l);  // l is wave-uniform
     const bool mine = valid && key == c;
@@ -81,9 +87,7 @@ __device__ uint32_t wave_key_rank(bool valid, uint32_t key, uint32_t* cell_count
     if (mine) {
       my_leader = l;
       my_off = count_below(same);
-    }
-    if (lane_id() == l) {
-      is_leader = true;
+      is_leader = lane_id() == l;
       gcount = (uint32_t)__popcll(same);
     }
     pending &= ~same;
