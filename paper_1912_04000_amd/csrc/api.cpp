@@ -98,7 +98,7 @@ Plan make_plan(uint32_t W, int B, int n_cells, int n_views, int levels = -1) {
   p.B = B;
   p.Bp = (B + 3) & ~3;
   p.n_cells = n_cells;
-  p.sub_shift = 3u * (uint32_t)(levels < 0 ? sub_levels_for(n_cells) : levels) + kDirSubBits;
+  p.sub_shift = 3u * (uint32_t)(levels < 0 ? sub_levels_for(n_cells, W) : levels) + kDirSubBits;
   p.key_words = std::max<uint32_t>(kKeyStride, 1u << p.sub_shift);
   p.n_views = n_views;
   size_t want = ((size_t)2 * W + kWG - 1) / kWG;
@@ -144,7 +144,7 @@ Plan make_plan(uint32_t W, int B, int n_cells, int n_views, int levels = -1) {
 // `bytes`, else the one with none: the levels only order the rays inside a queue key, so a
 // smaller workspace costs traversal coherence, never results.
 Plan fit_plan(uint32_t W, int B, int n_cells, int n_views, size_t bytes) {
-  for (int L = sub_levels_for(n_cells); L > 0; --L) {
+  for (int L = sub_levels_for(n_cells, W); L > 0; --L) {
     const Plan p = make_plan(W, B, n_cells, n_views, L);
     if (p.total <= bytes) return p;
   }

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <algorithm>
 #include <stddef.h>
 #include <stdint.h>
 
@@ -33,16 +34,18 @@ constexpr int kKeyStride = 16;
 // origin (blocks in Morton order). The rays of a tile, and of its 64-ray parts, then start close
 // together in similar directions and descend the cell's BVH along similar paths. Tiles still
 // span the whole key. L is the largest level up to kMaxSubLevels that keeps the sub-ranges of all
-// keys within kSubRangeBudget (sub_levels_for), so finer grids, whose keys hold fewer rays, get
-// fewer levels and the counters stay small. A key's counters are consecutive words of its own
+// keys within kSubRangeBudget and within the 2W rays a wavefront of W paths can queue
+// (sub_levels_for): finer grids, whose keys hold fewer rays, get fewer levels and the counters
+// stay small, and short wavefronts (a photon-map build) do not pay for sub-ranges they cannot fill. A key's counters are consecutive words of its own
 // counter lines (DevWS::key_words per key), so the atomics on a line come from the producers of
 // one key.
 constexpr int kMaxSubLevels = 3;
 constexpr int kDirSubBits = 2;
 constexpr uint64_t kSubRangeBudget = 1ull << 23;
-inline int sub_levels_for(int n_cells) {
+inline int sub_levels_for(int n_cells, uint32_t W) {
+  const uint64_t cap = std::min<uint64_t>(kSubRangeBudget, 2ull * W);
   int L = kMaxSubLevels;
-  while (L > 0 && ((uint64_t)n_cells * kDirBins << (3 * L + kDirSubBits)) > kSubRangeBudget) --L;
+  while (L > 0 && ((uint64_t)n_cells * kDirBins << (3 * L + kDirSubBits)) > cap) --L;
   return L;
 }
 // sub-ranges per key, 2^(3 L + kDirSubBits): whole waves' shares up to 64, whole workgroups' above

@@ -93,32 +93,37 @@ def test_cell_order_out_of_range_is_rejected(ctx):
 def test_smaller_workspace_orders_coarser_and_renders_the_same(ctx):
     """A workspace below sdd_workspace_bytes gets fewer origin blocks per queue key (the most whose
     counters fit, down to none): only the order of rays inside a key changes, so the image equals
-    the full workspace's bit for bit; a workspace below the plan without blocks is refused."""
+    the full workspace's bit for bit; a workspace below the plan without blocks is refused. The
+    96 x 96 x 8-spp render keeps 73,728 paths in flight, enough for two block levels on 8 cells."""
     import ctypes as C
     import torch
     import paper_1912_04000_amd as sd
     sc = scenegen.nave_scene(8)
-    cam = scenegen.nave_camera(40, 32)
+    cam = scenegen.nave_camera(96, 96)
     S = sd.Scene.from_description(sc, grid=(2, 2, 2))
     ctx.upload(S)
     c = sd.camera(cam.eye, cam.target, cam.up, cam.vfov_deg, cam.width, cam.height)
-    p = sd.render_params(spp=2, max_depth=5, seed=3)
+    # as many paths in flight as the frame has samples, so that sdd_workspace_bytes (which knows no
+    # camera) sizes the same wavefront as the render
+    p = sd.render_params(spp=8, max_depth=5, seed=3, wave_paths=96 * 96 * 8)
     full = ctx.workspace_bytes(S, p)
     ref = ctx.render(S, c, p).cpu().numpy()
     ws = ctx.workspace(full)
     img = torch.empty((8, cam.height, cam.width), dtype=torch.float32, device="cuda")
-    rendered = 0
-    for nbytes in (full - 1, full // 2, full // 3, 4096):
+    rendered, refused = 0, 0
+    for cut in (1, 1 << 10, 1 << 14, 1 << 17, 1 << 18, 1 << 19, 3 << 18, 1 << 20, 1 << 21):
+        nbytes = full - cut
         rc = sd.lib().sdd_render(ctx.handle, S.handle, C.byref(c), C.byref(p), C.c_void_p(ws.data_ptr()),
                                  nbytes, C.c_void_p(img.data_ptr()))
         if rc != 0:
             with pytest.raises(sd.SddError, match="workspace too small"):
                 ctx._err(rc)
             say(f"workspace {nbytes} of {full} bytes: refused")
-            continue
+            refused += 1
+            break
         ctx.finish()
         same = np.array_equal(img.cpu().numpy(), ref)
         say(f"workspace {nbytes} of {full} bytes: identical={same}")
         assert same
         rendered += 1
-    assert rendered >= 2
+    assert rendered >= 2 and refused == 1
