@@ -831,7 +831,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(DevScene S, DevWS w, int 
 // one instruction and the odd ones in the next writes the rays of 64 neighbouring vertices per
 // instruction, whose ranks in a shared sub-range are consecutive.
 __global__ void k_scatter(DevWS w, int gen) {
-  constexpr int kPer = 2;
+  constexpr int kPer = 4;
   const uint32_t n = w.ctl->list_count[gen & 1];
   const uint32_t np = (n + 1) / 2;
   const uint32_t stride = gridDim.x * blockDim.x;
@@ -3181,7 +3181,7 @@ hipError_t launch_scan(const Launch& L, const DevScene& S, const DevWS& w, int g
 }
 
 hipError_t launch_scatter(const Launch& L, const DevWS& w, int gen) {
-  hipLaunchKernelGGL(k_scatter, dim3(grid_for((size_t)w.W, 4096)), dim3(kWG), 0, L.stream, w, gen);
+  hipLaunchKernelGGL(k_scatter, dim3(grid_for((size_t)w.W / 2, 8192)), dim3(kWG), 0, L.stream, w, gen);
   return hipGetLastError();
 }
 
