@@ -36,9 +36,9 @@ constexpr int kKeyStride = 16;
 // span the whole key. L is the largest level up to kMaxSubLevels that keeps the sub-ranges of all
 // keys within kSubRangeBudget and within the 2W rays a wavefront of W paths can queue
 // (sub_levels_for): finer grids, whose keys hold fewer rays, get fewer levels and the counters
-// stay small, and short wavefronts (a photon-map build) do not pay for sub-ranges they cannot fill. A key's counters are consecutive words of its own
-// counter lines (DevWS::key_words per key), so the atomics on a line come from the producers of
-// one key.
+// stay small, and short wavefronts (a photon-map build) do not pay for sub-ranges they cannot
+// fill. A key's counters are consecutive words of its own counter lines (DevWS::key_words per
+// key), so the atomics on a line come from the producers of one key.
 constexpr int kMaxSubLevels = 3;
 constexpr int kDirSubBits = 2;
 constexpr uint64_t kSubRangeBudget = 1ull << 23;
@@ -48,10 +48,16 @@ inline int sub_levels_for(int n_cells, uint32_t W) {
   while (L > 0 && ((uint64_t)n_cells * kDirBins << (3 * L + kDirSubBits)) > cap) --L;
   return L;
 }
-// sub-ranges per key, 2^(3 L + kDirSubBits): whole waves' shares up to 64, whole workgroups' above
-static_assert(64 % (1 << kDirSubBits) == 0 && 64 % (1 << (3 + kDirSubBits)) == 0 &&
-                  (1 << (6 + kDirSubBits)) % 256 == 0,
-              "k_subscan takes a key's sub-ranges by wave or by workgroup");
+// k_subscan takes a key's 2^(3 L + kDirSubBits) sub-ranges by wave up to 64 (a divisor of 64)
+// and by workgroup above (a multiple of kWG), at every level L
+constexpr bool sub_ranges_suit_scan() {
+  for (int L = 0; L <= kMaxSubLevels; ++L) {
+    const int n = 1 << (3 * L + kDirSubBits);
+    if (!(n <= 64 ? 64 % n == 0 : n % kWG == 0)) return false;
+  }
+  return true;
+}
+static_assert(sub_ranges_suit_scan(), "sub-ranges per key that k_subscan cannot take");
 constexpr uint32_t kBlocked = 0xFFFFFFFFu;
 constexpr uint32_t kFirstVisit = 0x80000000u;
 constexpr uint32_t kShadowBit = 0x80000000u;  // in the ray's slot word
