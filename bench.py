@@ -62,7 +62,7 @@ def parse():
                                                           "tune_cache.json"))
     ap.add_argument("--spp", type=int, default=None, help="override samples per pixel (profiling runs)")
     ap.add_argument("--wave-paths", type=int, default=1 << 25,
-                    help="paths per wavefront (C2 measured 1046 / 925 / 889 / 838 / 821 ms per frame at 2^21 .. 2^25)")
+                    help="paths per wavefront (church frame: 1046 / 925 / 889 / 838 / 821 ms at 2^21 .. 2^25)")
     ap.add_argument("--queue-rounds", type=int, default=0)
     ap.add_argument("--persistent", type=int, default=0, choices=[0, 1],
                     help="church/nave workloads: render with the one persistent kernel instead of the wavefronts")
@@ -263,8 +263,9 @@ def _rmse(img, ref, px):
 
 
 def load_reference():
-    """The oracle's C4 reference (tests/golden/c4_reference.npz): pixel indices, the mean image
-    [B][n] of its two halves, and their noise variance, which _rmse subtracts from then on."""
+    """The oracle's reference of the church view for the cached comparison
+    (tests/golden/c4_reference.npz): pixel indices, the mean image [B][n] of its two halves, and
+    their noise variance, which _rmse subtracts from then on."""
     global _REF_NOISE_VAR
     ref_f = np.load(os.path.join(ROOT, "tests", "golden", "c4_reference.npz"))
     _REF_NOISE_VAR = float(ref_f["noise_var"]) if "noise_var" in ref_f.files else 0.0
@@ -374,7 +375,7 @@ def equal_rmse(cached, a, plain_rate, W, H, warm_frames):
 
 def bench_cached(args):
     """Equal-RMSE comparison of the plain full-depth path and the cache-terminated path on the
-    church-1M view (the C2 frame, 40 bins, depth 8). Both are scored by RMSE against the
+    church-1M view (1920x1080, 40 bins, depth 8). Both are scored by RMSE against the
     oracle's FP64 1024-spp reference on the pixel subset x % 4 == 0, y % 4 == 0
     (tests/golden/c4_reference.npz, its own noise variance subtracted). Plain: RMSE at spp = 1 .. 256 gives the least-squares fit
     RMSE = a / sqrt(spp) and the frame rate. Cached: the cache starts untrained and is trained
@@ -539,7 +540,7 @@ def bench_photons(ctx, S, sc, cam, cfg, wave, n_photons=4_000_000, radius=0.1, s
 
 
 def bench_batch_leg(ctx, S, sc, steps=2):
-    """The C3 batch on the church scene already uploaded (8x4x4 cells, the grid the autotuner
+    """The 32-view batch on the church scene already uploaded (8x4x4 cells, the grid the autotuner
     picks for it; --workload batch runs the tuner): 32 seeded views of uneven size and spp, one
     graph launch per step of the wavefront sequence (2^24 paths, one round, fullest cells first),
     then the same views as one graph-launched persistent kernel per step."""
@@ -618,7 +619,7 @@ def bench_large(args):
 
 
 def large_result(args):
-    """C5: procedural church of ~10M triangles (200 windows), 80 bins (5 nm), 3840x2160, 16x8x8
+    """The large configuration: procedural church of ~10M triangles (200 windows), 80 bins (5 nm), 3840x2160, 16x8x8
     cells, depth 8. Plain 256 spp against the cache-terminated path given the same wall time
     (untrained cache; 1-spp frames, accumulated, until the plain time is used up; every frame
     trains the cache once: 8 Adam steps of 2^14 records, lr 3e-3, position grids of 2^21 entries
@@ -903,7 +904,7 @@ def main():
             out["photon_map"] = bench_photons(ctx, S, sc, cam, cfg, p.wave_paths)
             out["global_map"] = bench_global_map(ctx, S, sc, cam, cfg, p.wave_paths)
             out["batch"] = bench_batch_leg(ctx, S, sc)
-            # the large configuration (C5) as one more leg: its own scene, context and workspace
+            # the large configuration as one more leg: its own scene, context and workspace
             try:
                 lg = large_result(args)
                 out["large"] = {"samples_per_s": lg["value"], "plain_s": lg["ms_per_step"] / 1e3,

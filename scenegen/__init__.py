@@ -173,7 +173,7 @@ def _glass_k_linear(lam_nm):
 
 
 # ----------------------------------------------------------------------------------------------
-# C1: the tiny box nave
+# the tiny box nave
 # ----------------------------------------------------------------------------------------------
 
 def nave_scene(n_bins: int = 8, seed: int = SCENE_SEED, lambda_min_nm: float = 380.0,
@@ -454,7 +454,7 @@ def random_rays(n: int, seed: int = 5, lo=-2.0, hi=12.0, aim_lo=0.0, aim_hi=10.0
 
 
 # ----------------------------------------------------------------------------------------------
-# C2 / C5: procedural church
+# procedural church (about 1M triangles, or 10M for the large configuration)
 # ----------------------------------------------------------------------------------------------
 
 def _grid_tris(P, skip=None):

@@ -63,7 +63,7 @@ def test_flat_spectrum_gives_y_equal_exposure(ctx):
 
 
 def test_rendered_nave_frame(ctx):
-    """The C1 nave frame rendered on the GPU, then its colour image on the GPU, against the
+    """The nave frame rendered on the GPU, then its colour image on the GPU, against the
     oracle's colorimetry of the same spectral image."""
     import paper_1912_04000_amd as sd
     sc = scenegen.nave_scene(8)
@@ -72,7 +72,7 @@ def test_rendered_nave_frame(ctx):
     ctx.upload(S)
     img = ctx.render(S, sd.camera(cam.eye, cam.target, cam.up, cam.vfov_deg, cam.width, cam.height),
                      sd.render_params(spp=4, max_depth=4, seed=1))
-    _check(ctx, img.cpu().numpy(), 380.0, 780.0, 4.0, "nave C1 frame")
+    _check(ctx, img.cpu().numpy(), 380.0, 780.0, 4.0, "nave frame")
 
 
 def test_argument_validation(ctx):

@@ -224,9 +224,9 @@ def test_render_c1_parity(ctx):
                      sd.render_params(spp=1, max_depth=4, seed=1)).cpu().numpy()
     ref = oracle.render(sc, cam, spp=1, max_depth=4, seed=1)
     st = ctx.stats()
-    say(f"C1 stats: {st}")
-    say(f"C1 oracle stats: {ref.stats}")
-    ok = _pixel_parity(img, ref.image, ref.tied, "C1")
+    say(f"nave stats: {st}")
+    say(f"nave oracle stats: {ref.stats}")
+    ok = _pixel_parity(img, ref.image, ref.tied, "nave")
     assert ok.mean() > 0.97
     assert ref.image.max() > 0.05  # the sun really lights the nave
 
@@ -367,7 +367,7 @@ def test_render_c2_full_size_sampled_parity(ctx, church):
     import paper_1912_04000_amd as sd
     import torch
     sc, cam, S, c = church
-    say("C2 full frame, 64 spp")
+    say("church full frame, 64 spp")
     img = ctx.render(S, c, sd.render_params(spp=64, max_depth=8, seed=1, wave_paths=1 << 25))
     rng = np.random.default_rng(0)
     px = np.sort(rng.choice(cam.width * cam.height, 4000, replace=False))
@@ -378,7 +378,7 @@ def test_render_c2_full_size_sampled_parity(ctx, church):
     ok = ref.tied == 0
     bad = ((np.abs(g - ref.image) > tol) & ok[None]).any(axis=0)
     rel = np.abs(g - ref.image) / np.maximum(np.abs(ref.image), 1e-3 * mean_bin[:, None])
-    say(f"C2 64spp: sampled={len(px)} tie-free={ok.sum()} bad={bad.sum()} median rel(all)={np.median(rel):.2e}")
+    say(f"church 64spp: sampled={len(px)} tie-free={ok.sum()} bad={bad.sum()} median rel(all)={np.median(rel):.2e}")
     assert ok.sum() >= 100 and not bad.any()
     # tied samples are few per pixel: even over all sampled pixels the means agree closely
     assert np.median(rel) < 1e-5
@@ -397,7 +397,7 @@ def test_render_c2_one_spp_sampled_parity(ctx, church):
     tol = 1e-4 * np.maximum(np.abs(ref.image), 1e-3 * mean_bin[:, None])
     ok = ref.tied == 0
     bad = ((np.abs(g - ref.image) > tol) & ok[None]).any(axis=0)
-    say(f"C2 1spp: sampled={len(px)} tie-free={ok.sum()} bad={bad.sum()}")
+    say(f"church 1spp: sampled={len(px)} tie-free={ok.sum()} bad={bad.sum()}")
     assert ok.mean() > 0.9 and not bad.any()
 
 
