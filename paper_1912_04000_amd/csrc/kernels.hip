@@ -98,6 +98,43 @@ __device__ uint32_t wave_key_rank(bool valid, uint32_t key, uint32_t* cell_count
   return cb + my_off;
 }
 
+// Group leaders and in-group offsets of wave_key_rank, without the atomic.
+struct KeyGroups {
+  uint32_t my_leader, my_off, gcount;
+  bool is_leader;
+};
+__device__ __forceinline__ KeyGroups wave_key_groups(bool valid, uint32_t key) {
+  const uint64_t m = __ballot(valid);
+  KeyGroups g{lane_id(), 0u, 1u, valid};
+  uint64_t pending = m;
+  for (int i = 0; i < kRankGroups && pending; ++i) {
+    const uint32_t l = (uint32_t)__ffsll((unsigned long long)pending) - 1u;
+    const uint32_t c = __builtin_amdgcn_readlane(key, (int)l);  // l is wave-uniform
+    const bool mine = valid && key == c;
+    const uint64_t same = __ballot(mine);
+    if (mine) {
+      g.my_leader = l;
+      g.my_off = count_below(same);
+      g.is_leader = lane_id() == l;
+      g.gcount = (uint32_t)__popcll(same);
+    }
+    pending &= ~same;
+  }
+  return g;
+}
+
+// wave_key_rank of two entries per lane (a vertex's extension and shadow rays): both atomics are
+// issued before either result is waited for. Every lane of the wave must call it.
+__device__ __forceinline__ void wave_key_rank2(bool v0, uint32_t k0, bool v1, uint32_t k1, uint32_t* cell_count,
+                                               const DevWS& w, uint32_t& r0, uint32_t& r1) {
+  const KeyGroups g0 = wave_key_groups(v0, k0), g1 = wave_key_groups(v1, k1);
+  uint32_t c0 = 0, c1 = 0;
+  if (g0.is_leader) c0 = atomicAdd(&cell_count[ctr_word(w, k0)], g0.gcount);
+  if (g1.is_leader) c1 = atomicAdd(&cell_count[ctr_word(w, k1)], g1.gcount);
+  r0 = __shfl(c0, (int)g0.my_leader) + g0.my_off;
+  r1 = __shfl(c1, (int)g1.my_leader) + g1.my_off;
+}
+
 // Workgroup-level append of up to two (src, key) entries per lane (all threads of the
 // workgroup call it; s_scr holds kWG / 64 words of LDS): the positions in the produced-entry
 // list come from one list-counter atomic per workgroup and a prefix over its waves, the ranks
@@ -1814,7 +1851,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2))) void k
       const uint32_t ke = ve ? qsub(w, ext_cell, ext_dir, ext_xo) : kNoKey;
       const uint32_t ks = vs ? qsub(w, sh_cell, sh_dir, sh_xo) : kNoKey;
       uint32_t* cc = ccount_of(S, w, gp);
-      const uint32_t re = wave_key_rank(ve, ke, cc, w), rs = wave_key_rank(vs, ks, cc, w);
+      uint32_t re, rs;
+      wave_key_rank2(ve, ke, vs, ks, cc, w, re, rs);
       if (valid) {
         ((uint2*)w.lsrc)[a] = make_uint2(s | kFirstVisit, ((uint32_t)W + s) | kFirstVisit);
         ((uint2*)w.ldst)[a] = make_uint2(ke, ks);
