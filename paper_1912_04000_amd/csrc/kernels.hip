@@ -1163,10 +1163,12 @@ enum : int { kLaneEnter = 1, kLaneTrav = 2, kLaneLeave = 3, kLaneDone = 4 };
 // iteration. A ray's cell is traversed inside the cell's half-open slab interval; in every
 // round but the last the ray then migrates to the queue of the next cell, in the last round it
 // walks on in place. Finished rays write their category byte; migrating rays are appended to
-// the next round's lists by the wave once its part is drained.
+// the next round's lists by the wave once its part is drained. The kernel runs 8 waves per SIMD
+// (64 VGPRs, 32 bytes per lane spilled): the eighth wave hides more fetch latency than the
+// spills cost (7.90 against 8.11 ms per launch at 7 waves and 72 VGPRs on the church frame).
 constexpr uint32_t kTileParts = kTile / 64;
 
-__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(7))) void k_trace(DevScene S, DevWS w, int gen, int hops) {
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(8))) void k_trace(DevScene S, DevWS w, int gen, int hops) {
   __shared__ uint32_t s_stack[kShortStack * kWG];
   __shared__ uint32_t s_rsrc[kWG], s_rkey[kWG];
   // the grid's slab planes, and its cell table when small enough, staged in LDS: a ray entering
