@@ -900,6 +900,14 @@ __global__ void k_scatter(DevWS w, int gen) {
   }
 }
 
+// x, opaque to the compiler: an address formed from it is computed where it is used instead of
+// being hoisted out of the traversal loop and held in registers across it (the stores of a
+// finished ray's records are rare; their addresses held live made the kernel spill).
+__device__ __forceinline__ uint32_t opaque(uint32_t x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
 // ==========================================================================================
 // traversal
 // ==========================================================================================
@@ -1110,7 +1118,7 @@ __device__ __forceinline__ bool trav_step(const DevScene& S, const DevWS& w, con
         return false;
       }
       if (st.ncross < (uint32_t)kMaxCross)
-        w.shx[(size_t)st.ncross * w.W + slot] = make_float2(__int_as_float(m), __uint_as_float(id));
+        w.shx[(size_t)st.ncross * w.W + opaque(slot)] = make_float2(__int_as_float(m), __uint_as_float(id));
       st.ncross++;
       work = kStepCross;
     } else if (t < st.tbest || (t == st.tbest && id < st.best_id)) {
@@ -1164,8 +1172,9 @@ enum : int { kLaneEnter = 1, kLaneTrav = 2, kLaneLeave = 3, kLaneDone = 4 };
 // round but the last the ray then migrates to the queue of the next cell, in the last round it
 // walks on in place. Finished rays write their category byte; migrating rays are appended to
 // the next round's lists by the wave once its part is drained. The kernel runs 8 waves per SIMD
-// (64 VGPRs, 32 bytes per lane spilled): the eighth wave hides more fetch latency than the
-// spills cost (7.90 against 8.11 ms per launch at 7 waves and 72 VGPRs on the church frame).
+// (64 VGPRs, 16 bytes per lane spilled once per thread): the eighth wave hides more fetch latency
+// than the spills cost (7.90 against 8.11 ms per launch at 7 waves and 72 VGPRs on the church
+// frame).
 constexpr uint32_t kTileParts = kTile / 64;
 
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(8))) void k_trace(DevScene S, DevWS w, int gen, int hops) {
@@ -1291,11 +1300,11 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(8))) void k
         if (!trav_step(S, w, R, shadow, cinfo, stack, spill, w.trace_threads, skip, t_lo, tf, slot, st, node, sp, pend,
                        work)) {
           if (shadow && st.blocked) {
-            w.shcnt[slot] = kBlocked;
+            w.shcnt[opaque(slot)] = kBlocked;
             fin = true;
           } else if (!shadow && st.best_id != 0xFFFFFFFFu) {
             const uint32_t mat = __float_as_uint(S.gtris[(size_t)st.best_id * 3 + 1].w);
-            w.hit[slot] = make_float4(st.tbest, __uint_as_float(st.best_id), 0.0f, 0.0f);
+            w.hit[opaque(slot)] = make_float4(st.tbest, __uint_as_float(st.best_id), 0.0f, 0.0f);
             out_cat = S.mtype[mat] == 0 ? kCatOpaque : kCatGlass;
             fin = true;
           } else {
@@ -1311,7 +1320,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(8))) void k
         const int ni = (int)((cpos >> (6 * axis)) & 63u) + (dc > 0.0f ? 1 : -1);
         if (ni < 0 || ni >= g || !(tf < INFINITY)) {
           if (!shadow) {
-            w.hit[slot] = make_float4(INFINITY, __uint_as_float(0xFFFFFFFFu), 0.0f, 0.0f);
+            w.hit[opaque(slot)] = make_float4(INFINITY, __uint_as_float(0xFFFFFFFFu), 0.0f, 0.0f);
             if (S.env_nonzero) out_cat = kCatEscape;
           } else {
             out_cat = st.ncross > 0 ? kCatShadowGlass : kCatShadowClear;
@@ -1338,9 +1347,9 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(8))) void k
         if (esc) atomicAdd(&s_st[2], 1u);
         // shadow rays that reach the sun through more slabs than were recorded
         if (shadow && !st.blocked && !out_req && st.ncross > (uint32_t)kMaxCross) atomicAdd(&s_st[4], 1u);
-        if (shadow && !st.blocked) w.shcnt[slot] = st.ncross;
+        if (shadow && !st.blocked) w.shcnt[opaque(slot)] = st.ncross;
         // the finished ray's category, by slot: gathered into slot-ordered lists after the trace
-        if (out_cat >= 0) w.catb[(shadow ? (size_t)w.W : 0) + slot] = (uint8_t)(out_cat + 1);
+        if (out_cat >= 0) w.catb[(shadow ? (size_t)w.W : 0) + opaque(slot)] = (uint8_t)(out_cat + 1);
         if (out_req) {
           s_rsrc[threadIdx.x] = shadow ? w.W + slot : slot;
           s_rkey[threadIdx.x] = qsub(w, cpos_cell(S, cpos), tdir, 0u);
