@@ -127,3 +127,25 @@ def test_smaller_workspace_orders_coarser_and_renders_the_same(ctx):
         assert same
         rendered += 1
     assert rendered >= 2 and refused == 1
+
+
+def test_noalloc_church_fits_the_static_workspace_and_matches(ctx):
+    """The church (128 cells, 40 bins, 1920 x 1080) through sdd_render_noalloc: its 64 MiB static
+    workspace cannot hold the full-depth queue sub-ranges (75 MB) beside a wavefront, so the render
+    takes fewer origin blocks and fewer paths in flight. At 1 spp every pixel holds one sample, so
+    the image equals sdd_render's (full workspace, 2^20 paths in flight) bit for bit."""
+    import torch
+    import paper_1912_04000_amd as sd
+    sc = scenegen.church_scene(40)
+    cam = scenegen.church_camera()
+    S = sd.Scene.from_description(sc, grid=(8, 4, 4))
+    ctx.upload(S)
+    c = sd.camera(cam.eye, cam.target, cam.up, cam.vfov_deg, cam.width, cam.height)
+    p = sd.render_params(spp=1, max_depth=8, seed=5)
+    say("church 1 spp: sdd_render, then sdd_render_noalloc")
+    ref = ctx.render(S, c, p).cpu().numpy()
+    out = torch.empty((40, cam.height, cam.width), dtype=torch.float32, device="cuda")
+    img = ctx.render_noalloc(S, c, p, out=out).cpu().numpy()
+    same = np.array_equal(img, ref)
+    say(f"church noalloc identical={same} mean={float(ref.mean()):.4e}")
+    assert same and float(ref.mean()) > 0.0
